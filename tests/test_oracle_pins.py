@@ -1,0 +1,368 @@
+"""Pins of the FP64 CPU oracle against what the paper and the mathematics fix.
+
+None of these tests compares the oracle with itself: every expected value
+comes from an independent construction (symbolic Blake image system with
+Faxen operators, textbook closed forms, dense linear algebra, finite
+differences of the value function, brute force on tiny inputs).
+"""
+import math
+
+import numpy as np
+import pytest
+import sympy as sp
+
+from paper_1709_02410_amd import workloads as wl
+
+MU0 = 1.0 / (6.0 * math.pi)
+
+
+# ------------------------------------------------------------------ symbolic
+
+@pytest.fixture(scope="module")
+def sym():
+    """Blake's image system for a point force above the no-slip plane z = 0
+    (target x, source y at height h, image at (y1, y2, -h)), its free Oseen
+    part, and the Faxen-corrected (double Laplacian) image part, lambdified.
+    Units: G * 8 pi eta; multiplying by 3a/4 converts to units of mu0."""
+    x1, y1, z1, x2, y2, z2, a = sp.symbols("x1 y1 z1 x2 y2 z2 a", real=True)
+    Rx, Ry, Rz, h = sp.symbols("Rx Ry Rz h", real=True)
+
+    def oseen(v):
+        r = sp.sqrt(v[0] ** 2 + v[1] ** 2 + v[2] ** 2)
+        return sp.Matrix(3, 3, lambda i, j: (1 if i == j else 0) / r + v[i] * v[j] / r ** 3)
+
+    Rv = [Rx, Ry, Rz]
+    Rn = sp.sqrt(Rx ** 2 + Ry ** 2 + Rz ** 2)
+    phi = [h * Rv[i] / Rn ** 3 - ((1 if i == 2 else 0) / Rn + Rv[i] * Rv[2] / Rn ** 3) for i in range(3)]
+    sgn = [1, 1, -1]  # image-force reflection acting on the force index
+    dip = sp.Matrix(3, 3, lambda i, j: sgn[j] * sp.diff(phi[i], Rv[j]))
+    image = (-oseen(Rv) + 2 * h * dip).subs({Rx: x1 - x2, Ry: y1 - y2, Rz: z1 + z2, h: z2})
+    free = oseen([x1 - x2, y1 - y2, z1 - z2])
+    blake = free + image
+    args = (x1, y1, z1, x2, y2, z2)
+
+    def lap(e, vs):
+        return sum(sp.diff(e, v, 2) for v in vs)
+
+    fax_img = []
+    for i in range(3):
+        for j in range(3):
+            e1 = image[i, j] + a ** 2 / 6 * lap(image[i, j], [x1, y1, z1])
+            fax_img.append(e1 + a ** 2 / 6 * lap(e1, [x2, y2, z2]))
+    fax_free = []
+    for i in range(3):
+        for j in range(3):
+            e1 = free[i, j] + a ** 2 / 6 * lap(free[i, j], [x1, y1, z1])
+            fax_free.append(e1 + a ** 2 / 6 * lap(e1, [x2, y2, z2]))
+    div_x = [sum(sp.diff(blake[i, j], [x1, y1, z1][i]) for i in range(3)) for j in range(3)]
+    return {
+        "blake": sp.lambdify(args, blake, "numpy"),
+        "oseen": sp.lambdify(args, free, "numpy"),
+        "div": sp.lambdify(args, div_x, "numpy"),
+        "fax_img": sp.lambdify(args + (a,), fax_img, "numpy"),
+        "fax_free": sp.lambdify(args + (a,), fax_free, "numpy"),
+    }
+
+
+def _arr(x):
+    return np.array(x, dtype=float)
+
+
+def test_blake_tensor_is_the_no_slip_greens_function(sym):
+    """The symbolic image system itself: zero velocity on the wall,
+    reciprocity, incompressibility, and Oseen far from the wall."""
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        y = [rng.uniform(-3, 3), rng.uniform(-3, 3), rng.uniform(0.5, 5)]
+        x = [rng.uniform(-3, 3), rng.uniform(-3, 3), rng.uniform(0.5, 5)]
+        on_wall = _arr(sym["blake"](x[0], x[1], 0.0, *y))
+        assert np.abs(on_wall).max() < 1e-13
+        g_xy = _arr(sym["blake"](*x, *y))
+        g_yx = _arr(sym["blake"](*y, *x))
+        assert np.abs(g_xy - g_yx.T).max() < 1e-13 * np.abs(g_xy).max()
+        assert np.abs(_arr(sym["div"](*x, *y))).max() < 1e-12
+    far = _arr(sym["blake"](0.0, 0.0, 1e6, 1.0, 2.0, 1e6 + 0.5))
+    osn = _arr(sym["oseen"](0.0, 0.0, 1e6, 1.0, 2.0, 1e6 + 0.5))
+    assert np.abs(far - osn).max() < 1e-5 * np.abs(osn).max()
+
+
+def test_wall_part_equals_faxen_corrected_blake_image(orc, sym):
+    """Every entry of the oracle's wall correction against the symbolic
+    construction, at random target/source pairs (any separation, including
+    overlapping blobs and the self pair), for two blob radii."""
+    rng = np.random.default_rng(7)
+    for a in (1.0, 0.7):
+        pts = []
+        for _ in range(60):
+            ri = np.array([rng.uniform(-6, 6), rng.uniform(-6, 6), rng.uniform(a, 7 * a)])
+            rj = np.array([rng.uniform(-6, 6), rng.uniform(-6, 6), rng.uniform(a, 7 * a)])
+            pts.append((ri, rj))
+            pts.append((ri, ri + rng.uniform(-0.8, 0.8, 3) * a * np.array([1, 1, 0])))
+            pts.append((ri, ri))
+        for ri, rj in pts:
+            ref = 0.75 * a * _arr(sym["fax_img"](*ri, *rj, a)).reshape(3, 3)
+            got = orc.pair_block(ri, rj, a, 1.0, part=2)
+            assert np.abs(ref - got).max() <= 1e-13 * max(1.0, np.abs(ref).max()), (ri, rj)
+
+
+def test_free_part_far_branch_equals_faxen_oseen(orc, sym):
+    """RPY for separated blobs is the Oseen tensor with both Faxen operators."""
+    rng = np.random.default_rng(11)
+    for _ in range(100):
+        ri = rng.uniform(-5, 5, 3) + np.array([0, 0, 10])
+        rj = rng.uniform(-5, 5, 3) + np.array([0, 0, 10])
+        if np.linalg.norm(ri - rj) <= 2.05:
+            continue
+        ref = 0.75 * _arr(sym["fax_free"](*ri, *rj, 1.0)).reshape(3, 3)
+        got = orc.pair_block(ri, rj, 1.0, 1.0, part=1)
+        assert np.abs(ref - got).max() <= 1e-14
+
+
+def test_free_part_overlap_branch_is_c1_at_two_radii(orc):
+    """Both RPY coefficients and their slopes are continuous at d = 2a:
+    values 7/16 and 3/16, slopes -9/(32a) and 3/(32a); identity at d = 0."""
+    a = 1.0
+    ex = np.array([1.0, 0.0, 0.0])
+    base = np.array([0.0, 0.0, 50.0])
+
+    def coeffs(d):
+        m = orc.pair_block(base + d * ex, base, a, 1.0, part=1)
+        c1 = m[1, 1]
+        return c1, m[0, 0] - c1
+
+    for d in (2.0 - 1e-12, 2.0 + 1e-12):
+        c1, c2 = coeffs(d)
+        assert abs(c1 - 7 / 16) < 1e-11 and abs(c2 - 3 / 16) < 1e-11
+    h = 1e-6
+    for side in (-1, 1):
+        d0 = 2.0 + side * 10 * h
+        s1 = (coeffs(d0 + h)[0] - coeffs(d0 - h)[0]) / (2 * h)
+        s2 = (coeffs(d0 + h)[1] - coeffs(d0 - h)[1]) / (2 * h)
+        assert abs(s1 + 9 / 32) < 1e-5 and abs(s2 - 3 / 32) < 1e-5
+    assert np.allclose(orc.pair_block(base, base, a, 1.0, part=1), np.eye(3), atol=0, rtol=0)
+    c1, c2 = coeffs(1.0)
+    assert abs(c1 - (1 - 9 / 32)) < 1e-15 and abs(c2 - 3 / 32) < 1e-15
+
+
+def test_free_rpy_is_divergence_free(orc):
+    """sum_b d M^free_ab / d r_j,b = 0 in both branches (incompressibility)."""
+    rng = np.random.default_rng(5)
+    h = 1e-5
+    for d in (0.7, 1.5, 1.99, 2.5, 6.0):
+        u = rng.standard_normal(3)
+        u /= np.linalg.norm(u)
+        ri = np.array([0.0, 0.0, 20.0])
+        rj = ri - d * u
+        div = np.zeros(3)
+        for b in range(3):
+            e = np.zeros(3)
+            e[b] = h
+            div += (orc.pair_block(ri, rj + e, 1.0, 1.0, 1)[:, b] - orc.pair_block(ri, rj - e, 1.0, 1.0, 1)[:, b]) / (2 * h)
+        assert np.abs(div).max() < 1e-8
+
+
+@pytest.mark.parametrize("t", [1.0, 1.1, 1.5, 2.0, 4.0, 10.0, 100.0])
+def test_self_mobility_closed_form(orc, t):
+    """Near-wall self-mobility of one blob (Faxen-corrected Blake):
+    mu_par/mu0 = 1 - 9/(16t) + 1/(8t^3) - 1/(16t^5),
+    mu_perp/mu0 = 1 - 9/(8t) + 1/(2t^3) - 1/(8t^5), t = z/a."""
+    for a in (1.0, 0.324):
+        r = np.array([0.3, -0.2, t * a])
+        m = orc.pair_block(r, r, a, 1.0, 0) * (6 * math.pi * a)
+        par = 1 - 9 / (16 * t) + 1 / (8 * t ** 3) - 1 / (16 * t ** 5)
+        perp = 1 - 9 / (8 * t) + 1 / (2 * t ** 3) - 1 / (8 * t ** 5)
+        assert abs(m[0, 0] - par) < 1e-14 and abs(m[1, 1] - par) < 1e-14
+        assert abs(m[2, 2] - perp) < 1e-14
+        off = m - np.diag(np.diag(m))
+        assert np.abs(off).max() < 1e-15
+
+
+def test_symmetric_positive_definite(orc):
+    """M is symmetric and SPD (Sec. II.A), also with blobs overlapping each
+    other and the wall (Sec. IV opening: the regularisation keeps M SPD)."""
+    cfg = wl.config0(seed=1)
+    pos = cfg.pos[:150]
+    M = orc.dense(pos)
+    assert np.abs(M - M.T).max() <= 1e-15 * np.abs(M).max()
+    np.linalg.cholesky(M)
+    rng = np.random.default_rng(2)
+    pos2 = np.column_stack([rng.uniform(0, 8, 80), rng.uniform(0, 8, 80), rng.uniform(0.05, 2.5, 80)])
+    M2 = orc.dense(pos2)
+    assert np.abs(M2 - M2.T).max() <= 1e-15 * np.abs(M2).max()
+    assert np.linalg.eigvalsh(M2).min() > 0
+    np.linalg.cholesky(M2)
+
+
+def test_free_space_limit(orc):
+    """Far from the wall the wall correction decays like a/h and M tends to
+    the free RPY tensor at fixed separation."""
+    prev = None
+    for hgt in (1e2, 1e3, 1e4):
+        ri = np.array([0.0, 0.0, hgt])
+        rj = np.array([1.3, -2.2, hgt + 0.4])
+        wall = orc.pair_block(ri, rj, 1.0, 1.0, 2)
+        full = orc.pair_block(ri, rj, 1.0, 1.0, 0) * 6 * math.pi
+        free = orc.pair_block(ri, rj, 1.0, 1.0, 1)
+        mx = np.abs(wall).max()
+        assert mx < 1.2 * 9 / (8 * hgt)
+        assert np.abs(full - free).max() == pytest.approx(mx, rel=1e-9)
+        if prev is not None:
+            assert mx == pytest.approx(prev / 10, rel=0.05)
+        prev = mx
+
+
+def test_wall_overlap_regularisation(orc):
+    """Continuity at z = a, the B^2 scaling below it, and M_ii -> 0 at the wall."""
+    for z in (1.0 - 1e-10, 1.0 + 1e-10):
+        r = np.array([0.0, 0.0, z])
+        m = orc.pair_block(r, r, 1.0, 1.0, 0) * 6 * math.pi
+        assert abs(m[0, 0] - 0.5) < 1e-9 and abs(m[2, 2] - 0.25) < 1e-9
+    r = np.array([0.0, 0.0, 0.5])
+    m = orc.pair_block(r, r, 1.0, 1.0, 0) * 6 * math.pi
+    assert np.allclose(m, np.diag([0.125, 0.125, 0.0625]), atol=1e-15)
+    r = np.array([0.0, 0.0, 1e-8])
+    assert np.abs(orc.pair_block(r, r, 1.0, 1.0, 0)).max() < 1e-15
+    ri, rj = np.array([0.0, 0.0, 0.999999999]), np.array([2.5, 0.0, 3.0])
+    rk = np.array([0.0, 0.0, 1.000000001])
+    assert np.abs(orc.pair_block(ri, rj, 1.0, 1.0, 0) - orc.pair_block(rk, rj, 1.0, 1.0, 0)).max() < 1e-9
+
+
+def test_matvec_rows_and_dense_agree(orc):
+    """The double-loop product equals the dense matrix times f, and the row
+    subset path returns the same rows."""
+    pos = wl.config0(seed=3).pos[:120]
+    f = wl.gaussian((120, 3), 4)
+    u = orc.matvec(pos, f)
+    u2 = (orc.dense(pos) @ f.reshape(-1)).reshape(-1, 3)
+    assert np.abs(u - u2).max() <= 1e-14 * np.abs(u).max()
+    rows = np.array([5, 0, 119, 64])
+    assert np.array_equal(orc.matvec(pos, f, rows=rows), u[rows])
+
+
+# -------------------------------------------------------------- square roots
+
+def _brute_root(fn, n3):
+    return np.column_stack([fn(np.eye(n3)[:, c]).reshape(-1) for c in range(n3)])
+
+
+@pytest.mark.parametrize("precondition", [True, False])
+def test_dense_root_reproduces_M(orc, precondition):
+    """S S^T = M for the dense reference root (Sec. II.B: any root works)."""
+    pos, offs = wl.boomerang_suspension(2, 12.0, 1.5, 3.0, seed=4)
+    M = orc.dense(pos)
+    S = _brute_root(lambda w: orc.dense_sqrt(pos, w, offs, precondition=precondition), M.shape[0])
+    assert np.linalg.norm(S @ S.T - M) <= 1e-12 * np.linalg.norm(M)
+
+
+def test_lanczos_root_reproduces_M_brute_force(orc):
+    """Preconditioned Lanczos run to convergence on every unit vector gives
+    the columns of a root S with S S^T = M (tiny N, 3N = 45)."""
+    pos, offs = wl.boomerang_suspension(1, 10.0, 1.5, 3.0, seed=9)
+    rng = np.random.default_rng(0)
+    pos = np.vstack([pos, rng.uniform(0, 4, (0, 3))])
+    M = orc.dense(pos)
+    S = _brute_root(lambda w: orc.lanczos_sqrt(pos, w, offs, tol=1e-13, max_iter=45)[0], M.shape[0])
+    assert np.linalg.norm(S @ S.T - M) <= 1e-10 * np.linalg.norm(M)
+
+
+@pytest.mark.parametrize("with_bodies", [True, False])
+def test_lanczos_converges_to_dense_root(orc, with_bodies):
+    """At convergence the Lanczos output matches L (L^-1 M L^-T)^{1/2} W
+    within 10 tol, and the unpreconditioned run matches M^{1/2} W."""
+    pos, offs = wl.boomerang_suspension(6, 20.0, 1.5, 4.0, seed=2)
+    if not with_bodies:
+        offs = None
+    W = wl.gaussian(pos.shape, 8)
+    for tol in (1e-6, 1e-10):
+        out, it, rel, ok = orc.lanczos_sqrt(pos, W, offs, tol=tol)
+        ref = orc.dense_sqrt(pos, W, offs)
+        assert ok and rel <= tol
+        assert np.linalg.norm(out - ref) <= 10 * tol * np.linalg.norm(ref)
+    out, it, rel, ok = orc.lanczos_sqrt(pos, W, None, tol=1e-10, precondition=False)
+    ref = orc.dense_sqrt(pos, W, None, precondition=False)
+    assert np.linalg.norm(out - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+@pytest.mark.slow
+def test_preconditioned_lanczos_iterations_size_independent(orc):
+    """Sec. II.B / Sec. IV.B: with the block-diagonal preconditioner, a
+    sedimented boomerang suspension needs about 5 iterations at tolerance
+    1e-3 independent of size; without it more iterations are needed."""
+    its_pc, its_un = [], []
+    for nb in (16, 32):
+        cfg = wl.paperlike_boomerangs(nb, seed=1)
+        W = wl.gaussian(cfg.pos.shape, 21)
+        its_pc.append(orc.lanczos_sqrt(cfg.pos, W, cfg.body_offsets, tol=1e-3)[1])
+        its_un.append(orc.lanczos_sqrt(cfg.pos, W, None, tol=1e-3, precondition=False)[1])
+    assert max(its_pc) <= 7 and abs(its_pc[0] - its_pc[1]) <= 1
+    assert all(u > p for u, p in zip(its_un, its_pc))
+
+
+# --------------------------------------------------------------- derivatives
+
+def _mixed_positions(n, seed):
+    rng = np.random.default_rng(seed)
+    pos = np.column_stack([rng.uniform(0, 9, n), rng.uniform(0, 9, n), rng.uniform(0.4, 4.0, n)])
+    return pos
+
+
+def test_vjp_matches_central_differences(orc):
+    """Dual-number VJP against central differences of the value function,
+    including blobs below z = a and overlapping pairs."""
+    pos = _mixed_positions(40, 1)
+    f = wl.gaussian(pos.shape, 2)
+    g = wl.gaussian(pos.shape, 3)
+    gp, gf = orc.vjp(pos, f, g)
+    assert np.abs(gf - orc.matvec(pos, g)).max() <= 1e-15 * 40
+    h = 1e-6
+    rng = np.random.default_rng(4)
+    for _ in range(8):
+        d = rng.standard_normal(pos.shape)
+        lp = (g * orc.matvec(pos + h * d, f)).sum()
+        lm = (g * orc.matvec(pos - h * d, f)).sum()
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - (gp * d).sum()) <= 1e-7 * max(1.0, abs(fd))
+    for k, c in [(0, 0), (7, 2), (20, 1), (39, 2)]:
+        e = np.zeros_like(pos)
+        e[k, c] = h
+        fd = ((g * orc.matvec(pos + e, f)).sum() - (g * orc.matvec(pos - e, f)).sum()) / (2 * h)
+        assert abs(fd - gp[k, c]) <= 1e-7 * max(1.0, np.abs(gp).max())
+
+
+@pytest.mark.parametrize("t", [1.2, 1.5, 2.0, 3.7])
+def test_single_blob_divergence_closed_form(orc, t):
+    """One blob above the wall: div M = mu0/a (0, 0, d mu_perp/dt), i.e.
+    mu0/a (9/(8t^2) - 3/(2t^4) + 5/(8t^6))."""
+    for a in (1.0, 0.5):
+        div = orc.divergence(np.array([[0.2, 0.1, t * a]]), a, 1.0)[0]
+        ref = (9 / (8 * t ** 2) - 3 / (2 * t ** 4) + 5 / (8 * t ** 6)) / (6 * math.pi * a * a)
+        assert abs(div[2] - ref) < 1e-15 and abs(div[0]) < 1e-16 and abs(div[1]) < 1e-16
+
+
+def test_divergence_matches_finite_differences_of_dense(orc):
+    """Exact divergence against central differences of the dense matrix."""
+    pos = _mixed_positions(12, 6)
+    div = orc.divergence(pos)
+    h = 1e-6
+    fd = np.zeros(36)
+    for j in range(12):
+        for b in range(3):
+            e = np.zeros_like(pos)
+            e[j, b] = h
+            dM = (orc.dense(pos + e) - orc.dense(pos - e)) / (2 * h)
+            fd += dM[:, 3 * j + b]
+    assert np.abs(fd - div.reshape(-1)).max() <= 1e-8 * np.abs(div).max()
+
+
+def test_rfd_mean_converges_to_divergence(orc):
+    """Centred RFD (Sec. III) with Delta P = Delta Q = W estimates the
+    divergence: per-component z-scores within 4.5 sigma and a global
+    chi-square consistent with the number of components."""
+    pos = _mixed_positions(10, 7)
+    pos[:, 2] += 0.8
+    div = orc.divergence(pos)
+    mean, se = orc.rfd_divergence(pos, 1e-6, 4000, seed=5)
+    z = (mean - div) / se
+    assert np.abs(z).max() < 4.5
+    chi2 = float((z ** 2).sum())
+    assert chi2 < 30 + 5 * math.sqrt(60)
