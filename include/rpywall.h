@@ -1,0 +1,167 @@
+/*
+ * rpywall.h - C ABI of librpywall.so: the wall-corrected Rotne-Prager-Yamakawa
+ * blob mobility M(r) of arXiv:1709.02410 on MI355X (gfx950).
+ *
+ * Physics (Sec. II.A): blob i moves with velocity u_i = sum_j M_ij f_j under
+ * forces f_j on all blobs j (self pair included); M_ij is the 3x3
+ * Rotne-Prager-Yamakawa tensor for blobs of hydrodynamic radius a in a fluid
+ * of viscosity eta, corrected for a no-slip wall at z = 0 (the
+ * Rotne-Prager-Blake tensor; fluid in z > 0), with the overlap form for
+ * blobs closer than 2a and a regularisation for blobs closer than a to the
+ * wall that keeps M symmetric positive definite (Sec. IV, opening):
+ *     z~ = max(z, a),  B = min(z/a, 1),  M_ij = B_i B_j Mhat(r~_i, r~_j).
+ * Blobs with z <= 0 are accepted and use the same formula (B <= 0; M is then
+ * singular at z = 0); positions are not scanned, NaN in gives NaN out.
+ * Units: M scales with mu0 = 1/(6 pi eta a); k_B T and time steps are the
+ * caller's (the Brownian velocity sqrt(2 k_B T / dt) M^{1/2} W of Sec. II.B
+ * is the caller's scaling of the square root below).
+ *
+ * Conventions for every entry point:
+ *   - Arrays named pos/force/vel/... are DEVICE pointers to FP64 row-major
+ *     [N][3] arrays (x, y, z per blob); multi-RHS arrays are [k][N][3].
+ *     Arrays documented as "host" are host pointers.
+ *   - The caller owns every buffer.  Scratch memory: pass a device workspace
+ *     `ws` of at least rpy_wall_workspace_bytes(...) bytes, 256-byte aligned;
+ *     with ws == NULL the library takes stream-ordered scratch itself
+ *     (hipMallocAsync/hipFreeAsync on `stream`).
+ *   - `stream` is a hipStream_t (NULL: the default stream).  Calls are
+ *     asynchronous on it unless stated otherwise.  Outputs must not alias
+ *     inputs.  Calls that share a workspace must be ordered by the caller.
+ *   - Arguments are validated on the host before any GPU work; a rejected
+ *     call returns RPYW_EINVAL and launches nothing.  HIP failures return
+ *     RPYW_EHIP.  No function throws or aborts.
+ *   - precision: RPYW_FP64 evaluates every pair in FP64.  RPYW_FP32C
+ *     evaluates pair terms in FP32 (positions carried as FP32 hi+lo pairs)
+ *     and accumulates each target's sum with compensated (TwoSum) FP32
+ *     arithmetic; inputs and outputs stay FP64.
+ */
+#ifndef RPYWALL_H
+#define RPYWALL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum rpyw_status {
+    RPYW_OK = 0,
+    RPYW_NOT_CONVERGED = 1, /* warning: max_iter reached, best iterate written */
+    RPYW_EINVAL = -1,       /* invalid argument, nothing launched */
+    RPYW_EHIP = -2,         /* HIP runtime error */
+    RPYW_ENOMEM = -3,       /* workspace too small or allocation failed */
+    RPYW_ENOTSPD = -4       /* a preconditioner block is not positive definite */
+};
+
+enum rpyw_precision { RPYW_FP64 = 0, RPYW_FP32C = 1 };
+
+enum rpyw_op {
+    RPYW_OP_MATVEC = 0,     /* rpy_wall_matvec / rpy_wall_matvec_multi */
+    RPYW_OP_BATCHED = 1,    /* rpy_wall_matvec_batched (N = total blobs, n_bodies = S) */
+    RPYW_OP_LANCZOS = 2,    /* rpy_wall_lanczos_sqrt */
+    RPYW_OP_VJP = 3,        /* rpy_wall_matvec_vjp */
+    RPYW_OP_DIVERGENCE = 4  /* rpy_wall_divergence */
+};
+
+/* u = M(r) f  (Sec. II.A: the dense product whose cost dominates every
+ * time step, evaluated by direct summation over all blob pairs).
+ * pos, force, vel: device [N][3] FP64.  N >= 1, a > 0, eta > 0 finite. */
+int rpy_wall_matvec(const double* pos, const double* force, double* vel, int64_t N, double a, double eta,
+                    int precision, void* ws, size_t ws_bytes, void* stream);
+
+/* U_l = M(r) F_l for k right-hand sides sharing one geometry (one time step
+ * needs M f, random-finite-difference probes and Lanczos vectors, Sec. III).
+ * F, U: device [k][N][3].  Each pair's 3x3 block is evaluated once per RHS
+ * block and contracted with every RHS in the block.  1 <= k <= 4096. */
+int rpy_wall_matvec_multi(const double* pos, const double* F, double* U, int64_t N, int32_t k, double a,
+                          double eta, int precision, void* ws, size_t ws_bytes, void* stream);
+
+/* S independent suspensions in one persistent launch: system s owns blobs
+ * [sys_offsets[s], sys_offsets[s+1]) and blobs of different systems do not
+ * interact.  sys_offsets: HOST int64 [S+1], sys_offsets[0] = 0, strictly
+ * increasing.  pos: device [Ntot][3]; F, U: device [k][Ntot][3].  Work items
+ * (system, target tile) are taken largest-first from an atomic counter. */
+int rpy_wall_matvec_batched(const double* pos, const int64_t* sys_offsets, int32_t S, const double* F,
+                            double* U, int32_t k, double a, double eta, int precision, void* ws,
+                            size_t ws_bytes, void* stream);
+
+/* Brownian blob displacements out = S W with S S^T = M (Sec. II.B), by the
+ * preconditioned Lanczos iteration:  out = L (L^-1 M L^-T)^{1/2} W, where L
+ * is block diagonal, made of the Cholesky factors of the per-body dense
+ * blocks M^(pp) that ignore other bodies (Sec. II.B, block-diagonal
+ * preconditioner).  body_offsets: HOST int64 [n_bodies+1] (0 .. N, strictly
+ * increasing, at most 42 blobs per body) or NULL for one 3x3 block per blob.
+ * The iteration stops when |y_k - y_{k-1}| <= tol |y_k| (k >= 2) or on an
+ * exact invariant subspace; full reorthogonalisation, FP64 Krylov vectors and
+ * tridiagonal eigensolve; `precision` selects the pair arithmetic of the
+ * products by M.  pos, W, out: device [N][3].  iters_out, err_est_out: HOST
+ * (may be NULL) receive the iteration count and the last relative change.
+ * Synchronises `stream` once per iteration.  Returns RPYW_NOT_CONVERGED
+ * (best iterate written) if max_iter is reached, RPYW_ENOTSPD if a block has
+ * no Cholesky factor (e.g. a blob at z <= 0). */
+int rpy_wall_lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, double a, double eta,
+                          const int64_t* body_offsets, int32_t n_bodies, double tol, int32_t max_iter,
+                          int precision, void* ws, size_t ws_bytes, int32_t* iters_out, double* err_est_out,
+                          void* stream);
+
+/* Vector-Jacobian product of u = M(r) f for L = sum_i g_i . u_i
+ * (derivatives of M drive the thermal drift, Sec. III):
+ *   grad_force = M g  (M is symmetric),
+ *   grad_pos_k = sum_j [g_k^T d1M(r_k, r_j) f_j + f_k^T d1M(r_k, r_j) g_j],
+ * d1 = derivative in the first (target) argument; by reciprocity this is the
+ * full gradient, self pair included.  Through the regularisation:
+ * d z~/dz = 1{z >= a}, dB/dz = 1{z < a}/a; at the kinks (z = a, |r_ij| = 2a)
+ * the upper branch is used, and coincident distinct blobs contribute zero.
+ * pos, force, grad_vel: device [N][3]; grad_pos, grad_force: device [N][3]
+ * or NULL (not computed; at least one must be non-NULL). */
+int rpy_wall_matvec_vjp(const double* pos, const double* force, const double* grad_vel, double* grad_pos,
+                        double* grad_force, int64_t N, double a, double eta, int precision, void* ws,
+                        size_t ws_bytes, void* stream);
+
+/* Exact divergence of M, div_i = sum_j sum_b dM_{ij,ab}/dr_{j,b}: the term
+ * k_B T (d/dQ . M) that random finite differences estimate (Sec. III; the
+ * self block contributes its total derivative).  pos, div: device [N][3]. */
+int rpy_wall_divergence(const double* pos, double* div, int64_t N, double a, double eta, int precision,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/* Bytes of workspace an entry point needs.  op: enum rpyw_op.  N: blobs
+ * (total blobs for BATCHED), k: right-hand sides, max_iter: Lanczos bound,
+ * n_bodies: bodies for LANCZOS (0 = one per blob) or systems S for BATCHED.
+ * Returns 0 for invalid arguments. */
+size_t rpy_wall_workspace_bytes(int op, int64_t N, int32_t k, int32_t max_iter, int32_t n_bodies,
+                                int precision);
+
+/* Static description of a status code (never NULL). */
+const char* rpyw_strerror(int status);
+
+/* Choose the launch shape (targets per lane, source tile, RHS block width)
+ * of the pair kernels for problems of this size by timing the candidates on
+ * the given inputs; the result is kept for the rest of the process and is
+ * used by every later call of the same precision and size class.  Inputs as
+ * for rpy_wall_matvec_multi (k RHS); blocks until the timing is done. */
+int rpy_wall_autotune(const double* pos, const double* F, double* U, int64_t N, int32_t k, double a,
+                      double eta, int precision, void* ws, size_t ws_bytes, void* stream);
+
+/* Host-only: coefficients c = beta0 Q Lambda^{1/2} Q^T e1 of the Lanczos
+ * iterate for the k x k symmetric tridiagonal T (diagonal alpha[k],
+ * off-diagonal beta[k-1]) with eigendecomposition T = Q Lambda Q^T, negative
+ * eigenvalues clamped to zero (Sec. II.B).  HOST arrays.  Implicit
+ * symmetric QL with Wilkinson shifts; returns RPYW_EINVAL for k < 1 or
+ * non-finite input, RPYW_NOT_CONVERGED if the QL sweep stalls. */
+int rpyw_tridiag_sqrt_coeffs(const double* alpha, const double* beta, int32_t k, double beta0,
+                             double* c_out);
+
+/* Instrumentation: when enabled, every launch of the pair kernels (the
+ * O(N^2) products) is bracketed by HIP events on the launch stream and
+ * rpy_wall_profile_read returns the summed kernel time (ms), the launch
+ * count and the pair interactions evaluated (sum of k N^2) since the last
+ * reset.  Reading synchronises the recorded events.  Not thread-safe. */
+int rpy_wall_profile_enable(int enable);
+int rpy_wall_profile_read(double* ms_total, int64_t* launches, double* pair_interactions, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPYWALL_H */

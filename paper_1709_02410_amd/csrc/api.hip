@@ -1,0 +1,326 @@
+// C ABI of librpywall.so: argument validation, workspace handling, launch
+// shape table, instrumentation.  Validation runs on the host before any HIP
+// call, so a rejected call touches no device state.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "rpyw_internal.h"
+
+namespace rpyw {
+
+namespace {
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+bool valid_prec(int p) { return p == RPYW_FP64 || p == RPYW_FP32C; }
+constexpr int64_t kMaxN = (int64_t)1 << 31;
+
+// Scratch: the caller's workspace, or stream-ordered memory owned for the
+// duration of one call.
+struct Scratch {
+    Arena ar{nullptr, 0, 0};
+    void* owned = nullptr;
+    hipStream_t st = nullptr;
+    ~Scratch() {
+        if (owned) (void)hipFreeAsync(owned, st);
+    }
+};
+
+int acquire(void* ws, size_t ws_bytes, size_t need, hipStream_t st, Scratch& s) {
+    s.st = st;
+    if (ws) {
+        if (((uintptr_t)ws % kAlign) != 0) return RPYW_EINVAL;
+        if (ws_bytes < need) return RPYW_ENOMEM;
+        s.ar = Arena{(char*)ws, ws_bytes, 0};
+        return RPYW_OK;
+    }
+    if (hipMallocAsync(&s.owned, need, st) != hipSuccess) {
+        s.owned = nullptr;
+        return RPYW_ENOMEM;
+    }
+    s.ar = Arena{(char*)s.owned, need, 0};
+    return RPYW_OK;
+}
+
+// ---------------------------------------------------------- shape table
+std::mutex g_shape_mu;
+std::map<std::tuple<int, int, int>, Shape> g_shapes;
+
+int size_class(int64_t N) {
+    int c = 0;
+    while (((int64_t)1 << (c + 1)) <= N) ++c;
+    return c;
+}
+int kclass(int k) {
+    int p = 1;
+    while (p < k && p < 16) p <<= 1;
+    return p;
+}
+
+// ---------------------------------------------------------- profiling
+struct ProfRec {
+    hipEvent_t a, b;
+    double pairs;
+};
+bool g_prof = false;
+std::vector<ProfRec> g_prof_recs;
+double g_prof_ms = 0.0, g_prof_pairs = 0.0;
+int64_t g_prof_n = 0;
+
+}  // namespace
+
+Shape default_shape(int64_t N, int k, int prec) {
+    Shape s;
+    s.tpl = N >= 65536 ? 2 : 1;
+    s.tile = 256;
+    s.kblk = std::min(kclass(k), prec == RPYW_FP32C ? 16 : 8);
+    return s;
+}
+
+Shape tuned_shape(int64_t N, int k, int prec) {
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    auto it = g_shapes.find({prec, size_class(N), kclass(k)});
+    if (it != g_shapes.end()) return it->second;
+    return default_shape(N, k, prec);
+}
+
+void set_tuned_shape(int64_t N, int k, int prec, Shape s) {
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    g_shapes[{prec, size_class(N), kclass(k)}] = s;
+}
+
+bool profiling_enabled() { return g_prof; }
+
+void profile_begin(hipStream_t st, hipEvent_t* ev) {
+    *ev = nullptr;
+    if (!g_prof) return;
+    if (hipEventCreate(ev) != hipSuccess) {
+        *ev = nullptr;
+        return;
+    }
+    (void)hipEventRecord(*ev, st);
+}
+
+void profile_end(hipStream_t st, hipEvent_t ev0, double pairs) {
+    if (!g_prof || !ev0) return;
+    hipEvent_t ev1;
+    if (hipEventCreate(&ev1) != hipSuccess) return;
+    (void)hipEventRecord(ev1, st);
+    g_prof_recs.push_back({ev0, ev1, pairs});
+}
+
+}  // namespace rpyw
+
+using namespace rpyw;
+
+extern "C" {
+
+const char* rpyw_strerror(int status) {
+    switch (status) {
+        case RPYW_OK: return "ok";
+        case RPYW_NOT_CONVERGED: return "iteration limit reached before the tolerance (best iterate written)";
+        case RPYW_EINVAL: return "invalid argument";
+        case RPYW_EHIP: return "HIP runtime error";
+        case RPYW_ENOMEM: return "workspace too small or device allocation failed";
+        case RPYW_ENOTSPD: return "preconditioner block not positive definite";
+        default: return "unknown status";
+    }
+}
+
+size_t rpy_wall_workspace_bytes(int op, int64_t N, int32_t k, int32_t max_iter, int32_t n_bodies, int precision) {
+    if (N < 1 || N >= kMaxN || !valid_prec(precision)) return 0;
+    switch (op) {
+        case RPYW_OP_MATVEC: {
+            if (k < 1) return 0;
+            return product_ws_bytes(N, precision, std::min(kclass(k), 16));
+        }
+        case RPYW_OP_BATCHED:
+            if (k < 1 || n_bodies < 1) return 0;
+            return batched_ws_bytes(N, n_bodies, k, precision);
+        case RPYW_OP_LANCZOS:
+            if (max_iter < 1) return 0;
+            return lanczos_ws_bytes(N, max_iter, n_bodies, precision);
+        case RPYW_OP_VJP:
+        case RPYW_OP_DIVERGENCE: return vjp_ws_bytes(N, precision);
+        default: return 0;
+    }
+}
+
+int rpy_wall_matvec_multi(const double* pos, const double* F, double* U, int64_t N, int32_t k, double a,
+                          double eta, int precision, void* ws, size_t ws_bytes, void* stream) {
+    if (!pos || !F || !U || N < 1 || N >= kMaxN || k < 1 || k > 4096 || !finite_pos(a) || !finite_pos(eta) ||
+        !valid_prec(precision))
+        return RPYW_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    Scratch s;
+    int rc = acquire(ws, ws_bytes, product_ws_bytes(N, precision, std::min(kclass(k), 16)), st, s);
+    if (rc != RPYW_OK) return rc;
+    return products(pos, F, U, N, k, a, eta, precision, s.ar, st);
+}
+
+int rpy_wall_matvec(const double* pos, const double* force, double* vel, int64_t N, double a, double eta,
+                    int precision, void* ws, size_t ws_bytes, void* stream) {
+    return rpy_wall_matvec_multi(pos, force, vel, N, 1, a, eta, precision, ws, ws_bytes, stream);
+}
+
+int rpy_wall_matvec_batched(const double* pos, const int64_t* sys_offsets, int32_t S, const double* F, double* U,
+                            int32_t k, double a, double eta, int precision, void* ws, size_t ws_bytes,
+                            void* stream) {
+    if (!pos || !sys_offsets || !F || !U || S < 1 || k < 1 || k > 4096 || !finite_pos(a) || !finite_pos(eta) ||
+        !valid_prec(precision))
+        return RPYW_EINVAL;
+    if (sys_offsets[0] != 0) return RPYW_EINVAL;
+    for (int s = 0; s < S; ++s)
+        if (sys_offsets[s + 1] <= sys_offsets[s]) return RPYW_EINVAL;
+    const int64_t Ntot = sys_offsets[S];
+    if (Ntot >= kMaxN) return RPYW_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    Scratch s;
+    int rc = acquire(ws, ws_bytes, batched_ws_bytes(Ntot, S, k, precision), st, s);
+    if (rc != RPYW_OK) return rc;
+    return batched_products(pos, sys_offsets, S, F, U, k, a, eta, precision, s.ar, st);
+}
+
+int rpy_wall_lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, double a, double eta,
+                          const int64_t* body_offsets, int32_t n_bodies, double tol, int32_t max_iter,
+                          int precision, void* ws, size_t ws_bytes, int32_t* iters_out, double* err_est_out,
+                          void* stream) {
+    if (!pos || !W || !out || N < 1 || N >= kMaxN || !finite_pos(a) || !finite_pos(eta) || !valid_prec(precision) ||
+        !finite_pos(tol) || max_iter < 1 || max_iter > 100000)
+        return RPYW_EINVAL;
+    if (body_offsets) {
+        if (n_bodies < 1 || body_offsets[0] != 0 || body_offsets[n_bodies] != N) return RPYW_EINVAL;
+        for (int p = 0; p < n_bodies; ++p) {
+            const int64_t n = body_offsets[p + 1] - body_offsets[p];
+            if (n < 1 || n > kMaxBodyBlobs) return RPYW_EINVAL;
+        }
+    } else {
+        n_bodies = 0;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    Scratch s;
+    int rc = acquire(ws, ws_bytes, lanczos_ws_bytes(N, max_iter, n_bodies, precision), st, s);
+    if (rc != RPYW_OK) return rc;
+    int it = 0;
+    double err = 0.0;
+    rc = lanczos_sqrt(pos, W, out, N, a, eta, body_offsets, n_bodies, tol, max_iter, precision, s.ar, &it, &err, st);
+    if (iters_out) *iters_out = it;
+    if (err_est_out) *err_est_out = err;
+    return rc;
+}
+
+int rpy_wall_matvec_vjp(const double* pos, const double* force, const double* grad_vel, double* grad_pos,
+                        double* grad_force, int64_t N, double a, double eta, int precision, void* ws,
+                        size_t ws_bytes, void* stream) {
+    if (!pos || !force || !grad_vel || (!grad_pos && !grad_force) || N < 1 || N >= kMaxN || !finite_pos(a) ||
+        !finite_pos(eta) || !valid_prec(precision))
+        return RPYW_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    Scratch s;
+    int rc = acquire(ws, ws_bytes, vjp_ws_bytes(N, precision), st, s);
+    if (rc != RPYW_OK) return rc;
+    return vjp(pos, force, grad_vel, grad_pos, grad_force, N, a, eta, precision, s.ar, st);
+}
+
+int rpy_wall_divergence(const double* pos, double* div, int64_t N, double a, double eta, int precision, void* ws,
+                        size_t ws_bytes, void* stream) {
+    if (!pos || !div || N < 1 || N >= kMaxN || !finite_pos(a) || !finite_pos(eta) || !valid_prec(precision))
+        return RPYW_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    Scratch s;
+    int rc = acquire(ws, ws_bytes, vjp_ws_bytes(N, precision), st, s);
+    if (rc != RPYW_OK) return rc;
+    return divergence(pos, div, N, a, eta, precision, s.ar, st);
+}
+
+int rpy_wall_autotune(const double* pos, const double* F, double* U, int64_t N, int32_t k, double a, double eta,
+                      int precision, void* ws, size_t ws_bytes, void* stream) {
+    if (!pos || !F || !U || N < 1 || N >= kMaxN || k < 1 || k > 4096 || !finite_pos(a) || !finite_pos(eta) ||
+        !valid_prec(precision))
+        return RPYW_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const int kc = kclass(k);
+    Scratch s;
+    int rc = acquire(ws, ws_bytes, product_ws_bytes(N, precision, std::min(kc, 16)), st, s);
+    if (rc != RPYW_OK) return rc;
+    hipEvent_t e0, e1;
+    RPYW_HIP(hipEventCreate(&e0));
+    RPYW_HIP(hipEventCreate(&e1));
+    const bool prof = g_prof;
+    g_prof = false;
+    Shape best = default_shape(N, k, precision);
+    double best_t = 1e300;
+    for (int kb = 1; kb <= std::min(kc, 16); kb <<= 1) {
+        if (precision == RPYW_FP64 && kb > 8) continue;
+        for (int tpl = 1; tpl <= 2; ++tpl)
+            for (int tile : {64, 256}) {
+                Shape sh{tpl, tile, kb};
+                float ms = 0.f;
+                for (int rep = 0; rep < 3; ++rep) {
+                    if (rep == 1) RPYW_HIP(hipEventRecord(e0, st));
+                    for (int k0 = 0; k0 < k; k0 += kb) {
+                        const int n = std::min(kb, k - k0);
+                        rc = product_pass(pos, F + (size_t)k0 * N * 3, U + (size_t)k0 * N * 3, N, n, a, eta,
+                                          precision, sh, s.ar, st);
+                        if (rc != RPYW_OK) {
+                            g_prof = prof;
+                            return rc;
+                        }
+                    }
+                }
+                RPYW_HIP(hipEventRecord(e1, st));
+                RPYW_HIP(hipEventSynchronize(e1));
+                RPYW_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best_t) {
+                    best_t = ms;
+                    best = sh;
+                }
+            }
+    }
+    g_prof = prof;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    set_tuned_shape(N, k, precision, best);
+    return RPYW_OK;
+}
+
+int rpyw_tridiag_sqrt_coeffs(const double* alpha, const double* beta, int32_t k, double beta0, double* c_out) {
+    if (!alpha || !c_out || k < 1 || (k > 1 && !beta) || !std::isfinite(beta0)) return RPYW_EINVAL;
+    for (int i = 0; i < k; ++i)
+        if (!std::isfinite(alpha[i]) || (i + 1 < k && !std::isfinite(beta[i]))) return RPYW_EINVAL;
+    return tridiag_sqrt_coeffs(alpha, beta, k, beta0, c_out);
+}
+
+int rpy_wall_profile_enable(int enable) {
+    g_prof = enable != 0;
+    return RPYW_OK;
+}
+
+int rpy_wall_profile_read(double* ms_total, int64_t* launches, double* pair_interactions, int reset) {
+    for (auto& r : g_prof_recs) {
+        float ms = 0.f;
+        RPYW_HIP(hipEventSynchronize(r.b));
+        RPYW_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        g_prof_ms += ms;
+        g_prof_pairs += r.pairs;
+        g_prof_n += 1;
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_prof_recs.clear();
+    if (ms_total) *ms_total = g_prof_ms;
+    if (launches) *launches = g_prof_n;
+    if (pair_interactions) *pair_interactions = g_prof_pairs;
+    if (reset) {
+        g_prof_ms = 0.0;
+        g_prof_pairs = 0.0;
+        g_prof_n = 0;
+    }
+    return RPYW_OK;
+}
+
+}  // extern "C"

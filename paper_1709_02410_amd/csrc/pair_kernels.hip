@@ -1,0 +1,493 @@
+// Dense O(N^2) products u = M(r) f of the wall-corrected RPY blob mobility
+// (arXiv:1709.02410, Sec. II.A: direct summation over all blob pairs, the
+// operation whose cost dominates every Brownian-dynamics step).
+//
+// Pipeline per pass of kb right-hand sides:
+//   pack      O(N):   AoS FP64 [N][3] -> one record per blob in the kernel
+//                     precision: scaled position (x, y, z~) (+ FP32 low parts
+//                     of x and y), then B_j f_j for each RHS.
+//   pair      O(N^2): workgroup = 256*TPL targets x one source chunk; source
+//                     records are staged through LDS tiles, every lane keeps
+//                     its targets' sums in registers.  FP32 sums are plain
+//                     within a tile and folded into a TwoSum (hi, lo) pair
+//                     after each tile.  Partial sums per source chunk go to
+//                     the workspace.
+//   epilogue  O(N):   fixed-order sum of the chunk partials, times
+//                     mu0 * B_i, written as FP64 [N][3].
+// No floating-point atomics: results are bitwise reproducible for a fixed
+// launch shape.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "pair_math.h"
+#include "rpyw_internal.h"
+
+namespace rpyw {
+
+namespace {
+
+template <typename R>
+constexpr int pos_slots() {
+    return sizeof(R) == 4 ? 5 : 3;
+}
+template <typename R, int K>
+constexpr int rec_w() {
+    return sizeof(R) == 4 ? (5 + 3 * K + 3) / 4 * 4 : (3 + 3 * K + 1) / 2 * 2;
+}
+
+// Records for blobs [0, N); F points at the first of kb RHS ([kb][N][3]).
+template <typename R>
+__global__ void pack_kernel(const double* __restrict__ pos, const double* __restrict__ F, int64_t N, int kb,
+                            int recw, double inv_a, R* __restrict__ rec, double* __restrict__ Bout) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double x = pos[3 * i] * inv_a, y = pos[3 * i + 1] * inv_a, z = pos[3 * i + 2] * inv_a;
+    const double B = z < 1.0 ? z : 1.0;
+    const double zt = z < 1.0 ? 1.0 : z;
+    R* r = rec + i * recw;
+    int o;
+    if constexpr (sizeof(R) == 4) {
+        const float xh = (float)x, yh = (float)y;
+        r[0] = xh;
+        r[1] = yh;
+        r[2] = (float)zt;
+        r[3] = (float)(x - (double)xh);
+        r[4] = (float)(y - (double)yh);
+        o = 5;
+    } else {
+        r[0] = x;
+        r[1] = y;
+        r[2] = zt;
+        o = 3;
+    }
+    for (int k = 0; k < kb; ++k)
+        for (int c = 0; c < 3; ++c) r[o + 3 * k + c] = (R)(B * F[(k * N + i) * 3 + c]);
+    for (int e = o + 3 * kb; e < recw; ++e) r[e] = R(0);
+    if (Bout) Bout[i] = B;
+}
+
+// Targets held by one lane.
+template <typename R, int K, int TPL>
+struct Lane {
+    R x[TPL], y[TPL], z[TPL], xl[TPL], yl[TPL];
+    R acc[TPL][K][3];
+    R hi[TPL][K][3], lo[TPL][K][3];  // FP32 compensated running sums
+
+    __device__ void load(const R* __restrict__ rec, int64_t first, int64_t last, int64_t tid) {
+        constexpr int RW = rec_w<R, K>();
+#pragma unroll
+        for (int t = 0; t < TPL; ++t) {
+            int64_t i = first + (int64_t)t * kBlock + tid;
+            if (i >= last) i = last - 1;
+            const R* r = rec + i * RW;
+            x[t] = r[0];
+            y[t] = r[1];
+            z[t] = r[2];
+            if constexpr (sizeof(R) == 4) {
+                xl[t] = r[3];
+                yl[t] = r[4];
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    acc[t][k][c] = R(0);
+                    hi[t][k][c] = R(0);
+                    lo[t][k][c] = R(0);
+                }
+        }
+    }
+
+    // Sum over sources [s0, s1) staged through the LDS tile.
+    template <int TILE>
+    __device__ void run(const R* __restrict__ rec, int64_t s0, int64_t s1, R* tile) {
+        constexpr int RW = rec_w<R, K>();
+        constexpr int PW = pos_slots<R>();
+        for (int64_t t0 = s0; t0 < s1; t0 += TILE) {
+            const int n = (int)((s1 - t0) < TILE ? (s1 - t0) : TILE);
+            __syncthreads();
+            const R* g = rec + t0 * RW;
+            for (int e = threadIdx.x; e < n * RW; e += kBlock) tile[e] = g[e];
+            __syncthreads();
+#pragma unroll 2
+            for (int j = 0; j < n; ++j) {
+                const R* s = tile + j * RW;
+                const R sx = s[0], sy = s[1], sz = s[2];
+                R sxl = R(0), syl = R(0);
+                if constexpr (sizeof(R) == 4) {
+                    sxl = s[3];
+                    syl = s[4];
+                }
+#pragma unroll
+                for (int t = 0; t < TPL; ++t) {
+                    R dx = x[t] - sx, dy = y[t] - sy;
+                    if constexpr (sizeof(R) == 4) {
+                        dx += xl[t] - sxl;
+                        dy += yl[t] - syl;
+                    }
+                    const R dz = z[t] - sz;
+                    const PairCoef<R> p = pair_coef<R>(dx, dy, dz, z[t], sz);
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+                        pair_apply<R>(p, dx, dy, dz, s[PW + 3 * k], s[PW + 3 * k + 1], s[PW + 3 * k + 2],
+                                      acc[t][k][0], acc[t][k][1], acc[t][k][2]);
+                }
+            }
+            if constexpr (sizeof(R) == 4) {
+#pragma unroll
+                for (int t = 0; t < TPL; ++t)
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            two_sum_acc(hi[t][k][c], lo[t][k][c], acc[t][k][c]);
+                            acc[t][k][c] = R(0);
+                        }
+            }
+        }
+    }
+
+    __device__ double total(int t, int k, int c) const {
+        if constexpr (sizeof(R) == 4)
+            return (double)hi[t][k][c] + (double)lo[t][k][c];
+        else
+            return (double)acc[t][k][c];
+    }
+};
+
+// Plain product: block b -> (source chunk b % splits, target block b / splits).
+// With splits a multiple of 8, all workgroups of one XCD (dispatched
+// round-robin by block index) read the same source chunk.
+template <typename R, int K, int TPL, int TILE>
+__global__ __launch_bounds__(kBlock) void pair_kernel(const R* __restrict__ rec, int64_t N, int splits,
+                                                      int64_t chunk, double* __restrict__ part) {
+    __shared__ __attribute__((aligned(16))) R tile[TILE * rec_w<R, K>()];
+    const int b = blockIdx.x;
+    const int split = b % splits;
+    const int64_t first = (int64_t)(b / splits) * kBlock * TPL;
+    const int64_t s0 = (int64_t)split * chunk;
+    const int64_t s1 = s0 + chunk < N ? s0 + chunk : N;
+    Lane<R, K, TPL> L;
+    L.load(rec, first, N, threadIdx.x);
+    L.template run<TILE>(rec, s0, s1, tile);
+#pragma unroll
+    for (int t = 0; t < TPL; ++t) {
+        const int64_t i = first + (int64_t)t * kBlock + threadIdx.x;
+        if (i >= N) continue;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) part[((int64_t)(split * K + k) * 3 + c) * N + i] = L.total(t, k, c);
+    }
+}
+
+// U[k][i][c] = mu0 B_i sum_s part[s][k][c][i] for k < kb (fixed order in s).
+__global__ void epilogue_kernel(const double* __restrict__ part, const double* __restrict__ B, int64_t N, int kdim,
+                                int kb, int splits, double mu0, double* __restrict__ U) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double sc = mu0 * B[i];
+    for (int k = 0; k < kb; ++k)
+        for (int c = 0; c < 3; ++c) {
+            double s = 0.0;
+            for (int p = 0; p < splits; ++p) s += part[((int64_t)(p * kdim + k) * 3 + c) * N + i];
+            U[((int64_t)k * N + i) * 3 + c] = sc * s;
+        }
+}
+
+// Batched systems: persistent workgroups take items {sys_begin, sys_end,
+// target_begin} from an atomic counter; every item covers all sources of its
+// system and writes final velocities.
+template <typename R, int K, int TPL, int TILE>
+__global__ __launch_bounds__(kBlock) void batched_kernel(const R* __restrict__ rec, const int4* __restrict__ items,
+                                                         int n_items, unsigned* __restrict__ counter,
+                                                         const double* __restrict__ B, double mu0, int64_t Ntot,
+                                                         int kb, double* __restrict__ U) {
+    __shared__ __attribute__((aligned(16))) R tile[TILE * rec_w<R, K>()];
+    __shared__ int s_item;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int item = s_item;
+        if (item >= n_items) break;
+        const int4 it = items[item];
+        Lane<R, K, TPL> L;
+        L.load(rec, it.z, it.y, threadIdx.x);
+        L.template run<TILE>(rec, it.x, it.y, tile);
+#pragma unroll
+        for (int t = 0; t < TPL; ++t) {
+            const int64_t i = (int64_t)it.z + (int64_t)t * kBlock + threadIdx.x;
+            if (i >= it.y) continue;
+            const double sc = mu0 * B[i];
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    if (k < kb) U[((int64_t)k * Ntot + i) * 3 + c] = sc * L.total(t, k, c);
+        }
+    }
+}
+
+__global__ void zero_u32(unsigned* p) { *p = 0u; }
+
+// ------------------------------------------------------------ dispatch
+
+template <typename R, int K, int TPL, int TILE>
+hipError_t launch_pair_t(const R* rec, int64_t N, int splits, int64_t chunk, double* part, int64_t nblocks,
+                         hipStream_t st) {
+    hipLaunchKernelGGL((pair_kernel<R, K, TPL, TILE>), dim3((unsigned)nblocks), dim3(kBlock), 0, st, rec, N, splits,
+                       chunk, part);
+    return hipGetLastError();
+}
+
+template <typename R, int K, int TPL, int TILE>
+hipError_t launch_batched_t(const R* rec, const int4* items, int n_items, unsigned* counter, const double* B,
+                            double mu0, int64_t Ntot, int kb, double* U, int grid, hipStream_t st) {
+    hipLaunchKernelGGL((batched_kernel<R, K, TPL, TILE>), dim3(grid), dim3(kBlock), 0, st, rec, items, n_items,
+                       counter, B, mu0, Ntot, kb, U);
+    return hipGetLastError();
+}
+
+// Expand (K, TPL, TILE) runtime values into template instantiations.
+#define RPYW_DISPATCH(R, K, TPL, TILE, FN, ...)                                   \
+    [&]() -> hipError_t {                                                         \
+        auto tiles = [&](auto kc, auto tc) -> hipError_t {                        \
+            constexpr int KK = decltype(kc)::value;                               \
+            constexpr int TT = decltype(tc)::value;                               \
+            if ((TILE) == 64) return FN<R, KK, TT, 64>(__VA_ARGS__);              \
+            return FN<R, KK, TT, 256>(__VA_ARGS__);                               \
+        };                                                                        \
+        auto tpls = [&](auto kc) -> hipError_t {                                  \
+            if ((TPL) == 2) return tiles(kc, std::integral_constant<int, 2>{});   \
+            return tiles(kc, std::integral_constant<int, 1>{});                   \
+        };                                                                        \
+        auto one = [&](auto kc) -> hipError_t {                                   \
+            return tiles(kc, std::integral_constant<int, 1>{});                   \
+        };                                                                        \
+        switch (K) {                                                              \
+            case 1: return tpls(std::integral_constant<int, 1>{});                \
+            case 2: return tpls(std::integral_constant<int, 2>{});                \
+            case 4: return tpls(std::integral_constant<int, 4>{});                \
+            case 8: return one(std::integral_constant<int, 8>{});                 \
+            default:                                                              \
+                if constexpr (sizeof(R) == 8) return one(std::integral_constant<int, 8>{}); \
+                else return one(std::integral_constant<int, 16>{});               \
+        }                                                                         \
+    }()
+
+int pow2ceil(int k) {
+    int p = 1;
+    while (p < k) p <<= 1;
+    return p;
+}
+
+// RHS block width of the kernel instantiation that serves kb right-hand
+// sides (FP64 stops at 8: wider blocks do not fit the register file).
+int kernel_k(int kb, int prec) { return std::min(pow2ceil(kb), prec == RPYW_FP32C ? 16 : 8); }
+
+double mu0_of(double a, double eta) { return 1.0 / (6.0 * M_PI * eta * a); }
+
+}  // namespace
+
+// ------------------------------------------------------------ host side
+
+void split_plan(int64_t N, int tpl, int* splits, int64_t* chunk) {
+    const int64_t ntb = (N + (int64_t)kBlock * tpl - 1) / ((int64_t)kBlock * tpl);
+    const int64_t want_wg = 2048;
+    int64_t s = (want_wg + ntb - 1) / ntb;
+    const int64_t max_s = std::max<int64_t>(1, N / 64);
+    if (s > max_s) s = max_s;
+    if (s > 8) s = (s + 7) / 8 * 8;
+    if (s < 1) s = 1;
+    int64_t c = (N + s - 1) / s;
+    s = (N + c - 1) / c;
+    *splits = (int)s;
+    *chunk = c;
+}
+
+size_t product_ws_bytes(int64_t N, int prec, int kblk) {
+    int s1, s2;
+    int64_t c;
+    split_plan(N, 1, &s1, &c);
+    split_plan(N, 2, &s2, &c);
+    const int smax = std::max(s1, s2);
+    size_t b = align_up((size_t)N * rec_width(prec, kblk) * real_size(prec));
+    b += align_up((size_t)N * sizeof(double));
+    b += align_up((size_t)smax * kblk * 3 * N * sizeof(double));
+    return b + 4 * kAlign;
+}
+
+int product_pass(const double* pos, const double* F, double* U, int64_t N, int kb, double a, double eta, int prec,
+                 Shape sh, Arena& ar, hipStream_t st) {
+    const size_t mark = ar.used;
+    const int K = kernel_k(kb, prec);
+    if (kb < 1 || kb > K) return RPYW_EINVAL;
+    const int rw = rec_width(prec, K);
+    void* rec = ar.take((size_t)N * rw * real_size(prec));
+    double* B = (double*)ar.take((size_t)N * sizeof(double));
+    int splits;
+    int64_t chunk;
+    split_plan(N, sh.tpl, &splits, &chunk);
+    double* part = (double*)ar.take((size_t)splits * K * 3 * N * sizeof(double));
+    if (!rec || !B || !part) {
+        ar.used = mark;
+        return RPYW_ENOMEM;
+    }
+    const unsigned g1 = (unsigned)((N + kBlock - 1) / kBlock);
+    if (prec == RPYW_FP32C)
+        hipLaunchKernelGGL(pack_kernel<float>, dim3(g1), dim3(kBlock), 0, st, pos, F, N, kb, rw, 1.0 / a, (float*)rec,
+                           B);
+    else
+        hipLaunchKernelGGL(pack_kernel<double>, dim3(g1), dim3(kBlock), 0, st, pos, F, N, kb, rw, 1.0 / a,
+                           (double*)rec, B);
+    RPYW_HIP(hipGetLastError());
+    const int64_t ntb = (N + (int64_t)kBlock * sh.tpl - 1) / ((int64_t)kBlock * sh.tpl);
+    const int64_t nblocks = ntb * splits;
+    hipEvent_t ev = nullptr;
+    profile_begin(st, &ev);
+    hipError_t e;
+    if (prec == RPYW_FP32C)
+        e = RPYW_DISPATCH(float, K, sh.tpl, sh.tile, launch_pair_t, (const float*)rec, N, splits, chunk, part, nblocks,
+                          st);
+    else
+        e = RPYW_DISPATCH(double, K, sh.tpl, sh.tile, launch_pair_t, (const double*)rec, N, splits, chunk, part,
+                          nblocks, st);
+    if (e != hipSuccess) return RPYW_EHIP;
+    profile_end(st, ev, (double)kb * (double)N * (double)N);
+    hipLaunchKernelGGL(epilogue_kernel, dim3(g1), dim3(kBlock), 0, st, part, B, N, K, kb, splits, mu0_of(a, eta), U);
+    RPYW_HIP(hipGetLastError());
+    ar.used = mark;
+    return RPYW_OK;
+}
+
+int products(const double* pos, const double* F, double* U, int64_t N, int k, double a, double eta, int prec,
+             Arena& ar, hipStream_t st) {
+    const Shape sh = tuned_shape(N, k, prec);
+    for (int k0 = 0; k0 < k; k0 += sh.kblk) {
+        const int kb = std::min(sh.kblk, k - k0);
+        const int rc = product_pass(pos, F + (size_t)k0 * N * 3, U + (size_t)k0 * N * 3, N, kb, a, eta, prec, sh, ar,
+                                    st);
+        if (rc != RPYW_OK) return rc;
+    }
+    return RPYW_OK;
+}
+
+// ------------------------------------------------------------ batched
+
+namespace {
+
+// Pinned staging for small host->device uploads that must stay asynchronous.
+struct Staging {
+    std::mutex mu;
+    void* host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+};
+Staging g_stage;
+
+int upload_async(const void* src, size_t bytes, void* dst, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_stage.mu);
+    if (g_stage.done) RPYW_HIP(hipEventSynchronize(g_stage.done));
+    if (bytes > g_stage.cap) {
+        if (g_stage.host) RPYW_HIP(hipHostFree(g_stage.host));
+        g_stage.host = nullptr;
+        g_stage.cap = 0;
+        RPYW_HIP(hipHostMalloc(&g_stage.host, bytes, hipHostMallocDefault));
+        g_stage.cap = bytes;
+    }
+    if (!g_stage.done) RPYW_HIP(hipEventCreateWithFlags(&g_stage.done, hipEventDisableTiming));
+    std::memcpy(g_stage.host, src, bytes);
+    RPYW_HIP(hipMemcpyAsync(dst, g_stage.host, bytes, hipMemcpyHostToDevice, st));
+    RPYW_HIP(hipEventRecord(g_stage.done, st));
+    return RPYW_OK;
+}
+
+}  // namespace
+
+size_t batched_ws_bytes(int64_t Ntot, int S, int k, int prec) {
+    const int kb = kernel_k(std::max(k, 1), prec);
+    size_t b = align_up((size_t)Ntot * rec_width(prec, kb) * real_size(prec));
+    b += align_up((size_t)Ntot * sizeof(double));
+    const size_t max_items = (size_t)(Ntot / kBlock) + (size_t)S + 1;
+    b += align_up(max_items * sizeof(int4));
+    b += kAlign;  // counter
+    return b + 4 * kAlign;
+}
+
+int batched_products(const double* pos, const int64_t* sys_offsets, int S, const double* F, double* U, int k,
+                     double a, double eta, int prec, Arena& ar, hipStream_t st) {
+    const int64_t Ntot = sys_offsets[S];
+    int64_t nmax = 0;
+    for (int s = 0; s < S; ++s) nmax = std::max(nmax, sys_offsets[s + 1] - sys_offsets[s]);
+    const Shape sh = tuned_shape(nmax, k, prec);
+    // Work list in LPT order: systems by decreasing size, then their tiles.
+    std::vector<int> order(S);
+    for (int s = 0; s < S; ++s) order[s] = s;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return sys_offsets[x + 1] - sys_offsets[x] > sys_offsets[y + 1] - sys_offsets[y];
+    });
+    const int span = kBlock * sh.tpl;
+    std::vector<int4> items;
+    for (int s : order) {
+        const int b0 = (int)sys_offsets[s], b1 = (int)sys_offsets[s + 1];
+        for (int t = b0; t < b1; t += span) items.push_back(make_int4(b0, b1, t, 0));
+    }
+    const size_t mark = ar.used;
+    const int K = kernel_k(sh.kblk, prec);
+    if (sh.kblk > K) return RPYW_EINVAL;
+    const int rw = rec_width(prec, K);
+    void* rec = ar.take((size_t)Ntot * rw * real_size(prec));
+    double* B = (double*)ar.take((size_t)Ntot * sizeof(double));
+    int4* ditems = (int4*)ar.take(items.size() * sizeof(int4));
+    unsigned* counter = (unsigned*)ar.take(sizeof(unsigned));
+    if (!rec || !B || !ditems || !counter) {
+        ar.used = mark;
+        return RPYW_ENOMEM;
+    }
+    int rc = upload_async(items.data(), items.size() * sizeof(int4), ditems, st);
+    if (rc != RPYW_OK) return rc;
+    int dev = 0, ncu = 256;
+    RPYW_HIP(hipGetDevice(&dev));
+    RPYW_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int grid = (int)std::min<size_t>(items.size(), (size_t)ncu * 4);
+    const unsigned g1 = (unsigned)((Ntot + kBlock - 1) / kBlock);
+    const double m0 = mu0_of(a, eta);
+    double pairs = 0.0;
+    for (int s = 0; s < S; ++s) {
+        const double n = (double)(sys_offsets[s + 1] - sys_offsets[s]);
+        pairs += n * n;
+    }
+    for (int k0 = 0; k0 < k; k0 += sh.kblk) {
+        const int kb = std::min(sh.kblk, k - k0);
+        const double* Fk = F + (size_t)k0 * Ntot * 3;
+        double* Uk = U + (size_t)k0 * Ntot * 3;
+        if (prec == RPYW_FP32C)
+            hipLaunchKernelGGL(pack_kernel<float>, dim3(g1), dim3(kBlock), 0, st, pos, Fk, Ntot, kb, rw, 1.0 / a,
+                               (float*)rec, B);
+        else
+            hipLaunchKernelGGL(pack_kernel<double>, dim3(g1), dim3(kBlock), 0, st, pos, Fk, Ntot, kb, rw, 1.0 / a,
+                               (double*)rec, B);
+        RPYW_HIP(hipGetLastError());
+        hipLaunchKernelGGL(zero_u32, dim3(1), dim3(1), 0, st, counter);
+        RPYW_HIP(hipGetLastError());
+        hipEvent_t ev = nullptr;
+        profile_begin(st, &ev);
+        hipError_t e;
+        if (prec == RPYW_FP32C)
+            e = RPYW_DISPATCH(float, K, sh.tpl, sh.tile, launch_batched_t, (const float*)rec, ditems,
+                              (int)items.size(), counter, B, m0, Ntot, kb, Uk, grid, st);
+        else
+            e = RPYW_DISPATCH(double, K, sh.tpl, sh.tile, launch_batched_t, (const double*)rec, ditems,
+                              (int)items.size(), counter, B, m0, Ntot, kb, Uk, grid, st);
+        if (e != hipSuccess) return RPYW_EHIP;
+        profile_end(st, ev, kb * pairs);
+    }
+    ar.used = mark;
+    return RPYW_OK;
+}
+
+}  // namespace rpyw

@@ -1,0 +1,158 @@
+// Device-side pair arithmetic of the wall-corrected RPY blob mobility
+// (arXiv:1709.02410, Sec. II.A: Rotne-Prager-Yamakawa blocks with the
+// no-slip wall correction of the Rotne-Prager-Blake tensor; Sec. IV opening:
+// overlap regularisations keeping M SPD).
+//
+// Everything here works in units where the blob radius is 1 and M is measured
+// in mu0 = 1/(6 pi eta a): positions arrive pre-divided by a with heights
+// already regularised (z~ = max(z, a)), forces arrive pre-multiplied by
+// B = min(z/a, 1), and the caller multiplies sums by mu0 * B_target.
+//
+// Notation per pair (target i, source j):
+//   d = r~_i - r~_j = (dx, dy, dz), r2 = |d|^2          (free RPY part)
+//   R = r~_i - mirror(r~_j) = (dx, dy, Rz), Rz = z_i + z_j, R2 = |R|^2
+//   w = 1/|R|, X = w^2, zz = z_i z_j                      (image part)
+// The wall correction, written in q = Rz w, p = z_j w, s = X, is rearranged
+// as polynomials in X whose coefficients depend on Rz^2 and zz only:
+//   |R| A  = -3/4 + X(-3/2 zz - 1/2 + X(3/2 Rz2 + 1/2 - 5/2 Rz2 X))
+//   |R| B  = -3/4 + X( 9/2 zz + 3/2 + X(-15/2 Rz2 - 5/2 + 35/2 Rz2 X))
+//   |R| C  = -3/4 dz + Rz X (-(9/2 zz + 3/2) + X(15/2 (Rz2 + 1) - 35/2 Rz2 X))
+//   |R| C' = -3/4 dz - Rz X (same bracket)
+//   |R| E  = -3/4 + X(e1 + X(e2 + X(e3 + X e4))),
+//            e1 = -3/4 Rz2 + 3/2 zz - 1/2, e2 = -Rz2 (9/2 zz + 3) - 3/2,
+//            e3 = Rz2 (15/2 Rz2 + 15), e4 = -35/2 Rz2^2
+// (using q p - p^2 = zz X, the identity that removes p).  The block acts as
+//   (Mf)_x = (c1 + w A') f_x + dx [c2 (d.f) + w X (B' G + C' f_z)]   (same y)
+//   (Mf)_z = (c1 + w E') f_z + c2 (d.f) dz + w X (Cm' G)
+// with G = dx f_x + dy f_y and primes denoting the |R|-scaled coefficients;
+// the free RPY coefficients are c1, c2 with c2 already divided by r2:
+//   r > 2: c1 = 3/(4r) + 1/(2r^3),  c2 = 3/(4r^3) - 3/(2r^5)
+//   r <= 2: c1 = 1 - 9r/32,          c2 = 3/(32 r);   r = 0: c1 = 1, c2 = 0.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace rpyw {
+
+// Fused multiply-add in the precision of the operands.
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename R>
+__device__ __forceinline__ R rsq(R x);
+
+// FP32: the hardware reciprocal square root (about 1 ulp).
+template <>
+__device__ __forceinline__ float rsq<float>(float x) {
+    return __builtin_amdgcn_rsqf(x);
+}
+
+// FP64: hardware estimate refined by one third-order (Householder) step,
+// y <- y + y e (1/2 + 3/8 e) with e = 1 - x y^2, which triples the number of
+// correct bits of the estimate.
+template <>
+__device__ __forceinline__ double rsq<double>(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = __builtin_fma(-x * y, y, 1.0);
+    return __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
+}
+
+// Geometry shared by every right-hand side of one pair.
+template <typename R>
+struct PairCoef {
+    R c1;   // free identity coefficient
+    R c2;   // free d d^T coefficient (divided by r2)
+    R cc;   // c1 + w |R|A   (in-plane diagonal)
+    R cz;   // c1 + w |R|E   (normal diagonal)
+    R kb;   // w X |R|B
+    R kcp;  // w X |R|C      (in-plane velocity from normal force)
+    R kcm;  // w X |R|C'     (normal velocity from in-plane force)
+};
+
+// Evaluate the pair coefficients.  dx, dy, dz: target minus source;
+// zi, zj: regularised heights.
+template <typename R>
+__device__ __forceinline__ PairCoef<R> pair_coef(R dx, R dy, R dz, R zi, R zj) {
+    PairCoef<R> o;
+    const R rz = zi + zj;
+    const R h2 = fma_(dy, dy, dx * dx);
+    const R r2 = fma_(dz, dz, h2);
+    const R rz2 = rz * rz;
+    const R R2 = h2 + rz2;
+    const R w = rsq<R>(R2);
+    const R X = w * w;
+    const R wX = w * X;
+    // free RPY, far branch (r > 2)
+    const R ir = rsq<R>(r2);
+    const R ir2 = ir * ir;
+    R c1 = ir * fma_(ir2, R(0.5), R(0.75));
+    R c2 = (ir * ir2) * fma_(ir2, R(-1.5), R(0.75));
+    // Overlap branch (r <= 2a), entered by the whole wave when any lane has
+    // an overlapping pair (rare: self pairs and touching neighbours); the
+    // guard keeps r = 0 finite (c1 = 1, c2 d = 0).
+    const bool near = r2 <= R(4);
+    if (__builtin_amdgcn_ballot_w64(near)) {
+        __asm__ volatile("" ::: "memory");  // keep this a branch: do not speculate it
+        const R irg = rsq<R>(r2 > R(1e-30) ? r2 : R(1e-30));
+        const R c1n = fma_(R(-9.0 / 32.0), r2 * irg, R(1));
+        const R c2n = R(3.0 / 32.0) * irg;
+        c1 = near ? c1n : c1;
+        c2 = near ? c2n : c2;
+    }
+    const R zz = zi * zj;
+    // |R| A
+    const R a1 = fma_(zz, R(-1.5), R(-0.5));
+    const R a2 = fma_(rz2, R(1.5), R(0.5));
+    const R a3 = rz2 * R(-2.5);
+    const R rA = fma_(X, fma_(X, fma_(X, a3, a2), a1), R(-0.75));
+    // |R| B
+    const R b1 = fma_(zz, R(4.5), R(1.5));
+    const R b2 = fma_(rz2, R(-7.5), R(-2.5));
+    const R b3 = rz2 * R(17.5);
+    const R rB = fma_(X, fma_(X, fma_(X, b3, b2), b1), R(-0.75));
+    // |R| C and |R| C' = U +- V
+    const R v2 = fma_(rz2, R(7.5), R(7.5));
+    const R pv = fma_(X, fma_(-X, b3, v2), -b1);
+    const R vw = (rz * X) * pv;
+    const R cw = dz * R(-0.75);
+    // |R| E
+    const R e1 = fma_(zz, R(1.5), fma_(rz2, R(-0.75), R(-0.5)));
+    const R e2 = fma_(rz2, fma_(zz, R(-4.5), R(-3.0)), R(-1.5));
+    const R e3 = rz2 * fma_(rz2, R(7.5), R(15.0));
+    const R e4 = (rz2 * rz2) * R(-17.5);
+    const R rE = fma_(
+        X, fma_(X, fma_(X, fma_(X, e4, e3), e2), e1), R(-0.75));
+    o.c1 = c1;
+    o.c2 = c2;
+    o.cc = fma_(w, rA, c1);
+    o.cz = fma_(w, rE, c1);
+    o.kb = wX * rB;
+    o.kcp = wX * (cw + vw);
+    o.kcm = wX * (cw - vw);
+    return o;
+}
+
+// Accumulate M_ij f_j (units of mu0, B factors excluded) into (ux, uy, uz).
+template <typename R>
+__device__ __forceinline__ void pair_apply(const PairCoef<R>& p, R dx, R dy, R dz, R fx, R fy, R fz, R& ux,
+                                           R& uy, R& uz) {
+    const R G = fma_(dy, fy, dx * fx);
+    const R D = fma_(dz, fz, G);
+    const R t0 = p.c2 * D;
+    const R t = fma_(p.kcp, fz, fma_(p.kb, G, t0));
+    ux = fma_(t, dx, fma_(p.cc, fx, ux));
+    uy = fma_(t, dy, fma_(p.cc, fy, uy));
+    uz = fma_(t0, dz, fma_(p.kcm, G, fma_(p.cz, fz, uz)));
+}
+
+// Knuth's TwoSum: s + e == a + b exactly (round-to-nearest, no reassociation).
+template <typename R>
+__device__ __forceinline__ void two_sum_acc(R& hi, R& lo, R b) {
+    const R s = hi + b;
+    const R bp = s - hi;
+    const R ap = s - bp;
+    lo += (hi - ap) + (b - bp);
+    hi = s;
+}
+
+}  // namespace rpyw

@@ -1,0 +1,97 @@
+// Host-side internals shared by the translation units of librpywall.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/rpywall.h"
+
+namespace rpyw {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
+constexpr int kMaxBodyBlobs = 42;    // largest body the preconditioner takes
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
+
+// Launch shape of the pair kernels.
+struct Shape {
+    int tpl;   // targets per lane: 1 or 2
+    int tile;  // sources per LDS tile: 64 or 256
+    int kblk;  // right-hand sides per pass: 1, 2, 4, 8 or 16
+};
+
+// Bump allocator over a caller workspace.
+struct Arena {
+    char* base;
+    size_t size;
+    size_t used;
+    void* take(size_t bytes) {
+        size_t off = align_up(used);
+        if (off + bytes > size) return nullptr;
+        used = off + bytes;
+        return base + off;
+    }
+};
+
+// Record width (elements of the kernel precision) of one preprocessed blob.
+inline int rec_width(int prec, int kblk) {
+    if (prec == RPYW_FP32C) return (5 + 3 * kblk + 3) / 4 * 4;
+    return (3 + 3 * kblk + 1) / 2 * 2;
+}
+inline size_t real_size(int prec) { return prec == RPYW_FP32C ? 4 : 8; }
+
+// Number of source splits of the plain product and the chunk length.
+void split_plan(int64_t N, int tpl, int* splits, int64_t* chunk);
+
+// Workspace bytes of one product pass of width kblk (upper bound over the
+// shapes the tuner may pick).
+size_t product_ws_bytes(int64_t N, int prec, int kblk);
+
+// u-block products: U[k0..k0+kb) = M F[k0..k0+kb); kb <= shape.kblk.
+// pre: preprocessed records already hold positions; forces are (re)packed.
+int product_pass(const double* pos, const double* F, double* U, int64_t N, int kb, double a, double eta, int prec,
+                 Shape shape, Arena& ar, hipStream_t st);
+
+// Full multi-RHS product with the tuned or default shape.
+int products(const double* pos, const double* F, double* U, int64_t N, int k, double a, double eta, int prec,
+             Arena& ar, hipStream_t st);
+
+// Batched independent systems (persistent kernel, LPT work list).
+size_t batched_ws_bytes(int64_t Ntot, int S, int k, int prec);
+int batched_products(const double* pos, const int64_t* sys_offsets, int S, const double* F, double* U, int k,
+                     double a, double eta, int prec, Arena& ar, hipStream_t st);
+
+// Shape selection.
+Shape default_shape(int64_t N, int k, int prec);
+Shape tuned_shape(int64_t N, int k, int prec);
+void set_tuned_shape(int64_t N, int k, int prec, Shape s);
+
+// Instrumentation around the O(N^2) launches.
+bool profiling_enabled();
+void profile_begin(hipStream_t st, hipEvent_t* ev);
+void profile_end(hipStream_t st, hipEvent_t ev0, double pairs);
+
+// Lanczos (lanczos.hip)
+size_t lanczos_ws_bytes(int64_t N, int max_iter, int n_bodies, int prec);
+int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, double a, double eta,
+                 const int64_t* body_offsets, int n_bodies, double tol, int max_iter, int prec, Arena& ar,
+                 int* iters, double* err, hipStream_t st);
+int tridiag_sqrt_coeffs(const double* alpha, const double* beta, int k, double beta0, double* c);
+
+// Derivatives (vjp.hip)
+size_t vjp_ws_bytes(int64_t N, int prec);
+int vjp(const double* pos, const double* f, const double* g, double* grad_pos, double* grad_f, int64_t N, double a,
+        double eta, int prec, Arena& ar, hipStream_t st);
+int divergence(const double* pos, double* div, int64_t N, double a, double eta, int prec, Arena& ar,
+               hipStream_t st);
+
+#define RPYW_HIP(call)                          \
+    do {                                        \
+        hipError_t e_ = (call);                 \
+        if (e_ != hipSuccess) return RPYW_EHIP; \
+    } while (0)
+
+}  // namespace rpyw

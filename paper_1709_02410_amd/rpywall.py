@@ -1,0 +1,261 @@
+"""Python binding of librpywall.so (the C ABI in include/rpywall.h).
+
+Argument marshalling only: tensors are checked (float64, contiguous, on the
+GPU), a workspace is taken from PyTorch's caching allocator, and the C entry
+point is called on PyTorch's current HIP stream.  Every step of the
+computation runs in the library's HIP kernels; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librpywall.so")
+
+FP64 = 0
+FP32C = 1
+OP_MATVEC, OP_BATCHED, OP_LANCZOS, OP_VJP, OP_DIVERGENCE = range(5)
+
+OK, NOT_CONVERGED, EINVAL, EHIP, ENOMEM, ENOTSPD = 0, 1, -1, -2, -3, -4
+
+_c_dp = ctypes.c_void_p
+_lib = None
+
+
+class RpywError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {lib().rpyw_strerror(status).decode()} (status {status})")
+
+
+def lib():
+    """Load librpywall.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1709_02410_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    i64, i32, dbl, sz, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    sig = {
+        "rpy_wall_matvec": [vp, vp, vp, i64, dbl, dbl, ctypes.c_int, vp, sz, vp],
+        "rpy_wall_matvec_multi": [vp, vp, vp, i64, i32, dbl, dbl, ctypes.c_int, vp, sz, vp],
+        "rpy_wall_matvec_batched": [vp, i64p, i32, vp, vp, i32, dbl, dbl, ctypes.c_int, vp, sz, vp],
+        "rpy_wall_lanczos_sqrt": [vp, vp, vp, i64, dbl, dbl, i64p, i32, dbl, i32, ctypes.c_int, vp, sz,
+                                  ctypes.POINTER(i32), ctypes.POINTER(dbl), vp],
+        "rpy_wall_matvec_vjp": [vp, vp, vp, vp, vp, i64, dbl, dbl, ctypes.c_int, vp, sz, vp],
+        "rpy_wall_divergence": [vp, vp, i64, dbl, dbl, ctypes.c_int, vp, sz, vp],
+        "rpy_wall_autotune": [vp, vp, vp, i64, i32, dbl, dbl, ctypes.c_int, vp, sz, vp],
+        "rpyw_tridiag_sqrt_coeffs": [ctypes.POINTER(dbl), ctypes.POINTER(dbl), i32, dbl, ctypes.POINTER(dbl)],
+        "rpy_wall_profile_enable": [ctypes.c_int],
+        "rpy_wall_profile_read": [ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl), ctypes.c_int],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    L.rpy_wall_workspace_bytes.argtypes = [ctypes.c_int, i64, i32, i32, i32, ctypes.c_int]
+    L.rpy_wall_workspace_bytes.restype = sz
+    L.rpyw_strerror.argtypes = [ctypes.c_int]
+    L.rpyw_strerror.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str, allow=(OK,)):
+    if status not in allow:
+        raise RpywError(status, where)
+    return status
+
+
+def _dev(t: torch.Tensor, name: str, shape=None) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float64 CUDA/HIP tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def workspace_bytes(op: int, N: int, k: int = 1, max_iter: int = 0, n_bodies: int = 0,
+                    precision: int = FP64) -> int:
+    return int(lib().rpy_wall_workspace_bytes(op, N, k, max_iter, n_bodies, precision))
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def matvec(pos: torch.Tensor, force: torch.Tensor, a: float = 1.0, eta: float = 1.0,
+           precision: int = FP64, out: torch.Tensor | None = None) -> torch.Tensor:
+    """u = M(r) f for pos, force of shape (N, 3)."""
+    N = pos.shape[0]
+    _dev(pos, "pos", (N, 3))
+    _dev(force, "force", (N, 3))
+    out = torch.empty_like(force) if out is None else _dev(out, "out", (N, 3))
+    ws = _workspace(workspace_bytes(OP_MATVEC, N, 1, precision=precision), pos.device)
+    _check(lib().rpy_wall_matvec(pos.data_ptr(), force.data_ptr(), out.data_ptr(), N, a, eta, precision,
+                                 ws.data_ptr(), ws.numel(), _stream(pos.device)), "rpy_wall_matvec")
+    return out
+
+
+def matvec_multi(pos: torch.Tensor, F: torch.Tensor, a: float = 1.0, eta: float = 1.0,
+                 precision: int = FP64, out: torch.Tensor | None = None) -> torch.Tensor:
+    """U_l = M(r) F_l for F of shape (k, N, 3)."""
+    N = pos.shape[0]
+    k = F.shape[0]
+    _dev(pos, "pos", (N, 3))
+    _dev(F, "F", (k, N, 3))
+    out = torch.empty_like(F) if out is None else _dev(out, "out", (k, N, 3))
+    ws = _workspace(workspace_bytes(OP_MATVEC, N, k, precision=precision), pos.device)
+    _check(lib().rpy_wall_matvec_multi(pos.data_ptr(), F.data_ptr(), out.data_ptr(), N, k, a, eta, precision,
+                                       ws.data_ptr(), ws.numel(), _stream(pos.device)), "rpy_wall_matvec_multi")
+    return out
+
+
+def _offsets(offs) -> np.ndarray:
+    arr = np.ascontiguousarray(np.asarray(offs.cpu() if isinstance(offs, torch.Tensor) else offs,
+                                          dtype=np.int64))
+    return arr
+
+
+def matvec_batched(pos: torch.Tensor, sys_offsets, F: torch.Tensor, a: float = 1.0, eta: float = 1.0,
+                   precision: int = FP32C, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Independent systems in one persistent launch; F, out: (k, Ntot, 3)."""
+    offs = _offsets(sys_offsets)
+    S = offs.shape[0] - 1
+    Ntot = pos.shape[0]
+    k = F.shape[0]
+    _dev(pos, "pos", (Ntot, 3))
+    _dev(F, "F", (k, Ntot, 3))
+    out = torch.empty_like(F) if out is None else _dev(out, "out", (k, Ntot, 3))
+    ws = _workspace(workspace_bytes(OP_BATCHED, Ntot, k, 0, S, precision), pos.device)
+    _check(lib().rpy_wall_matvec_batched(pos.data_ptr(), offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), S,
+                                         F.data_ptr(), out.data_ptr(), k, a, eta, precision, ws.data_ptr(),
+                                         ws.numel(), _stream(pos.device)), "rpy_wall_matvec_batched")
+    return out
+
+
+def lanczos_sqrt(pos: torch.Tensor, W: torch.Tensor, a: float = 1.0, eta: float = 1.0, body_offsets=None,
+                 tol: float = 1e-6, max_iter: int = 200, precision: int = FP64, out: torch.Tensor | None = None,
+                 strict: bool = False):
+    """Brownian blob displacements S W with S S^T = M by preconditioned
+    Lanczos.  Returns (out (N,3), iterations, last relative change,
+    converged flag).  strict=True raises when max_iter is reached."""
+    N = pos.shape[0]
+    _dev(pos, "pos", (N, 3))
+    _dev(W, "W", (N, 3))
+    out = torch.empty_like(W) if out is None else _dev(out, "out", (N, 3))
+    if body_offsets is None:
+        offs_p, nb = None, 0
+    else:
+        offs = _offsets(body_offsets)
+        nb = offs.shape[0] - 1
+        offs_p = offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    ws = _workspace(workspace_bytes(OP_LANCZOS, N, 1, max_iter, nb, precision), pos.device)
+    it = ctypes.c_int32(0)
+    err = ctypes.c_double(0.0)
+    st = lib().rpy_wall_lanczos_sqrt(pos.data_ptr(), W.data_ptr(), out.data_ptr(), N, a, eta, offs_p, nb, tol,
+                                     max_iter, precision, ws.data_ptr(), ws.numel(), ctypes.byref(it),
+                                     ctypes.byref(err), _stream(pos.device))
+    _check(st, "rpy_wall_lanczos_sqrt", allow=(OK,) if strict else (OK, NOT_CONVERGED))
+    return out, int(it.value), float(err.value), st == OK
+
+
+def matvec_vjp(pos: torch.Tensor, force: torch.Tensor, grad_vel: torch.Tensor, a: float = 1.0, eta: float = 1.0,
+               precision: int = FP64, need_pos: bool = True, need_force: bool = True):
+    """(grad_pos, grad_force) of L = sum grad_vel . M(pos) force."""
+    N = pos.shape[0]
+    for t, n in ((pos, "pos"), (force, "force"), (grad_vel, "grad_vel")):
+        _dev(t, n, (N, 3))
+    gp = torch.empty_like(pos) if need_pos else None
+    gf = torch.empty_like(force) if need_force else None
+    ws = _workspace(workspace_bytes(OP_VJP, N, 1, precision=precision), pos.device)
+    _check(lib().rpy_wall_matvec_vjp(pos.data_ptr(), force.data_ptr(), grad_vel.data_ptr(),
+                                     gp.data_ptr() if gp is not None else None,
+                                     gf.data_ptr() if gf is not None else None, N, a, eta, precision,
+                                     ws.data_ptr(), ws.numel(), _stream(pos.device)), "rpy_wall_matvec_vjp")
+    return gp, gf
+
+
+def divergence(pos: torch.Tensor, a: float = 1.0, eta: float = 1.0, precision: int = FP64) -> torch.Tensor:
+    """Exact divergence of M, shape (N, 3)."""
+    N = pos.shape[0]
+    _dev(pos, "pos", (N, 3))
+    out = torch.empty_like(pos)
+    ws = _workspace(workspace_bytes(OP_DIVERGENCE, N, 1, precision=precision), pos.device)
+    _check(lib().rpy_wall_divergence(pos.data_ptr(), out.data_ptr(), N, a, eta, precision, ws.data_ptr(),
+                                     ws.numel(), _stream(pos.device)), "rpy_wall_divergence")
+    return out
+
+
+def autotune(pos: torch.Tensor, F: torch.Tensor, a: float = 1.0, eta: float = 1.0, precision: int = FP32C):
+    """Time the launch-shape candidates on these inputs (F: (k, N, 3)) and
+    keep the fastest for this precision and size class."""
+    N = pos.shape[0]
+    k = F.shape[0]
+    _dev(pos, "pos", (N, 3))
+    _dev(F, "F", (k, N, 3))
+    U = torch.empty_like(F)
+    ws = _workspace(workspace_bytes(OP_MATVEC, N, k, precision=precision), pos.device)
+    _check(lib().rpy_wall_autotune(pos.data_ptr(), F.data_ptr(), U.data_ptr(), N, k, a, eta, precision,
+                                   ws.data_ptr(), ws.numel(), _stream(pos.device)), "rpy_wall_autotune")
+
+
+def tridiag_sqrt_coeffs(alpha, beta, beta0: float) -> np.ndarray:
+    """Host: c = beta0 Q Lambda^{1/2} Q^T e1 for tridiag(beta, alpha, beta)."""
+    a_ = np.ascontiguousarray(alpha, dtype=np.float64)
+    b_ = np.ascontiguousarray(beta, dtype=np.float64)
+    k = a_.shape[0]
+    c = np.empty(k)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib().rpyw_tridiag_sqrt_coeffs(a_.ctypes.data_as(dp), b_.ctypes.data_as(dp) if k > 1 else None, k,
+                                          float(beta0), c.ctypes.data_as(dp)), "rpyw_tridiag_sqrt_coeffs")
+    return c
+
+
+def profile_enable(flag: bool = True):
+    lib().rpy_wall_profile_enable(1 if flag else 0)
+
+
+def profile_read(reset: bool = True):
+    """(summed pair-kernel milliseconds, launches, pair interactions)."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    pairs = ctypes.c_double(0.0)
+    _check(lib().rpy_wall_profile_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(pairs), 1 if reset else 0),
+           "rpy_wall_profile_read")
+    return ms.value, n.value, pairs.value
+
+
+class RPYWallMatvec(torch.autograd.Function):
+    """u = M(pos) force with a hand-written backward (the library's VJP)."""
+
+    @staticmethod
+    def forward(ctx, pos, force, a=1.0, eta=1.0, precision=FP64):
+        ctx.save_for_backward(pos, force)
+        ctx.params = (a, eta, precision)
+        return matvec(pos.detach().contiguous(), force.detach().contiguous(), a, eta, precision)
+
+    @staticmethod
+    def backward(ctx, grad_vel):
+        pos, force = ctx.saved_tensors
+        a, eta, precision = ctx.params
+        gp, gf = matvec_vjp(pos.detach().contiguous(), force.detach().contiguous(), grad_vel.contiguous(), a, eta,
+                            precision, need_pos=ctx.needs_input_grad[0], need_force=ctx.needs_input_grad[1])
+        return gp, gf, None, None, None
+
+
+def rpy_wall_matvec(pos, force, a: float = 1.0, eta: float = 1.0, precision: int = FP64):
+    """Differentiable u = M(pos) force."""
+    return RPYWallMatvec.apply(pos, force, a, eta, precision)

@@ -1,0 +1,103 @@
+"""C-ABI checks that need no GPU: every declared symbol is exported, argument
+validation rejects bad calls before any HIP work, workspace sizing, and the
+host tridiagonal square-root solver against a dense eigendecomposition."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1709_02410_amd import rpywall
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rpywall.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(rpywall.LIB_PATH):
+        pytest.skip("librpywall.so not built")
+    return rpywall.lib()
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:rpy_wall|rpyw)_\w+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert "rpy_wall_matvec" in names and "rpy_wall_lanczos_sqrt" in names and "rpy_wall_matvec_vjp" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", rpywall.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert hasattr(lib, n)
+
+
+def test_validation_rejects_before_any_launch(lib):
+    E = rpywall.EINVAL
+    dummy = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    assert lib.rpy_wall_matvec(None, dummy, dummy, 10, 1.0, 1.0, 0, None, 0, None) == E
+    assert lib.rpy_wall_matvec(dummy, dummy, dummy, 0, 1.0, 1.0, 0, None, 0, None) == E
+    assert lib.rpy_wall_matvec(dummy, dummy, dummy, 10, 0.0, 1.0, 0, None, 0, None) == E
+    assert lib.rpy_wall_matvec(dummy, dummy, dummy, 10, 1.0, float("nan"), 0, None, 0, None) == E
+    assert lib.rpy_wall_matvec(dummy, dummy, dummy, 10, 1.0, 1.0, 7, None, 0, None) == E
+    assert lib.rpy_wall_matvec_multi(dummy, dummy, dummy, 10, 0, 1.0, 1.0, 0, None, 0, None) == E
+    bad_offs = (ctypes.c_int64 * 3)(0, 5, 5)
+    assert lib.rpy_wall_matvec_batched(dummy, bad_offs, 2, dummy, dummy, 1, 1.0, 1.0, 1, None, 0, None) == E
+    offs = (ctypes.c_int64 * 3)(0, 5, 9)
+    it = ctypes.c_int32()
+    er = ctypes.c_double()
+    assert lib.rpy_wall_lanczos_sqrt(dummy, dummy, dummy, 10, 1.0, 1.0, offs, 2, 1e-6, 50, 0, None, 0,
+                                     ctypes.byref(it), ctypes.byref(er), None) == E  # offsets end at 9 != N
+    big = (ctypes.c_int64 * 2)(0, 43)
+    assert lib.rpy_wall_lanczos_sqrt(dummy, dummy, dummy, 43, 1.0, 1.0, big, 1, 1e-6, 50, 0, None, 0,
+                                     ctypes.byref(it), ctypes.byref(er), None) == E  # body too large
+    assert lib.rpy_wall_lanczos_sqrt(dummy, dummy, dummy, 10, 1.0, 1.0, None, 0, 0.0, 50, 0, None, 0,
+                                     ctypes.byref(it), ctypes.byref(er), None) == E  # tol <= 0
+    assert lib.rpy_wall_matvec_vjp(dummy, dummy, dummy, None, None, 10, 1.0, 1.0, 0, None, 0, None) == E
+    assert lib.rpy_wall_divergence(dummy, None, 10, 1.0, 1.0, 0, None, 0, None) == E
+    # misaligned caller workspace
+    assert lib.rpy_wall_matvec(dummy, dummy, dummy, 10, 1.0, 1.0, 0, ctypes.c_void_p(0x1001), 1 << 20,
+                               None) == E
+
+
+def test_workspace_sizes(lib):
+    for op in range(5):
+        assert rpywall.workspace_bytes(op, 1000, 4, 50, 10 if op == 1 else 0, 1) > 0
+    assert lib.rpy_wall_workspace_bytes(0, 0, 1, 0, 0, 0) == 0
+    assert lib.rpy_wall_workspace_bytes(9, 10, 1, 0, 0, 0) == 0
+    small = rpywall.workspace_bytes(0, 1000, 1)
+    assert rpywall.workspace_bytes(0, 100000, 1) > small
+    assert rpywall.workspace_bytes(2, 1000, 1, 100, 0) > rpywall.workspace_bytes(2, 1000, 1, 10, 0)
+    for s in (0, 1, -1, -2, -3, -4, 99):
+        assert lib.rpyw_strerror(s)
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 30, 120])
+def test_tridiagonal_root_coefficients(lib, k):
+    """beta0 Q Lambda^{1/2} Q^T e1 from the host QL solver against numpy."""
+    rng = np.random.default_rng(k)
+    alpha = rng.uniform(0.5, 2.0, k)
+    beta = rng.uniform(0.01, 0.4, max(k - 1, 0))
+    T = np.diag(alpha) + np.diag(beta, 1) + np.diag(beta, -1)
+    lam, Q = np.linalg.eigh(T)
+    ref = 1.7 * Q @ (np.sqrt(np.clip(lam, 0, None)) * Q[0])
+    got = rpywall.tridiag_sqrt_coeffs(alpha, beta, 1.7)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_tridiagonal_root_clamps_negative_eigenvalues(lib):
+    alpha = np.array([1.0, -3.0, 0.5])
+    beta = np.array([0.2, 0.1])
+    T = np.diag(alpha) + np.diag(beta, 1) + np.diag(beta, -1)
+    lam, Q = np.linalg.eigh(T)
+    ref = Q @ (np.sqrt(np.clip(lam, 0, None)) * Q[0])
+    assert np.allclose(rpywall.tridiag_sqrt_coeffs(alpha, beta, 1.0), ref, atol=1e-14)
+    with pytest.raises(rpywall.RpywError):
+        rpywall.tridiag_sqrt_coeffs(np.array([1.0, np.nan]), np.array([0.1]), 1.0)
