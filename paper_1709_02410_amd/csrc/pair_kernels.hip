@@ -23,51 +23,12 @@
 #include <vector>
 
 #include "pair_math.h"
+#include "records.h"
 #include "rpyw_internal.h"
 
 namespace rpyw {
 
 namespace {
-
-template <typename R>
-constexpr int pos_slots() {
-    return sizeof(R) == 4 ? 5 : 3;
-}
-template <typename R, int K>
-constexpr int rec_w() {
-    return sizeof(R) == 4 ? (5 + 3 * K + 3) / 4 * 4 : (3 + 3 * K + 1) / 2 * 2;
-}
-
-// Records for blobs [0, N); F points at the first of kb RHS ([kb][N][3]).
-template <typename R>
-__global__ void pack_kernel(const double* __restrict__ pos, const double* __restrict__ F, int64_t N, int kb,
-                            int recw, double inv_a, R* __restrict__ rec, double* __restrict__ Bout) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const double x = pos[3 * i] * inv_a, y = pos[3 * i + 1] * inv_a, z = pos[3 * i + 2] * inv_a;
-    const double B = z < 1.0 ? z : 1.0;
-    const double zt = z < 1.0 ? 1.0 : z;
-    R* r = rec + i * recw;
-    int o;
-    if constexpr (sizeof(R) == 4) {
-        const float xh = (float)x, yh = (float)y;
-        r[0] = xh;
-        r[1] = yh;
-        r[2] = (float)zt;
-        r[3] = (float)(x - (double)xh);
-        r[4] = (float)(y - (double)yh);
-        o = 5;
-    } else {
-        r[0] = x;
-        r[1] = y;
-        r[2] = zt;
-        o = 3;
-    }
-    for (int k = 0; k < kb; ++k)
-        for (int c = 0; c < 3; ++c) r[o + 3 * k + c] = (R)(B * F[(k * N + i) * 3 + c]);
-    for (int e = o + 3 * kb; e < recw; ++e) r[e] = R(0);
-    if (Bout) Bout[i] = B;
-}
 
 // Targets held by one lane.
 template <typename R, int K, int TPL>
@@ -340,10 +301,10 @@ int product_pass(const double* pos, const double* F, double* U, int64_t N, int k
     const unsigned g1 = (unsigned)((N + kBlock - 1) / kBlock);
     if (prec == RPYW_FP32C)
         hipLaunchKernelGGL(pack_kernel<float>, dim3(g1), dim3(kBlock), 0, st, pos, F, N, kb, rw, 1.0 / a, (float*)rec,
-                           B);
+                           B, nullptr);
     else
         hipLaunchKernelGGL(pack_kernel<double>, dim3(g1), dim3(kBlock), 0, st, pos, F, N, kb, rw, 1.0 / a,
-                           (double*)rec, B);
+                           (double*)rec, B, nullptr);
     RPYW_HIP(hipGetLastError());
     const int64_t ntb = (N + (int64_t)kBlock * sh.tpl - 1) / ((int64_t)kBlock * sh.tpl);
     const int64_t nblocks = ntb * splits;
@@ -467,10 +428,10 @@ int batched_products(const double* pos, const int64_t* sys_offsets, int S, const
         double* Uk = U + (size_t)k0 * Ntot * 3;
         if (prec == RPYW_FP32C)
             hipLaunchKernelGGL(pack_kernel<float>, dim3(g1), dim3(kBlock), 0, st, pos, Fk, Ntot, kb, rw, 1.0 / a,
-                               (float*)rec, B);
+                               (float*)rec, B, nullptr);
         else
             hipLaunchKernelGGL(pack_kernel<double>, dim3(g1), dim3(kBlock), 0, st, pos, Fk, Ntot, kb, rw, 1.0 / a,
-                               (double*)rec, B);
+                               (double*)rec, B, nullptr);
         RPYW_HIP(hipGetLastError());
         hipLaunchKernelGGL(zero_u32, dim3(1), dim3(1), 0, st, counter);
         RPYW_HIP(hipGetLastError());

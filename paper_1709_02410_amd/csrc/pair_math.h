@@ -145,6 +145,133 @@ __device__ __forceinline__ void pair_apply(const PairCoef<R>& p, R dx, R dy, R d
     uz = fma_(t0, dz, fma_(p.kcm, G, fma_(p.cz, fz, uz)));
 }
 
+// Gradient of Phi = a^T M b + a2^T M b2 (units of mu0, radius 1) for one
+// pair, with respect to the base variables of the pair geometry
+// (dx, dy, dz, Rz = z_i + z_j, zz = z_i z_j).  Writing
+//   a^T M b = c1 (a.b) + c2 D_a D_b
+//           + w [|R|A h_ab + X |R|B G_a G_b + X Cw (G_a b_z + a_z G_b)
+//                + X Vw (G_a b_z - a_z G_b) + |R|E a_z b_z],
+// G_v = dx v_x + dy v_y, D_v = G_v + dz v_z, h_ab = a_x b_x + a_y b_y,
+// Cw = -3/4 dz, Vw = Rz X Pv, the two forms share all coefficients and
+// enter through the sums S1, S2, SA, SB, SC, SV, SE below.  w and X depend
+// on R2 = dx^2 + dy^2 + Rz^2 only, c1 and c2 on r2 = dx^2 + dy^2 + dz^2.
+// Target derivatives: d/dx_i = g.dx, d/dy_i = g.dy,
+//   d/dz_i = g.dz + g.rz + z_j g.zz;  source: d/dx_j = -g.dx,
+//   d/dz_j = -g.dz + g.rz + z_i g.zz.  Coincident blobs (r2 = 0) give no
+// free-part derivative.  Also returns the pair coefficients for value sums.
+template <typename R>
+struct PairGrad {
+    R dx, dy, dz, rz, zz;
+};
+
+template <typename R>
+__device__ __forceinline__ PairGrad<R> pair_grad(R dx, R dy, R dz, R zi, R zj, const R* a, const R* b,
+                                                 const R* a2, const R* b2, PairCoef<R>* coef) {
+    const R rz = zi + zj;
+    const R h2 = fma_(dy, dy, dx * dx);
+    const R r2 = fma_(dz, dz, h2);
+    const R rz2 = rz * rz;
+    const R R2 = h2 + rz2;
+    const R w = rsq<R>(R2);
+    const R X = w * w;
+    const R wX = w * X;
+    // free RPY coefficients and their derivatives in r2
+    const R ir = rsq<R>(r2);
+    const R ir2 = ir * ir;
+    const R ir3 = ir * ir2;
+    R c1 = ir * fma_(ir2, R(0.5), R(0.75));
+    R c2 = ir3 * fma_(ir2, R(-1.5), R(0.75));
+    R dc1 = -ir3 * fma_(ir2, R(0.75), R(0.375));
+    R dc2 = ir3 * ir2 * fma_(ir2, R(3.75), R(-1.125));
+    const bool near = r2 <= R(4);
+    if (__builtin_amdgcn_ballot_w64(near)) {
+        __asm__ volatile("" ::: "memory");
+        const R irg = rsq<R>(r2 > R(1e-30) ? r2 : R(1e-30));
+        const bool zero = r2 == R(0);
+        c1 = near ? fma_(R(-9.0 / 32.0), r2 * irg, R(1)) : c1;
+        c2 = near ? R(3.0 / 32.0) * irg : c2;
+        dc1 = near ? (zero ? R(0) : R(-9.0 / 64.0) * irg) : dc1;
+        dc2 = near ? (zero ? R(0) : R(-3.0 / 64.0) * irg * irg * irg) : dc2;
+    }
+    // bilinear building blocks
+    const R Ga = fma_(dy, a[1], dx * a[0]), Gb = fma_(dy, b[1], dx * b[0]);
+    const R Gc = fma_(dy, a2[1], dx * a2[0]), Gd = fma_(dy, b2[1], dx * b2[0]);
+    const R Da = fma_(dz, a[2], Ga), Db = fma_(dz, b[2], Gb);
+    const R Dc = fma_(dz, a2[2], Gc), Dd = fma_(dz, b2[2], Gd);
+    const R SA = fma_(a[0], b[0], a[1] * b[1]) + fma_(a2[0], b2[0], a2[1] * b2[1]);
+    const R SE = fma_(a[2], b[2], a2[2] * b2[2]);
+    const R S1 = SA + SE;
+    const R S2 = fma_(Da, Db, Dc * Dd);
+    const R SB = fma_(Ga, Gb, Gc * Gd);
+    const R SC = fma_(Ga, b[2], a[2] * Gb) + fma_(Gc, b2[2], a2[2] * Gd);
+    const R SV = fma_(Ga, b[2], -a[2] * Gb) + fma_(Gc, b2[2], -a2[2] * Gd);
+    // their derivatives in dx, dy, dz
+    const R S2x = fma_(a[0], Db, Da * b[0]) + fma_(a2[0], Dd, Dc * b2[0]);
+    const R S2y = fma_(a[1], Db, Da * b[1]) + fma_(a2[1], Dd, Dc * b2[1]);
+    const R S2z = fma_(a[2], Db, Da * b[2]) + fma_(a2[2], Dd, Dc * b2[2]);
+    const R SBx = fma_(a[0], Gb, Ga * b[0]) + fma_(a2[0], Gd, Gc * b2[0]);
+    const R SBy = fma_(a[1], Gb, Ga * b[1]) + fma_(a2[1], Gd, Gc * b2[1]);
+    const R SCx = fma_(a[0], b[2], a[2] * b[0]) + fma_(a2[0], b2[2], a2[2] * b2[0]);
+    const R SCy = fma_(a[1], b[2], a[2] * b[1]) + fma_(a2[1], b2[2], a2[2] * b2[1]);
+    const R SVx = fma_(a[0], b[2], -a[2] * b[0]) + fma_(a2[0], b2[2], -a2[2] * b2[0]);
+    const R SVy = fma_(a[1], b[2], -a[2] * b[1]) + fma_(a2[1], b2[2], -a2[2] * b2[1]);
+    // wall coefficients and their partial derivatives in X, Rz, zz
+    const R zz = zi * zj;
+    const R a1 = fma_(zz, R(-1.5), R(-0.5)), a2c = fma_(rz2, R(1.5), R(0.5)), a3 = rz2 * R(-2.5);
+    const R rA = fma_(X, fma_(X, fma_(X, a3, a2c), a1), R(-0.75));
+    const R rA_X = fma_(X, fma_(X, R(3) * a3, R(2) * a2c), a1);
+    const R rA_rz = X * X * rz * fma_(X, R(-5), R(3));
+    const R rA_zz = R(-1.5) * X;
+    const R b1 = fma_(zz, R(4.5), R(1.5)), b2c = fma_(rz2, R(-7.5), R(-2.5)), b3 = rz2 * R(17.5);
+    const R rB = fma_(X, fma_(X, fma_(X, b3, b2c), b1), R(-0.75));
+    const R rB_X = fma_(X, fma_(X, R(3) * b3, R(2) * b2c), b1);
+    const R rB_rz = X * X * rz * fma_(X, R(35), R(-15));
+    const R rB_zz = R(4.5) * X;
+    const R v2 = fma_(rz2, R(7.5), R(7.5));
+    const R pv = fma_(X, fma_(-X, b3, v2), -b1);
+    const R vw = (rz * X) * pv;
+    const R vw_X = rz * fma_(X, fma_(X, R(-3) * b3, R(2) * v2), -b1);
+    const R vw_rz = fma_(X * X * rz2, fma_(X, R(-35), R(15)), X * pv);
+    const R vw_zz = R(-4.5) * rz * X;
+    const R cw = dz * R(-0.75);
+    const R e1 = fma_(zz, R(1.5), fma_(rz2, R(-0.75), R(-0.5)));
+    const R e2 = fma_(rz2, fma_(zz, R(-4.5), R(-3.0)), R(-1.5));
+    const R e3 = rz2 * fma_(rz2, R(7.5), R(15.0));
+    const R e4 = (rz2 * rz2) * R(-17.5);
+    const R rE = fma_(X, fma_(X, fma_(X, fma_(X, e4, e3), e2), e1), R(-0.75));
+    const R rE_X = fma_(X, fma_(X, fma_(X, R(4) * e4, R(3) * e3), R(2) * e2), e1);
+    const R de1 = R(-1.5) * rz;
+    const R de2 = R(2) * rz * fma_(zz, R(-4.5), R(-3.0));
+    const R de3 = R(30) * rz * (rz2 + R(1));
+    const R de4 = R(-70) * rz * rz2;
+    const R rE_rz = X * fma_(X, fma_(X, fma_(X, de4, de3), de2), de1);
+    const R rE_zz = X * fma_(X, R(-4.5) * rz2, R(1.5));
+    // Phi = c1 S1 + c2 S2 + w P1 + w X P2
+    const R P1 = fma_(rA, SA, rE * SE);
+    const R P2 = fma_(rB, SB, fma_(cw, SC, vw * SV));
+    const R P1_X = fma_(rA_X, SA, rE_X * SE);
+    const R P2_X = fma_(rB_X, SB, vw_X * SV);
+    const R dR2 = -wX * fma_(X * X, P2_X, fma_(X, fma_(R(1.5), P2, P1_X), R(0.5) * P1));
+    const R dr2 = fma_(dc1, S1, dc2 * S2);
+    const R sh = R(2) * (dr2 + dR2);
+    PairGrad<R> g;
+    g.dx = fma_(sh, dx, fma_(c2, S2x, wX * fma_(rB, SBx, fma_(cw, SCx, vw * SVx))));
+    g.dy = fma_(sh, dy, fma_(c2, S2y, wX * fma_(rB, SBy, fma_(cw, SCy, vw * SVy))));
+    g.dz = fma_(R(2) * dr2, dz, fma_(c2, S2z, wX * R(-0.75) * SC));
+    g.rz = fma_(R(2) * dR2, rz, fma_(w, fma_(rA_rz, SA, rE_rz * SE), wX * fma_(rB_rz, SB, vw_rz * SV)));
+    g.zz = fma_(w, fma_(rA_zz, SA, rE_zz * SE), wX * fma_(rB_zz, SB, vw_zz * SV));
+    if (coef) {
+        coef->c1 = c1;
+        coef->c2 = c2;
+        coef->cc = fma_(w, rA, c1);
+        coef->cz = fma_(w, rE, c1);
+        coef->kb = wX * rB;
+        coef->kcp = wX * (cw + vw);
+        coef->kcm = wX * (cw - vw);
+    }
+    return g;
+}
+
 // Knuth's TwoSum: s + e == a + b exactly (round-to-nearest, no reassociation).
 template <typename R>
 __device__ __forceinline__ void two_sum_acc(R& hi, R& lo, R b) {

@@ -192,15 +192,20 @@ def config1(seed: int = 0) -> Config:
 def paperlike_boomerangs(n_bodies: int, seed: int = 0, spacing: float = 0.926,
                          density: float = 256.0 / 139.8 ** 2, zlo: float = 1.5,
                          zhi: float = 4.0, min_gap: float = 2.0,
-                         max_tries: int = 200_000) -> Config:
+                         max_tries: int = 2_000_000) -> Config:
     """Boomerangs at the paper's blob spacing with no inter-body blob overlap.
 
-    Random sequential addition: a candidate body is rejected when any of its
-    blobs comes closer than ``min_gap`` to a blob of an accepted body.
+    Random sequential addition in a square box at the given number density
+    of bodies: a candidate body is rejected when any of its blobs comes
+    closer than ``min_gap`` to a blob of an accepted body.  Accepted bodies
+    are binned by corner position in cells wider than two arm lengths plus
+    the gap, so only the 3 x 3 neighbouring cells are checked.
     """
     rng = np.random.default_rng(seed)
     box = math.sqrt(n_bodies / density)
     frame = boomerang_frame(spacing)
+    reach = 2.0 * float(np.linalg.norm(frame, axis=1).max()) + min_gap
+    cells: dict[tuple[int, int], list[np.ndarray]] = {}
     bodies: list[np.ndarray] = []
     tries = 0
     while len(bodies) < n_bodies:
@@ -209,12 +214,15 @@ def paperlike_boomerangs(n_bodies: int, seed: int = 0, spacing: float = 0.926,
             raise RuntimeError("random sequential addition did not place all bodies")
         c = np.array([rng.uniform(0, box), rng.uniform(0, box), rng.uniform(zlo, zhi)])
         cand = c + frame @ _rot_z(rng.uniform(0.0, 2.0 * math.pi)).T
-        if bodies:
-            allp = np.concatenate(bodies)
+        cx, cy = int(c[0] // reach), int(c[1] // reach)
+        near = [b for dx in (-1, 0, 1) for dy in (-1, 0, 1) for b in cells.get((cx + dx, cy + dy), [])]
+        if near:
+            allp = np.concatenate(near)
             d2 = ((cand[:, None, :] - allp[None, :, :]) ** 2).sum(-1)
             if d2.min() < min_gap * min_gap:
                 continue
         bodies.append(cand)
+        cells.setdefault((cx, cy), []).append(cand)
     pos = np.concatenate(bodies)
     offs = np.arange(0, 15 * n_bodies + 1, 15, dtype=np.int64)
     return Config(f"PB{n_bodies}", pos, body_offsets=offs,

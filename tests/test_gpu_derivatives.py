@@ -1,0 +1,131 @@
+"""GPU VJP and divergence against the oracle, central differences and the
+random-finite-difference estimate of the drift (Sec. III)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1709_02410_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1709_02410_amd import rpywall
+    rpywall.lib()
+    return rpywall
+
+
+def _t(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def _mixed(n, seed, box=None):
+    rng = np.random.default_rng(seed)
+    box = box or 2.0 * math.sqrt(n)
+    return np.column_stack([rng.uniform(0, box, n), rng.uniform(0, box, n), rng.uniform(0.3, 4.0, n)])
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 2e-5)])
+def test_vjp_matches_oracle(rp, orc, prec, tol):
+    """Blobs below z = a, overlapping pairs, ragged size (several tiles)."""
+    a, eta = 0.8, 1.1
+    pos = _mixed(777, 1) * a
+    f = wl.gaussian(pos.shape, 2)
+    g = wl.gaussian(pos.shape, 3)
+    gp_ref, gf_ref = orc.vjp(pos, f, g, a, eta)
+    gp, gf = rp.matvec_vjp(_t(pos), _t(f), _t(g), a, eta, precision=prec)
+    gp, gf = gp.cpu().numpy(), gf.cpu().numpy()
+    rel_p = np.linalg.norm(gp - gp_ref) / np.linalg.norm(gp_ref)
+    rel_f = np.linalg.norm(gf - gf_ref) / np.linalg.norm(gf_ref)
+    print(f"vjp prec={prec} rel grad_pos={rel_p:.3e} grad_f={rel_f:.3e}", flush=True)
+    assert rel_p <= tol and rel_f <= tol
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_vjp_central_differences_50k(rp, prec):
+    """Differentiation workload (5e4 blobs, box 300): VJP against central
+    differences (h = 1e-4) of the FP64 GPU product, on 8 random directions
+    and 64 sampled coordinates."""
+    cfg = wl.config4(seed=0)
+    pos = _t(cfg.pos)
+    f = _t(wl.gaussian(cfg.pos.shape, 1))
+    g = _t(wl.gaussian(cfg.pos.shape, 2))
+    gp, gf = rp.matvec_vjp(pos, f, g, precision=prec)
+    h = 1e-4
+
+    def L(p):
+        return float((g * rp.matvec(p, f, precision=0)).sum())
+
+    rng = np.random.default_rng(3)
+    worst = 0.0
+    for _ in range(8):
+        d = _t(rng.standard_normal(cfg.pos.shape))
+        fd = (L(pos + h * d) - L(pos - h * d)) / (2 * h)
+        an = float((gp * d).sum())
+        worst = max(worst, abs(fd - an) / abs(fd))
+    gmax = float(gp.abs().max())
+    worst_c = 0.0
+    for flat in rng.choice(cfg.N * 3, 64, replace=False):
+        e = torch.zeros_like(pos).view(-1)
+        e[flat] = h
+        e = e.view(-1, 3)
+        fd = (L(pos + e) - L(pos - e)) / (2 * h)
+        worst_c = max(worst_c, abs(fd - float(gp.view(-1)[flat])) / gmax)
+    print(f"vjp-fd prec={prec} directional rel={worst:.3e} coordinate rel={worst_c:.3e}", flush=True)
+    assert worst <= 1e-4 and worst_c <= 1e-4
+    gf_ref = rp.matvec(pos, g, precision=prec)
+    assert float((gf - gf_ref).norm() / gf_ref.norm()) <= (1e-14 if prec == 0 else 1e-6)
+
+
+def test_autograd_function(rp):
+    pos = _t(_mixed(300, 4)).requires_grad_(True)
+    f = _t(wl.gaussian((300, 3), 5)).requires_grad_(True)
+    g = _t(wl.gaussian((300, 3), 6))
+    u = rp.rpy_wall_matvec(pos, f)
+    (u * g).sum().backward()
+    gp, gf = rp.matvec_vjp(pos.detach(), f.detach(), g)
+    assert torch.equal(pos.grad, gp) and torch.equal(f.grad, gf)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 5e-5)])
+def test_divergence_matches_oracle(rp, orc, prec, tol):
+    cfg = wl.divergence_config(seed=0)
+    pos = cfg.pos.copy()
+    pos[:40, 2] = np.linspace(0.2, 0.99, 40)  # some blobs overlap the wall
+    ref = orc.divergence(pos)
+    got = rp.divergence(_t(pos), precision=prec).cpu().numpy()
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"divergence prec={prec} rel={rel:.3e}", flush=True)
+    assert rel <= tol
+
+
+@pytest.mark.parametrize("prec,delta", [(0, 1e-6), (1, 1e-3)])
+def test_rfd_drift_estimate_matches_exact_divergence(rp, prec, delta):
+    """Centred RFD with Delta P = Delta Q = W (Sec. III) on the 500-blob
+    workload: 1e4 samples, all 2e4 displaced systems in one batched launch;
+    per-component z-scores and a global chi-square against the exact
+    divergence."""
+    cfg = wl.divergence_config(seed=0)
+    N = cfg.N
+    S = 10_000
+    div = rp.divergence(_t(cfg.pos), precision=0).cpu().numpy()
+    rng = np.random.default_rng(17)
+    W = rng.standard_normal((S, N, 3))
+    pos = np.concatenate([cfg.pos[None] + 0.5 * delta * W, cfg.pos[None] - 0.5 * delta * W], 0).reshape(-1, 3)
+    F = np.concatenate([W, W], 0).reshape(1, -1, 3)
+    offs = np.arange(0, 2 * S * N + 1, N, dtype=np.int64)
+    U = rp.matvec_batched(_t(pos), offs, _t(F), precision=prec).cpu().numpy().reshape(2, S, N, 3)
+    samples = (U[0] - U[1]) / delta
+    mean = samples.mean(0)
+    se = samples.std(0, ddof=1) / math.sqrt(S)
+    z = (mean - div) / se
+    chi2 = float((z ** 2).sum())
+    dof = z.size
+    print(f"rfd prec={prec} max|z|={np.abs(z).max():.2f} chi2/dof={chi2 / dof:.3f}", flush=True)
+    assert np.abs(z).max() < 5.0
+    assert abs(chi2 - dof) < 6 * math.sqrt(2 * dof)

@@ -1,0 +1,120 @@
+"""GPU preconditioned Lanczos (Sec. II.B) against the oracle's Lanczos and
+dense square roots."""
+import numpy as np
+import pytest
+
+from paper_1709_02410_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1709_02410_amd import rpywall
+    rpywall.lib()
+    return rpywall
+
+
+def _t(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("bodies", [True, False])
+def test_small_against_dense_root(rp, orc, bodies):
+    pos, offs = wl.boomerang_suspension(12, 25.0, 1.5, 4.0, seed=3)
+    offs = offs if bodies else None
+    W = wl.gaussian(pos.shape, 4)
+    ref = orc.dense_sqrt(pos, W, offs)
+    out, it, err, ok = rp.lanczos_sqrt(_t(pos), _t(W), body_offsets=offs, tol=1e-10)
+    got = out.cpu().numpy()
+    print(f"dense-root bodies={bodies} iters={it} rel={_rel(got, ref):.3e}", flush=True)
+    assert ok and _rel(got, ref) <= 1e-9
+
+
+def test_boomerangs_3840_tol_1e6(rp, orc):
+    """256 boomerangs (3840 blobs), FP64 products, tolerance 1e-6: same
+    iteration count and iterate as the oracle's Lanczos, and within 10 tol
+    of the converged root (oracle at 1e-12)."""
+    cfg = wl.config1(seed=0)
+    W = wl.gaussian(cfg.pos.shape, 1)
+    out, it, err, ok = rp.lanczos_sqrt(_t(cfg.pos), _t(W), body_offsets=cfg.body_offsets, tol=1e-6)
+    got = out.cpu().numpy()
+    ref6, it6, _, ok6 = orc.lanczos_sqrt(cfg.pos, W, cfg.body_offsets, tol=1e-6)
+    ref12, it12, _, _ = orc.lanczos_sqrt(cfg.pos, W, cfg.body_offsets, tol=1e-12)
+    print(f"C1 iters gpu={it} oracle={it6} (tol 1e-12: {it12}) rel-same-tol={_rel(got, ref6):.3e} "
+          f"rel-converged={_rel(got, ref12):.3e}", flush=True)
+    assert ok and ok6 and it == it6
+    assert _rel(got, ref6) <= 1e-9
+    assert _rel(got, ref12) <= 1e-5
+
+
+def test_per_blob_preconditioner_config0(rp, orc):
+    cfg = wl.config0(seed=1)
+    W = wl.gaussian(cfg.pos.shape, 2)
+    out, it, err, ok = rp.lanczos_sqrt(_t(cfg.pos), _t(W), tol=1e-8)
+    ref, it_o, _, _ = orc.lanczos_sqrt(cfg.pos, W, None, tol=1e-8)
+    assert ok and abs(it - it_o) <= 1 and _rel(out.cpu().numpy(), ref) <= 1e-7
+
+
+def test_not_converged_returns_best_iterate(rp, orc):
+    pos, offs = wl.boomerang_suspension(8, 20.0, 1.5, 4.0, seed=5)
+    W = wl.gaussian(pos.shape, 6)
+    out, it, err, ok = rp.lanczos_sqrt(_t(pos), _t(W), body_offsets=offs, tol=1e-14, max_iter=3)
+    ref, it_o, _, ok_o = orc.lanczos_sqrt(pos, W, offs, tol=1e-14, max_iter=3)
+    assert not ok and not ok_o and it == 3 and it_o == 3
+    assert _rel(out.cpu().numpy(), ref) <= 1e-12
+    with pytest.raises(rp.RpywError):
+        rp.lanczos_sqrt(_t(pos), _t(W), body_offsets=offs, tol=1e-14, max_iter=3, strict=True)
+
+
+def test_non_spd_block_is_reported(rp):
+    """A body with a blob on the wall (B = 0) has a singular block."""
+    pos, offs = wl.boomerang_suspension(2, 10.0, 1.5, 2.0, seed=7)
+    pos[3, 2] = 0.0
+    W = wl.gaussian(pos.shape, 1)
+    with pytest.raises(rp.RpywError) as ei:
+        rp.lanczos_sqrt(_t(pos), _t(W), body_offsets=offs, tol=1e-6)
+    assert ei.value.status == rp.ENOTSPD
+
+
+def test_zero_vector(rp):
+    pos, offs = wl.boomerang_suspension(2, 10.0, 1.5, 2.0, seed=7)
+    out, it, err, ok = rp.lanczos_sqrt(_t(pos), _t(np.zeros_like(pos)), body_offsets=offs)
+    assert ok and it == 0 and float(out.abs().max()) == 0.0
+
+
+def test_microrollers_fp32_products(rp):
+    """196608-blob microroller suspension (12-blob bodies): Lanczos with
+    FP32C products and FP64 Krylov arithmetic against the all-FP64 run."""
+    cfg = wl.config2(seed=0)
+    W = wl.gaussian(cfg.pos.shape, 3)
+    pos, w = _t(cfg.pos), _t(W)
+    o64, it64, _, ok64 = rp.lanczos_sqrt(pos, w, body_offsets=cfg.body_offsets, tol=1e-6, precision=0)
+    o32, it32, _, ok32 = rp.lanczos_sqrt(pos, w, body_offsets=cfg.body_offsets, tol=1e-6, precision=1)
+    rel = float((o32 - o64).norm() / o64.norm())
+    print(f"C2 lanczos iters fp64={it64} fp32c={it32} rel={rel:.3e}", flush=True)
+    assert ok64 and ok32 and abs(it64 - it32) <= 1
+    assert rel <= 1e-5
+
+
+def test_iterations_independent_of_size(rp):
+    """Sec. II.B / IV.B: preconditioned iterations at tolerance 1e-3 stay
+    about 5 and do not grow with the number of boomerangs."""
+    its = []
+    for nb in (64, 256, 1024):
+        cfg = wl.paperlike_boomerangs(nb, seed=2)
+        W = wl.gaussian(cfg.pos.shape, 9)
+        _, it, _, ok = rp.lanczos_sqrt(_t(cfg.pos), _t(W), body_offsets=cfg.body_offsets, tol=1e-3)
+        _, it_u, _, _ = rp.lanczos_sqrt(_t(cfg.pos), _t(W), tol=1e-3)
+        its.append((it, it_u))
+        assert ok
+    print(f"iterations (pc, per-blob) by size: {its}", flush=True)
+    pc = [p for p, _ in its]
+    assert max(pc) <= 8 and max(pc) - min(pc) <= 1
