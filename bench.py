@@ -1,0 +1,274 @@
+#!/usr/bin/env python3
+"""Benchmark of the wall-corrected RPY blob mobility on one MI355X.
+
+Metric: blob-pair interactions per second of the dense product u = M(r) f
+(FP32 pair terms with compensated sums, and FP64), on 1e5 free blobs with
+the config-0 density (x, y ~ U[0, 600], z ~ U[1.1, 6], a = eta = 1,
+f ~ N(0,1), seed 0).  A timed step is one product: pack (O(N)), the O(N^2)
+pair kernel and the epilogue, inputs resident in HBM.  The same run also
+times the other parts of the hot path on their own workloads (FP64 product,
+16-RHS product, batched suspensions against per-instance launches,
+preconditioned Lanczos, VJP, divergence) and the FP64 CPU oracle on a
+bounded sample of the headline product.
+
+Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "wall-RPY blob-pair interactions/s (FP32 vs FP64) at 1e5 blobs; % vector peak"
+PEAK_FP32 = 157.3  # TFLOP/s, MI355X FP32 vector
+PEAK_FP64 = 78.6   # TFLOP/s, MI355X FP64 vector
+# Algorithmic FLOPs per pair of the product kernel (FMA = 2, rsqrt = 1,
+# compare/select = 0, precision bookkeeping not counted): 84 shared by all
+# right-hand sides + 24 per right-hand side.
+FLOP_PAIR_SHARED = 84
+FLOP_PAIR_RHS = 24
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pair_kernel_traffic.json")
+KERNEL_SOURCES = ["pair_kernels.hip", "pair_math.h", "records.h"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1709_02410_amd", "csrc", s), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic():
+    """HBM bytes per launch of the headline pair kernel from the committed
+    counter runs, or None when the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--headline-only", action="store_true", help="time only the headline product")
+    ap.add_argument("--calib-copy", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the row-sharded design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1709_02410_amd import rpywall as rp
+    from paper_1709_02410_amd import workloads as wl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    rp.lib()
+
+    def T(x):
+        return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+
+    def sync():
+        torch.cuda.synchronize()
+
+    def timed(fn, steps, warmup):
+        """Wall time per call over `steps` calls and the library-recorded
+        pair-kernel time (HIP events on the launch stream)."""
+        for _ in range(warmup):
+            fn()
+        sync()
+        rp.profile_enable(True)
+        rp.profile_read(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        sync()
+        wall = (time.perf_counter() - t0) / steps
+        kms, launches, pairs = rp.profile_read(True)
+        rp.profile_enable(False)
+        return wall, kms, launches, pairs
+
+    out = {}
+    # ---------------------------------------------------------- headline
+    H = wl.headline(seed=0)
+    N = H.N
+    pos = T(H.pos)
+    f = T(wl.gaussian(H.pos.shape, 1))
+    vel = torch.empty_like(f)
+    F1 = f.view(1, N, 3)
+    rp.autotune(pos, F1, precision=rp.FP32C)
+    rp.autotune(pos, F1, precision=rp.FP64)
+    step = lambda: rp.matvec(pos, f, precision=rp.FP32C, out=vel)  # noqa: E731
+    wall, kms, launches, pairs = timed(step, args.steps, args.warmup)
+    kavg = kms / launches
+    value = N * N / wall
+    flop_launch = (FLOP_PAIR_SHARED + FLOP_PAIR_RHS) * float(N) * N
+    achieved = flop_launch / (kavg * 1e-3) / 1e12
+    traffic = stored_traffic()
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32, 4), "traffic": traffic,
+                "kernel": "pair_kernel<float,K=1> (FP32 pair terms, TwoSum sums)",
+                "kernel_ms_avg": round(kavg, 4), "flop_per_pair": FLOP_PAIR_SHARED + FLOP_PAIR_RHS}
+
+    if args.calib_copy:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        sync()
+        out["calib_copy_bytes"] = src.numel() * 8
+
+    # FP64 product on the same input
+    step64 = lambda: rp.matvec(pos, f, precision=rp.FP64, out=vel)  # noqa: E731
+    w64, k64, l64, p64 = timed(step64, max(3, args.steps // 2), 1)
+    a64 = flop_launch / (k64 / l64 * 1e-3) / 1e12
+    out["fp64"] = {"value": N * N / w64, "unit": "pair interactions/s", "ms_per_step": w64 * 1e3,
+                   "kernel_ms_avg": k64 / l64,
+                   "roofline": {"bound": "alu", "achieved": round(a64, 3), "peak": PEAK_FP64, "unit": "TFLOP/s",
+                                "frac": round(a64 / PEAK_FP64, 4)}}
+
+    rows = {}
+    if not args.headline_only:
+        # 16-RHS product on the headline geometry
+        k = 16
+        F16 = T(wl.gaussian((k, N, 3), 2))
+        U16 = torch.empty_like(F16)
+        rp.autotune(pos, F16, precision=rp.FP32C)
+        w, km, ln, pr = timed(lambda: rp.matvec_multi(pos, F16, precision=rp.FP32C, out=U16), 3, 1)
+        fl = (FLOP_PAIR_SHARED + k * FLOP_PAIR_RHS) * float(N) * N
+        rows["multi_rhs_H_k16_fp32c"] = {"pair_rhs_per_s": k * N * N / w, "ms": w * 1e3,
+                                         "tflops_alg": fl / (km * 1e-3) / 1e12}
+        del F16, U16
+
+        # batched suspensions (config 3) against per-instance launches
+        C3 = wl.config3(seed=0)
+        offs = C3.sys_offsets
+        S = len(offs) - 1
+        F3 = T(wl.gaussian((k, C3.N, 3), 3))
+        U3 = torch.empty_like(F3)
+        p3 = T(C3.pos)
+        nmax = int(max(offs[s + 1] - offs[s] for s in range(S)))
+        smax = int(np.argmax(np.diff(offs)))
+        rp.autotune(p3[offs[smax]:offs[smax + 1]].contiguous(),
+                    F3[:, offs[smax]:offs[smax + 1]].contiguous(), precision=rp.FP32C)
+        pairs3 = float(sum(float(offs[s + 1] - offs[s]) ** 2 for s in range(S)))
+        wb, _, _, _ = timed(lambda: rp.matvec_batched(p3, offs, F3, precision=rp.FP32C, out=U3), 3, 1)
+        slices = [(int(offs[s]), int(offs[s + 1])) for s in range(S)]
+        sub = [(p3[a:b].contiguous(), F3[:, a:b].contiguous()) for a, b in slices]
+
+        def per_system_multi():
+            for ps, Fs in sub:
+                rp.matvec_multi(ps, Fs, precision=rp.FP32C)
+
+        def per_system_single():
+            for ps, Fs in sub:
+                for l in range(k):
+                    rp.matvec(ps, Fs[l], precision=rp.FP32C)
+
+        wm, _, _, _ = timed(per_system_multi, 2, 1)
+        wsn, _, _, _ = timed(per_system_single, 1, 1)
+        rows["batched_C3_k16_fp32c"] = {
+            "systems": S, "blobs": C3.N, "largest": nmax, "pair_rhs": k * pairs3,
+            "batched_ms": wb * 1e3, "per_system_multi_rhs_ms": wm * 1e3, "per_system_single_rhs_ms": wsn * 1e3,
+            "speedup_vs_multi": wm / wb, "speedup_vs_single": wsn / wb,
+            "batched_pair_rhs_per_s": k * pairs3 / wb}
+        del F3, U3, sub
+
+        # Lanczos: 256 boomerangs FP64 tol 1e-6; microrollers FP32C tol 1e-6
+        C1 = wl.config1(seed=0)
+        pc1, W1 = T(C1.pos), T(wl.gaussian(C1.pos.shape, 1))
+        rp.lanczos_sqrt(pc1, W1, body_offsets=C1.body_offsets, tol=1e-6)
+        sync()
+        t0 = time.perf_counter()
+        _, it1, err1, ok1 = rp.lanczos_sqrt(pc1, W1, body_offsets=C1.body_offsets, tol=1e-6)
+        sync()
+        t1 = time.perf_counter() - t0
+        rows["lanczos_C1_fp64_tol1e-6"] = {"blobs": C1.N, "iterations": it1, "converged": ok1, "ms": t1 * 1e3,
+                                           "ms_per_iteration": t1 * 1e3 / max(it1, 1)}
+        C2 = wl.config2(seed=0)
+        pc2, W2 = T(C2.pos), T(wl.gaussian(C2.pos.shape, 3))
+        sync()
+        t0 = time.perf_counter()
+        _, it2, err2, ok2 = rp.lanczos_sqrt(pc2, W2, body_offsets=C2.body_offsets, tol=1e-6,
+                                            precision=rp.FP32C)
+        sync()
+        t2 = time.perf_counter() - t0
+        u64c2 = rp.matvec(pc2, W2, precision=rp.FP64)
+        w2, k2, l2, p2 = timed(lambda: rp.matvec(pc2, W2, precision=rp.FP32C), 2, 1)
+        u32c2 = rp.matvec(pc2, W2, precision=rp.FP32C)
+        rows["lanczos_C2_fp32c_tol1e-6"] = {"blobs": C2.N, "iterations": it2, "converged": ok2, "ms": t2 * 1e3,
+                                            "ms_per_iteration": t2 * 1e3 / max(it2, 1)}
+        rows["product_C2_fp32c"] = {"blobs": C2.N, "pairs_per_s": C2.N ** 2 / w2, "ms": w2 * 1e3,
+                                    "rel_l2_vs_fp64": float((u32c2 - u64c2).norm() / u64c2.norm())}
+        del pc2, W2, u64c2, u32c2
+
+        # VJP on the differentiation workload
+        C4 = wl.config4(seed=0)
+        p4, f4, g4 = T(C4.pos), T(wl.gaussian(C4.pos.shape, 1)), T(wl.gaussian(C4.pos.shape, 2))
+        for prec, name in ((rp.FP32C, "fp32c"), (rp.FP64, "fp64")):
+            w, km, ln, pr = timed(lambda: rp.matvec_vjp(p4, f4, g4, precision=prec), 3, 1)
+            rows[f"vjp_C4_{name}"] = {"blobs": C4.N, "ms": w * 1e3, "pairs_per_s": C4.N ** 2 / w,
+                                      "kernel_ms": km / ln}
+        D = wl.divergence_config(seed=0)
+        pd = T(D.pos)
+        w, _, _, _ = timed(lambda: rp.divergence(pd, precision=rp.FP64), 3, 1)
+        rows["divergence_500_fp64"] = {"blobs": D.N, "ms": w * 1e3}
+
+    # ---------------------------------------------------------- CPU oracle
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as orc
+        orc.build()
+        nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        nthreads = max(1, min(nthreads, os.cpu_count() or 1))
+        fh = wl.gaussian(H.pos.shape, 1)
+        rng = np.random.default_rng(0)
+        probe = rng.choice(N, 4 * nthreads, replace=False)
+        t0 = time.perf_counter()
+        orc.matvec(H.pos, fh, rows=probe, nthreads=nthreads)
+        rate = len(probe) * N / (time.perf_counter() - t0)
+        nrows = int(min(N, max(len(probe), args.cpu_seconds * rate / N)))
+        rows_s = rng.choice(N, nrows, replace=False)
+        t0 = time.perf_counter()
+        orc.matvec(H.pos, fh, rows=rows_s, nthreads=nthreads)
+        dt = time.perf_counter() - t0
+        cpu = {"value": nrows * N / dt, "unit": "pair interactions/s", "cores": nthreads, "kind": "oracle",
+               "sample": f"{nrows} random target rows x all {N} sources of the headline product, FP64, "
+                         f"{dt:.1f} s (C++ double loop, OpenMP)"}
+
+    rec = {
+        "metric": METRIC, "value": value, "unit": "pair interactions/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "1e5 free blobs, x,y~U[0,600], z~U[1.1,6], a=eta=1, f~N(0,1), seed 0 "
+                               "(config-0 density at 1e5 blobs)",
+                   "N": N, "precision": "FP32 pair terms, compensated FP32 sums, FP64 in/out",
+                   "pairs_per_step": N * N},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        **out,
+        "rows": rows,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -256,7 +256,7 @@ int rpy_wall_autotune(const double* pos, const double* F, double* U, int64_t N, 
     double best_t = 1e300;
     for (int kb = 1; kb <= std::min(kc, 16); kb <<= 1) {
         if (precision == RPYW_FP64 && kb > 8) continue;
-        for (int tpl = 1; tpl <= 2; ++tpl)
+        for (int tpl = 1; tpl <= (kb >= 8 ? 1 : 2); ++tpl)
             for (int tile : {64, 256}) {
                 Shape sh{tpl, tile, kb};
                 float ms = 0.f;

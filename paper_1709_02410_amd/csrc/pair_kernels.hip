@@ -250,6 +250,15 @@ int pow2ceil(int k) {
 // sides (FP64 stops at 8: wider blocks do not fit the register file).
 int kernel_k(int kb, int prec) { return std::min(pow2ceil(kb), prec == RPYW_FP32C ? 16 : 8); }
 
+// The launch shape the dispatch actually instantiates: blocks of 8 or more
+// right-hand sides run one target per lane, tiles are 64 or 256.
+Shape normalized(Shape s, int K) {
+    if (K >= 8) s.tpl = 1;
+    s.tpl = s.tpl == 2 ? 2 : 1;
+    s.tile = s.tile == 64 ? 64 : 256;
+    return s;
+}
+
 double mu0_of(double a, double eta) { return 1.0 / (6.0 * M_PI * eta * a); }
 
 }  // namespace
@@ -287,6 +296,7 @@ int product_pass(const double* pos, const double* F, double* U, int64_t N, int k
     const size_t mark = ar.used;
     const int K = kernel_k(kb, prec);
     if (kb < 1 || kb > K) return RPYW_EINVAL;
+    sh = normalized(sh, K);
     const int rw = rec_width(prec, K);
     void* rec = ar.take((size_t)N * rw * real_size(prec));
     double* B = (double*)ar.take((size_t)N * sizeof(double));
@@ -384,7 +394,8 @@ int batched_products(const double* pos, const int64_t* sys_offsets, int S, const
     const int64_t Ntot = sys_offsets[S];
     int64_t nmax = 0;
     for (int s = 0; s < S; ++s) nmax = std::max(nmax, sys_offsets[s + 1] - sys_offsets[s]);
-    const Shape sh = tuned_shape(nmax, k, prec);
+    Shape sh = tuned_shape(nmax, k, prec);
+    sh = normalized(sh, kernel_k(sh.kblk, prec));
     // Work list in LPT order: systems by decreasing size, then their tiles.
     std::vector<int> order(S);
     for (int s = 0; s < S; ++s) order[s] = s;
