@@ -38,6 +38,17 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pair_kernel_traffic.json")
 KERNEL_SOURCES = ["pair_kernels.hip", "pair_math.h", "records.h"]
 
 
+def algorithmic_flop(N: int, k: int, sym: int) -> float:
+    """Algorithmic FLOPs of one product of N blobs and k RHS.  The plain
+    kernel evaluates every ordered pair (84 + 24 k each); the symmetric
+    kernel evaluates each unordered pair once and applies it both ways
+    (84 + 48 k), self pairs once (84 + 24 k)."""
+    n = float(N)
+    if sym:
+        return n * (n - 1) / 2 * (FLOP_PAIR_SHARED + 2 * k * FLOP_PAIR_RHS) + n * (FLOP_PAIR_SHARED + k * FLOP_PAIR_RHS)
+    return n * n * (FLOP_PAIR_SHARED + k * FLOP_PAIR_RHS)
+
+
 def kernel_hash() -> str:
     h = hashlib.sha256()
     for s in KERNEL_SOURCES:
@@ -121,13 +132,17 @@ def main():
     wall, kms, launches, pairs = timed(step, args.steps, args.warmup)
     kavg = kms / launches
     value = N * N / wall
-    flop_launch = (FLOP_PAIR_SHARED + FLOP_PAIR_RHS) * float(N) * N
+    shape32 = rp.get_shape(rp.FP32C, N, 1)
+    flop_launch = algorithmic_flop(N, 1, shape32["sym"])
     achieved = flop_launch / (kavg * 1e-3) / 1e12
     traffic = stored_traffic()
+    kname = ("sym_kernel<float,1> (each unordered pair once, both directions)" if shape32["sym"]
+             else f"pair_kernel<float,1,{shape32['tpl']},{shape32['tile']}>")
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32, 4), "traffic": traffic,
-                "kernel": "pair_kernel<float,K=1> (FP32 pair terms, TwoSum sums)",
-                "kernel_ms_avg": round(kavg, 4), "flop_per_pair": FLOP_PAIR_SHARED + FLOP_PAIR_RHS}
+                "kernel": kname + ", FP32 pair terms, TwoSum sums", "shape": shape32,
+                "kernel_ms_avg": round(kavg, 4), "flop_per_launch": flop_launch,
+                "flop_per_ordered_pair": round(flop_launch / (float(N) * N), 2)}
 
     if args.calib_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
@@ -139,9 +154,10 @@ def main():
     # FP64 product on the same input
     step64 = lambda: rp.matvec(pos, f, precision=rp.FP64, out=vel)  # noqa: E731
     w64, k64, l64, p64 = timed(step64, max(3, args.steps // 2), 1)
-    a64 = flop_launch / (k64 / l64 * 1e-3) / 1e12
+    shape64 = rp.get_shape(rp.FP64, N, 1)
+    a64 = algorithmic_flop(N, 1, shape64["sym"]) / (k64 / l64 * 1e-3) / 1e12
     out["fp64"] = {"value": N * N / w64, "unit": "pair interactions/s", "ms_per_step": w64 * 1e3,
-                   "kernel_ms_avg": k64 / l64,
+                   "kernel_ms_avg": k64 / l64, "shape": shape64,
                    "roofline": {"bound": "alu", "achieved": round(a64, 3), "peak": PEAK_FP64, "unit": "TFLOP/s",
                                 "frac": round(a64 / PEAK_FP64, 4)}}
 
@@ -153,8 +169,9 @@ def main():
         U16 = torch.empty_like(F16)
         rp.autotune(pos, F16, precision=rp.FP32C)
         w, km, ln, pr = timed(lambda: rp.matvec_multi(pos, F16, precision=rp.FP32C, out=U16), 3, 1)
-        fl = (FLOP_PAIR_SHARED + k * FLOP_PAIR_RHS) * float(N) * N
-        rows["multi_rhs_H_k16_fp32c"] = {"pair_rhs_per_s": k * N * N / w, "ms": w * 1e3,
+        sh16 = rp.get_shape(rp.FP32C, N, k)
+        fl = sum(algorithmic_flop(N, min(sh16["kblk"], k - k0), sh16["sym"]) for k0 in range(0, k, sh16["kblk"]))
+        rows["multi_rhs_H_k16_fp32c"] = {"pair_rhs_per_s": k * N * N / w, "ms": w * 1e3, "shape": sh16,
                                          "tflops_alg": fl / (km * 1e-3) / 1e12}
         del F16, U16
 

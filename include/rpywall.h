@@ -143,6 +143,21 @@ const char* rpyw_strerror(int status);
 int rpy_wall_autotune(const double* pos, const double* F, double* U, int64_t N, int32_t k, double a,
                       double eta, int precision, void* ws, size_t ws_bytes, void* stream);
 
+/* Fix the launch shape used for products of this precision and size class
+ * (the class of N: floor(log2 N); of k: next power of two up to 16) instead
+ * of the tuner's choice.  tpl: targets per lane (1, 2); tile: LDS tile (64,
+ * 256); kblk: RHS block width (1..16, FP64 up to 8); sym: 1 selects the
+ * symmetric kernel, which evaluates each unordered pair once and applies it
+ * in both directions (kblk <= 4); ipw: source groups per workgroup of the
+ * symmetric kernel.  Host-only, takes effect for later calls. */
+int rpy_wall_set_shape(int precision, int64_t N, int32_t k, int32_t tpl, int32_t tile, int32_t kblk, int32_t sym,
+                       int32_t ipw);
+
+/* The launch shape later products of this precision and size class will
+ * use: out5 = {tpl, tile, kblk, sym, ipw} (HOST int32[5]), as for
+ * rpy_wall_set_shape.  Host-only. */
+int rpy_wall_get_shape(int precision, int64_t N, int32_t k, int32_t* out5);
+
 /* Host-only: coefficients c = beta0 Q Lambda^{1/2} Q^T e1 of the Lanczos
  * iterate for the k x k symmetric tridiagonal T (diagonal alpha[k],
  * off-diagonal beta[k-1]) with eigendecomposition T = Q Lambda Q^T, negative

@@ -73,11 +73,18 @@ int64_t g_prof_n = 0;
 
 }  // namespace
 
+// Defaults from measurements on MI355X: the symmetric kernel wins for one
+// right-hand side from a few thousand blobs up (1.7x at 1e5); wider RHS
+// blocks are faster on the plain kernel.  ipw keeps the symmetric grid at
+// roughly 16k workgroups or more.
 Shape default_shape(int64_t N, int k, int prec) {
     Shape s;
     s.tpl = N >= 65536 ? 2 : 1;
-    s.tile = 256;
+    s.tile = 64;
     s.kblk = std::min(kclass(k), prec == RPYW_FP32C ? 16 : 8);
+    s.sym = (s.kblk == 1 && N >= 2048) ? 1 : 0;
+    const int64_t ng = (N + 255) / 256, hm = ng / 2 + 1;
+    s.ipw = (int)std::max<int64_t>(1, std::min<int64_t>(4, hm * ng / 16384));
     return s;
 }
 
@@ -256,9 +263,12 @@ int rpy_wall_autotune(const double* pos, const double* F, double* U, int64_t N, 
     double best_t = 1e300;
     for (int kb = 1; kb <= std::min(kc, 16); kb <<= 1) {
         if (precision == RPYW_FP64 && kb > 8) continue;
-        for (int tpl = 1; tpl <= (kb >= 8 ? 1 : 2); ++tpl)
-            for (int tile : {64, 256}) {
-                Shape sh{tpl, tile, kb};
+        for (int cand = 0; cand < 7; ++cand) {
+                // plain: (tpl, tile) in {1,2} x {64,256}; symmetric: ipw in {1, 2, 4}
+                Shape sh{1 + (cand & 1), (cand & 2) ? 256 : 64, kb, 0, 4};
+                if (cand >= 4) sh = Shape{1, 256, kb, 1, 1 << (cand - 4)};
+                if (cand < 4 && kb >= 8 && sh.tpl == 2) continue;
+                if (cand >= 4 && kb > 4) continue;
                 float ms = 0.f;
                 for (int rep = 0; rep < 3; ++rep) {
                     if (rep == 1) RPYW_HIP(hipEventRecord(e0, st));
@@ -285,6 +295,30 @@ int rpy_wall_autotune(const double* pos, const double* F, double* U, int64_t N, 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     set_tuned_shape(N, k, precision, best);
+    return RPYW_OK;
+}
+
+int rpy_wall_set_shape(int precision, int64_t N, int32_t k, int32_t tpl, int32_t tile, int32_t kblk, int32_t sym,
+                       int32_t ipw) {
+    if (!valid_prec(precision) || N < 1 || N >= kMaxN || k < 1 || (tpl != 1 && tpl != 2) ||
+        (tile != 64 && tile != 256) || kblk < 1 || kblk > (precision == RPYW_FP32C ? 16 : 8) ||
+        (kblk & (kblk - 1)) != 0 || (sym != 0 && sym != 1) || (sym && kblk > 4) || ipw < 1)
+        return RPYW_EINVAL;
+    set_tuned_shape(N, k, precision, Shape{tpl, tile, kblk, sym, ipw});
+    return RPYW_OK;
+}
+
+int rpy_wall_get_shape(int precision, int64_t N, int32_t k, int32_t* out5) {
+    if (!valid_prec(precision) || N < 1 || N >= kMaxN || k < 1 || !out5) return RPYW_EINVAL;
+    Shape s = tuned_shape(N, k, precision);
+    const int K = std::min(kclass(s.kblk), precision == RPYW_FP32C ? 16 : 8);
+    if (K >= 8) s.tpl = 1;
+    if (K > 4) s.sym = 0;
+    out5[0] = s.tpl;
+    out5[1] = s.tile;
+    out5[2] = s.kblk;
+    out5[3] = s.sym;
+    out5[4] = s.ipw;
     return RPYW_OK;
 }
 

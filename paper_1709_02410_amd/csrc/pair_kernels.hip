@@ -193,7 +193,257 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(const R* __restrict__ r
     }
 }
 
+// ------------------------------------------------------------ symmetric product
+//
+// Reciprocity (M_ji = M_ij^T) lets one evaluation of a pair's coefficients
+// serve both directions: M_ji f = the same block applied with the two
+// off-diagonal wall coefficients (kcp, kcm) exchanged.  Blobs are grouped in
+// 256 (four 64-lane blocks).  Work item (P, d): target group P against source
+// group Q = (P + d) mod ng, d = 0 .. H(P), which covers every unordered group
+// pair once.  Wave w holds target block 4P + w; for each source block of Q it
+// runs 64 steps in which lane l pairs its target with source (l + s) mod 64,
+// adds M_ij f_j to its target sums and M_ji f_i to a source accumulator that
+// moves one lane down after every step, so that after the pass lane l holds
+// the complete sum for source l of the block.  Within the diagonal item
+// (d = 0) blocks above the wave's own are done symmetrically, the wave's own
+// block over all ordered pairs (self included), and blocks below it are left
+// to the waves that own them.  Target sums are written per (row, chunk) and
+// source sums per (group, d); the epilogue adds both in a fixed order.
+
+// Number of source-group offsets d > 0 that row P owns (ng groups).
+__host__ __device__ inline int sym_rowlen(int P, int ng) {
+    return (ng & 1) ? (ng - 1) / 2 : ng / 2 - 1 + (P < ng / 2 ? 1 : 0);
+}
+
+// Lane l receives the value held by lane (l + 1) mod 64.
+__device__ __forceinline__ float rot_next(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x134, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double rot_next(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x134, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x134, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+template <typename R>
+struct Vec;
+template <>
+struct Vec<float> {
+    using T = float4;
+    static constexpr int W = 4;
+    __device__ static float get(const float4& v, int e) { return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w; }
+};
+template <>
+struct Vec<double> {
+    using T = double2;
+    static constexpr int W = 2;
+    __device__ static double get(const double2& v, int e) { return e == 0 ? v.x : v.y; }
+};
+
+template <typename R, int K>
+struct SymLane {
+    static constexpr int RW = rec_w<R, K>();
+    static constexpr int NV = RW / Vec<R>::W;
+    static constexpr int PW = pos_slots<R>();
+    R x, y, z, xl, yl;
+    R f[K][3];
+    R acc[K][3], hi[K][3], lo[K][3];
+
+    // One 64-step pass over source block `blk` (LDS rows of 128 entries:
+    // the block's 64 records stored twice, so entry l + s needs no wrap).
+    template <bool SYM>
+    __device__ void pass(const typename Vec<R>::T* __restrict__ tile, int blk, int l, R (&S)[K][3]) {
+        using VT = typename Vec<R>::T;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) S[k][c] = R(0);
+        const VT* base = tile + blk * 128 + l;
+#pragma unroll 4
+        for (int s = 0; s < 64; ++s) {
+            R r[RW];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const VT q = base[v * 512 + s];
+#pragma unroll
+                for (int e = 0; e < Vec<R>::W; ++e) r[v * Vec<R>::W + e] = Vec<R>::get(q, e);
+            }
+            R dx = x - r[0], dy = y - r[1];
+            if constexpr (sizeof(R) == 4) {
+                dx += xl - r[3];
+                dy += yl - r[4];
+            }
+            const R dz = z - r[2];
+            PairCoef<R> p = pair_coef<R>(dx, dy, dz, z, r[2]);
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                pair_apply<R>(p, dx, dy, dz, r[PW + 3 * k], r[PW + 3 * k + 1], r[PW + 3 * k + 2], acc[k][0], acc[k][1],
+                              acc[k][2]);
+            if constexpr (SYM) {
+                const R t = p.kcp;
+                p.kcp = p.kcm;
+                p.kcm = t;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    R u[3] = {R(0), R(0), R(0)};
+                    pair_apply<R>(p, dx, dy, dz, f[k][0], f[k][1], f[k][2], u[0], u[1], u[2]);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) S[k][c] = rot_next(S[k][c]) + u[c];
+                }
+            }
+        }
+        if constexpr (SYM) {
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) S[k][c] = rot_next(S[k][c]);
+        }
+        if constexpr (sizeof(R) == 4) {
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    two_sum_acc(hi[k][c], lo[k][c], acc[k][c]);
+                    acc[k][c] = R(0);
+                }
+        }
+    }
+
+    __device__ double total(int k, int c) const {
+        if constexpr (sizeof(R) == 4)
+            return (double)hi[k][c] + (double)lo[k][c];
+        else
+            return (double)acc[k][c];
+    }
+};
+
+// rec: ng * 256 records (padded with force-free blobs far away).
+// tpart: [ng * C][3K][256] doubles; spart: [ng * (Hmax + 1)][3K][256].
+template <typename R, int K>
+__global__ __launch_bounds__(kBlock) void sym_kernel(const R* __restrict__ rec, int ng, int C, int ipw, int Hmax,
+                                                     double* __restrict__ tpart, R* __restrict__ spart) {
+    using VT = typename Vec<R>::T;
+    using L = SymLane<R, K>;
+    __shared__ VT tile[L::NV * 512];
+    __shared__ R red[4][3 * K][256];
+    const int P = blockIdx.x / C, c = blockIdx.x % C;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    L me;
+    {
+        const R* r = rec + ((int64_t)P * 256 + threadIdx.x) * L::RW;
+        me.x = r[0];
+        me.y = r[1];
+        me.z = r[2];
+        me.xl = sizeof(R) == 4 ? r[3] : R(0);
+        me.yl = sizeof(R) == 4 ? r[4] : R(0);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                me.f[k][cc] = r[L::PW + 3 * k + cc];
+                me.acc[k][cc] = me.hi[k][cc] = me.lo[k][cc] = R(0);
+            }
+    }
+    const int H = sym_rowlen(P, ng);
+    const int d0 = c * ipw;
+    const int d1 = d0 + ipw - 1 < H ? d0 + ipw - 1 : H;
+    for (int d = d0; d <= d1; ++d) {
+        const int Q = (P + d) % ng;
+        __syncthreads();
+        {
+            const VT* g = reinterpret_cast<const VT*>(rec + ((int64_t)Q * 256 + threadIdx.x) * L::RW);
+            const int b = threadIdx.x >> 6, j = threadIdx.x & 63;
+#pragma unroll
+            for (int v = 0; v < L::NV; ++v) {
+                const VT q = g[v];
+                tile[v * 512 + b * 128 + j] = q;
+                tile[v * 512 + b * 128 + j + 64] = q;
+            }
+        }
+        __syncthreads();
+        for (int bb = 0; bb < 4; ++bb) {
+            const int blk = (w + bb) & 3;
+            R S[K][3];
+            if (d == 0 && blk < w) {
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc) S[k][cc] = R(0);
+            } else if (d == 0 && blk == w) {
+                me.template pass<false>(tile, blk, l, S);
+            } else {
+                me.template pass<true>(tile, blk, l, S);
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) red[w][3 * k + cc][blk * 64 + l] = S[k][cc];
+        }
+        __syncthreads();
+        R* out = spart + ((int64_t)Q * (Hmax + 1) + d) * (3 * K) * 256;
+#pragma unroll
+        for (int q = 0; q < 3 * K; ++q)
+            out[q * 256 + threadIdx.x] =
+                ((red[0][q][threadIdx.x] + red[1][q][threadIdx.x]) + red[2][q][threadIdx.x]) + red[3][q][threadIdx.x];
+    }
+    double* tp = tpart + ((int64_t)P * C + c) * (3 * K) * 256;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) tp[(3 * k + cc) * 256 + threadIdx.x] = me.total(k, cc);
+}
+
+// One thread per (blob, output component q = 3k + c).  Source slots of group
+// P: d = 0 .. Hmax, except that with an even group count the offset ng/2 is
+// owned only by rows below ng/2, so groups P < ng/2 stop at Hmax - 1.
+template <typename R>
+__global__ void sym_epilogue(const double* __restrict__ tpart, const R* __restrict__ spart,
+                             const double* __restrict__ B, int64_t N, int ng, int C, int Hmax, int K, int kb,
+                             double mu0, double* __restrict__ U) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = blockIdx.y;
+    if (i >= N || q >= 3 * kb) return;
+    const int P = (int)(i >> 8), t = (int)(i & 255);
+    const int dmax = ((ng & 1) == 0 && P < ng / 2) ? Hmax - 1 : Hmax;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    const double* tp = tpart + ((int64_t)P * C * (3 * K) + q) * 256 + t;
+    for (int c = 0; c < C; ++c) s0 += tp[(int64_t)c * (3 * K) * 256];
+    const R* sp = spart + ((int64_t)P * (Hmax + 1) * (3 * K) + q) * 256 + t;
+    const int64_t st = (int64_t)(3 * K) * 256;
+    int d = 0;
+    for (; d + 3 <= dmax; d += 4) {
+        s0 += (double)sp[(d + 0) * st];
+        s1 += (double)sp[(d + 1) * st];
+        s2 += (double)sp[(d + 2) * st];
+        s3 += (double)sp[(d + 3) * st];
+    }
+    for (; d <= dmax; ++d) s0 += (double)sp[d * st];
+    const int k = q / 3, cc = q % 3;
+    U[((int64_t)k * N + i) * 3 + cc] = mu0 * B[i] * ((s0 + s1) + (s2 + s3));
+}
+
+template <typename R, int K>
+hipError_t launch_sym_t(const R* rec, int ng, int C, int ipw, int Hmax, double* tpart, R* spart, hipStream_t st) {
+    hipLaunchKernelGGL((sym_kernel<R, K>), dim3((unsigned)(ng * C)), dim3(kBlock), 0, st, rec, ng, C, ipw, Hmax, tpart,
+                       spart);
+    return hipGetLastError();
+}
+
 __global__ void zero_u32(unsigned* p) { *p = 0u; }
+
+// Records [N, Npad): force-free blobs far from everything (x = y = 1e6 a).
+template <typename R>
+__global__ void pad_kernel(R* __restrict__ rec, int64_t N, int64_t Npad, int recw, double* __restrict__ B) {
+    const int64_t i = N + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Npad) return;
+    R* r = rec + i * recw;
+    for (int e = 0; e < recw; ++e) r[e] = R(0);
+    r[0] = R(1e6);
+    r[1] = R(1e6);
+    r[2] = R(1);
+    B[i] = 0.0;
+}
 
 // ------------------------------------------------------------ dispatch
 
@@ -254,6 +504,8 @@ int kernel_k(int kb, int prec) { return std::min(pow2ceil(kb), prec == RPYW_FP32
 // right-hand sides run one target per lane, tiles are 64 or 256.
 Shape normalized(Shape s, int K) {
     if (K >= 8) s.tpl = 1;
+    if (K > 4) s.sym = 0;
+    if (s.ipw < 1) s.ipw = 4;
     s.tpl = s.tpl == 2 ? 2 : 1;
     s.tile = s.tile == 64 ? 64 : 256;
     return s;
@@ -264,6 +516,20 @@ double mu0_of(double a, double eta) { return 1.0 / (6.0 * M_PI * eta * a); }
 }  // namespace
 
 // ------------------------------------------------------------ host side
+
+SymPlan sym_plan(int64_t N, int prec, int K, int ipw) {
+    SymPlan s{};
+    s.ng = (int)((N + 255) / 256);
+    s.Hmax = s.ng / 2;
+    if (ipw < 1) ipw = 1;
+    s.C = (s.Hmax + 1 + ipw - 1) / ipw;
+    const size_t npad = (size_t)s.ng * 256;
+    s.rec_bytes = align_up(npad * rec_width(prec, K) * real_size(prec)) + align_up(npad * sizeof(double));
+    s.tpart_bytes = align_up((size_t)s.ng * s.C * 3 * K * 256 * sizeof(double));
+    s.spart_bytes = align_up((size_t)s.ng * (s.Hmax + 1) * 3 * K * 256 * real_size(prec));
+    s.ok = K <= 4 && s.spart_bytes <= ((size_t)4 << 30);
+    return s;
+}
 
 void split_plan(int64_t N, int tpl, int* splits, int64_t* chunk) {
     const int64_t ntb = (N + (int64_t)kBlock * tpl - 1) / ((int64_t)kBlock * tpl);
@@ -288,8 +554,71 @@ size_t product_ws_bytes(int64_t N, int prec, int kblk) {
     size_t b = align_up((size_t)N * rec_width(prec, kblk) * real_size(prec));
     b += align_up((size_t)N * sizeof(double));
     b += align_up((size_t)smax * kblk * 3 * N * sizeof(double));
-    return b + 4 * kAlign;
+    size_t sb = 0;
+    for (int K = 1; K <= std::min(kblk, 4); K <<= 1) {
+        const SymPlan sp = sym_plan(N, prec, K, 1);
+        if (sp.ok) sb = std::max(sb, sp.rec_bytes + sp.tpart_bytes + sp.spart_bytes);
+    }
+    return std::max(b, sb) + 8 * kAlign;
 }
+
+namespace {
+
+int sym_pass(const double* pos, const double* F, double* U, int64_t N, int kb, int K, double a, double eta, int prec,
+             const SymPlan& sp, int ipw, Arena& ar, hipStream_t st) {
+    const size_t mark = ar.used;
+    const int rw = rec_width(prec, K);
+    const int64_t npad = (int64_t)sp.ng * 256;
+    void* rec = ar.take((size_t)npad * rw * real_size(prec));
+    double* B = (double*)ar.take((size_t)npad * sizeof(double));
+    double* tpart = (double*)ar.take(sp.tpart_bytes);
+    void* spart = ar.take(sp.spart_bytes);
+    if (!rec || !B || !tpart || !spart) {
+        ar.used = mark;
+        return RPYW_ENOMEM;
+    }
+    const unsigned g1 = (unsigned)((N + kBlock - 1) / kBlock);
+    const unsigned gp = (unsigned)((npad - N + kBlock - 1) / kBlock);
+    if (prec == RPYW_FP32C) {
+        hipLaunchKernelGGL(pack_kernel<float>, dim3(g1), dim3(kBlock), 0, st, pos, F, N, kb, rw, 1.0 / a, (float*)rec, B,
+                           nullptr);
+        if (gp) hipLaunchKernelGGL(pad_kernel<float>, dim3(gp), dim3(kBlock), 0, st, (float*)rec, N, npad, rw, B);
+    } else {
+        hipLaunchKernelGGL(pack_kernel<double>, dim3(g1), dim3(kBlock), 0, st, pos, F, N, kb, rw, 1.0 / a,
+                           (double*)rec, B, nullptr);
+        if (gp) hipLaunchKernelGGL(pad_kernel<double>, dim3(gp), dim3(kBlock), 0, st, (double*)rec, N, npad, rw, B);
+    }
+    RPYW_HIP(hipGetLastError());
+    hipEvent_t ev = nullptr;
+    profile_begin(st, &ev);
+    hipError_t e;
+    auto go = [&](auto Rt, auto Kc) -> hipError_t {
+        using R = decltype(Rt);
+        constexpr int KK = decltype(Kc)::value;
+        return launch_sym_t<R, KK>((const R*)rec, sp.ng, sp.C, ipw, sp.Hmax, tpart, (R*)spart, st);
+    };
+    if (prec == RPYW_FP32C)
+        e = K == 1 ? go(0.f, std::integral_constant<int, 1>{})
+                   : K == 2 ? go(0.f, std::integral_constant<int, 2>{}) : go(0.f, std::integral_constant<int, 4>{});
+    else
+        e = K == 1 ? go(0.0, std::integral_constant<int, 1>{})
+                   : K == 2 ? go(0.0, std::integral_constant<int, 2>{}) : go(0.0, std::integral_constant<int, 4>{});
+    if (e != hipSuccess) return RPYW_EHIP;
+    profile_end(st, ev, (double)kb * (double)N * (double)N);
+    const double m0 = mu0_of(a, eta);
+    const dim3 ge(g1, (unsigned)(3 * kb));
+    if (prec == RPYW_FP32C)
+        hipLaunchKernelGGL(sym_epilogue<float>, ge, dim3(kBlock), 0, st, tpart, (const float*)spart, B, N, sp.ng, sp.C,
+                           sp.Hmax, K, kb, m0, U);
+    else
+        hipLaunchKernelGGL(sym_epilogue<double>, ge, dim3(kBlock), 0, st, tpart, (const double*)spart, B, N, sp.ng,
+                           sp.C, sp.Hmax, K, kb, m0, U);
+    RPYW_HIP(hipGetLastError());
+    ar.used = mark;
+    return RPYW_OK;
+}
+
+}  // namespace
 
 int product_pass(const double* pos, const double* F, double* U, int64_t N, int kb, double a, double eta, int prec,
                  Shape sh, Arena& ar, hipStream_t st) {
@@ -297,6 +626,10 @@ int product_pass(const double* pos, const double* F, double* U, int64_t N, int k
     const int K = kernel_k(kb, prec);
     if (kb < 1 || kb > K) return RPYW_EINVAL;
     sh = normalized(sh, K);
+    if (sh.sym && K <= 4) {
+        const SymPlan sp = sym_plan(N, prec, K, sh.ipw);
+        if (sp.ok) return sym_pass(pos, F, U, N, kb, K, a, eta, prec, sp, sh.ipw, ar, st);
+    }
     const int rw = rec_width(prec, K);
     void* rec = ar.take((size_t)N * rw * real_size(prec));
     double* B = (double*)ar.take((size_t)N * sizeof(double));

@@ -21,7 +21,17 @@ struct Shape {
     int tpl;   // targets per lane: 1 or 2
     int tile;  // sources per LDS tile: 64 or 256
     int kblk;  // right-hand sides per pass: 1, 2, 4, 8 or 16
+    int sym;   // 1: symmetric pair evaluation (kblk <= 4), items per workgroup in ipw
+    int ipw;   // symmetric path: source groups per workgroup
 };
+
+// Symmetric path geometry for N blobs, K right-hand sides.
+struct SymPlan {
+    int ng, Hmax, C;
+    size_t rec_bytes, tpart_bytes, spart_bytes;
+    bool ok;
+};
+SymPlan sym_plan(int64_t N, int prec, int K, int ipw);
 
 // Bump allocator over a caller workspace.
 struct Arena {

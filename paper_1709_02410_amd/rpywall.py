@@ -53,6 +53,8 @@ def lib():
         "rpy_wall_autotune": [vp, vp, vp, i64, i32, dbl, dbl, ctypes.c_int, vp, sz, vp],
         "rpyw_tridiag_sqrt_coeffs": [ctypes.POINTER(dbl), ctypes.POINTER(dbl), i32, dbl, ctypes.POINTER(dbl)],
         "rpy_wall_profile_enable": [ctypes.c_int],
+        "rpy_wall_set_shape": [ctypes.c_int, i64, i32, i32, i32, i32, i32, i32],
+        "rpy_wall_get_shape": [ctypes.c_int, i64, i32, ctypes.POINTER(i32)],
         "rpy_wall_profile_read": [ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl), ctypes.c_int],
     }
     for name, args in sig.items():
@@ -210,6 +212,19 @@ def autotune(pos: torch.Tensor, F: torch.Tensor, a: float = 1.0, eta: float = 1.
     ws = _workspace(workspace_bytes(OP_MATVEC, N, k, precision=precision), pos.device)
     _check(lib().rpy_wall_autotune(pos.data_ptr(), F.data_ptr(), U.data_ptr(), N, k, a, eta, precision,
                                    ws.data_ptr(), ws.numel(), _stream(pos.device)), "rpy_wall_autotune")
+
+
+def set_shape(precision: int, N: int, k: int = 1, tpl: int = 1, tile: int = 256, kblk: int = 1, sym: int = 0,
+              ipw: int = 4):
+    """Fix the launch shape for products of this precision and size class."""
+    _check(lib().rpy_wall_set_shape(precision, N, k, tpl, tile, kblk, sym, ipw), "rpy_wall_set_shape")
+
+
+def get_shape(precision: int, N: int, k: int = 1) -> dict:
+    """Launch shape that products of this precision and size class use."""
+    out = (ctypes.c_int32 * 5)()
+    _check(lib().rpy_wall_get_shape(precision, N, k, out), "rpy_wall_get_shape")
+    return dict(zip(("tpl", "tile", "kblk", "sym", "ipw"), list(out)))
 
 
 def tridiag_sqrt_coeffs(alpha, beta, beta0: float) -> np.ndarray:
