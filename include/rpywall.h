@@ -149,7 +149,8 @@ int rpy_wall_autotune(const double* pos, const double* F, double* U, int64_t N, 
  * 256); kblk: RHS block width (1..16, FP64 up to 8); sym: 1 selects the
  * symmetric kernel, which evaluates each unordered pair once and applies it
  * in both directions (kblk <= 4); ipw: source groups per workgroup of the
- * symmetric kernel.  Host-only, takes effect for later calls. */
+ * symmetric kernel.  tpl = 0 removes the override (back to the tuner's or
+ * the built-in choice).  Host-only, takes effect for later calls. */
 int rpy_wall_set_shape(int precision, int64_t N, int32_t k, int32_t tpl, int32_t tile, int32_t kblk, int32_t sym,
                        int32_t ipw);
 

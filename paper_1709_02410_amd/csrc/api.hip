@@ -100,6 +100,11 @@ void set_tuned_shape(int64_t N, int k, int prec, Shape s) {
     g_shapes[{prec, size_class(N), kclass(k)}] = s;
 }
 
+void clear_tuned_shape(int64_t N, int k, int prec) {
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    g_shapes.erase({prec, size_class(N), kclass(k)});
+}
+
 bool profiling_enabled() { return g_prof; }
 
 void profile_begin(hipStream_t st, hipEvent_t* ev) {
@@ -300,6 +305,10 @@ int rpy_wall_autotune(const double* pos, const double* F, double* U, int64_t N, 
 
 int rpy_wall_set_shape(int precision, int64_t N, int32_t k, int32_t tpl, int32_t tile, int32_t kblk, int32_t sym,
                        int32_t ipw) {
+    if (tpl == 0 && valid_prec(precision) && N >= 1 && N < kMaxN && k >= 1) {
+        clear_tuned_shape(N, k, precision);
+        return RPYW_OK;
+    }
     if (!valid_prec(precision) || N < 1 || N >= kMaxN || k < 1 || (tpl != 1 && tpl != 2) ||
         (tile != 64 && tile != 256) || kblk < 1 || kblk > (precision == RPYW_FP32C ? 16 : 8) ||
         (kblk & (kblk - 1)) != 0 || (sym != 0 && sym != 1) || (sym && kblk > 4) || ipw < 1)

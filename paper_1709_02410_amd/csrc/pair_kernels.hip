@@ -25,6 +25,7 @@
 #include "pair_math.h"
 #include "records.h"
 #include "rpyw_internal.h"
+#include "sym_pairs.h"
 
 namespace rpyw {
 
@@ -195,208 +196,39 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(const R* __restrict__ r
 
 // ------------------------------------------------------------ symmetric product
 //
-// Reciprocity (M_ji = M_ij^T) lets one evaluation of a pair's coefficients
-// serve both directions: M_ji f = the same block applied with the two
-// off-diagonal wall coefficients (kcp, kcm) exchanged.  Blobs are grouped in
-// 256 (four 64-lane blocks).  Work item (P, d): target group P against source
-// group Q = (P + d) mod ng, d = 0 .. H(P), which covers every unordered group
-// pair once.  Wave w holds target block 4P + w; for each source block of Q it
-// runs 64 steps in which lane l pairs its target with source (l + s) mod 64,
-// adds M_ij f_j to its target sums and M_ji f_i to a source accumulator that
-// moves one lane down after every step, so that after the pass lane l holds
-// the complete sum for source l of the block.  Within the diagonal item
-// (d = 0) blocks above the wave's own are done symmetrically, the wave's own
-// block over all ordered pairs (self included), and blocks below it are left
-// to the waves that own them.  Target sums are written per (row, chunk) and
-// source sums per (group, d); the epilogue adds both in a fixed order.
-
-// Number of source-group offsets d > 0 that row P owns (ng groups).
-__host__ __device__ inline int sym_rowlen(int P, int ng) {
-    return (ng & 1) ? (ng - 1) / 2 : ng / 2 - 1 + (P < ng / 2 ? 1 : 0);
-}
-
-// Lane l receives the value held by lane (l + 1) mod 64.
-__device__ __forceinline__ float rot_next(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x134, 0xF, 0xF, false));
-}
-__device__ __forceinline__ double rot_next(double v) {
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x134, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x134, 0xF, 0xF, false);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
-}
-
-template <typename R>
-struct Vec;
-template <>
-struct Vec<float> {
-    using T = float4;
-    static constexpr int W = 4;
-    __device__ static float get(const float4& v, int e) { return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w; }
-};
-template <>
-struct Vec<double> {
-    using T = double2;
-    static constexpr int W = 2;
-    __device__ static double get(const double2& v, int e) { return e == 0 ? v.x : v.y; }
-};
+// Each unordered pair is evaluated once (sym_pairs.h): the target side
+// accumulates M_ij f_j, the source side M_ji f_i, which is the same block
+// applied with the two off-diagonal wall coefficients exchanged.
 
 template <typename R, int K>
-struct SymLane {
-    static constexpr int RW = rec_w<R, K>();
-    static constexpr int NV = RW / Vec<R>::W;
-    static constexpr int PW = pos_slots<R>();
-    R x, y, z, xl, yl;
-    R f[K][3];
-    R acc[K][3], hi[K][3], lo[K][3];
-
-    // One 64-step pass over source block `blk` (LDS rows of 128 entries:
-    // the block's 64 records stored twice, so entry l + s needs no wrap).
+struct ProductBody {
+    static constexpr int KREC = K;
+    static constexpr int NQ = 3 * K;
     template <bool SYM>
-    __device__ void pass(const typename Vec<R>::T* __restrict__ tile, int blk, int l, R (&S)[K][3]) {
-        using VT = typename Vec<R>::T;
+    __device__ static void pair(const SymTarget<R, K>& t, const R* r, R (&acc)[NQ], R (&src)[NQ]) {
+        constexpr int PW = pos_slots<R>();
+        R dx, dy, dz;
+        sym_diff(t, r, dx, dy, dz);
+        PairCoef<R> p = pair_coef<R>(dx, dy, dz, t.z, r[2]);
 #pragma unroll
         for (int k = 0; k < K; ++k)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) S[k][c] = R(0);
-        const VT* base = tile + blk * 128 + l;
-#pragma unroll 4
-        for (int s = 0; s < 64; ++s) {
-            R r[RW];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const VT q = base[v * 512 + s];
-#pragma unroll
-                for (int e = 0; e < Vec<R>::W; ++e) r[v * Vec<R>::W + e] = Vec<R>::get(q, e);
-            }
-            R dx = x - r[0], dy = y - r[1];
-            if constexpr (sizeof(R) == 4) {
-                dx += xl - r[3];
-                dy += yl - r[4];
-            }
-            const R dz = z - r[2];
-            PairCoef<R> p = pair_coef<R>(dx, dy, dz, z, r[2]);
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                pair_apply<R>(p, dx, dy, dz, r[PW + 3 * k], r[PW + 3 * k + 1], r[PW + 3 * k + 2], acc[k][0], acc[k][1],
-                              acc[k][2]);
-            if constexpr (SYM) {
-                const R t = p.kcp;
-                p.kcp = p.kcm;
-                p.kcm = t;
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    R u[3] = {R(0), R(0), R(0)};
-                    pair_apply<R>(p, dx, dy, dz, f[k][0], f[k][1], f[k][2], u[0], u[1], u[2]);
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) S[k][c] = rot_next(S[k][c]) + u[c];
-                }
-            }
-        }
+            pair_apply<R>(p, dx, dy, dz, r[PW + 3 * k], r[PW + 3 * k + 1], r[PW + 3 * k + 2], acc[3 * k],
+                          acc[3 * k + 1], acc[3 * k + 2]);
         if constexpr (SYM) {
+            const R x = p.kcp;
+            p.kcp = p.kcm;
+            p.kcm = x;
 #pragma unroll
-            for (int k = 0; k < K; ++k)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) S[k][c] = rot_next(S[k][c]);
+            for (int k = 0; k < K; ++k) {
+                src[3 * k] = src[3 * k + 1] = src[3 * k + 2] = R(0);
+                pair_apply<R>(p, dx, dy, dz, t.f[k][0], t.f[k][1], t.f[k][2], src[3 * k], src[3 * k + 1],
+                              src[3 * k + 2]);
+            }
         }
-        if constexpr (sizeof(R) == 4) {
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    two_sum_acc(hi[k][c], lo[k][c], acc[k][c]);
-                    acc[k][c] = R(0);
-                }
-        }
-    }
-
-    __device__ double total(int k, int c) const {
-        if constexpr (sizeof(R) == 4)
-            return (double)hi[k][c] + (double)lo[k][c];
-        else
-            return (double)acc[k][c];
     }
 };
 
-// rec: ng * 256 records (padded with force-free blobs far away).
-// tpart: [ng * C][3K][256] doubles; spart: [ng * (Hmax + 1)][3K][256].
-template <typename R, int K>
-__global__ __launch_bounds__(kBlock) void sym_kernel(const R* __restrict__ rec, int ng, int C, int ipw, int Hmax,
-                                                     double* __restrict__ tpart, R* __restrict__ spart) {
-    using VT = typename Vec<R>::T;
-    using L = SymLane<R, K>;
-    __shared__ VT tile[L::NV * 512];
-    __shared__ R red[4][3 * K][256];
-    const int P = blockIdx.x / C, c = blockIdx.x % C;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    L me;
-    {
-        const R* r = rec + ((int64_t)P * 256 + threadIdx.x) * L::RW;
-        me.x = r[0];
-        me.y = r[1];
-        me.z = r[2];
-        me.xl = sizeof(R) == 4 ? r[3] : R(0);
-        me.yl = sizeof(R) == 4 ? r[4] : R(0);
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-#pragma unroll
-            for (int cc = 0; cc < 3; ++cc) {
-                me.f[k][cc] = r[L::PW + 3 * k + cc];
-                me.acc[k][cc] = me.hi[k][cc] = me.lo[k][cc] = R(0);
-            }
-    }
-    const int H = sym_rowlen(P, ng);
-    const int d0 = c * ipw;
-    const int d1 = d0 + ipw - 1 < H ? d0 + ipw - 1 : H;
-    for (int d = d0; d <= d1; ++d) {
-        const int Q = (P + d) % ng;
-        __syncthreads();
-        {
-            const VT* g = reinterpret_cast<const VT*>(rec + ((int64_t)Q * 256 + threadIdx.x) * L::RW);
-            const int b = threadIdx.x >> 6, j = threadIdx.x & 63;
-#pragma unroll
-            for (int v = 0; v < L::NV; ++v) {
-                const VT q = g[v];
-                tile[v * 512 + b * 128 + j] = q;
-                tile[v * 512 + b * 128 + j + 64] = q;
-            }
-        }
-        __syncthreads();
-        for (int bb = 0; bb < 4; ++bb) {
-            const int blk = (w + bb) & 3;
-            R S[K][3];
-            if (d == 0 && blk < w) {
-#pragma unroll
-                for (int k = 0; k < K; ++k)
-#pragma unroll
-                    for (int cc = 0; cc < 3; ++cc) S[k][cc] = R(0);
-            } else if (d == 0 && blk == w) {
-                me.template pass<false>(tile, blk, l, S);
-            } else {
-                me.template pass<true>(tile, blk, l, S);
-            }
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc) red[w][3 * k + cc][blk * 64 + l] = S[k][cc];
-        }
-        __syncthreads();
-        R* out = spart + ((int64_t)Q * (Hmax + 1) + d) * (3 * K) * 256;
-#pragma unroll
-        for (int q = 0; q < 3 * K; ++q)
-            out[q * 256 + threadIdx.x] =
-                ((red[0][q][threadIdx.x] + red[1][q][threadIdx.x]) + red[2][q][threadIdx.x]) + red[3][q][threadIdx.x];
-    }
-    double* tp = tpart + ((int64_t)P * C + c) * (3 * K) * 256;
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc) tp[(3 * k + cc) * 256 + threadIdx.x] = me.total(k, cc);
-}
-
-// One thread per (blob, output component q = 3k + c).  Source slots of group
-// P: d = 0 .. Hmax, except that with an even group count the offset ng/2 is
-// owned only by rows below ng/2, so groups P < ng/2 stop at Hmax - 1.
+// One thread per (blob, output component q = 3k + c).
 template <typename R>
 __global__ void sym_epilogue(const double* __restrict__ tpart, const R* __restrict__ spart,
                              const double* __restrict__ B, int64_t N, int ng, int C, int Hmax, int K, int kb,
@@ -404,46 +236,18 @@ __global__ void sym_epilogue(const double* __restrict__ tpart, const R* __restri
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int q = blockIdx.y;
     if (i >= N || q >= 3 * kb) return;
-    const int P = (int)(i >> 8), t = (int)(i & 255);
-    const int dmax = ((ng & 1) == 0 && P < ng / 2) ? Hmax - 1 : Hmax;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    const double* tp = tpart + ((int64_t)P * C * (3 * K) + q) * 256 + t;
-    for (int c = 0; c < C; ++c) s0 += tp[(int64_t)c * (3 * K) * 256];
-    const R* sp = spart + ((int64_t)P * (Hmax + 1) * (3 * K) + q) * 256 + t;
-    const int64_t st = (int64_t)(3 * K) * 256;
-    int d = 0;
-    for (; d + 3 <= dmax; d += 4) {
-        s0 += (double)sp[(d + 0) * st];
-        s1 += (double)sp[(d + 1) * st];
-        s2 += (double)sp[(d + 2) * st];
-        s3 += (double)sp[(d + 3) * st];
-    }
-    for (; d <= dmax; ++d) s0 += (double)sp[d * st];
-    const int k = q / 3, cc = q % 3;
-    U[((int64_t)k * N + i) * 3 + cc] = mu0 * B[i] * ((s0 + s1) + (s2 + s3));
+    const double s = sym_gather<R>(tpart, spart, i, ng, C, Hmax, 3 * K, q);
+    U[((int64_t)(q / 3) * N + i) * 3 + q % 3] = mu0 * B[i] * s;
 }
 
 template <typename R, int K>
 hipError_t launch_sym_t(const R* rec, int ng, int C, int ipw, int Hmax, double* tpart, R* spart, hipStream_t st) {
-    hipLaunchKernelGGL((sym_kernel<R, K>), dim3((unsigned)(ng * C)), dim3(kBlock), 0, st, rec, ng, C, ipw, Hmax, tpart,
-                       spart);
+    hipLaunchKernelGGL((sym_kernel<R, ProductBody<R, K>>), dim3((unsigned)(ng * C)), dim3(kBlock), 0, st, rec, ng, C,
+                       ipw, Hmax, tpart, spart);
     return hipGetLastError();
 }
 
 __global__ void zero_u32(unsigned* p) { *p = 0u; }
-
-// Records [N, Npad): force-free blobs far from everything (x = y = 1e6 a).
-template <typename R>
-__global__ void pad_kernel(R* __restrict__ rec, int64_t N, int64_t Npad, int recw, double* __restrict__ B) {
-    const int64_t i = N + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= Npad) return;
-    R* r = rec + i * recw;
-    for (int e = 0; e < recw; ++e) r[e] = R(0);
-    r[0] = R(1e6);
-    r[1] = R(1e6);
-    r[2] = R(1);
-    B[i] = 0.0;
-}
 
 // ------------------------------------------------------------ dispatch
 

@@ -78,6 +78,7 @@ int batched_products(const double* pos, const int64_t* sys_offsets, int S, const
 Shape default_shape(int64_t N, int k, int prec);
 Shape tuned_shape(int64_t N, int k, int prec);
 void set_tuned_shape(int64_t N, int k, int prec, Shape s);
+void clear_tuned_shape(int64_t N, int k, int prec);
 
 // Instrumentation around the O(N^2) launches.
 bool profiling_enabled();

@@ -1,0 +1,262 @@
+// Symmetric evaluation of pair sums: every unordered pair (i, j) is
+// evaluated once and contributes to both blobs.  This uses the reciprocity
+// of the blob mobility (M_ji = M_ij^T, arXiv:1709.02410 Sec. II.A: M is
+// symmetric), under which the transposed block is the same coefficient set
+// with the two off-diagonal wall coefficients exchanged.
+//
+// Work decomposition.  Blobs are grouped by 256 (four 64-lane blocks).  Work
+// item (P, d) pairs target group P with source group Q = (P + d) mod ng for
+// d = 0 .. H(P) (sym_rowlen), which covers every unordered pair of groups
+// exactly once.  A workgroup of four waves takes `ipw` consecutive items of
+// one row.  Wave w holds target block 4P + w; for each source block of Q it
+// runs 64 steps in which lane l pairs its target with source (l + s) mod 64,
+// read from LDS rows that hold the block twice (so l + s needs no wrap).  The
+// lane adds the target-side contribution to its own sums and the source-side
+// contribution to an accumulator that moves one lane down after every step
+// (a DPP wavefront rotate fused into the add), so that after the pass lane l
+// holds the complete source-side sum of source l.  In the diagonal item
+// (d = 0) blocks above the wave's own are done symmetrically, the wave's own
+// block over all ordered pairs (self included, target side only), and blocks
+// below it are left to the waves that own them.  Target sums are written per
+// (row, chunk) and source sums per (group, d); an epilogue adds both in a
+// fixed order, so results are bitwise reproducible.
+//
+// A Body supplies the per-pair arithmetic: KREC right-hand sides in the
+// record, NQ accumulated quantities, and
+//   template <bool SYM> static void pair(const SymTarget&, const R* rec,
+//                                        R (&acc)[NQ], R (&src)[NQ]);
+// which adds the target-side contribution to acc and, when SYM, writes the
+// source-side contribution to src.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "pair_math.h"
+#include "records.h"
+
+namespace rpyw {
+
+constexpr int kSymBlock = 256;
+
+// Number of source-group offsets d > 0 that row P owns (ng groups).
+__host__ __device__ inline int sym_rowlen(int P, int ng) {
+    return (ng & 1) ? (ng - 1) / 2 : ng / 2 - 1 + (P < ng / 2 ? 1 : 0);
+}
+
+// Last source slot d of group P that some item fills (see sym_rowlen).
+__host__ __device__ inline int sym_dmax(int P, int ng) {
+    const int hmax = ng / 2;
+    return ((ng & 1) == 0 && P < ng / 2) ? hmax - 1 : hmax;
+}
+
+// Lane l receives the value held by lane (l + 1) mod 64.
+__device__ __forceinline__ float rot_next(float v) {
+    return __builtin_bit_cast(float,
+                              __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x134, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double rot_next(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x134, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x134, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+template <typename R>
+struct Vec;
+template <>
+struct Vec<float> {
+    using T = float4;
+    static constexpr int W = 4;
+    __device__ static float get(const float4& v, int e) { return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w; }
+};
+template <>
+struct Vec<double> {
+    using T = double2;
+    static constexpr int W = 2;
+    __device__ static double get(const double2& v, int e) { return e == 0 ? v.x : v.y; }
+};
+
+// The target a lane holds: scaled position (FP32: plus low parts) and the
+// record's right-hand sides.
+template <typename R, int KREC>
+struct SymTarget {
+    R x, y, z, xl, yl;
+    R f[KREC][3];
+};
+
+// Difference vector target - source of a record (FP32: hi/lo parts).
+template <typename R, int KREC>
+__device__ __forceinline__ void sym_diff(const SymTarget<R, KREC>& t, const R* r, R& dx, R& dy, R& dz) {
+    dx = t.x - r[0];
+    dy = t.y - r[1];
+    if constexpr (sizeof(R) == 4) {
+        dx += t.xl - r[3];
+        dy += t.yl - r[4];
+    }
+    dz = t.z - r[2];
+}
+
+template <typename R, class Body>
+struct SymLane {
+    static constexpr int KREC = Body::KREC;
+    static constexpr int NQ = Body::NQ;
+    static constexpr int RW = rec_w<R, KREC>();
+    static constexpr int NV = RW / Vec<R>::W;
+    SymTarget<R, KREC> t;
+    R acc[NQ], hi[NQ], lo[NQ];
+
+    __device__ void load(const R* __restrict__ r) {
+        t.x = r[0];
+        t.y = r[1];
+        t.z = r[2];
+        t.xl = sizeof(R) == 4 ? r[3] : R(0);
+        t.yl = sizeof(R) == 4 ? r[4] : R(0);
+#pragma unroll
+        for (int k = 0; k < KREC; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) t.f[k][c] = r[pos_slots<R>() + 3 * k + c];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] = hi[q] = lo[q] = R(0);
+    }
+
+    // One 64-step pass over source block `blk`; S returns the source-side
+    // sums (lane l: source l of the block) when SYM, zeros otherwise.
+    template <bool SYM>
+    __device__ void pass(const typename Vec<R>::T* __restrict__ tile, int blk, int l, R (&S)[NQ]) {
+        using VT = typename Vec<R>::T;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) S[q] = R(0);
+        const VT* base = tile + blk * 128 + l;
+#pragma unroll 4
+        for (int s = 0; s < 64; ++s) {
+            R r[RW];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const VT q = base[v * 512 + s];
+#pragma unroll
+                for (int e = 0; e < Vec<R>::W; ++e) r[v * Vec<R>::W + e] = Vec<R>::get(q, e);
+            }
+            R c[NQ];
+            Body::template pair<SYM>(t, r, acc, c);
+            if constexpr (SYM) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) S[q] = rot_next(S[q]) + c[q];
+            }
+        }
+        if constexpr (SYM) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) S[q] = rot_next(S[q]);
+        }
+        if constexpr (sizeof(R) == 4) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                two_sum_acc(hi[q], lo[q], acc[q]);
+                acc[q] = R(0);
+            }
+        }
+    }
+
+    __device__ double total(int q) const {
+        if constexpr (sizeof(R) == 4)
+            return (double)hi[q] + (double)lo[q];
+        else
+            return (double)acc[q];
+    }
+};
+
+// rec: ng * 256 records (padded with force-free blobs far away).
+// tpart: [ng * C][NQ][256] doubles; spart: [ng * (Hmax + 1)][NQ][256].
+template <typename R, class Body>
+__global__ __launch_bounds__(kSymBlock) void sym_kernel(const R* __restrict__ rec, int ng, int C, int ipw, int Hmax,
+                                                        double* __restrict__ tpart, R* __restrict__ spart) {
+    using L = SymLane<R, Body>;
+    using VT = typename Vec<R>::T;
+    constexpr int NQ = L::NQ;
+    __shared__ VT tile[L::NV * 512];
+    __shared__ R red[4][NQ][256];
+    const int P = blockIdx.x / C, c = blockIdx.x % C;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    L me;
+    me.load(rec + ((int64_t)P * 256 + threadIdx.x) * L::RW);
+    const int H = sym_rowlen(P, ng);
+    const int d0 = c * ipw;
+    const int d1 = d0 + ipw - 1 < H ? d0 + ipw - 1 : H;
+    for (int d = d0; d <= d1; ++d) {
+        const int Q = (P + d) % ng;
+        __syncthreads();
+        {
+            const VT* g = reinterpret_cast<const VT*>(rec + ((int64_t)Q * 256 + threadIdx.x) * L::RW);
+            const int b = threadIdx.x >> 6, j = threadIdx.x & 63;
+#pragma unroll
+            for (int v = 0; v < L::NV; ++v) {
+                const VT q = g[v];
+                tile[v * 512 + b * 128 + j] = q;
+                tile[v * 512 + b * 128 + j + 64] = q;
+            }
+        }
+        __syncthreads();
+        for (int bb = 0; bb < 4; ++bb) {
+            const int blk = (w + bb) & 3;
+            R S[NQ];
+            if (d == 0 && blk < w) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) S[q] = R(0);
+            } else if (d == 0 && blk == w) {
+                me.template pass<false>(tile, blk, l, S);
+            } else {
+                me.template pass<true>(tile, blk, l, S);
+            }
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) red[w][q][blk * 64 + l] = S[q];
+        }
+        __syncthreads();
+        R* out = spart + ((int64_t)Q * (Hmax + 1) + d) * NQ * 256;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            out[q * 256 + threadIdx.x] =
+                ((red[0][q][threadIdx.x] + red[1][q][threadIdx.x]) + red[2][q][threadIdx.x]) + red[3][q][threadIdx.x];
+    }
+    double* tp = tpart + ((int64_t)P * C + c) * NQ * 256;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) tp[q * 256 + threadIdx.x] = me.total(q);
+}
+
+// Sum of quantity q of blob i over the chunk target partials and the item
+// source partials, in a fixed order.
+template <typename R>
+__device__ __forceinline__ double sym_gather(const double* __restrict__ tpart, const R* __restrict__ spart, int64_t i,
+                                             int ng, int C, int Hmax, int NQ, int q) {
+    const int P = (int)(i >> 8), t = (int)(i & 255);
+    const int dmax = sym_dmax(P, ng);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    const double* tp = tpart + ((int64_t)P * C * NQ + q) * 256 + t;
+    for (int c = 0; c < C; ++c) s0 += tp[(int64_t)c * NQ * 256];
+    const R* sp = spart + ((int64_t)P * (Hmax + 1) * NQ + q) * 256 + t;
+    const int64_t st = (int64_t)NQ * 256;
+    int d = 0;
+    for (; d + 3 <= dmax; d += 4) {
+        s0 += (double)sp[(d + 0) * st];
+        s1 += (double)sp[(d + 1) * st];
+        s2 += (double)sp[(d + 2) * st];
+        s3 += (double)sp[(d + 3) * st];
+    }
+    for (; d <= dmax; ++d) s0 += (double)sp[d * st];
+    return (s0 + s1) + (s2 + s3);
+}
+
+// Records [N, Npad): force-free blobs far from everything (x = y = 1e6 a).
+template <typename R>
+__global__ void pad_kernel(R* __restrict__ rec, int64_t N, int64_t Npad, int recw, double* __restrict__ B) {
+    const int64_t i = N + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Npad) return;
+    R* r = rec + i * recw;
+    for (int e = 0; e < recw; ++e) r[e] = R(0);
+    r[0] = R(1e6);
+    r[1] = R(1e6);
+    r[2] = R(1);
+    B[i] = 0.0;
+}
+
+}  // namespace rpyw

@@ -16,6 +16,7 @@
 #include "pair_math.h"
 #include "records.h"
 #include "rpyw_internal.h"
+#include "sym_pairs.h"
 
 namespace rpyw {
 
@@ -111,6 +112,68 @@ __global__ void vjp_epilogue(const double* __restrict__ part, const double* __re
         for (int c = 0; c < 3; ++c) grad_f[3 * i + c] = mu0 * B * s[6 + c];
 }
 
+// Symmetric VJP (sym_pairs.h).  For the pair (i, j) the scalar
+//   Phi = G~_i^T Mhat(r~_i, r~_j) F~_j + F~_i^T Mhat(r~_i, r~_j) G~_j
+// is also the pair's term seen from j (reciprocity), so one analytic pair
+// gradient gives both blobs' contributions: the target derivatives for i and
+// the source derivatives for j.  The two products are applied directly for i
+// and transposed (wall coefficients exchanged) for j.
+template <typename R>
+struct VjpBody {
+    static constexpr int KREC = 2;  // F~, G~
+    static constexpr int NQ = kQ;   // grad (3), Mhat F~ (3), Mhat G~ (3)
+    template <bool SYM>
+    __device__ static void pair(const SymTarget<R, 2>& t, const R* r, R (&acc)[kQ], R (&src)[kQ]) {
+        constexpr int PW = pos_slots<R>();
+        R dx, dy, dz;
+        sym_diff(t, r, dx, dy, dz);
+        const R zj = r[2];
+        const R Bf[3] = {r[PW], r[PW + 1], r[PW + 2]};
+        const R Bg[3] = {r[PW + 3], r[PW + 4], r[PW + 5]};
+        PairCoef<R> p;
+        const PairGrad<R> g = pair_grad<R>(dx, dy, dz, t.z, zj, t.f[1], Bf, t.f[0], Bg, &p);
+        acc[0] += g.dx;
+        acc[1] += g.dy;
+        acc[2] += fma_(zj, g.zz, g.dz + g.rz);
+        pair_apply<R>(p, dx, dy, dz, Bf[0], Bf[1], Bf[2], acc[3], acc[4], acc[5]);
+        pair_apply<R>(p, dx, dy, dz, Bg[0], Bg[1], Bg[2], acc[6], acc[7], acc[8]);
+        if constexpr (SYM) {
+            src[0] = -g.dx;
+            src[1] = -g.dy;
+            src[2] = fma_(t.z, g.zz, g.rz - g.dz);
+            const R x = p.kcp;
+            p.kcp = p.kcm;
+            p.kcm = x;
+#pragma unroll
+            for (int q = 3; q < kQ; ++q) src[q] = R(0);
+            pair_apply<R>(p, dx, dy, dz, t.f[0][0], t.f[0][1], t.f[0][2], src[3], src[4], src[5]);
+            pair_apply<R>(p, dx, dy, dz, t.f[1][0], t.f[1][1], t.f[1][2], src[6], src[7], src[8]);
+        }
+    }
+};
+
+template <typename R>
+__global__ void sym_vjp_epilogue(const double* __restrict__ tpart, const R* __restrict__ spart,
+                                 const double* __restrict__ pos, const double* __restrict__ f,
+                                 const double* __restrict__ g, int64_t N, int ng, int C, int Hmax, double inv_a,
+                                 double mu0, double* __restrict__ grad_pos, double* __restrict__ grad_f) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double s[kQ];
+    for (int q = 0; q < kQ; ++q) s[q] = sym_gather<R>(tpart, spart, i, ng, C, Hmax, kQ, q);
+    const double z = pos[3 * i + 2] * inv_a;
+    const double B = z < 1.0 ? z : 1.0;
+    if (grad_pos) {
+        const double dLdB = mu0 * (g[3 * i] * s[3] + g[3 * i + 1] * s[4] + g[3 * i + 2] * s[5] + f[3 * i] * s[6] +
+                                   f[3 * i + 1] * s[7] + f[3 * i + 2] * s[8]);
+        grad_pos[3 * i] = mu0 * inv_a * s[0];
+        grad_pos[3 * i + 1] = mu0 * inv_a * s[1];
+        grad_pos[3 * i + 2] = z < 1.0 ? inv_a * dLdB : mu0 * inv_a * s[2];
+    }
+    if (grad_f)
+        for (int c = 0; c < 3; ++c) grad_f[3 * i + c] = mu0 * B * s[6 + c];
+}
+
 // div_i,a = sum_j sum_b d(M_ij)_ab / d r_j,b (source derivative; for j = i
 // the total derivative of the self block).  One thread per target; meant
 // for the small systems on which the divergence is checked.
@@ -158,6 +221,20 @@ __global__ void divergence_kernel(const double* __restrict__ pos, int64_t N, dou
 
 }  // namespace
 
+namespace {
+
+// Symmetric VJP plan: same groups as the product, 9 quantities per blob.
+bool vjp_sym_plan(int64_t N, int prec, int ipw, int* ng, int* C, int* Hmax, size_t* tb, size_t* sb) {
+    *ng = (int)((N + 255) / 256);
+    *Hmax = *ng / 2;
+    *C = (*Hmax + 1 + ipw - 1) / ipw;
+    *tb = align_up((size_t)*ng * *C * kQ * 256 * sizeof(double));
+    *sb = align_up((size_t)*ng * (*Hmax + 1) * kQ * 256 * real_size(prec));
+    return *tb <= ((size_t)4 << 30) && *sb <= ((size_t)4 << 30);
+}
+
+}  // namespace
+
 size_t vjp_ws_bytes(int64_t N, int prec) {
     int splits;
     int64_t chunk;
@@ -165,13 +242,69 @@ size_t vjp_ws_bytes(int64_t N, int prec) {
     size_t b = align_up((size_t)N * rec_width(prec, 2) * real_size(prec));
     b += align_up((size_t)N * sizeof(double));
     b += align_up((size_t)splits * kQ * N * sizeof(double));
-    return b + 4 * kAlign;
+    int ng, C, Hmax;
+    size_t tb, sb;
+    if (vjp_sym_plan(N, prec, 1, &ng, &C, &Hmax, &tb, &sb)) {
+        const size_t npad = (size_t)ng * 256;
+        const size_t s = align_up(npad * rec_width(prec, 2) * real_size(prec)) + align_up(npad * sizeof(double)) + tb + sb;
+        b = std::max(b, s);
+    }
+    return b + 8 * kAlign;
 }
 
 int vjp(const double* pos, const double* f, const double* g, double* grad_pos, double* grad_f, int64_t N, double a,
         double eta, int prec, Arena& ar, hipStream_t st) {
     const size_t mark = ar.used;
     const int rw = rec_width(prec, 2);
+    const Shape sh = tuned_shape(N, 1, prec);
+    int ng, C, Hmax;
+    size_t tb, sb;
+    const int ipw = sh.ipw < 1 ? 1 : sh.ipw;
+    const bool sym = sh.sym && vjp_sym_plan(N, prec, ipw, &ng, &C, &Hmax, &tb, &sb);
+    const double m0 = 1.0 / (6.0 * M_PI * eta * a);
+    const unsigned g1 = (unsigned)((N + kBlock - 1) / kBlock);
+    if (sym) {
+        const int64_t npad = (int64_t)ng * 256;
+        void* rec = ar.take((size_t)npad * rw * real_size(prec));
+        double* B = (double*)ar.take((size_t)npad * sizeof(double));
+        double* tpart = (double*)ar.take(tb);
+        void* spart = ar.take(sb);
+        if (!rec || !B || !tpart || !spart) {
+            ar.used = mark;
+            return RPYW_ENOMEM;
+        }
+        const unsigned gp = (unsigned)((npad - N + kBlock - 1) / kBlock);
+        hipEvent_t ev = nullptr;
+        if (prec == RPYW_FP32C) {
+            hipLaunchKernelGGL(pack_kernel<float>, dim3(g1), dim3(kBlock), 0, st, pos, f, N, 2, rw, 1.0 / a,
+                               (float*)rec, B, g);
+            if (gp) hipLaunchKernelGGL(pad_kernel<float>, dim3(gp), dim3(kBlock), 0, st, (float*)rec, N, npad, rw, B);
+            RPYW_HIP(hipGetLastError());
+            profile_begin(st, &ev);
+            hipLaunchKernelGGL((sym_kernel<float, VjpBody<float>>), dim3((unsigned)(ng * C)), dim3(kBlock), 0, st,
+                               (const float*)rec, ng, C, ipw, Hmax, tpart, (float*)spart);
+            RPYW_HIP(hipGetLastError());
+            profile_end(st, ev, (double)N * (double)N);
+            hipLaunchKernelGGL(sym_vjp_epilogue<float>, dim3(g1), dim3(kBlock), 0, st, tpart, (const float*)spart, pos,
+                               f, g, N, ng, C, Hmax, 1.0 / a, m0, grad_pos, grad_f);
+        } else {
+            hipLaunchKernelGGL(pack_kernel<double>, dim3(g1), dim3(kBlock), 0, st, pos, f, N, 2, rw, 1.0 / a,
+                               (double*)rec, B, g);
+            if (gp)
+                hipLaunchKernelGGL(pad_kernel<double>, dim3(gp), dim3(kBlock), 0, st, (double*)rec, N, npad, rw, B);
+            RPYW_HIP(hipGetLastError());
+            profile_begin(st, &ev);
+            hipLaunchKernelGGL((sym_kernel<double, VjpBody<double>>), dim3((unsigned)(ng * C)), dim3(kBlock), 0, st,
+                               (const double*)rec, ng, C, ipw, Hmax, tpart, (double*)spart);
+            RPYW_HIP(hipGetLastError());
+            profile_end(st, ev, (double)N * (double)N);
+            hipLaunchKernelGGL(sym_vjp_epilogue<double>, dim3(g1), dim3(kBlock), 0, st, tpart, (const double*)spart,
+                               pos, f, g, N, ng, C, Hmax, 1.0 / a, m0, grad_pos, grad_f);
+        }
+        RPYW_HIP(hipGetLastError());
+        ar.used = mark;
+        return RPYW_OK;
+    }
     void* rec = ar.take((size_t)N * rw * real_size(prec));
     double* B = (double*)ar.take((size_t)N * sizeof(double));
     int splits;
@@ -182,7 +315,6 @@ int vjp(const double* pos, const double* f, const double* g, double* grad_pos, d
         ar.used = mark;
         return RPYW_ENOMEM;
     }
-    const unsigned g1 = (unsigned)((N + kBlock - 1) / kBlock);
     const int64_t nblocks = (int64_t)g1 * splits;
     hipEvent_t ev = nullptr;
     if (prec == RPYW_FP32C) {
@@ -202,8 +334,8 @@ int vjp(const double* pos, const double* f, const double* g, double* grad_pos, d
     }
     RPYW_HIP(hipGetLastError());
     profile_end(st, ev, (double)N * (double)N);
-    hipLaunchKernelGGL(vjp_epilogue, dim3(g1), dim3(kBlock), 0, st, part, pos, f, g, N, splits, 1.0 / a,
-                       1.0 / (6.0 * M_PI * eta * a), grad_pos, grad_f);
+    hipLaunchKernelGGL(vjp_epilogue, dim3(g1), dim3(kBlock), 0, st, part, pos, f, g, N, splits, 1.0 / a, m0, grad_pos,
+                       grad_f);
     RPYW_HIP(hipGetLastError());
     ar.used = mark;
     return RPYW_OK;

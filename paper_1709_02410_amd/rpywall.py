@@ -216,8 +216,14 @@ def autotune(pos: torch.Tensor, F: torch.Tensor, a: float = 1.0, eta: float = 1.
 
 def set_shape(precision: int, N: int, k: int = 1, tpl: int = 1, tile: int = 256, kblk: int = 1, sym: int = 0,
               ipw: int = 4):
-    """Fix the launch shape for products of this precision and size class."""
+    """Fix the launch shape for products of this precision and size class
+    (tpl=0 removes the override)."""
     _check(lib().rpy_wall_set_shape(precision, N, k, tpl, tile, kblk, sym, ipw), "rpy_wall_set_shape")
+
+
+def reset_shape(precision: int, N: int, k: int = 1):
+    """Back to the built-in or tuned launch shape for this size class."""
+    _check(lib().rpy_wall_set_shape(precision, N, k, 0, 0, 0, 0, 0), "rpy_wall_set_shape")
 
 
 def get_shape(precision: int, N: int, k: int = 1) -> dict:

@@ -129,3 +129,25 @@ def test_rfd_drift_estimate_matches_exact_divergence(rp, prec, delta):
     print(f"rfd prec={prec} max|z|={np.abs(z).max():.2f} chi2/dof={chi2 / dof:.3f}", flush=True)
     assert np.abs(z).max() < 5.0
     assert abs(chi2 - dof) < 6 * math.sqrt(2 * dof)
+
+
+@pytest.mark.parametrize("N", [1, 7, 300, 513, 1300])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 2e-5)])
+def test_symmetric_vjp_matches_oracle(rp, orc, N, prec, tol):
+    """The symmetric VJP kernel (one pair gradient per unordered pair, used
+    for both blobs) forced at small and ragged sizes, with blobs below the
+    wall and overlapping pairs."""
+    a, eta = 0.8, 1.1
+    pos = _mixed(N, 10 + N) * a
+    if N >= 3:
+        pos[2] = pos[1] + np.array([0.3, 0.0, 0.1]) * a
+    f = wl.gaussian(pos.shape, 20 + N)
+    g = wl.gaussian(pos.shape, 30 + N)
+    gp_ref, gf_ref = orc.vjp(pos, f, g, a, eta)
+    for ipw in (1, 2):
+        rp.set_shape(prec, N, 1, tpl=1, tile=256, kblk=1, sym=1, ipw=ipw)
+        gp, gf = rp.matvec_vjp(_t(pos), _t(f), _t(g), a, eta, precision=prec)
+        gp, gf = gp.cpu().numpy(), gf.cpu().numpy()
+        assert np.linalg.norm(gp - gp_ref) <= tol * np.linalg.norm(gp_ref)
+        assert np.linalg.norm(gf - gf_ref) <= tol * np.linalg.norm(gf_ref)
+    rp.reset_shape(prec, N, 1)

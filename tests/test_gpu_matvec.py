@@ -149,7 +149,7 @@ def test_symmetric_kernel_ragged(rp, orc, N, prec, kblk):
             assert _rel(U[l], ref) <= TOL[prec], (ipw, l, _rel(U[l], ref))
         U2 = rp.matvec_multi(_t(pos), _t(F), precision=prec).cpu().numpy()
         assert np.array_equal(U, U2)
-    rp.set_shape(prec, N, k, tpl=1, tile=256, kblk=kblk, sym=0)
+    rp.reset_shape(prec, N, k)
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -161,6 +161,7 @@ def test_symmetric_equals_plain_at_1e5(rp, prec):
     u_plain = rp.matvec(pos, f, precision=prec)
     rp.set_shape(prec, cfg.N, 1, tpl=1, tile=256, kblk=1, sym=1, ipw=4)
     u_sym = rp.matvec(pos, f, precision=prec)
+    rp.reset_shape(prec, cfg.N, 1)
     rel = float((u_sym - u_plain).norm() / u_plain.norm())
     print(f"sym vs plain prec={prec} rel={rel:.3e}", flush=True)
     assert rel <= (1e-13 if prec == 0 else 2e-6)
