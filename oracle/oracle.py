@@ -18,6 +18,11 @@ Contents (arXiv:1709.02410):
   * ``rfd_divergence``: the centred random-finite-difference estimate of
     the divergence of M (Sec. III, centred RFD with B = M and
     Delta P = Delta Q = W).
+  * ``body_K``/``rigid_solve``/``body_mobility``: rigid multiblobs
+    (Sec. II.A): the geometric matrix K, the saddle-point mobility problem
+    solved densely, and N = (K^T M^-1 K)^-1.
+  * ``rigid_gmres``: the same system by GMRES right-preconditioned with the
+    per-body block-diagonal operator (Sec. II.B); used for iteration counts.
 
 Readings where the paper is silent (the Lanczos stopping rule, full
 reorthogonalisation, breakdown handling) are stated in each docstring.
@@ -300,3 +305,152 @@ def rfd_divergence(pos, delta: float, n_samples: int, seed: int, a: float = 1.0,
     mean = acc / n_samples
     var = np.maximum(acc2 / n_samples - mean * mean, 0.0)
     return mean, np.sqrt(var / n_samples)
+
+
+# ------------------------------------------------------------- rigid bodies
+
+def _body_ranges(N: int, body_offsets):
+    offs = np.asarray(body_offsets, dtype=np.int64)
+    if offs[0] != 0 or offs[-1] != N or np.any(np.diff(offs) < 1):
+        raise ValueError("body_offsets must start at 0, end at N and be strictly increasing")
+    return [(int(offs[p]), int(offs[p + 1])) for p in range(len(offs) - 1)]
+
+
+def _cross_matrix(d) -> np.ndarray:
+    """[d]_x with [d]_x v = d x v."""
+    return np.array([[0.0, -d[2], d[1]], [d[2], 0.0, -d[0]], [-d[1], d[0], 0.0]])
+
+
+def body_K(pos, q, body_offsets) -> np.ndarray:
+    """Geometric matrix K of Sec. II.A (eq. K), dense (3N, 6 n_bodies).
+
+    (K U)_i = u_p + omega_p x (r_i - q_p) for blob i of body p, with the
+    body unknowns ordered (u_x, u_y, u_z, omega_x, omega_y, omega_z) and q_p
+    the body's reference point.  omega x d = -[d]_x omega, so the blob's
+    3x6 block is [I, -[r_i - q_p]_x].  K^T maps blob forces to the body
+    force and torque about q_p.
+    """
+    pos = _c(pos)
+    q = _c(q).reshape(-1, 3)
+    ranges = _body_ranges(pos.shape[0], body_offsets)
+    K = np.zeros((3 * pos.shape[0], 6 * len(ranges)))
+    for p, (s, e) in enumerate(ranges):
+        for i in range(s, e):
+            K[3 * i:3 * i + 3, 6 * p:6 * p + 3] = np.eye(3)
+            K[3 * i:3 * i + 3, 6 * p + 3:6 * p + 6] = -_cross_matrix(pos[i] - q[p])
+    return K
+
+
+def _rigid_rhs(N: int, nb: int, slip, FT) -> np.ndarray:
+    s = np.zeros(3 * N) if slip is None else np.asarray(slip, dtype=np.float64).reshape(-1)
+    F = np.zeros(6 * nb) if FT is None else np.asarray(FT, dtype=np.float64).reshape(-1)
+    return np.concatenate([-s, -F])
+
+
+def rigid_solve(pos, q, body_offsets, slip=None, FT=None, a: float = 1.0, eta: float = 1.0):
+    """Mobility problem of rigid multiblobs (Sec. II.A, saddle-point system):
+
+        [ M   -K ] [lambda]   [-slip]
+        [-K^T  0 ] [  U   ] = [ -F  ]
+
+    assembled densely (M from the pair formula, K from body_K) and solved by
+    LU.  slip: (N, 3) prescribed slip (None = 0); FT: (n_bodies, 6) force
+    and torque about q_p (None = 0).  Returns (lambda (N, 3), U (nb, 6)).
+    """
+    pos = _c(pos)
+    N = pos.shape[0]
+    K = body_K(pos, q, body_offsets)
+    nb = K.shape[1] // 6
+    M = dense(pos, a, eta)
+    A = np.block([[M, -K], [-K.T, np.zeros((6 * nb, 6 * nb))]])
+    x = np.linalg.solve(A, _rigid_rhs(N, nb, slip, FT))
+    return x[:3 * N].reshape(N, 3), x[3 * N:].reshape(nb, 6)
+
+
+def body_mobility(pos, q, body_offsets, a: float = 1.0, eta: float = 1.0) -> np.ndarray:
+    """Body mobility N = (K^T M^-1 K)^-1 (Sec. II.A, eq. N_def), through a
+    dense Cholesky factorisation of M.  (6 nb, 6 nb)."""
+    K = body_K(pos, q, body_offsets)
+    cf = sla.cho_factor(dense(pos, a, eta), lower=True)
+    return np.linalg.inv(K.T @ sla.cho_solve(cf, K))
+
+
+def rigid_gmres(pos, q, body_offsets, slip=None, FT=None, a: float = 1.0, eta: float = 1.0,
+                tol: float = 1e-8, max_iter: int = 200, precondition: bool = True, matvec_fn=None,
+                nthreads: int = 0):
+    """The saddle-point system of rigid_solve by GMRES, right-preconditioned
+    with the block-diagonal approximation of Sec. II.B (interactions between
+    distinct bodies dropped, each body's own block M^(pp) kept, wall
+    included), i.e. the per-body saddle-point operator
+
+        P = [ diag_p M^(pp)   -K ]
+            [ -K^T             0 ],
+
+    applied exactly body by body (dense LU of each small system).
+
+    Plain GMRES (Saad): x0 = 0, Arnoldi on A P^-1 from b / |b| with
+    Gram-Schmidt applied twice per step, least-squares residual
+    min |beta e1 - H y| after every step; stop when it is <= tol |b| or on
+    breakdown.  x = P^-1 V y.  Returns (lambda (N, 3), U (nb, 6),
+    iterations, relative residual estimate, converged).
+    """
+    pos = _c(pos)
+    N = pos.shape[0]
+    ranges = _body_ranges(N, body_offsets)
+    nb = len(ranges)
+    q = _c(q).reshape(-1, 3)
+    K = body_K(pos, q, body_offsets)
+    b = _rigid_rhs(N, nb, slip, FT)
+    n = b.shape[0]
+    small = []
+    for p, (s, e) in enumerate(ranges):
+        Kp = K[3 * s:3 * e, 6 * p:6 * p + 6]
+        Mpp = dense(pos[s:e], a, eta)
+        small.append(np.block([[Mpp, -Kp], [-Kp.T, np.zeros((6, 6))]]))
+
+    def Pinv(v):
+        if not precondition:
+            return v.copy()
+        out = np.empty_like(v)
+        for p, (s, e) in enumerate(ranges):
+            rhs = np.concatenate([v[3 * s:3 * e], v[3 * N + 6 * p:3 * N + 6 * p + 6]])
+            sol = np.linalg.solve(small[p], rhs)
+            out[3 * s:3 * e] = sol[:3 * (e - s)]
+            out[3 * N + 6 * p:3 * N + 6 * p + 6] = sol[3 * (e - s):]
+        return out
+
+    def A(x):
+        lam, U = x[:3 * N], x[3 * N:]
+        if matvec_fn is None:
+            Ml = matvec(pos, lam.reshape(-1, 3), a, eta, nthreads=nthreads).reshape(-1)
+        else:
+            Ml = np.asarray(matvec_fn(lam.reshape(-1, 3))).reshape(-1)
+        return np.concatenate([Ml - K @ U, -(K.T @ lam)])
+
+    beta = float(np.linalg.norm(b))
+    if beta == 0.0:
+        return np.zeros((N, 3)), np.zeros((nb, 6)), 0, 0.0, True
+    V = np.zeros((n, max_iter + 1))
+    H = np.zeros((max_iter + 1, max_iter))
+    V[:, 0] = b / beta
+    res = 1.0
+    converged = False
+    k = 0
+    y = np.zeros(0)
+    for k in range(1, max_iter + 1):
+        w = A(Pinv(V[:, k - 1]))
+        for _ in range(2):
+            h = V[:, :k].T @ w
+            w -= V[:, :k] @ h
+            H[:k, k - 1] += h
+        H[k, k - 1] = np.linalg.norm(w)
+        e1 = np.zeros(k + 1)
+        e1[0] = beta
+        y = np.linalg.lstsq(H[:k + 1, :k], e1, rcond=None)[0]
+        res = float(np.linalg.norm(e1 - H[:k + 1, :k] @ y)) / beta
+        if res <= tol or H[k, k - 1] <= 1e-14 * beta:
+            converged = True
+            break
+        V[:, k] = w / H[k, k - 1]
+    x = Pinv(V[:, :len(y)] @ y)
+    return x[:3 * N].reshape(N, 3), x[3 * N:].reshape(nb, 6), k, res, converged
