@@ -35,7 +35,7 @@ PEAK_FP64 = 78.6   # TFLOP/s, MI355X FP64 vector
 FLOP_PAIR_SHARED = 84
 FLOP_PAIR_RHS = 24
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pair_kernel_traffic.json")
-KERNEL_SOURCES = ["pair_kernels.hip", "pair_math.h", "records.h"]
+KERNEL_SOURCES = ["pair_kernels.hip", "pair_math.h", "records.h", "sym_pairs.h"]
 
 
 def algorithmic_flop(N: int, k: int, sym: int) -> float:
@@ -57,9 +57,10 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def stored_traffic():
+def stored_traffic(shape: dict):
     """HBM bytes per launch of the headline pair kernel from the committed
-    counter runs, or None when the kernel sources changed since."""
+    counter runs, or None when the kernel sources changed since or the
+    counters were taken with another launch shape than `shape`."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -67,7 +68,11 @@ def stored_traffic():
         return None
     if t.get("kernel_hash") != kernel_hash():
         return None
-    return t.get("bytes_per_launch")
+    keys = ("sym", "ipw") if shape.get("sym") else ("sym", "tpl", "tile")
+    for e in t.get("shapes", []):
+        if all(e["shape"].get(k) == shape.get(k) for k in keys):
+            return e["bytes_per_launch"]
+    return None
 
 
 def main():
@@ -79,6 +84,9 @@ def main():
     ap.add_argument("--calib-copy", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--force-ipw", type=int, default=0,
+                    help="after tuning, force the symmetric headline kernel with this many items per workgroup "
+                         "(for counter runs of one launch shape)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -128,6 +136,8 @@ def main():
     F1 = f.view(1, N, 3)
     rp.autotune(pos, F1, precision=rp.FP32C)
     rp.autotune(pos, F1, precision=rp.FP64)
+    if args.force_ipw:
+        rp.set_shape(rp.FP32C, N, 1, tpl=1, tile=256, kblk=1, sym=1, ipw=args.force_ipw)
     step = lambda: rp.matvec(pos, f, precision=rp.FP32C, out=vel)  # noqa: E731
     wall, kms, launches, pairs = timed(step, args.steps, args.warmup)
     kavg = kms / launches
@@ -135,7 +145,7 @@ def main():
     shape32 = rp.get_shape(rp.FP32C, N, 1)
     flop_launch = algorithmic_flop(N, 1, shape32["sym"])
     achieved = flop_launch / (kavg * 1e-3) / 1e12
-    traffic = stored_traffic()
+    traffic = stored_traffic(shape32)
     kname = ("sym_kernel<float,1> (each unordered pair once, both directions)" if shape32["sym"]
              else f"pair_kernel<float,1,{shape32['tpl']},{shape32['tile']}>")
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32, "unit": "TFLOP/s",
@@ -222,6 +232,38 @@ def main():
         t1 = time.perf_counter() - t0
         rows["lanczos_C1_fp64_tol1e-6"] = {"blobs": C1.N, "iterations": it1, "converged": ok1, "ms": t1 * 1e3,
                                            "ms_per_iteration": t1 * 1e3 / max(it1, 1)}
+        # Rigid-body mobility solve (GMRES, block-diagonal preconditioner):
+        # 256 boomerangs, reference point at the corner blob, random F and T
+        q1 = T(C1.pos[C1.body_offsets[:-1]])
+        FT1 = T(wl.gaussian((len(C1.body_offsets) - 1, 6), 5))
+        for prec, pname in ((rp.FP64, "fp64"), (rp.FP32C, "fp32c")):
+            for tol in (1e-3, 1e-6):
+                rp.rigid_solve(pc1, q1, C1.body_offsets, None, FT1, tol=tol, precision=prec)
+                sync()
+                t0 = time.perf_counter()
+                _, _, itr, resr, okr = rp.rigid_solve(pc1, q1, C1.body_offsets, None, FT1, tol=tol, precision=prec)
+                sync()
+                tr = time.perf_counter() - t0
+                rows[f"rigid_C1_{pname}_tol{tol:g}"] = {"blobs": C1.N, "bodies": len(C1.body_offsets) - 1,
+                                                        "iterations": itr, "converged": okr, "residual": resr,
+                                                        "ms": tr * 1e3, "ms_per_iteration": tr * 1e3 / max(itr, 1)}
+        # Iterations versus suspension size with the paper's boomerang
+        # geometry (Sec. II.B: about five at tolerance 1e-3, size-independent)
+        for nbody in (256, 1024, 4096):
+            PB = wl.paperlike_boomerangs(nbody, seed=2)
+            ppb, qpb = T(PB.pos), T(PB.pos[PB.body_offsets[:-1]])
+            FTpb = T(wl.gaussian((nbody, 6), 11))
+            rp.rigid_solve(ppb, qpb, PB.body_offsets, None, FTpb, tol=1e-3, precision=rp.FP32C)
+            sync()
+            t0 = time.perf_counter()
+            _, _, itp, resp, okp = rp.rigid_solve(ppb, qpb, PB.body_offsets, None, FTpb, tol=1e-3,
+                                                 precision=rp.FP32C)
+            sync()
+            tp = time.perf_counter() - t0
+            rows[f"rigid_paperlike_{nbody}_fp32c_tol0.001"] = {
+                "blobs": PB.N, "bodies": nbody, "iterations": itp, "converged": okp, "residual": resp,
+                "ms": tp * 1e3, "ms_per_iteration": tp * 1e3 / max(itp, 1)}
+            del ppb, qpb, FTpb
         C2 = wl.config2(seed=0)
         pc2, W2 = T(C2.pos), T(wl.gaussian(C2.pos.shape, 3))
         sync()
@@ -237,7 +279,19 @@ def main():
                                             "ms_per_iteration": t2 * 1e3 / max(it2, 1)}
         rows["product_C2_fp32c"] = {"blobs": C2.N, "pairs_per_s": C2.N ** 2 / w2, "ms": w2 * 1e3,
                                     "rel_l2_vs_fp64": float((u32c2 - u64c2).norm() / u64c2.norm())}
-        del pc2, W2, u64c2, u32c2
+        nb2 = len(C2.body_offsets) - 1
+        q2 = T(C2.pos.reshape(nb2, 12, 3).mean(1))
+        FT2 = T(wl.gaussian((nb2, 6), 7))
+        rp.rigid_solve(pc2, q2, C2.body_offsets, None, FT2, tol=1e-3, precision=rp.FP32C)
+        sync()
+        t0 = time.perf_counter()
+        _, _, itr2, resr2, okr2 = rp.rigid_solve(pc2, q2, C2.body_offsets, None, FT2, tol=1e-3, precision=rp.FP32C)
+        sync()
+        tr2 = time.perf_counter() - t0
+        rows["rigid_C2_fp32c_tol0.001"] = {"blobs": C2.N, "bodies": nb2, "iterations": itr2, "converged": okr2,
+                                           "residual": resr2, "ms": tr2 * 1e3,
+                                           "ms_per_iteration": tr2 * 1e3 / max(itr2, 1)}
+        del pc2, W2, u64c2, u32c2, q2, FT2
 
         # VJP on the differentiation workload
         C4 = wl.config4(seed=0)

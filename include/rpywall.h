@@ -61,7 +61,8 @@ enum rpyw_op {
     RPYW_OP_BATCHED = 1,    /* rpy_wall_matvec_batched (N = total blobs, n_bodies = S) */
     RPYW_OP_LANCZOS = 2,    /* rpy_wall_lanczos_sqrt */
     RPYW_OP_VJP = 3,        /* rpy_wall_matvec_vjp */
-    RPYW_OP_DIVERGENCE = 4  /* rpy_wall_divergence */
+    RPYW_OP_DIVERGENCE = 4, /* rpy_wall_divergence */
+    RPYW_OP_RIGID = 5       /* rpy_wall_rigid_solve */
 };
 
 /* u = M(r) f  (Sec. II.A: the dense product whose cost dominates every
@@ -105,6 +106,36 @@ int rpy_wall_lanczos_sqrt(const double* pos, const double* W, double* out, int64
                           int precision, void* ws, size_t ws_bytes, int32_t* iters_out, double* err_est_out,
                           void* stream);
 
+/* Mobility problem of rigid multiblobs (Sec. II.A, saddle-point system):
+ *     M lambda - K U = -slip,    -K^T lambda = -F,
+ * for the blob forces lambda and the body velocities U_p = (u_p, omega_p),
+ * where (K U)_i = u_p + omega_p x (r_i - q_p) for blob i of body p and
+ * K^T lambda is the force and the torque about q_p.  Solved by GMRES (no
+ * restart, FP64 Arnoldi with two classical Gram-Schmidt passes, x0 = 0),
+ * right-preconditioned with the block-diagonal operator of Sec. II.B
+ * (interactions between distinct bodies dropped, each body's own dense
+ * block M^(pp) kept, wall included), which is inverted exactly body by
+ * body.  Stops when the residual estimate |b - A x| <= tol |b|,
+ * b = [-slip; -F], or on breakdown.  Random slip slip = M^{1/2} W (from
+ * rpy_wall_lanczos_sqrt) with F = 0 gives the Brownian body velocities
+ * U = N^{1/2} W, N = (K^T M^-1 K)^-1 (Sec. II.B); kT and dt scalings are
+ * the caller's.
+ * pos: device [N][3]; q: device [n_bodies][3] reference points;
+ * body_offsets: HOST int64 [n_bodies+1] (0 .. N, strictly increasing, at
+ * most 42 blobs per body); slip: device [N][3] or NULL (zero);
+ * force_torque: device [n_bodies][6] (F, T) or NULL (zero); outputs
+ * lambda: device [N][3], U: device [n_bodies][6] (u, omega).  `precision`
+ * selects the pair arithmetic of the products by M.  iters_out, res_out:
+ * HOST (may be NULL) receive the iterations and the relative residual
+ * estimate.  Synchronises `stream` once per iteration.  Returns
+ * RPYW_NOT_CONVERGED (iterate written) if max_iter is reached,
+ * RPYW_ENOTSPD if a body block has no Cholesky factor or a body's blobs do
+ * not fix all six rigid motions (a single blob, a straight rod). */
+int rpy_wall_rigid_solve(const double* pos, const double* q, const int64_t* body_offsets, int32_t n_bodies,
+                         const double* slip, const double* force_torque, double* lambda, double* U, int64_t N,
+                         double a, double eta, double tol, int32_t max_iter, int precision, void* ws,
+                         size_t ws_bytes, int32_t* iters_out, double* res_out, void* stream);
+
 /* Vector-Jacobian product of u = M(r) f for L = sum_i g_i . u_i
  * (derivatives of M drive the thermal drift, Sec. III):
  *   grad_force = M g  (M is symmetric),
@@ -126,8 +157,9 @@ int rpy_wall_divergence(const double* pos, double* div, int64_t N, double a, dou
                         void* ws, size_t ws_bytes, void* stream);
 
 /* Bytes of workspace an entry point needs.  op: enum rpyw_op.  N: blobs
- * (total blobs for BATCHED), k: right-hand sides, max_iter: Lanczos bound,
- * n_bodies: bodies for LANCZOS (0 = one per blob) or systems S for BATCHED.
+ * (total blobs for BATCHED), k: right-hand sides, max_iter: Lanczos or GMRES
+ * bound, n_bodies: bodies for LANCZOS (0 = one per blob) and RIGID, or
+ * systems S for BATCHED.
  * Returns 0 for invalid arguments. */
 size_t rpy_wall_workspace_bytes(int op, int64_t N, int32_t k, int32_t max_iter, int32_t n_bodies,
                                 int precision);
@@ -135,11 +167,14 @@ size_t rpy_wall_workspace_bytes(int op, int64_t N, int32_t k, int32_t max_iter, 
 /* Static description of a status code (never NULL). */
 const char* rpyw_strerror(int status);
 
-/* Choose the launch shape (targets per lane, source tile, RHS block width)
- * of the pair kernels for problems of this size by timing the candidates on
- * the given inputs; the result is kept for the rest of the process and is
- * used by every later call of the same precision and size class.  Inputs as
- * for rpy_wall_matvec_multi (k RHS); blocks until the timing is done. */
+/* Choose the launch shape (targets per lane, source tile, RHS block width,
+ * symmetric or plain kernel) of the pair kernels for problems of this size
+ * by timing the candidates on the given inputs; the result is kept for the
+ * rest of the process and is used by every later call of the same precision
+ * and size class.  Candidates are tried in a fixed order of preference and
+ * a later one must be at least 1.5% faster to replace an earlier one, so
+ * near-ties are resolved the same way from run to run.  Inputs as for
+ * rpy_wall_matvec_multi (k RHS); blocks until the timing is done. */
 int rpy_wall_autotune(const double* pos, const double* F, double* U, int64_t N, int32_t k, double a,
                       double eta, int precision, void* ws, size_t ws_bytes, void* stream);
 

@@ -158,6 +158,9 @@ size_t rpy_wall_workspace_bytes(int op, int64_t N, int32_t k, int32_t max_iter, 
             return lanczos_ws_bytes(N, max_iter, n_bodies, precision);
         case RPYW_OP_VJP:
         case RPYW_OP_DIVERGENCE: return vjp_ws_bytes(N, precision);
+        case RPYW_OP_RIGID:
+            if (max_iter < 1 || n_bodies < 1) return 0;
+            return rigid_ws_bytes(N, max_iter, n_bodies, precision);
         default: return 0;
     }
 }
@@ -225,6 +228,31 @@ int rpy_wall_lanczos_sqrt(const double* pos, const double* W, double* out, int64
     return rc;
 }
 
+int rpy_wall_rigid_solve(const double* pos, const double* q, const int64_t* body_offsets, int32_t n_bodies,
+                         const double* slip, const double* force_torque, double* lambda, double* U, int64_t N,
+                         double a, double eta, double tol, int32_t max_iter, int precision, void* ws,
+                         size_t ws_bytes, int32_t* iters_out, double* res_out, void* stream) {
+    if (!pos || !q || !body_offsets || !lambda || !U || N < 1 || N >= kMaxN || n_bodies < 1 || !finite_pos(a) ||
+        !finite_pos(eta) || !valid_prec(precision) || !finite_pos(tol) || max_iter < 1 || max_iter > 100000)
+        return RPYW_EINVAL;
+    if (body_offsets[0] != 0 || body_offsets[n_bodies] != N) return RPYW_EINVAL;
+    for (int p = 0; p < n_bodies; ++p) {
+        const int64_t n = body_offsets[p + 1] - body_offsets[p];
+        if (n < 1 || n > kMaxBodyBlobs) return RPYW_EINVAL;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    Scratch s;
+    int rc = acquire(ws, ws_bytes, rigid_ws_bytes(N, max_iter, n_bodies, precision), st, s);
+    if (rc != RPYW_OK) return rc;
+    int it = 0;
+    double res = 0.0;
+    rc = rigid_solve(pos, q, body_offsets, n_bodies, slip, force_torque, lambda, U, N, a, eta, tol, max_iter,
+                     precision, s.ar, &it, &res, st);
+    if (iters_out) *iters_out = it;
+    if (res_out) *res_out = res;
+    return rc;
+}
+
 int rpy_wall_matvec_vjp(const double* pos, const double* force, const double* grad_vel, double* grad_pos,
                         double* grad_force, int64_t N, double a, double eta, int precision, void* ws,
                         size_t ws_bytes, void* stream) {
@@ -264,38 +292,52 @@ int rpy_wall_autotune(const double* pos, const double* F, double* U, int64_t N, 
     RPYW_HIP(hipEventCreate(&e1));
     const bool prof = g_prof;
     g_prof = false;
-    Shape best = default_shape(N, k, precision);
-    double best_t = 1e300;
+    // Candidates in order of preference (least partial-sum traffic first):
+    // symmetric with ipw 4, 2, 1, then plain (tpl, tile) in {1,2} x {64,256},
+    // for every RHS block width.  Two timed rounds over all candidates (the
+    // first also brings the clocks up); each candidate keeps its faster
+    // round.  A later candidate must be faster by 1.5% to win, so near-ties
+    // resolve the same way every time.
+    std::vector<Shape> cands;
     for (int kb = 1; kb <= std::min(kc, 16); kb <<= 1) {
         if (precision == RPYW_FP64 && kb > 8) continue;
         for (int cand = 0; cand < 7; ++cand) {
-                // plain: (tpl, tile) in {1,2} x {64,256}; symmetric: ipw in {1, 2, 4}
-                Shape sh{1 + (cand & 1), (cand & 2) ? 256 : 64, kb, 0, 4};
-                if (cand >= 4) sh = Shape{1, 256, kb, 1, 1 << (cand - 4)};
-                if (cand < 4 && kb >= 8 && sh.tpl == 2) continue;
-                if (cand >= 4 && kb > 4) continue;
-                float ms = 0.f;
-                for (int rep = 0; rep < 3; ++rep) {
-                    if (rep == 1) RPYW_HIP(hipEventRecord(e0, st));
-                    for (int k0 = 0; k0 < k; k0 += kb) {
-                        const int n = std::min(kb, k - k0);
-                        rc = product_pass(pos, F + (size_t)k0 * N * 3, U + (size_t)k0 * N * 3, N, n, a, eta,
-                                          precision, sh, s.ar, st);
-                        if (rc != RPYW_OK) {
-                            g_prof = prof;
-                            return rc;
-                        }
+            Shape sh{1, 256, kb, 1, 4 >> cand};
+            if (cand >= 3) sh = Shape{1 + ((cand - 3) & 1), ((cand - 3) & 2) ? 256 : 64, kb, 0, 4};
+            if (cand >= 3 && kb >= 8 && sh.tpl == 2) continue;
+            if (cand < 3 && kb > 4) continue;
+            cands.push_back(sh);
+        }
+    }
+    std::vector<double> tbest(cands.size(), 1e300);
+    for (int round = 0; round < 2; ++round) {
+        for (size_t c = 0; c < cands.size(); ++c) {
+            float ms = 0.f;
+            for (int rep = 0; rep < 3; ++rep) {
+                if (rep == 1) RPYW_HIP(hipEventRecord(e0, st));
+                for (int k0 = 0; k0 < k; k0 += cands[c].kblk) {
+                    const int n = std::min(cands[c].kblk, k - k0);
+                    rc = product_pass(pos, F + (size_t)k0 * N * 3, U + (size_t)k0 * N * 3, N, n, a, eta, precision,
+                                      cands[c], s.ar, st);
+                    if (rc != RPYW_OK) {
+                        g_prof = prof;
+                        return rc;
                     }
                 }
-                RPYW_HIP(hipEventRecord(e1, st));
-                RPYW_HIP(hipEventSynchronize(e1));
-                RPYW_HIP(hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best_t) {
-                    best_t = ms;
-                    best = sh;
-                }
             }
+            RPYW_HIP(hipEventRecord(e1, st));
+            RPYW_HIP(hipEventSynchronize(e1));
+            RPYW_HIP(hipEventElapsedTime(&ms, e0, e1));
+            tbest[c] = std::min(tbest[c], (double)ms);
+        }
     }
+    Shape best = default_shape(N, k, precision);
+    double best_t = 1e300;
+    for (size_t c = 0; c < cands.size(); ++c)
+        if (tbest[c] < 0.985 * best_t) {
+            best_t = tbest[c];
+            best = cands[c];
+        }
     g_prof = prof;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -1,0 +1,330 @@
+// Building blocks shared by the Krylov solvers (preconditioned Lanczos for
+// M^{1/2} W and GMRES for the rigid-body saddle-point system,
+// arXiv:1709.02410 Sec. II): the block-diagonal preconditioner factors
+// (Sec. II.B: per body, the dense block M^(pp) of that body alone, other
+// bodies ignored, wall kept, and its Cholesky factor), and FP64 vector
+// kernels (update, dot products with a fixed-order finish, combination).
+// All reductions use a fixed order, so results are bitwise reproducible.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "pair_math.h"
+#include "rpyw_internal.h"
+
+namespace rpyw {
+
+namespace {
+
+constexpr int kBodyThreads = 128;
+
+// Dense M^(pp) of one body (units: physical, includes mu0 and B factors)
+// assembled in LDS, then factorised in place (right-looking Cholesky).
+__global__ __launch_bounds__(kBodyThreads) void precond_build_kernel(const double* __restrict__ pos,
+                                                                     const int* __restrict__ bofs,
+                                                                     const int64_t* __restrict__ lofs, double inv_a,
+                                                                     double mu0, double* __restrict__ Lout,
+                                                                     int* __restrict__ notspd) {
+    __shared__ double A[3 * kMaxBodyBlobs][3 * kMaxBodyBlobs + 1];
+    __shared__ double px[kMaxBodyBlobs], py[kMaxBodyBlobs], pz[kMaxBodyBlobs], pb[kMaxBodyBlobs];
+    __shared__ int bad;
+    const int p = blockIdx.x;
+    const int b0 = bofs[p], nb = bofs[p + 1] - b0, n = 3 * nb;
+    if (threadIdx.x == 0) bad = 0;
+    for (int a = threadIdx.x; a < nb; a += blockDim.x) {
+        const double x = pos[3 * (b0 + a)] * inv_a, y = pos[3 * (b0 + a) + 1] * inv_a,
+                     z = pos[3 * (b0 + a) + 2] * inv_a;
+        px[a] = x;
+        py[a] = y;
+        pz[a] = z < 1.0 ? 1.0 : z;
+        pb[a] = z < 1.0 ? z : 1.0;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < nb * nb; q += blockDim.x) {
+        const int ia = q / nb, ib = q % nb;
+        const double dx = px[ia] - px[ib], dy = py[ia] - py[ib], dz = pz[ia] - pz[ib];
+        const PairCoef<double> c = pair_coef<double>(dx, dy, dz, pz[ia], pz[ib]);
+        const double sc = mu0 * pb[ia] * pb[ib];
+        for (int beta = 0; beta < 3; ++beta) {
+            double u[3] = {0.0, 0.0, 0.0};
+            pair_apply<double>(c, dx, dy, dz, beta == 0 ? 1.0 : 0.0, beta == 1 ? 1.0 : 0.0, beta == 2 ? 1.0 : 0.0,
+                               u[0], u[1], u[2]);
+            for (int al = 0; al < 3; ++al) A[3 * ia + al][3 * ib + beta] = sc * u[al];
+        }
+    }
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        if (threadIdx.x == 0) {
+            const double d = A[k][k];
+            if (!(d > 0.0)) bad = 1;
+            A[k][k] = d > 0.0 ? sqrt(d) : 1.0;
+        }
+        __syncthreads();
+        const double dk = A[k][k];
+        for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) A[i][k] /= dk;
+        __syncthreads();
+        const int m = n - k - 1;
+        for (int q = threadIdx.x; q < m * m; q += blockDim.x) {
+            const int i = k + 1 + q / m, j = k + 1 + q % m;
+            if (j <= i) A[i][j] -= A[i][k] * A[j][k];
+        }
+        __syncthreads();
+    }
+    double* L = Lout + 2 * lofs[p];
+    double* Li = L + (int64_t)n * n;
+    for (int q = threadIdx.x; q < n * n; q += blockDim.x) {
+        const int i = q / n, j = q % n;
+        L[q] = j <= i ? A[i][j] : 0.0;
+    }
+    // Inverse factor L^-1 (lower triangular), one column per thread: forward
+    // substitution of L x = e_col, the column written to global memory.
+    for (int col = threadIdx.x; col < n; col += blockDim.x) {
+        for (int i = 0; i < col; ++i) Li[i * n + col] = 0.0;
+        double xc = 1.0 / A[col][col];
+        Li[col * n + col] = xc;
+        for (int i = col + 1; i < n; ++i) {
+            double s = 0.0;
+            for (int k = col; k < i; ++k) s += A[i][k] * Li[k * n + col];
+            Li[i * n + col] = -s / A[i][i];
+        }
+    }
+    if (threadIdx.x == 0 && bad) atomicOr(notspd, 1);
+}
+
+// mode 0: out = L v;  1: out = L^-1 v;  2: out = L^-T v, with the factor L
+// and its inverse Li stored per body (both lower triangular, n x n).  One
+// workgroup per body, one output entry per thread (dense triangular
+// mat-vec).  With `scale`, the input is v / scale[0] and, with `store`, that
+// scaled input is also written there (this forms the next Lanczos vector
+// v_{k+1} = w / beta_k).
+__global__ __launch_bounds__(kBodyThreads) void precond_apply_kernel(const double* __restrict__ Lall,
+                                                                     const int* __restrict__ bofs,
+                                                                     const int64_t* __restrict__ lofs, int mode,
+                                                                     const double* __restrict__ v,
+                                                                     const double* __restrict__ scale,
+                                                                     double* __restrict__ store,
+                                                                     double* __restrict__ out) {
+    __shared__ double x[3 * kMaxBodyBlobs];
+    const int p = blockIdx.x;
+    const int e0 = 3 * bofs[p], n = 3 * bofs[p + 1] - e0;
+    const double* F = Lall + 2 * lofs[p] + (mode == 0 ? 0 : (int64_t)n * n);
+    const double inv = scale ? 1.0 / scale[0] : 1.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double vi = scale ? v[e0 + i] * inv : v[e0 + i];
+        x[i] = vi;
+        if (store) store[e0 + i] = vi;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double s = 0.0;
+        if (mode == 2)
+            for (int j = i; j < n; ++j) s += F[j * n + i] * x[j];  // (L^-1)^T row i
+        else
+            for (int j = 0; j <= i; ++j) s += F[i * n + j] * x[j];
+        out[e0 + i] = s;
+    }
+}
+
+// Per-blob 3x3 blocks (no body structure): the self block is diagonal,
+// B^2 mu0 diag(mu_par, mu_par, mu_perp), so L is its square root.
+__global__ void blob_diag_kernel(const double* __restrict__ pos, int64_t N, double inv_a, double mu0,
+                                 double* __restrict__ ldiag, int* __restrict__ notspd) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double z = pos[3 * i + 2] * inv_a;
+    const double zt = z < 1.0 ? 1.0 : z, B = z < 1.0 ? z : 1.0;
+    const PairCoef<double> c = pair_coef<double>(0.0, 0.0, 0.0, zt, zt);
+    double u[3] = {0, 0, 0}, w[3] = {0, 0, 0};
+    pair_apply<double>(c, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, u[0], u[1], u[2]);
+    pair_apply<double>(c, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0, w[0], w[1], w[2]);
+    const double d[3] = {mu0 * B * B * u[0], mu0 * B * B * u[0], mu0 * B * B * w[2]};
+    for (int c2 = 0; c2 < 3; ++c2) {
+        if (!(d[c2] > 0.0)) atomicOr(notspd, 1);
+        ldiag[3 * i + c2] = d[c2] > 0.0 ? sqrt(d[c2]) : 1.0;
+    }
+}
+
+// mode 0: out = D v; 1, 2: out = v / D (diagonal L); scale/store as above.
+__global__ void diag_apply_kernel(const double* __restrict__ ldiag, int64_t n3, int mode, const double* __restrict__ v,
+                                  const double* __restrict__ scale, double* __restrict__ store,
+                                  double* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n3) return;
+    const double vi = scale ? v[e] * (1.0 / scale[0]) : v[e];
+    if (store) store[e] = vi;
+    out[e] = mode == 0 ? ldiag[e] * vi : vi / ldiag[e];
+}
+
+// w_out = w_in - bscale[0] * vprev - sum_{j < nsub} csub[j] V_j (each term
+// only when given; w_in may be w_out).
+__global__ void update_kernel(const double* win, double* wout, int64_t n3,
+                              const double* __restrict__ vprev, const double* __restrict__ bscale,
+                              const double* __restrict__ V, int64_t ld, const double* __restrict__ csub, int nsub) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n3) return;
+    double x = win[e];
+    if (vprev) x -= bscale[0] * vprev[e];
+    for (int j = 0; j < nsub; ++j) x -= csub[j] * V[j * ld + e];
+    wout[e] = x;
+}
+
+constexpr int kDotChunk = 2048;  // entries per dot-product block (8 per thread)
+
+// Dot products V_j . w (j < nv), or w . w when nv == 0, on a 2-D grid of
+// (chunk, j) blocks; block partials go to partial[j][chunk].  The last block
+// to finish (one atomic ticket, no waiting) adds each j's partials in chunk
+// order (one thread per j) into out[j] (square root for the norm), copies
+// out[copy_idx] to copy_to, and re-arms the ticket.
+__global__ __launch_bounds__(256) void dots_kernel(const double* __restrict__ V, int64_t ld, int nv,
+                                                   const double* __restrict__ w, int64_t n3,
+                                                   double* __restrict__ partial, unsigned* __restrict__ ticket,
+                                                   double* __restrict__ out, int copy_idx,
+                                                   double* __restrict__ copy_to) {
+    __shared__ double red[256];
+    __shared__ bool last;
+    const int j = blockIdx.y, nchunk = gridDim.x;
+    const double* a = nv > 0 ? V + j * ld : w;
+    const int64_t e0 = (int64_t)blockIdx.x * kDotChunk + threadIdx.x;
+    double s = 0.0;
+#pragma unroll
+    for (int r = 0; r < kDotChunk / 256; ++r) {
+        const int64_t e = e0 + r * 256;
+        if (e < n3) s += a[e] * w[e];
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(int64_t)j * nchunk + blockIdx.x] = red[0];
+    __threadfence();
+    if (threadIdx.x == 0) last = atomicAdd(ticket, 1u) == gridDim.x * gridDim.y - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    const int nd = gridDim.y;
+    for (int jj = threadIdx.x; jj < nd; jj += blockDim.x) {
+        const double* p = partial + (int64_t)jj * nchunk;
+        double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+        int c = 0;
+        for (; c + 3 < nchunk; c += 4) {
+            t0 += p[c];
+            t1 += p[c + 1];
+            t2 += p[c + 2];
+            t3 += p[c + 3];
+        }
+        for (; c < nchunk; ++c) t0 += p[c];
+        const double t = (t0 + t1) + (t2 + t3);
+        out[jj] = nv > 0 ? t : sqrt(t);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (copy_to) copy_to[0] = out[copy_idx];
+        *ticket = 0u;
+    }
+}
+
+// out = sum_{j < nv} c[j] V_j
+__global__ void vc_kernel(const double* __restrict__ V, int64_t ld, int nv, const double* __restrict__ c,
+                          double* __restrict__ out, int64_t n3) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n3) return;
+    double s = 0.0;
+    for (int j = 0; j < nv; ++j) s += c[j] * V[j * ld + e];
+    out[e] = s;
+}
+
+
+unsigned grid_of(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+int64_t dot_chunks(int64_t n) { return (n + kDotChunk - 1) / kDotChunk; }
+
+int vec_update(const double* win, double* wout, int64_t n, const double* vprev, const double* bscale,
+               const double* V, int64_t ld, const double* csub, int nsub, hipStream_t st) {
+    hipLaunchKernelGGL(update_kernel, dim3(grid_of(n)), dim3(256), 0, st, win, wout, n, vprev, bscale, V, ld, csub,
+                       nsub);
+    RPYW_HIP(hipGetLastError());
+    return RPYW_OK;
+}
+
+int vec_dots(const double* V, int64_t ld, int nv, const double* w, int64_t n, double* partial, unsigned* ticket,
+             double* out, int copy_idx, double* copy_to, hipStream_t st) {
+    hipLaunchKernelGGL(dots_kernel, dim3((unsigned)dot_chunks(n), (unsigned)(nv > 0 ? nv : 1)), dim3(256), 0, st, V,
+                       ld, nv, w, n, partial, ticket, out, copy_idx, copy_to);
+    RPYW_HIP(hipGetLastError());
+    return RPYW_OK;
+}
+
+int vec_comb(const double* V, int64_t ld, int nv, const double* c, double* out, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(vc_kernel, dim3(grid_of(n)), dim3(256), 0, st, V, ld, nv, c, out, n);
+    RPYW_HIP(hipGetLastError());
+    return RPYW_OK;
+}
+
+int BodyFactors::apply(int mode, const double* v, double* out, int64_t n3, hipStream_t st, const double* scale,
+                       double* store) const {
+    if (diag)
+        hipLaunchKernelGGL(diag_apply_kernel, dim3(grid_of(n3)), dim3(256), 0, st, L, n3, mode, v, scale, store, out);
+    else
+        hipLaunchKernelGGL(precond_apply_kernel, dim3(nb), dim3(kBodyThreads), 0, st, L, bofs, lofs, mode, v, scale,
+                           store, out);
+    RPYW_HIP(hipGetLastError());
+    return RPYW_OK;
+}
+
+size_t body_factors_bytes(int64_t N, int n_bodies) {
+    if (n_bodies == 0) return align_up((size_t)3 * N * sizeof(double));
+    // sum over bodies of 2 (3 n_p)^2 <= 18 N max_p n_p
+    const size_t lsz = (size_t)18 * std::min<int64_t>(N, kMaxBodyBlobs) * N;
+    return align_up((size_t)(n_bodies + 1) * sizeof(int)) + align_up((size_t)(n_bodies + 1) * sizeof(int64_t)) +
+           align_up(lsz * sizeof(double));
+}
+
+int body_factors_build(const double* pos, int64_t N, double a, double eta, const int64_t* body_offsets, int n_bodies,
+                       Arena& ar, hipStream_t st, BodyFactors& pc, int* notspd) {
+    const double inv_a = 1.0 / a, m0 = 1.0 / (6.0 * M_PI * eta * a);
+    pc.diag = n_bodies == 0;
+    pc.nb = n_bodies;
+    if (!pc.diag) {
+        std::vector<int> hb(n_bodies + 1);
+        std::vector<int64_t> hl(n_bodies + 1, 0);
+        for (int p = 0; p <= n_bodies; ++p) hb[p] = (int)body_offsets[p];
+        for (int p = 0; p < n_bodies; ++p) {
+            const int64_t n = 3 * (body_offsets[p + 1] - body_offsets[p]);
+            hl[p + 1] = hl[p] + n * n;
+        }
+        pc.bofs = (int*)ar.take(hb.size() * sizeof(int));
+        pc.lofs = (int64_t*)ar.take(hl.size() * sizeof(int64_t));
+        pc.L = (double*)ar.take((size_t)2 * hl[n_bodies] * sizeof(double));  // L and L^-1
+        if (!pc.bofs || !pc.lofs || !pc.L) return RPYW_ENOMEM;
+        RPYW_HIP(hipMemcpyAsync(pc.bofs, hb.data(), hb.size() * sizeof(int), hipMemcpyHostToDevice, st));
+        RPYW_HIP(hipMemcpyAsync(pc.lofs, hl.data(), hl.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        RPYW_HIP(hipStreamSynchronize(st));  // host vectors go out of scope
+        hipLaunchKernelGGL(precond_build_kernel, dim3(n_bodies), dim3(kBodyThreads), 0, st, pos, pc.bofs, pc.lofs,
+                           inv_a, m0, pc.L, notspd);
+    } else {
+        pc.L = (double*)ar.take((size_t)3 * N * sizeof(double));
+        if (!pc.L) return RPYW_ENOMEM;
+        hipLaunchKernelGGL(blob_diag_kernel, dim3(grid_of(N)), dim3(256), 0, st, pos, N, inv_a, m0, pc.L, notspd);
+    }
+    RPYW_HIP(hipGetLastError());
+    return RPYW_OK;
+}
+
+int PinnedSlots::reserve(size_t bytes) {
+    if (cap < bytes) {
+        if (p) RPYW_HIP(hipHostFree(p));
+        p = nullptr;
+        cap = 0;
+        RPYW_HIP(hipHostMalloc((void**)&p, bytes, hipHostMallocDefault));
+        cap = bytes;
+    }
+    for (auto& e : ev)
+        if (!e) RPYW_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return RPYW_OK;
+}
+
+}  // namespace rpyw

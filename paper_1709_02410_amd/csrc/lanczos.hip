@@ -21,264 +21,15 @@
 #include <mutex>
 #include <vector>
 
-#include "pair_math.h"
 #include "rpyw_internal.h"
 
 namespace rpyw {
 
 namespace {
 
-constexpr int kBodyThreads = 128;
-
-// Dense M^(pp) of one body (units: physical, includes mu0 and B factors)
-// assembled in LDS, then factorised in place (right-looking Cholesky).
-__global__ __launch_bounds__(kBodyThreads) void precond_build_kernel(const double* __restrict__ pos,
-                                                                     const int* __restrict__ bofs,
-                                                                     const int64_t* __restrict__ lofs, double inv_a,
-                                                                     double mu0, double* __restrict__ Lout,
-                                                                     int* __restrict__ notspd) {
-    __shared__ double A[3 * kMaxBodyBlobs][3 * kMaxBodyBlobs + 1];
-    __shared__ double px[kMaxBodyBlobs], py[kMaxBodyBlobs], pz[kMaxBodyBlobs], pb[kMaxBodyBlobs];
-    __shared__ int bad;
-    const int p = blockIdx.x;
-    const int b0 = bofs[p], nb = bofs[p + 1] - b0, n = 3 * nb;
-    if (threadIdx.x == 0) bad = 0;
-    for (int a = threadIdx.x; a < nb; a += blockDim.x) {
-        const double x = pos[3 * (b0 + a)] * inv_a, y = pos[3 * (b0 + a) + 1] * inv_a,
-                     z = pos[3 * (b0 + a) + 2] * inv_a;
-        px[a] = x;
-        py[a] = y;
-        pz[a] = z < 1.0 ? 1.0 : z;
-        pb[a] = z < 1.0 ? z : 1.0;
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < nb * nb; q += blockDim.x) {
-        const int ia = q / nb, ib = q % nb;
-        const double dx = px[ia] - px[ib], dy = py[ia] - py[ib], dz = pz[ia] - pz[ib];
-        const PairCoef<double> c = pair_coef<double>(dx, dy, dz, pz[ia], pz[ib]);
-        const double sc = mu0 * pb[ia] * pb[ib];
-        for (int beta = 0; beta < 3; ++beta) {
-            double u[3] = {0.0, 0.0, 0.0};
-            pair_apply<double>(c, dx, dy, dz, beta == 0 ? 1.0 : 0.0, beta == 1 ? 1.0 : 0.0, beta == 2 ? 1.0 : 0.0,
-                               u[0], u[1], u[2]);
-            for (int al = 0; al < 3; ++al) A[3 * ia + al][3 * ib + beta] = sc * u[al];
-        }
-    }
-    __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        if (threadIdx.x == 0) {
-            const double d = A[k][k];
-            if (!(d > 0.0)) bad = 1;
-            A[k][k] = d > 0.0 ? sqrt(d) : 1.0;
-        }
-        __syncthreads();
-        const double dk = A[k][k];
-        for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) A[i][k] /= dk;
-        __syncthreads();
-        const int m = n - k - 1;
-        for (int q = threadIdx.x; q < m * m; q += blockDim.x) {
-            const int i = k + 1 + q / m, j = k + 1 + q % m;
-            if (j <= i) A[i][j] -= A[i][k] * A[j][k];
-        }
-        __syncthreads();
-    }
-    double* L = Lout + 2 * lofs[p];
-    double* Li = L + (int64_t)n * n;
-    for (int q = threadIdx.x; q < n * n; q += blockDim.x) {
-        const int i = q / n, j = q % n;
-        L[q] = j <= i ? A[i][j] : 0.0;
-    }
-    // Inverse factor L^-1 (lower triangular), one column per thread: forward
-    // substitution of L x = e_col, the column written to global memory.
-    for (int col = threadIdx.x; col < n; col += blockDim.x) {
-        for (int i = 0; i < col; ++i) Li[i * n + col] = 0.0;
-        double xc = 1.0 / A[col][col];
-        Li[col * n + col] = xc;
-        for (int i = col + 1; i < n; ++i) {
-            double s = 0.0;
-            for (int k = col; k < i; ++k) s += A[i][k] * Li[k * n + col];
-            Li[i * n + col] = -s / A[i][i];
-        }
-    }
-    if (threadIdx.x == 0 && bad) atomicOr(notspd, 1);
-}
-
-// mode 0: out = L v;  1: out = L^-1 v;  2: out = L^-T v, with the factor L
-// and its inverse Li stored per body (both lower triangular, n x n).  One
-// workgroup per body, one output entry per thread (dense triangular
-// mat-vec).  With `scale`, the input is v / scale[0] and, with `store`, that
-// scaled input is also written there (this forms the next Lanczos vector
-// v_{k+1} = w / beta_k).
-__global__ __launch_bounds__(kBodyThreads) void precond_apply_kernel(const double* __restrict__ Lall,
-                                                                     const int* __restrict__ bofs,
-                                                                     const int64_t* __restrict__ lofs, int mode,
-                                                                     const double* __restrict__ v,
-                                                                     const double* __restrict__ scale,
-                                                                     double* __restrict__ store,
-                                                                     double* __restrict__ out) {
-    __shared__ double x[3 * kMaxBodyBlobs];
-    const int p = blockIdx.x;
-    const int e0 = 3 * bofs[p], n = 3 * bofs[p + 1] - e0;
-    const double* F = Lall + 2 * lofs[p] + (mode == 0 ? 0 : (int64_t)n * n);
-    const double inv = scale ? 1.0 / scale[0] : 1.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const double vi = scale ? v[e0 + i] * inv : v[e0 + i];
-        x[i] = vi;
-        if (store) store[e0 + i] = vi;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        double s = 0.0;
-        if (mode == 2)
-            for (int j = i; j < n; ++j) s += F[j * n + i] * x[j];  // (L^-1)^T row i
-        else
-            for (int j = 0; j <= i; ++j) s += F[i * n + j] * x[j];
-        out[e0 + i] = s;
-    }
-}
-
-// Per-blob 3x3 blocks (no body structure): the self block is diagonal,
-// B^2 mu0 diag(mu_par, mu_par, mu_perp), so L is its square root.
-__global__ void blob_diag_kernel(const double* __restrict__ pos, int64_t N, double inv_a, double mu0,
-                                 double* __restrict__ ldiag, int* __restrict__ notspd) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const double z = pos[3 * i + 2] * inv_a;
-    const double zt = z < 1.0 ? 1.0 : z, B = z < 1.0 ? z : 1.0;
-    const PairCoef<double> c = pair_coef<double>(0.0, 0.0, 0.0, zt, zt);
-    double u[3] = {0, 0, 0}, w[3] = {0, 0, 0};
-    pair_apply<double>(c, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, u[0], u[1], u[2]);
-    pair_apply<double>(c, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0, w[0], w[1], w[2]);
-    const double d[3] = {mu0 * B * B * u[0], mu0 * B * B * u[0], mu0 * B * B * w[2]};
-    for (int c2 = 0; c2 < 3; ++c2) {
-        if (!(d[c2] > 0.0)) atomicOr(notspd, 1);
-        ldiag[3 * i + c2] = d[c2] > 0.0 ? sqrt(d[c2]) : 1.0;
-    }
-}
-
-// mode 0: out = D v; 1, 2: out = v / D (diagonal L); scale/store as above.
-__global__ void diag_apply_kernel(const double* __restrict__ ldiag, int64_t n3, int mode, const double* __restrict__ v,
-                                  const double* __restrict__ scale, double* __restrict__ store,
-                                  double* __restrict__ out) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n3) return;
-    const double vi = scale ? v[e] * (1.0 / scale[0]) : v[e];
-    if (store) store[e] = vi;
-    out[e] = mode == 0 ? ldiag[e] * vi : vi / ldiag[e];
-}
-
-// w_out = w_in - bscale[0] * vprev - sum_{j < nsub} csub[j] V_j (each term
-// only when given).
-__global__ void update_kernel(const double* __restrict__ win, double* __restrict__ wout, int64_t n3,
-                              const double* __restrict__ vprev, const double* __restrict__ bscale,
-                              const double* __restrict__ V, int64_t ld, const double* __restrict__ csub, int nsub) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n3) return;
-    double x = win[e];
-    if (vprev) x -= bscale[0] * vprev[e];
-    for (int j = 0; j < nsub; ++j) x -= csub[j] * V[j * ld + e];
-    wout[e] = x;
-}
-
-constexpr int kDotChunk = 2048;  // entries per dot-product block (8 per thread)
-
-// Dot products V_j . w (j < nv), or w . w when nv == 0, on a 2-D grid of
-// (chunk, j) blocks; block partials go to partial[j][chunk].  The last block
-// to finish (one atomic ticket, no waiting) adds each j's partials in chunk
-// order (one thread per j) into out[j] (square root for the norm), copies
-// out[copy_idx] to copy_to, and re-arms the ticket.
-__global__ __launch_bounds__(256) void dots_kernel(const double* __restrict__ V, int64_t ld, int nv,
-                                                   const double* __restrict__ w, int64_t n3,
-                                                   double* __restrict__ partial, unsigned* __restrict__ ticket,
-                                                   double* __restrict__ out, int copy_idx,
-                                                   double* __restrict__ copy_to) {
-    __shared__ double red[256];
-    __shared__ bool last;
-    const int j = blockIdx.y, nchunk = gridDim.x;
-    const double* a = nv > 0 ? V + j * ld : w;
-    const int64_t e0 = (int64_t)blockIdx.x * kDotChunk + threadIdx.x;
-    double s = 0.0;
-#pragma unroll
-    for (int r = 0; r < kDotChunk / 256; ++r) {
-        const int64_t e = e0 + r * 256;
-        if (e < n3) s += a[e] * w[e];
-    }
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[(int64_t)j * nchunk + blockIdx.x] = red[0];
-    __threadfence();
-    if (threadIdx.x == 0) last = atomicAdd(ticket, 1u) == gridDim.x * gridDim.y - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    const int nd = gridDim.y;
-    for (int jj = threadIdx.x; jj < nd; jj += blockDim.x) {
-        const double* p = partial + (int64_t)jj * nchunk;
-        double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
-        int c = 0;
-        for (; c + 3 < nchunk; c += 4) {
-            t0 += p[c];
-            t1 += p[c + 1];
-            t2 += p[c + 2];
-            t3 += p[c + 3];
-        }
-        for (; c < nchunk; ++c) t0 += p[c];
-        const double t = (t0 + t1) + (t2 + t3);
-        out[jj] = nv > 0 ? t : sqrt(t);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        if (copy_to) copy_to[0] = out[copy_idx];
-        *ticket = 0u;
-    }
-}
-
-// out = sum_{j < nv} c[j] V_j
-__global__ void vc_kernel(const double* __restrict__ V, int64_t ld, int nv, const double* __restrict__ c,
-                          double* __restrict__ out, int64_t n3) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n3) return;
-    double s = 0.0;
-    for (int j = 0; j < nv; ++j) s += c[j] * V[j * ld + e];
-    out[e] = s;
-}
-
-unsigned grid_of(int64_t n) { return (unsigned)((n + 255) / 256); }
-int64_t dot_chunks(int64_t n3) { return (n3 + kDotChunk - 1) / kDotChunk; }
-
-// Pinned host slots for the per-iteration (alpha_k, beta_k) copies, so the
-// copies are truly asynchronous; one Lanczos call uses them at a time.
-struct PinnedAB {
-    std::mutex mu;
-    double* p = nullptr;
-    size_t cap = 0;
-    hipEvent_t ev[2] = {nullptr, nullptr};
-};
-PinnedAB g_ab;
-
-struct Precond {
-    bool diag = true;
-    int nb = 0;
-    int* bofs = nullptr;
-    int64_t* lofs = nullptr;
-    double* L = nullptr;  // factors (bodies) or diagonal [3N]
-
-    int apply(int mode, const double* v, double* out, int64_t n3, hipStream_t st, const double* scale = nullptr,
-              double* store = nullptr) const {
-        if (diag)
-            hipLaunchKernelGGL(diag_apply_kernel, dim3(grid_of(n3)), dim3(256), 0, st, L, n3, mode, v, scale, store,
-                               out);
-        else
-            hipLaunchKernelGGL(precond_apply_kernel, dim3(nb), dim3(kBodyThreads), 0, st, L, bofs, lofs, mode, v,
-                               scale, store, out);
-        RPYW_HIP(hipGetLastError());
-        return RPYW_OK;
-    }
-};
+// Pinned host slots for the per-iteration (alpha_k, beta_k) copies; one
+// Lanczos call uses them at a time.
+PinnedSlots g_ab;
 
 }  // namespace
 
@@ -376,16 +127,12 @@ int tridiag_sqrt_coeffs(const double* alpha, const double* beta, int k, double b
 
 size_t lanczos_ws_bytes(int64_t N, int max_iter, int n_bodies, int prec) {
     const size_t n3 = (size_t)3 * N;
-    size_t b = 0;
-    b += align_up((size_t)(n_bodies + 1) * sizeof(int));
-    b += align_up((size_t)(n_bodies + 1) * sizeof(int64_t));
-    const size_t lsz = n_bodies > 0 ? (size_t)18 * std::min<int64_t>(N, kMaxBodyBlobs) * N : n3;
-    b += align_up(lsz * sizeof(double));
+    size_t b = body_factors_bytes(N, n_bodies);
     b += align_up((size_t)(max_iter + 1) * n3 * sizeof(double));  // V
     b += 3 * align_up(n3 * sizeof(double));                        // x, y, w
     b += align_up((size_t)(max_iter + 2) * dot_chunks(n3) * sizeof(double));
     b += 4 * align_up((size_t)2 * (max_iter + 8) * sizeof(double));  // alpha/beta, c1, c2, b0
-    b += align_up(sizeof(int));
+    b += align_up(sizeof(unsigned)) + align_up(sizeof(int));        // ticket, notspd
     b += product_ws_bytes(N, prec, 1);
     return b + 16 * kAlign;
 }
@@ -394,32 +141,9 @@ int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, dou
                  const int64_t* body_offsets, int n_bodies, double tol, int max_iter, int prec, Arena& ar, int* iters,
                  double* err, hipStream_t st) {
     const int64_t n3 = 3 * N;
-    const double inv_a = 1.0 / a, m0 = 1.0 / (6.0 * M_PI * eta * a);
     *iters = 0;
     *err = 0.0;
-    Precond pc;
-    pc.diag = n_bodies == 0;
-    pc.nb = n_bodies;
-    int* notspd = nullptr;
-    if (!pc.diag) {
-        std::vector<int> hb(n_bodies + 1);
-        std::vector<int64_t> hl(n_bodies + 1, 0);
-        for (int p = 0; p <= n_bodies; ++p) hb[p] = (int)body_offsets[p];
-        for (int p = 0; p < n_bodies; ++p) {
-            const int64_t n = 3 * (body_offsets[p + 1] - body_offsets[p]);
-            hl[p + 1] = hl[p] + n * n;
-        }
-        pc.bofs = (int*)ar.take(hb.size() * sizeof(int));
-        pc.lofs = (int64_t*)ar.take(hl.size() * sizeof(int64_t));
-        pc.L = (double*)ar.take((size_t)2 * hl[n_bodies] * sizeof(double));  // L and L^-1
-        if (!pc.bofs || !pc.lofs || !pc.L) return RPYW_ENOMEM;
-        RPYW_HIP(hipMemcpyAsync(pc.bofs, hb.data(), hb.size() * sizeof(int), hipMemcpyHostToDevice, st));
-        RPYW_HIP(hipMemcpyAsync(pc.lofs, hl.data(), hl.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
-        RPYW_HIP(hipStreamSynchronize(st));  // host vectors go out of scope
-    } else {
-        pc.L = (double*)ar.take((size_t)n3 * sizeof(double));
-        if (!pc.L) return RPYW_ENOMEM;
-    }
+    BodyFactors pc;
     double* V = (double*)ar.take((size_t)(max_iter + 1) * n3 * sizeof(double));
     double* x = (double*)ar.take(n3 * sizeof(double));
     double* y = (double*)ar.take(n3 * sizeof(double));
@@ -431,48 +155,28 @@ int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, dou
     double* d_c2 = (double*)ar.take(2 * (max_iter + 8) * sizeof(double));
     double* d_b0 = (double*)ar.take(8 * sizeof(double));
     unsigned* ticket = (unsigned*)ar.take(kAlign);
-    notspd = (int*)ar.take(sizeof(int));
+    int* notspd = (int*)ar.take(sizeof(int));
     if (!V || !x || !y || !w || !partial || !d_ab || !d_c1 || !d_c2 || !d_b0 || !ticket || !notspd)
         return RPYW_ENOMEM;
     std::lock_guard<std::mutex> lk(g_ab.mu);
-    const size_t need = (size_t)2 * (max_iter + 2) * sizeof(double);
-    if (g_ab.cap < need) {
-        if (g_ab.p) RPYW_HIP(hipHostFree(g_ab.p));
-        g_ab.p = nullptr;
-        g_ab.cap = 0;
-        RPYW_HIP(hipHostMalloc((void**)&g_ab.p, need, hipHostMallocDefault));
-        g_ab.cap = need;
-    }
-    for (auto& e : g_ab.ev)
-        if (!e) RPYW_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    int rc = g_ab.reserve((size_t)2 * (max_iter + 2) * sizeof(double));
+    if (rc) return rc;
     double* h_ab = g_ab.p;
 
     RPYW_HIP(hipMemsetAsync(notspd, 0, sizeof(int), st));
     RPYW_HIP(hipMemsetAsync(ticket, 0, sizeof(unsigned), st));
-    if (pc.diag)
-        hipLaunchKernelGGL(blob_diag_kernel, dim3(grid_of(N)), dim3(256), 0, st, pos, N, inv_a, m0, pc.L, notspd);
-    else
-        hipLaunchKernelGGL(precond_build_kernel, dim3(n_bodies), dim3(kBodyThreads), 0, st, pos, pc.bofs, pc.lofs,
-                           inv_a, m0, pc.L, notspd);
-    RPYW_HIP(hipGetLastError());
+    if ((rc = body_factors_build(pos, N, a, eta, body_offsets, n_bodies, ar, st, pc, notspd))) return rc;
 
-    const unsigned gv = grid_of(n3);
-    auto update = [&](const double* vprev, const double* bscale, const double* csub, int nsub) -> int {
-        hipLaunchKernelGGL(update_kernel, dim3(gv), dim3(256), 0, st, w, w, n3, vprev, bscale, V, n3, csub, nsub);
-        RPYW_HIP(hipGetLastError());
-        return RPYW_OK;
+    auto update = [&](const double* vprev, const double* bscale, const double* csub, int nsub) {
+        return vec_update(w, w, n3, vprev, bscale, V, n3, csub, nsub, st);
     };
     // dot products with V_0..V_{nv-1} (nv > 0) or the norm (nv = 0) of vec
-    auto dots = [&](const double* vec, int nv, double* res, int copy_idx, double* copy_to) -> int {
-        hipLaunchKernelGGL(dots_kernel, dim3((unsigned)nchunk, (unsigned)(nv > 0 ? nv : 1)), dim3(256), 0, st, V, n3,
-                           nv, vec, n3, partial, ticket, res, copy_idx, copy_to);
-        RPYW_HIP(hipGetLastError());
-        return RPYW_OK;
+    auto dots = [&](const double* vec, int nv, double* res, int copy_idx, double* copy_to) {
+        return vec_dots(V, n3, nv, vec, n3, partial, ticket, res, copy_idx, copy_to, st);
     };
 
     // beta0 = |W|
-    int rc = dots(W, 0, d_b0, 0, nullptr);
-    if (rc) return rc;
+    if ((rc = dots(W, 0, d_b0, 0, nullptr))) return rc;
     double beta0 = 0.0;
     int bad = 0;
     RPYW_HIP(hipMemcpyAsync(&beta0, d_b0, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -547,8 +251,7 @@ int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, dou
     *iters = converged ? k + 1 : max_iter;
     *err = std::isfinite(rel) ? rel : 0.0;
     RPYW_HIP(hipMemcpyAsync(d_c1, c.data(), used * sizeof(double), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(vc_kernel, dim3(gv), dim3(256), 0, st, V, n3, used, d_c1, y, n3);  // y = V c
-    RPYW_HIP(hipGetLastError());
+    if ((rc = vec_comb(V, n3, used, d_c1, y, n3, st))) return rc;  // y = V c
     if ((rc = pc.apply(0, y, out, n3, st))) return rc;  // out = L y
     RPYW_HIP(hipStreamSynchronize(st));                // c leaves scope
     return converged ? RPYW_OK : RPYW_NOT_CONVERGED;

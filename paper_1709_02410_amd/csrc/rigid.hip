@@ -1,0 +1,406 @@
+// Rigid multiblob mobility problem (arXiv:1709.02410, Sec. II.A): the
+// saddle-point system
+//
+//     [ M   -K ] [lambda]   [-slip]
+//     [-K^T  0 ] [  U   ] = [ -F  ]
+//
+// for blob forces lambda [N][3] and body velocities U = (u_p, omega_p), with
+// (K U)_i = u_p + omega_p x (r_i - q_p) for blob i of body p, solved by
+// GMRES right-preconditioned with the block-diagonal operator of Sec. II.B:
+// interactions between distinct bodies dropped, each body's own block
+// M^(pp) kept (wall included), so the preconditioner is the exact inverse
+// of one small saddle-point system per body:
+//
+//     z_U      = -N_p (r_U + W_p^T r_lambda),   W_p = M_pp^-1 K_p,
+//     z_lambda = M_pp^-1 r_lambda + W_p z_U,    N_p = (K_p^T W_p)^-1,
+//
+// with M_pp^-1 = L_p^-T L_p^-1 from the factors the Lanczos solver uses.
+// Krylov vectors are [lambda (3N) | U (6 n_bodies)] in FP64; every Arnoldi
+// step costs one product by M plus O(N) work.  Classical Gram-Schmidt is
+// applied twice; the Hessenberg column goes to pinned host memory, where
+// Givens rotations give the residual.  Step k + 1 only needs the norm
+// h_{k+1,k} on the device, so it is queued before the host has examined
+// step k (and is discarded if step k converged).
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "rpyw_internal.h"
+
+namespace rpyw {
+
+namespace {
+
+constexpr int kRT = 128;  // threads per body (bodies have at most 42 blobs)
+constexpr int kMaxN3 = 3 * kMaxBodyBlobs;
+
+// Entry (alpha, col) of the 3 x 6 block of K for a blob at d = r_i - q_p:
+// the identity for col < 3 and, for col = 3 + beta, (e_beta x d)_alpha.
+__device__ inline double k_entry(int alpha, int col, const double d[3]) {
+    if (col < 3) return alpha == col ? 1.0 : 0.0;
+    const int beta = col - 3;
+    if (alpha == beta) return 0.0;
+    const int g = 3 - alpha - beta;                                      // the remaining index
+    const double sgn = ((beta - alpha + 3) % 3 == 1) ? 1.0 : -1.0;       // Levi-Civita eps(alpha, beta, g)
+    return sgn * d[g];
+}
+
+// Per body: W_p = M_pp^-1 K_p ([3n][6], at 18 bofs[p]) and the 6 x 6 body
+// mobility N_p = (K_p^T W_p)^-1 (at 36 p).  Sets *notspd when K_p^T W_p is
+// not numerically positive definite (a body whose blobs do not fix all six
+// rigid motions, e.g. a single blob or a straight rod).
+__global__ __launch_bounds__(kRT) void rigid_factors_kernel(const double* __restrict__ pos,
+                                                           const double* __restrict__ q,
+                                                           const int* __restrict__ bofs,
+                                                           const int64_t* __restrict__ lofs,
+                                                           const double* __restrict__ Lall, double* __restrict__ Wall,
+                                                           double* __restrict__ Nall, int* __restrict__ notspd) {
+    __shared__ double Kl[kMaxN3][6], X[kMaxN3][6], Wl[kMaxN3][6];
+    __shared__ double G[6][6], A[6][6], Linv[6][6];
+    const int p = blockIdx.x;
+    const int b0 = bofs[p], n = 3 * (bofs[p + 1] - b0);
+    const double* Li = Lall + 2 * lofs[p] + (int64_t)n * n;
+    for (int idx = threadIdx.x; idx < 6 * n; idx += blockDim.x) {
+        const int i = idx / 6, c = idx % 6;
+        const int blob = b0 + i / 3;
+        const double d[3] = {pos[3 * blob] - q[3 * p], pos[3 * blob + 1] - q[3 * p + 1],
+                             pos[3 * blob + 2] - q[3 * p + 2]};
+        Kl[i][c] = k_entry(i % 3, c, d);
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 6 * n; idx += blockDim.x) {  // X = L^-1 K
+        const int i = idx / 6, c = idx % 6;
+        double s = 0.0;
+        for (int j = 0; j <= i; ++j) s += Li[(int64_t)i * n + j] * Kl[j][c];
+        X[i][c] = s;
+    }
+    __syncthreads();
+    double* Wp = Wall + 18 * (int64_t)b0;
+    for (int idx = threadIdx.x; idx < 6 * n; idx += blockDim.x) {  // W = L^-T X
+        const int i = idx / 6, c = idx % 6;
+        double s = 0.0;
+        for (int j = i; j < n; ++j) s += Li[(int64_t)j * n + i] * X[j][c];
+        Wl[i][c] = s;
+        Wp[idx] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 36) {  // G = K^T W
+        const int c = threadIdx.x / 6, e = threadIdx.x % 6;
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += Kl[i][c] * Wl[i][e];
+        G[c][e] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // Cholesky of the symmetrised G, then N = L^-T L^-1 (one thread).
+        double dmax = 0.0;
+        for (int i = 0; i < 6; ++i) {
+            for (int j = 0; j < 6; ++j) A[i][j] = 0.5 * (G[i][j] + G[j][i]);
+            dmax = fmax(dmax, fabs(A[i][i]));
+        }
+        bool bad = !(dmax > 0.0);
+        for (int k = 0; k < 6 && !bad; ++k) {
+            double dk = A[k][k];
+            for (int m = 0; m < k; ++m) dk -= A[k][m] * A[k][m];
+            if (!(dk > 1e-12 * dmax)) {
+                bad = true;
+                break;
+            }
+            dk = sqrt(dk);
+            A[k][k] = dk;
+            for (int i = k + 1; i < 6; ++i) {
+                double s = A[i][k];
+                for (int m = 0; m < k; ++m) s -= A[i][m] * A[k][m];
+                A[i][k] = s / dk;
+            }
+        }
+        double* Np = Nall + 36 * (int64_t)p;
+        if (bad) {
+            atomicOr(notspd, 1);
+            for (int i = 0; i < 36; ++i) Np[i] = 0.0;
+        } else {
+            for (int c = 0; c < 6; ++c)  // columns of L^-1 by forward substitution
+                for (int i = 0; i < 6; ++i) {
+                    double s = (i == c) ? 1.0 : 0.0;
+                    for (int m = 0; m < i; ++m) s -= A[i][m] * Linv[m][c];
+                    Linv[i][c] = s / A[i][i];
+                }
+            for (int i = 0; i < 6; ++i)
+                for (int j = 0; j < 6; ++j) {
+                    double s = 0.0;
+                    for (int m = 0; m < 6; ++m) s += Linv[m][i] * Linv[m][j];
+                    Np[6 * i + j] = s;
+                }
+        }
+    }
+}
+
+// z = P^-1 r for r = [rl (3N) | ru (6 nb)] (see the file comment).  With
+// scale the input is r / scale[0] and, with store (pointing at a full
+// vector), that scaled input is also written there.
+__global__ __launch_bounds__(kRT) void rigid_precond_kernel(const double* __restrict__ Lall,
+                                                           const int* __restrict__ bofs,
+                                                           const int64_t* __restrict__ lofs,
+                                                           const double* __restrict__ Wall,
+                                                           const double* __restrict__ Nall, int64_t n3,
+                                                           const double* __restrict__ rl,
+                                                           const double* __restrict__ ru,
+                                                           const double* __restrict__ scale,
+                                                           double* __restrict__ store, double* __restrict__ zl,
+                                                           double* __restrict__ zu) {
+    __shared__ double r[kMaxN3], t1[kMaxN3], t[kMaxN3];
+    __shared__ double r6[6], s6[6], z6[6];
+    const int p = blockIdx.x;
+    const int b0 = bofs[p], n = 3 * (bofs[p + 1] - b0);
+    const int64_t e0 = 3 * (int64_t)b0;
+    const double* Li = Lall + 2 * lofs[p] + (int64_t)n * n;
+    const double* W = Wall + 18 * (int64_t)b0;
+    const double inv = scale ? 1.0 / scale[0] : 1.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double v = scale ? rl[e0 + i] * inv : rl[e0 + i];
+        r[i] = v;
+        if (store) store[e0 + i] = v;
+    }
+    if (threadIdx.x < 6) {
+        const double v = scale ? ru[6 * p + threadIdx.x] * inv : ru[6 * p + threadIdx.x];
+        r6[threadIdx.x] = v;
+        if (store) store[n3 + 6 * p + threadIdx.x] = v;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {  // t1 = L^-1 r
+        double s = 0.0;
+        for (int j = 0; j <= i; ++j) s += Li[(int64_t)i * n + j] * r[j];
+        t1[i] = s;
+    }
+    if (threadIdx.x < 6) {  // s = W^T r = K^T M^-1 r
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += W[6 * i + threadIdx.x] * r[i];
+        s6[threadIdx.x] = s;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {  // t = L^-T t1 = M^-1 r
+        double s = 0.0;
+        for (int j = i; j < n; ++j) s += Li[(int64_t)j * n + i] * t1[j];
+        t[i] = s;
+    }
+    if (threadIdx.x < 6) {  // z_U = -N (r_U + s)
+        const double* Np = Nall + 36 * (int64_t)p + 6 * threadIdx.x;
+        double s = 0.0;
+        for (int e = 0; e < 6; ++e) s += Np[e] * (r6[e] + s6[e]);
+        z6[threadIdx.x] = -s;
+        zu[6 * p + threadIdx.x] = -s;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {  // z_lambda = t + W z_U
+        double s = t[i];
+        for (int c = 0; c < 6; ++c) s += W[6 * i + c] * z6[c];
+        zl[e0 + i] = s;
+    }
+}
+
+// out = A x with x = [xl | xu]: outl = y - K xu (y = M xl already formed),
+// outu = -K^T xl.  One workgroup per body.
+__global__ __launch_bounds__(kRT) void rigid_apply_kernel(const double* __restrict__ pos,
+                                                         const double* __restrict__ q,
+                                                         const int* __restrict__ bofs,
+                                                         const double* __restrict__ xl,
+                                                         const double* __restrict__ xu,
+                                                         const double* __restrict__ y, double* __restrict__ outl,
+                                                         double* __restrict__ outu) {
+    __shared__ double red[6][kMaxBodyBlobs];
+    const int p = blockIdx.x;
+    const int b0 = bofs[p], nb = bofs[p + 1] - b0;
+    for (int a = threadIdx.x; a < nb; a += blockDim.x) {
+        const int64_t i = b0 + a;
+        const double d[3] = {pos[3 * i] - q[3 * p], pos[3 * i + 1] - q[3 * p + 1], pos[3 * i + 2] - q[3 * p + 2]};
+        const double* U = xu + 6 * (int64_t)p;
+        const double ku[3] = {U[0] + U[4] * d[2] - U[5] * d[1], U[1] + U[5] * d[0] - U[3] * d[2],
+                              U[2] + U[3] * d[1] - U[4] * d[0]};
+        const double l[3] = {xl[3 * i], xl[3 * i + 1], xl[3 * i + 2]};
+        for (int c = 0; c < 3; ++c) outl[3 * i + c] = y[3 * i + c] - ku[c];
+        red[0][a] = l[0];
+        red[1][a] = l[1];
+        red[2][a] = l[2];
+        red[3][a] = d[1] * l[2] - d[2] * l[1];
+        red[4][a] = d[2] * l[0] - d[0] * l[2];
+        red[5][a] = d[0] * l[1] - d[1] * l[0];
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        double s = 0.0;
+        for (int a = 0; a < nb; ++a) s += red[threadIdx.x][a];
+        outu[6 * p + threadIdx.x] = -s;
+    }
+}
+
+// b = [-slip | -F] (absent terms are zero).
+__global__ void rigid_rhs_kernel(const double* __restrict__ slip, const double* __restrict__ FT, int64_t n3,
+                                 int64_t n6, double* __restrict__ b) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n3)
+        b[e] = slip ? -slip[e] : 0.0;
+    else if (e < n3 + n6)
+        b[e] = FT ? -FT[e - n3] : 0.0;
+}
+
+PinnedSlots g_h;  // Hessenberg columns, two alternating slots
+
+}  // namespace
+
+size_t rigid_ws_bytes(int64_t N, int max_iter, int n_bodies, int prec) {
+    const size_t n3 = (size_t)3 * N, n = n3 + (size_t)6 * n_bodies;
+    const size_t m = (size_t)max_iter;
+    size_t b = body_factors_bytes(N, n_bodies);
+    b += align_up((size_t)18 * N * sizeof(double));          // W_p
+    b += align_up((size_t)36 * n_bodies * sizeof(double));   // N_p
+    b += align_up((m + 1) * n * sizeof(double));              // V
+    b += 3 * align_up(n * sizeof(double));                    // z, w, b
+    b += align_up(n3 * sizeof(double));                       // y = M z_lambda
+    b += align_up((m + 2) * dot_chunks(n) * sizeof(double));  // dot partials
+    b += 4 * align_up((m + 8) * sizeof(double));              // c1, c2, norms, coefficients
+    b += align_up(sizeof(unsigned)) + align_up(sizeof(int));  // ticket, notspd
+    b += product_ws_bytes(N, prec, 1);
+    return b + 16 * kAlign;
+}
+
+int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets, int n_bodies, const double* slip,
+                const double* FT, double* lam_out, double* U_out, int64_t N, double a, double eta, double tol,
+                int max_iter, int prec, Arena& ar, int* iters, double* res_out, hipStream_t st) {
+    const int64_t n3 = 3 * N, n6 = 6 * (int64_t)n_bodies, n = n3 + n6;
+    *iters = 0;
+    *res_out = 0.0;
+    BodyFactors pc;
+    double* Wall = (double*)ar.take((size_t)18 * N * sizeof(double));
+    double* Nall = (double*)ar.take((size_t)36 * n_bodies * sizeof(double));
+    double* V = (double*)ar.take((size_t)(max_iter + 1) * n * sizeof(double));
+    double* z = (double*)ar.take(n * sizeof(double));
+    double* w = (double*)ar.take(n * sizeof(double));
+    double* bv = (double*)ar.take(n * sizeof(double));
+    double* y = (double*)ar.take(n3 * sizeof(double));
+    double* partial = (double*)ar.take((size_t)(max_iter + 2) * dot_chunks(n) * sizeof(double));
+    double* d_c1 = (double*)ar.take((max_iter + 8) * sizeof(double));
+    double* d_c2 = (double*)ar.take((max_iter + 8) * sizeof(double));
+    double* d_hn = (double*)ar.take((max_iter + 8) * sizeof(double));  // [0] = |b|, [k + 1] = h_{k+1,k}
+    double* d_y = (double*)ar.take((max_iter + 8) * sizeof(double));
+    unsigned* ticket = (unsigned*)ar.take(kAlign);
+    int* notspd = (int*)ar.take(sizeof(int));
+    if (!Wall || !Nall || !V || !z || !w || !bv || !y || !partial || !d_c1 || !d_c2 || !d_hn || !d_y || !ticket ||
+        !notspd)
+        return RPYW_ENOMEM;
+    std::lock_guard<std::mutex> lk(g_h.mu);
+    const int slot = 2 * (max_iter + 2);  // c1[0..k], c2[0..k], h_{k+1,k}
+    int rc = g_h.reserve((size_t)2 * slot * sizeof(double));
+    if (rc) return rc;
+    double* h_slot = g_h.p;
+
+    RPYW_HIP(hipMemsetAsync(notspd, 0, sizeof(int), st));
+    RPYW_HIP(hipMemsetAsync(ticket, 0, sizeof(unsigned), st));
+    if ((rc = body_factors_build(pos, N, a, eta, body_offsets, n_bodies, ar, st, pc, notspd))) return rc;
+    hipLaunchKernelGGL(rigid_factors_kernel, dim3(n_bodies), dim3(kRT), 0, st, pos, q, pc.bofs, pc.lofs, pc.L, Wall,
+                       Nall, notspd);
+    RPYW_HIP(hipGetLastError());
+    hipLaunchKernelGGL(rigid_rhs_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, slip, FT, n3, n6, bv);
+    RPYW_HIP(hipGetLastError());
+
+    auto precond = [&](const double* in, const double* scale, double* store, double* outl, double* outu) -> int {
+        hipLaunchKernelGGL(rigid_precond_kernel, dim3(n_bodies), dim3(kRT), 0, st, pc.L, pc.bofs, pc.lofs, Wall, Nall,
+                           n3, in, in + n3, scale, store, outl, outu);
+        RPYW_HIP(hipGetLastError());
+        return RPYW_OK;
+    };
+    auto dots = [&](const double* vec, int nv, double* res, int copy_idx, double* copy_to) {
+        return vec_dots(V, n, nv, vec, n, partial, ticket, res, copy_idx, copy_to, st);
+    };
+
+    // beta = |b|
+    if ((rc = dots(bv, 0, d_hn, 0, nullptr))) return rc;
+    double beta = 0.0;
+    int bad = 0;
+    RPYW_HIP(hipMemcpyAsync(&beta, d_hn, sizeof(double), hipMemcpyDeviceToHost, st));
+    RPYW_HIP(hipMemcpyAsync(&bad, notspd, sizeof(int), hipMemcpyDeviceToHost, st));
+    RPYW_HIP(hipStreamSynchronize(st));
+    if (bad) return RPYW_ENOTSPD;
+    if (!std::isfinite(beta)) return RPYW_EINVAL;
+    if (beta == 0.0) {
+        RPYW_HIP(hipMemsetAsync(lam_out, 0, n3 * sizeof(double), st));
+        RPYW_HIP(hipMemsetAsync(U_out, 0, n6 * sizeof(double), st));
+        return RPYW_OK;
+    }
+
+    // Arnoldi step k: v_k = (k ? w : b) / d_hn[k], z = P^-1 v_k, w = A z,
+    // two Gram-Schmidt passes, d_hn[k + 1] = |w|; column k of H to the host.
+    auto launch_step = [&](int k) -> int {
+        double* vk = V + (size_t)k * n;
+        int r;
+        if ((r = precond(k == 0 ? bv : w, d_hn + k, vk, z, z + n3))) return r;
+        if ((r = products(pos, z, y, N, 1, a, eta, prec, ar, st))) return r;
+        hipLaunchKernelGGL(rigid_apply_kernel, dim3(n_bodies), dim3(kRT), 0, st, pos, q, pc.bofs, z, z + n3, y, w,
+                           w + n3);
+        RPYW_HIP(hipGetLastError());
+        if ((r = dots(w, k + 1, d_c1, 0, nullptr))) return r;
+        if ((r = vec_update(w, w, n, nullptr, nullptr, V, n, d_c1, k + 1, st))) return r;
+        if ((r = dots(w, k + 1, d_c2, 0, nullptr))) return r;
+        if ((r = vec_update(w, w, n, nullptr, nullptr, V, n, d_c2, k + 1, st))) return r;
+        if ((r = dots(w, 0, d_hn + k + 1, 0, nullptr))) return r;
+        double* hs = h_slot + (size_t)(k & 1) * slot;
+        RPYW_HIP(hipMemcpyAsync(hs, d_c1, (k + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+        RPYW_HIP(hipMemcpyAsync(hs + k + 1, d_c2, (k + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+        RPYW_HIP(hipMemcpyAsync(hs + 2 * (k + 1), d_hn + k + 1, sizeof(double), hipMemcpyDeviceToHost, st));
+        RPYW_HIP(hipEventRecord(g_h.ev[k & 1], st));
+        return RPYW_OK;
+    };
+
+    // Host: upper-triangular R (columns), Givens rotations, g = beta e1.
+    std::vector<std::vector<double>> R;
+    std::vector<double> cs, sn, g(1, beta);
+    bool converged = false;
+    double res = 1.0;
+    int k = 0;
+    if ((rc = launch_step(0))) return rc;
+    for (; k < max_iter; ++k) {
+        RPYW_HIP(hipEventSynchronize(g_h.ev[k & 1]));
+        const double* hs = h_slot + (size_t)(k & 1) * slot;
+        std::vector<double> h(k + 2);
+        for (int j = 0; j <= k; ++j) h[j] = hs[j] + hs[k + 1 + j];
+        h[k + 1] = hs[2 * (k + 1)];
+        if (k + 1 < max_iter && (rc = launch_step(k + 1))) return rc;
+        for (int j = 0; j < k; ++j) {
+            const double t0 = cs[j] * h[j] + sn[j] * h[j + 1];
+            h[j + 1] = -sn[j] * h[j] + cs[j] * h[j + 1];
+            h[j] = t0;
+        }
+        const double rr = std::hypot(h[k], h[k + 1]);
+        const double c = rr > 0.0 ? h[k] / rr : 1.0, s = rr > 0.0 ? h[k + 1] / rr : 0.0;
+        cs.push_back(c);
+        sn.push_back(s);
+        const double hk1 = h[k + 1];
+        h[k] = rr;
+        h.resize(k + 1);
+        R.push_back(h);
+        g.push_back(-s * g[k]);
+        g[k] = c * g[k];
+        res = std::fabs(g[k + 1]) / beta;
+        if (!std::isfinite(res)) return RPYW_EHIP;
+        if (res <= tol || hk1 <= 1e-14 * beta) {
+            converged = true;
+            break;
+        }
+    }
+    const int m = (int)R.size();
+    *iters = m;
+    *res_out = res;
+    // Back substitution R y = g, then x = P^-1 (V y).
+    std::vector<double> yv(m);
+    for (int i = m - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int j = i + 1; j < m; ++j) s -= R[j][i] * yv[j];
+        yv[i] = R[i][i] != 0.0 ? s / R[i][i] : 0.0;
+    }
+    RPYW_HIP(hipMemcpyAsync(d_y, yv.data(), m * sizeof(double), hipMemcpyHostToDevice, st));
+    if ((rc = vec_comb(V, n, m, d_y, w, n, st))) return rc;
+    if ((rc = precond(w, nullptr, nullptr, lam_out, U_out))) return rc;
+    RPYW_HIP(hipStreamSynchronize(st));  // yv leaves scope
+    return converged ? RPYW_OK : RPYW_NOT_CONVERGED;
+}
+
+}  // namespace rpyw

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <mutex>
 
 #include "../../include/rpywall.h"
 
@@ -85,12 +86,62 @@ bool profiling_enabled();
 void profile_begin(hipStream_t st, hipEvent_t* ev);
 void profile_end(hipStream_t st, hipEvent_t ev0, double pairs);
 
+// Krylov building blocks (krylov.hip).
+// Block-diagonal preconditioner factors: per body the Cholesky factor L_p of
+// its own block M^(pp) (other bodies ignored, wall kept) and L_p^-1; with no
+// body structure, the per-blob diagonal square root.
+struct BodyFactors {
+    bool diag = true;
+    int nb = 0;
+    int* bofs = nullptr;      // device [nb + 1] blob offsets
+    int64_t* lofs = nullptr;  // device [nb + 1] offsets of the (3 n_p)^2 blocks
+    double* L = nullptr;      // per body L_p then L_p^-1 (at 2 lofs[p]); or the diagonal [3N]
+    // mode 0: out = L v; 1: out = L^-1 v; 2: out = L^-T v.  With scale the
+    // input is v / scale[0] and, with store, that scaled input is written
+    // there too.
+    int apply(int mode, const double* v, double* out, int64_t n3, hipStream_t st, const double* scale = nullptr,
+              double* store = nullptr) const;
+};
+size_t body_factors_bytes(int64_t N, int n_bodies);
+// Builds the factors on the stream; sets *notspd (device int, zeroed by the
+// caller) when a block is not positive definite.  body_offsets: host.
+int body_factors_build(const double* pos, int64_t N, double a, double eta, const int64_t* body_offsets, int n_bodies,
+                       Arena& ar, hipStream_t st, BodyFactors& pc, int* notspd);
+// Vector kernels (FP64, length n, basis vectors V_j at V + j ld):
+//   update: wout = win - bscale[0] vprev - sum_{j < nsub} csub[j] V_j;
+//   dots:   out[j] = V_j . w (j < nv), or out[0] = |w| when nv == 0, with a
+//           fixed-order finish; out[copy_idx] is also copied to copy_to;
+//           partial holds max(nv, 1) dot_chunks(n) doubles, ticket one
+//           zeroed unsigned that the kernel re-arms;
+//   comb:   out = sum_{j < nv} c[j] V_j.
+int64_t dot_chunks(int64_t n);
+int vec_update(const double* win, double* wout, int64_t n, const double* vprev, const double* bscale,
+               const double* V, int64_t ld, const double* csub, int nsub, hipStream_t st);
+int vec_dots(const double* V, int64_t ld, int nv, const double* w, int64_t n, double* partial, unsigned* ticket,
+             double* out, int copy_idx, double* copy_to, hipStream_t st);
+int vec_comb(const double* V, int64_t ld, int nv, const double* c, double* out, int64_t n, hipStream_t st);
+// Library-owned pinned host buffer plus two events for per-iteration
+// device->host copies of a solver; the caller holds mu while using it.
+struct PinnedSlots {
+    std::mutex mu;
+    double* p = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int reserve(size_t bytes);
+};
+
 // Lanczos (lanczos.hip)
 size_t lanczos_ws_bytes(int64_t N, int max_iter, int n_bodies, int prec);
 int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, double a, double eta,
                  const int64_t* body_offsets, int n_bodies, double tol, int max_iter, int prec, Arena& ar,
                  int* iters, double* err, hipStream_t st);
 int tridiag_sqrt_coeffs(const double* alpha, const double* beta, int k, double beta0, double* c);
+
+// Rigid multiblobs (rigid.hip)
+size_t rigid_ws_bytes(int64_t N, int max_iter, int n_bodies, int prec);
+int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets, int n_bodies, const double* slip,
+                const double* FT, double* lam_out, double* U_out, int64_t N, double a, double eta, double tol,
+                int max_iter, int prec, Arena& ar, int* iters, double* res_out, hipStream_t st);
 
 // Derivatives (vjp.hip)
 size_t vjp_ws_bytes(int64_t N, int prec);

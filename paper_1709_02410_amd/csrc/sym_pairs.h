@@ -63,6 +63,17 @@ __device__ __forceinline__ double rot_next(double v) {
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 
+// rot_next(s) + c.  The rotation takes c as its old value (never read: the
+// rotate has a source lane for every lane, and bound_ctrl is set), which
+// keeps it next to the add that consumes it, so the two fuse into one DPP
+// add instead of a DPP move and an add.
+__device__ __forceinline__ float rot_add(float s, float c) {
+    const int r = __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, c), __builtin_bit_cast(int, s), 0x134, 0xF, 0xF,
+                                              true);
+    return __builtin_bit_cast(float, r) + c;
+}
+__device__ __forceinline__ double rot_add(double s, double c) { return rot_next(s) + c; }
+
 template <typename R>
 struct Vec;
 template <>
@@ -142,7 +153,14 @@ struct SymLane {
             Body::template pair<SYM>(t, r, acc, c);
             if constexpr (SYM) {
 #pragma unroll
-                for (int q = 0; q < NQ; ++q) S[q] = rot_next(S[q]) + c[q];
+                for (int q = 0; q < NQ; ++q) {
+                    S[q] = rot_add(S[q], c[q]);
+                    // An empty asm use pins the add to this pair's block:
+                    // otherwise the tail of the pair is sunk past the next
+                    // pair's overlap branch, away from the (unmovable) DPP
+                    // rotate it should fuse with.
+                    __asm__ volatile("" ::"v"(S[q]));
+                }
             }
         }
         if constexpr (SYM) {

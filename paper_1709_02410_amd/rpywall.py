@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "librpywall.so")
 
 FP64 = 0
 FP32C = 1
-OP_MATVEC, OP_BATCHED, OP_LANCZOS, OP_VJP, OP_DIVERGENCE = range(5)
+OP_MATVEC, OP_BATCHED, OP_LANCZOS, OP_VJP, OP_DIVERGENCE, OP_RIGID = range(6)
 
 OK, NOT_CONVERGED, EINVAL, EHIP, ENOMEM, ENOTSPD = 0, 1, -1, -2, -3, -4
 
@@ -48,6 +48,8 @@ def lib():
         "rpy_wall_matvec_batched": [vp, i64p, i32, vp, vp, i32, dbl, dbl, ctypes.c_int, vp, sz, vp],
         "rpy_wall_lanczos_sqrt": [vp, vp, vp, i64, dbl, dbl, i64p, i32, dbl, i32, ctypes.c_int, vp, sz,
                                   ctypes.POINTER(i32), ctypes.POINTER(dbl), vp],
+        "rpy_wall_rigid_solve": [vp, vp, i64p, i32, vp, vp, vp, vp, i64, dbl, dbl, dbl, i32, ctypes.c_int, vp, sz,
+                                 ctypes.POINTER(i32), ctypes.POINTER(dbl), vp],
         "rpy_wall_matvec_vjp": [vp, vp, vp, vp, vp, i64, dbl, dbl, ctypes.c_int, vp, sz, vp],
         "rpy_wall_divergence": [vp, vp, i64, dbl, dbl, ctypes.c_int, vp, sz, vp],
         "rpy_wall_autotune": [vp, vp, vp, i64, i32, dbl, dbl, ctypes.c_int, vp, sz, vp],
@@ -172,6 +174,37 @@ def lanczos_sqrt(pos: torch.Tensor, W: torch.Tensor, a: float = 1.0, eta: float 
                                      ctypes.byref(err), _stream(pos.device))
     _check(st, "rpy_wall_lanczos_sqrt", allow=(OK,) if strict else (OK, NOT_CONVERGED))
     return out, int(it.value), float(err.value), st == OK
+
+
+def rigid_solve(pos: torch.Tensor, q: torch.Tensor, body_offsets, slip: torch.Tensor | None = None,
+                force_torque: torch.Tensor | None = None, a: float = 1.0, eta: float = 1.0, tol: float = 1e-6,
+                max_iter: int = 200, precision: int = FP64, strict: bool = False):
+    """Rigid-multiblob mobility problem M lambda - K U = -slip,
+    -K^T lambda = -F by block-preconditioned GMRES.  pos (N,3), q (nb,3)
+    reference points, body_offsets host int64 [nb+1], slip (N,3) or None,
+    force_torque (nb,6) or None.  Returns (lambda (N,3), U (nb,6) =
+    (u, omega), iterations, relative residual estimate, converged flag)."""
+    N = pos.shape[0]
+    offs = _offsets(body_offsets)
+    nb = offs.shape[0] - 1
+    _dev(pos, "pos", (N, 3))
+    _dev(q, "q", (nb, 3))
+    if slip is not None:
+        _dev(slip, "slip", (N, 3))
+    if force_torque is not None:
+        _dev(force_torque, "force_torque", (nb, 6))
+    lam = torch.empty_like(pos)
+    U = torch.empty((nb, 6), dtype=torch.float64, device=pos.device)
+    ws = _workspace(workspace_bytes(OP_RIGID, N, 1, max_iter, nb, precision), pos.device)
+    it = ctypes.c_int32(0)
+    res = ctypes.c_double(0.0)
+    st = lib().rpy_wall_rigid_solve(pos.data_ptr(), q.data_ptr(), offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                    nb, slip.data_ptr() if slip is not None else None,
+                                    force_torque.data_ptr() if force_torque is not None else None, lam.data_ptr(),
+                                    U.data_ptr(), N, a, eta, tol, max_iter, precision, ws.data_ptr(), ws.numel(),
+                                    ctypes.byref(it), ctypes.byref(res), _stream(pos.device))
+    _check(st, "rpy_wall_rigid_solve", allow=(OK,) if strict else (OK, NOT_CONVERGED))
+    return lam, U, int(it.value), float(res.value), st == OK
 
 
 def matvec_vjp(pos: torch.Tensor, force: torch.Tensor, grad_vel: torch.Tensor, a: float = 1.0, eta: float = 1.0,

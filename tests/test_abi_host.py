@@ -62,14 +62,25 @@ def test_validation_rejects_before_any_launch(lib):
                                      ctypes.byref(it), ctypes.byref(er), None) == E  # tol <= 0
     assert lib.rpy_wall_matvec_vjp(dummy, dummy, dummy, None, None, 10, 1.0, 1.0, 0, None, 0, None) == E
     assert lib.rpy_wall_divergence(dummy, None, 10, 1.0, 1.0, 0, None, 0, None) == E
+    rig = lambda offs_, nb, N, q=dummy, tol=1e-6, it_=50: lib.rpy_wall_rigid_solve(  # noqa: E731
+        dummy, q, offs_, nb, None, None, dummy, dummy, N, 1.0, 1.0, tol, it_, 0, None, 0, ctypes.byref(it),
+        ctypes.byref(er), None)
+    assert rig(offs, 2, 10) == E        # offsets end at 9 != N
+    assert rig(big, 1, 43) == E         # body too large for the per-body factors
+    assert rig(offs, 2, 9, q=None) == E  # reference points missing
+    assert rig(offs, 0, 9) == E         # no bodies
+    assert rig(offs, 2, 9, tol=0.0) == E
+    assert rig(offs, 2, 9, it_=0) == E
+    assert rig(bad_offs, 2, 5) == E     # empty body
     # misaligned caller workspace
     assert lib.rpy_wall_matvec(dummy, dummy, dummy, 10, 1.0, 1.0, 0, ctypes.c_void_p(0x1001), 1 << 20,
                                None) == E
 
 
 def test_workspace_sizes(lib):
-    for op in range(5):
-        assert rpywall.workspace_bytes(op, 1000, 4, 50, 10 if op == 1 else 0, 1) > 0
+    for op in range(6):
+        assert rpywall.workspace_bytes(op, 1000, 4, 50, 10 if op in (1, 5) else 0, 1) > 0
+    assert rpywall.workspace_bytes(5, 1000, 1, 50, 0) == 0  # rigid solve needs bodies
     assert lib.rpy_wall_workspace_bytes(0, 0, 1, 0, 0, 0) == 0
     assert lib.rpy_wall_workspace_bytes(9, 10, 1, 0, 0, 0) == 0
     small = rpywall.workspace_bytes(0, 1000, 1)
