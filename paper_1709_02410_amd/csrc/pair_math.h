@@ -13,14 +13,11 @@
 //   R = r~_i - mirror(r~_j) = (dx, dy, Rz), Rz = z_i + z_j, R2 = |R|^2
 //   w = 1/|R|, X = w^2, zz = z_i z_j                      (image part)
 // The wall correction, written in q = Rz w, p = z_j w, s = X, is rearranged
-// as polynomials in X whose coefficients depend on Rz^2 and zz only:
-//   |R| A  = -3/4 + X(-3/2 zz - 1/2 + X(3/2 Rz2 + 1/2 - 5/2 Rz2 X))
-//   |R| B  = -3/4 + X( 9/2 zz + 3/2 + X(-15/2 Rz2 - 5/2 + 35/2 Rz2 X))
-//   |R| C  = -3/4 dz + Rz X (-(9/2 zz + 3/2) + X(15/2 (Rz2 + 1) - 35/2 Rz2 X))
-//   |R| C' = -3/4 dz - Rz X (same bracket)
-//   |R| E  = -3/4 + X(e1 + X(e2 + X(e3 + X e4))),
-//            e1 = -3/4 Rz2 + 3/2 zz - 1/2, e2 = -Rz2 (9/2 zz + 3) - 3/2,
-//            e3 = Rz2 (15/2 Rz2 + 15), e4 = -35/2 Rz2^2
+// as polynomials in X whose coefficients depend on u = Rz^2 X and v = zz X:
+//   |R| A  = -3/4 - 3/2 v + X(-1/2 + 3/2 u + X(1/2 - 5/2 u))
+//   |R| B  = -3/4 + 9/2 v + X( 3/2 - 15/2 u + X(-5/2 + 35/2 u))
+//   |R| C  = -3/4 dz + Rz g,   |R| C' = -3/4 dz - Rz g,   g = 5 X^2 - 3/4 - |R| B
+//   |R| E  = -u |R| B - 3/4 - 3/2 u + 3/2 v + X(-1/2 - 3/2 u + X(-3/2 + 25/2 u))
 // (using q p - p^2 = zz X, the identity that removes p).  The block acts as
 //   (Mf)_x = (c1 + w A') f_x + dx [c2 (d.f) + w X (B' G + C' f_z)]   (same y)
 //   (Mf)_z = (c1 + w E') f_z + c2 (d.f) dz + w X (Cm' G)
@@ -99,36 +96,26 @@ __device__ __forceinline__ PairCoef<R> pair_coef(R dx, R dy, R dz, R zi, R zj) {
         c1 = near ? c1n : c1;
         c2 = near ? c2n : c2;
     }
-    const R zz = zi * zj;
-    // |R| A
-    const R a1 = fma_(zz, R(-1.5), R(-0.5));
-    const R a2 = fma_(rz2, R(1.5), R(0.5));
-    const R a3 = rz2 * R(-2.5);
-    const R rA = fma_(X, fma_(X, fma_(X, a3, a2), a1), R(-0.75));
-    // |R| B
-    const R b1 = fma_(zz, R(4.5), R(1.5));
-    const R b2 = fma_(rz2, R(-7.5), R(-2.5));
-    const R b3 = rz2 * R(17.5);
-    const R rB = fma_(X, fma_(X, fma_(X, b3, b2), b1), R(-0.75));
-    // |R| C and |R| C' = U +- V
-    const R v2 = fma_(rz2, R(7.5), R(7.5));
-    const R pv = fma_(X, fma_(-X, b3, v2), -b1);
-    const R vw = (rz * X) * pv;
+    const R u = rz2 * X;
+    // v = zz X enters only as v c; written (z_j X)(c z_i) so that c z_i is
+    // hoisted out of loops over sources.
+    const R zjX = zj * X;
+    const R rA =
+        fma_(X, fma_(X, fma_(u, R(-2.5), R(0.5)), fma_(u, R(1.5), R(-0.5))), fma_(zjX, R(-1.5) * zi, R(-0.75)));
+    const R rB =
+        fma_(X, fma_(X, fma_(u, R(17.5), R(-2.5)), fma_(u, R(-7.5), R(1.5))), fma_(zjX, R(4.5) * zi, R(-0.75)));
+    const R g = fma_(X * X, R(5.0), R(-0.75)) - rB;
     const R cw = dz * R(-0.75);
-    // |R| E
-    const R e1 = fma_(zz, R(1.5), fma_(rz2, R(-0.75), R(-0.5)));
-    const R e2 = fma_(rz2, fma_(zz, R(-4.5), R(-3.0)), R(-1.5));
-    const R e3 = rz2 * fma_(rz2, R(7.5), R(15.0));
-    const R e4 = (rz2 * rz2) * R(-17.5);
-    const R rE = fma_(
-        X, fma_(X, fma_(X, fma_(X, e4, e3), e2), e1), R(-0.75));
+    const R qE = fma_(X, fma_(X, fma_(u, R(12.5), R(-1.5)), fma_(u, R(-1.5), R(-0.5))),
+                      fma_(zjX, R(1.5) * zi, fma_(u, R(-1.5), R(-0.75))));
+    const R rE = fma_(-u, rB, qE);
     o.c1 = c1;
     o.c2 = c2;
     o.cc = fma_(w, rA, c1);
     o.cz = fma_(w, rE, c1);
     o.kb = wX * rB;
-    o.kcp = wX * (cw + vw);
-    o.kcm = wX * (cw - vw);
+    o.kcp = wX * fma_(rz, g, cw);
+    o.kcm = wX * fma_(-rz, g, cw);
     return o;
 }
 

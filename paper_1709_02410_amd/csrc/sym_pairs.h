@@ -8,18 +8,26 @@
 // item (P, d) pairs target group P with source group Q = (P + d) mod ng for
 // d = 0 .. H(P) (sym_rowlen), which covers every unordered pair of groups
 // exactly once.  A workgroup of four waves takes `ipw` consecutive items of
-// one row.  Wave w holds target block 4P + w; for each source block of Q it
-// runs 64 steps in which lane l pairs its target with source (l + s) mod 64,
-// read from LDS rows that hold the block twice (so l + s needs no wrap).  The
-// lane adds the target-side contribution to its own sums and the source-side
-// contribution to an accumulator that moves one lane down after every step
-// (a DPP wavefront rotate fused into the add), so that after the pass lane l
-// holds the complete source-side sum of source l.  In the diagonal item
-// (d = 0) blocks above the wave's own are done symmetrically, the wave's own
-// block over all ordered pairs (self included, target side only), and blocks
-// below it are left to the waves that own them.  Target sums are written per
-// (row, chunk) and source sums per (group, d); an epilogue adds both in a
-// fixed order, so results are bitwise reproducible.
+// one row.  Wave w holds target block 4P + w; in phase b (b = 0..3) it takes
+// source block (w + b) mod 4, so the four waves work on four different
+// source blocks (in FP64 with a workgroup barrier between phases).  A phase is 64
+// steps in which lane l pairs its target with source (l + s) mod 64, read
+// from LDS rows that hold the block twice (so l + s needs no wrap).  The lane
+// adds the target-side contribution to its own sums.  The source-side
+// contribution goes, in FP32, to an accumulator that moves one lane down
+// after every step (a DPP wavefront rotate fused into the add), so that
+// after the phase lane l holds the complete sum of source l, and the four
+// waves' sums are added through LDS; in FP64 it goes to an LDS slot l + s of
+// that source block by an LDS atomic add (no two lanes of an instruction
+// share a slot, one wave owns a block per phase and the phases are ordered
+// by the barriers, so the order of additions is fixed; slots j and j + 64
+// together hold source j's sum).
+// In the diagonal item (d = 0) blocks above the wave's own are done
+// symmetrically, the wave's own block over all ordered pairs (self
+// included, target side only), and blocks below it are left to the waves
+// that own them.  Target sums are written per (row, chunk) and source sums
+// per (group, d); an epilogue adds both in a fixed order, so results are
+// bitwise reproducible.
 //
 // A Body supplies the per-pair arithmetic: KREC right-hand sides in the
 // record, NQ accumulated quantities, and
@@ -132,14 +140,18 @@ struct SymLane {
         for (int q = 0; q < NQ; ++q) acc[q] = hi[q] = lo[q] = R(0);
     }
 
-    // One 64-step pass over source block `blk`; S returns the source-side
-    // sums (lane l: source l of the block) when SYM, zeros otherwise.
+    // One 64-step pass over source block `blk`.  When SYM, the source-side
+    // contribution for source (l + s) mod 64 goes either to the accumulator
+    // S, which moves one lane down after every step (a DPP wave rotate fused
+    // into the add), so that after the pass lane l holds source l's sum
+    // (sa == nullptr), or to LDS sa[q * 128 + l + s] by an atomic add.
     template <bool SYM>
-    __device__ void pass(const typename Vec<R>::T* __restrict__ tile, int blk, int l, R (&S)[NQ]) {
+    __device__ void pass(const typename Vec<R>::T* __restrict__ tile, int blk, int l, R* sa, R (&S)[NQ]) {
         using VT = typename Vec<R>::T;
+        const VT* base = tile + blk * 128 + l;
+        R* sl = sa + l;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) S[q] = R(0);
-        const VT* base = tile + blk * 128 + l;
 #pragma unroll 4
         for (int s = 0; s < 64; ++s) {
             R r[RW];
@@ -152,20 +164,28 @@ struct SymLane {
             R c[NQ];
             Body::template pair<SYM>(t, r, acc, c);
             if constexpr (SYM) {
+                if (sa) {
 #pragma unroll
-                for (int q = 0; q < NQ; ++q) {
-                    S[q] = rot_add(S[q], c[q]);
-                    // An empty asm use pins the add to this pair's block:
-                    // otherwise the tail of the pair is sunk past the next
-                    // pair's overlap branch, away from the (unmovable) DPP
-                    // rotate it should fuse with.
-                    __asm__ volatile("" ::"v"(S[q]));
+                    for (int q = 0; q < NQ; ++q)
+                        __hip_atomic_fetch_add(sl + q * 128 + s, c[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) {
+                        S[q] = rot_add(S[q], c[q]);
+                        // An empty asm use pins the add to this pair's block:
+                        // otherwise the tail of the pair is sunk past the next
+                        // pair's overlap branch, away from the (unmovable) DPP
+                        // rotate it should fuse with.
+                        __asm__ volatile("" ::"v"(S[q]));
+                    }
                 }
             }
         }
         if constexpr (SYM) {
+            if (!sa) {
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) S[q] = rot_next(S[q]);
+                for (int q = 0; q < NQ; ++q) S[q] = rot_next(S[q]);
+            }
         }
         if constexpr (sizeof(R) == 4) {
 #pragma unroll
@@ -192,8 +212,14 @@ __global__ __launch_bounds__(kSymBlock) void sym_kernel(const R* __restrict__ re
     using L = SymLane<R, Body>;
     using VT = typename Vec<R>::T;
     constexpr int NQ = L::NQ;
+    // FP64: source sums by LDS atomics (one wave per source block and phase);
+    // FP32: by the DPP rotation, then across the waves through `red` (LDS
+    // FP32 atomic adds are far slower than the rotation on this GPU, FP64
+    // ones are faster).
+    constexpr bool kLds = sizeof(R) == 8;
     __shared__ VT tile[L::NV * 512];
-    __shared__ R red[4][NQ][256];
+    __shared__ R sacc[kLds ? 4 : 1][kLds ? NQ : 1][kLds ? 128 : 1];  // per source block, slots l + s
+    __shared__ R red[kLds ? 1 : 4][kLds ? 1 : NQ][kLds ? 1 : 256];
     const int P = blockIdx.x / C, c = blockIdx.x % C;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     L me;
@@ -213,6 +239,10 @@ __global__ __launch_bounds__(kSymBlock) void sym_kernel(const R* __restrict__ re
                 tile[v * 512 + b * 128 + j] = q;
                 tile[v * 512 + b * 128 + j + 64] = q;
             }
+            if constexpr (kLds) {
+                R* z = &sacc[0][0][0];
+                for (int e = threadIdx.x; e < 4 * NQ * 128; e += blockDim.x) z[e] = R(0);
+            }
         }
         __syncthreads();
         for (int bb = 0; bb < 4; ++bb) {
@@ -222,19 +252,28 @@ __global__ __launch_bounds__(kSymBlock) void sym_kernel(const R* __restrict__ re
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) S[q] = R(0);
             } else if (d == 0 && blk == w) {
-                me.template pass<false>(tile, blk, l, S);
+                me.template pass<false>(tile, blk, l, nullptr, S);
             } else {
-                me.template pass<true>(tile, blk, l, S);
+                me.template pass<true>(tile, blk, l, kLds ? &sacc[blk][0][0] : nullptr, S);
             }
+            if constexpr (kLds) {
+                __syncthreads();  // one wave per source block in every phase
+            } else {
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) red[w][q][blk * 64 + l] = S[q];
+                for (int q = 0; q < NQ; ++q) red[w][q][blk * 64 + l] = S[q];
+            }
         }
-        __syncthreads();
+        if constexpr (!kLds) __syncthreads();
         R* out = spart + ((int64_t)Q * (Hmax + 1) + d) * NQ * 256;
+        const int b = threadIdx.x >> 6, j = threadIdx.x & 63;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q)
-            out[q * 256 + threadIdx.x] =
-                ((red[0][q][threadIdx.x] + red[1][q][threadIdx.x]) + red[2][q][threadIdx.x]) + red[3][q][threadIdx.x];
+        for (int q = 0; q < NQ; ++q) {
+            if constexpr (kLds)
+                out[q * 256 + threadIdx.x] = sacc[b][q][j] + sacc[b][q][j + 64];
+            else
+                out[q * 256 + threadIdx.x] =
+                    ((red[0][q][threadIdx.x] + red[1][q][threadIdx.x]) + red[2][q][threadIdx.x]) + red[3][q][threadIdx.x];
+        }
     }
     double* tp = tpart + ((int64_t)P * C + c) * NQ * 256;
 #pragma unroll

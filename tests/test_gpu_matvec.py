@@ -153,6 +153,25 @@ def test_symmetric_kernel_ragged(rp, orc, N, prec, kblk):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_symmetric_kernel_bitwise_repeatable(rp, prec):
+    """Fixed-order sums (FP32: wave rotation; FP64: LDS atomic adds ordered
+    by wave and phase): four repeated products and VJPs on 20000 blobs (79
+    groups, thousands of concurrent workgroups) are bitwise identical."""
+    cfg = wl.headline(seed=4, N=20000)
+    pos = _t(cfg.pos)
+    f = _t(wl.gaussian(cfg.pos.shape, 5))
+    g = _t(wl.gaussian(cfg.pos.shape, 6))
+    for ipw in (1, 2):
+        rp.set_shape(prec, cfg.N, 1, tpl=1, tile=256, kblk=1, sym=1, ipw=ipw)
+        U0 = rp.matvec(pos, f, precision=prec)
+        G0 = rp.matvec_vjp(pos, f, g, precision=prec)[0]
+        for _ in range(3):
+            assert torch.equal(rp.matvec(pos, f, precision=prec), U0)
+            assert torch.equal(rp.matvec_vjp(pos, f, g, precision=prec)[0], G0)
+    rp.reset_shape(prec, cfg.N, 1)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 def test_symmetric_equals_plain_at_1e5(rp, prec):
     """Both kernels on the measured workload agree to the precision bound."""
     cfg = wl.headline(seed=0)
