@@ -23,6 +23,9 @@ Contents (arXiv:1709.02410):
     solved densely, and N = (K^T M^-1 K)^-1.
   * ``rigid_gmres``: the same system by GMRES right-preconditioned with the
     per-body block-diagonal operator (Sec. II.B); used for iteration counts.
+  * ``box=(Lx, Ly)`` on the products, dense matrices, roots and solves: the
+    pseudo-periodic domain of the paper's suspensions (Sec. V): each source
+    at its minimum image plus the 8 periodic images around it.
 
 Readings where the paper is silent (the Lanczos stopping rule, full
 reorthogonalisation, breakdown handling) are stated in each docstring.
@@ -69,11 +72,16 @@ def _L():
         lib.oracle_matvec.argtypes = [_dp, _dp, _dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                       _lp, ctypes.c_int64, ctypes.c_int]
         lib.oracle_dense.argtypes = [_dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double, _dp]
+        lib.oracle_matvec_periodic.argtypes = [_dp, _dp, _dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                               ctypes.c_double, ctypes.c_double, _lp, ctypes.c_int64, ctypes.c_int]
+        lib.oracle_dense_periodic.argtypes = [_dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                              ctypes.c_double, ctypes.c_double, _dp]
         lib.oracle_vjp.argtypes = [_dp, _dp, _dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                    _dp, _dp, ctypes.c_int]
         lib.oracle_divergence.argtypes = [_dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double, _dp,
                                           ctypes.c_int]
-        for fn in ("oracle_pair_block", "oracle_matvec", "oracle_dense", "oracle_vjp", "oracle_divergence"):
+        for fn in ("oracle_pair_block", "oracle_matvec", "oracle_dense", "oracle_vjp", "oracle_divergence",
+                   "oracle_matvec_periodic", "oracle_dense_periodic"):
             getattr(lib, fn).restype = None
         _lib = lib
     return _lib
@@ -100,28 +108,33 @@ def pair_block(ri, rj, a: float = 1.0, eta: float = 1.0, part: int = 0) -> np.nd
     return out.reshape(3, 3)
 
 
-def matvec(pos, f, a: float = 1.0, eta: float = 1.0, rows=None, nthreads: int = 0) -> np.ndarray:
-    """u = M f; with ``rows`` only those target rows (shape (len(rows), 3))."""
+def matvec(pos, f, a: float = 1.0, eta: float = 1.0, rows=None, nthreads: int = 0, box=None) -> np.ndarray:
+    """u = M f; with ``rows`` only those target rows (shape (len(rows), 3)).
+    box = (Lx, Ly): pseudo-periodic domain (Sec. V): every source at its
+    minimum image and the 8 periodic images around it."""
     pos, f = _c(pos), _c(f)
     N = pos.shape[0]
     assert pos.shape == (N, 3) and f.shape == (N, 3)
-    if rows is None:
-        out = np.empty((N, 3))
-        _L().oracle_matvec(_p(pos), _p(f), _p(out), N, a, eta, None, 0, nthreads)
+    rp, nr = (None, 0) if rows is None else (_c(rows, np.int64), len(rows))
+    out = np.empty((N if rows is None else nr, 3))
+    rptr = None if rp is None else rp.ctypes.data_as(_lp)
+    if box is None:
+        _L().oracle_matvec(_p(pos), _p(f), _p(out), N, a, eta, rptr, nr, nthreads)
     else:
-        rows = _c(rows, np.int64)
-        out = np.empty((rows.shape[0], 3))
-        _L().oracle_matvec(_p(pos), _p(f), _p(out), N, a, eta, rows.ctypes.data_as(_lp), rows.shape[0],
-                           nthreads)
+        _L().oracle_matvec_periodic(_p(pos), _p(f), _p(out), N, a, eta, float(box[0]), float(box[1]), rptr, nr,
+                                    nthreads)
     return out
 
 
-def dense(pos, a: float = 1.0, eta: float = 1.0) -> np.ndarray:
-    """Dense 3N x 3N blob mobility matrix (small N)."""
+def dense(pos, a: float = 1.0, eta: float = 1.0, box=None) -> np.ndarray:
+    """Dense 3N x 3N blob mobility matrix (small N); box as for matvec."""
     pos = _c(pos)
     N = pos.shape[0]
     out = np.empty((3 * N, 3 * N))
-    _L().oracle_dense(_p(pos), N, a, eta, _p(out))
+    if box is None:
+        _L().oracle_dense(_p(pos), N, a, eta, _p(out))
+    else:
+        _L().oracle_dense_periodic(_p(pos), N, a, eta, float(box[0]), float(box[1]), _p(out))
     return out
 
 
@@ -180,14 +193,16 @@ def _apply_blocks(blocks, v, mode: str) -> np.ndarray:
     return out
 
 
-def dense_sqrt(pos, W, body_offsets=None, a: float = 1.0, eta: float = 1.0, precondition: bool = True):
+def dense_sqrt(pos, W, body_offsets=None, a: float = 1.0, eta: float = 1.0, precondition: bool = True, box=None):
     """Dense reference root applied to W (flat 3N or (N,3)).
 
     precondition=True: L (L^-1 M L^-T)^{1/2} W with the block-Cholesky L,
     the root the preconditioned Lanczos converges to.  False: the symmetric
-    M^{1/2} W.  Both satisfy S S^T = M (Sec. II.B).
+    M^{1/2} W.  Both satisfy S S^T = M (Sec. II.B).  With box, M is the
+    pseudo-periodic mobility; the preconditioner blocks stay those of the
+    bodies alone (their periodic images ignored like other bodies).
     """
-    M = dense(pos, a, eta)
+    M = dense(pos, a, eta, box)
     w = np.asarray(W, dtype=np.float64).reshape(-1)
     if not precondition:
         lam, Q = np.linalg.eigh(M)
@@ -216,7 +231,7 @@ def _tridiag_sqrt_coeffs(alpha, beta, beta0):
 
 
 def lanczos_sqrt(pos, W, body_offsets=None, a: float = 1.0, eta: float = 1.0, tol: float = 1e-6,
-                 max_iter: int = 200, precondition: bool = True, matvec_fn=None, nthreads: int = 0):
+                 max_iter: int = 200, precondition: bool = True, matvec_fn=None, nthreads: int = 0, box=None):
     """Preconditioned Lanczos for the Brownian blob displacements (Sec. II.B).
 
     G = L^-1 M L^-T with the block-Cholesky factor L (identity when
@@ -241,7 +256,7 @@ def lanczos_sqrt(pos, W, body_offsets=None, a: float = 1.0, eta: float = 1.0, to
     def G(v):
         x = _apply_blocks(blocks, v, "LinvT") if blocks else v
         if matvec_fn is None:
-            y = matvec(pos, x.reshape(-1, 3), a, eta, nthreads=nthreads).reshape(-1)
+            y = matvec(pos, x.reshape(-1, 3), a, eta, nthreads=nthreads, box=box).reshape(-1)
         else:
             y = np.asarray(matvec_fn(x.reshape(-1, 3))).reshape(-1)
         return _apply_blocks(blocks, y, "Linv") if blocks else y
@@ -347,7 +362,7 @@ def _rigid_rhs(N: int, nb: int, slip, FT) -> np.ndarray:
     return np.concatenate([-s, -F])
 
 
-def rigid_solve(pos, q, body_offsets, slip=None, FT=None, a: float = 1.0, eta: float = 1.0):
+def rigid_solve(pos, q, body_offsets, slip=None, FT=None, a: float = 1.0, eta: float = 1.0, box=None):
     """Mobility problem of rigid multiblobs (Sec. II.A, saddle-point system):
 
         [ M   -K ] [lambda]   [-slip]
@@ -361,23 +376,23 @@ def rigid_solve(pos, q, body_offsets, slip=None, FT=None, a: float = 1.0, eta: f
     N = pos.shape[0]
     K = body_K(pos, q, body_offsets)
     nb = K.shape[1] // 6
-    M = dense(pos, a, eta)
+    M = dense(pos, a, eta, box)
     A = np.block([[M, -K], [-K.T, np.zeros((6 * nb, 6 * nb))]])
     x = np.linalg.solve(A, _rigid_rhs(N, nb, slip, FT))
     return x[:3 * N].reshape(N, 3), x[3 * N:].reshape(nb, 6)
 
 
-def body_mobility(pos, q, body_offsets, a: float = 1.0, eta: float = 1.0) -> np.ndarray:
+def body_mobility(pos, q, body_offsets, a: float = 1.0, eta: float = 1.0, box=None) -> np.ndarray:
     """Body mobility N = (K^T M^-1 K)^-1 (Sec. II.A, eq. N_def), through a
     dense Cholesky factorisation of M.  (6 nb, 6 nb)."""
     K = body_K(pos, q, body_offsets)
-    cf = sla.cho_factor(dense(pos, a, eta), lower=True)
+    cf = sla.cho_factor(dense(pos, a, eta, box), lower=True)
     return np.linalg.inv(K.T @ sla.cho_solve(cf, K))
 
 
 def rigid_gmres(pos, q, body_offsets, slip=None, FT=None, a: float = 1.0, eta: float = 1.0,
                 tol: float = 1e-8, max_iter: int = 200, precondition: bool = True, matvec_fn=None,
-                nthreads: int = 0):
+                nthreads: int = 0, box=None):
     """The saddle-point system of rigid_solve by GMRES, right-preconditioned
     with the block-diagonal approximation of Sec. II.B (interactions between
     distinct bodies dropped, each body's own block M^(pp) kept, wall
@@ -422,7 +437,7 @@ def rigid_gmres(pos, q, body_offsets, slip=None, FT=None, a: float = 1.0, eta: f
     def A(x):
         lam, U = x[:3 * N], x[3 * N:]
         if matvec_fn is None:
-            Ml = matvec(pos, lam.reshape(-1, 3), a, eta, nthreads=nthreads).reshape(-1)
+            Ml = matvec(pos, lam.reshape(-1, 3), a, eta, nthreads=nthreads, box=box).reshape(-1)
         else:
             Ml = np.asarray(matvec_fn(lam.reshape(-1, 3))).reshape(-1)
         return np.concatenate([Ml - K @ U, -(K.T @ lam)])

@@ -217,6 +217,64 @@ void oracle_matvec(const double* pos, const double* f, double* u, int64_t N, dou
     }
 }
 
+/* Source blob j as seen from target i in the pseudo-periodic domain
+ * (Sec. V, dense suspensions): the minimum image of r_j, shifted by
+ * (n_x + sx) Lx and (n_y + sy) Ly with n the nearest integer to
+ * (r_i - r_j) / L (ties to even) and sx, sy in {-1, 0, 1}. */
+static void periodic_image(const double* ri, const double* rj, double Lx, double Ly, int sx, int sy, double* out) {
+    const double nx = std::nearbyint((ri[0] - rj[0]) / Lx), ny = std::nearbyint((ri[1] - rj[1]) / Ly);
+    out[0] = rj[0] + (nx + sx) * Lx;
+    out[1] = rj[1] + (ny + sy) * Ly;
+    out[2] = rj[2];
+}
+
+/* u = M f in the pseudo-periodic domain: for every (target, source) pair
+ * the source's minimum image and the 8 periodic images around it (the self
+ * pair included: the blob itself and its 8 images). */
+void oracle_matvec_periodic(const double* pos, const double* f, double* u, int64_t N, double a, double eta,
+                            double Lx, double Ly, const int64_t* rows, int64_t nrows, int nthreads) {
+    const double m0 = mu0(a, eta);
+    const int64_t nr = rows ? nrows : N;
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nr; ++r) {
+        const int64_t i = rows ? rows[r] : r;
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int64_t j = 0; j < N; ++j)
+            for (int sx = -1; sx <= 1; ++sx)
+                for (int sy = -1; sy <= 1; ++sy) {
+                    double rj[3], blk[3][3];
+                    periodic_image(pos + 3 * i, pos + 3 * j, Lx, Ly, sx, sy, rj);
+                    pair_block<double>(pos + 3 * i, rj, a, 0, blk);
+                    for (int c = 0; c < 3; ++c)
+                        acc[c] += blk[c][0] * f[3 * j] + blk[c][1] * f[3 * j + 1] + blk[c][2] * f[3 * j + 2];
+                }
+        for (int c = 0; c < 3; ++c) u[3 * r + c] = m0 * acc[c];
+    }
+}
+
+/* Dense pseudo-periodic M (row-major 3N x 3N), for tiny N. */
+void oracle_dense_periodic(const double* pos, int64_t N, double a, double eta, double Lx, double Ly,
+                           double* out) {
+    const double m0 = mu0(a, eta);
+    const int64_t n3 = 3 * N;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i)
+        for (int64_t j = 0; j < N; ++j) {
+            double sum[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+            for (int sx = -1; sx <= 1; ++sx)
+                for (int sy = -1; sy <= 1; ++sy) {
+                    double rj[3], blk[3][3];
+                    periodic_image(pos + 3 * i, pos + 3 * j, Lx, Ly, sx, sy, rj);
+                    pair_block<double>(pos + 3 * i, rj, a, 0, blk);
+                    for (int r = 0; r < 3; ++r)
+                        for (int c = 0; c < 3; ++c) sum[r][c] += blk[r][c];
+                }
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) out[(3 * i + r) * n3 + 3 * j + c] = m0 * sum[r][c];
+        }
+}
+
 /* Dense 3N x 3N matrix M (row-major), for tiny N. */
 void oracle_dense(const double* pos, int64_t N, double a, double eta, double* out) {
     const double m0 = mu0(a, eta);
