@@ -78,6 +78,20 @@ int rpy_wall_matvec(const double* pos, const double* force, double* vel, int64_t
 int rpy_wall_matvec_multi(const double* pos, const double* F, double* U, int64_t N, int32_t k, double a,
                           double eta, int precision, void* ws, size_t ws_bytes, void* stream);
 
+/* Pseudo-periodic domain along the wall (the paper's dense suspensions,
+ * Sec. V): u = M f where every source blob enters at its minimum image
+ * relative to the target and at the 8 periodic images around that one,
+ * for the unit cell Lx x Ly in x and y (the wall stays at z = 0); the self
+ * pair includes the blob's own 8 images.  The minimum image is the shift
+ * by the nearest integer multiple of the cell (ties to even).  Positions
+ * may lie outside the cell: they are wrapped into it first.  Evaluated by
+ * the symmetric kernel, one right-hand side at a time (9 image blocks per
+ * unordered pair).  F, U: device [k][N][3]; Lx, Ly > 0 in the units of
+ * pos; other arguments as for rpy_wall_matvec_multi. */
+int rpy_wall_matvec_periodic(const double* pos, const double* F, double* U, int64_t N, int32_t k, double a,
+                             double eta, double Lx, double Ly, int precision, void* ws, size_t ws_bytes,
+                             void* stream);
+
 /* S independent suspensions in one persistent launch: system s owns blobs
  * [sys_offsets[s], sys_offsets[s+1]) and blobs of different systems do not
  * interact.  sys_offsets: HOST int64 [S+1], sys_offsets[0] = 0, strictly
@@ -105,6 +119,15 @@ int rpy_wall_lanczos_sqrt(const double* pos, const double* W, double* out, int64
                           const int64_t* body_offsets, int32_t n_bodies, double tol, int32_t max_iter,
                           int precision, void* ws, size_t ws_bytes, int32_t* iters_out, double* err_est_out,
                           void* stream);
+
+/* rpy_wall_lanczos_sqrt with the pseudo-periodic mobility of
+ * rpy_wall_matvec_periodic (cell Lx x Ly).  The preconditioner blocks are
+ * those of each body alone: its periodic images are ignored like the other
+ * bodies. */
+int rpy_wall_lanczos_sqrt_periodic(const double* pos, const double* W, double* out, int64_t N, double a, double eta,
+                                   double Lx, double Ly, const int64_t* body_offsets, int32_t n_bodies, double tol,
+                                   int32_t max_iter, int precision, void* ws, size_t ws_bytes, int32_t* iters_out,
+                                   double* err_est_out, void* stream);
 
 /* Mobility problem of rigid multiblobs (Sec. II.A, saddle-point system):
  *     M lambda - K U = -slip,    -K^T lambda = -F,
@@ -135,6 +158,15 @@ int rpy_wall_rigid_solve(const double* pos, const double* q, const int64_t* body
                          const double* slip, const double* force_torque, double* lambda, double* U, int64_t N,
                          double a, double eta, double tol, int32_t max_iter, int precision, void* ws,
                          size_t ws_bytes, int32_t* iters_out, double* res_out, void* stream);
+
+/* rpy_wall_rigid_solve with the pseudo-periodic mobility of
+ * rpy_wall_matvec_periodic (cell Lx x Ly); the preconditioner as for
+ * rpy_wall_lanczos_sqrt_periodic. */
+int rpy_wall_rigid_solve_periodic(const double* pos, const double* q, const int64_t* body_offsets, int32_t n_bodies,
+                                  const double* slip, const double* force_torque, double* lambda, double* U,
+                                  int64_t N, double a, double eta, double Lx, double Ly, double tol,
+                                  int32_t max_iter, int precision, void* ws, size_t ws_bytes, int32_t* iters_out,
+                                  double* res_out, void* stream);
 
 /* Vector-Jacobian product of u = M(r) f for L = sum_i g_i . u_i
  * (derivatives of M drive the thermal drift, Sec. III):

@@ -177,6 +177,19 @@ int rpy_wall_matvec_multi(const double* pos, const double* F, double* U, int64_t
     return products(pos, F, U, N, k, a, eta, precision, s.ar, st);
 }
 
+int rpy_wall_matvec_periodic(const double* pos, const double* F, double* U, int64_t N, int32_t k, double a,
+                             double eta, double Lx, double Ly, int precision, void* ws, size_t ws_bytes,
+                             void* stream) {
+    if (!pos || !F || !U || N < 1 || N >= kMaxN || k < 1 || k > 4096 || !finite_pos(a) || !finite_pos(eta) ||
+        !finite_pos(Lx) || !finite_pos(Ly) || !valid_prec(precision))
+        return RPYW_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    Scratch s;
+    int rc = acquire(ws, ws_bytes, product_ws_bytes(N, precision, 1), st, s);
+    if (rc != RPYW_OK) return rc;
+    return products(pos, F, U, N, k, a, eta, precision, s.ar, st, Domain{Lx, Ly});
+}
+
 int rpy_wall_matvec(const double* pos, const double* force, double* vel, int64_t N, double a, double eta,
                     int precision, void* ws, size_t ws_bytes, void* stream) {
     return rpy_wall_matvec_multi(pos, force, vel, N, 1, a, eta, precision, ws, ws_bytes, stream);
@@ -200,10 +213,10 @@ int rpy_wall_matvec_batched(const double* pos, const int64_t* sys_offsets, int32
     return batched_products(pos, sys_offsets, S, F, U, k, a, eta, precision, s.ar, st);
 }
 
-int rpy_wall_lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, double a, double eta,
-                          const int64_t* body_offsets, int32_t n_bodies, double tol, int32_t max_iter,
-                          int precision, void* ws, size_t ws_bytes, int32_t* iters_out, double* err_est_out,
-                          void* stream) {
+static int lanczos_api(const double* pos, const double* W, double* out, int64_t N, double a, double eta,
+                       const int64_t* body_offsets, int32_t n_bodies, double tol, int32_t max_iter, int precision,
+                       void* ws, size_t ws_bytes, int32_t* iters_out, double* err_est_out, void* stream,
+                       const Domain& dom) {
     if (!pos || !W || !out || N < 1 || N >= kMaxN || !finite_pos(a) || !finite_pos(eta) || !valid_prec(precision) ||
         !finite_pos(tol) || max_iter < 1 || max_iter > 100000)
         return RPYW_EINVAL;
@@ -222,16 +235,34 @@ int rpy_wall_lanczos_sqrt(const double* pos, const double* W, double* out, int64
     if (rc != RPYW_OK) return rc;
     int it = 0;
     double err = 0.0;
-    rc = lanczos_sqrt(pos, W, out, N, a, eta, body_offsets, n_bodies, tol, max_iter, precision, s.ar, &it, &err, st);
+    rc = lanczos_sqrt(pos, W, out, N, a, eta, body_offsets, n_bodies, tol, max_iter, precision, s.ar, &it, &err, st,
+                      dom);
     if (iters_out) *iters_out = it;
     if (err_est_out) *err_est_out = err;
     return rc;
 }
 
-int rpy_wall_rigid_solve(const double* pos, const double* q, const int64_t* body_offsets, int32_t n_bodies,
-                         const double* slip, const double* force_torque, double* lambda, double* U, int64_t N,
-                         double a, double eta, double tol, int32_t max_iter, int precision, void* ws,
-                         size_t ws_bytes, int32_t* iters_out, double* res_out, void* stream) {
+int rpy_wall_lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, double a, double eta,
+                          const int64_t* body_offsets, int32_t n_bodies, double tol, int32_t max_iter,
+                          int precision, void* ws, size_t ws_bytes, int32_t* iters_out, double* err_est_out,
+                          void* stream) {
+    return lanczos_api(pos, W, out, N, a, eta, body_offsets, n_bodies, tol, max_iter, precision, ws, ws_bytes,
+                       iters_out, err_est_out, stream, Domain{});
+}
+
+int rpy_wall_lanczos_sqrt_periodic(const double* pos, const double* W, double* out, int64_t N, double a, double eta,
+                                   double Lx, double Ly, const int64_t* body_offsets, int32_t n_bodies, double tol,
+                                   int32_t max_iter, int precision, void* ws, size_t ws_bytes, int32_t* iters_out,
+                                   double* err_est_out, void* stream) {
+    if (!finite_pos(Lx) || !finite_pos(Ly)) return RPYW_EINVAL;
+    return lanczos_api(pos, W, out, N, a, eta, body_offsets, n_bodies, tol, max_iter, precision, ws, ws_bytes,
+                       iters_out, err_est_out, stream, Domain{Lx, Ly});
+}
+
+static int rigid_api(const double* pos, const double* q, const int64_t* body_offsets, int32_t n_bodies,
+                     const double* slip, const double* force_torque, double* lambda, double* U, int64_t N, double a,
+                     double eta, double tol, int32_t max_iter, int precision, void* ws, size_t ws_bytes,
+                     int32_t* iters_out, double* res_out, void* stream, const Domain& dom) {
     if (!pos || !q || !body_offsets || !lambda || !U || N < 1 || N >= kMaxN || n_bodies < 1 || !finite_pos(a) ||
         !finite_pos(eta) || !valid_prec(precision) || !finite_pos(tol) || max_iter < 1 || max_iter > 100000)
         return RPYW_EINVAL;
@@ -247,10 +278,28 @@ int rpy_wall_rigid_solve(const double* pos, const double* q, const int64_t* body
     int it = 0;
     double res = 0.0;
     rc = rigid_solve(pos, q, body_offsets, n_bodies, slip, force_torque, lambda, U, N, a, eta, tol, max_iter,
-                     precision, s.ar, &it, &res, st);
+                     precision, s.ar, &it, &res, st, dom);
     if (iters_out) *iters_out = it;
     if (res_out) *res_out = res;
     return rc;
+}
+
+int rpy_wall_rigid_solve(const double* pos, const double* q, const int64_t* body_offsets, int32_t n_bodies,
+                         const double* slip, const double* force_torque, double* lambda, double* U, int64_t N,
+                         double a, double eta, double tol, int32_t max_iter, int precision, void* ws,
+                         size_t ws_bytes, int32_t* iters_out, double* res_out, void* stream) {
+    return rigid_api(pos, q, body_offsets, n_bodies, slip, force_torque, lambda, U, N, a, eta, tol, max_iter,
+                     precision, ws, ws_bytes, iters_out, res_out, stream, Domain{});
+}
+
+int rpy_wall_rigid_solve_periodic(const double* pos, const double* q, const int64_t* body_offsets, int32_t n_bodies,
+                                  const double* slip, const double* force_torque, double* lambda, double* U,
+                                  int64_t N, double a, double eta, double Lx, double Ly, double tol,
+                                  int32_t max_iter, int precision, void* ws, size_t ws_bytes, int32_t* iters_out,
+                                  double* res_out, void* stream) {
+    if (!finite_pos(Lx) || !finite_pos(Ly)) return RPYW_EINVAL;
+    return rigid_api(pos, q, body_offsets, n_bodies, slip, force_torque, lambda, U, N, a, eta, tol, max_iter,
+                     precision, ws, ws_bytes, iters_out, res_out, stream, Domain{Lx, Ly});
 }
 
 int rpy_wall_matvec_vjp(const double* pos, const double* force, const double* grad_vel, double* grad_pos,

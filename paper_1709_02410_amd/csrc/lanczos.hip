@@ -139,7 +139,7 @@ size_t lanczos_ws_bytes(int64_t N, int max_iter, int n_bodies, int prec) {
 
 int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, double a, double eta,
                  const int64_t* body_offsets, int n_bodies, double tol, int max_iter, int prec, Arena& ar, int* iters,
-                 double* err, hipStream_t st) {
+                 double* err, hipStream_t st, const Domain& dom) {
     const int64_t n3 = 3 * N;
     *iters = 0;
     *err = 0.0;
@@ -199,7 +199,7 @@ int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, dou
         else
             r = pc.apply(2, w, x, n3, st, d_ab + 2 * (k - 1) + 1, vk);  // v_k = w / beta_{k-1}
         if (r) return r;
-        if ((r = products(pos, x, y, N, 1, a, eta, prec, ar, st))) return r;  // y = M x
+        if ((r = products(pos, x, y, N, 1, a, eta, prec, ar, st, dom))) return r;  // y = M x
         if ((r = pc.apply(1, y, w, n3, st))) return r;                        // w = L^-1 y
         // w -= beta_{k-1} v_{k-1}; full reorthogonalisation in two passes,
         // alpha_k = v_k . w from the first

@@ -200,15 +200,18 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(const R* __restrict__ r
 // accumulates M_ij f_j, the source side M_ji f_i, which is the same block
 // applied with the two off-diagonal wall coefficients exchanged.
 
-template <typename R, int K>
+template <typename R, int K, bool PER = false>
 struct ProductBody {
     static constexpr int KREC = K;
     static constexpr int NQ = 3 * K;
+    static constexpr int kUnroll = PER ? 1 : 4;
+    // One source image: target side into acc and, when SYM, source side
+    // (transposed block: the two off-diagonal wall coefficients exchanged)
+    // into src.
     template <bool SYM>
-    __device__ static void pair(const SymTarget<R, K>& t, const R* r, R (&acc)[NQ], R (&src)[NQ]) {
+    __device__ static void image(const SymTarget<R, K>& t, const R* r, R dx, R dy, R dz, R (&acc)[NQ],
+                                 R (&src)[NQ]) {
         constexpr int PW = pos_slots<R>();
-        R dx, dy, dz;
-        sym_diff(t, r, dx, dy, dz);
         PairCoef<R> p = pair_coef<R>(dx, dy, dz, t.z, r[2]);
 #pragma unroll
         for (int k = 0; k < K; ++k)
@@ -219,11 +222,37 @@ struct ProductBody {
             p.kcp = p.kcm;
             p.kcm = x;
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                src[3 * k] = src[3 * k + 1] = src[3 * k + 2] = R(0);
+            for (int k = 0; k < K; ++k)
                 pair_apply<R>(p, dx, dy, dz, t.f[k][0], t.f[k][1], t.f[k][2], src[3 * k], src[3 * k + 1],
                               src[3 * k + 2]);
-            }
+        }
+    }
+    template <bool SYM>
+    __device__ static void pair(const SymTarget<R, K>& t, const R* r, R (&acc)[NQ], R (&src)[NQ],
+                                const Box<R>& box) {
+        R dx, dy, dz;
+        sym_diff(t, r, dx, dy, dz);
+        if constexpr (SYM) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) src[q] = R(0);
+        }
+        if constexpr (!PER) {
+            image<SYM>(t, r, dx, dy, dz, acc, src);
+        } else {
+            // Pseudo-periodic domain: the source's minimum image (records
+            // are wrapped into the cell, so the shift is 0 or one cell) and
+            // the 8 periodic images around it.
+            const R nx = rint_(dx * box.ilx), ny = rint_(dy * box.ily);
+            dx = fma_(-nx, box.lxl, fma_(-nx, box.lxh, dx));
+            dy = fma_(-ny, box.lyl, fma_(-ny, box.lyh, dy));
+#pragma unroll
+            for (int sx = -1; sx <= 1; ++sx)
+#pragma unroll
+                for (int sy = -1; sy <= 1; ++sy) {
+                    const R ex = sx == 0 ? dx : sx < 0 ? dx - box.lx : dx + box.lx;
+                    const R ey = sy == 0 ? dy : sy < 0 ? dy - box.ly : dy + box.ly;
+                    image<SYM>(t, r, ex, ey, dz, acc, src);
+                }
         }
     }
 };
@@ -240,11 +269,34 @@ __global__ void sym_epilogue(const double* __restrict__ tpart, const R* __restri
     U[((int64_t)(q / 3) * N + i) * 3 + q % 3] = mu0 * B[i] * s;
 }
 
-template <typename R, int K>
-hipError_t launch_sym_t(const R* rec, int ng, int C, int ipw, int Hmax, double* tpart, R* spart, hipStream_t st) {
-    hipLaunchKernelGGL((sym_kernel<R, ProductBody<R, K>>), dim3((unsigned)(ng * C)), dim3(kBlock), 0, st, rec, ng, C,
-                       ipw, Hmax, tpart, spart);
+template <typename R, int K, bool PER>
+hipError_t launch_sym_t(const R* rec, int ng, int C, int ipw, int Hmax, double* tpart, R* spart, const Box<R>& box,
+                        hipStream_t st) {
+    hipLaunchKernelGGL((sym_kernel<R, ProductBody<R, K, PER>>), dim3((unsigned)(ng * C)), dim3(kBlock), 0, st, rec,
+                       ng, C, ipw, Hmax, tpart, spart, box);
     return hipGetLastError();
+}
+
+// Kernel-side cell description in units of a (zeros for the open domain).
+template <typename R>
+Box<R> make_box(const Domain& dom, double a) {
+    Box<R> b{};
+    if (!dom.periodic()) return b;
+    auto split = [](double L, R& hi, R& lo) {
+        int e;
+        std::frexp(L, &e);
+        const double h = std::ldexp(std::nearbyint(std::ldexp(L, 12 - e)), e - 12);  // 12 significant bits
+        hi = (R)h;
+        lo = (R)(L - h);
+    };
+    const double lx = dom.lx / a, ly = dom.ly / a;
+    b.lx = (R)lx;
+    b.ly = (R)ly;
+    split(lx, b.lxh, b.lxl);
+    split(ly, b.lyh, b.lyl);
+    b.ilx = (R)(1.0 / lx);
+    b.ily = (R)(1.0 / ly);
+    return b;
 }
 
 __global__ void zero_u32(unsigned* p) { *p = 0u; }
@@ -369,7 +421,7 @@ size_t product_ws_bytes(int64_t N, int prec, int kblk) {
 namespace {
 
 int sym_pass(const double* pos, const double* F, double* U, int64_t N, int kb, int K, double a, double eta, int prec,
-             const SymPlan& sp, int ipw, Arena& ar, hipStream_t st) {
+             const SymPlan& sp, int ipw, Arena& ar, hipStream_t st, const Domain& dom = Domain{}) {
     const size_t mark = ar.used;
     const int rw = rec_width(prec, K);
     const int64_t npad = (int64_t)sp.ng * 256;
@@ -385,11 +437,11 @@ int sym_pass(const double* pos, const double* F, double* U, int64_t N, int kb, i
     const unsigned gp = (unsigned)((npad - N + kBlock - 1) / kBlock);
     if (prec == RPYW_FP32C) {
         hipLaunchKernelGGL(pack_kernel<float>, dim3(g1), dim3(kBlock), 0, st, pos, F, N, kb, rw, 1.0 / a, (float*)rec, B,
-                           nullptr);
+                           nullptr, dom.lx / a, dom.ly / a);
         if (gp) hipLaunchKernelGGL(pad_kernel<float>, dim3(gp), dim3(kBlock), 0, st, (float*)rec, N, npad, rw, B);
     } else {
         hipLaunchKernelGGL(pack_kernel<double>, dim3(g1), dim3(kBlock), 0, st, pos, F, N, kb, rw, 1.0 / a,
-                           (double*)rec, B, nullptr);
+                           (double*)rec, B, nullptr, dom.lx / a, dom.ly / a);
         if (gp) hipLaunchKernelGGL(pad_kernel<double>, dim3(gp), dim3(kBlock), 0, st, (double*)rec, N, npad, rw, B);
     }
     RPYW_HIP(hipGetLastError());
@@ -399,7 +451,13 @@ int sym_pass(const double* pos, const double* F, double* U, int64_t N, int kb, i
     auto go = [&](auto Rt, auto Kc) -> hipError_t {
         using R = decltype(Rt);
         constexpr int KK = decltype(Kc)::value;
-        return launch_sym_t<R, KK>((const R*)rec, sp.ng, sp.C, ipw, sp.Hmax, tpart, (R*)spart, st);
+        if (dom.periodic()) {
+            if constexpr (KK == 1)
+                return launch_sym_t<R, 1, true>((const R*)rec, sp.ng, sp.C, ipw, sp.Hmax, tpart, (R*)spart,
+                                                make_box<R>(dom, a), st);
+            return hipErrorInvalidValue;
+        }
+        return launch_sym_t<R, KK, false>((const R*)rec, sp.ng, sp.C, ipw, sp.Hmax, tpart, (R*)spart, Box<R>{}, st);
     };
     if (prec == RPYW_FP32C)
         e = K == 1 ? go(0.f, std::integral_constant<int, 1>{})
@@ -408,7 +466,7 @@ int sym_pass(const double* pos, const double* F, double* U, int64_t N, int kb, i
         e = K == 1 ? go(0.0, std::integral_constant<int, 1>{})
                    : K == 2 ? go(0.0, std::integral_constant<int, 2>{}) : go(0.0, std::integral_constant<int, 4>{});
     if (e != hipSuccess) return RPYW_EHIP;
-    profile_end(st, ev, (double)kb * (double)N * (double)N);
+    profile_end(st, ev, (dom.periodic() ? 9.0 : 1.0) * (double)kb * (double)N * (double)N);
     const double m0 = mu0_of(a, eta);
     const dim3 ge(g1, (unsigned)(3 * kb));
     if (prec == RPYW_FP32C)
@@ -448,10 +506,10 @@ int product_pass(const double* pos, const double* F, double* U, int64_t N, int k
     const unsigned g1 = (unsigned)((N + kBlock - 1) / kBlock);
     if (prec == RPYW_FP32C)
         hipLaunchKernelGGL(pack_kernel<float>, dim3(g1), dim3(kBlock), 0, st, pos, F, N, kb, rw, 1.0 / a, (float*)rec,
-                           B, nullptr);
+                           B, nullptr, 0.0, 0.0);
     else
         hipLaunchKernelGGL(pack_kernel<double>, dim3(g1), dim3(kBlock), 0, st, pos, F, N, kb, rw, 1.0 / a,
-                           (double*)rec, B, nullptr);
+                           (double*)rec, B, nullptr, 0.0, 0.0);
     RPYW_HIP(hipGetLastError());
     const int64_t ntb = (N + (int64_t)kBlock * sh.tpl - 1) / ((int64_t)kBlock * sh.tpl);
     const int64_t nblocks = ntb * splits;
@@ -473,7 +531,17 @@ int product_pass(const double* pos, const double* F, double* U, int64_t N, int k
 }
 
 int products(const double* pos, const double* F, double* U, int64_t N, int k, double a, double eta, int prec,
-             Arena& ar, hipStream_t st) {
+             Arena& ar, hipStream_t st, const Domain& dom) {
+    if (dom.periodic()) {
+        const SymPlan sp = sym_plan(N, prec, 1, tuned_shape(N, 1, prec).ipw);
+        if (!sp.ok) return RPYW_ENOMEM;
+        for (int k0 = 0; k0 < k; ++k0) {
+            const int rc = sym_pass(pos, F + (size_t)k0 * N * 3, U + (size_t)k0 * N * 3, N, 1, 1, a, eta, prec, sp,
+                                    tuned_shape(N, 1, prec).ipw, ar, st, dom);
+            if (rc != RPYW_OK) return rc;
+        }
+        return RPYW_OK;
+    }
     const Shape sh = tuned_shape(N, k, prec);
     for (int k0 = 0; k0 < k; k0 += sh.kblk) {
         const int kb = std::min(sh.kblk, k - k0);
@@ -576,10 +644,10 @@ int batched_products(const double* pos, const int64_t* sys_offsets, int S, const
         double* Uk = U + (size_t)k0 * Ntot * 3;
         if (prec == RPYW_FP32C)
             hipLaunchKernelGGL(pack_kernel<float>, dim3(g1), dim3(kBlock), 0, st, pos, Fk, Ntot, kb, rw, 1.0 / a,
-                               (float*)rec, B, nullptr);
+                               (float*)rec, B, nullptr, 0.0, 0.0);
         else
             hipLaunchKernelGGL(pack_kernel<double>, dim3(g1), dim3(kBlock), 0, st, pos, Fk, Ntot, kb, rw, 1.0 / a,
-                               (double*)rec, B, nullptr);
+                               (double*)rec, B, nullptr, 0.0, 0.0);
         RPYW_HIP(hipGetLastError());
         hipLaunchKernelGGL(zero_u32, dim3(1), dim3(1), 0, st, counter);
         RPYW_HIP(hipGetLastError());

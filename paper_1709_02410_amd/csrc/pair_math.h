@@ -35,6 +35,10 @@ namespace rpyw {
 __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// Round to the nearest integer, ties to even.
+__device__ __forceinline__ float rint_(float x) { return __builtin_rintf(x); }
+__device__ __forceinline__ double rint_(double x) { return __builtin_rint(x); }
+
 template <typename R>
 __device__ __forceinline__ R rsq(R x);
 

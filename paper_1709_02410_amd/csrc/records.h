@@ -20,14 +20,21 @@ constexpr int rec_w() {
 }
 
 // Records for blobs [0, N).  RHS k is read from F + k N 3 ([kb][N][3]);
-// when F2 is given (kb = 2) the second RHS is read from F2 instead.
+// when F2 is given (kb = 2) the second RHS is read from F2 instead.  With a
+// periodic cell (lx, ly > 0, units of a) x and y are wrapped into [0, lx) and
+// [0, ly) first, in FP64, so that differences stay below one cell length.
 template <typename R>
 __global__ void pack_kernel(const double* __restrict__ pos, const double* __restrict__ F, int64_t N, int kb,
                             int recw, double inv_a, R* __restrict__ rec, double* __restrict__ Bout,
-                            const double* __restrict__ F2) {
+                            const double* __restrict__ F2, double lx, double ly) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    const double x = pos[3 * i] * inv_a, y = pos[3 * i + 1] * inv_a, z = pos[3 * i + 2] * inv_a;
+    double x = pos[3 * i] * inv_a, y = pos[3 * i + 1] * inv_a;
+    const double z = pos[3 * i + 2] * inv_a;
+    if (lx > 0.0) {
+        x -= lx * floor(x / lx);
+        y -= ly * floor(y / ly);
+    }
     const double B = z < 1.0 ? z : 1.0;
     const double zt = z < 1.0 ? 1.0 : z;
     R* r = rec + i * recw;

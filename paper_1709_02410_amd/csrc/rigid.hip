@@ -265,7 +265,7 @@ size_t rigid_ws_bytes(int64_t N, int max_iter, int n_bodies, int prec) {
 
 int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets, int n_bodies, const double* slip,
                 const double* FT, double* lam_out, double* U_out, int64_t N, double a, double eta, double tol,
-                int max_iter, int prec, Arena& ar, int* iters, double* res_out, hipStream_t st) {
+                int max_iter, int prec, Arena& ar, int* iters, double* res_out, hipStream_t st, const Domain& dom) {
     const int64_t n3 = 3 * N, n6 = 6 * (int64_t)n_bodies, n = n3 + n6;
     *iters = 0;
     *res_out = 0.0;
@@ -333,7 +333,7 @@ int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets,
         double* vk = V + (size_t)k * n;
         int r;
         if ((r = precond(k == 0 ? bv : w, d_hn + k, vk, z, z + n3))) return r;
-        if ((r = products(pos, z, y, N, 1, a, eta, prec, ar, st))) return r;
+        if ((r = products(pos, z, y, N, 1, a, eta, prec, ar, st, dom))) return r;
         hipLaunchKernelGGL(rigid_apply_kernel, dim3(n_bodies), dim3(kRT), 0, st, pos, q, pc.bofs, z, z + n3, y, w,
                            w + n3);
         RPYW_HIP(hipGetLastError());

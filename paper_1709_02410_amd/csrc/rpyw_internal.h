@@ -26,6 +26,14 @@ struct Shape {
     int ipw;   // symmetric path: source groups per workgroup
 };
 
+// Domain along the wall: open (lx = ly = 0) or the pseudo-periodic cell
+// lx x ly (physical units): every source at its minimum image plus the 8
+// periodic images around it.
+struct Domain {
+    double lx = 0.0, ly = 0.0;
+    bool periodic() const { return lx > 0.0; }
+};
+
 // Symmetric path geometry for N blobs, K right-hand sides.
 struct SymPlan {
     int ng, Hmax, C;
@@ -66,9 +74,10 @@ size_t product_ws_bytes(int64_t N, int prec, int kblk);
 int product_pass(const double* pos, const double* F, double* U, int64_t N, int kb, double a, double eta, int prec,
                  Shape shape, Arena& ar, hipStream_t st);
 
-// Full multi-RHS product with the tuned or default shape.
+// Full multi-RHS product with the tuned or default shape; in a periodic
+// domain one right-hand side at a time through the symmetric kernel.
 int products(const double* pos, const double* F, double* U, int64_t N, int k, double a, double eta, int prec,
-             Arena& ar, hipStream_t st);
+             Arena& ar, hipStream_t st, const Domain& dom = Domain{});
 
 // Batched independent systems (persistent kernel, LPT work list).
 size_t batched_ws_bytes(int64_t Ntot, int S, int k, int prec);
@@ -134,14 +143,15 @@ struct PinnedSlots {
 size_t lanczos_ws_bytes(int64_t N, int max_iter, int n_bodies, int prec);
 int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, double a, double eta,
                  const int64_t* body_offsets, int n_bodies, double tol, int max_iter, int prec, Arena& ar,
-                 int* iters, double* err, hipStream_t st);
+                 int* iters, double* err, hipStream_t st, const Domain& dom = Domain{});
 int tridiag_sqrt_coeffs(const double* alpha, const double* beta, int k, double beta0, double* c);
 
 // Rigid multiblobs (rigid.hip)
 size_t rigid_ws_bytes(int64_t N, int max_iter, int n_bodies, int prec);
 int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets, int n_bodies, const double* slip,
                 const double* FT, double* lam_out, double* U_out, int64_t N, double a, double eta, double tol,
-                int max_iter, int prec, Arena& ar, int* iters, double* res_out, hipStream_t st);
+                int max_iter, int prec, Arena& ar, int* iters, double* res_out, hipStream_t st,
+                const Domain& dom = Domain{});
 
 // Derivatives (vjp.hip)
 size_t vjp_ws_bytes(int64_t N, int prec);

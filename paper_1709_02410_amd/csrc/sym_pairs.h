@@ -30,9 +30,11 @@
 // bitwise reproducible.
 //
 // A Body supplies the per-pair arithmetic: KREC right-hand sides in the
-// record, NQ accumulated quantities, and
+// record, NQ accumulated quantities, the unroll factor of the 64-step loop,
+// and
 //   template <bool SYM> static void pair(const SymTarget&, const R* rec,
-//                                        R (&acc)[NQ], R (&src)[NQ]);
+//                                        R (&acc)[NQ], R (&src)[NQ],
+//                                        const Box<R>&);
 // which adds the target-side contribution to acc and, when SYM, writes the
 // source-side contribution to src.
 #pragma once
@@ -47,6 +49,15 @@
 namespace rpyw {
 
 constexpr int kSymBlock = 256;
+
+// Pseudo-periodic cell along the wall, units of a: lengths, the lengths
+// split into a high part with 12 significant bits (small integer multiples
+// of it are exact) plus the rest, and the inverse lengths.  Unused by bodies
+// for the open domain.
+template <typename R>
+struct Box {
+    R lx, ly, lxh, lxl, lyh, lyl, ilx, ily;
+};
 
 // Number of source-group offsets d > 0 that row P owns (ng groups).
 __host__ __device__ inline int sym_rowlen(int P, int ng) {
@@ -146,13 +157,14 @@ struct SymLane {
     // into the add), so that after the pass lane l holds source l's sum
     // (sa == nullptr), or to LDS sa[q * 128 + l + s] by an atomic add.
     template <bool SYM>
-    __device__ void pass(const typename Vec<R>::T* __restrict__ tile, int blk, int l, R* sa, R (&S)[NQ]) {
+    __device__ void pass(const typename Vec<R>::T* __restrict__ tile, int blk, int l, R* sa, R (&S)[NQ],
+                         const Box<R>& box) {
         using VT = typename Vec<R>::T;
         const VT* base = tile + blk * 128 + l;
         R* sl = sa + l;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) S[q] = R(0);
-#pragma unroll 4
+#pragma unroll Body::kUnroll
         for (int s = 0; s < 64; ++s) {
             R r[RW];
 #pragma unroll
@@ -162,7 +174,7 @@ struct SymLane {
                 for (int e = 0; e < Vec<R>::W; ++e) r[v * Vec<R>::W + e] = Vec<R>::get(q, e);
             }
             R c[NQ];
-            Body::template pair<SYM>(t, r, acc, c);
+            Body::template pair<SYM>(t, r, acc, c, box);
             if constexpr (SYM) {
                 if (sa) {
 #pragma unroll
@@ -208,7 +220,8 @@ struct SymLane {
 // tpart: [ng * C][NQ][256] doubles; spart: [ng * (Hmax + 1)][NQ][256].
 template <typename R, class Body>
 __global__ __launch_bounds__(kSymBlock) void sym_kernel(const R* __restrict__ rec, int ng, int C, int ipw, int Hmax,
-                                                        double* __restrict__ tpart, R* __restrict__ spart) {
+                                                        double* __restrict__ tpart, R* __restrict__ spart,
+                                                        Box<R> box) {
     using L = SymLane<R, Body>;
     using VT = typename Vec<R>::T;
     constexpr int NQ = L::NQ;
@@ -252,9 +265,9 @@ __global__ __launch_bounds__(kSymBlock) void sym_kernel(const R* __restrict__ re
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) S[q] = R(0);
             } else if (d == 0 && blk == w) {
-                me.template pass<false>(tile, blk, l, nullptr, S);
+                me.template pass<false>(tile, blk, l, nullptr, S, box);
             } else {
-                me.template pass<true>(tile, blk, l, kLds ? &sacc[blk][0][0] : nullptr, S);
+                me.template pass<true>(tile, blk, l, kLds ? &sacc[blk][0][0] : nullptr, S, box);
             }
             if constexpr (kLds) {
                 __syncthreads();  // one wave per source block in every phase

@@ -122,8 +122,9 @@ template <typename R>
 struct VjpBody {
     static constexpr int KREC = 2;  // F~, G~
     static constexpr int NQ = kQ;   // grad (3), Mhat F~ (3), Mhat G~ (3)
+    static constexpr int kUnroll = 4;
     template <bool SYM>
-    __device__ static void pair(const SymTarget<R, 2>& t, const R* r, R (&acc)[kQ], R (&src)[kQ]) {
+    __device__ static void pair(const SymTarget<R, 2>& t, const R* r, R (&acc)[kQ], R (&src)[kQ], const Box<R>&) {
         constexpr int PW = pos_slots<R>();
         R dx, dy, dz;
         sym_diff(t, r, dx, dy, dz);
@@ -277,25 +278,25 @@ int vjp(const double* pos, const double* f, const double* g, double* grad_pos, d
         hipEvent_t ev = nullptr;
         if (prec == RPYW_FP32C) {
             hipLaunchKernelGGL(pack_kernel<float>, dim3(g1), dim3(kBlock), 0, st, pos, f, N, 2, rw, 1.0 / a,
-                               (float*)rec, B, g);
+                               (float*)rec, B, g, 0.0, 0.0);
             if (gp) hipLaunchKernelGGL(pad_kernel<float>, dim3(gp), dim3(kBlock), 0, st, (float*)rec, N, npad, rw, B);
             RPYW_HIP(hipGetLastError());
             profile_begin(st, &ev);
             hipLaunchKernelGGL((sym_kernel<float, VjpBody<float>>), dim3((unsigned)(ng * C)), dim3(kBlock), 0, st,
-                               (const float*)rec, ng, C, ipw, Hmax, tpart, (float*)spart);
+                               (const float*)rec, ng, C, ipw, Hmax, tpart, (float*)spart, Box<float>{});
             RPYW_HIP(hipGetLastError());
             profile_end(st, ev, (double)N * (double)N);
             hipLaunchKernelGGL(sym_vjp_epilogue<float>, dim3(g1), dim3(kBlock), 0, st, tpart, (const float*)spart, pos,
                                f, g, N, ng, C, Hmax, 1.0 / a, m0, grad_pos, grad_f);
         } else {
             hipLaunchKernelGGL(pack_kernel<double>, dim3(g1), dim3(kBlock), 0, st, pos, f, N, 2, rw, 1.0 / a,
-                               (double*)rec, B, g);
+                               (double*)rec, B, g, 0.0, 0.0);
             if (gp)
                 hipLaunchKernelGGL(pad_kernel<double>, dim3(gp), dim3(kBlock), 0, st, (double*)rec, N, npad, rw, B);
             RPYW_HIP(hipGetLastError());
             profile_begin(st, &ev);
             hipLaunchKernelGGL((sym_kernel<double, VjpBody<double>>), dim3((unsigned)(ng * C)), dim3(kBlock), 0, st,
-                               (const double*)rec, ng, C, ipw, Hmax, tpart, (double*)spart);
+                               (const double*)rec, ng, C, ipw, Hmax, tpart, (double*)spart, Box<double>{});
             RPYW_HIP(hipGetLastError());
             profile_end(st, ev, (double)N * (double)N);
             hipLaunchKernelGGL(sym_vjp_epilogue<double>, dim3(g1), dim3(kBlock), 0, st, tpart, (const double*)spart,
@@ -319,14 +320,14 @@ int vjp(const double* pos, const double* f, const double* g, double* grad_pos, d
     hipEvent_t ev = nullptr;
     if (prec == RPYW_FP32C) {
         hipLaunchKernelGGL(pack_kernel<float>, dim3(g1), dim3(kBlock), 0, st, pos, f, N, 2, rw, 1.0 / a, (float*)rec, B,
-                           g);
+                           g, 0.0, 0.0);
         RPYW_HIP(hipGetLastError());
         profile_begin(st, &ev);
         hipLaunchKernelGGL((vjp_kernel<float, 256>), dim3((unsigned)nblocks), dim3(kBlock), 0, st, (const float*)rec,
                            N, splits, chunk, part);
     } else {
         hipLaunchKernelGGL(pack_kernel<double>, dim3(g1), dim3(kBlock), 0, st, pos, f, N, 2, rw, 1.0 / a,
-                           (double*)rec, B, g);
+                           (double*)rec, B, g, 0.0, 0.0);
         RPYW_HIP(hipGetLastError());
         profile_begin(st, &ev);
         hipLaunchKernelGGL((vjp_kernel<double, 128>), dim3((unsigned)nblocks), dim3(kBlock), 0, st,

@@ -45,6 +45,11 @@ def lib():
     sig = {
         "rpy_wall_matvec": [vp, vp, vp, i64, dbl, dbl, ctypes.c_int, vp, sz, vp],
         "rpy_wall_matvec_multi": [vp, vp, vp, i64, i32, dbl, dbl, ctypes.c_int, vp, sz, vp],
+        "rpy_wall_matvec_periodic": [vp, vp, vp, i64, i32, dbl, dbl, dbl, dbl, ctypes.c_int, vp, sz, vp],
+        "rpy_wall_lanczos_sqrt_periodic": [vp, vp, vp, i64, dbl, dbl, dbl, dbl, i64p, i32, dbl, i32, ctypes.c_int,
+                                           vp, sz, ctypes.POINTER(i32), ctypes.POINTER(dbl), vp],
+        "rpy_wall_rigid_solve_periodic": [vp, vp, i64p, i32, vp, vp, vp, vp, i64, dbl, dbl, dbl, dbl, dbl, i32,
+                                          ctypes.c_int, vp, sz, ctypes.POINTER(i32), ctypes.POINTER(dbl), vp],
         "rpy_wall_matvec_batched": [vp, i64p, i32, vp, vp, i32, dbl, dbl, ctypes.c_int, vp, sz, vp],
         "rpy_wall_lanczos_sqrt": [vp, vp, vp, i64, dbl, dbl, i64p, i32, dbl, i32, ctypes.c_int, vp, sz,
                                   ctypes.POINTER(i32), ctypes.POINTER(dbl), vp],
@@ -101,12 +106,15 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 
 def matvec(pos: torch.Tensor, force: torch.Tensor, a: float = 1.0, eta: float = 1.0,
-           precision: int = FP64, out: torch.Tensor | None = None) -> torch.Tensor:
-    """u = M(r) f for pos, force of shape (N, 3)."""
+           precision: int = FP64, out: torch.Tensor | None = None, box=None) -> torch.Tensor:
+    """u = M(r) f for pos, force of shape (N, 3).  box = (Lx, Ly): the
+    pseudo-periodic domain (minimum image plus 8 periodic images)."""
     N = pos.shape[0]
     _dev(pos, "pos", (N, 3))
     _dev(force, "force", (N, 3))
     out = torch.empty_like(force) if out is None else _dev(out, "out", (N, 3))
+    if box is not None:
+        return matvec_periodic(pos, force.view(1, N, 3), box, a, eta, precision, out.view(1, N, 3)).view(N, 3)
     ws = _workspace(workspace_bytes(OP_MATVEC, N, 1, precision=precision), pos.device)
     _check(lib().rpy_wall_matvec(pos.data_ptr(), force.data_ptr(), out.data_ptr(), N, a, eta, precision,
                                  ws.data_ptr(), ws.numel(), _stream(pos.device)), "rpy_wall_matvec")
@@ -133,6 +141,21 @@ def _offsets(offs) -> np.ndarray:
     return arr
 
 
+def matvec_periodic(pos: torch.Tensor, F: torch.Tensor, box, a: float = 1.0, eta: float = 1.0,
+                    precision: int = FP64, out: torch.Tensor | None = None) -> torch.Tensor:
+    """U[l] = M F[l] in the pseudo-periodic cell box = (Lx, Ly); F, out: (k, N, 3)."""
+    N = pos.shape[0]
+    k = F.shape[0]
+    _dev(pos, "pos", (N, 3))
+    _dev(F, "F", (k, N, 3))
+    out = torch.empty_like(F) if out is None else _dev(out, "out", (k, N, 3))
+    ws = _workspace(workspace_bytes(OP_MATVEC, N, 1, precision=precision), pos.device)
+    _check(lib().rpy_wall_matvec_periodic(pos.data_ptr(), F.data_ptr(), out.data_ptr(), N, k, a, eta,
+                                          float(box[0]), float(box[1]), precision, ws.data_ptr(), ws.numel(),
+                                          _stream(pos.device)), "rpy_wall_matvec_periodic")
+    return out
+
+
 def matvec_batched(pos: torch.Tensor, sys_offsets, F: torch.Tensor, a: float = 1.0, eta: float = 1.0,
                    precision: int = FP32C, out: torch.Tensor | None = None) -> torch.Tensor:
     """Independent systems in one persistent launch; F, out: (k, Ntot, 3)."""
@@ -152,7 +175,7 @@ def matvec_batched(pos: torch.Tensor, sys_offsets, F: torch.Tensor, a: float = 1
 
 def lanczos_sqrt(pos: torch.Tensor, W: torch.Tensor, a: float = 1.0, eta: float = 1.0, body_offsets=None,
                  tol: float = 1e-6, max_iter: int = 200, precision: int = FP64, out: torch.Tensor | None = None,
-                 strict: bool = False):
+                 strict: bool = False, box=None):
     """Brownian blob displacements S W with S S^T = M by preconditioned
     Lanczos.  Returns (out (N,3), iterations, last relative change,
     converged flag).  strict=True raises when max_iter is reached."""
@@ -169,16 +192,22 @@ def lanczos_sqrt(pos: torch.Tensor, W: torch.Tensor, a: float = 1.0, eta: float 
     ws = _workspace(workspace_bytes(OP_LANCZOS, N, 1, max_iter, nb, precision), pos.device)
     it = ctypes.c_int32(0)
     err = ctypes.c_double(0.0)
-    st = lib().rpy_wall_lanczos_sqrt(pos.data_ptr(), W.data_ptr(), out.data_ptr(), N, a, eta, offs_p, nb, tol,
-                                     max_iter, precision, ws.data_ptr(), ws.numel(), ctypes.byref(it),
-                                     ctypes.byref(err), _stream(pos.device))
+    if box is None:
+        st = lib().rpy_wall_lanczos_sqrt(pos.data_ptr(), W.data_ptr(), out.data_ptr(), N, a, eta, offs_p, nb, tol,
+                                         max_iter, precision, ws.data_ptr(), ws.numel(), ctypes.byref(it),
+                                         ctypes.byref(err), _stream(pos.device))
+    else:
+        st = lib().rpy_wall_lanczos_sqrt_periodic(pos.data_ptr(), W.data_ptr(), out.data_ptr(), N, a, eta,
+                                                  float(box[0]), float(box[1]), offs_p, nb, tol, max_iter,
+                                                  precision, ws.data_ptr(), ws.numel(), ctypes.byref(it),
+                                                  ctypes.byref(err), _stream(pos.device))
     _check(st, "rpy_wall_lanczos_sqrt", allow=(OK,) if strict else (OK, NOT_CONVERGED))
     return out, int(it.value), float(err.value), st == OK
 
 
 def rigid_solve(pos: torch.Tensor, q: torch.Tensor, body_offsets, slip: torch.Tensor | None = None,
                 force_torque: torch.Tensor | None = None, a: float = 1.0, eta: float = 1.0, tol: float = 1e-6,
-                max_iter: int = 200, precision: int = FP64, strict: bool = False):
+                max_iter: int = 200, precision: int = FP64, strict: bool = False, box=None):
     """Rigid-multiblob mobility problem M lambda - K U = -slip,
     -K^T lambda = -F by block-preconditioned GMRES.  pos (N,3), q (nb,3)
     reference points, body_offsets host int64 [nb+1], slip (N,3) or None,
@@ -198,11 +227,18 @@ def rigid_solve(pos: torch.Tensor, q: torch.Tensor, body_offsets, slip: torch.Te
     ws = _workspace(workspace_bytes(OP_RIGID, N, 1, max_iter, nb, precision), pos.device)
     it = ctypes.c_int32(0)
     res = ctypes.c_double(0.0)
-    st = lib().rpy_wall_rigid_solve(pos.data_ptr(), q.data_ptr(), offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                                    nb, slip.data_ptr() if slip is not None else None,
-                                    force_torque.data_ptr() if force_torque is not None else None, lam.data_ptr(),
-                                    U.data_ptr(), N, a, eta, tol, max_iter, precision, ws.data_ptr(), ws.numel(),
-                                    ctypes.byref(it), ctypes.byref(res), _stream(pos.device))
+    offs_p = offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    sp = slip.data_ptr() if slip is not None else None
+    fp = force_torque.data_ptr() if force_torque is not None else None
+    if box is None:
+        st = lib().rpy_wall_rigid_solve(pos.data_ptr(), q.data_ptr(), offs_p, nb, sp, fp, lam.data_ptr(),
+                                        U.data_ptr(), N, a, eta, tol, max_iter, precision, ws.data_ptr(), ws.numel(),
+                                        ctypes.byref(it), ctypes.byref(res), _stream(pos.device))
+    else:
+        st = lib().rpy_wall_rigid_solve_periodic(pos.data_ptr(), q.data_ptr(), offs_p, nb, sp, fp, lam.data_ptr(),
+                                                 U.data_ptr(), N, a, eta, float(box[0]), float(box[1]), tol,
+                                                 max_iter, precision, ws.data_ptr(), ws.numel(), ctypes.byref(it),
+                                                 ctypes.byref(res), _stream(pos.device))
     _check(st, "rpy_wall_rigid_solve", allow=(OK,) if strict else (OK, NOT_CONVERGED))
     return lam, U, int(it.value), float(res.value), st == OK
 

@@ -72,6 +72,14 @@ def test_validation_rejects_before_any_launch(lib):
     assert rig(offs, 2, 9, tol=0.0) == E
     assert rig(offs, 2, 9, it_=0) == E
     assert rig(bad_offs, 2, 5) == E     # empty body
+    nan = float("nan")
+    assert lib.rpy_wall_matvec_periodic(dummy, dummy, dummy, 10, 1, 1.0, 1.0, 0.0, 5.0, 0, None, 0, None) == E
+    assert lib.rpy_wall_matvec_periodic(dummy, dummy, dummy, 10, 1, 1.0, 1.0, 5.0, nan, 0, None, 0, None) == E
+    assert lib.rpy_wall_lanczos_sqrt_periodic(dummy, dummy, dummy, 10, 1.0, 1.0, -1.0, 5.0, None, 0, 1e-6, 50, 0,
+                                              None, 0, ctypes.byref(it), ctypes.byref(er), None) == E
+    assert lib.rpy_wall_rigid_solve_periodic(dummy, dummy, offs, 2, None, None, dummy, dummy, 9, 1.0, 1.0, 5.0,
+                                             float("inf"), 1e-6, 50, 0, None, 0, ctypes.byref(it),
+                                             ctypes.byref(er), None) == E
     # misaligned caller workspace
     assert lib.rpy_wall_matvec(dummy, dummy, dummy, 10, 1.0, 1.0, 0, ctypes.c_void_p(0x1001), 1 << 20,
                                None) == E
