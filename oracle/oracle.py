@@ -23,6 +23,9 @@ Contents (arXiv:1709.02410):
     solved densely, and N = (K^T M^-1 K)^-1.
   * ``rigid_gmres``: the same system by GMRES right-preconditioned with the
     per-body block-diagonal operator (Sec. II.B); used for iteration counts.
+  * ``quat_rotate``/``body_blobs``/``body_move``/``ts_step``: body kinematics
+    with unit quaternions (appendix on quaternions) and one step of the
+    Trapezoidal Slip scheme (Alg. 2) with dense solves.
   * ``box=(Lx, Ly)`` on the products, dense matrices, roots and solves: the
     pseudo-periodic domain of the paper's suspensions (Sec. V): each source
     at its minimum image plus the 8 periodic images around it.
@@ -469,3 +472,98 @@ def rigid_gmres(pos, q, body_offsets, slip=None, FT=None, a: float = 1.0, eta: f
         V[:, k] = w / H[k, k - 1]
     x = Pinv(V[:, :len(y)] @ y)
     return x[:3 * N].reshape(N, 3), x[3 * N:].reshape(nb, 6), k, res, converged
+
+
+# ------------------------------------------------------------- integrators
+
+def quat_mul(a, b) -> np.ndarray:
+    """Quaternion product of (s, p) quaternions, rows of (n, 4) arrays:
+    (s1 s2 - p1.p2, s1 p2 + s2 p1 + p1 x p2)."""
+    a, b = np.atleast_2d(a), np.atleast_2d(b)
+    s1, p1, s2, p2 = a[:, :1], a[:, 1:], b[:, :1], b[:, 1:]
+    return np.concatenate([s1 * s2 - (p1 * p2).sum(1, keepdims=True), s1 * p2 + s2 * p1 + np.cross(p1, p2)], 1)
+
+
+def quat_rotate(theta, phi) -> np.ndarray:
+    """Rotate(theta, phi) of the quaternion appendix: the orientation theta
+    (rows (s, p), unit norm) turned by the rotation vector phi (angle |phi|
+    about phi / |phi|), i.e. theta' = [cos(|phi|/2), sin(|phi|/2) phi/|phi|] theta."""
+    phi = np.atleast_2d(np.asarray(phi, dtype=np.float64))
+    ang = np.linalg.norm(phi, axis=1, keepdims=True)
+    axis = np.divide(phi, ang, out=np.zeros_like(phi), where=ang > 0)
+    r = np.concatenate([np.cos(0.5 * ang), np.sin(0.5 * ang) * axis], 1)
+    return quat_mul(r, theta)
+
+
+def quat_matrix(theta) -> np.ndarray:
+    """Rotation matrices (n, 3, 3) of unit quaternions (s, p):
+    R = (s^2 - p.p) I + 2 p p^T + 2 s [p]_x."""
+    theta = np.atleast_2d(theta)
+    s, p = theta[:, 0], theta[:, 1:]
+    R = (s * s - (p * p).sum(1))[:, None, None] * np.eye(3) + 2.0 * p[:, :, None] * p[:, None, :]
+    return R + 2.0 * s[:, None, None] * np.stack([_cross_matrix(v) for v in p])
+
+
+def body_blobs(q, theta, ref, body_offsets) -> np.ndarray:
+    """Blob positions r_i = q_p + R(theta_p) rho_i of every body, with rho_i
+    the blob's position in the body frame (ref, (N, 3))."""
+    q = _c(q).reshape(-1, 3)
+    ref = _c(ref)
+    R = quat_matrix(theta)
+    out = np.empty_like(ref)
+    for p, (s, e) in enumerate(_body_ranges(ref.shape[0], body_offsets)):
+        out[s:e] = q[p] + ref[s:e] @ R[p].T
+    return out
+
+
+def body_move(q, theta, U, scale: float):
+    """Q + scale U for bodies: q + scale u, Rotate(theta, scale omega)."""
+    U = np.asarray(U, dtype=np.float64).reshape(-1, 6)
+    return _c(q).reshape(-1, 3) + scale * U[:, :3], quat_rotate(theta, scale * U[:, 3:])
+
+
+def ts_step(q, theta, ref, body_offsets, Lp, force_fn, Ws, Wn, kT: float, dt: float, delta: float,
+            a: float = 1.0, eta: float = 1.0, box=None):
+    """One Trapezoidal Slip step (Alg. 2), with dense linear algebra.
+
+    force_fn(q, theta) -> (n_bodies, 6) forces and torques; Ws, Wn: (N, 3)
+    Gaussian vectors of the slip RFD and of the Brownian increment; Lp:
+    body length scales.  Steps, in the algorithm's order:
+      1a. W^D = [L_p W^s_p], W^F = [kT / L_p W^s_p];
+      1b. RFD displacement problem with slip W^D, F = 0 -> dQ^RFD;
+      1c. Q+- = Q^n +- delta/2 dQ^RFD;
+      1d. D^F = [K^T(Q+) - K^T(Q-)] W^F / delta,
+          D^S = [M(Q+) - M(Q-)] W^F / delta;
+      2.  (M^{1/2})^n W^n: the block-preconditioned root L (L^-1 M L^-T)^{1/2} W^n;
+      3.  predictor: slip sqrt(2 kT / dt) M^{1/2} W^n, force F^n -> U^n;
+      4.  Q~ = Q^n + dt U^n;
+      5.  corrector at Q~: slip 2 D^S + sqrt(2 kT / dt) M^{1/2} W^n,
+          force F(Q~) - 2 D^F -> U~;
+      6.  Q^{n+1} = Q^n + dt/2 (U^n + U~).
+    Rigid solves are rigid_solve (dense LU) at the configuration named; body
+    reference points are the tracking points q_p.  Returns (q1, theta1,
+    intermediates dict).
+    """
+    ranges = _body_ranges(_c(ref).shape[0], body_offsets)
+    Lb = np.concatenate([np.full(e - s, float(Lp[p])) for p, (s, e) in enumerate(ranges)])[:, None]
+    WD = Lb * np.asarray(Ws)
+    WF = kT / Lb * np.asarray(Ws)
+    pos0 = body_blobs(q, theta, ref, body_offsets)
+    _, dQ = rigid_solve(pos0, q, body_offsets, WD, None, a, eta, box)
+    qp, tp = body_move(q, theta, dQ, 0.5 * delta)
+    qm, tm = body_move(q, theta, dQ, -0.5 * delta)
+    posp, posm = body_blobs(qp, tp, ref, body_offsets), body_blobs(qm, tm, ref, body_offsets)
+    DF = (body_K(posp, qp, body_offsets).T @ WF.reshape(-1) - body_K(posm, qm, body_offsets).T @ WF.reshape(-1))
+    DF = (DF / delta).reshape(-1, 6)
+    DS = (matvec(posp, WF, a, eta, box=box) - matvec(posm, WF, a, eta, box=box)) / delta
+    root = dense_sqrt(pos0, Wn, body_offsets, a, eta, box=box)
+    c = math.sqrt(2.0 * kT / dt)
+    F0 = force_fn(q, theta)
+    _, U0 = rigid_solve(pos0, q, body_offsets, c * root, F0, a, eta, box)
+    qt, tt = body_move(q, theta, U0, dt)
+    post = body_blobs(qt, tt, ref, body_offsets)
+    Ft = force_fn(qt, tt)
+    _, Ut = rigid_solve(post, qt, body_offsets, 2.0 * DS + c * root, Ft - 2.0 * DF, a, eta, box)
+    q1, t1 = body_move(q, theta, U0 + Ut, 0.5 * dt)
+    return q1, t1, {"dQ_rfd": dQ, "DF": DF, "DS": DS, "root": root, "U0": U0, "q_tilde": qt, "theta_tilde": tt,
+                    "U_tilde": Ut, "pos_plus": posp, "pos_minus": posm, "WF": WF}
