@@ -62,7 +62,8 @@ enum rpyw_op {
     RPYW_OP_LANCZOS = 2,    /* rpy_wall_lanczos_sqrt */
     RPYW_OP_VJP = 3,        /* rpy_wall_matvec_vjp */
     RPYW_OP_DIVERGENCE = 4, /* rpy_wall_divergence */
-    RPYW_OP_RIGID = 5       /* rpy_wall_rigid_solve */
+    RPYW_OP_RIGID = 5,      /* rpy_wall_rigid_solve (and _periodic) */
+    RPYW_OP_TS = 6          /* rpy_wall_ts_predict / rpy_wall_ts_correct */
 };
 
 /* u = M(r) f  (Sec. II.A: the dense product whose cost dominates every
@@ -167,6 +168,69 @@ int rpy_wall_rigid_solve_periodic(const double* pos, const double* q, const int6
                                   int64_t N, double a, double eta, double Lx, double Ly, double tol,
                                   int32_t max_iter, int precision, void* ws, size_t ws_bytes, int32_t* iters_out,
                                   double* res_out, void* stream);
+
+/* Rigid-body kinematics (Sec. II: tracking point q_p and orientation
+ * theta_p of every body; quaternion appendix: unit quaternions theta =
+ * (s, p), rotated by quaternion multiplication).
+ *
+ * rpy_wall_body_blobs: blob positions r_i = q_p + R(theta_p) rho_i for blob i
+ * of body p, with rho_i its position in the body frame.  q: device
+ * [n_bodies][3]; theta: device [n_bodies][4] unit quaternions (s, px, py,
+ * pz); ref: device [N][3] body-frame positions rho; body_offsets: HOST int64
+ * [n_bodies+1] (0 .. N, strictly increasing); pos: device [N][3].
+ * Synchronises `stream` (the offsets are uploaded from the host). */
+int rpy_wall_body_blobs(const double* q, const double* theta, const double* ref, const int64_t* body_offsets,
+                        int32_t n_bodies, double* pos, int64_t N, void* ws, size_t ws_bytes, void* stream);
+
+/* rpy_wall_body_move: Q + h U for every body: q_out = q + h u, theta_out =
+ * Rotate(theta, h omega), the quaternion of the rotation by the vector
+ * h omega (angle |h omega|) times theta.  U: device [n_bodies][6] (u,
+ * omega); other arrays as for rpy_wall_body_blobs.  Asynchronous. */
+int rpy_wall_body_move(const double* q, const double* theta, const double* U, double h, int32_t n_bodies,
+                       double* q_out, double* theta_out, void* stream);
+
+/* One step of the Trapezoidal Slip scheme (Alg. 2), in two calls around the
+ * caller's evaluation of forces and torques at the predicted configuration:
+ *
+ * rpy_wall_ts_predict, from Q^n = (q, theta), the forces and torques
+ * force_torque = F(Q^n) (device [n_bodies][6], about q_p) and the Gaussian
+ * vectors Ws (slip RFD) and Wn (Brownian), device [N][3]:
+ *   W^D = [L_p W^s_p], W^F = [kT / L_p W^s_p] (Lp: device [n_bodies]);
+ *   dQ^RFD: mobility problem with slip W^D and no force;
+ *   Q+- = Q^n +- delta/2 dQ^RFD;  D^F = [K^T(Q+) - K^T(Q-)] W^F / delta,
+ *   D^S = [M(Q+) - M(Q-)] W^F / delta (one batched product of both);
+ *   sqrt(2 kT / dt) M^{1/2} W^n by the preconditioned Lanczos;
+ *   U^n: mobility problem with that slip and force F^n;
+ *   Q~ = Q^n + dt U^n -> q_tilde, theta_tilde and its blob positions
+ *   pos_tilde (device [N][3]) for the caller's forces.
+ * The quantities the corrector needs go to `state` (device, 256-byte
+ * aligned, rpy_wall_ts_state_bytes(N, n_bodies) bytes, the caller's).
+ * rpy_wall_ts_correct, with F(Q~) in force_torque_tilde: U~ from the
+ * mobility problem at Q~ with slip 2 D^S + sqrt(2 kT / dt) M^{1/2} W^n and
+ * force F(Q~) - 2 D^F, then Q^{n+1} = Q^n + dt/2 (U^n + U~) -> q_next,
+ * theta_next (q, theta: Q^n again).
+ *
+ * Bodies: ref = body-frame blob positions, body_offsets HOST int64
+ * [n_bodies+1], at most 42 blobs per body; the tracking points q_p are the
+ * reference points of K.  Lx = Ly = 0: open domain; Lx, Ly > 0: the
+ * pseudo-periodic cell of rpy_wall_matvec_periodic.  tol, max_iter: of every
+ * iterative solve (Lanczos and GMRES); `precision`: pair arithmetic of the
+ * products by M.  iters_out: HOST, may be NULL: predict writes 3 counts
+ * (RFD solve, Lanczos, predictor solve), correct 1.  Both synchronise
+ * `stream`.  Returns RPYW_NOT_CONVERGED (step completed) if an iterative
+ * solve hit max_iter, RPYW_ENOTSPD as the rigid solve does. */
+size_t rpy_wall_ts_state_bytes(int64_t N, int32_t n_bodies);
+int rpy_wall_ts_predict(const double* q, const double* theta, const double* ref, const int64_t* body_offsets,
+                        int32_t n_bodies, int64_t N, const double* Lp, const double* force_torque, const double* Ws,
+                        const double* Wn, double kT, double dt, double delta, double a, double eta, double Lx,
+                        double Ly, double tol, int32_t max_iter, int precision, double* q_tilde, double* theta_tilde,
+                        double* pos_tilde, void* state, size_t state_bytes, void* ws, size_t ws_bytes,
+                        int32_t* iters_out, void* stream);
+int rpy_wall_ts_correct(const double* q, const double* theta, const double* q_tilde, const double* theta_tilde,
+                        const double* ref, const int64_t* body_offsets, int32_t n_bodies, int64_t N,
+                        const double* force_torque_tilde, const void* state, double dt, double a, double eta,
+                        double Lx, double Ly, double tol, int32_t max_iter, int precision, double* q_next,
+                        double* theta_next, void* ws, size_t ws_bytes, int32_t* iters_out, void* stream);
 
 /* Vector-Jacobian product of u = M(r) f for L = sum_i g_i . u_i
  * (derivatives of M drive the thermal drift, Sec. III):

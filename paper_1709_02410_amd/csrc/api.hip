@@ -161,6 +161,9 @@ size_t rpy_wall_workspace_bytes(int op, int64_t N, int32_t k, int32_t max_iter, 
         case RPYW_OP_RIGID:
             if (max_iter < 1 || n_bodies < 1) return 0;
             return rigid_ws_bytes(N, max_iter, n_bodies, precision);
+        case RPYW_OP_TS:
+            if (max_iter < 1 || n_bodies < 1) return 0;
+            return ts_ws_bytes(N, max_iter, n_bodies, precision);
         default: return 0;
     }
 }
@@ -300,6 +303,98 @@ int rpy_wall_rigid_solve_periodic(const double* pos, const double* q, const int6
     if (!finite_pos(Lx) || !finite_pos(Ly)) return RPYW_EINVAL;
     return rigid_api(pos, q, body_offsets, n_bodies, slip, force_torque, lambda, U, N, a, eta, tol, max_iter,
                      precision, ws, ws_bytes, iters_out, res_out, stream, Domain{Lx, Ly});
+}
+
+static bool valid_bodies(const int64_t* offs, int32_t nb, int64_t N) {
+    if (!offs || nb < 1 || offs[0] != 0 || offs[nb] != N) return false;
+    for (int p = 0; p < nb; ++p) {
+        const int64_t n = offs[p + 1] - offs[p];
+        if (n < 1 || n > kMaxBodyBlobs) return false;
+    }
+    return true;
+}
+
+static bool valid_cell(double Lx, double Ly) {
+    return (Lx == 0.0 && Ly == 0.0) || (finite_pos(Lx) && finite_pos(Ly));
+}
+
+int rpy_wall_body_blobs(const double* q, const double* theta, const double* ref, const int64_t* body_offsets,
+                        int32_t n_bodies, double* pos, int64_t N, void* ws, size_t ws_bytes, void* stream) {
+    if (!q || !theta || !ref || !pos || N < 1 || N >= kMaxN || !body_offsets || n_bodies < 1 ||
+        body_offsets[0] != 0 || body_offsets[n_bodies] != N)
+        return RPYW_EINVAL;
+    for (int p = 0; p < n_bodies; ++p)
+        if (body_offsets[p + 1] <= body_offsets[p]) return RPYW_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    Scratch s;
+    int rc = acquire(ws, ws_bytes, align_up((size_t)(n_bodies + 1) * sizeof(int)) + kAlign, st, s);
+    if (rc != RPYW_OK) return rc;
+    int* bofs = (int*)s.ar.take((size_t)(n_bodies + 1) * sizeof(int));
+    if (!bofs) return RPYW_ENOMEM;
+    std::vector<int> hb(n_bodies + 1);
+    for (int p = 0; p <= n_bodies; ++p) hb[p] = (int)body_offsets[p];
+    RPYW_HIP(hipMemcpyAsync(bofs, hb.data(), hb.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    rc = body_blobs(q, theta, ref, bofs, n_bodies, pos, st);
+    RPYW_HIP(hipStreamSynchronize(st));  // hb goes out of scope
+    return rc;
+}
+
+int rpy_wall_body_move(const double* q, const double* theta, const double* U, double h, int32_t n_bodies,
+                       double* q_out, double* theta_out, void* stream) {
+    if (!q || !theta || !U || !q_out || !theta_out || n_bodies < 1 || !std::isfinite(h)) return RPYW_EINVAL;
+    return body_move(q, theta, U, nullptr, h, n_bodies, q_out, theta_out, (hipStream_t)stream);
+}
+
+size_t rpy_wall_ts_state_bytes(int64_t N, int32_t n_bodies) {
+    if (N < 1 || N >= kMaxN || n_bodies < 1) return 0;
+    return ts_state_bytes(N, n_bodies);
+}
+
+int rpy_wall_ts_predict(const double* q, const double* theta, const double* ref, const int64_t* body_offsets,
+                        int32_t n_bodies, int64_t N, const double* Lp, const double* force_torque, const double* Ws,
+                        const double* Wn, double kT, double dt, double delta, double a, double eta, double Lx,
+                        double Ly, double tol, int32_t max_iter, int precision, double* q_tilde, double* theta_tilde,
+                        double* pos_tilde, void* state, size_t state_bytes, void* ws, size_t ws_bytes,
+                        int32_t* iters_out, void* stream) {
+    if (!q || !theta || !ref || !Lp || !force_torque || !Ws || !Wn || !q_tilde || !theta_tilde || !pos_tilde ||
+        !state || N < 1 || N >= kMaxN || !valid_bodies(body_offsets, n_bodies, N) || !(kT >= 0.0) ||
+        !std::isfinite(kT) || !finite_pos(dt) || !finite_pos(delta) || !finite_pos(a) || !finite_pos(eta) ||
+        !valid_cell(Lx, Ly) || !finite_pos(tol) || max_iter < 1 || max_iter > 100000 || !valid_prec(precision) ||
+        state_bytes < ts_state_bytes(N, n_bodies) || ((uintptr_t)state % 256) != 0)
+        return RPYW_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    Scratch s;
+    int rc = acquire(ws, ws_bytes, ts_ws_bytes(N, max_iter, n_bodies, precision), st, s);
+    if (rc != RPYW_OK) return rc;
+    int it[3] = {0, 0, 0};
+    rc = ts_predict(q, theta, ref, body_offsets, n_bodies, N, Lp, force_torque, Ws, Wn, kT, dt, delta, a, eta,
+                    Domain{Lx, Ly}, tol, max_iter, precision, q_tilde, theta_tilde, pos_tilde, (double*)state, s.ar,
+                    it, st);
+    if (iters_out)
+        for (int k = 0; k < 3; ++k) iters_out[k] = it[k];
+    return rc;
+}
+
+int rpy_wall_ts_correct(const double* q, const double* theta, const double* q_tilde, const double* theta_tilde,
+                        const double* ref, const int64_t* body_offsets, int32_t n_bodies, int64_t N,
+                        const double* force_torque_tilde, const void* state, double dt, double a, double eta,
+                        double Lx, double Ly, double tol, int32_t max_iter, int precision, double* q_next,
+                        double* theta_next, void* ws, size_t ws_bytes, int32_t* iters_out, void* stream) {
+    if (!q || !theta || !q_tilde || !theta_tilde || !ref || !force_torque_tilde || !state || !q_next ||
+        !theta_next || N < 1 || N >= kMaxN || !valid_bodies(body_offsets, n_bodies, N) || !finite_pos(dt) ||
+        !finite_pos(a) || !finite_pos(eta) || !valid_cell(Lx, Ly) || !finite_pos(tol) || max_iter < 1 ||
+        max_iter > 100000 || !valid_prec(precision) || ((uintptr_t)state % 256) != 0)
+        return RPYW_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    Scratch s;
+    int rc = acquire(ws, ws_bytes, ts_ws_bytes(N, max_iter, n_bodies, precision), st, s);
+    if (rc != RPYW_OK) return rc;
+    int it = 0;
+    rc = ts_correct(q, theta, q_tilde, theta_tilde, ref, body_offsets, n_bodies, N, force_torque_tilde,
+                    (const double*)state, dt, a, eta, Domain{Lx, Ly}, tol, max_iter, precision, q_next, theta_next,
+                    s.ar, &it, st);
+    if (iters_out) *iters_out = it;
+    return rc;
 }
 
 int rpy_wall_matvec_vjp(const double* pos, const double* force, const double* grad_vel, double* grad_pos,

@@ -19,17 +19,26 @@ namespace {
 constexpr int kBodyThreads = 128;
 
 // Dense M^(pp) of one body (units: physical, includes mu0 and B factors)
-// assembled in LDS, then factorised in place (right-looking Cholesky).
+// assembled in LDS, then factorised in place (right-looking Cholesky).  The
+// LDS is sized at launch for the largest body of the call (ld = 3 n_max + 1
+// doubles per row, then 4 n_max doubles of blob data), so that small bodies
+// keep many workgroups per CU.
 __global__ __launch_bounds__(kBodyThreads) void precond_build_kernel(const double* __restrict__ pos,
                                                                      const int* __restrict__ bofs,
                                                                      const int64_t* __restrict__ lofs, double inv_a,
                                                                      double mu0, double* __restrict__ Lout,
-                                                                     int* __restrict__ notspd) {
-    __shared__ double A[3 * kMaxBodyBlobs][3 * kMaxBodyBlobs + 1];
-    __shared__ double px[kMaxBodyBlobs], py[kMaxBodyBlobs], pz[kMaxBodyBlobs], pb[kMaxBodyBlobs];
+                                                                     int* __restrict__ notspd, int nmax) {
+    extern __shared__ double lds[];
+    const int ld = 3 * nmax + 1;
+    double* Abase = lds;
+    double* px = lds + 3 * nmax * ld;
+    double* py = px + nmax;
+    double* pz = py + nmax;
+    double* pb = pz + nmax;
     __shared__ int bad;
     const int p = blockIdx.x;
     const int b0 = bofs[p], nb = bofs[p + 1] - b0, n = 3 * nb;
+#define A(i, j) Abase[(i) * ld + (j)]
     if (threadIdx.x == 0) bad = 0;
     for (int a = threadIdx.x; a < nb; a += blockDim.x) {
         const double x = pos[3 * (b0 + a)] * inv_a, y = pos[3 * (b0 + a) + 1] * inv_a,
@@ -49,24 +58,24 @@ __global__ __launch_bounds__(kBodyThreads) void precond_build_kernel(const doubl
             double u[3] = {0.0, 0.0, 0.0};
             pair_apply<double>(c, dx, dy, dz, beta == 0 ? 1.0 : 0.0, beta == 1 ? 1.0 : 0.0, beta == 2 ? 1.0 : 0.0,
                                u[0], u[1], u[2]);
-            for (int al = 0; al < 3; ++al) A[3 * ia + al][3 * ib + beta] = sc * u[al];
+            for (int al = 0; al < 3; ++al) A(3 * ia + al, 3 * ib + beta) = sc * u[al];
         }
     }
     __syncthreads();
     for (int k = 0; k < n; ++k) {
         if (threadIdx.x == 0) {
-            const double d = A[k][k];
+            const double d = A(k, k);
             if (!(d > 0.0)) bad = 1;
-            A[k][k] = d > 0.0 ? sqrt(d) : 1.0;
+            A(k, k) = d > 0.0 ? sqrt(d) : 1.0;
         }
         __syncthreads();
-        const double dk = A[k][k];
-        for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) A[i][k] /= dk;
+        const double dk = A(k, k);
+        for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) A(i, k) /= dk;
         __syncthreads();
         const int m = n - k - 1;
         for (int q = threadIdx.x; q < m * m; q += blockDim.x) {
             const int i = k + 1 + q / m, j = k + 1 + q % m;
-            if (j <= i) A[i][j] -= A[i][k] * A[j][k];
+            if (j <= i) A(i, j) -= A(i, k) * A(j, k);
         }
         __syncthreads();
     }
@@ -74,21 +83,22 @@ __global__ __launch_bounds__(kBodyThreads) void precond_build_kernel(const doubl
     double* Li = L + (int64_t)n * n;
     for (int q = threadIdx.x; q < n * n; q += blockDim.x) {
         const int i = q / n, j = q % n;
-        L[q] = j <= i ? A[i][j] : 0.0;
+        L[q] = j <= i ? A(i, j) : 0.0;
     }
     // Inverse factor L^-1 (lower triangular), one column per thread: forward
     // substitution of L x = e_col, the column written to global memory.
     for (int col = threadIdx.x; col < n; col += blockDim.x) {
         for (int i = 0; i < col; ++i) Li[i * n + col] = 0.0;
-        double xc = 1.0 / A[col][col];
+        double xc = 1.0 / A(col, col);
         Li[col * n + col] = xc;
         for (int i = col + 1; i < n; ++i) {
             double s = 0.0;
-            for (int k = col; k < i; ++k) s += A[i][k] * Li[k * n + col];
-            Li[i * n + col] = -s / A[i][i];
+            for (int k = col; k < i; ++k) s += A(i, k) * Li[k * n + col];
+            Li[i * n + col] = -s / A(i, i);
         }
     }
     if (threadIdx.x == 0 && bad) atomicOr(notspd, 1);
+#undef A
 }
 
 // mode 0: out = L v;  1: out = L^-1 v;  2: out = L^-T v, with the factor L
@@ -303,8 +313,14 @@ int body_factors_build(const double* pos, int64_t N, double a, double eta, const
         RPYW_HIP(hipMemcpyAsync(pc.bofs, hb.data(), hb.size() * sizeof(int), hipMemcpyHostToDevice, st));
         RPYW_HIP(hipMemcpyAsync(pc.lofs, hl.data(), hl.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
         RPYW_HIP(hipStreamSynchronize(st));  // host vectors go out of scope
-        hipLaunchKernelGGL(precond_build_kernel, dim3(n_bodies), dim3(kBodyThreads), 0, st, pos, pc.bofs, pc.lofs,
-                           inv_a, m0, pc.L, notspd);
+        int nmax = 1;
+        for (int p = 0; p < n_bodies; ++p) nmax = std::max(nmax, (int)(body_offsets[p + 1] - body_offsets[p]));
+        const size_t lds = ((size_t)3 * nmax * (3 * nmax + 1) + 4 * (size_t)nmax) * sizeof(double);
+        if (lds > 65536)  // up to 129 KB for 42-blob bodies
+            RPYW_HIP(hipFuncSetAttribute((const void*)precond_build_kernel,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(precond_build_kernel, dim3(n_bodies), dim3(kBodyThreads), lds, st, pos, pc.bofs, pc.lofs,
+                           inv_a, m0, pc.L, notspd, nmax);
     } else {
         pc.L = (double*)ar.take((size_t)3 * N * sizeof(double));
         if (!pc.L) return RPYW_ENOMEM;

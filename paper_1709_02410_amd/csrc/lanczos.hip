@@ -9,8 +9,9 @@
 //   reorthogonalisation (two classical Gram-Schmidt passes), alpha/beta kept
 //   on the device; one device->host copy of (alpha_k, beta_k) per iteration
 //   into pinned memory.  Iteration k + 1 only needs beta_k on the device, so
-//   it is queued before the host has examined iteration k and is discarded
-//   if k turns out to be the last: the host solve overlaps the GPU work.
+//   for small problems it is queued before the host has examined iteration
+//   k and is discarded if k turns out to be the last: the host solve
+//   overlaps the GPU work.
 //   Host: eigendecomposition of the k x k tridiagonal T_k, coefficients
 //   c_k = beta0 Q Lambda^{1/2} Q^T e1; since V is orthonormal the stopping
 //   test |y_k - y_{k-1}| <= tol |y_k| is evaluated on c.  At the end
@@ -218,11 +219,12 @@ int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, dou
     bool converged = false;
     double rel = INFINITY;
     int k = 0;
+    const bool speculate = (double)N * (double)N <= kSpeculatePairs;
     if ((rc = launch_iter(0))) return rc;
     for (; k < max_iter; ++k) {
         RPYW_HIP(hipEventSynchronize(g_ab.ev[k & 1]));
         const double ak = h_ab[2 * k], bk = h_ab[2 * k + 1];
-        if (k + 1 < max_iter && (rc = launch_iter(k + 1))) return rc;
+        if (speculate && k + 1 < max_iter && (rc = launch_iter(k + 1))) return rc;
         alpha.push_back(ak);
         c.assign(k + 1, 0.0);
         if (tridiag_sqrt_coeffs(alpha.data(), beta.data(), k + 1, beta0, c.data()) != RPYW_OK) return RPYW_EHIP;
@@ -246,6 +248,7 @@ int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, dou
         }
         cprev = c;
         beta.push_back(bk);
+        if (!speculate && k + 1 < max_iter && (rc = launch_iter(k + 1))) return rc;
     }
     const int used = (int)c.size();
     *iters = converged ? k + 1 : max_iter;

@@ -19,8 +19,8 @@
 // step costs one product by M plus O(N) work.  Classical Gram-Schmidt is
 // applied twice; the Hessenberg column goes to pinned host memory, where
 // Givens rotations give the residual.  Step k + 1 only needs the norm
-// h_{k+1,k} on the device, so it is queued before the host has examined
-// step k (and is discarded if step k converged).
+// h_{k+1,k} on the device, so for small problems it is queued before the
+// host has examined step k (and is discarded if step k converged).
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -356,6 +356,7 @@ int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets,
     bool converged = false;
     double res = 1.0;
     int k = 0;
+    const bool speculate = (double)N * (double)N <= kSpeculatePairs;
     if ((rc = launch_step(0))) return rc;
     for (; k < max_iter; ++k) {
         RPYW_HIP(hipEventSynchronize(g_h.ev[k & 1]));
@@ -363,7 +364,7 @@ int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets,
         std::vector<double> h(k + 2);
         for (int j = 0; j <= k; ++j) h[j] = hs[j] + hs[k + 1 + j];
         h[k + 1] = hs[2 * (k + 1)];
-        if (k + 1 < max_iter && (rc = launch_step(k + 1))) return rc;
+        if (speculate && k + 1 < max_iter && (rc = launch_step(k + 1))) return rc;
         for (int j = 0; j < k; ++j) {
             const double t0 = cs[j] * h[j] + sn[j] * h[j + 1];
             h[j + 1] = -sn[j] * h[j] + cs[j] * h[j + 1];
@@ -385,6 +386,7 @@ int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets,
             converged = true;
             break;
         }
+        if (!speculate && k + 1 < max_iter && (rc = launch_step(k + 1))) return rc;
     }
     const int m = (int)R.size();
     *iters = m;

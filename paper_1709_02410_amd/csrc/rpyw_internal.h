@@ -129,6 +129,12 @@ int vec_update(const double* win, double* wout, int64_t n, const double* vprev, 
 int vec_dots(const double* V, int64_t ld, int nv, const double* w, int64_t n, double* partial, unsigned* ticket,
              double* out, int copy_idx, double* copy_to, hipStream_t st);
 int vec_comb(const double* V, int64_t ld, int nv, const double* c, double* out, int64_t n, hipStream_t st);
+// Krylov drivers queue step k + 1 before the host has examined step k only
+// while one product is cheap against the host's per-step latency (about
+// 0.1 ms): above this many pairs the speculative step, wasted after the last
+// iteration, costs more than it hides.
+constexpr double kSpeculatePairs = 4.0e8;
+
 // Library-owned pinned host buffer plus two events for per-iteration
 // device->host copies of a solver; the caller holds mu while using it.
 struct PinnedSlots {
@@ -152,6 +158,22 @@ int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets,
                 const double* FT, double* lam_out, double* U_out, int64_t N, double a, double eta, double tol,
                 int max_iter, int prec, Arena& ar, int* iters, double* res_out, hipStream_t st,
                 const Domain& dom = Domain{});
+
+// Body kinematics and the Trapezoidal Slip step (ts.hip)
+int body_blobs(const double* q, const double* theta, const double* ref, const int* bofs_dev, int nb, double* pos,
+               hipStream_t st);
+int body_move(const double* q, const double* theta, const double* U, const double* U2, double h, int nb,
+              double* q_out, double* theta_out, hipStream_t st);
+size_t ts_state_bytes(int64_t N, int nb);
+size_t ts_ws_bytes(int64_t N, int max_iter, int nb, int prec);
+int ts_predict(const double* q, const double* theta, const double* ref, const int64_t* body_offsets, int nb,
+               int64_t N, const double* Lp, const double* FT, const double* Ws, const double* Wn, double kT,
+               double dt, double delta, double a, double eta, const Domain& dom, double tol, int max_iter, int prec,
+               double* q_t, double* theta_t, double* pos_t, double* state, Arena& ar, int* iters, hipStream_t st);
+int ts_correct(const double* q, const double* theta, const double* q_t, const double* theta_t, const double* ref,
+               const int64_t* body_offsets, int nb, int64_t N, const double* FT_t, const double* state, double dt,
+               double a, double eta, const Domain& dom, double tol, int max_iter, int prec, double* q_next,
+               double* theta_next, Arena& ar, int* iters, hipStream_t st);
 
 // Derivatives (vjp.hip)
 size_t vjp_ws_bytes(int64_t N, int prec);

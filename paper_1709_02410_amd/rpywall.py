@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "librpywall.so")
 
 FP64 = 0
 FP32C = 1
-OP_MATVEC, OP_BATCHED, OP_LANCZOS, OP_VJP, OP_DIVERGENCE, OP_RIGID = range(6)
+OP_MATVEC, OP_BATCHED, OP_LANCZOS, OP_VJP, OP_DIVERGENCE, OP_RIGID, OP_TS = range(7)
 
 OK, NOT_CONVERGED, EINVAL, EHIP, ENOMEM, ENOTSPD = 0, 1, -1, -2, -3, -4
 
@@ -55,6 +55,12 @@ def lib():
                                   ctypes.POINTER(i32), ctypes.POINTER(dbl), vp],
         "rpy_wall_rigid_solve": [vp, vp, i64p, i32, vp, vp, vp, vp, i64, dbl, dbl, dbl, i32, ctypes.c_int, vp, sz,
                                  ctypes.POINTER(i32), ctypes.POINTER(dbl), vp],
+        "rpy_wall_body_blobs": [vp, vp, vp, i64p, i32, vp, i64, vp, sz, vp],
+        "rpy_wall_body_move": [vp, vp, vp, dbl, i32, vp, vp, vp],
+        "rpy_wall_ts_predict": [vp, vp, vp, i64p, i32, i64, vp, vp, vp, vp, dbl, dbl, dbl, dbl, dbl, dbl, dbl, dbl,
+                                i32, ctypes.c_int, vp, vp, vp, vp, sz, vp, sz, ctypes.POINTER(i32), vp],
+        "rpy_wall_ts_correct": [vp, vp, vp, vp, vp, i64p, i32, i64, vp, vp, dbl, dbl, dbl, dbl, dbl, dbl, i32,
+                                ctypes.c_int, vp, vp, vp, sz, ctypes.POINTER(i32), vp],
         "rpy_wall_matvec_vjp": [vp, vp, vp, vp, vp, i64, dbl, dbl, ctypes.c_int, vp, sz, vp],
         "rpy_wall_divergence": [vp, vp, i64, dbl, dbl, ctypes.c_int, vp, sz, vp],
         "rpy_wall_autotune": [vp, vp, vp, i64, i32, dbl, dbl, ctypes.c_int, vp, sz, vp],
@@ -68,6 +74,8 @@ def lib():
         fn = getattr(L, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
+    L.rpy_wall_ts_state_bytes.argtypes = [i64, i32]
+    L.rpy_wall_ts_state_bytes.restype = sz
     L.rpy_wall_workspace_bytes.argtypes = [ctypes.c_int, i64, i32, i32, i32, ctypes.c_int]
     L.rpy_wall_workspace_bytes.restype = sz
     L.rpyw_strerror.argtypes = [ctypes.c_int]
@@ -241,6 +249,101 @@ def rigid_solve(pos: torch.Tensor, q: torch.Tensor, body_offsets, slip: torch.Te
                                                  ctypes.byref(res), _stream(pos.device))
     _check(st, "rpy_wall_rigid_solve", allow=(OK,) if strict else (OK, NOT_CONVERGED))
     return lam, U, int(it.value), float(res.value), st == OK
+
+
+def body_blobs(q: torch.Tensor, theta: torch.Tensor, ref: torch.Tensor, body_offsets) -> torch.Tensor:
+    """Blob positions q_p + R(theta_p) rho_i; q (nb,3), theta (nb,4) unit
+    quaternions (s, p), ref (N,3) body-frame positions."""
+    offs = _offsets(body_offsets)
+    nb, N = offs.shape[0] - 1, ref.shape[0]
+    _dev(q, "q", (nb, 3))
+    _dev(theta, "theta", (nb, 4))
+    _dev(ref, "ref", (N, 3))
+    pos = torch.empty_like(ref)
+    ws = _workspace(8 * (nb + 1) + 1024, ref.device)
+    _check(lib().rpy_wall_body_blobs(q.data_ptr(), theta.data_ptr(), ref.data_ptr(),
+                                     offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), nb, pos.data_ptr(), N,
+                                     ws.data_ptr(), ws.numel(), _stream(ref.device)), "rpy_wall_body_blobs")
+    return pos
+
+
+def body_move(q: torch.Tensor, theta: torch.Tensor, U: torch.Tensor, h: float):
+    """(q + h u, Rotate(theta, h omega)) for U (nb, 6)."""
+    nb = q.shape[0]
+    _dev(q, "q", (nb, 3))
+    _dev(theta, "theta", (nb, 4))
+    _dev(U, "U", (nb, 6))
+    qo, to = torch.empty_like(q), torch.empty_like(theta)
+    _check(lib().rpy_wall_body_move(q.data_ptr(), theta.data_ptr(), U.data_ptr(), h, nb, qo.data_ptr(),
+                                    to.data_ptr(), _stream(q.device)), "rpy_wall_body_move")
+    return qo, to
+
+
+class TSStep:
+    """The Trapezoidal Slip step (Alg. 2) as predict / correct around the
+    caller's force evaluation.  Geometry: ref (N,3) body-frame blob
+    positions, body_offsets (host), Lp (nb,) length scales; box = (Lx, Ly)
+    for the pseudo-periodic cell."""
+
+    def __init__(self, ref: torch.Tensor, body_offsets, Lp: torch.Tensor, kT: float, dt: float, delta: float,
+                 a: float = 1.0, eta: float = 1.0, tol: float = 1e-3, max_iter: int = 200,
+                 precision: int = FP64, box=None):
+        self.offs = _offsets(body_offsets)
+        self.nb, self.N = self.offs.shape[0] - 1, ref.shape[0]
+        _dev(ref, "ref", (self.N, 3))
+        _dev(Lp, "Lp", (self.nb,))
+        self.ref, self.Lp = ref, Lp
+        self.kT, self.dt, self.delta, self.a, self.eta = kT, dt, delta, a, eta
+        self.tol, self.max_iter, self.precision = tol, max_iter, precision
+        self.box = (0.0, 0.0) if box is None else (float(box[0]), float(box[1]))
+        dev = ref.device
+        sb = int(lib().rpy_wall_ts_state_bytes(self.N, self.nb))
+        self.state = torch.empty(sb // 8 + 32, dtype=torch.float64, device=dev)
+        self.ws = _workspace(workspace_bytes(OP_TS, self.N, 1, max_iter, self.nb, precision), dev)
+        self.iters = []
+
+    def _po(self):
+        return self.offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+    def predict(self, q, theta, force_torque, Ws, Wn):
+        """Returns (q~, theta~, blob positions at Q~)."""
+        for t, n, sh in ((q, "q", (self.nb, 3)), (theta, "theta", (self.nb, 4)),
+                         (force_torque, "force_torque", (self.nb, 6)), (Ws, "Ws", (self.N, 3)),
+                         (Wn, "Wn", (self.N, 3))):
+            _dev(t, n, sh)
+        qt, tt, pt = torch.empty_like(q), torch.empty_like(theta), torch.empty_like(self.ref)
+        it = (ctypes.c_int32 * 3)()
+        st = lib().rpy_wall_ts_predict(q.data_ptr(), theta.data_ptr(), self.ref.data_ptr(), self._po(), self.nb,
+                                       self.N, self.Lp.data_ptr(), force_torque.data_ptr(), Ws.data_ptr(),
+                                       Wn.data_ptr(), self.kT, self.dt, self.delta, self.a, self.eta, self.box[0],
+                                       self.box[1], self.tol, self.max_iter, self.precision, qt.data_ptr(),
+                                       tt.data_ptr(), pt.data_ptr(), self.state.data_ptr(), self.state.numel() * 8,
+                                       self.ws.data_ptr(), self.ws.numel(), it, _stream(q.device))
+        _check(st, "rpy_wall_ts_predict", allow=(OK, NOT_CONVERGED))
+        self.iters = list(it)
+        return qt, tt, pt
+
+    def correct(self, q, theta, q_tilde, theta_tilde, force_torque_tilde):
+        """Returns (q^{n+1}, theta^{n+1})."""
+        _dev(force_torque_tilde, "force_torque_tilde", (self.nb, 6))
+        q1, t1 = torch.empty_like(q), torch.empty_like(theta)
+        it = ctypes.c_int32(0)
+        st = lib().rpy_wall_ts_correct(q.data_ptr(), theta.data_ptr(), q_tilde.data_ptr(), theta_tilde.data_ptr(),
+                                       self.ref.data_ptr(), self._po(), self.nb, self.N,
+                                       force_torque_tilde.data_ptr(), self.state.data_ptr(), self.dt, self.a,
+                                       self.eta, self.box[0], self.box[1], self.tol, self.max_iter, self.precision,
+                                       q1.data_ptr(), t1.data_ptr(), self.ws.data_ptr(), self.ws.numel(),
+                                       ctypes.byref(it), _stream(q.device))
+        _check(st, "rpy_wall_ts_correct", allow=(OK, NOT_CONVERGED))
+        self.iters.append(int(it.value))
+        return q1, t1
+
+    def step(self, q, theta, force_fn, Ws, Wn):
+        """force_fn(q, theta, blob positions) -> (nb, 6) forces and torques
+        at Q^n, predict, force_fn at Q~, correct."""
+        F0 = force_fn(q, theta, body_blobs(q, theta, self.ref, self.offs))
+        qt, tt, pt = self.predict(q, theta, F0, Ws, Wn)
+        return self.correct(q, theta, qt, tt, force_fn(qt, tt, pt))
 
 
 def matvec_vjp(pos: torch.Tensor, force: torch.Tensor, grad_vel: torch.Tensor, a: float = 1.0, eta: float = 1.0,

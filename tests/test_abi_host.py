@@ -80,14 +80,28 @@ def test_validation_rejects_before_any_launch(lib):
     assert lib.rpy_wall_rigid_solve_periodic(dummy, dummy, offs, 2, None, None, dummy, dummy, 9, 1.0, 1.0, 5.0,
                                              float("inf"), 1e-6, 50, 0, None, 0, ctypes.byref(it),
                                              ctypes.byref(er), None) == E
+    i3 = (ctypes.c_int32 * 3)()
+    ts = lambda dt=0.1, delta=1e-3, kT=1.0, Lp=dummy, st=ctypes.c_void_p(0x100000), sb=1 << 30: (  # noqa: E731
+        lib.rpy_wall_ts_predict(dummy, dummy, dummy, offs, 2, 9, Lp, dummy, dummy, dummy, kT, dt, delta, 1.0, 1.0,
+                                0.0, 0.0, 1e-3, 50, 0, dummy, dummy, dummy, st, sb, None, 0, i3, None))
+    assert ts(dt=0.0) == E
+    assert ts(delta=-1.0) == E
+    assert ts(kT=-1.0) == E
+    assert ts(Lp=None) == E
+    assert ts(st=ctypes.c_void_p(0x100008)) == E  # state not 256-byte aligned
+    assert ts(sb=16) == E                         # state too small
+    assert lib.rpy_wall_ts_correct(dummy, dummy, dummy, dummy, dummy, offs, 2, 9, dummy, None, 0.1, 1.0, 1.0, 0.0,
+                                   0.0, 1e-3, 50, 0, dummy, dummy, None, 0, ctypes.byref(it), None) == E
+    assert lib.rpy_wall_body_move(dummy, dummy, None, 0.1, 2, dummy, dummy, None) == E
+    assert lib.rpy_wall_body_blobs(dummy, dummy, dummy, bad_offs, 2, dummy, 5, None, 0, None) == E
     # misaligned caller workspace
     assert lib.rpy_wall_matvec(dummy, dummy, dummy, 10, 1.0, 1.0, 0, ctypes.c_void_p(0x1001), 1 << 20,
                                None) == E
 
 
 def test_workspace_sizes(lib):
-    for op in range(6):
-        assert rpywall.workspace_bytes(op, 1000, 4, 50, 10 if op in (1, 5) else 0, 1) > 0
+    for op in range(7):
+        assert rpywall.workspace_bytes(op, 1000, 4, 50, 10 if op in (1, 5, 6) else 0, 1) > 0
     assert rpywall.workspace_bytes(5, 1000, 1, 50, 0) == 0  # rigid solve needs bodies
     assert lib.rpy_wall_workspace_bytes(0, 0, 1, 0, 0, 0) == 0
     assert lib.rpy_wall_workspace_bytes(9, 10, 1, 0, 0, 0) == 0

@@ -118,3 +118,22 @@ def test_iterations_independent_of_size(rp):
     print(f"iterations (pc, per-blob) by size: {its}", flush=True)
     pc = [p for p, _ in its]
     assert max(pc) <= 8 and max(pc) - min(pc) <= 1
+
+
+def test_largest_bodies_42_blobs(rp, orc):
+    """Bodies of the largest supported size (42 blobs, a 6 x 7 plate; the
+    preconditioner factors need 129 KB of LDS) next to small ones: the
+    Lanczos root and the rigid solve against the oracle."""
+    gx, gy = np.meshgrid(np.arange(6) * 1.9, np.arange(7) * 1.9)
+    plate = np.column_stack([gx.ravel(), gy.ravel(), np.full(42, 3.0)])
+    pos = np.concatenate([plate, plate + [16.0, 0.0, 0.5], plate[[0, 1, 6, 7, 13]] + [0.0, 16.0, 0.0]])
+    offs = np.array([0, 42, 84, 89])
+    W = wl.gaussian(pos.shape, 21)
+    out, it, err, ok = rp.lanczos_sqrt(_t(pos), _t(W), body_offsets=offs, tol=1e-10)
+    ref = orc.dense_sqrt(pos, W, offs)
+    assert ok and _rel(out.cpu().numpy(), ref) <= 1e-8
+    q = np.array([pos[offs[p]:offs[p + 1]].mean(0) for p in range(3)])
+    FT = wl.gaussian((3, 6), 22)
+    lam_ref, U_ref = orc.rigid_solve(pos, q, offs, None, FT)
+    lam, U, it, res, ok = rp.rigid_solve(_t(pos), _t(q), offs, None, _t(FT), tol=1e-11)
+    assert ok and _rel(U.cpu().numpy(), U_ref) <= 1e-8

@@ -1,0 +1,111 @@
+"""GPU body kinematics and Trapezoidal Slip step (Alg. 2) against the
+oracle's dense implementation, with the same random vectors and forces."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1709_02410_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1709_02410_amd import rpywall
+    rpywall.lib()
+    return rpywall
+
+
+def _t(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def _unit_quats(n, seed):
+    v = np.random.default_rng(seed).standard_normal((n, 4))
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+def _suspension(nb, seed, spacing=0.926):
+    """Boomerangs with the paper's blob spacing, tracking point at the
+    corner blob (body frame origin), random orientations, heights 2..3.5 a."""
+    fr = wl.boomerang_frame(spacing)
+    ref = np.concatenate([fr] * nb)
+    offs = np.arange(0, 15 * nb + 1, 15)
+    rng = np.random.default_rng(seed)
+    side = math.ceil(math.sqrt(nb))
+    q = np.column_stack([(np.arange(nb) % side) * 9.0 + rng.uniform(0, 1, nb),
+                         (np.arange(nb) // side) * 9.0 + rng.uniform(0, 1, nb), rng.uniform(3.0, 4.0, nb)])
+    th = _unit_quats(nb, seed + 1)
+    th[:, 1:3] *= 0.2  # mostly flat: rotations about z dominate, so no blob reaches the wall
+    th /= np.linalg.norm(th, axis=1, keepdims=True)
+    return q, th, ref, offs
+
+
+def _force(q0, k=0.4):
+    def f(q, theta):
+        F = np.zeros((len(q), 6))
+        F[:, :3] = -k * (q - q0)
+        F[:, 2] -= 0.3
+        F[:, 5] = 0.05 * (q[:, 0] - q0[:, 0])
+        return F
+    return f
+
+
+def test_body_kinematics_match_oracle(rp, orc):
+    q, th, ref, offs = _suspension(5, 1)
+    pos = rp.body_blobs(_t(q), _t(th), _t(ref), offs).cpu().numpy()
+    np.testing.assert_allclose(pos, orc.body_blobs(q, th, ref, offs), atol=1e-13)
+    U = np.random.default_rng(2).standard_normal((5, 6))
+    U[0] = 0.0
+    for h in (0.0, 1e-3, 0.7):
+        q2, t2 = rp.body_move(_t(q), _t(th), _t(U), h)
+        rq, rt = orc.body_move(q, th, U, h)
+        np.testing.assert_allclose(q2.cpu().numpy(), rq, atol=1e-14)
+        np.testing.assert_allclose(t2.cpu().numpy(), rt, atol=1e-14)
+
+
+@pytest.mark.parametrize("prec,periodic", [(0, False), (0, True), (1, False)])
+def test_ts_step_matches_oracle(rp, orc, prec, periodic):
+    nb = 6
+    q, th, ref, offs = _suspension(nb, 3)
+    box = (30.0, 28.0) if periodic else None
+    Lp = np.full(nb, 3.0)
+    Ws, Wn = wl.gaussian(ref.shape, 4), wl.gaussian(ref.shape, 5)
+    kT, dt = 0.8, 0.05
+    delta = 1e-4 if prec == 0 else 1e-2
+    force = _force(q + np.array([0.3, -0.2, 0.1]))
+    q1r, t1r, inter = orc.ts_step(q, th, ref, offs, Lp, force, Ws, Wn, kT=kT, dt=dt, delta=delta, box=box)
+    step = rp.TSStep(_t(ref), offs, _t(Lp), kT, dt, delta, tol=1e-12 if prec == 0 else 1e-9, max_iter=400,
+                     precision=prec, box=box)
+    fn = lambda qq, tt, pos: _t(force(qq.cpu().numpy(), tt.cpu().numpy()))  # noqa: E731
+    qT, tT, pT = step.predict(_t(q), _t(th), fn(_t(q), _t(th), None), _t(Ws), _t(Wn))
+    np.testing.assert_allclose(pT.cpu().numpy(), orc.body_blobs(qT.cpu().numpy(), tT.cpu().numpy(), ref, offs),
+                               atol=1e-12)
+    q1, t1 = step.correct(_t(q), _t(th), qT, tT, fn(qT, tT, pT))
+    q1, t1 = q1.cpu().numpy(), t1.cpu().numpy()
+    dq, dqr = q1 - q, q1r - q
+    dtq, dtr = t1 - th, t1r - th
+    rel_q = np.linalg.norm(dq - dqr) / np.linalg.norm(dqr)
+    rel_t = np.linalg.norm(dtq - dtr) / np.linalg.norm(dtr)
+    rel_tilde = np.linalg.norm(qT.cpu().numpy() - inter["q_tilde"]) / np.linalg.norm(inter["q_tilde"] - q)
+    print(f"T-S prec={prec} periodic={periodic} iters={step.iters} rel dq={rel_q:.2e} dtheta={rel_t:.2e} "
+          f"q~={rel_tilde:.2e}", flush=True)
+    bound = 1e-7 if prec == 0 else 5e-3
+    assert rel_q <= bound and rel_t <= bound and rel_tilde <= bound
+    np.testing.assert_allclose(np.linalg.norm(t1, axis=1), 1.0, atol=1e-13)
+
+
+def test_ts_zero_temperature_is_deterministic_heun(rp, orc):
+    """kT = 0 (no noise, no drift): the GPU step is Heun's method."""
+    q, th, ref, offs = _suspension(4, 6)
+    force = _force(q + 0.5)
+    Ws, Wn = wl.gaussian(ref.shape, 7), wl.gaussian(ref.shape, 8)
+    step = rp.TSStep(_t(ref), offs, _t(np.full(4, 3.0)), 0.0, 0.1, 1e-4, tol=1e-12, max_iter=400)
+    q1, t1 = step.step(_t(q), _t(th), lambda qq, tt, pos: _t(force(qq.cpu().numpy(), tt.cpu().numpy())), _t(Ws),
+                       _t(Wn))
+    q1r, t1r, _ = orc.ts_step(q, th, ref, offs, np.full(4, 3.0), force, Ws, Wn, kT=0.0, dt=0.1, delta=1e-4)
+    assert np.linalg.norm(q1.cpu().numpy() - q1r) <= 1e-9 * np.linalg.norm(q1r - q)
