@@ -24,8 +24,9 @@ Contents (arXiv:1709.02410):
   * ``rigid_gmres``: the same system by GMRES right-preconditioned with the
     per-body block-diagonal operator (Sec. II.B); used for iteration counts.
   * ``quat_rotate``/``body_blobs``/``body_move``/``ts_step``: body kinematics
-    with unit quaternions (appendix on quaternions) and one step of the
-    Trapezoidal Slip scheme (Alg. 2) with dense solves.
+    with unit quaternions (appendix on quaternions), one step of the
+    Trapezoidal Slip scheme (Alg. 2) and one of the Euler-Maruyama Traction
+    scheme (Alg. 1, ``emt_step``), with dense solves.
   * ``box=(Lx, Ly)`` on the products, dense matrices, roots and solves: the
     pseudo-periodic domain of the paper's suspensions (Sec. V): each source
     at its minimum image plus the 8 periodic images around it.
@@ -567,3 +568,41 @@ def ts_step(q, theta, ref, body_offsets, Lp, force_fn, Ws, Wn, kT: float, dt: fl
     q1, t1 = body_move(q, theta, U0 + Ut, 0.5 * dt)
     return q1, t1, {"dQ_rfd": dQ, "DF": DF, "DS": DS, "root": root, "U0": U0, "q_tilde": qt, "theta_tilde": tt,
                     "U_tilde": Ut, "pos_plus": posp, "pos_minus": posm, "WF": WF}
+
+
+def emt_step(q, theta, ref, body_offsets, Lp, FT, Wf, Wt, Wn, kT: float, dt: float, delta: float,
+             a: float = 1.0, eta: float = 1.0, box=None):
+    """One Euler-Maruyama Traction step (Alg. 1), with dense linear algebra.
+
+    FT: (n_bodies, 6) forces and torques at Q^n; Wf, Wt: (n_bodies, 3)
+    Gaussian vectors of the traction RFD; Wn: (N, 3) Brownian.  Steps:
+      1a. W^FT_p = kT [W^f_p / L_p, W^tau_p];
+      1b. RFD mobility problem with no slip and force W^FT -> lambda^RFD,
+          U^RFD;
+      1c. Q+- = Q^n +- delta/2 [L_p W^f_p, W^tau_p];
+      1d. D^F = [K^T(Q+) - K^T(Q-)] lambda^RFD / delta,
+          D^S = [M(Q+) - M(Q-)] lambda^RFD / delta
+                - [K(Q+) - K(Q-)] U^RFD / delta;
+      2.  (M^{1/2})^n W^n (block-preconditioned root);
+      3.  slip D^S + sqrt(2 kT / dt) M^{1/2} W^n, force F^n - D^F -> U^n;
+      4.  Q^{n+1} = Q^n + dt U^n.
+    Returns (q1, theta1, intermediates dict)."""
+    Lp = np.asarray(Lp, dtype=np.float64)
+    WFT = kT * np.concatenate([np.asarray(Wf) / Lp[:, None], np.asarray(Wt)], 1)
+    pos0 = body_blobs(q, theta, ref, body_offsets)
+    lam_r, U_r = rigid_solve(pos0, q, body_offsets, None, WFT, a, eta, box)
+    dQ = np.concatenate([Lp[:, None] * np.asarray(Wf), np.asarray(Wt)], 1)
+    qp, tp = body_move(q, theta, dQ, 0.5 * delta)
+    qm, tm = body_move(q, theta, dQ, -0.5 * delta)
+    posp, posm = body_blobs(qp, tp, ref, body_offsets), body_blobs(qm, tm, ref, body_offsets)
+    Kp, Km = body_K(posp, qp, body_offsets), body_K(posm, qm, body_offsets)
+    lam_flat = lam_r.reshape(-1)
+    DF = ((Kp.T @ lam_flat - Km.T @ lam_flat) / delta).reshape(-1, 6)
+    DS = (matvec(posp, lam_r, a, eta, box=box) - matvec(posm, lam_r, a, eta, box=box)) / delta
+    DS -= ((Kp @ U_r.reshape(-1) - Km @ U_r.reshape(-1)) / delta).reshape(-1, 3)
+    root = dense_sqrt(pos0, Wn, body_offsets, a, eta, box=box)
+    c = math.sqrt(2.0 * kT / dt)
+    _, U0 = rigid_solve(pos0, q, body_offsets, DS + c * root, np.asarray(FT) - DF, a, eta, box)
+    q1, t1 = body_move(q, theta, U0, dt)
+    return q1, t1, {"lam_rfd": lam_r, "U_rfd": U_r, "dQ": dQ, "DF": DF, "DS": DS, "root": root, "U0": U0,
+                    "pos_plus": posp, "pos_minus": posm}

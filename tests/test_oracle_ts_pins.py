@@ -1,11 +1,13 @@
-"""Pins of the oracle's body kinematics (quaternion appendix) and of its
-Trapezoidal Slip step (Alg. 2).
+"""Pins of the oracle's body kinematics (quaternion appendix), of its
+Trapezoidal Slip step (Alg. 2) and of its Euler-Maruyama Traction step
+(Alg. 1).
 
 Independent references: scipy's rotation routines for the quaternion
-updates, the deterministic trapezoidal (Heun) method with the body mobility
-N formed by a separate Cholesky route for kT = 0, the dual-number
-vector-Jacobian product of M for the slip drift D^S, and the small-angle
-rotation formula for the force drift D^F."""
+updates, the deterministic trapezoidal (Heun) and forward Euler methods
+with the body mobility N formed by a separate Cholesky route for kT = 0, the
+dual-number vector-Jacobian product of M for the slip drifts D^S, and the
+small-angle rotation formula for the force drifts D^F and the K part of the
+traction drift."""
 import numpy as np
 import pytest
 from scipy.spatial.transform import Rotation
@@ -125,3 +127,47 @@ def test_force_drift_is_the_rotation_of_the_lever_arms(orc):
         dth = it["dQ_rfd"][p, 3:]
         expect = np.cross(np.cross(dth, d), it["WF"][15 * p:15 * p + 15]).sum(0)
         np.testing.assert_allclose(it["DF"][p, 3:], expect, rtol=1e-6, atol=1e-9 * np.abs(expect).max())
+
+
+def test_emt_deterministic_limit_is_forward_euler(orc):
+    """kT = 0: Q^{n+1} = Q^n + dt N F with N from a Cholesky route."""
+    q, th, ref, offs = _boomerangs(3, 20)
+    force = _harmonic(q + 0.5)
+    Wf, Wt = np.random.default_rng(21).standard_normal((2, 3, 3))
+    Wn = wl.gaussian(ref.shape, 22)
+    F0 = force(q, th)
+    q1, t1, _ = orc.emt_step(q, th, ref, offs, np.full(3, 4.0), F0, Wf, Wt, Wn, kT=0.0, dt=0.2, delta=1e-4)
+    pos = orc.body_blobs(q, th, ref, offs)
+    U = (orc.body_mobility(pos, q, offs) @ F0.reshape(-1)).reshape(-1, 6)
+    qe, te = orc.body_move(q, th, U, 0.2)
+    np.testing.assert_allclose(q1, qe, atol=1e-10)
+    np.testing.assert_allclose(orc.quat_matrix(t1), orc.quat_matrix(te), atol=1e-10)
+
+
+def test_emt_drifts_are_directional_derivatives(orc):
+    """D^S = [M(Q+) - M(Q-)] lambda / delta - [K(Q+) - K(Q-)] U / delta and
+    D^F = [K^T(Q+) - K^T(Q-)] lambda / delta against their first-order
+    expansions: the dual-number VJP of M along the blob displacement, and
+    the rotation of the lever arms d -> dtheta x d."""
+    q, th, ref, offs = _boomerangs(3, 23)
+    Lp = np.array([3.0, 4.0, 5.0])
+    Wf, Wt = np.random.default_rng(24).standard_normal((2, 3, 3))
+    delta = 1e-5
+    _, _, it = orc.emt_step(q, th, ref, offs, Lp, np.zeros((3, 6)), Wf, Wt, wl.gaussian(ref.shape, 25), kT=0.9,
+                            dt=0.1, delta=delta)
+    pos0 = orc.body_blobs(q, th, ref, offs)
+    dr = (it["pos_plus"] - it["pos_minus"]) / delta
+    lam, U = it["lam_rfd"], it["U_rfd"]
+    dth = Wt  # rotation part of dQ = [L_p W^f, W^tau]
+    kpart = np.concatenate([np.cross(U[p, 3:], np.cross(dth[p], pos0[15 * p:15 * p + 15] - q[p]))
+                            for p in range(3)])
+    for seed in (26, 27):
+        g = wl.gaussian(ref.shape, seed)
+        gp, _ = orc.vjp(pos0, lam, g)
+        expect = float((gp * dr).sum()) - float((g * kpart).sum())
+        assert abs(float((g * it["DS"]).sum()) - expect) <= 1e-6 * abs(expect)
+    for p in range(3):
+        d = pos0[15 * p:15 * p + 15] - q[p]
+        expect = np.cross(np.cross(dth[p], d), lam[15 * p:15 * p + 15]).sum(0)
+        np.testing.assert_allclose(it["DF"][p, 3:], expect, rtol=1e-6, atol=1e-9 * np.abs(expect).max())
+        assert np.abs(it["DF"][p, :3]).max() <= 1e-9 * np.abs(expect).max()
