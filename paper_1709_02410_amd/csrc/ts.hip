@@ -1,6 +1,7 @@
-// Trapezoidal Slip (T-S) step for rigid multiblobs (arXiv:1709.02410,
-// Alg. 2, with the slip-corrected random finite difference of Sec. IV),
-// split in two calls around the caller's force evaluation:
+// Temporal integrators for rigid multiblobs (arXiv:1709.02410, Sec. IV).
+//
+// Trapezoidal Slip (T-S, Alg. 2, with the slip-corrected random finite
+// difference), split in two calls around the caller's force evaluation:
 //
 //   predict: W^D = [L_p W^s_p], W^F = [kT / L_p W^s_p];
 //            dQ^RFD from the saddle-point problem with slip W^D, F = 0;
@@ -13,6 +14,13 @@
 //            force F^n; Q~ = Q^n + dt U^n.
 //   correct: U~ at Q~ with slip 2 D^S + c M^{1/2} W^n and force F(Q~) - 2 D^F;
 //            Q^{n+1} = Q^n + dt/2 (U^n + U~).
+//
+// Euler-Maruyama Traction (EM-T, Alg. 1, with the traction-corrected random
+// finite difference), one call: W^FT_p = kT [W^f_p / L_p, W^tau_p]; the RFD
+// problem with no slip and force W^FT gives lambda^RFD, U^RFD; Q+- = Q^n +-
+// delta/2 [L_p W^f, W^tau]; D^F = [K^T(Q+) - K^T(Q-)] lambda^RFD / delta,
+// D^S = [M(Q+) - M(Q-)] lambda^RFD / delta - [K(Q+) - K(Q-)] U^RFD / delta;
+// U^n from slip D^S + c M^{1/2} W^n and force F^n - D^F; Q^{n+1} = Q^n + dt U^n.
 //
 // Bodies: tracking point q_p and unit quaternion theta_p = (s, p); blob i
 // of body p sits at q_p + R(theta_p) rho_i with rho_i its body-frame
@@ -129,6 +137,37 @@ __global__ void lincomb_kernel(const double* __restrict__ x, double ax, const do
     if (e < n) out[e] = ax * x[e] + (y ? ay * y[e] : 0.0);
 }
 
+// EM-T: W^FT_p = kT [W^f_p / L_p, W^tau_p] and dQ_p = [L_p W^f_p, W^tau_p].
+__global__ void traction_vectors_kernel(const double* __restrict__ Wf, const double* __restrict__ Wt,
+                                        const double* __restrict__ Lp, double kT, int nb, double* __restrict__ WFT,
+                                        double* __restrict__ dQ) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    for (int c = 0; c < 3; ++c) {
+        WFT[6 * b + c] = kT * Wf[3 * b + c] / Lp[b];
+        WFT[6 * b + 3 + c] = kT * Wt[3 * b + c];
+        dQ[6 * b + c] = Lp[b] * Wf[3 * b + c];
+        dQ[6 * b + 3 + c] = Wt[3 * b + c];
+    }
+}
+
+// DS_i -= ([K(Q+) - K(Q-)] U)_i / delta = omega_p x ((r+_i - q+_p) - (r-_i - q-_p)) / delta
+// (the translational parts cancel).
+__global__ __launch_bounds__(kTT) void k_drift_kernel(const double* __restrict__ posp, const double* __restrict__ qp,
+                                                     const double* __restrict__ posm, const double* __restrict__ qm,
+                                                     const double* __restrict__ U, const int* __restrict__ bofs,
+                                                     double inv_delta, double* __restrict__ DS) {
+    const int b = blockIdx.x;
+    const double wx = U[6 * b + 3], wy = U[6 * b + 4], wz = U[6 * b + 5];
+    for (int i = bofs[b] + threadIdx.x; i < bofs[b + 1]; i += blockDim.x) {
+        double e[3];
+        for (int c = 0; c < 3; ++c) e[c] = (posp[3 * i + c] - qp[3 * b + c]) - (posm[3 * i + c] - qm[3 * b + c]);
+        DS[3 * i] -= (wy * e[2] - wz * e[1]) * inv_delta;
+        DS[3 * i + 1] -= (wz * e[0] - wx * e[2]) * inv_delta;
+        DS[3 * i + 2] -= (wx * e[1] - wy * e[0]) * inv_delta;
+    }
+}
+
 unsigned gridn(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 struct Bodies {
@@ -182,10 +221,11 @@ size_t ts_state_bytes(int64_t N, int nb) {
 size_t ts_ws_bytes(int64_t N, int max_iter, int nb, int prec) {
     const size_t n3 = (size_t)3 * N;
     size_t b = align_up((size_t)(nb + 1) * sizeof(int));
-    b += 9 * align_up(n3 * sizeof(double));                 // pos0, WD, WF (x2), lam, pos+-, U+-
-    b += align_up(n3 * sizeof(double));                     // slip
-    b += 4 * align_up((size_t)6 * nb * sizeof(double));     // dQ, F, q+-, theta+-
-    b += 2 * align_up((size_t)4 * nb * sizeof(double));
+    // T-S: pos0, W^D, W^F (x2), lambda, pos+-, U+-, slip; EM-T: pos0,
+    // lambda (x2), pos+-, U+-, D^S, slip
+    b += 10 * align_up(n3 * sizeof(double));
+    b += 8 * align_up((size_t)6 * nb * sizeof(double));     // body vectors (q+- counts as one)
+    b += 2 * align_up((size_t)4 * nb * sizeof(double));     // theta+-
     size_t sub = rigid_ws_bytes(N, max_iter, nb, prec);
     sub = std::max(sub, lanczos_ws_bytes(N, max_iter, nb, prec));
     sub = std::max(sub, batched_ws_bytes(2 * N, 2, 1, prec));
@@ -298,6 +338,82 @@ int ts_correct(const double* q, const double* theta, const double* q_t, const do
     if (rc < 0) return rc;
     const int status = rc;
     if ((rc = body_move(q, theta, U0, Ut, 0.5 * dt, nb, q_next, theta_next, st))) return rc;
+    RPYW_HIP(hipStreamSynchronize(st));
+    return status;
+}
+
+int emt_step(const double* q, const double* theta, const double* ref, const int64_t* body_offsets, int nb, int64_t N,
+             const double* Lp, const double* FT, const double* Wf, const double* Wt, const double* Wn, double kT,
+             double dt, double delta, double a, double eta, const Domain& dom, double tol, int max_iter, int prec,
+             double* q_next, double* theta_next, Arena& ar, int* iters, hipStream_t st) {
+    const int64_t n3 = 3 * N, n6 = 6 * (int64_t)nb;
+    Bodies bd;
+    int rc = upload_bodies(body_offsets, nb, ar, st, bd);
+    if (rc) return rc;
+    double* pos0 = (double*)ar.take(n3 * sizeof(double));
+    double* lam2 = (double*)ar.take(2 * n3 * sizeof(double));  // lambda^RFD twice (both RFD systems)
+    double* pospm = (double*)ar.take(2 * n3 * sizeof(double));
+    double* Upm = (double*)ar.take(2 * n3 * sizeof(double));
+    double* DS = (double*)ar.take(n3 * sizeof(double));
+    double* slip = (double*)ar.take(n3 * sizeof(double));
+    double* WFT = (double*)ar.take(n6 * sizeof(double));
+    double* dQ = (double*)ar.take(n6 * sizeof(double));
+    double* Ur = (double*)ar.take(n6 * sizeof(double));
+    double* DF = (double*)ar.take(n6 * sizeof(double));
+    double* F = (double*)ar.take(n6 * sizeof(double));
+    double* U0 = (double*)ar.take(n6 * sizeof(double));
+    double* qpm = (double*)ar.take(n6 * sizeof(double));
+    double* thpm = (double*)ar.take((size_t)8 * nb * sizeof(double));
+    if (!pos0 || !lam2 || !pospm || !Upm || !DS || !slip || !WFT || !dQ || !Ur || !DF || !F || !U0 || !qpm || !thpm)
+        return RPYW_ENOMEM;
+    int status = RPYW_OK, it = 0;
+    double res = 0.0, err = 0.0;
+    if ((rc = body_blobs(q, theta, ref, bd.bofs, nb, pos0, st))) return rc;
+    hipLaunchKernelGGL(traction_vectors_kernel, dim3(gridn(nb)), dim3(256), 0, st, Wf, Wt, Lp, kT, nb, WFT, dQ);
+    RPYW_HIP(hipGetLastError());
+    // RFD mobility problem: no slip, random force and torque W^FT (the
+    // sub-solvers keep what they take from the arena: rewound after each)
+    const size_t mark = ar.used;
+    rc = rigid_solve(pos0, q, body_offsets, nb, nullptr, WFT, lam2, Ur, N, a, eta, tol, max_iter, prec, ar, &it, &res,
+                     st, dom);
+    ar.used = mark;
+    iters[0] = it;
+    if (rc < 0) return rc;
+    merge(status, rc);
+    if ((rc = lincomb(lam2, 1.0, nullptr, 0.0, n3, lam2 + n3, st))) return rc;
+    if ((rc = body_move(q, theta, dQ, nullptr, 0.5 * delta, nb, qpm, thpm, st))) return rc;
+    if ((rc = body_move(q, theta, dQ, nullptr, -0.5 * delta, nb, qpm + 3 * nb, thpm + 4 * nb, st))) return rc;
+    if ((rc = body_blobs(qpm, thpm, ref, bd.bofs, nb, pospm, st))) return rc;
+    if ((rc = body_blobs(qpm + 3 * nb, thpm + 4 * nb, ref, bd.bofs, nb, pospm + n3, st))) return rc;
+    hipLaunchKernelGGL(force_drift_kernel, dim3(nb), dim3(kTT), 0, st, pospm, qpm, pospm + n3, qpm + 3 * nb, lam2,
+                       bd.bofs, 1.0 / delta, DF);
+    RPYW_HIP(hipGetLastError());
+    if (dom.periodic()) {
+        if ((rc = products(pospm, lam2, Upm, N, 1, a, eta, prec, ar, st, dom))) return rc;
+        if ((rc = products(pospm + n3, lam2, Upm + n3, N, 1, a, eta, prec, ar, st, dom))) return rc;
+    } else {
+        const int64_t so[3] = {0, N, 2 * N};
+        if ((rc = batched_products(pospm, so, 2, lam2, Upm, 1, a, eta, prec, ar, st))) return rc;
+    }
+    if ((rc = lincomb(Upm, 1.0 / delta, Upm + n3, -1.0 / delta, n3, DS, st))) return rc;
+    hipLaunchKernelGGL(k_drift_kernel, dim3(nb), dim3(kTT), 0, st, pospm, qpm, pospm + n3, qpm + 3 * nb, Ur, bd.bofs,
+                       1.0 / delta, DS);
+    RPYW_HIP(hipGetLastError());
+    // Brownian slip and the mobility problem
+    rc = lanczos_sqrt(pos0, Wn, slip, N, a, eta, body_offsets, nb, tol, max_iter, prec, ar, &it, &err, st, dom);
+    ar.used = mark;
+    iters[1] = it;
+    if (rc < 0) return rc;
+    merge(status, rc);
+    if ((rc = lincomb(slip, std::sqrt(2.0 * kT / dt), DS, 1.0, n3, slip, st))) return rc;
+    if ((rc = lincomb(FT, 1.0, DF, -1.0, n6, F, st))) return rc;
+    rc = rigid_solve(pos0, q, body_offsets, nb, slip, F, lam2, U0, N, a, eta, tol, max_iter, prec, ar, &it, &res, st,
+                     dom);
+    ar.used = mark;
+    iters[2] = it;
+    if (rc < 0) return rc;
+    merge(status, rc);
+    if ((rc = body_move(q, theta, U0, nullptr, dt, nb, q_next, theta_next, st))) return rc;
     RPYW_HIP(hipStreamSynchronize(st));
     return status;
 }

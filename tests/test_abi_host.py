@@ -93,6 +93,10 @@ def test_validation_rejects_before_any_launch(lib):
     assert lib.rpy_wall_ts_correct(dummy, dummy, dummy, dummy, dummy, offs, 2, 9, dummy, None, 0.1, 1.0, 1.0, 0.0,
                                    0.0, 1e-3, 50, 0, dummy, dummy, None, 0, ctypes.byref(it), None) == E
     assert lib.rpy_wall_body_move(dummy, dummy, None, 0.1, 2, dummy, dummy, None) == E
+    assert lib.rpy_wall_emt_step(dummy, dummy, dummy, offs, 2, 9, dummy, dummy, dummy, None, dummy, 1.0, 0.1, 1e-3,
+                                 1.0, 1.0, 0.0, 0.0, 1e-3, 50, 0, dummy, dummy, None, 0, i3, None) == E  # Wt missing
+    assert lib.rpy_wall_emt_step(dummy, dummy, dummy, offs, 2, 9, dummy, dummy, dummy, dummy, dummy, 1.0, 0.1, 1e-3,
+                                 1.0, 1.0, 5.0, 0.0, 1e-3, 50, 0, dummy, dummy, None, 0, i3, None) == E  # half a cell
     assert lib.rpy_wall_body_blobs(dummy, dummy, dummy, bad_offs, 2, dummy, 5, None, 0, None) == E
     # misaligned caller workspace
     assert lib.rpy_wall_matvec(dummy, dummy, dummy, 10, 1.0, 1.0, 0, ctypes.c_void_p(0x1001), 1 << 20,

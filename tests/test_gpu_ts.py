@@ -94,7 +94,7 @@ def test_ts_step_matches_oracle(rp, orc, prec, periodic):
     rel_tilde = np.linalg.norm(qT.cpu().numpy() - inter["q_tilde"]) / np.linalg.norm(inter["q_tilde"] - q)
     print(f"T-S prec={prec} periodic={periodic} iters={step.iters} rel dq={rel_q:.2e} dtheta={rel_t:.2e} "
           f"q~={rel_tilde:.2e}", flush=True)
-    bound = 1e-7 if prec == 0 else 5e-3
+    bound = 1e-10 if prec == 0 else 1e-5
     assert rel_q <= bound and rel_t <= bound and rel_tilde <= bound
     np.testing.assert_allclose(np.linalg.norm(t1, axis=1), 1.0, atol=1e-13)
 
@@ -109,3 +109,26 @@ def test_ts_zero_temperature_is_deterministic_heun(rp, orc):
                        _t(Wn))
     q1r, t1r, _ = orc.ts_step(q, th, ref, offs, np.full(4, 3.0), force, Ws, Wn, kT=0.0, dt=0.1, delta=1e-4)
     assert np.linalg.norm(q1.cpu().numpy() - q1r) <= 1e-9 * np.linalg.norm(q1r - q)
+
+
+@pytest.mark.parametrize("prec,periodic", [(0, False), (0, True), (1, False)])
+def test_emt_step_matches_oracle(rp, orc, prec, periodic):
+    nb = 6
+    q, th, ref, offs = _suspension(nb, 9)
+    box = (30.0, 28.0) if periodic else None
+    Lp = np.full(nb, 3.0)
+    rng = np.random.default_rng(10)
+    Wf, Wt = rng.standard_normal((nb, 3)), rng.standard_normal((nb, 3))
+    Wn = wl.gaussian(ref.shape, 11)
+    F0 = _force(q + np.array([0.3, -0.2, 0.1]))(q, th)
+    kT, dt = 0.8, 0.05
+    delta = 1e-4 if prec == 0 else 1e-2
+    q1r, t1r, _ = orc.emt_step(q, th, ref, offs, Lp, F0, Wf, Wt, Wn, kT=kT, dt=dt, delta=delta, box=box)
+    q1, t1, iters = rp.emt_step(_t(q), _t(th), _t(ref), offs, _t(Lp), _t(F0), _t(Wf), _t(Wt), _t(Wn), kT, dt,
+                                delta, tol=1e-12 if prec == 0 else 1e-9, max_iter=400, precision=prec, box=box)
+    q1, t1 = q1.cpu().numpy(), t1.cpu().numpy()
+    rel_q = np.linalg.norm((q1 - q) - (q1r - q)) / np.linalg.norm(q1r - q)
+    rel_t = np.linalg.norm((t1 - th) - (t1r - th)) / np.linalg.norm(t1r - th)
+    print(f"EM-T prec={prec} periodic={periodic} iters={iters} rel dq={rel_q:.2e} dtheta={rel_t:.2e}", flush=True)
+    bound = 1e-10 if prec == 0 else 1e-5
+    assert rel_q <= bound and rel_t <= bound
