@@ -25,8 +25,9 @@ Contents (arXiv:1709.02410):
     per-body block-diagonal operator (Sec. II.B); used for iteration counts.
   * ``quat_rotate``/``body_blobs``/``body_move``/``ts_step``: body kinematics
     with unit quaternions (appendix on quaternions), one step of the
-    Trapezoidal Slip scheme (Alg. 2) and one of the Euler-Maruyama Traction
-    scheme (Alg. 1, ``emt_step``), with dense solves.
+    Trapezoidal Slip scheme (Alg. 2), of the Euler-Maruyama Traction scheme
+    (Alg. 1, ``emt_step``) and of the Euler-Maruyama RFD scheme (Alg. 3,
+    ``emrfd_step``), with dense solves.
   * ``box=(Lx, Ly)`` on the products, dense matrices, roots and solves: the
     pseudo-periodic domain of the paper's suspensions (Sec. V): each source
     at its minimum image plus the 8 periodic images around it.
@@ -606,3 +607,27 @@ def emt_step(q, theta, ref, body_offsets, Lp, FT, Wf, Wt, Wn, kT: float, dt: flo
     q1, t1 = body_move(q, theta, U0, dt)
     return q1, t1, {"lam_rfd": lam_r, "U_rfd": U_r, "dQ": dQ, "DF": DF, "DS": DS, "root": root, "U0": U0,
                     "pos_plus": posp, "pos_minus": posm}
+
+
+def emrfd_step(q, theta, ref, body_offsets, Lp, FT, Wf, Wt, Wn, kT: float, dt: float, delta: float,
+               a: float = 1.0, eta: float = 1.0, box=None):
+    """One Euler-Maruyama RFD step (Alg. 3), with dense linear algebra:
+      1. W^FT_p = kT [W^f_p / L_p, W^tau_p]; Q+- = Q^n +- delta/2 [L_p W^f_p, W^tau_p];
+         U+- from the mobility problems at Q+- with no slip and force W^FT;
+      2. (M^{1/2})^n W^n (block-preconditioned root);
+      3. U^n: slip sqrt(2 kT / dt) M^{1/2} W^n, force F^n;
+      4. Q^{n+1} = Q^n + dt (U^n + (U+ - U-) / delta).
+    Returns (q1, theta1, intermediates dict)."""
+    Lp = np.asarray(Lp, dtype=np.float64)
+    WFT = kT * np.concatenate([np.asarray(Wf) / Lp[:, None], np.asarray(Wt)], 1)
+    dQ = np.concatenate([Lp[:, None] * np.asarray(Wf), np.asarray(Wt)], 1)
+    qp, tp = body_move(q, theta, dQ, 0.5 * delta)
+    qm, tm = body_move(q, theta, dQ, -0.5 * delta)
+    _, Up = rigid_solve(body_blobs(qp, tp, ref, body_offsets), qp, body_offsets, None, WFT, a, eta, box)
+    _, Um = rigid_solve(body_blobs(qm, tm, ref, body_offsets), qm, body_offsets, None, WFT, a, eta, box)
+    pos0 = body_blobs(q, theta, ref, body_offsets)
+    root = dense_sqrt(pos0, Wn, body_offsets, a, eta, box=box)
+    _, U0 = rigid_solve(pos0, q, body_offsets, math.sqrt(2.0 * kT / dt) * root, FT, a, eta, box)
+    q1, t1 = body_move(q, theta, U0 + (Up - Um) / delta, dt)
+    return q1, t1, {"U_plus": Up, "U_minus": Um, "U0": U0, "WFT": WFT, "q_plus": qp, "theta_plus": tp,
+                    "q_minus": qm, "theta_minus": tm}

@@ -171,3 +171,26 @@ def test_emt_drifts_are_directional_derivatives(orc):
         expect = np.cross(np.cross(dth[p], d), lam[15 * p:15 * p + 15]).sum(0)
         np.testing.assert_allclose(it["DF"][p, 3:], expect, rtol=1e-6, atol=1e-9 * np.abs(expect).max())
         assert np.abs(it["DF"][p, :3]).max() <= 1e-9 * np.abs(expect).max()
+
+
+def test_emrfd_drift_is_the_rfd_of_the_body_mobility(orc):
+    """EM-RFD (Alg. 3): (U+ - U-) / delta equals [N(Q+) - N(Q-)] W^FT / delta
+    with N = (K^T M^-1 K)^-1 formed by Cholesky at both configurations, and
+    kT = 0 reduces the step to forward Euler."""
+    q, th, ref, offs = _boomerangs(3, 30)
+    Lp = np.array([3.0, 4.0, 5.0])
+    Wf, Wt = np.random.default_rng(31).standard_normal((2, 3, 3))
+    Wn = wl.gaussian(ref.shape, 32)
+    F0 = _harmonic(q + 0.5)(q, th)
+    _, _, it = orc.emrfd_step(q, th, ref, offs, Lp, F0, Wf, Wt, Wn, kT=0.9, dt=0.1, delta=1e-4)
+
+    def N_of(qq, tt):
+        return orc.body_mobility(orc.body_blobs(qq, tt, ref, offs), qq, offs)
+
+    expect = (N_of(it["q_plus"], it["theta_plus"]) - N_of(it["q_minus"], it["theta_minus"])) @ it["WFT"].reshape(-1)
+    got = (it["U_plus"] - it["U_minus"]).reshape(-1)
+    np.testing.assert_allclose(got, expect, rtol=0, atol=1e-9 * np.abs(expect).max())
+    q1, t1, _ = orc.emrfd_step(q, th, ref, offs, Lp, F0, Wf, Wt, Wn, kT=0.0, dt=0.2, delta=1e-4)
+    U = (N_of(q, th) @ F0.reshape(-1)).reshape(-1, 6)
+    qe, te = orc.body_move(q, th, U, 0.2)
+    np.testing.assert_allclose(q1, qe, atol=1e-10)
