@@ -324,6 +324,17 @@ def main():
                 rows["emt_step_periodic_paperlike_256_fp32c_tol0.001"] = {
                     "blobs": PB.N, "bodies": nbody, "ms_per_step": (time.perf_counter() - t0) / 3 * 1e3,
                     "iterations_rfd_lanczos_solve": ite, "products_per_step": sum(ite) + 2}
+                emr = lambda: rp.emt_step(qb, thb, refb, PB.body_offsets, Lpb, Fb, Wfb, Wtb, Wnb, 1.0, 0.01,  # noqa
+                                          1e-3, tol=1e-3, precision=rp.FP32C, box=(Lc, Lc), scheme="emrfd")
+                emr()
+                sync()
+                t0 = time.perf_counter()
+                for _ in range(3):
+                    _, _, ite = emr()
+                sync()
+                rows["emrfd_step_periodic_paperlike_256_fp32c_tol0.001"] = {
+                    "blobs": PB.N, "bodies": nbody, "ms_per_step": (time.perf_counter() - t0) / 3 * 1e3,
+                    "iterations_rfd_rfd_lanczos_solve": ite, "products_per_step": sum(ite)}
             del ppb, fpb
         C2 = wl.config2(seed=0)
         pc2, W2 = T(C2.pos), T(wl.gaussian(C2.pos.shape, 3))

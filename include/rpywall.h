@@ -63,7 +63,7 @@ enum rpyw_op {
     RPYW_OP_VJP = 3,        /* rpy_wall_matvec_vjp */
     RPYW_OP_DIVERGENCE = 4, /* rpy_wall_divergence */
     RPYW_OP_RIGID = 5,      /* rpy_wall_rigid_solve (and _periodic) */
-    RPYW_OP_TS = 6          /* rpy_wall_ts_predict / _correct, rpy_wall_emt_step */
+    RPYW_OP_TS = 6          /* rpy_wall_ts_predict / _correct, rpy_wall_emt_step, _emrfd_step */
 };
 
 /* u = M(r) f  (Sec. II.A: the dense product whose cost dominates every
@@ -247,6 +247,19 @@ int rpy_wall_emt_step(const double* q, const double* theta, const double* ref, c
                       const double* Wt, const double* Wn, double kT, double dt, double delta, double a, double eta,
                       double Lx, double Ly, double tol, int32_t max_iter, int precision, double* q_next,
                       double* theta_next, void* ws, size_t ws_bytes, int32_t* iters_out, void* stream);
+
+/* One step of the Euler-Maruyama RFD scheme (Alg. 3): U+- from the
+ * mobility problems at Q+- = Q^n +- delta/2 [L_p W^f_p, W^tau_p] with no
+ * slip and force W^FT (as for rpy_wall_emt_step); U^n from the mobility
+ * problem at Q^n with slip sqrt(2 kT / dt) M^{1/2} W^n and force F^n;
+ * Q^{n+1} = Q^n + dt (U^n + (U+ - U-) / delta).  Arguments as for
+ * rpy_wall_emt_step; iters_out (HOST [4], may be NULL): the two RFD solves,
+ * Lanczos, the mobility solve.  Synchronises `stream`. */
+int rpy_wall_emrfd_step(const double* q, const double* theta, const double* ref, const int64_t* body_offsets,
+                        int32_t n_bodies, int64_t N, const double* Lp, const double* force_torque, const double* Wf,
+                        const double* Wt, const double* Wn, double kT, double dt, double delta, double a, double eta,
+                        double Lx, double Ly, double tol, int32_t max_iter, int precision, double* q_next,
+                        double* theta_next, void* ws, size_t ws_bytes, int32_t* iters_out, void* stream);
 
 /* Vector-Jacobian product of u = M(r) f for L = sum_i g_i . u_i
  * (derivatives of M drive the thermal drift, Sec. III):

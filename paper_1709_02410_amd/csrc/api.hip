@@ -419,6 +419,28 @@ int rpy_wall_emt_step(const double* q, const double* theta, const double* ref, c
     return rc;
 }
 
+int rpy_wall_emrfd_step(const double* q, const double* theta, const double* ref, const int64_t* body_offsets,
+                        int32_t n_bodies, int64_t N, const double* Lp, const double* force_torque, const double* Wf,
+                        const double* Wt, const double* Wn, double kT, double dt, double delta, double a, double eta,
+                        double Lx, double Ly, double tol, int32_t max_iter, int precision, double* q_next,
+                        double* theta_next, void* ws, size_t ws_bytes, int32_t* iters_out, void* stream) {
+    if (!q || !theta || !ref || !Lp || !force_torque || !Wf || !Wt || !Wn || !q_next || !theta_next || N < 1 ||
+        N >= kMaxN || !valid_bodies(body_offsets, n_bodies, N) || !(kT >= 0.0) || !std::isfinite(kT) ||
+        !finite_pos(dt) || !finite_pos(delta) || !finite_pos(a) || !finite_pos(eta) || !valid_cell(Lx, Ly) ||
+        !finite_pos(tol) || max_iter < 1 || max_iter > 100000 || !valid_prec(precision))
+        return RPYW_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    Scratch s;
+    int rc = acquire(ws, ws_bytes, ts_ws_bytes(N, max_iter, n_bodies, precision), st, s);
+    if (rc != RPYW_OK) return rc;
+    int it[4] = {0, 0, 0, 0};
+    rc = emrfd_step(q, theta, ref, body_offsets, n_bodies, N, Lp, force_torque, Wf, Wt, Wn, kT, dt, delta, a, eta,
+                    Domain{Lx, Ly}, tol, max_iter, precision, q_next, theta_next, s.ar, it, st);
+    if (iters_out)
+        for (int k = 0; k < 4; ++k) iters_out[k] = it[k];
+    return rc;
+}
+
 int rpy_wall_matvec_vjp(const double* pos, const double* force, const double* grad_vel, double* grad_pos,
                         double* grad_force, int64_t N, double a, double eta, int precision, void* ws,
                         size_t ws_bytes, void* stream) {

@@ -180,6 +180,11 @@ int emt_step(const double* q, const double* theta, const double* ref, const int6
              double dt, double delta, double a, double eta, const Domain& dom, double tol, int max_iter, int prec,
              double* q_next, double* theta_next, Arena& ar, int* iters, hipStream_t st);
 
+int emrfd_step(const double* q, const double* theta, const double* ref, const int64_t* body_offsets, int nb,
+               int64_t N, const double* Lp, const double* FT, const double* Wf, const double* Wt, const double* Wn,
+               double kT, double dt, double delta, double a, double eta, const Domain& dom, double tol, int max_iter,
+               int prec, double* q_next, double* theta_next, Arena& ar, int* iters, hipStream_t st);
+
 // Derivatives (vjp.hip)
 size_t vjp_ws_bytes(int64_t N, int prec);
 int vjp(const double* pos, const double* f, const double* g, double* grad_pos, double* grad_f, int64_t N, double a,

@@ -22,6 +22,11 @@
 // D^S = [M(Q+) - M(Q-)] lambda^RFD / delta - [K(Q+) - K(Q-)] U^RFD / delta;
 // U^n from slip D^S + c M^{1/2} W^n and force F^n - D^F; Q^{n+1} = Q^n + dt U^n.
 //
+// Euler-Maruyama RFD (EM-RFD, Alg. 3), one call: U+- from the mobility
+// problems at Q+- = Q^n +- delta/2 [L_p W^f, W^tau] with no slip and force
+// W^FT; U^n at Q^n from slip c M^{1/2} W^n and force F^n;
+// Q^{n+1} = Q^n + dt (U^n + (U+ - U-) / delta).
+//
 // Bodies: tracking point q_p and unit quaternion theta_p = (s, p); blob i
 // of body p sits at q_p + R(theta_p) rho_i with rho_i its body-frame
 // position; Q + h U moves q_p by h u_p and rotates theta_p by the rotation
@@ -130,9 +135,8 @@ __global__ __launch_bounds__(kTT) void force_drift_kernel(const double* __restri
     }
 }
 
-// out = ax x + ay y (y may be null).
-__global__ void lincomb_kernel(const double* __restrict__ x, double ax, const double* __restrict__ y, double ay,
-                               int64_t n, double* __restrict__ out) {
+// out = ax x + ay y (y may be null; out may be x or y).
+__global__ void lincomb_kernel(const double* x, double ax, const double* y, double ay, int64_t n, double* out) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < n) out[e] = ax * x[e] + (y ? ay * y[e] : 0.0);
 }
@@ -414,6 +418,65 @@ int emt_step(const double* q, const double* theta, const double* ref, const int6
     if (rc < 0) return rc;
     merge(status, rc);
     if ((rc = body_move(q, theta, U0, nullptr, dt, nb, q_next, theta_next, st))) return rc;
+    RPYW_HIP(hipStreamSynchronize(st));
+    return status;
+}
+
+int emrfd_step(const double* q, const double* theta, const double* ref, const int64_t* body_offsets, int nb,
+               int64_t N, const double* Lp, const double* FT, const double* Wf, const double* Wt, const double* Wn,
+               double kT, double dt, double delta, double a, double eta, const Domain& dom, double tol, int max_iter,
+               int prec, double* q_next, double* theta_next, Arena& ar, int* iters, hipStream_t st) {
+    const int64_t n3 = 3 * N, n6 = 6 * (int64_t)nb;
+    Bodies bd;
+    int rc = upload_bodies(body_offsets, nb, ar, st, bd);
+    if (rc) return rc;
+    double* pos = (double*)ar.take(n3 * sizeof(double));
+    double* lam = (double*)ar.take(n3 * sizeof(double));
+    double* WFT = (double*)ar.take(n6 * sizeof(double));
+    double* dQ = (double*)ar.take(n6 * sizeof(double));
+    double* Upm = (double*)ar.take(2 * n6 * sizeof(double));
+    double* U0 = (double*)ar.take(n6 * sizeof(double));
+    double* qpm = (double*)ar.take(n6 * sizeof(double));
+    double* thpm = (double*)ar.take((size_t)8 * nb * sizeof(double));
+    if (!pos || !lam || !WFT || !dQ || !Upm || !U0 || !qpm || !thpm) return RPYW_ENOMEM;
+    int status = RPYW_OK, it = 0;
+    double res = 0.0, err = 0.0;
+    hipLaunchKernelGGL(traction_vectors_kernel, dim3(gridn(nb)), dim3(256), 0, st, Wf, Wt, Lp, kT, nb, WFT, dQ);
+    RPYW_HIP(hipGetLastError());
+    const size_t mark = ar.used;
+    // the two RFD mobility problems at Q+ and Q- (no slip, force W^FT)
+    for (int sgn = 0; sgn < 2; ++sgn) {
+        double* qs = qpm + 3 * nb * sgn;
+        double* ts = thpm + 4 * nb * sgn;
+        if ((rc = body_move(q, theta, dQ, nullptr, sgn == 0 ? 0.5 * delta : -0.5 * delta, nb, qs, ts, st))) return rc;
+        if ((rc = body_blobs(qs, ts, ref, bd.bofs, nb, pos, st))) return rc;
+        rc = rigid_solve(pos, qs, body_offsets, nb, nullptr, WFT, lam, Upm + n6 * sgn, N, a, eta, tol, max_iter, prec,
+                         ar, &it, &res, st, dom);
+        ar.used = mark;
+        iters[sgn] = it;
+        if (rc < 0) return rc;
+        merge(status, rc);
+    }
+    // Brownian slip and the mobility problem at Q^n
+    if ((rc = body_blobs(q, theta, ref, bd.bofs, nb, pos, st))) return rc;
+    rc = lanczos_sqrt(pos, Wn, lam, N, a, eta, body_offsets, nb, tol, max_iter, prec, ar, &it, &err, st, dom);
+    ar.used = mark;
+    iters[2] = it;
+    if (rc < 0) return rc;
+    merge(status, rc);
+    if ((rc = lincomb(lam, std::sqrt(2.0 * kT / dt), nullptr, 0.0, n3, lam, st))) return rc;
+    double* lam0 = (double*)ar.take(n3 * sizeof(double));
+    if (!lam0) return RPYW_ENOMEM;
+    const size_t mark2 = ar.used;
+    rc = rigid_solve(pos, q, body_offsets, nb, lam, FT, lam0, U0, N, a, eta, tol, max_iter, prec, ar, &it, &res, st,
+                     dom);
+    ar.used = mark2;
+    iters[3] = it;
+    if (rc < 0) return rc;
+    merge(status, rc);
+    // U = U^n + (U+ - U-) / delta, then Q^{n+1} = Q^n + dt U
+    if ((rc = lincomb(Upm, 1.0 / delta, Upm + n6, -1.0 / delta, n6, Upm, st))) return rc;
+    if ((rc = body_move(q, theta, U0, Upm, dt, nb, q_next, theta_next, st))) return rc;
     RPYW_HIP(hipStreamSynchronize(st));
     return status;
 }

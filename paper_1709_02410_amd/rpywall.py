@@ -63,6 +63,8 @@ def lib():
                                 ctypes.c_int, vp, vp, vp, sz, ctypes.POINTER(i32), vp],
         "rpy_wall_emt_step": [vp, vp, vp, i64p, i32, i64, vp, vp, vp, vp, vp, dbl, dbl, dbl, dbl, dbl, dbl, dbl,
                               dbl, i32, ctypes.c_int, vp, vp, vp, sz, ctypes.POINTER(i32), vp],
+        "rpy_wall_emrfd_step": [vp, vp, vp, i64p, i32, i64, vp, vp, vp, vp, vp, dbl, dbl, dbl, dbl, dbl, dbl, dbl,
+                                dbl, i32, ctypes.c_int, vp, vp, vp, sz, ctypes.POINTER(i32), vp],
         "rpy_wall_matvec_vjp": [vp, vp, vp, vp, vp, i64, dbl, dbl, ctypes.c_int, vp, sz, vp],
         "rpy_wall_divergence": [vp, vp, i64, dbl, dbl, ctypes.c_int, vp, sz, vp],
         "rpy_wall_autotune": [vp, vp, vp, i64, i32, dbl, dbl, ctypes.c_int, vp, sz, vp],
@@ -351,9 +353,10 @@ class TSStep:
 def emt_step(q: torch.Tensor, theta: torch.Tensor, ref: torch.Tensor, body_offsets, Lp: torch.Tensor,
              force_torque: torch.Tensor, Wf: torch.Tensor, Wt: torch.Tensor, Wn: torch.Tensor, kT: float, dt: float,
              delta: float, a: float = 1.0, eta: float = 1.0, tol: float = 1e-3, max_iter: int = 200,
-             precision: int = FP64, box=None):
-    """One Euler-Maruyama Traction step (Alg. 1).  Returns (q^{n+1},
-    theta^{n+1}, [RFD solve, Lanczos, mobility solve] iterations)."""
+             precision: int = FP64, box=None, scheme: str = "emt"):
+    """One Euler-Maruyama step: the traction-corrected scheme (Alg. 1,
+    scheme="emt") or the RFD scheme (Alg. 3, scheme="emrfd").  Returns
+    (q^{n+1}, theta^{n+1}, iteration counts of the solves)."""
     offs = _offsets(body_offsets)
     nb, N = offs.shape[0] - 1, ref.shape[0]
     for t, n, sh in ((q, "q", (nb, 3)), (theta, "theta", (nb, 4)), (ref, "ref", (N, 3)), (Lp, "Lp", (nb,)),
@@ -363,14 +366,16 @@ def emt_step(q: torch.Tensor, theta: torch.Tensor, ref: torch.Tensor, body_offse
     box = (0.0, 0.0) if box is None else (float(box[0]), float(box[1]))
     q1, t1 = torch.empty_like(q), torch.empty_like(theta)
     ws = _workspace(workspace_bytes(OP_TS, N, 1, max_iter, nb, precision), q.device)
-    it = (ctypes.c_int32 * 3)()
-    st = lib().rpy_wall_emt_step(q.data_ptr(), theta.data_ptr(), ref.data_ptr(),
-                                 offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), nb, N, Lp.data_ptr(),
-                                 force_torque.data_ptr(), Wf.data_ptr(), Wt.data_ptr(), Wn.data_ptr(), kT, dt, delta,
-                                 a, eta, box[0], box[1], tol, max_iter, precision, q1.data_ptr(), t1.data_ptr(),
-                                 ws.data_ptr(), ws.numel(), it, _stream(q.device))
-    _check(st, "rpy_wall_emt_step", allow=(OK, NOT_CONVERGED))
-    return q1, t1, list(it)
+    if scheme not in ("emt", "emrfd"):
+        raise ValueError("scheme must be 'emt' or 'emrfd'")
+    it = (ctypes.c_int32 * 4)()
+    fn = lib().rpy_wall_emt_step if scheme == "emt" else lib().rpy_wall_emrfd_step
+    st = fn(q.data_ptr(), theta.data_ptr(), ref.data_ptr(), offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), nb,
+            N, Lp.data_ptr(), force_torque.data_ptr(), Wf.data_ptr(), Wt.data_ptr(), Wn.data_ptr(), kT, dt, delta, a,
+            eta, box[0], box[1], tol, max_iter, precision, q1.data_ptr(), t1.data_ptr(), ws.data_ptr(), ws.numel(),
+            it, _stream(q.device))
+    _check(st, f"rpy_wall_{scheme}_step", allow=(OK, NOT_CONVERGED))
+    return q1, t1, list(it)[:3 if scheme == "emt" else 4]
 
 
 def matvec_vjp(pos: torch.Tensor, force: torch.Tensor, grad_vel: torch.Tensor, a: float = 1.0, eta: float = 1.0,

@@ -1,5 +1,6 @@
-"""GPU body kinematics and Trapezoidal Slip step (Alg. 2) against the
-oracle's dense implementation, with the same random vectors and forces."""
+"""GPU body kinematics and the temporal integrators (Trapezoidal Slip,
+Alg. 2; Euler-Maruyama Traction, Alg. 1; Euler-Maruyama RFD, Alg. 3) against
+the oracle's dense implementations, with the same random vectors and forces."""
 import math
 
 import numpy as np
@@ -111,8 +112,10 @@ def test_ts_zero_temperature_is_deterministic_heun(rp, orc):
     assert np.linalg.norm(q1.cpu().numpy() - q1r) <= 1e-9 * np.linalg.norm(q1r - q)
 
 
+@pytest.mark.parametrize("scheme", ["emt", "emrfd"])
 @pytest.mark.parametrize("prec,periodic", [(0, False), (0, True), (1, False)])
-def test_emt_step_matches_oracle(rp, orc, prec, periodic):
+def test_em_steps_match_oracle(rp, orc, prec, periodic, scheme):
+    """Euler-Maruyama Traction (Alg. 1) and Euler-Maruyama RFD (Alg. 3)."""
     nb = 6
     q, th, ref, offs = _suspension(nb, 9)
     box = (30.0, 28.0) if periodic else None
@@ -123,12 +126,15 @@ def test_emt_step_matches_oracle(rp, orc, prec, periodic):
     F0 = _force(q + np.array([0.3, -0.2, 0.1]))(q, th)
     kT, dt = 0.8, 0.05
     delta = 1e-4 if prec == 0 else 1e-2
-    q1r, t1r, _ = orc.emt_step(q, th, ref, offs, Lp, F0, Wf, Wt, Wn, kT=kT, dt=dt, delta=delta, box=box)
+    ofn = orc.emt_step if scheme == "emt" else orc.emrfd_step
+    q1r, t1r, _ = ofn(q, th, ref, offs, Lp, F0, Wf, Wt, Wn, kT=kT, dt=dt, delta=delta, box=box)
     q1, t1, iters = rp.emt_step(_t(q), _t(th), _t(ref), offs, _t(Lp), _t(F0), _t(Wf), _t(Wt), _t(Wn), kT, dt,
-                                delta, tol=1e-12 if prec == 0 else 1e-9, max_iter=400, precision=prec, box=box)
+                                delta, tol=1e-12 if prec == 0 else 1e-9, max_iter=400, precision=prec, box=box,
+                                scheme=scheme)
     q1, t1 = q1.cpu().numpy(), t1.cpu().numpy()
     rel_q = np.linalg.norm((q1 - q) - (q1r - q)) / np.linalg.norm(q1r - q)
     rel_t = np.linalg.norm((t1 - th) - (t1r - th)) / np.linalg.norm(t1r - th)
-    print(f"EM-T prec={prec} periodic={periodic} iters={iters} rel dq={rel_q:.2e} dtheta={rel_t:.2e}", flush=True)
+    print(f"{scheme} prec={prec} periodic={periodic} iters={iters} rel dq={rel_q:.2e} dtheta={rel_t:.2e}",
+          flush=True)
     bound = 1e-10 if prec == 0 else 1e-5
     assert rel_q <= bound and rel_t <= bound
