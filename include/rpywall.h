@@ -306,10 +306,13 @@ int rpy_wall_autotune(const double* pos, const double* F, double* U, int64_t N, 
 /* Fix the launch shape used for products of this precision and size class
  * (the class of N: floor(log2 N); of k: next power of two up to 16) instead
  * of the tuner's choice.  tpl: targets per lane (1, 2); tile: LDS tile (64,
- * 256); kblk: RHS block width (1..16, FP64 up to 8); sym: 1 selects the
- * symmetric kernel, which evaluates each unordered pair once and applies it
- * in both directions (kblk <= 4); ipw: source groups per workgroup of the
- * symmetric kernel.  tpl = 0 removes the override (back to the tuner's or
+ * 256); kblk: RHS block width (1..16, FP64 up to 8); sym: 1 or 2 selects
+ * the symmetric kernel, which evaluates each unordered pair once and applies
+ * it in both directions (kblk <= 4), over groups of 256 blobs (1) or of 64
+ * blobs (2, more workgroups for small problems; taken for N <= 32768, else
+ * groups of 256); ipw: source groups per workgroup of the symmetric kernel.
+ * Pseudo-periodic products always use the symmetric kernel, over groups of
+ * 256 when sym is 1 and of 64 otherwise.  tpl = 0 removes the override (back to the tuner's or
  * the built-in choice).  Host-only, takes effect for later calls. */
 int rpy_wall_set_shape(int precision, int64_t N, int32_t k, int32_t tpl, int32_t tile, int32_t kblk, int32_t sym,
                        int32_t ipw);

@@ -74,17 +74,19 @@ int64_t g_prof_n = 0;
 }  // namespace
 
 // Defaults from measurements on MI355X: the symmetric kernel wins for one
-// right-hand side from a few thousand blobs up (1.7x at 1e5); wider RHS
-// blocks are faster on the plain kernel.  ipw keeps the symmetric grid at
-// roughly 16k workgroups or more.
+// right-hand side from about a thousand blobs up (1.7x at 1e5); groups of
+// 64 blobs, one item per workgroup, are up to 3x faster than groups of 256
+// below ten thousand blobs (which leave the GPU underfilled) and still 5% at
+// 30000; wider RHS blocks are faster on the plain kernel.  For groups of 256
+// ipw keeps the grid at roughly 16k workgroups or more.
 Shape default_shape(int64_t N, int k, int prec) {
     Shape s;
     s.tpl = N >= 65536 ? 2 : 1;
     s.tile = 64;
     s.kblk = std::min(kclass(k), prec == RPYW_FP32C ? 16 : 8);
-    s.sym = (s.kblk == 1 && N >= 2048) ? 1 : 0;
+    s.sym = (s.kblk == 1 && N >= 1024) ? (N <= kSym64MaxN ? 2 : 1) : 0;
     const int64_t ng = (N + 255) / 256, hm = ng / 2 + 1;
-    s.ipw = (int)std::max<int64_t>(1, std::min<int64_t>(4, hm * ng / 16384));
+    s.ipw = s.sym == 2 ? 1 : (int)std::max<int64_t>(1, std::min<int64_t>(4, hm * ng / 16384));
     return s;
 }
 
@@ -481,19 +483,21 @@ int rpy_wall_autotune(const double* pos, const double* F, double* U, int64_t N, 
     const bool prof = g_prof;
     g_prof = false;
     // Candidates in order of preference (least partial-sum traffic first):
-    // symmetric with ipw 4, 2, 1, then plain (tpl, tile) in {1,2} x {64,256},
-    // for every RHS block width.  Two timed rounds over all candidates (the
+    // symmetric over groups of 256 with ipw 4, 2, 1, then (small problems)
+    // over groups of 64 with ipw 4, 2, 1, then plain (tpl, tile) in
+    // {1,2} x {64,256}, for every RHS block width.  Two timed rounds over all candidates (the
     // first also brings the clocks up); each candidate keeps its faster
     // round.  A later candidate must be faster by 1.5% to win, so near-ties
     // resolve the same way every time.
     std::vector<Shape> cands;
     for (int kb = 1; kb <= std::min(kc, 16); kb <<= 1) {
         if (precision == RPYW_FP64 && kb > 8) continue;
-        for (int cand = 0; cand < 7; ++cand) {
-            Shape sh{1, 256, kb, 1, 4 >> cand};
-            if (cand >= 3) sh = Shape{1 + ((cand - 3) & 1), ((cand - 3) & 2) ? 256 : 64, kb, 0, 4};
-            if (cand >= 3 && kb >= 8 && sh.tpl == 2) continue;
-            if (cand < 3 && kb > 4) continue;
+        for (int cand = 0; cand < 10; ++cand) {
+            Shape sh{1, 256, kb, cand < 3 ? 1 : 2, 4 >> (cand % 3)};
+            if (cand >= 6) sh = Shape{1 + ((cand - 6) & 1), ((cand - 6) & 2) ? 256 : 64, kb, 0, 4};
+            if (cand >= 6 && kb >= 8 && sh.tpl == 2) continue;
+            if (cand < 6 && kb > 4) continue;
+            if (sh.sym == 2 && N > kSym64MaxN) continue;
             cands.push_back(sh);
         }
     }
@@ -541,7 +545,7 @@ int rpy_wall_set_shape(int precision, int64_t N, int32_t k, int32_t tpl, int32_t
     }
     if (!valid_prec(precision) || N < 1 || N >= kMaxN || k < 1 || (tpl != 1 && tpl != 2) ||
         (tile != 64 && tile != 256) || kblk < 1 || kblk > (precision == RPYW_FP32C ? 16 : 8) ||
-        (kblk & (kblk - 1)) != 0 || (sym != 0 && sym != 1) || (sym && kblk > 4) || ipw < 1)
+        (kblk & (kblk - 1)) != 0 || sym < 0 || sym > 2 || (sym && kblk > 4) || ipw < 1)
         return RPYW_EINVAL;
     set_tuned_shape(N, k, precision, Shape{tpl, tile, kblk, sym, ipw});
     return RPYW_OK;

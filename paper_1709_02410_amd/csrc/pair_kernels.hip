@@ -261,19 +261,23 @@ struct ProductBody {
 template <typename R>
 __global__ void sym_epilogue(const double* __restrict__ tpart, const R* __restrict__ spart,
                              const double* __restrict__ B, int64_t N, int ng, int C, int Hmax, int K, int kb,
-                             double mu0, double* __restrict__ U) {
+                             int G, double mu0, double* __restrict__ U) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int q = blockIdx.y;
     if (i >= N || q >= 3 * kb) return;
-    const double s = sym_gather<R>(tpart, spart, i, ng, C, Hmax, 3 * K, q);
+    const double s = sym_gather<R>(tpart, spart, i, ng, C, Hmax, 3 * K, q, G);
     U[((int64_t)(q / 3) * N + i) * 3 + q % 3] = mu0 * B[i] * s;
 }
 
 template <typename R, int K, bool PER>
-hipError_t launch_sym_t(const R* rec, int ng, int C, int ipw, int Hmax, double* tpart, R* spart, const Box<R>& box,
-                        hipStream_t st) {
-    hipLaunchKernelGGL((sym_kernel<R, ProductBody<R, K, PER>>), dim3((unsigned)(ng * C)), dim3(kBlock), 0, st, rec,
-                       ng, C, ipw, Hmax, tpart, spart, box);
+hipError_t launch_sym_t(const R* rec, int G, int ng, int C, int ipw, int Hmax, double* tpart, R* spart,
+                        const Box<R>& box, hipStream_t st) {
+    if (G == 64)
+        hipLaunchKernelGGL((sym_kernel<R, ProductBody<R, K, PER>, 1>), dim3((unsigned)(ng * C)), dim3(64), 0, st, rec,
+                           ng, C, ipw, Hmax, tpart, spart, box);
+    else
+        hipLaunchKernelGGL((sym_kernel<R, ProductBody<R, K, PER>, 4>), dim3((unsigned)(ng * C)), dim3(256), 0, st,
+                           rec, ng, C, ipw, Hmax, tpart, spart, box);
     return hipGetLastError();
 }
 
@@ -373,17 +377,18 @@ double mu0_of(double a, double eta) { return 1.0 / (6.0 * M_PI * eta * a); }
 
 // ------------------------------------------------------------ host side
 
-SymPlan sym_plan(int64_t N, int prec, int K, int ipw) {
+SymPlan sym_plan(int64_t N, int prec, int K, int ipw, int G) {
     SymPlan s{};
-    s.ng = (int)((N + 255) / 256);
+    s.G = G == 64 ? 64 : 256;
+    s.ng = (int)((N + s.G - 1) / s.G);
     s.Hmax = s.ng / 2;
     if (ipw < 1) ipw = 1;
     s.C = (s.Hmax + 1 + ipw - 1) / ipw;
-    const size_t npad = (size_t)s.ng * 256;
+    const size_t npad = (size_t)s.ng * s.G;
     s.rec_bytes = align_up(npad * rec_width(prec, K) * real_size(prec)) + align_up(npad * sizeof(double));
-    s.tpart_bytes = align_up((size_t)s.ng * s.C * 3 * K * 256 * sizeof(double));
-    s.spart_bytes = align_up((size_t)s.ng * (s.Hmax + 1) * 3 * K * 256 * real_size(prec));
-    s.ok = K <= 4 && s.spart_bytes <= ((size_t)4 << 30);
+    s.tpart_bytes = align_up((size_t)s.ng * s.C * 3 * K * s.G * sizeof(double));
+    s.spart_bytes = align_up((size_t)s.ng * (s.Hmax + 1) * 3 * K * s.G * real_size(prec));
+    s.ok = K <= 4 && s.spart_bytes <= ((size_t)4 << 30) && (s.G == 256 || N <= kSym64MaxN);
     return s;
 }
 
@@ -411,10 +416,11 @@ size_t product_ws_bytes(int64_t N, int prec, int kblk) {
     b += align_up((size_t)N * sizeof(double));
     b += align_up((size_t)smax * kblk * 3 * N * sizeof(double));
     size_t sb = 0;
-    for (int K = 1; K <= std::min(kblk, 4); K <<= 1) {
-        const SymPlan sp = sym_plan(N, prec, K, 1);
-        if (sp.ok) sb = std::max(sb, sp.rec_bytes + sp.tpart_bytes + sp.spart_bytes);
-    }
+    for (int K = 1; K <= std::min(kblk, 4); K <<= 1)
+        for (int G : {256, 64}) {
+            const SymPlan sp = sym_plan(N, prec, K, 1, G);
+            if (sp.ok) sb = std::max(sb, sp.rec_bytes + sp.tpart_bytes + sp.spart_bytes);
+        }
     return std::max(b, sb) + 8 * kAlign;
 }
 
@@ -424,7 +430,7 @@ int sym_pass(const double* pos, const double* F, double* U, int64_t N, int kb, i
              const SymPlan& sp, int ipw, Arena& ar, hipStream_t st, const Domain& dom = Domain{}) {
     const size_t mark = ar.used;
     const int rw = rec_width(prec, K);
-    const int64_t npad = (int64_t)sp.ng * 256;
+    const int64_t npad = (int64_t)sp.ng * sp.G;
     void* rec = ar.take((size_t)npad * rw * real_size(prec));
     double* B = (double*)ar.take((size_t)npad * sizeof(double));
     double* tpart = (double*)ar.take(sp.tpart_bytes);
@@ -453,11 +459,12 @@ int sym_pass(const double* pos, const double* F, double* U, int64_t N, int kb, i
         constexpr int KK = decltype(Kc)::value;
         if (dom.periodic()) {
             if constexpr (KK == 1)
-                return launch_sym_t<R, 1, true>((const R*)rec, sp.ng, sp.C, ipw, sp.Hmax, tpart, (R*)spart,
+                return launch_sym_t<R, 1, true>((const R*)rec, sp.G, sp.ng, sp.C, ipw, sp.Hmax, tpart, (R*)spart,
                                                 make_box<R>(dom, a), st);
             return hipErrorInvalidValue;
         }
-        return launch_sym_t<R, KK, false>((const R*)rec, sp.ng, sp.C, ipw, sp.Hmax, tpart, (R*)spart, Box<R>{}, st);
+        return launch_sym_t<R, KK, false>((const R*)rec, sp.G, sp.ng, sp.C, ipw, sp.Hmax, tpart, (R*)spart,
+                                          Box<R>{}, st);
     };
     if (prec == RPYW_FP32C)
         e = K == 1 ? go(0.f, std::integral_constant<int, 1>{})
@@ -471,10 +478,10 @@ int sym_pass(const double* pos, const double* F, double* U, int64_t N, int kb, i
     const dim3 ge(g1, (unsigned)(3 * kb));
     if (prec == RPYW_FP32C)
         hipLaunchKernelGGL(sym_epilogue<float>, ge, dim3(kBlock), 0, st, tpart, (const float*)spart, B, N, sp.ng, sp.C,
-                           sp.Hmax, K, kb, m0, U);
+                           sp.Hmax, K, kb, sp.G, m0, U);
     else
         hipLaunchKernelGGL(sym_epilogue<double>, ge, dim3(kBlock), 0, st, tpart, (const double*)spart, B, N, sp.ng,
-                           sp.C, sp.Hmax, K, kb, m0, U);
+                           sp.C, sp.Hmax, K, kb, sp.G, m0, U);
     RPYW_HIP(hipGetLastError());
     ar.used = mark;
     return RPYW_OK;
@@ -489,7 +496,8 @@ int product_pass(const double* pos, const double* F, double* U, int64_t N, int k
     if (kb < 1 || kb > K) return RPYW_EINVAL;
     sh = normalized(sh, K);
     if (sh.sym && K <= 4) {
-        const SymPlan sp = sym_plan(N, prec, K, sh.ipw);
+        SymPlan sp = sym_plan(N, prec, K, sh.ipw, sym_group(sh.sym));
+        if (!sp.ok && sp.G == 64) sp = sym_plan(N, prec, K, sh.ipw, 256);
         if (sp.ok) return sym_pass(pos, F, U, N, kb, K, a, eta, prec, sp, sh.ipw, ar, st);
     }
     const int rw = rec_width(prec, K);
@@ -533,11 +541,15 @@ int product_pass(const double* pos, const double* F, double* U, int64_t N, int k
 int products(const double* pos, const double* F, double* U, int64_t N, int k, double a, double eta, int prec,
              Arena& ar, hipStream_t st, const Domain& dom) {
     if (dom.periodic()) {
-        const SymPlan sp = sym_plan(N, prec, 1, tuned_shape(N, 1, prec).ipw);
+        // Always symmetric (one right-hand side per pass): groups of 64
+        // unless the shape asks for groups of 256.
+        const Shape sh = tuned_shape(N, 1, prec);
+        SymPlan sp = sym_plan(N, prec, 1, sh.ipw, sh.sym == 1 ? 256 : 64);
+        if (!sp.ok) sp = sym_plan(N, prec, 1, sh.ipw, 256);
         if (!sp.ok) return RPYW_ENOMEM;
         for (int k0 = 0; k0 < k; ++k0) {
             const int rc = sym_pass(pos, F + (size_t)k0 * N * 3, U + (size_t)k0 * N * 3, N, 1, 1, a, eta, prec, sp,
-                                    tuned_shape(N, 1, prec).ipw, ar, st, dom);
+                                    sh.ipw, ar, st, dom);
             if (rc != RPYW_OK) return rc;
         }
         return RPYW_OK;

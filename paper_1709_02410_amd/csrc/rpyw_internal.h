@@ -22,7 +22,7 @@ struct Shape {
     int tpl;   // targets per lane: 1 or 2
     int tile;  // sources per LDS tile: 64 or 256
     int kblk;  // right-hand sides per pass: 1, 2, 4, 8 or 16
-    int sym;   // 1: symmetric pair evaluation (kblk <= 4), items per workgroup in ipw
+    int sym;   // symmetric pair evaluation (kblk <= 4): 0 off, 1 groups of 256 blobs, 2 groups of 64
     int ipw;   // symmetric path: source groups per workgroup
 };
 
@@ -36,11 +36,17 @@ struct Domain {
 
 // Symmetric path geometry for N blobs, K right-hand sides.
 struct SymPlan {
+    int G;  // blobs per group: 256 or 64
     int ng, Hmax, C;
     size_t rec_bytes, tpart_bytes, spart_bytes;
     bool ok;
 };
-SymPlan sym_plan(int64_t N, int prec, int K, int ipw);
+// Groups of 64 are for problems up to this size: their source partials grow
+// as N^2 / 128 per quantity, four times those of groups of 256, and beyond
+// a few ten thousand blobs both group sizes run at the same speed.
+constexpr int64_t kSym64MaxN = 32768;
+SymPlan sym_plan(int64_t N, int prec, int K, int ipw, int G = 256);
+inline int sym_group(int sym) { return sym == 2 ? 64 : 256; }
 
 // Bump allocator over a caller workspace.
 struct Arena {

@@ -4,19 +4,21 @@
 // symmetric), under which the transposed block is the same coefficient set
 // with the two off-diagonal wall coefficients exchanged.
 //
-// Work decomposition.  Blobs are grouped by 256 (four 64-lane blocks).  Work
-// item (P, d) pairs target group P with source group Q = (P + d) mod ng for
-// d = 0 .. H(P) (sym_rowlen), which covers every unordered pair of groups
-// exactly once.  A workgroup of four waves takes `ipw` consecutive items of
-// one row.  Wave w holds target block 4P + w; in phase b (b = 0..3) it takes
-// source block (w + b) mod 4, so the four waves work on four different
-// source blocks (in FP64 with a workgroup barrier between phases).  A phase is 64
+// Work decomposition.  Blobs are grouped by G = 64 NB (NB 64-lane blocks:
+// NB = 4 for large problems, NB = 1 when there would be too few groups to
+// fill the GPU).  Work item (P, d) pairs target group P with source group
+// Q = (P + d) mod ng for d = 0 .. H(P) (sym_rowlen), which covers every
+// unordered pair of groups exactly once.  A workgroup of NB waves takes
+// `ipw` consecutive items of one row.  Wave w holds target block NB P + w;
+// in phase b (b = 0 .. NB-1) it takes source block (w + b) mod NB, so the
+// waves work on different source blocks (in FP64 with a workgroup barrier
+// between phases).  A phase is 64
 // steps in which lane l pairs its target with source (l + s) mod 64, read
 // from LDS rows that hold the block twice (so l + s needs no wrap).  The lane
 // adds the target-side contribution to its own sums.  The source-side
 // contribution goes, in FP32, to an accumulator that moves one lane down
 // after every step (a DPP wavefront rotate fused into the add), so that
-// after the phase lane l holds the complete sum of source l, and the four
+// after the phase lane l holds the complete sum of source l, and the
 // waves' sums are added through LDS; in FP64 it goes to an LDS slot l + s of
 // that source block by an LDS atomic add (no two lanes of an instruction
 // share a slot, one wave owns a block per phase and the phases are ordered
@@ -47,8 +49,6 @@
 #include "records.h"
 
 namespace rpyw {
-
-constexpr int kSymBlock = 256;
 
 // Pseudo-periodic cell along the wall, units of a: lengths, the lengths
 // split into a high part with 12 significant bits (small integer multiples
@@ -156,8 +156,9 @@ struct SymLane {
     // S, which moves one lane down after every step (a DPP wave rotate fused
     // into the add), so that after the pass lane l holds source l's sum
     // (sa == nullptr), or to LDS sa[q * 128 + l + s] by an atomic add.
+    // vs: LDS entries per vector slot of the tile (128 per source block).
     template <bool SYM>
-    __device__ void pass(const typename Vec<R>::T* __restrict__ tile, int blk, int l, R* sa, R (&S)[NQ],
+    __device__ void pass(const typename Vec<R>::T* __restrict__ tile, int vs, int blk, int l, R* sa, R (&S)[NQ],
                          const Box<R>& box) {
         using VT = typename Vec<R>::T;
         const VT* base = tile + blk * 128 + l;
@@ -169,7 +170,7 @@ struct SymLane {
             R r[RW];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const VT q = base[v * 512 + s];
+                const VT q = base[v * vs + s];
 #pragma unroll
                 for (int e = 0; e < Vec<R>::W; ++e) r[v * Vec<R>::W + e] = Vec<R>::get(q, e);
             }
@@ -216,27 +217,31 @@ struct SymLane {
     }
 };
 
-// rec: ng * 256 records (padded with force-free blobs far away).
-// tpart: [ng * C][NQ][256] doubles; spart: [ng * (Hmax + 1)][NQ][256].
-template <typename R, class Body>
-__global__ __launch_bounds__(kSymBlock) void sym_kernel(const R* __restrict__ rec, int ng, int C, int ipw, int Hmax,
-                                                        double* __restrict__ tpart, R* __restrict__ spart,
-                                                        Box<R> box) {
+// Groups of G = 64 NB blobs (NB blocks of 64, one wave each): NB = 4 for
+// large problems, NB = 1 to have enough workgroups when there are few groups.
+// rec: ng * G records (padded with force-free blobs far away).
+// tpart: [ng * C][NQ][G] doubles; spart: [ng * (Hmax + 1)][NQ][G].
+template <typename R, class Body, int NB = 4>
+__global__ __launch_bounds__(64 * NB) void sym_kernel(const R* __restrict__ rec, int ng, int C, int ipw, int Hmax,
+                                                      double* __restrict__ tpart, R* __restrict__ spart,
+                                                      Box<R> box) {
     using L = SymLane<R, Body>;
     using VT = typename Vec<R>::T;
     constexpr int NQ = L::NQ;
+    constexpr int G = 64 * NB;
+    constexpr int VS = 128 * NB;  // tile entries per vector slot
     // FP64: source sums by LDS atomics (one wave per source block and phase);
     // FP32: by the DPP rotation, then across the waves through `red` (LDS
     // FP32 atomic adds are far slower than the rotation on this GPU, FP64
     // ones are faster).
     constexpr bool kLds = sizeof(R) == 8;
-    __shared__ VT tile[L::NV * 512];
-    __shared__ R sacc[kLds ? 4 : 1][kLds ? NQ : 1][kLds ? 128 : 1];  // per source block, slots l + s
-    __shared__ R red[kLds ? 1 : 4][kLds ? 1 : NQ][kLds ? 1 : 256];
+    __shared__ VT tile[L::NV * VS];
+    __shared__ R sacc[kLds ? NB : 1][kLds ? NQ : 1][kLds ? 128 : 1];  // per source block, slots l + s
+    __shared__ R red[kLds ? 1 : NB][kLds ? 1 : NQ][kLds ? 1 : G];
     const int P = blockIdx.x / C, c = blockIdx.x % C;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     L me;
-    me.load(rec + ((int64_t)P * 256 + threadIdx.x) * L::RW);
+    me.load(rec + ((int64_t)P * G + threadIdx.x) * L::RW);
     const int H = sym_rowlen(P, ng);
     const int d0 = c * ipw;
     const int d1 = d0 + ipw - 1 < H ? d0 + ipw - 1 : H;
@@ -244,30 +249,30 @@ __global__ __launch_bounds__(kSymBlock) void sym_kernel(const R* __restrict__ re
         const int Q = (P + d) % ng;
         __syncthreads();
         {
-            const VT* g = reinterpret_cast<const VT*>(rec + ((int64_t)Q * 256 + threadIdx.x) * L::RW);
+            const VT* g = reinterpret_cast<const VT*>(rec + ((int64_t)Q * G + threadIdx.x) * L::RW);
             const int b = threadIdx.x >> 6, j = threadIdx.x & 63;
 #pragma unroll
             for (int v = 0; v < L::NV; ++v) {
                 const VT q = g[v];
-                tile[v * 512 + b * 128 + j] = q;
-                tile[v * 512 + b * 128 + j + 64] = q;
+                tile[v * VS + b * 128 + j] = q;
+                tile[v * VS + b * 128 + j + 64] = q;
             }
             if constexpr (kLds) {
                 R* z = &sacc[0][0][0];
-                for (int e = threadIdx.x; e < 4 * NQ * 128; e += blockDim.x) z[e] = R(0);
+                for (int e = threadIdx.x; e < NB * NQ * 128; e += blockDim.x) z[e] = R(0);
             }
         }
         __syncthreads();
-        for (int bb = 0; bb < 4; ++bb) {
-            const int blk = (w + bb) & 3;
+        for (int bb = 0; bb < NB; ++bb) {
+            const int blk = (w + bb) % NB;
             R S[NQ];
             if (d == 0 && blk < w) {
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) S[q] = R(0);
             } else if (d == 0 && blk == w) {
-                me.template pass<false>(tile, blk, l, nullptr, S, box);
+                me.template pass<false>(tile, VS, blk, l, nullptr, S, box);
             } else {
-                me.template pass<true>(tile, blk, l, kLds ? &sacc[blk][0][0] : nullptr, S, box);
+                me.template pass<true>(tile, VS, blk, l, kLds ? &sacc[blk][0][0] : nullptr, S, box);
             }
             if constexpr (kLds) {
                 __syncthreads();  // one wave per source block in every phase
@@ -277,34 +282,37 @@ __global__ __launch_bounds__(kSymBlock) void sym_kernel(const R* __restrict__ re
             }
         }
         if constexpr (!kLds) __syncthreads();
-        R* out = spart + ((int64_t)Q * (Hmax + 1) + d) * NQ * 256;
+        R* out = spart + ((int64_t)Q * (Hmax + 1) + d) * NQ * G;
         const int b = threadIdx.x >> 6, j = threadIdx.x & 63;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            if constexpr (kLds)
-                out[q * 256 + threadIdx.x] = sacc[b][q][j] + sacc[b][q][j + 64];
-            else
-                out[q * 256 + threadIdx.x] =
-                    ((red[0][q][threadIdx.x] + red[1][q][threadIdx.x]) + red[2][q][threadIdx.x]) + red[3][q][threadIdx.x];
+            if constexpr (kLds) {
+                out[q * G + threadIdx.x] = sacc[b][q][j] + sacc[b][q][j + 64];
+            } else {
+                R t = red[0][q][threadIdx.x];
+#pragma unroll
+                for (int k = 1; k < NB; ++k) t += red[k][q][threadIdx.x];
+                out[q * G + threadIdx.x] = t;
+            }
         }
     }
-    double* tp = tpart + ((int64_t)P * C + c) * NQ * 256;
+    double* tp = tpart + ((int64_t)P * C + c) * NQ * G;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) tp[q * 256 + threadIdx.x] = me.total(q);
+    for (int q = 0; q < NQ; ++q) tp[q * G + threadIdx.x] = me.total(q);
 }
 
 // Sum of quantity q of blob i over the chunk target partials and the item
 // source partials, in a fixed order.
 template <typename R>
 __device__ __forceinline__ double sym_gather(const double* __restrict__ tpart, const R* __restrict__ spart, int64_t i,
-                                             int ng, int C, int Hmax, int NQ, int q) {
-    const int P = (int)(i >> 8), t = (int)(i & 255);
+                                             int ng, int C, int Hmax, int NQ, int q, int G = 256) {
+    const int P = (int)(i / G), t = (int)(i % G);
     const int dmax = sym_dmax(P, ng);
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    const double* tp = tpart + ((int64_t)P * C * NQ + q) * 256 + t;
-    for (int c = 0; c < C; ++c) s0 += tp[(int64_t)c * NQ * 256];
-    const R* sp = spart + ((int64_t)P * (Hmax + 1) * NQ + q) * 256 + t;
-    const int64_t st = (int64_t)NQ * 256;
+    const double* tp = tpart + ((int64_t)P * C * NQ + q) * G + t;
+    for (int c = 0; c < C; ++c) s0 += tp[(int64_t)c * NQ * G];
+    const R* sp = spart + ((int64_t)P * (Hmax + 1) * NQ + q) * G + t;
+    const int64_t st = (int64_t)NQ * G;
     int d = 0;
     for (; d + 3 <= dmax; d += 4) {
         s0 += (double)sp[(d + 0) * st];

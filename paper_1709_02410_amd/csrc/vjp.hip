@@ -156,12 +156,12 @@ struct VjpBody {
 template <typename R>
 __global__ void sym_vjp_epilogue(const double* __restrict__ tpart, const R* __restrict__ spart,
                                  const double* __restrict__ pos, const double* __restrict__ f,
-                                 const double* __restrict__ g, int64_t N, int ng, int C, int Hmax, double inv_a,
-                                 double mu0, double* __restrict__ grad_pos, double* __restrict__ grad_f) {
+                                 const double* __restrict__ g, int64_t N, int ng, int C, int Hmax, int G,
+                                 double inv_a, double mu0, double* __restrict__ grad_pos, double* __restrict__ grad_f) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     double s[kQ];
-    for (int q = 0; q < kQ; ++q) s[q] = sym_gather<R>(tpart, spart, i, ng, C, Hmax, kQ, q);
+    for (int q = 0; q < kQ; ++q) s[q] = sym_gather<R>(tpart, spart, i, ng, C, Hmax, kQ, q, G);
     const double z = pos[3 * i + 2] * inv_a;
     const double B = z < 1.0 ? z : 1.0;
     if (grad_pos) {
@@ -224,14 +224,22 @@ __global__ void divergence_kernel(const double* __restrict__ pos, int64_t N, dou
 
 namespace {
 
-// Symmetric VJP plan: same groups as the product, 9 quantities per blob.
-bool vjp_sym_plan(int64_t N, int prec, int ipw, int* ng, int* C, int* Hmax, size_t* tb, size_t* sb) {
-    *ng = (int)((N + 255) / 256);
+// Symmetric VJP plan: groups of G blobs as for the product (64 only up to
+// kSym64MaxN), 9 quantities per blob.
+bool vjp_sym_plan(int64_t N, int prec, int ipw, int G, int* ng, int* C, int* Hmax, size_t* tb, size_t* sb) {
+    if (G == 64 && N > kSym64MaxN) return false;
+    *ng = (int)((N + G - 1) / G);
     *Hmax = *ng / 2;
     *C = (*Hmax + 1 + ipw - 1) / ipw;
-    *tb = align_up((size_t)*ng * *C * kQ * 256 * sizeof(double));
-    *sb = align_up((size_t)*ng * (*Hmax + 1) * kQ * 256 * real_size(prec));
+    *tb = align_up((size_t)*ng * *C * kQ * G * sizeof(double));
+    *sb = align_up((size_t)*ng * (*Hmax + 1) * kQ * G * real_size(prec));
     return *tb <= ((size_t)4 << 30) && *sb <= ((size_t)4 << 30);
+}
+
+template <typename R, int NB>
+void launch_vjp_sym(const R* rec, int ng, int C, int ipw, int Hmax, double* tpart, R* spart, hipStream_t st) {
+    hipLaunchKernelGGL((sym_kernel<R, VjpBody<R>, NB>), dim3((unsigned)(ng * C)), dim3(64 * NB), 0, st, rec, ng, C,
+                       ipw, Hmax, tpart, spart, Box<R>{});
 }
 
 }  // namespace
@@ -245,11 +253,13 @@ size_t vjp_ws_bytes(int64_t N, int prec) {
     b += align_up((size_t)splits * kQ * N * sizeof(double));
     int ng, C, Hmax;
     size_t tb, sb;
-    if (vjp_sym_plan(N, prec, 1, &ng, &C, &Hmax, &tb, &sb)) {
-        const size_t npad = (size_t)ng * 256;
-        const size_t s = align_up(npad * rec_width(prec, 2) * real_size(prec)) + align_up(npad * sizeof(double)) + tb + sb;
-        b = std::max(b, s);
-    }
+    for (int G : {256, 64})
+        if (vjp_sym_plan(N, prec, 1, G, &ng, &C, &Hmax, &tb, &sb)) {
+            const size_t npad = (size_t)ng * G;
+            const size_t s =
+                align_up(npad * rec_width(prec, 2) * real_size(prec)) + align_up(npad * sizeof(double)) + tb + sb;
+            b = std::max(b, s);
+        }
     return b + 8 * kAlign;
 }
 
@@ -261,11 +271,16 @@ int vjp(const double* pos, const double* f, const double* g, double* grad_pos, d
     int ng, C, Hmax;
     size_t tb, sb;
     const int ipw = sh.ipw < 1 ? 1 : sh.ipw;
-    const bool sym = sh.sym && vjp_sym_plan(N, prec, ipw, &ng, &C, &Hmax, &tb, &sb);
+    int G = sym_group(sh.sym);
+    bool sym = sh.sym && vjp_sym_plan(N, prec, ipw, G, &ng, &C, &Hmax, &tb, &sb);
+    if (sh.sym && !sym && G == 64) {
+        G = 256;
+        sym = vjp_sym_plan(N, prec, ipw, G, &ng, &C, &Hmax, &tb, &sb);
+    }
     const double m0 = 1.0 / (6.0 * M_PI * eta * a);
     const unsigned g1 = (unsigned)((N + kBlock - 1) / kBlock);
     if (sym) {
-        const int64_t npad = (int64_t)ng * 256;
+        const int64_t npad = (int64_t)ng * G;
         void* rec = ar.take((size_t)npad * rw * real_size(prec));
         double* B = (double*)ar.take((size_t)npad * sizeof(double));
         double* tpart = (double*)ar.take(tb);
@@ -282,12 +297,14 @@ int vjp(const double* pos, const double* f, const double* g, double* grad_pos, d
             if (gp) hipLaunchKernelGGL(pad_kernel<float>, dim3(gp), dim3(kBlock), 0, st, (float*)rec, N, npad, rw, B);
             RPYW_HIP(hipGetLastError());
             profile_begin(st, &ev);
-            hipLaunchKernelGGL((sym_kernel<float, VjpBody<float>>), dim3((unsigned)(ng * C)), dim3(kBlock), 0, st,
-                               (const float*)rec, ng, C, ipw, Hmax, tpart, (float*)spart, Box<float>{});
+            if (G == 64)
+                launch_vjp_sym<float, 1>((const float*)rec, ng, C, ipw, Hmax, tpart, (float*)spart, st);
+            else
+                launch_vjp_sym<float, 4>((const float*)rec, ng, C, ipw, Hmax, tpart, (float*)spart, st);
             RPYW_HIP(hipGetLastError());
             profile_end(st, ev, (double)N * (double)N);
             hipLaunchKernelGGL(sym_vjp_epilogue<float>, dim3(g1), dim3(kBlock), 0, st, tpart, (const float*)spart, pos,
-                               f, g, N, ng, C, Hmax, 1.0 / a, m0, grad_pos, grad_f);
+                               f, g, N, ng, C, Hmax, G, 1.0 / a, m0, grad_pos, grad_f);
         } else {
             hipLaunchKernelGGL(pack_kernel<double>, dim3(g1), dim3(kBlock), 0, st, pos, f, N, 2, rw, 1.0 / a,
                                (double*)rec, B, g, 0.0, 0.0);
@@ -295,12 +312,14 @@ int vjp(const double* pos, const double* f, const double* g, double* grad_pos, d
                 hipLaunchKernelGGL(pad_kernel<double>, dim3(gp), dim3(kBlock), 0, st, (double*)rec, N, npad, rw, B);
             RPYW_HIP(hipGetLastError());
             profile_begin(st, &ev);
-            hipLaunchKernelGGL((sym_kernel<double, VjpBody<double>>), dim3((unsigned)(ng * C)), dim3(kBlock), 0, st,
-                               (const double*)rec, ng, C, ipw, Hmax, tpart, (double*)spart, Box<double>{});
+            if (G == 64)
+                launch_vjp_sym<double, 1>((const double*)rec, ng, C, ipw, Hmax, tpart, (double*)spart, st);
+            else
+                launch_vjp_sym<double, 4>((const double*)rec, ng, C, ipw, Hmax, tpart, (double*)spart, st);
             RPYW_HIP(hipGetLastError());
             profile_end(st, ev, (double)N * (double)N);
             hipLaunchKernelGGL(sym_vjp_epilogue<double>, dim3(g1), dim3(kBlock), 0, st, tpart, (const double*)spart,
-                               pos, f, g, N, ng, C, Hmax, 1.0 / a, m0, grad_pos, grad_f);
+                               pos, f, g, N, ng, C, Hmax, G, 1.0 / a, m0, grad_pos, grad_f);
         }
         RPYW_HIP(hipGetLastError());
         ar.used = mark;

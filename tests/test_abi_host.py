@@ -138,3 +138,21 @@ def test_tridiagonal_root_clamps_negative_eigenvalues(lib):
     assert np.allclose(rpywall.tridiag_sqrt_coeffs(alpha, beta, 1.0), ref, atol=1e-14)
     with pytest.raises(rpywall.RpywError):
         rpywall.tridiag_sqrt_coeffs(np.array([1.0, np.nan]), np.array([0.1]), 1.0)
+
+
+def test_launch_shape_validation_and_defaults(lib):
+    """Shape overrides: sym 0, 1 (groups of 256) and 2 (groups of 64) are
+    accepted, other values and symmetric blocks wider than 4 are not; the
+    built-in choice takes groups of 64 for small single-RHS problems."""
+    E = rpywall.EINVAL
+    assert lib.rpy_wall_set_shape(1, 5000, 1, 1, 256, 1, 3, 1) == E
+    assert lib.rpy_wall_set_shape(1, 5000, 1, 1, 256, 8, 2, 1) == E
+    assert lib.rpy_wall_set_shape(1, 5000, 1, 1, 256, 1, -1, 1) == E
+    for sym in (0, 1, 2):
+        rpywall.set_shape(1, 5000, 1, tpl=1, tile=256, kblk=1, sym=sym, ipw=2)
+        assert rpywall.get_shape(1, 5000, 1)["sym"] == sym
+    rpywall.reset_shape(1, 5000, 1)
+    assert rpywall.get_shape(1, 3840, 1)["sym"] == 2
+    assert rpywall.get_shape(0, 100000, 1)["sym"] == 1
+    assert rpywall.get_shape(1, 1000, 1)["sym"] == 0
+    assert rpywall.get_shape(1, 3840, 4)["sym"] == 0

@@ -131,12 +131,14 @@ def test_rfd_drift_estimate_matches_exact_divergence(rp, prec, delta):
     assert abs(chi2 - dof) < 6 * math.sqrt(2 * dof)
 
 
-@pytest.mark.parametrize("N", [1, 7, 300, 513, 1300])
+@pytest.mark.parametrize("N", [1, 7, 65, 300, 513, 1300])
 @pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 2e-5)])
-def test_symmetric_vjp_matches_oracle(rp, orc, N, prec, tol):
+@pytest.mark.parametrize("sym", [1, 2])
+def test_symmetric_vjp_matches_oracle(rp, orc, N, prec, tol, sym):
     """The symmetric VJP kernel (one pair gradient per unordered pair, used
-    for both blobs) forced at small and ragged sizes, with blobs below the
-    wall and overlapping pairs."""
+    for both blobs), over groups of 256 (sym 1) and of 64 blobs (sym 2),
+    forced at small and ragged sizes, with blobs below the wall and
+    overlapping pairs."""
     a, eta = 0.8, 1.1
     pos = _mixed(N, 10 + N) * a
     if N >= 3:
@@ -145,7 +147,7 @@ def test_symmetric_vjp_matches_oracle(rp, orc, N, prec, tol):
     g = wl.gaussian(pos.shape, 30 + N)
     gp_ref, gf_ref = orc.vjp(pos, f, g, a, eta)
     for ipw in (1, 2):
-        rp.set_shape(prec, N, 1, tpl=1, tile=256, kblk=1, sym=1, ipw=ipw)
+        rp.set_shape(prec, N, 1, tpl=1, tile=256, kblk=1, sym=sym, ipw=ipw)
         gp, gf = rp.matvec_vjp(_t(pos), _t(f), _t(g), a, eta, precision=prec)
         gp, gf = gp.cpu().numpy(), gf.cpu().numpy()
         assert np.linalg.norm(gp - gp_ref) <= tol * np.linalg.norm(gp_ref)

@@ -126,13 +126,15 @@ def test_invalid_arguments_rejected(rp):
                                None) == rp.ENOMEM
 
 
-@pytest.mark.parametrize("N", [1, 2, 200, 256, 257, 511, 770, 1500, 4097])
+@pytest.mark.parametrize("N", [1, 2, 63, 64, 65, 200, 256, 257, 511, 770, 1500, 4097])
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("kblk", [1, 2, 4])
-def test_symmetric_kernel_ragged(rp, orc, N, prec, kblk):
+@pytest.mark.parametrize("sym", [1, 2])
+def test_symmetric_kernel_ragged(rp, orc, N, prec, kblk, sym):
     """The symmetric kernel (each unordered pair evaluated once, applied in
-    both directions) at sizes from one partial group to many groups, odd and
-    even group counts, with several RHS blocks; against the oracle."""
+    both directions), over groups of 256 (sym 1) and of 64 blobs (sym 2), at
+    sizes from one partial group to many groups, odd and even group counts,
+    with several RHS blocks; against the oracle."""
     rng = np.random.default_rng(1000 + N)
     box = max(2.0, 2.0 * np.sqrt(N))
     pos = np.column_stack([rng.uniform(0, box, N), rng.uniform(0, box, N), rng.uniform(0.3, 4.0, N)])
@@ -141,7 +143,7 @@ def test_symmetric_kernel_ragged(rp, orc, N, prec, kblk):
     k = kblk + 1 if kblk > 1 else 1
     F = rng.standard_normal((k, N, 3))
     for ipw in (1, 3):
-        rp.set_shape(prec, N, k, tpl=1, tile=256, kblk=kblk, sym=1, ipw=ipw)
+        rp.set_shape(prec, N, k, tpl=1, tile=256, kblk=kblk, sym=sym, ipw=ipw)
         U = rp.matvec_multi(_t(pos), _t(F), precision=prec).cpu().numpy()
         assert np.all(np.isfinite(U))
         for l in range(k):
@@ -153,16 +155,18 @@ def test_symmetric_kernel_ragged(rp, orc, N, prec, kblk):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-def test_symmetric_kernel_bitwise_repeatable(rp, prec):
+@pytest.mark.parametrize("sym", [1, 2])
+def test_symmetric_kernel_bitwise_repeatable(rp, prec, sym):
     """Fixed-order sums (FP32: wave rotation; FP64: LDS atomic adds ordered
     by wave and phase): four repeated products and VJPs on 20000 blobs (79
-    groups, thousands of concurrent workgroups) are bitwise identical."""
+    groups of 256 or 313 of 64, thousands of concurrent workgroups) are
+    bitwise identical."""
     cfg = wl.headline(seed=4, N=20000)
     pos = _t(cfg.pos)
     f = _t(wl.gaussian(cfg.pos.shape, 5))
     g = _t(wl.gaussian(cfg.pos.shape, 6))
     for ipw in (1, 2):
-        rp.set_shape(prec, cfg.N, 1, tpl=1, tile=256, kblk=1, sym=1, ipw=ipw)
+        rp.set_shape(prec, cfg.N, 1, tpl=1, tile=256, kblk=1, sym=sym, ipw=ipw)
         U0 = rp.matvec(pos, f, precision=prec)
         G0 = rp.matvec_vjp(pos, f, g, precision=prec)[0]
         for _ in range(3):

@@ -51,10 +51,10 @@ def test_periodic_product_matches_oracle(rp, orc, N, prec):
     pos, box = _cell(N, 100 + N, a)
     f = wl.gaussian(pos.shape, 200 + N)
     ref = orc.matvec(pos, f, a, eta, box=box)
-    for ipw in (1, 2):
-        rp.set_shape(prec, N, 1, tpl=1, tile=256, kblk=1, sym=1, ipw=ipw)
+    for sym, ipw in ((1, 1), (1, 2), (2, 1), (2, 3), (0, 2)):  # groups of 256, of 64, of 64
+        rp.set_shape(prec, N, 1, tpl=1, tile=256, kblk=1, sym=sym, ipw=ipw)
         got = rp.matvec(_t(pos), _t(f), a, eta, precision=prec, box=box).cpu().numpy()
-        print(f"periodic N={N} prec={prec} ipw={ipw} rel={_rel(got, ref):.3e}", flush=True)
+        print(f"periodic N={N} prec={prec} sym={sym} ipw={ipw} rel={_rel(got, ref):.3e}", flush=True)
         assert _rel(got, ref) <= TOL[prec]
     rp.reset_shape(prec, N, 1)
 
