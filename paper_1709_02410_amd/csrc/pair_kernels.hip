@@ -205,14 +205,21 @@ struct ProductBody {
     static constexpr int KREC = K;
     static constexpr int NQ = 3 * K;
     static constexpr int kUnroll = PER ? 1 : 4;
+    // Open domain: two sources per step sharing one overlap branch, so that
+    // their arithmetic interleaves (pair2).
+    static constexpr bool kDuo = !PER;
     // One source image: target side into acc and, when SYM, source side
     // (transposed block: the two off-diagonal wall coefficients exchanged)
     // into src.
     template <bool SYM>
     __device__ static void image(const SymTarget<R, K>& t, const R* r, R dx, R dy, R dz, R (&acc)[NQ],
                                  R (&src)[NQ]) {
+        apply<SYM>(pair_coef<R>(dx, dy, dz, t.z, r[2]), t, r, dx, dy, dz, acc, src);
+    }
+    template <bool SYM>
+    __device__ static void apply(PairCoef<R> p, const SymTarget<R, K>& t, const R* r, R dx, R dy, R dz,
+                                 R (&acc)[NQ], R (&src)[NQ]) {
         constexpr int PW = pos_slots<R>();
-        PairCoef<R> p = pair_coef<R>(dx, dy, dz, t.z, r[2]);
 #pragma unroll
         for (int k = 0; k < K; ++k)
             pair_apply<R>(p, dx, dy, dz, r[PW + 3 * k], r[PW + 3 * k + 1], r[PW + 3 * k + 2], acc[3 * k],
@@ -226,6 +233,27 @@ struct ProductBody {
                 pair_apply<R>(p, dx, dy, dz, t.f[k][0], t.f[k][1], t.f[k][2], src[3 * k], src[3 * k + 1],
                               src[3 * k + 2]);
         }
+    }
+    // Sources ra and rb (open domain): the source sides go to sa and sb.
+    template <bool SYM>
+    __device__ static void pair2(const SymTarget<R, K>& t, const R* ra, const R* rb, R (&acc)[NQ], R (&sa)[NQ],
+                                 R (&sb)[NQ]) {
+        R dxa, dya, dza, dxb, dyb, dzb;
+        sym_diff(t, ra, dxa, dya, dza);
+        sym_diff(t, rb, dxb, dyb, dzb);
+        PairPre<R> pa = pair_pre<R>(dxa, dya, dza, t.z, ra[2]);
+        PairPre<R> pb = pair_pre<R>(dxb, dyb, dzb, t.z, rb[2]);
+        if (__builtin_amdgcn_ballot_w64(pair_near(pa) || pair_near(pb))) {
+            __asm__ volatile("" ::: "memory");  // keep this a branch: do not speculate it
+            pair_fix(pa);
+            pair_fix(pb);
+        }
+        if constexpr (SYM) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) sa[q] = sb[q] = R(0);
+        }
+        apply<SYM>(pair_fin(pa), t, ra, dxa, dya, dza, acc, sa);
+        apply<SYM>(pair_fin(pb), t, rb, dxb, dyb, dzb, acc, sb);
     }
     template <bool SYM>
     __device__ static void pair(const SymTarget<R, K>& t, const R* r, R (&acc)[NQ], R (&src)[NQ],
@@ -611,7 +639,14 @@ int batched_products(const double* pos, const int64_t* sys_offsets, int S, const
     const int64_t Ntot = sys_offsets[S];
     int64_t nmax = 0;
     for (int s = 0; s < S; ++s) nmax = std::max(nmax, sys_offsets[s + 1] - sys_offsets[s]);
+    // The batched kernel is the plain one: a symmetric tuned shape (chosen
+    // for single products of this size) gives way to the plain default with
+    // the widest RHS block.
     Shape sh = tuned_shape(nmax, k, prec);
+    if (sh.sym) {
+        sh = default_shape(nmax, k, prec);
+        sh.sym = 0;
+    }
     sh = normalized(sh, kernel_k(sh.kblk, prec));
     // Work list in LPT order: systems by decreasing size, then their tiles.
     std::vector<int> order(S);

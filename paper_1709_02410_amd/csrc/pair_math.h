@@ -70,11 +70,20 @@ struct PairCoef {
     R kcm;  // w X |R|C'     (normal velocity from in-plane force)
 };
 
-// Evaluate the pair coefficients.  dx, dy, dz: target minus source;
-// zi, zj: regularised heights.
+// The pair coefficients in three stages, so that several pairs can share one
+// overlap branch.  pair_pre evaluates everything with the far-field free
+// coefficients (r > 2); pair_fix replaces c1, c2 where r <= 2 (the guard
+// keeps r = 0 finite: c1 = 1, c2 d = 0); pair_fin forms the two diagonal
+// coefficients.  dx, dy, dz: target minus source; zi, zj: regularised
+// heights.
 template <typename R>
-__device__ __forceinline__ PairCoef<R> pair_coef(R dx, R dy, R dz, R zi, R zj) {
-    PairCoef<R> o;
+struct PairPre {
+    R c1, c2, w, rA, rE, kb, kcp, kcm, r2;
+};
+
+template <typename R>
+__device__ __forceinline__ PairPre<R> pair_pre(R dx, R dy, R dz, R zi, R zj) {
+    PairPre<R> o;
     const R rz = zi + zj;
     const R h2 = fma_(dy, dy, dx * dx);
     const R r2 = fma_(dz, dz, h2);
@@ -86,41 +95,66 @@ __device__ __forceinline__ PairCoef<R> pair_coef(R dx, R dy, R dz, R zi, R zj) {
     // free RPY, far branch (r > 2)
     const R ir = rsq<R>(r2);
     const R ir2 = ir * ir;
-    R c1 = ir * fma_(ir2, R(0.5), R(0.75));
-    R c2 = (ir * ir2) * fma_(ir2, R(-1.5), R(0.75));
-    // Overlap branch (r <= 2a), entered by the whole wave when any lane has
-    // an overlapping pair (rare: self pairs and touching neighbours); the
-    // guard keeps r = 0 finite (c1 = 1, c2 d = 0).
-    const bool near = r2 <= R(4);
-    if (__builtin_amdgcn_ballot_w64(near)) {
-        __asm__ volatile("" ::: "memory");  // keep this a branch: do not speculate it
-        const R irg = rsq<R>(r2 > R(1e-30) ? r2 : R(1e-30));
-        const R c1n = fma_(R(-9.0 / 32.0), r2 * irg, R(1));
-        const R c2n = R(3.0 / 32.0) * irg;
-        c1 = near ? c1n : c1;
-        c2 = near ? c2n : c2;
-    }
+    o.c1 = ir * fma_(ir2, R(0.5), R(0.75));
+    o.c2 = (ir * ir2) * fma_(ir2, R(-1.5), R(0.75));
     const R u = rz2 * X;
     // v = zz X enters only as v c; written (z_j X)(c z_i) so that c z_i is
     // hoisted out of loops over sources.
     const R zjX = zj * X;
-    const R rA =
-        fma_(X, fma_(X, fma_(u, R(-2.5), R(0.5)), fma_(u, R(1.5), R(-0.5))), fma_(zjX, R(-1.5) * zi, R(-0.75)));
+    o.rA = fma_(X, fma_(X, fma_(u, R(-2.5), R(0.5)), fma_(u, R(1.5), R(-0.5))), fma_(zjX, R(-1.5) * zi, R(-0.75)));
     const R rB =
         fma_(X, fma_(X, fma_(u, R(17.5), R(-2.5)), fma_(u, R(-7.5), R(1.5))), fma_(zjX, R(4.5) * zi, R(-0.75)));
     const R g = fma_(X * X, R(5.0), R(-0.75)) - rB;
     const R cw = dz * R(-0.75);
     const R qE = fma_(X, fma_(X, fma_(u, R(12.5), R(-1.5)), fma_(u, R(-1.5), R(-0.5))),
                       fma_(zjX, R(1.5) * zi, fma_(u, R(-1.5), R(-0.75))));
-    const R rE = fma_(-u, rB, qE);
-    o.c1 = c1;
-    o.c2 = c2;
-    o.cc = fma_(w, rA, c1);
-    o.cz = fma_(w, rE, c1);
+    o.rE = fma_(-u, rB, qE);
+    o.w = w;
     o.kb = wX * rB;
     o.kcp = wX * fma_(rz, g, cw);
     o.kcm = wX * fma_(-rz, g, cw);
+    o.r2 = r2;
     return o;
+}
+
+template <typename R>
+__device__ __forceinline__ bool pair_near(const PairPre<R>& p) {
+    return p.r2 <= R(4);
+}
+
+template <typename R>
+__device__ __forceinline__ void pair_fix(PairPre<R>& p) {
+    const bool near = pair_near(p);
+    const R irg = rsq<R>(p.r2 > R(1e-30) ? p.r2 : R(1e-30));
+    const R c1n = fma_(R(-9.0 / 32.0), p.r2 * irg, R(1));
+    const R c2n = R(3.0 / 32.0) * irg;
+    p.c1 = near ? c1n : p.c1;
+    p.c2 = near ? c2n : p.c2;
+}
+
+template <typename R>
+__device__ __forceinline__ PairCoef<R> pair_fin(const PairPre<R>& p) {
+    PairCoef<R> o;
+    o.c1 = p.c1;
+    o.c2 = p.c2;
+    o.cc = fma_(p.w, p.rA, p.c1);
+    o.cz = fma_(p.w, p.rE, p.c1);
+    o.kb = p.kb;
+    o.kcp = p.kcp;
+    o.kcm = p.kcm;
+    return o;
+}
+
+// One pair with its own overlap branch: entered by the whole wave when any
+// lane has an overlapping pair (rare: self pairs and touching neighbours).
+template <typename R>
+__device__ __forceinline__ PairCoef<R> pair_coef(R dx, R dy, R dz, R zi, R zj) {
+    PairPre<R> p = pair_pre<R>(dx, dy, dz, zi, zj);
+    if (__builtin_amdgcn_ballot_w64(pair_near(p))) {
+        __asm__ volatile("" ::: "memory");  // keep this a branch: do not speculate it
+        pair_fix(p);
+    }
+    return pair_fin(p);
 }
 
 // Accumulate M_ij f_j (units of mu0, B factors excluded) into (ux, uy, uz).

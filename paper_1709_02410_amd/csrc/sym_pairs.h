@@ -38,7 +38,12 @@
 //                                        R (&acc)[NQ], R (&src)[NQ],
 //                                        const Box<R>&);
 // which adds the target-side contribution to acc and, when SYM, writes the
-// source-side contribution to src.
+// source-side contribution to src.  A Body with kDuo set also supplies
+//   template <bool SYM> static void pair2(const SymTarget&, const R* ra,
+//                                         const R* rb, R (&acc)[NQ],
+//                                         R (&sa)[NQ], R (&sb)[NQ]);
+// for two consecutive sources at once (the 64-step loop then takes two
+// steps per iteration).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -165,33 +170,54 @@ struct SymLane {
         R* sl = sa + l;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) S[q] = R(0);
-#pragma unroll Body::kUnroll
-        for (int s = 0; s < 64; ++s) {
-            R r[RW];
+        // Source side of step s: to the LDS slots (FP64) or into the rotating
+        // accumulator (FP32).
+        auto source_side = [&](const R(&c)[NQ], int s) {
+            if (sa) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+                    __hip_atomic_fetch_add(sl + q * 128 + s, c[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            } else {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    S[q] = rot_add(S[q], c[q]);
+                    // An empty asm use pins the add to this pair's block:
+                    // otherwise the tail of the pair is sunk past the next
+                    // overlap branch, away from the (unmovable) DPP rotate it
+                    // should fuse with.
+                    __asm__ volatile("" ::"v"(S[q]));
+                }
+            }
+        };
+        auto fetch = [&](R(&r)[RW], int s) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 const VT q = base[v * vs + s];
 #pragma unroll
                 for (int e = 0; e < Vec<R>::W; ++e) r[v * Vec<R>::W + e] = Vec<R>::get(q, e);
             }
-            R c[NQ];
-            Body::template pair<SYM>(t, r, acc, c, box);
-            if constexpr (SYM) {
-                if (sa) {
-#pragma unroll
-                    for (int q = 0; q < NQ; ++q)
-                        __hip_atomic_fetch_add(sl + q * 128 + s, c[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                } else {
-#pragma unroll
-                    for (int q = 0; q < NQ; ++q) {
-                        S[q] = rot_add(S[q], c[q]);
-                        // An empty asm use pins the add to this pair's block:
-                        // otherwise the tail of the pair is sunk past the next
-                        // pair's overlap branch, away from the (unmovable) DPP
-                        // rotate it should fuse with.
-                        __asm__ volatile("" ::"v"(S[q]));
-                    }
+        };
+        if constexpr (Body::kDuo) {
+            // Two steps per iteration sharing one overlap branch; not
+            // unrolled further (fewer registers, and more waves per SIMD).
+#pragma unroll 1
+            for (int s = 0; s < 64; s += 2) {
+                R ra[RW], rb[RW], ca[NQ], cb[NQ];
+                fetch(ra, s);
+                fetch(rb, s + 1);
+                Body::template pair2<SYM>(t, ra, rb, acc, ca, cb);
+                if constexpr (SYM) {
+                    source_side(ca, s);
+                    source_side(cb, s + 1);
                 }
+            }
+        } else {
+#pragma unroll Body::kUnroll
+            for (int s = 0; s < 64; ++s) {
+                R r[RW], c[NQ];
+                fetch(r, s);
+                Body::template pair<SYM>(t, r, acc, c, box);
+                if constexpr (SYM) source_side(c, s);
             }
         }
         if constexpr (SYM) {

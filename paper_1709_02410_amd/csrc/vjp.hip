@@ -123,6 +123,7 @@ struct VjpBody {
     static constexpr int KREC = 2;  // F~, G~
     static constexpr int NQ = kQ;   // grad (3), Mhat F~ (3), Mhat G~ (3)
     static constexpr int kUnroll = 4;
+    static constexpr bool kDuo = false;
     template <bool SYM>
     __device__ static void pair(const SymTarget<R, 2>& t, const R* r, R (&acc)[kQ], R (&src)[kQ], const Box<R>&) {
         constexpr int PW = pos_slots<R>();
