@@ -178,59 +178,149 @@ __global__ void update_kernel(const double* win, double* wout, int64_t n3,
     wout[e] = x;
 }
 
-constexpr int kDotChunk = 2048;  // entries per dot-product block (8 per thread)
+// Blocking of the dot products: a block of 256 threads takes 256 m
+// consecutive entries (m per thread, 1 <= m <= kDotPerThread), with m as
+// small as keeps the grid at kDotBlocks blocks or fewer.
+constexpr int kDotBlocks = 1024;
+constexpr int kDotPerThread = 8;
 
-// Dot products V_j . w (j < nv), or w . w when nv == 0, on a 2-D grid of
-// (chunk, j) blocks; block partials go to partial[j][chunk].  The last block
-// to finish (one atomic ticket, no waiting) adds each j's partials in chunk
-// order (one thread per j) into out[j] (square root for the norm), copies
-// out[copy_idx] to copy_to, and re-arms the ticket.
-__global__ __launch_bounds__(256) void dots_kernel(const double* __restrict__ V, int64_t ld, int nv,
-                                                   const double* __restrict__ w, int64_t n3,
-                                                   double* __restrict__ partial, unsigned* __restrict__ ticket,
-                                                   double* __restrict__ out, int copy_idx,
-                                                   double* __restrict__ copy_to) {
-    __shared__ double red[256];
-    __shared__ bool last;
-    const int j = blockIdx.y, nchunk = gridDim.x;
-    const double* a = nv > 0 ? V + j * ld : w;
-    const int64_t e0 = (int64_t)blockIdx.x * kDotChunk + threadIdx.x;
-    double s = 0.0;
+__host__ __device__ inline int dot_per_thread(int64_t n) {
+    const int64_t m = (n + 256 * (int64_t)kDotBlocks - 1) / (256 * (int64_t)kDotBlocks);
+    return (int)(m < 1 ? 1 : m > kDotPerThread ? kDotPerThread : m);
+}
+
+// Sum over groups of G consecutive lanes (G a power of two up to 64; fixed
+// butterfly order); every lane of a group gets its group's sum.
+template <int G>
+__device__ __forceinline__ double group_sum(double s) {
 #pragma unroll
-    for (int r = 0; r < kDotChunk / 256; ++r) {
-        const int64_t e = e0 + r * 256;
-        if (e < n3) s += a[e] * w[e];
+    for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    return s;
+}
+
+constexpr int kDotBatch = 16;
+
+// Last block of update_dots_kernel: out[j] = sum of partial[j][0..nblk) for
+// j < nd (square root when nv == 0), TPV threads per vector, each adding the
+// blocks b = its index (mod TPV) in order (eight loads in flight), then a
+// TPV-lane butterfly.
+template <int TPV>
+__device__ __forceinline__ void finish_dots(const double* __restrict__ partial, int nblk, int nd, int nv,
+                                            int copy_idx, double* __restrict__ out, double* cpv) {
+    constexpr int kPass = 256 / TPV;
+    const int jq = threadIdx.x / TPV, q = threadIdx.x % TPV;
+    for (int j0 = 0; j0 < nd; j0 += kPass) {
+        const int j = j0 + jq;
+        double s = 0.0;
+        if (j < nd) {
+            const double* pj = partial + (int64_t)j * nblk;
+            for (int b = q; b < nblk; b += 8 * TPV) {
+                double v[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) v[i] = b + i * TPV < nblk ? pj[b + i * TPV] : 0.0;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) s += v[i];
+            }
+        }
+        s = group_sum<TPV>(s);
+        if (q == 0 && j < nd) {
+            const double r = nv > 0 ? s : sqrt(s);
+            out[j] = r;
+            if (j == copy_idx) *cpv = r;
+        }
     }
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+}
+
+// Update then dot products in one pass:
+//   w = win - bscale[0] vprev - sum_{j < nsub} csub[j] V_j  (each term only
+//   when given; written to wout unless there is nothing to write),
+//   out[j] = V_j . w (j < nv), or out[0] = |w| when nv == 0.
+// A block takes 256 m consecutive entries.  Dot products go kDotBatch
+// vectors at a time: every thread puts its entries' products into an LDS
+// tile, then 16 threads per vector add 16 tile columns each and a 16-lane
+// butterfly finishes the block partial, partial[j][block].  The last block
+// to finish (one atomic ticket, no waiting) adds each j's partials
+// (finish_dots) into out[j], copies out[copy_idx] to copy_to and re-arms the
+// ticket.  Every sum has a fixed order.
+__global__ __launch_bounds__(256) void update_dots_kernel(const double* win, double* wout, int64_t n, int m,
+                                                          const double* vprev, const double* __restrict__ bscale,
+                                                          const double* V, int64_t ld,
+                                                          const double* __restrict__ csub, int nsub, int nv,
+                                                          double* __restrict__ partial, unsigned* __restrict__ ticket,
+                                                          double* __restrict__ out, int copy_idx,
+                                                          double* __restrict__ copy_to) {
+    __shared__ double tile[kDotBatch][257];
+    __shared__ double cpv;
+    __shared__ bool last;
+    const int t = threadIdx.x;
+    const int nblk = gridDim.x;
+    const int64_t base = (int64_t)blockIdx.x * 256 * m + t;
+    const bool upd = vprev || nsub > 0;
+    double x[kDotPerThread];
+#pragma unroll
+    for (int r = 0; r < kDotPerThread; ++r) {
+        const int64_t e = base + (int64_t)r * 256;
+        x[r] = 0.0;
+        if (r >= m || e >= n) continue;
+        double v = win[e];
+        if (vprev) v -= bscale[0] * vprev[e];
+        int j = 0;
+        for (; j + 3 < nsub; j += 4) {
+            const double a0 = V[j * ld + e], a1 = V[(j + 1) * ld + e];
+            const double a2 = V[(j + 2) * ld + e], a3 = V[(j + 3) * ld + e];
+            v -= csub[j] * a0;
+            v -= csub[j + 1] * a1;
+            v -= csub[j + 2] * a2;
+            v -= csub[j + 3] * a3;
+        }
+        for (; j < nsub; ++j) v -= csub[j] * V[j * ld + e];
+        if (upd) wout[e] = v;
+        x[r] = v;
+    }
+    const int nd = nv > 0 ? nv : 1;
+    const int jr = t >> 4, c0 = t & 15;  // reduction: vector jr of the batch, columns c0 + 16 i
+    for (int j0 = 0; j0 < nd; j0 += kDotBatch) {
+        const int jn = nd - j0 < kDotBatch ? nd - j0 : kDotBatch;
+#pragma unroll
+        for (int u = 0; u < kDotBatch; ++u) {
+            double p = 0.0;
+            if (u < jn) {
+                if (nv > 0) {
+                    const double* a = V + (j0 + u) * ld;
+#pragma unroll
+                    for (int r = 0; r < kDotPerThread; ++r) {
+                        const int64_t e = base + (int64_t)r * 256;
+                        if (r < m && e < n) p = fma(a[e], x[r], p);
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < kDotPerThread; ++r) p = fma(x[r], x[r], p);
+                }
+            }
+            tile[u][t] = p;
+        }
+        __syncthreads();
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) s += tile[jr][c0 + 16 * i];
+        s = group_sum<16>(s);
+        if (c0 == 0 && jr < jn) partial[(int64_t)(j0 + jr) * nblk + blockIdx.x] = s;
         __syncthreads();
     }
-    if (threadIdx.x == 0) partial[(int64_t)j * nchunk + blockIdx.x] = red[0];
     __threadfence();
-    if (threadIdx.x == 0) last = atomicAdd(ticket, 1u) == gridDim.x * gridDim.y - 1;
+    if (t == 0) last = atomicAdd(ticket, 1u) == (unsigned)nblk - 1;
     __syncthreads();
     if (!last) return;
     __threadfence();
-    const int nd = gridDim.y;
-    for (int jj = threadIdx.x; jj < nd; jj += blockDim.x) {
-        const double* p = partial + (int64_t)jj * nchunk;
-        double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
-        int c = 0;
-        for (; c + 3 < nchunk; c += 4) {
-            t0 += p[c];
-            t1 += p[c + 1];
-            t2 += p[c + 2];
-            t3 += p[c + 3];
-        }
-        for (; c < nchunk; ++c) t0 += p[c];
-        const double t = (t0 + t1) + (t2 + t3);
-        out[jj] = nv > 0 ? t : sqrt(t);
-    }
+    if (nd <= 4)
+        finish_dots<64>(partial, nblk, nd, nv, copy_idx, out, &cpv);
+    else if (nd <= 16)
+        finish_dots<16>(partial, nblk, nd, nv, copy_idx, out, &cpv);
+    else
+        finish_dots<4>(partial, nblk, nd, nv, copy_idx, out, &cpv);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        if (copy_to) copy_to[0] = out[copy_idx];
+    if (t == 0) {
+        if (copy_to) copy_to[0] = cpv;
         *ticket = 0u;
     }
 }
@@ -250,7 +340,10 @@ unsigned grid_of(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
-int64_t dot_chunks(int64_t n) { return (n + kDotChunk - 1) / kDotChunk; }
+int64_t dot_chunks(int64_t n) {
+    const int64_t span = 256 * (int64_t)dot_per_thread(n);
+    return (n + span - 1) / span;
+}
 
 int vec_update(const double* win, double* wout, int64_t n, const double* vprev, const double* bscale,
                const double* V, int64_t ld, const double* csub, int nsub, hipStream_t st) {
@@ -260,12 +353,20 @@ int vec_update(const double* win, double* wout, int64_t n, const double* vprev, 
     return RPYW_OK;
 }
 
-int vec_dots(const double* V, int64_t ld, int nv, const double* w, int64_t n, double* partial, unsigned* ticket,
-             double* out, int copy_idx, double* copy_to, hipStream_t st) {
-    hipLaunchKernelGGL(dots_kernel, dim3((unsigned)dot_chunks(n), (unsigned)(nv > 0 ? nv : 1)), dim3(256), 0, st, V,
-                       ld, nv, w, n, partial, ticket, out, copy_idx, copy_to);
+int vec_update_dots(const double* win, double* wout, int64_t n, const double* vprev, const double* bscale,
+                    const double* V, int64_t ld, const double* csub, int nsub, int nv, double* partial,
+                    unsigned* ticket, double* out, int copy_idx, double* copy_to, hipStream_t st) {
+    hipLaunchKernelGGL(update_dots_kernel, dim3((unsigned)dot_chunks(n)), dim3(256), 0, st, win, wout, n,
+                       dot_per_thread(n), vprev, bscale, V, ld, csub, nsub, nv, partial, ticket, out, copy_idx,
+                       copy_to);
     RPYW_HIP(hipGetLastError());
     return RPYW_OK;
+}
+
+int vec_dots(const double* V, int64_t ld, int nv, const double* w, int64_t n, double* partial, unsigned* ticket,
+             double* out, int copy_idx, double* copy_to, hipStream_t st) {
+    return vec_update_dots(w, nullptr, n, nullptr, nullptr, V, ld, nullptr, 0, nv, partial, ticket, out, copy_idx,
+                           copy_to, st);
 }
 
 int vec_comb(const double* V, int64_t ld, int nv, const double* c, double* out, int64_t n, hipStream_t st) {

@@ -168,10 +168,13 @@ int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, dou
     RPYW_HIP(hipMemsetAsync(ticket, 0, sizeof(unsigned), st));
     if ((rc = body_factors_build(pos, N, a, eta, body_offsets, n_bodies, ar, st, pc, notspd))) return rc;
 
-    auto update = [&](const double* vprev, const double* bscale, const double* csub, int nsub) {
-        return vec_update(w, w, n3, vprev, bscale, V, n3, csub, nsub, st);
+    // w -= bscale[0] vprev + V csub (terms when given), then the dot products
+    // of w with V_0..V_{nv-1} (nv > 0) or its norm (nv = 0)
+    auto update_dots = [&](const double* vprev, const double* bscale, const double* csub, int nsub, int nv,
+                           double* res, int copy_idx, double* copy_to) {
+        return vec_update_dots(w, w, n3, vprev, bscale, V, n3, csub, nsub, nv, partial, ticket, res, copy_idx,
+                               copy_to, st);
     };
-    // dot products with V_0..V_{nv-1} (nv > 0) or the norm (nv = 0) of vec
     auto dots = [&](const double* vec, int nv, double* res, int copy_idx, double* copy_to) {
         return vec_dots(V, n3, nv, vec, n3, partial, ticket, res, copy_idx, copy_to, st);
     };
@@ -203,15 +206,21 @@ int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, dou
         if ((r = products(pos, x, y, N, 1, a, eta, prec, ar, st, dom))) return r;  // y = M x
         if ((r = pc.apply(1, y, w, n3, st))) return r;                        // w = L^-1 y
         // w -= beta_{k-1} v_{k-1}; full reorthogonalisation in two passes,
-        // alpha_k = v_k . w from the first
-        if (k > 0 && (r = update(V + (size_t)(k - 1) * n3, d_ab + 2 * (k - 1) + 1, nullptr, 0))) return r;
-        if ((r = dots(w, k + 1, d_c1, k, d_ab + 2 * k))) return r;
-        if ((r = update(nullptr, nullptr, d_c1, k + 1))) return r;
-        if ((r = dots(w, k + 1, d_c2, 0, nullptr))) return r;
-        if ((r = update(nullptr, nullptr, d_c2, k + 1))) return r;
-        if ((r = dots(w, 0, d_ab + 2 * k + 1, 0, nullptr))) return r;  // beta_k = |w|
+        // alpha_k = v_k . w from the first; beta_k = |w|
+        const double* vprev = k > 0 ? V + (size_t)(k - 1) * n3 : nullptr;
+        const double* bprev = k > 0 ? d_ab + 2 * (k - 1) + 1 : nullptr;
+        if ((r = update_dots(vprev, bprev, nullptr, 0, k + 1, d_c1, k, d_ab + 2 * k))) return r;
+        if ((r = update_dots(nullptr, nullptr, d_c1, k + 1, k + 1, d_c2, 0, nullptr))) return r;
+        if ((r = update_dots(nullptr, nullptr, d_c2, k + 1, 0, d_ab + 2 * k + 1, 0, nullptr))) return r;
         RPYW_HIP(hipMemcpyAsync(h_ab + 2 * k, d_ab + 2 * k, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-        RPYW_HIP(hipEventRecord(g_ab.ev[k & 1], st));
+        RPYW_HIP(hipEventRecord(g_ab.ev[k % PinnedSlots::kSlots], st));
+        return RPYW_OK;
+    };
+    const int depth = (double)N * (double)N <= kSpeculatePairs ? kSpeculateDepth : 0;
+    int queued = 0;
+    auto fill = [&](int upto) -> int {  // queue steps up to index upto - 1
+        for (; queued < upto && queued < max_iter; ++queued)
+            if (int r = launch_iter(queued)) return r;
         return RPYW_OK;
     };
 
@@ -219,12 +228,11 @@ int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, dou
     bool converged = false;
     double rel = INFINITY;
     int k = 0;
-    const bool speculate = (double)N * (double)N <= kSpeculatePairs;
-    if ((rc = launch_iter(0))) return rc;
+    if ((rc = fill(1 + depth))) return rc;
     for (; k < max_iter; ++k) {
-        RPYW_HIP(hipEventSynchronize(g_ab.ev[k & 1]));
+        RPYW_HIP(hipEventSynchronize(g_ab.ev[k % PinnedSlots::kSlots]));
         const double ak = h_ab[2 * k], bk = h_ab[2 * k + 1];
-        if (speculate && k + 1 < max_iter && (rc = launch_iter(k + 1))) return rc;
+        if (depth && (rc = fill(k + 1 + depth))) return rc;
         alpha.push_back(ak);
         c.assign(k + 1, 0.0);
         if (tridiag_sqrt_coeffs(alpha.data(), beta.data(), k + 1, beta0, c.data()) != RPYW_OK) return RPYW_EHIP;
@@ -248,7 +256,7 @@ int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, dou
         }
         cprev = c;
         beta.push_back(bk);
-        if (!speculate && k + 1 < max_iter && (rc = launch_iter(k + 1))) return rc;
+        if (!depth && (rc = fill(k + 2))) return rc;
     }
     const int used = (int)c.size();
     *iters = converged ? k + 1 : max_iter;

@@ -285,15 +285,26 @@ struct ProductBody {
     }
 };
 
-// One thread per (blob, output component q = 3k + c).
+// kEpiParts threads per (blob, output component q = 3k + c): each adds its
+// share of the partials (sym_gather), then the shares are added in a fixed
+// order.  Blocks cover 64 consecutive blobs (coalesced partial reads).
+constexpr int kEpiParts = 8;
 template <typename R>
-__global__ void sym_epilogue(const double* __restrict__ tpart, const R* __restrict__ spart,
-                             const double* __restrict__ B, int64_t N, int ng, int C, int Hmax, int K, int kb,
-                             int G, double mu0, double* __restrict__ U) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(64 * kEpiParts) void sym_epilogue(const double* __restrict__ tpart,
+                                                               const R* __restrict__ spart,
+                                                               const double* __restrict__ B, int64_t N, int ng, int C,
+                                                               int Hmax, int K, int G, double mu0,
+                                                               double* __restrict__ U) {
+    __shared__ double red[kEpiParts][64];
+    const int x = threadIdx.x & 63, u = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 64 + x;
     const int q = blockIdx.y;
-    if (i >= N || q >= 3 * kb) return;
-    const double s = sym_gather<R>(tpart, spart, i, ng, C, Hmax, 3 * K, q, G);
+    red[u][x] = i < N ? sym_gather<R>(tpart, spart, i, ng, C, Hmax, 3 * K, q, G, u, kEpiParts) : 0.0;
+    __syncthreads();
+    if (u != 0 || i >= N) return;
+    double s = red[0][x];
+#pragma unroll
+    for (int v = 1; v < kEpiParts; ++v) s += red[v][x];
     U[((int64_t)(q / 3) * N + i) * 3 + q % 3] = mu0 * B[i] * s;
 }
 
@@ -503,13 +514,13 @@ int sym_pass(const double* pos, const double* F, double* U, int64_t N, int kb, i
     if (e != hipSuccess) return RPYW_EHIP;
     profile_end(st, ev, (dom.periodic() ? 9.0 : 1.0) * (double)kb * (double)N * (double)N);
     const double m0 = mu0_of(a, eta);
-    const dim3 ge(g1, (unsigned)(3 * kb));
+    const dim3 ge((unsigned)((N + 63) / 64), (unsigned)(3 * kb));
     if (prec == RPYW_FP32C)
-        hipLaunchKernelGGL(sym_epilogue<float>, ge, dim3(kBlock), 0, st, tpart, (const float*)spart, B, N, sp.ng, sp.C,
-                           sp.Hmax, K, kb, sp.G, m0, U);
+        hipLaunchKernelGGL(sym_epilogue<float>, ge, dim3(64 * kEpiParts), 0, st, tpart, (const float*)spart, B, N,
+                           sp.ng, sp.C, sp.Hmax, K, sp.G, m0, U);
     else
-        hipLaunchKernelGGL(sym_epilogue<double>, ge, dim3(kBlock), 0, st, tpart, (const double*)spart, B, N, sp.ng,
-                           sp.C, sp.Hmax, K, kb, sp.G, m0, U);
+        hipLaunchKernelGGL(sym_epilogue<double>, ge, dim3(64 * kEpiParts), 0, st, tpart, (const double*)spart, B, N,
+                           sp.ng, sp.C, sp.Hmax, K, sp.G, m0, U);
     RPYW_HIP(hipGetLastError());
     ar.used = mark;
     return RPYW_OK;

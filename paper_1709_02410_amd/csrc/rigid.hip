@@ -243,7 +243,7 @@ __global__ void rigid_rhs_kernel(const double* __restrict__ slip, const double* 
         b[e] = FT ? -FT[e - n3] : 0.0;
 }
 
-PinnedSlots g_h;  // Hessenberg columns, two alternating slots
+PinnedSlots g_h;  // Hessenberg columns, one slot per step in flight
 
 }  // namespace
 
@@ -278,18 +278,17 @@ int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets,
     double* bv = (double*)ar.take(n * sizeof(double));
     double* y = (double*)ar.take(n3 * sizeof(double));
     double* partial = (double*)ar.take((size_t)(max_iter + 2) * dot_chunks(n) * sizeof(double));
-    double* d_c1 = (double*)ar.take((max_iter + 8) * sizeof(double));
-    double* d_c2 = (double*)ar.take((max_iter + 8) * sizeof(double));
+    // column of step k: c1[0..k], c2[0..k], h_{k+1,k} (one copy to the host)
+    double* d_col = (double*)ar.take((2 * max_iter + 8) * sizeof(double));
     double* d_hn = (double*)ar.take((max_iter + 8) * sizeof(double));  // [0] = |b|, [k + 1] = h_{k+1,k}
     double* d_y = (double*)ar.take((max_iter + 8) * sizeof(double));
     unsigned* ticket = (unsigned*)ar.take(kAlign);
     int* notspd = (int*)ar.take(sizeof(int));
-    if (!Wall || !Nall || !V || !z || !w || !bv || !y || !partial || !d_c1 || !d_c2 || !d_hn || !d_y || !ticket ||
-        !notspd)
+    if (!Wall || !Nall || !V || !z || !w || !bv || !y || !partial || !d_col || !d_hn || !d_y || !ticket || !notspd)
         return RPYW_ENOMEM;
     std::lock_guard<std::mutex> lk(g_h.mu);
     const int slot = 2 * (max_iter + 2);  // c1[0..k], c2[0..k], h_{k+1,k}
-    int rc = g_h.reserve((size_t)2 * slot * sizeof(double));
+    int rc = g_h.reserve((size_t)PinnedSlots::kSlots * slot * sizeof(double));
     if (rc) return rc;
     double* h_slot = g_h.p;
 
@@ -337,16 +336,25 @@ int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets,
         hipLaunchKernelGGL(rigid_apply_kernel, dim3(n_bodies), dim3(kRT), 0, st, pos, q, pc.bofs, z, z + n3, y, w,
                            w + n3);
         RPYW_HIP(hipGetLastError());
-        if ((r = dots(w, k + 1, d_c1, 0, nullptr))) return r;
-        if ((r = vec_update(w, w, n, nullptr, nullptr, V, n, d_c1, k + 1, st))) return r;
-        if ((r = dots(w, k + 1, d_c2, 0, nullptr))) return r;
-        if ((r = vec_update(w, w, n, nullptr, nullptr, V, n, d_c2, k + 1, st))) return r;
-        if ((r = dots(w, 0, d_hn + k + 1, 0, nullptr))) return r;
-        double* hs = h_slot + (size_t)(k & 1) * slot;
-        RPYW_HIP(hipMemcpyAsync(hs, d_c1, (k + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
-        RPYW_HIP(hipMemcpyAsync(hs + k + 1, d_c2, (k + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
-        RPYW_HIP(hipMemcpyAsync(hs + 2 * (k + 1), d_hn + k + 1, sizeof(double), hipMemcpyDeviceToHost, st));
-        RPYW_HIP(hipEventRecord(g_h.ev[k & 1], st));
+        double* c1 = d_col;
+        double* c2 = d_col + (k + 1);
+        if ((r = dots(w, k + 1, c1, 0, nullptr))) return r;
+        if ((r = vec_update_dots(w, w, n, nullptr, nullptr, V, n, c1, k + 1, k + 1, partial, ticket, c2, 0, nullptr,
+                                 st)))
+            return r;
+        if ((r = vec_update_dots(w, w, n, nullptr, nullptr, V, n, c2, k + 1, 0, partial, ticket, c2 + (k + 1), 0,
+                                 d_hn + k + 1, st)))
+            return r;
+        double* hs = h_slot + (size_t)(k % PinnedSlots::kSlots) * slot;
+        RPYW_HIP(hipMemcpyAsync(hs, d_col, (2 * (k + 1) + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+        RPYW_HIP(hipEventRecord(g_h.ev[k % PinnedSlots::kSlots], st));
+        return RPYW_OK;
+    };
+    const int depth = (double)N * (double)N <= kSpeculatePairs ? kSpeculateDepth : 0;
+    int queued = 0;
+    auto fill = [&](int upto) -> int {  // queue steps up to index upto - 1
+        for (; queued < upto && queued < max_iter; ++queued)
+            if (int r = launch_step(queued)) return r;
         return RPYW_OK;
     };
 
@@ -356,15 +364,14 @@ int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets,
     bool converged = false;
     double res = 1.0;
     int k = 0;
-    const bool speculate = (double)N * (double)N <= kSpeculatePairs;
-    if ((rc = launch_step(0))) return rc;
+    if ((rc = fill(1 + depth))) return rc;
     for (; k < max_iter; ++k) {
-        RPYW_HIP(hipEventSynchronize(g_h.ev[k & 1]));
-        const double* hs = h_slot + (size_t)(k & 1) * slot;
+        RPYW_HIP(hipEventSynchronize(g_h.ev[k % PinnedSlots::kSlots]));
+        const double* hs = h_slot + (size_t)(k % PinnedSlots::kSlots) * slot;
         std::vector<double> h(k + 2);
         for (int j = 0; j <= k; ++j) h[j] = hs[j] + hs[k + 1 + j];
         h[k + 1] = hs[2 * (k + 1)];
-        if (speculate && k + 1 < max_iter && (rc = launch_step(k + 1))) return rc;
+        if (depth && (rc = fill(k + 1 + depth))) return rc;
         for (int j = 0; j < k; ++j) {
             const double t0 = cs[j] * h[j] + sn[j] * h[j + 1];
             h[j + 1] = -sn[j] * h[j] + cs[j] * h[j + 1];
@@ -386,7 +393,7 @@ int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets,
             converged = true;
             break;
         }
-        if (!speculate && k + 1 < max_iter && (rc = launch_step(k + 1))) return rc;
+        if (!depth && (rc = fill(k + 2))) return rc;
     }
     const int m = (int)R.size();
     *iters = m;

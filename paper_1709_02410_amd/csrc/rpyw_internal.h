@@ -128,26 +128,35 @@ int body_factors_build(const double* pos, int64_t N, double a, double eta, const
 //           fixed-order finish; out[copy_idx] is also copied to copy_to;
 //           partial holds max(nv, 1) dot_chunks(n) doubles, ticket one
 //           zeroed unsigned that the kernel re-arms;
+//   update_dots: update (when vprev or nsub is given, result to wout) then
+//           dots of the result, in one pass;
 //   comb:   out = sum_{j < nv} c[j] V_j.
 int64_t dot_chunks(int64_t n);
 int vec_update(const double* win, double* wout, int64_t n, const double* vprev, const double* bscale,
                const double* V, int64_t ld, const double* csub, int nsub, hipStream_t st);
 int vec_dots(const double* V, int64_t ld, int nv, const double* w, int64_t n, double* partial, unsigned* ticket,
              double* out, int copy_idx, double* copy_to, hipStream_t st);
+int vec_update_dots(const double* win, double* wout, int64_t n, const double* vprev, const double* bscale,
+                    const double* V, int64_t ld, const double* csub, int nsub, int nv, double* partial,
+                    unsigned* ticket, double* out, int copy_idx, double* copy_to, hipStream_t st);
 int vec_comb(const double* V, int64_t ld, int nv, const double* c, double* out, int64_t n, hipStream_t st);
-// Krylov drivers queue step k + 1 before the host has examined step k only
-// while one product is cheap against the host's per-step latency (about
-// 0.1 ms): above this many pairs the speculative step, wasted after the last
-// iteration, costs more than it hides.
+// Krylov drivers keep kSpeculateDepth steps queued beyond the one the host
+// examines (a step needs only device data from the previous one), so the GPU
+// does not wait for the host between steps, but only while one product is
+// cheap against the host's per-step latency (about 0.1 ms): above this many
+// pairs the speculative steps, wasted after the last iteration, cost more
+// than they hide, and step k + 1 is queued after the host has examined k.
 constexpr double kSpeculatePairs = 4.0e8;
+constexpr int kSpeculateDepth = 2;
 
 // Library-owned pinned host buffer plus two events for per-iteration
 // device->host copies of a solver; the caller holds mu while using it.
 struct PinnedSlots {
+    static constexpr int kSlots = 4;  // steps in flight at most (kSpeculateDepth + 1)
     std::mutex mu;
     double* p = nullptr;
     size_t cap = 0;
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t ev[kSlots] = {};
     int reserve(size_t bytes);
 };
 

@@ -327,26 +327,34 @@ __global__ __launch_bounds__(64 * NB) void sym_kernel(const R* __restrict__ rec,
     for (int q = 0; q < NQ; ++q) tp[q * G + threadIdx.x] = me.total(q);
 }
 
-// Sum of quantity q of blob i over the chunk target partials and the item
-// source partials, in a fixed order.
+// Part u of U of the sum of quantity q of blob i over the chunk target
+// partials and the item source partials: chunks c and items d with
+// c, d = u (mod U), in a fixed order.  U = 1 gives the whole sum.
 template <typename R>
 __device__ __forceinline__ double sym_gather(const double* __restrict__ tpart, const R* __restrict__ spart, int64_t i,
-                                             int ng, int C, int Hmax, int NQ, int q, int G = 256) {
+                                             int ng, int C, int Hmax, int NQ, int q, int G = 256, int u = 0,
+                                             int U = 1) {
     const int P = (int)(i / G), t = (int)(i % G);
     const int dmax = sym_dmax(P, ng);
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     const double* tp = tpart + ((int64_t)P * C * NQ + q) * G + t;
-    for (int c = 0; c < C; ++c) s0 += tp[(int64_t)c * NQ * G];
-    const R* sp = spart + ((int64_t)P * (Hmax + 1) * NQ + q) * G + t;
-    const int64_t st = (int64_t)NQ * G;
-    int d = 0;
-    for (; d + 3 <= dmax; d += 4) {
-        s0 += (double)sp[(d + 0) * st];
-        s1 += (double)sp[(d + 1) * st];
-        s2 += (double)sp[(d + 2) * st];
-        s3 += (double)sp[(d + 3) * st];
+    const int64_t tst = (int64_t)NQ * G;
+    int c = u;
+    for (; c + U < C; c += 2 * U) {
+        s2 += tp[c * tst];
+        s3 += tp[(c + U) * tst];
     }
-    for (; d <= dmax; ++d) s0 += (double)sp[d * st];
+    if (c < C) s2 += tp[c * tst];
+    const R* sp = spart + ((int64_t)P * (Hmax + 1) * NQ + q) * G + t;
+    const int64_t st = tst;
+    int d = u;
+    for (; d + 3 * U <= dmax; d += 4 * U) {
+        s0 += (double)sp[d * st];
+        s1 += (double)sp[(d + U) * st];
+        s2 += (double)sp[(d + 2 * U) * st];
+        s3 += (double)sp[(d + 3 * U) * st];
+    }
+    for (; d <= dmax; d += U) s0 += (double)sp[d * st];
     return (s0 + s1) + (s2 + s3);
 }
 
