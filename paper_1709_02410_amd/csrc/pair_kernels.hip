@@ -293,13 +293,13 @@ template <typename R>
 __global__ __launch_bounds__(64 * kEpiParts) void sym_epilogue(const double* __restrict__ tpart,
                                                                const R* __restrict__ spart,
                                                                const double* __restrict__ B, int64_t N, int ng, int C,
-                                                               int Hmax, int K, int G, double mu0,
+                                                               int Hmax, int nseg, int K, int G, double mu0,
                                                                double* __restrict__ U) {
     __shared__ double red[kEpiParts][64];
     const int x = threadIdx.x & 63, u = threadIdx.x >> 6;
     const int64_t i = (int64_t)blockIdx.x * 64 + x;
     const int q = blockIdx.y;
-    red[u][x] = i < N ? sym_gather<R>(tpart, spart, i, ng, C, Hmax, 3 * K, q, G, u, kEpiParts) : 0.0;
+    red[u][x] = i < N ? sym_gather<R>(tpart, spart, i, ng, C, Hmax, 3 * K, q, G, u, kEpiParts, nseg) : 0.0;
     __syncthreads();
     if (u != 0 || i >= N) return;
     double s = red[0][x];
@@ -309,14 +309,15 @@ __global__ __launch_bounds__(64 * kEpiParts) void sym_epilogue(const double* __r
 }
 
 template <typename R, int K, bool PER>
-hipError_t launch_sym_t(const R* rec, int G, int ng, int C, int ipw, int Hmax, double* tpart, R* spart,
-                        const Box<R>& box, hipStream_t st) {
-    if (G == 64)
-        hipLaunchKernelGGL((sym_kernel<R, ProductBody<R, K, PER>, 1>), dim3((unsigned)(ng * C)), dim3(64), 0, st, rec,
-                           ng, C, ipw, Hmax, tpart, spart, box);
+hipError_t launch_sym_t(const R* rec, const SymPlan& sp, int ipw, double* tpart, R* spart, const Box<R>& box,
+                        hipStream_t st) {
+    const dim3 grid((unsigned)((int64_t)sp.ng * sp.C * sp.nseg));
+    if (sp.G == 64)
+        hipLaunchKernelGGL((sym_kernel<R, ProductBody<R, K, PER>, 1>), grid, dim3(64), 0, st, rec, sp.ng, sp.C, ipw,
+                           sp.Hmax, sp.nseg, tpart, spart, box);
     else
-        hipLaunchKernelGGL((sym_kernel<R, ProductBody<R, K, PER>, 4>), dim3((unsigned)(ng * C)), dim3(256), 0, st,
-                           rec, ng, C, ipw, Hmax, tpart, spart, box);
+        hipLaunchKernelGGL((sym_kernel<R, ProductBody<R, K, PER>, 4>), grid, dim3(256), 0, st, rec, sp.ng, sp.C, ipw,
+                           sp.Hmax, sp.nseg, tpart, spart, box);
     return hipGetLastError();
 }
 
@@ -423,10 +424,15 @@ SymPlan sym_plan(int64_t N, int prec, int K, int ipw, int G) {
     s.Hmax = s.ng / 2;
     if (ipw < 1) ipw = 1;
     s.C = (s.Hmax + 1 + ipw - 1) / ipw;
+    // Segments: enough work items to give every SIMD several (independent
+    // of ipw, so that the workspace bound taken at ipw 1 holds).
+    const int64_t items = (int64_t)s.ng * (s.Hmax + 1);
+    s.nseg = 1;
+    while (s.nseg < 4 && items * s.nseg < kSymItemsMin) s.nseg *= 2;
     const size_t npad = (size_t)s.ng * s.G;
     s.rec_bytes = align_up(npad * rec_width(prec, K) * real_size(prec)) + align_up(npad * sizeof(double));
-    s.tpart_bytes = align_up((size_t)s.ng * s.C * 3 * K * s.G * sizeof(double));
-    s.spart_bytes = align_up((size_t)s.ng * (s.Hmax + 1) * 3 * K * s.G * real_size(prec));
+    s.tpart_bytes = align_up((size_t)s.ng * s.C * s.nseg * 3 * K * s.G * sizeof(double));
+    s.spart_bytes = align_up((size_t)s.ng * (s.Hmax + 1) * s.nseg * 3 * K * s.G * real_size(prec));
     s.ok = K <= 4 && s.spart_bytes <= ((size_t)4 << 30) && (s.G == 256 || N <= kSym64MaxN);
     return s;
 }
@@ -498,12 +504,10 @@ int sym_pass(const double* pos, const double* F, double* U, int64_t N, int kb, i
         constexpr int KK = decltype(Kc)::value;
         if (dom.periodic()) {
             if constexpr (KK == 1)
-                return launch_sym_t<R, 1, true>((const R*)rec, sp.G, sp.ng, sp.C, ipw, sp.Hmax, tpart, (R*)spart,
-                                                make_box<R>(dom, a), st);
+                return launch_sym_t<R, 1, true>((const R*)rec, sp, ipw, tpart, (R*)spart, make_box<R>(dom, a), st);
             return hipErrorInvalidValue;
         }
-        return launch_sym_t<R, KK, false>((const R*)rec, sp.G, sp.ng, sp.C, ipw, sp.Hmax, tpart, (R*)spart,
-                                          Box<R>{}, st);
+        return launch_sym_t<R, KK, false>((const R*)rec, sp, ipw, tpart, (R*)spart, Box<R>{}, st);
     };
     if (prec == RPYW_FP32C)
         e = K == 1 ? go(0.f, std::integral_constant<int, 1>{})
@@ -517,10 +521,10 @@ int sym_pass(const double* pos, const double* F, double* U, int64_t N, int kb, i
     const dim3 ge((unsigned)((N + 63) / 64), (unsigned)(3 * kb));
     if (prec == RPYW_FP32C)
         hipLaunchKernelGGL(sym_epilogue<float>, ge, dim3(64 * kEpiParts), 0, st, tpart, (const float*)spart, B, N,
-                           sp.ng, sp.C, sp.Hmax, K, sp.G, m0, U);
+                           sp.ng, sp.C, sp.Hmax, sp.nseg, K, sp.G, m0, U);
     else
         hipLaunchKernelGGL(sym_epilogue<double>, ge, dim3(64 * kEpiParts), 0, st, tpart, (const double*)spart, B, N,
-                           sp.ng, sp.C, sp.Hmax, K, sp.G, m0, U);
+                           sp.ng, sp.C, sp.Hmax, sp.nseg, K, sp.G, m0, U);
     RPYW_HIP(hipGetLastError());
     ar.used = mark;
     return RPYW_OK;

@@ -36,7 +36,8 @@ struct Domain {
 
 // Symmetric path geometry for N blobs, K right-hand sides.
 struct SymPlan {
-    int G;  // blobs per group: 256 or 64
+    int G;     // blobs per group: 256 or 64
+    int nseg;  // segments per item pass (1, 2 or 4: more workgroups for tiny problems)
     int ng, Hmax, C;
     size_t rec_bytes, tpart_bytes, spart_bytes;
     bool ok;
@@ -45,6 +46,9 @@ struct SymPlan {
 // as N^2 / 128 per quantity, four times those of groups of 256, and beyond
 // a few ten thousand blobs both group sizes run at the same speed.
 constexpr int64_t kSym64MaxN = 32768;
+// Work items (group pairs) below which the symmetric passes are split into
+// segments.
+constexpr int64_t kSymItemsMin = 8192;
 SymPlan sym_plan(int64_t N, int prec, int K, int ipw, int G = 256);
 inline int sym_group(int sym) { return sym == 2 ? 64 : 256; }
 

@@ -162,9 +162,11 @@ struct SymLane {
     // into the add), so that after the pass lane l holds source l's sum
     // (sa == nullptr), or to LDS sa[q * 128 + l + s] by an atomic add.
     // vs: LDS entries per vector slot of the tile (128 per source block).
+    // Steps s0 .. s1 - 1 only (a segment of the pass; s1 - s0 even): the
+    // rotating accumulator then ends with source (l + s1) mod 64 in lane l.
     template <bool SYM>
     __device__ void pass(const typename Vec<R>::T* __restrict__ tile, int vs, int blk, int l, R* sa, R (&S)[NQ],
-                         const Box<R>& box) {
+                         const Box<R>& box, int s0 = 0, int s1 = 64) {
         using VT = typename Vec<R>::T;
         const VT* base = tile + blk * 128 + l;
         R* sl = sa + l;
@@ -201,7 +203,7 @@ struct SymLane {
             // Two steps per iteration sharing one overlap branch; not
             // unrolled further (fewer registers, and more waves per SIMD).
 #pragma unroll 1
-            for (int s = 0; s < 64; s += 2) {
+            for (int s = s0; s < s1; s += 2) {
                 R ra[RW], rb[RW], ca[NQ], cb[NQ];
                 fetch(ra, s);
                 fetch(rb, s + 1);
@@ -213,7 +215,7 @@ struct SymLane {
             }
         } else {
 #pragma unroll Body::kUnroll
-            for (int s = 0; s < 64; ++s) {
+            for (int s = s0; s < s1; ++s) {
                 R r[RW], c[NQ];
                 fetch(r, s);
                 Body::template pair<SYM>(t, r, acc, c, box);
@@ -245,11 +247,13 @@ struct SymLane {
 
 // Groups of G = 64 NB blobs (NB blocks of 64, one wave each): NB = 4 for
 // large problems, NB = 1 to have enough workgroups when there are few groups.
+// Very small problems also split every item's 64-step passes into nseg
+// segments, each its own workgroup (nseg = 1, 2 or 4).
 // rec: ng * G records (padded with force-free blobs far away).
-// tpart: [ng * C][NQ][G] doubles; spart: [ng * (Hmax + 1)][NQ][G].
+// tpart: [ng * C * nseg][NQ][G] doubles; spart: [ng * (Hmax + 1) * nseg][NQ][G].
 template <typename R, class Body, int NB = 4>
 __global__ __launch_bounds__(64 * NB) void sym_kernel(const R* __restrict__ rec, int ng, int C, int ipw, int Hmax,
-                                                      double* __restrict__ tpart, R* __restrict__ spart,
+                                                      int nseg, double* __restrict__ tpart, R* __restrict__ spart,
                                                       Box<R> box) {
     using L = SymLane<R, Body>;
     using VT = typename Vec<R>::T;
@@ -264,7 +268,8 @@ __global__ __launch_bounds__(64 * NB) void sym_kernel(const R* __restrict__ rec,
     __shared__ VT tile[L::NV * VS];
     __shared__ R sacc[kLds ? NB : 1][kLds ? NQ : 1][kLds ? 128 : 1];  // per source block, slots l + s
     __shared__ R red[kLds ? 1 : NB][kLds ? 1 : NQ][kLds ? 1 : G];
-    const int P = blockIdx.x / C, c = blockIdx.x % C;
+    const int g = blockIdx.x % nseg, P = blockIdx.x / nseg / C, c = blockIdx.x / nseg % C;
+    const int s0 = g * (64 / nseg), s1 = s0 + 64 / nseg;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     L me;
     me.load(rec + ((int64_t)P * G + threadIdx.x) * L::RW);
@@ -275,11 +280,11 @@ __global__ __launch_bounds__(64 * NB) void sym_kernel(const R* __restrict__ rec,
         const int Q = (P + d) % ng;
         __syncthreads();
         {
-            const VT* g = reinterpret_cast<const VT*>(rec + ((int64_t)Q * G + threadIdx.x) * L::RW);
+            const VT* gr = reinterpret_cast<const VT*>(rec + ((int64_t)Q * G + threadIdx.x) * L::RW);
             const int b = threadIdx.x >> 6, j = threadIdx.x & 63;
 #pragma unroll
             for (int v = 0; v < L::NV; ++v) {
-                const VT q = g[v];
+                const VT q = gr[v];
                 tile[v * VS + b * 128 + j] = q;
                 tile[v * VS + b * 128 + j + 64] = q;
             }
@@ -296,19 +301,19 @@ __global__ __launch_bounds__(64 * NB) void sym_kernel(const R* __restrict__ rec,
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) S[q] = R(0);
             } else if (d == 0 && blk == w) {
-                me.template pass<false>(tile, VS, blk, l, nullptr, S, box);
+                me.template pass<false>(tile, VS, blk, l, nullptr, S, box, s0, s1);
             } else {
-                me.template pass<true>(tile, VS, blk, l, kLds ? &sacc[blk][0][0] : nullptr, S, box);
+                me.template pass<true>(tile, VS, blk, l, kLds ? &sacc[blk][0][0] : nullptr, S, box, s0, s1);
             }
             if constexpr (kLds) {
                 __syncthreads();  // one wave per source block in every phase
             } else {
 #pragma unroll
-                for (int q = 0; q < NQ; ++q) red[w][q][blk * 64 + l] = S[q];
+                for (int q = 0; q < NQ; ++q) red[w][q][blk * 64 + ((l + s1) & 63)] = S[q];
             }
         }
         if constexpr (!kLds) __syncthreads();
-        R* out = spart + ((int64_t)Q * (Hmax + 1) + d) * NQ * G;
+        R* out = spart + (((int64_t)Q * (Hmax + 1) + d) * nseg + g) * NQ * G;
         const int b = threadIdx.x >> 6, j = threadIdx.x & 63;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
@@ -322,30 +327,32 @@ __global__ __launch_bounds__(64 * NB) void sym_kernel(const R* __restrict__ rec,
             }
         }
     }
-    double* tp = tpart + ((int64_t)P * C + c) * NQ * G;
+    double* tp = tpart + (int64_t)blockIdx.x * NQ * G;  // chunk c * nseg + g of row P
 #pragma unroll
     for (int q = 0; q < NQ; ++q) tp[q * G + threadIdx.x] = me.total(q);
 }
 
 // Part u of U of the sum of quantity q of blob i over the chunk target
-// partials and the item source partials: chunks c and items d with
-// c, d = u (mod U), in a fixed order.  U = 1 gives the whole sum.
+// partials and the item source partials (nseg of each per chunk and item):
+// chunks c and items d with c, d = u (mod U), in a fixed order.  U = 1 gives
+// the whole sum.
 template <typename R>
 __device__ __forceinline__ double sym_gather(const double* __restrict__ tpart, const R* __restrict__ spart, int64_t i,
                                              int ng, int C, int Hmax, int NQ, int q, int G = 256, int u = 0,
-                                             int U = 1) {
+                                             int U = 1, int nseg = 1) {
     const int P = (int)(i / G), t = (int)(i % G);
-    const int dmax = sym_dmax(P, ng);
+    const int Cs = C * nseg;
+    const int dmax = (sym_dmax(P, ng) + 1) * nseg - 1;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    const double* tp = tpart + ((int64_t)P * C * NQ + q) * G + t;
+    const double* tp = tpart + ((int64_t)P * Cs * NQ + q) * G + t;
     const int64_t tst = (int64_t)NQ * G;
     int c = u;
-    for (; c + U < C; c += 2 * U) {
+    for (; c + U < Cs; c += 2 * U) {
         s2 += tp[c * tst];
         s3 += tp[(c + U) * tst];
     }
-    if (c < C) s2 += tp[c * tst];
-    const R* sp = spart + ((int64_t)P * (Hmax + 1) * NQ + q) * G + t;
+    if (c < Cs) s2 += tp[c * tst];
+    const R* sp = spart + ((int64_t)P * (Hmax + 1) * nseg * NQ + q) * G + t;
     const int64_t st = tst;
     int d = u;
     for (; d + 3 * U <= dmax; d += 4 * U) {

@@ -240,7 +240,7 @@ bool vjp_sym_plan(int64_t N, int prec, int ipw, int G, int* ng, int* C, int* Hma
 template <typename R, int NB>
 void launch_vjp_sym(const R* rec, int ng, int C, int ipw, int Hmax, double* tpart, R* spart, hipStream_t st) {
     hipLaunchKernelGGL((sym_kernel<R, VjpBody<R>, NB>), dim3((unsigned)(ng * C)), dim3(64 * NB), 0, st, rec, ng, C,
-                       ipw, Hmax, tpart, spart, Box<R>{});
+                       ipw, Hmax, 1, tpart, spart, Box<R>{});
 }
 
 }  // namespace
