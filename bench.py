@@ -187,6 +187,21 @@ def main():
                                          "frac_fp32_peak": fl / (call_ms * 1e-3) / 1e12 / PEAK_FP32}
         del F16, U16
 
+        # single products on configs 0, 1 and 4 (default launch shapes), both
+        # precisions: pairs/s and the pair kernel's share of the call
+        for cname, cfg in (("C0", wl.config0(seed=0)), ("C1", wl.config1(seed=0)), ("C4", wl.config4(seed=0))):
+            pcf, fcf = T(cfg.pos), T(wl.gaussian(cfg.pos.shape, 4))
+            ucf = torch.empty_like(fcf)
+            for prec, pname in ((rp.FP32C, "fp32c"), (rp.FP64, "fp64")):
+                reps = 50 if cfg.N <= 4000 else 10
+                w, km, ln, pr = timed(lambda: rp.matvec(pcf, fcf, precision=prec, out=ucf), reps, 3)
+                shc = rp.get_shape(prec, cfg.N, 1)
+                kms = km / max(ln, 1)
+                rows[f"product_{cname}_{pname}"] = {
+                    "blobs": cfg.N, "pairs_per_s": cfg.N ** 2 / w, "ms": w * 1e3, "kernel_ms": kms, "shape": shc,
+                    "tflops_alg": algorithmic_flop(cfg.N, 1, shc["sym"]) / (kms * 1e-3) / 1e12}
+            del pcf, fcf, ucf
+
         # batched suspensions (config 3) against per-instance launches
         C3 = wl.config3(seed=0)
         offs = C3.sys_offsets

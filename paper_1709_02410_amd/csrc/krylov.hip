@@ -399,6 +399,7 @@ int body_factors_build(const double* pos, int64_t N, double a, double eta, const
     const double inv_a = 1.0 / a, m0 = 1.0 / (6.0 * M_PI * eta * a);
     pc.diag = n_bodies == 0;
     pc.nb = n_bodies;
+    pc.flag = notspd;
     if (!pc.diag) {
         std::vector<int> hb(n_bodies + 1);
         std::vector<int64_t> hl(n_bodies + 1, 0);

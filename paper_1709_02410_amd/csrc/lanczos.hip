@@ -140,7 +140,7 @@ size_t lanczos_ws_bytes(int64_t N, int max_iter, int n_bodies, int prec) {
 
 int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, double a, double eta,
                  const int64_t* body_offsets, int n_bodies, double tol, int max_iter, int prec, Arena& ar, int* iters,
-                 double* err, hipStream_t st, const Domain& dom) {
+                 double* err, hipStream_t st, const Domain& dom, const BodyFactors* pre) {
     const int64_t n3 = 3 * N;
     *iters = 0;
     *err = 0.0;
@@ -166,7 +166,10 @@ int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, dou
 
     RPYW_HIP(hipMemsetAsync(notspd, 0, sizeof(int), st));
     RPYW_HIP(hipMemsetAsync(ticket, 0, sizeof(unsigned), st));
-    if ((rc = body_factors_build(pos, N, a, eta, body_offsets, n_bodies, ar, st, pc, notspd))) return rc;
+    if (pre)
+        pc = *pre;
+    else if ((rc = body_factors_build(pos, N, a, eta, body_offsets, n_bodies, ar, st, pc, notspd)))
+        return rc;
 
     // w -= bscale[0] vprev + V csub (terms when given), then the dot products
     // of w with V_0..V_{nv-1} (nv > 0) or its norm (nv = 0)
@@ -184,9 +187,11 @@ int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, dou
     double beta0 = 0.0;
     int bad = 0;
     RPYW_HIP(hipMemcpyAsync(&beta0, d_b0, sizeof(double), hipMemcpyDeviceToHost, st));
+    int bad_pre = 0;
     RPYW_HIP(hipMemcpyAsync(&bad, notspd, sizeof(int), hipMemcpyDeviceToHost, st));
+    if (pre && pre->flag) RPYW_HIP(hipMemcpyAsync(&bad_pre, pre->flag, sizeof(int), hipMemcpyDeviceToHost, st));
     RPYW_HIP(hipStreamSynchronize(st));
-    if (bad) return RPYW_ENOTSPD;
+    if (bad || bad_pre) return RPYW_ENOTSPD;
     if (beta0 == 0.0) {
         RPYW_HIP(hipMemsetAsync(out, 0, n3 * sizeof(double), st));
         return RPYW_OK;

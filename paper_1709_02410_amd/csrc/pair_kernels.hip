@@ -200,7 +200,11 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(const R* __restrict__ r
 // accumulates M_ij f_j, the source side M_ji f_i, which is the same block
 // applied with the two off-diagonal wall coefficients exchanged.
 
-template <typename R, int K, bool PER = false>
+// PER: 0 open domain; 1 pseudo-periodic; 2 pseudo-periodic with cell sides
+// above 4.5 a, where only the minimum image can overlap its target (every
+// other image is at least half a cell away), so the other eight skip the
+// overlap branch and their arithmetic can interleave (used in FP64).
+template <typename R, int K, int PER = 0>
 struct ProductBody {
     static constexpr int KREC = K;
     static constexpr int NQ = 3 * K;
@@ -215,6 +219,12 @@ struct ProductBody {
     __device__ static void image(const SymTarget<R, K>& t, const R* r, R dx, R dy, R dz, R (&acc)[NQ],
                                  R (&src)[NQ]) {
         apply<SYM>(pair_coef<R>(dx, dy, dz, t.z, r[2]), t, r, dx, dy, dz, acc, src);
+    }
+    // An image that cannot overlap its target (r > 2 a): no overlap branch.
+    template <bool SYM>
+    __device__ static void far_image(const SymTarget<R, K>& t, const R* r, R dx, R dy, R dz, R (&acc)[NQ],
+                                     R (&src)[NQ]) {
+        apply<SYM>(pair_fin(pair_pre<R>(dx, dy, dz, t.z, r[2])), t, r, dx, dy, dz, acc, src);
     }
     template <bool SYM>
     __device__ static void apply(PairCoef<R> p, const SymTarget<R, K>& t, const R* r, R dx, R dy, R dz,
@@ -279,7 +289,10 @@ struct ProductBody {
                 for (int sy = -1; sy <= 1; ++sy) {
                     const R ex = sx == 0 ? dx : sx < 0 ? dx - box.lx : dx + box.lx;
                     const R ey = sy == 0 ? dy : sy < 0 ? dy - box.ly : dy + box.ly;
-                    image<SYM>(t, r, ex, ey, dz, acc, src);
+                    if (PER == 2 && (sx != 0 || sy != 0))
+                        far_image<SYM>(t, r, ex, ey, dz, acc, src);
+                    else
+                        image<SYM>(t, r, ex, ey, dz, acc, src);
                 }
         }
     }
@@ -308,7 +321,7 @@ __global__ __launch_bounds__(64 * kEpiParts) void sym_epilogue(const double* __r
     U[((int64_t)(q / 3) * N + i) * 3 + q % 3] = mu0 * B[i] * s;
 }
 
-template <typename R, int K, bool PER>
+template <typename R, int K, int PER>
 hipError_t launch_sym_t(const R* rec, const SymPlan& sp, int ipw, double* tpart, R* spart, const Box<R>& box,
                         hipStream_t st) {
     const dim3 grid((unsigned)((int64_t)sp.ng * sp.C * sp.nseg));
@@ -503,11 +516,18 @@ int sym_pass(const double* pos, const double* F, double* U, int64_t N, int kb, i
         using R = decltype(Rt);
         constexpr int KK = decltype(Kc)::value;
         if (dom.periodic()) {
-            if constexpr (KK == 1)
-                return launch_sym_t<R, 1, true>((const R*)rec, sp, ipw, tpart, (R*)spart, make_box<R>(dom, a), st);
+            if constexpr (KK == 1) {
+                // FP64 only: in FP32 the branch-free far images measured
+                // 4-7% slower, in FP64 up to 10% faster
+                if constexpr (sizeof(R) == 8)
+                    if (std::min(dom.lx, dom.ly) > 4.5 * a)
+                        return launch_sym_t<R, 1, 2>((const R*)rec, sp, ipw, tpart, (R*)spart, make_box<R>(dom, a),
+                                                     st);
+                return launch_sym_t<R, 1, 1>((const R*)rec, sp, ipw, tpart, (R*)spart, make_box<R>(dom, a), st);
+            }
             return hipErrorInvalidValue;
         }
-        return launch_sym_t<R, KK, false>((const R*)rec, sp, ipw, tpart, (R*)spart, Box<R>{}, st);
+        return launch_sym_t<R, KK, 0>((const R*)rec, sp, ipw, tpart, (R*)spart, Box<R>{}, st);
     };
     if (prec == RPYW_FP32C)
         e = K == 1 ? go(0.f, std::integral_constant<int, 1>{})

@@ -265,7 +265,8 @@ size_t rigid_ws_bytes(int64_t N, int max_iter, int n_bodies, int prec) {
 
 int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets, int n_bodies, const double* slip,
                 const double* FT, double* lam_out, double* U_out, int64_t N, double a, double eta, double tol,
-                int max_iter, int prec, Arena& ar, int* iters, double* res_out, hipStream_t st, const Domain& dom) {
+                int max_iter, int prec, Arena& ar, int* iters, double* res_out, hipStream_t st, const Domain& dom,
+                const BodyFactors* pre) {
     const int64_t n3 = 3 * N, n6 = 6 * (int64_t)n_bodies, n = n3 + n6;
     *iters = 0;
     *res_out = 0.0;
@@ -294,7 +295,10 @@ int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets,
 
     RPYW_HIP(hipMemsetAsync(notspd, 0, sizeof(int), st));
     RPYW_HIP(hipMemsetAsync(ticket, 0, sizeof(unsigned), st));
-    if ((rc = body_factors_build(pos, N, a, eta, body_offsets, n_bodies, ar, st, pc, notspd))) return rc;
+    if (pre)
+        pc = *pre;
+    else if ((rc = body_factors_build(pos, N, a, eta, body_offsets, n_bodies, ar, st, pc, notspd)))
+        return rc;
     hipLaunchKernelGGL(rigid_factors_kernel, dim3(n_bodies), dim3(kRT), 0, st, pos, q, pc.bofs, pc.lofs, pc.L, Wall,
                        Nall, notspd);
     RPYW_HIP(hipGetLastError());
@@ -316,9 +320,11 @@ int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets,
     double beta = 0.0;
     int bad = 0;
     RPYW_HIP(hipMemcpyAsync(&beta, d_hn, sizeof(double), hipMemcpyDeviceToHost, st));
+    int bad_pre = 0;
     RPYW_HIP(hipMemcpyAsync(&bad, notspd, sizeof(int), hipMemcpyDeviceToHost, st));
+    if (pre && pre->flag) RPYW_HIP(hipMemcpyAsync(&bad_pre, pre->flag, sizeof(int), hipMemcpyDeviceToHost, st));
     RPYW_HIP(hipStreamSynchronize(st));
-    if (bad) return RPYW_ENOTSPD;
+    if (bad || bad_pre) return RPYW_ENOTSPD;
     if (!std::isfinite(beta)) return RPYW_EINVAL;
     if (beta == 0.0) {
         RPYW_HIP(hipMemsetAsync(lam_out, 0, n3 * sizeof(double), st));

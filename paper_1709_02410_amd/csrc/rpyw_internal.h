@@ -115,6 +115,7 @@ struct BodyFactors {
     int* bofs = nullptr;      // device [nb + 1] blob offsets
     int64_t* lofs = nullptr;  // device [nb + 1] offsets of the (3 n_p)^2 blocks
     double* L = nullptr;      // per body L_p then L_p^-1 (at 2 lofs[p]); or the diagonal [3N]
+    int* flag = nullptr;      // device int set by the build when a block is not positive definite
     // mode 0: out = L v; 1: out = L^-1 v; 2: out = L^-T v.  With scale the
     // input is v / scale[0] and, with store, that scaled input is written
     // there too.
@@ -166,9 +167,11 @@ struct PinnedSlots {
 
 // Lanczos (lanczos.hip)
 size_t lanczos_ws_bytes(int64_t N, int max_iter, int n_bodies, int prec);
+// pre: factors already built for these positions and bodies (then not rebuilt).
 int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, double a, double eta,
                  const int64_t* body_offsets, int n_bodies, double tol, int max_iter, int prec, Arena& ar,
-                 int* iters, double* err, hipStream_t st, const Domain& dom = Domain{});
+                 int* iters, double* err, hipStream_t st, const Domain& dom = Domain{},
+                 const BodyFactors* pre = nullptr);
 int tridiag_sqrt_coeffs(const double* alpha, const double* beta, int k, double beta0, double* c);
 
 // Rigid multiblobs (rigid.hip)
@@ -176,7 +179,7 @@ size_t rigid_ws_bytes(int64_t N, int max_iter, int n_bodies, int prec);
 int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets, int n_bodies, const double* slip,
                 const double* FT, double* lam_out, double* U_out, int64_t N, double a, double eta, double tol,
                 int max_iter, int prec, Arena& ar, int* iters, double* res_out, hipStream_t st,
-                const Domain& dom = Domain{});
+                const Domain& dom = Domain{}, const BodyFactors* pre = nullptr);
 
 // Body kinematics and the Trapezoidal Slip step (ts.hip)
 int body_blobs(const double* q, const double* theta, const double* ref, const int* bofs_dev, int nb, double* pos,

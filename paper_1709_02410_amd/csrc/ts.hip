@@ -230,11 +230,22 @@ size_t ts_ws_bytes(int64_t N, int max_iter, int nb, int prec) {
     b += 10 * align_up(n3 * sizeof(double));
     b += 8 * align_up((size_t)6 * nb * sizeof(double));     // body vectors (q+- counts as one)
     b += 2 * align_up((size_t)4 * nb * sizeof(double));     // theta+-
+    b += body_factors_bytes(N, nb) + 2 * kAlign;  // factors shared by the solves at Q^n, and their flag
     size_t sub = rigid_ws_bytes(N, max_iter, nb, prec);
     sub = std::max(sub, lanczos_ws_bytes(N, max_iter, nb, prec));
     sub = std::max(sub, batched_ws_bytes(2 * N, 2, 1, prec));
     sub = std::max(sub, product_ws_bytes(N, prec, 1));
     return b + sub + 16 * kAlign;
+}
+
+// Preconditioner factors of one configuration, built once for the solves
+// that share it (their flag is checked by each solve).
+int shared_factors(const double* pos, int64_t N, double a, double eta, const int64_t* body_offsets, int nb,
+                   Arena& ar, hipStream_t st, BodyFactors& pc) {
+    int* flag = (int*)ar.take(sizeof(int));
+    if (!flag) return RPYW_ENOMEM;
+    RPYW_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+    return body_factors_build(pos, N, a, eta, body_offsets, nb, ar, st, pc, flag);
 }
 
 int ts_predict(const double* q, const double* theta, const double* ref, const int64_t* body_offsets, int nb,
@@ -267,11 +278,14 @@ int ts_predict(const double* q, const double* theta, const double* ref, const in
     if ((rc = body_blobs(q, theta, ref, bd.bofs, nb, pos0, st))) return rc;
     hipLaunchKernelGGL(slip_vectors_kernel, dim3(nb), dim3(kTT), 0, st, Ws, Lp, bd.bofs, kT, n3, WD, WF);
     RPYW_HIP(hipGetLastError());
+    // one set of preconditioner factors for the three solves at Q^n
+    BodyFactors pc0;
+    if ((rc = shared_factors(pos0, N, a, eta, body_offsets, nb, ar, st, pc0))) return rc;
     // RFD displacement problem (the sub-solvers keep what they take from the
     // arena, so it is rewound after each)
     const size_t mark = ar.used;
     rc = rigid_solve(pos0, q, body_offsets, nb, WD, nullptr, lam, dQ, N, a, eta, tol, max_iter, prec, ar, &it, &res,
-                     st, dom);
+                     st, dom, &pc0);
     ar.used = mark;
     iters[0] = it;
     if (rc < 0) return rc;
@@ -294,7 +308,8 @@ int ts_predict(const double* q, const double* theta, const double* ref, const in
     if ((rc = lincomb(Upm, 1.0 / delta, Upm + n3, -1.0 / delta, n3, DS, st))) return rc;
     // Brownian slip c M^{1/2} W^n
     double err = 0.0;
-    rc = lanczos_sqrt(pos0, Wn, lam, N, a, eta, body_offsets, nb, tol, max_iter, prec, ar, &it, &err, st, dom);
+    rc = lanczos_sqrt(pos0, Wn, lam, N, a, eta, body_offsets, nb, tol, max_iter, prec, ar, &it, &err, st, dom,
+                      &pc0);
     ar.used = mark;
     iters[1] = it;
     if (rc < 0) return rc;
@@ -302,7 +317,7 @@ int ts_predict(const double* q, const double* theta, const double* ref, const in
     if ((rc = lincomb(lam, std::sqrt(2.0 * kT / dt), nullptr, 0.0, n3, root, st))) return rc;
     // predictor
     rc = rigid_solve(pos0, q, body_offsets, nb, root, FT, lam, U0, N, a, eta, tol, max_iter, prec, ar, &it, &res, st,
-                     dom);
+                     dom, &pc0);
     ar.used = mark;
     iters[2] = it;
     if (rc < 0) return rc;
@@ -375,11 +390,13 @@ int emt_step(const double* q, const double* theta, const double* ref, const int6
     if ((rc = body_blobs(q, theta, ref, bd.bofs, nb, pos0, st))) return rc;
     hipLaunchKernelGGL(traction_vectors_kernel, dim3(gridn(nb)), dim3(256), 0, st, Wf, Wt, Lp, kT, nb, WFT, dQ);
     RPYW_HIP(hipGetLastError());
+    BodyFactors pc0;  // shared by the three solves at Q^n
+    if ((rc = shared_factors(pos0, N, a, eta, body_offsets, nb, ar, st, pc0))) return rc;
     // RFD mobility problem: no slip, random force and torque W^FT (the
     // sub-solvers keep what they take from the arena: rewound after each)
     const size_t mark = ar.used;
     rc = rigid_solve(pos0, q, body_offsets, nb, nullptr, WFT, lam2, Ur, N, a, eta, tol, max_iter, prec, ar, &it, &res,
-                     st, dom);
+                     st, dom, &pc0);
     ar.used = mark;
     iters[0] = it;
     if (rc < 0) return rc;
@@ -404,7 +421,8 @@ int emt_step(const double* q, const double* theta, const double* ref, const int6
                        1.0 / delta, DS);
     RPYW_HIP(hipGetLastError());
     // Brownian slip and the mobility problem
-    rc = lanczos_sqrt(pos0, Wn, slip, N, a, eta, body_offsets, nb, tol, max_iter, prec, ar, &it, &err, st, dom);
+    rc = lanczos_sqrt(pos0, Wn, slip, N, a, eta, body_offsets, nb, tol, max_iter, prec, ar, &it, &err, st, dom,
+                      &pc0);
     ar.used = mark;
     iters[1] = it;
     if (rc < 0) return rc;
@@ -412,7 +430,7 @@ int emt_step(const double* q, const double* theta, const double* ref, const int6
     if ((rc = lincomb(slip, std::sqrt(2.0 * kT / dt), DS, 1.0, n3, slip, st))) return rc;
     if ((rc = lincomb(FT, 1.0, DF, -1.0, n6, F, st))) return rc;
     rc = rigid_solve(pos0, q, body_offsets, nb, slip, F, lam2, U0, N, a, eta, tol, max_iter, prec, ar, &it, &res, st,
-                     dom);
+                     dom, &pc0);
     ar.used = mark;
     iters[2] = it;
     if (rc < 0) return rc;
@@ -457,19 +475,21 @@ int emrfd_step(const double* q, const double* theta, const double* ref, const in
         if (rc < 0) return rc;
         merge(status, rc);
     }
-    // Brownian slip and the mobility problem at Q^n
+    // Brownian slip and the mobility problem at Q^n (one set of factors)
     if ((rc = body_blobs(q, theta, ref, bd.bofs, nb, pos, st))) return rc;
-    rc = lanczos_sqrt(pos, Wn, lam, N, a, eta, body_offsets, nb, tol, max_iter, prec, ar, &it, &err, st, dom);
-    ar.used = mark;
+    BodyFactors pc0;
+    if ((rc = shared_factors(pos, N, a, eta, body_offsets, nb, ar, st, pc0))) return rc;
+    double* lam0 = (double*)ar.take(n3 * sizeof(double));
+    if (!lam0) return RPYW_ENOMEM;
+    const size_t mark2 = ar.used;
+    rc = lanczos_sqrt(pos, Wn, lam, N, a, eta, body_offsets, nb, tol, max_iter, prec, ar, &it, &err, st, dom, &pc0);
+    ar.used = mark2;
     iters[2] = it;
     if (rc < 0) return rc;
     merge(status, rc);
     if ((rc = lincomb(lam, std::sqrt(2.0 * kT / dt), nullptr, 0.0, n3, lam, st))) return rc;
-    double* lam0 = (double*)ar.take(n3 * sizeof(double));
-    if (!lam0) return RPYW_ENOMEM;
-    const size_t mark2 = ar.used;
     rc = rigid_solve(pos, q, body_offsets, nb, lam, FT, lam0, U0, N, a, eta, tol, max_iter, prec, ar, &it, &res, st,
-                     dom);
+                     dom, &pc0);
     ar.used = mark2;
     iters[3] = it;
     if (rc < 0) return rc;

@@ -110,3 +110,24 @@ def test_periodic_rigid_solve_matches_dense(rp, orc):
     lam, U, it, res, ok = rp.rigid_solve(_t(cfg.pos), _t(q), offs, _t(slip), _t(FT), tol=1e-11, box=(L, L))
     print(f"periodic rigid iters={it} rel U={_rel(U.cpu().numpy(), U_ref):.3e}", flush=True)
     assert ok and _rel(U.cpu().numpy(), U_ref) <= 1e-8 and _rel(lam.cpu().numpy(), lam_ref) <= 1e-7
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_small_cell_images_overlap(rp, orc, prec):
+    """Cells narrower than 4.5 a, where periodic images other than the minimum
+    one overlap their targets (r < 2 a): the kernel keeps the overlap branch
+    for every image there (the wider-cell FP64 path skips it for the eight
+    shifted images)."""
+    rng = np.random.default_rng(77)
+    N, box = 30, (4.0, 4.2)
+    pos = np.column_stack([rng.uniform(0, box[0], N), rng.uniform(0, box[1], N), rng.uniform(0.8, 3.0, N)])
+    f = wl.gaussian(pos.shape, 78)
+    ref = orc.matvec(pos, f, box=box)
+    got = rp.matvec(_t(pos), _t(f), precision=prec, box=box).cpu().numpy()
+    print(f"small cell prec={prec} rel={_rel(got, ref):.3e}", flush=True)
+    assert _rel(got, ref) <= TOL[prec]
+    # just above the threshold: the shifted images are at least 2.25 a away
+    box2 = (4.6, 4.7)
+    ref2 = orc.matvec(pos, f, box=box2)
+    got2 = rp.matvec(_t(pos), _t(f), precision=prec, box=box2).cpu().numpy()
+    assert _rel(got2, ref2) <= TOL[prec]
