@@ -74,7 +74,8 @@ int64_t g_prof_n = 0;
 }  // namespace
 
 // Defaults from measurements on MI355X: the symmetric kernel wins for one
-// right-hand side from about a thousand blobs up (1.7x at 1e5); groups of
+// right-hand side from a few hundred blobs up (1.7x at 1e5, 2x at 1000,
+// where its passes are also split into segments); groups of
 // 64 blobs, one item per workgroup, are up to 3x faster than groups of 256
 // below ten thousand blobs (which leave the GPU underfilled) and still 5% at
 // 30000; wider RHS blocks are faster on the plain kernel.  For groups of 256
@@ -84,7 +85,7 @@ Shape default_shape(int64_t N, int k, int prec) {
     s.tpl = N >= 65536 ? 2 : 1;
     s.tile = 64;
     s.kblk = std::min(kclass(k), prec == RPYW_FP32C ? 16 : 8);
-    s.sym = (s.kblk == 1 && N >= 1024) ? (N <= kSym64MaxN ? 2 : 1) : 0;
+    s.sym = (s.kblk == 1 && N >= 512) ? (N <= kSym64MaxN ? 2 : 1) : 0;
     const int64_t ng = (N + 255) / 256, hm = ng / 2 + 1;
     s.ipw = s.sym == 2 ? 1 : (int)std::max<int64_t>(1, std::min<int64_t>(4, hm * ng / 16384));
     return s;

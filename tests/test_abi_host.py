@@ -154,5 +154,6 @@ def test_launch_shape_validation_and_defaults(lib):
     rpywall.reset_shape(1, 5000, 1)
     assert rpywall.get_shape(1, 3840, 1)["sym"] == 2
     assert rpywall.get_shape(0, 100000, 1)["sym"] == 1
-    assert rpywall.get_shape(1, 1000, 1)["sym"] == 0
+    assert rpywall.get_shape(1, 1000, 1)["sym"] == 2
+    assert rpywall.get_shape(1, 300, 1)["sym"] == 0
     assert rpywall.get_shape(1, 3840, 4)["sym"] == 0
