@@ -113,9 +113,12 @@ int rpy_wall_matvec_batched(const double* pos, const int64_t* sys_offsets, int32
  * tridiagonal eigensolve; `precision` selects the pair arithmetic of the
  * products by M.  pos, W, out: device [N][3].  iters_out, err_est_out: HOST
  * (may be NULL) receive the iteration count and the last relative change.
- * Synchronises `stream` once per iteration.  Returns RPYW_NOT_CONVERGED
- * (best iterate written) if max_iter is reached, RPYW_ENOTSPD if a block has
- * no Cholesky factor (e.g. a blob at z <= 0). */
+ * Waits once per iteration for that step's scalars, so the iteration count
+ * and the status are known on return; the final combination into `out`
+ * (and up to two speculatively queued steps) are still stream-ordered on
+ * `stream` then.  Returns RPYW_NOT_CONVERGED (best iterate written) if
+ * max_iter is reached, RPYW_ENOTSPD if a block has no Cholesky factor (e.g.
+ * a blob at z <= 0). */
 int rpy_wall_lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, double a, double eta,
                           const int64_t* body_offsets, int32_t n_bodies, double tol, int32_t max_iter,
                           int precision, void* ws, size_t ws_bytes, int32_t* iters_out, double* err_est_out,
@@ -151,8 +154,10 @@ int rpy_wall_lanczos_sqrt_periodic(const double* pos, const double* W, double* o
  * lambda: device [N][3], U: device [n_bodies][6] (u, omega).  `precision`
  * selects the pair arithmetic of the products by M.  iters_out, res_out:
  * HOST (may be NULL) receive the iterations and the relative residual
- * estimate.  Synchronises `stream` once per iteration.  Returns
- * RPYW_NOT_CONVERGED (iterate written) if max_iter is reached,
+ * estimate.  Waits once per iteration for that step's Hessenberg column;
+ * the outputs are written stream-ordered after the call returns, as for
+ * rpy_wall_lanczos_sqrt.  Returns RPYW_NOT_CONVERGED (iterate written) if
+ * max_iter is reached,
  * RPYW_ENOTSPD if a body block has no Cholesky factor or a body's blobs do
  * not fix all six rigid motions (a single blob, a straight rod). */
 int rpy_wall_rigid_solve(const double* pos, const double* q, const int64_t* body_offsets, int32_t n_bodies,
@@ -178,7 +183,8 @@ int rpy_wall_rigid_solve_periodic(const double* pos, const double* q, const int6
  * [n_bodies][3]; theta: device [n_bodies][4] unit quaternions (s, px, py,
  * pz); ref: device [N][3] body-frame positions rho; body_offsets: HOST int64
  * [n_bodies+1] (0 .. N, strictly increasing); pos: device [N][3].
- * Synchronises `stream` (the offsets are uploaded from the host). */
+ * Asynchronous (the offsets go up through a library-owned pinned buffer,
+ * so the caller's host array may be freed on return). */
 int rpy_wall_body_blobs(const double* q, const double* theta, const double* ref, const int64_t* body_offsets,
                         int32_t n_bodies, double* pos, int64_t N, void* ws, size_t ws_bytes, void* stream);
 
@@ -216,9 +222,11 @@ int rpy_wall_body_move(const double* q, const double* theta, const double* U, do
  * pseudo-periodic cell of rpy_wall_matvec_periodic.  tol, max_iter: of every
  * iterative solve (Lanczos and GMRES); `precision`: pair arithmetic of the
  * products by M.  iters_out: HOST, may be NULL: predict writes 3 counts
- * (RFD solve, Lanczos, predictor solve), correct 1.  Both synchronise
- * `stream`.  Returns RPYW_NOT_CONVERGED (step completed) if an iterative
- * solve hit max_iter, RPYW_ENOTSPD as the rigid solve does. */
+ * (RFD solve, Lanczos, predictor solve), correct 1.  Both wait for the
+ * iterative solves' per-iteration scalars; their device outputs are
+ * stream-ordered (complete once `stream` reaches the end of the call's
+ * work).  Returns RPYW_NOT_CONVERGED (step completed) if an iterative solve
+ * hit max_iter, RPYW_ENOTSPD as the rigid solve does. */
 size_t rpy_wall_ts_state_bytes(int64_t N, int32_t n_bodies);
 int rpy_wall_ts_predict(const double* q, const double* theta, const double* ref, const int64_t* body_offsets,
                         int32_t n_bodies, int64_t N, const double* Lp, const double* force_torque, const double* Ws,
@@ -241,7 +249,8 @@ int rpy_wall_ts_correct(const double* q, const double* theta, const double* q_ti
  *   U^n: mobility problem with slip D^S + sqrt(2 kT / dt) M^{1/2} W^n and
  *   force F^n - D^F (force_torque = F(Q^n));  Q^{n+1} = Q^n + dt U^n.
  * Other arguments as for rpy_wall_ts_predict; iters_out (HOST [3], may be
- * NULL): RFD solve, Lanczos, mobility solve.  Synchronises `stream`. */
+ * NULL): RFD solve, Lanczos, mobility solve.  Waits as
+ * rpy_wall_ts_predict does; outputs stream-ordered. */
 int rpy_wall_emt_step(const double* q, const double* theta, const double* ref, const int64_t* body_offsets,
                       int32_t n_bodies, int64_t N, const double* Lp, const double* force_torque, const double* Wf,
                       const double* Wt, const double* Wn, double kT, double dt, double delta, double a, double eta,
@@ -254,7 +263,8 @@ int rpy_wall_emt_step(const double* q, const double* theta, const double* ref, c
  * problem at Q^n with slip sqrt(2 kT / dt) M^{1/2} W^n and force F^n;
  * Q^{n+1} = Q^n + dt (U^n + (U+ - U-) / delta).  Arguments as for
  * rpy_wall_emt_step; iters_out (HOST [4], may be NULL): the two RFD solves,
- * Lanczos, the mobility solve.  Synchronises `stream`. */
+ * Lanczos, the mobility solve.  Waits as rpy_wall_ts_predict does; outputs
+ * stream-ordered. */
 int rpy_wall_emrfd_step(const double* q, const double* theta, const double* ref, const int64_t* body_offsets,
                         int32_t n_bodies, int64_t N, const double* Lp, const double* force_torque, const double* Wf,
                         const double* Wt, const double* Wn, double kT, double dt, double delta, double a, double eta,

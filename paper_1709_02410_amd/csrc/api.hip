@@ -336,10 +336,8 @@ int rpy_wall_body_blobs(const double* q, const double* theta, const double* ref,
     if (!bofs) return RPYW_ENOMEM;
     std::vector<int> hb(n_bodies + 1);
     for (int p = 0; p <= n_bodies; ++p) hb[p] = (int)body_offsets[p];
-    RPYW_HIP(hipMemcpyAsync(bofs, hb.data(), hb.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    rc = body_blobs(q, theta, ref, bofs, n_bodies, pos, st);
-    RPYW_HIP(hipStreamSynchronize(st));  // hb goes out of scope
-    return rc;
+    if ((rc = stage_upload(hb.data(), hb.size() * sizeof(int), bofs, st))) return rc;
+    return body_blobs(q, theta, ref, bofs, n_bodies, pos, st);
 }
 
 int rpy_wall_body_move(const double* q, const double* theta, const double* U, double h, int32_t n_bodies,

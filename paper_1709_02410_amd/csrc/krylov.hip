@@ -7,6 +7,8 @@
 // All reductions use a fixed order, so results are bitwise reproducible.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "pair_math.h"
@@ -412,9 +414,8 @@ int body_factors_build(const double* pos, int64_t N, double a, double eta, const
         pc.lofs = (int64_t*)ar.take(hl.size() * sizeof(int64_t));
         pc.L = (double*)ar.take((size_t)2 * hl[n_bodies] * sizeof(double));  // L and L^-1
         if (!pc.bofs || !pc.lofs || !pc.L) return RPYW_ENOMEM;
-        RPYW_HIP(hipMemcpyAsync(pc.bofs, hb.data(), hb.size() * sizeof(int), hipMemcpyHostToDevice, st));
-        RPYW_HIP(hipMemcpyAsync(pc.lofs, hl.data(), hl.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
-        RPYW_HIP(hipStreamSynchronize(st));  // host vectors go out of scope
+        if (int r = stage_upload(hb.data(), hb.size() * sizeof(int), pc.bofs, st)) return r;
+        if (int r = stage_upload(hl.data(), hl.size() * sizeof(int64_t), pc.lofs, st)) return r;
         int nmax = 1;
         for (int p = 0; p < n_bodies; ++p) nmax = std::max(nmax, (int)(body_offsets[p + 1] - body_offsets[p]));
         const size_t lds = ((size_t)3 * nmax * (3 * nmax + 1) + 4 * (size_t)nmax) * sizeof(double);
@@ -432,7 +433,75 @@ int body_factors_build(const double* pos, int64_t N, double a, double eta, const
     return RPYW_OK;
 }
 
+// ---------------------------------------------------------- staging ring
+
+namespace {
+
+// Pinned ring buffer for small host -> device uploads: an upload takes the
+// next free stretch, copied from host memory the caller may free at once;
+// a stretch is reused only after the copy that last read it has completed
+// (its event), so uploads normally never wait.
+struct StageRing {
+    std::mutex mu;
+    char* host = nullptr;
+    size_t cap = 0, head = 0;
+    struct Use {
+        size_t off, len;
+        hipEvent_t ev;
+    };
+    std::vector<Use> busy;
+    std::vector<hipEvent_t> idle;
+};
+StageRing g_ring;
+
+}  // namespace
+
+int stage_upload(const void* src, size_t bytes, void* dst, hipStream_t st) {
+    if (bytes == 0) return RPYW_OK;
+    std::lock_guard<std::mutex> lk(g_ring.mu);
+    const size_t len = align_up(bytes);
+    auto retire = [&](size_t lo, size_t hi) -> int {  // wait for uses overlapping [lo, hi)
+        for (size_t i = 0; i < g_ring.busy.size();) {
+            const StageRing::Use u = g_ring.busy[i];
+            if (u.off < hi && lo < u.off + u.len) {
+                RPYW_HIP(hipEventSynchronize(u.ev));
+                g_ring.idle.push_back(u.ev);
+                g_ring.busy.erase(g_ring.busy.begin() + (long)i);
+            } else {
+                ++i;
+            }
+        }
+        return RPYW_OK;
+    };
+    if (len > g_ring.cap) {
+        if (int r = retire(0, g_ring.cap)) return r;
+        if (g_ring.host) RPYW_HIP(hipHostFree(g_ring.host));
+        g_ring.host = nullptr;
+        g_ring.cap = g_ring.head = 0;
+        const size_t cap = std::max(len * 4, (size_t)1 << 20);
+        RPYW_HIP(hipHostMalloc((void**)&g_ring.host, cap, hipHostMallocDefault));
+        g_ring.cap = cap;
+    }
+    if (g_ring.head + len > g_ring.cap) g_ring.head = 0;
+    const size_t off = g_ring.head;
+    if (int r = retire(off, off + len)) return r;
+    hipEvent_t ev;
+    if (!g_ring.idle.empty()) {
+        ev = g_ring.idle.back();
+        g_ring.idle.pop_back();
+    } else {
+        RPYW_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    }
+    std::memcpy(g_ring.host + off, src, bytes);
+    RPYW_HIP(hipMemcpyAsync(dst, g_ring.host + off, bytes, hipMemcpyHostToDevice, st));
+    RPYW_HIP(hipEventRecord(ev, st));
+    g_ring.busy.push_back({off, len, ev});
+    g_ring.head = off + len;
+    return RPYW_OK;
+}
+
 int PinnedSlots::reserve(size_t bytes) {
+    if (tail) RPYW_HIP(hipEventSynchronize(tail));
     if (cap < bytes) {
         if (p) RPYW_HIP(hipHostFree(p));
         p = nullptr;
@@ -442,6 +511,12 @@ int PinnedSlots::reserve(size_t bytes) {
     }
     for (auto& e : ev)
         if (!e) RPYW_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return RPYW_OK;
+}
+
+int PinnedSlots::release(hipStream_t st) {
+    if (!tail) RPYW_HIP(hipEventCreateWithFlags(&tail, hipEventDisableTiming));
+    RPYW_HIP(hipEventRecord(tail, st));
     return RPYW_OK;
 }
 

@@ -160,9 +160,13 @@ int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, dou
     if (!V || !x || !y || !w || !partial || !d_ab || !d_c1 || !d_c2 || !d_b0 || !ticket || !notspd)
         return RPYW_ENOMEM;
     std::lock_guard<std::mutex> lk(g_ab.mu);
-    int rc = g_ab.reserve((size_t)2 * (max_iter + 2) * sizeof(double));
+    int rc = g_ab.reserve((size_t)(2 * (max_iter + 2) + 2) * sizeof(double));
     if (rc) return rc;
     double* h_ab = g_ab.p;
+    SlotRelease slots_done{g_ab, st};
+    // beta0 and the not-positive-definite flags come back with step 0
+    double* h_b0 = h_ab + 2 * (max_iter + 2);
+    int* h_bad = (int*)(h_b0 + 1);
 
     RPYW_HIP(hipMemsetAsync(notspd, 0, sizeof(int), st));
     RPYW_HIP(hipMemsetAsync(ticket, 0, sizeof(unsigned), st));
@@ -184,18 +188,11 @@ int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, dou
 
     // beta0 = |W|
     if ((rc = dots(W, 0, d_b0, 0, nullptr))) return rc;
+    h_bad[0] = h_bad[1] = 0;
+    RPYW_HIP(hipMemcpyAsync(h_b0, d_b0, sizeof(double), hipMemcpyDeviceToHost, st));
+    RPYW_HIP(hipMemcpyAsync(h_bad, notspd, sizeof(int), hipMemcpyDeviceToHost, st));
+    if (pre && pre->flag) RPYW_HIP(hipMemcpyAsync(h_bad + 1, pre->flag, sizeof(int), hipMemcpyDeviceToHost, st));
     double beta0 = 0.0;
-    int bad = 0;
-    RPYW_HIP(hipMemcpyAsync(&beta0, d_b0, sizeof(double), hipMemcpyDeviceToHost, st));
-    int bad_pre = 0;
-    RPYW_HIP(hipMemcpyAsync(&bad, notspd, sizeof(int), hipMemcpyDeviceToHost, st));
-    if (pre && pre->flag) RPYW_HIP(hipMemcpyAsync(&bad_pre, pre->flag, sizeof(int), hipMemcpyDeviceToHost, st));
-    RPYW_HIP(hipStreamSynchronize(st));
-    if (bad || bad_pre) return RPYW_ENOTSPD;
-    if (beta0 == 0.0) {
-        RPYW_HIP(hipMemsetAsync(out, 0, n3 * sizeof(double), st));
-        return RPYW_OK;
-    }
 
     // Enqueue iteration k on the GPU: it needs beta_{k-1} only on the device,
     // so iteration k + 1 is queued before the host has decided whether
@@ -231,13 +228,23 @@ int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, dou
 
     std::vector<double> alpha, beta, c, cprev;
     bool converged = false;
-    double rel = INFINITY;
+    double rel = INFINITY, rel1 = INFINITY, rel2 = INFINITY;  // of steps k - 1, k - 2
     int k = 0;
     if ((rc = fill(1 + depth))) return rc;
     for (; k < max_iter; ++k) {
         RPYW_HIP(hipEventSynchronize(g_ab.ev[k % PinnedSlots::kSlots]));
+        if (k == 0) {  // the first wait also brings beta0 and the flags
+            beta0 = *h_b0;
+            const bool bad = h_bad[0] || h_bad[1];
+            if (bad || beta0 == 0.0) {
+                RPYW_HIP(hipStreamSynchronize(st));  // drain the queued steps
+                if (bad) return RPYW_ENOTSPD;
+                RPYW_HIP(hipMemsetAsync(out, 0, n3 * sizeof(double), st));
+                return RPYW_OK;
+            }
+        }
         const double ak = h_ab[2 * k], bk = h_ab[2 * k + 1];
-        if (depth && (rc = fill(k + 1 + depth))) return rc;
+        if (depth && (rc = fill(speculate_to(k, depth, rel1, rel2, tol) + 1))) return rc;
         alpha.push_back(ak);
         c.assign(k + 1, 0.0);
         if (tridiag_sqrt_coeffs(alpha.data(), beta.data(), k + 1, beta0, c.data()) != RPYW_OK) return RPYW_EHIP;
@@ -261,15 +268,16 @@ int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, dou
         }
         cprev = c;
         beta.push_back(bk);
-        if (!depth && (rc = fill(k + 2))) return rc;
+        rel2 = rel1;
+        rel1 = rel;
+        if ((rc = fill(k + 2))) return rc;  // step k + 1, unless queued already
     }
     const int used = (int)c.size();
     *iters = converged ? k + 1 : max_iter;
     *err = std::isfinite(rel) ? rel : 0.0;
-    RPYW_HIP(hipMemcpyAsync(d_c1, c.data(), used * sizeof(double), hipMemcpyHostToDevice, st));
+    if ((rc = stage_upload(c.data(), used * sizeof(double), d_c1, st))) return rc;
     if ((rc = vec_comb(V, n3, used, d_c1, y, n3, st))) return rc;  // y = V c
     if ((rc = pc.apply(0, y, out, n3, st))) return rc;  // out = L y
-    RPYW_HIP(hipStreamSynchronize(st));                // c leaves scope
     return converged ? RPYW_OK : RPYW_NOT_CONVERGED;
 }
 

@@ -629,36 +629,6 @@ int products(const double* pos, const double* F, double* U, int64_t N, int k, do
 
 // ------------------------------------------------------------ batched
 
-namespace {
-
-// Pinned staging for small host->device uploads that must stay asynchronous.
-struct Staging {
-    std::mutex mu;
-    void* host = nullptr;
-    size_t cap = 0;
-    hipEvent_t done = nullptr;
-};
-Staging g_stage;
-
-int upload_async(const void* src, size_t bytes, void* dst, hipStream_t st) {
-    std::lock_guard<std::mutex> lk(g_stage.mu);
-    if (g_stage.done) RPYW_HIP(hipEventSynchronize(g_stage.done));
-    if (bytes > g_stage.cap) {
-        if (g_stage.host) RPYW_HIP(hipHostFree(g_stage.host));
-        g_stage.host = nullptr;
-        g_stage.cap = 0;
-        RPYW_HIP(hipHostMalloc(&g_stage.host, bytes, hipHostMallocDefault));
-        g_stage.cap = bytes;
-    }
-    if (!g_stage.done) RPYW_HIP(hipEventCreateWithFlags(&g_stage.done, hipEventDisableTiming));
-    std::memcpy(g_stage.host, src, bytes);
-    RPYW_HIP(hipMemcpyAsync(dst, g_stage.host, bytes, hipMemcpyHostToDevice, st));
-    RPYW_HIP(hipEventRecord(g_stage.done, st));
-    return RPYW_OK;
-}
-
-}  // namespace
-
 size_t batched_ws_bytes(int64_t Ntot, int S, int k, int prec) {
     const int kb = kernel_k(std::max(k, 1), prec);
     size_t b = align_up((size_t)Ntot * rec_width(prec, kb) * real_size(prec));
@@ -707,7 +677,7 @@ int batched_products(const double* pos, const int64_t* sys_offsets, int S, const
         ar.used = mark;
         return RPYW_ENOMEM;
     }
-    int rc = upload_async(items.data(), items.size() * sizeof(int4), ditems, st);
+    int rc = stage_upload(items.data(), items.size() * sizeof(int4), ditems, st);
     if (rc != RPYW_OK) return rc;
     int dev = 0, ncu = 256;
     RPYW_HIP(hipGetDevice(&dev));

@@ -289,9 +289,13 @@ int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets,
         return RPYW_ENOMEM;
     std::lock_guard<std::mutex> lk(g_h.mu);
     const int slot = 2 * (max_iter + 2);  // c1[0..k], c2[0..k], h_{k+1,k}
-    int rc = g_h.reserve((size_t)PinnedSlots::kSlots * slot * sizeof(double));
+    int rc = g_h.reserve(((size_t)PinnedSlots::kSlots * slot + 2) * sizeof(double));
     if (rc) return rc;
+    SlotRelease slots_done{g_h, st};
     double* h_slot = g_h.p;
+    // |b| and the not-positive-definite flags come back with step 0
+    double* h_b = h_slot + (size_t)PinnedSlots::kSlots * slot;
+    int* h_bad = (int*)(h_b + 1);
 
     RPYW_HIP(hipMemsetAsync(notspd, 0, sizeof(int), st));
     RPYW_HIP(hipMemsetAsync(ticket, 0, sizeof(unsigned), st));
@@ -317,20 +321,11 @@ int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets,
 
     // beta = |b|
     if ((rc = dots(bv, 0, d_hn, 0, nullptr))) return rc;
+    h_bad[0] = h_bad[1] = 0;
+    RPYW_HIP(hipMemcpyAsync(h_b, d_hn, sizeof(double), hipMemcpyDeviceToHost, st));
+    RPYW_HIP(hipMemcpyAsync(h_bad, notspd, sizeof(int), hipMemcpyDeviceToHost, st));
+    if (pre && pre->flag) RPYW_HIP(hipMemcpyAsync(h_bad + 1, pre->flag, sizeof(int), hipMemcpyDeviceToHost, st));
     double beta = 0.0;
-    int bad = 0;
-    RPYW_HIP(hipMemcpyAsync(&beta, d_hn, sizeof(double), hipMemcpyDeviceToHost, st));
-    int bad_pre = 0;
-    RPYW_HIP(hipMemcpyAsync(&bad, notspd, sizeof(int), hipMemcpyDeviceToHost, st));
-    if (pre && pre->flag) RPYW_HIP(hipMemcpyAsync(&bad_pre, pre->flag, sizeof(int), hipMemcpyDeviceToHost, st));
-    RPYW_HIP(hipStreamSynchronize(st));
-    if (bad || bad_pre) return RPYW_ENOTSPD;
-    if (!std::isfinite(beta)) return RPYW_EINVAL;
-    if (beta == 0.0) {
-        RPYW_HIP(hipMemsetAsync(lam_out, 0, n3 * sizeof(double), st));
-        RPYW_HIP(hipMemsetAsync(U_out, 0, n6 * sizeof(double), st));
-        return RPYW_OK;
-    }
 
     // Arnoldi step k: v_k = (k ? w : b) / d_hn[k], z = P^-1 v_k, w = A z,
     // two Gram-Schmidt passes, d_hn[k + 1] = |w|; column k of H to the host.
@@ -366,18 +361,31 @@ int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets,
 
     // Host: upper-triangular R (columns), Givens rotations, g = beta e1.
     std::vector<std::vector<double>> R;
-    std::vector<double> cs, sn, g(1, beta);
+    std::vector<double> cs, sn, g;
     bool converged = false;
-    double res = 1.0;
+    double res = 1.0, res1 = INFINITY, res2 = INFINITY;  // residual estimates of steps k - 1, k - 2
     int k = 0;
     if ((rc = fill(1 + depth))) return rc;
     for (; k < max_iter; ++k) {
         RPYW_HIP(hipEventSynchronize(g_h.ev[k % PinnedSlots::kSlots]));
+        if (k == 0) {  // the first wait also brings |b| and the flags
+            beta = *h_b;
+            const bool bad = h_bad[0] || h_bad[1];
+            if (bad || !std::isfinite(beta) || beta == 0.0) {
+                RPYW_HIP(hipStreamSynchronize(st));  // drain the queued steps
+                if (bad) return RPYW_ENOTSPD;
+                if (!std::isfinite(beta)) return RPYW_EINVAL;
+                RPYW_HIP(hipMemsetAsync(lam_out, 0, n3 * sizeof(double), st));
+                RPYW_HIP(hipMemsetAsync(U_out, 0, n6 * sizeof(double), st));
+                return RPYW_OK;
+            }
+            g.assign(1, beta);
+        }
         const double* hs = h_slot + (size_t)(k % PinnedSlots::kSlots) * slot;
         std::vector<double> h(k + 2);
         for (int j = 0; j <= k; ++j) h[j] = hs[j] + hs[k + 1 + j];
         h[k + 1] = hs[2 * (k + 1)];
-        if (depth && (rc = fill(k + 1 + depth))) return rc;
+        if (depth && (rc = fill(speculate_to(k, depth, res1, res2, tol) + 1))) return rc;
         for (int j = 0; j < k; ++j) {
             const double t0 = cs[j] * h[j] + sn[j] * h[j + 1];
             h[j + 1] = -sn[j] * h[j] + cs[j] * h[j + 1];
@@ -399,7 +407,9 @@ int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets,
             converged = true;
             break;
         }
-        if (!depth && (rc = fill(k + 2))) return rc;
+        res2 = res1;
+        res1 = res;
+        if ((rc = fill(k + 2))) return rc;  // step k + 1, unless queued already
     }
     const int m = (int)R.size();
     *iters = m;
@@ -411,10 +421,9 @@ int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets,
         for (int j = i + 1; j < m; ++j) s -= R[j][i] * yv[j];
         yv[i] = R[i][i] != 0.0 ? s / R[i][i] : 0.0;
     }
-    RPYW_HIP(hipMemcpyAsync(d_y, yv.data(), m * sizeof(double), hipMemcpyHostToDevice, st));
+    if ((rc = stage_upload(yv.data(), m * sizeof(double), d_y, st))) return rc;
     if ((rc = vec_comb(V, n, m, d_y, w, n, st))) return rc;
     if ((rc = precond(w, nullptr, nullptr, lam_out, U_out))) return rc;
-    RPYW_HIP(hipStreamSynchronize(st));  // yv leaves scope
     return converged ? RPYW_OK : RPYW_NOT_CONVERGED;
 }
 

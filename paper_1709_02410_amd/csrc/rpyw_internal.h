@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstddef>
 #include <cstdint>
 #include <mutex>
@@ -136,6 +138,9 @@ int body_factors_build(const double* pos, int64_t N, double a, double eta, const
 //   update_dots: update (when vprev or nsub is given, result to wout) then
 //           dots of the result, in one pass;
 //   comb:   out = sum_{j < nv} c[j] V_j.
+// Asynchronous upload of a small host array (which the caller may free at
+// once) through a library-owned pinned ring.
+int stage_upload(const void* src, size_t bytes, void* dst, hipStream_t st);
 int64_t dot_chunks(int64_t n);
 int vec_update(const double* win, double* wout, int64_t n, const double* vprev, const double* bscale,
                const double* V, int64_t ld, const double* csub, int nsub, hipStream_t st);
@@ -153,6 +158,17 @@ int vec_comb(const double* V, int64_t ld, int nv, const double* c, double* out, 
 // than they hide, and step k + 1 is queued after the host has examined k.
 constexpr double kSpeculatePairs = 4.0e8;
 constexpr int kSpeculateDepth = 2;
+// Highest step index to have queued while the host examines step k, with at
+// most `depth` steps beyond k, and none beyond the step at which a geometric
+// extrapolation of the last two convergence measures m1 (step k - 1) and m2
+// (step k - 2) reaches tol (so that few queued steps are wasted).
+inline int speculate_to(int k, int depth, double m1, double m2, double tol) {
+    if (depth <= 0) return k;
+    int need = 1 << 20;  // steps after k - 1 until convergence
+    if (m1 > tol && m2 > m1 && m1 > 0.0)
+        need = std::max(1, (int)std::ceil(std::log(tol / m1) / std::log(m1 / m2)));
+    return std::max(k, std::min(k + depth, k - 1 + need));
+}
 
 // Library-owned pinned host buffer plus two events for per-iteration
 // device->host copies of a solver; the caller holds mu while using it.
@@ -162,7 +178,18 @@ struct PinnedSlots {
     double* p = nullptr;
     size_t cap = 0;
     hipEvent_t ev[kSlots] = {};
+    hipEvent_t tail = nullptr;  // after the last copy into p of the previous call
+    // Waits for the previous call's copies into p, then makes p hold bytes.
     int reserve(size_t bytes);
+    // Marks the end of this call's copies (the solvers return without
+    // waiting for the speculative steps still queued).
+    int release(hipStream_t st);
+};
+// Calls release on every return path of a solver holding the slots.
+struct SlotRelease {
+    PinnedSlots& s;
+    hipStream_t st;
+    ~SlotRelease() { (void)s.release(st); }
 };
 
 // Lanczos (lanczos.hip)

@@ -185,9 +185,7 @@ int upload_bodies(const int64_t* body_offsets, int nb, Arena& ar, hipStream_t st
     bd.nb = nb;
     bd.bofs = (int*)ar.take(hb.size() * sizeof(int));
     if (!bd.bofs) return RPYW_ENOMEM;
-    RPYW_HIP(hipMemcpyAsync(bd.bofs, hb.data(), hb.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    RPYW_HIP(hipStreamSynchronize(st));  // hb goes out of scope
-    return RPYW_OK;
+    return stage_upload(hb.data(), hb.size() * sizeof(int), bd.bofs, st);
 }
 
 int lincomb(const double* x, double ax, const double* y, double ay, int64_t n, double* out, hipStream_t st) {
@@ -324,7 +322,6 @@ int ts_predict(const double* q, const double* theta, const double* ref, const in
     merge(status, rc);
     if ((rc = body_move(q, theta, U0, nullptr, dt, nb, q_t, theta_t, st))) return rc;
     if ((rc = body_blobs(q_t, theta_t, ref, bd.bofs, nb, pos_t, st))) return rc;
-    RPYW_HIP(hipStreamSynchronize(st));
     return status;
 }
 
@@ -357,7 +354,6 @@ int ts_correct(const double* q, const double* theta, const double* q_t, const do
     if (rc < 0) return rc;
     const int status = rc;
     if ((rc = body_move(q, theta, U0, Ut, 0.5 * dt, nb, q_next, theta_next, st))) return rc;
-    RPYW_HIP(hipStreamSynchronize(st));
     return status;
 }
 
@@ -436,7 +432,6 @@ int emt_step(const double* q, const double* theta, const double* ref, const int6
     if (rc < 0) return rc;
     merge(status, rc);
     if ((rc = body_move(q, theta, U0, nullptr, dt, nb, q_next, theta_next, st))) return rc;
-    RPYW_HIP(hipStreamSynchronize(st));
     return status;
 }
 
@@ -497,7 +492,6 @@ int emrfd_step(const double* q, const double* theta, const double* ref, const in
     // U = U^n + (U+ - U-) / delta, then Q^{n+1} = Q^n + dt U
     if ((rc = lincomb(Upm, 1.0 / delta, Upm + n6, -1.0 / delta, n6, Upm, st))) return rc;
     if ((rc = body_move(q, theta, U0, Upm, dt, nb, q_next, theta_next, st))) return rc;
-    RPYW_HIP(hipStreamSynchronize(st));
     return status;
 }
 
