@@ -167,19 +167,6 @@ __global__ void diag_apply_kernel(const double* __restrict__ ldiag, int64_t n3, 
     out[e] = mode == 0 ? ldiag[e] * vi : vi / ldiag[e];
 }
 
-// w_out = w_in - bscale[0] * vprev - sum_{j < nsub} csub[j] V_j (each term
-// only when given; w_in may be w_out).
-__global__ void update_kernel(const double* win, double* wout, int64_t n3,
-                              const double* __restrict__ vprev, const double* __restrict__ bscale,
-                              const double* __restrict__ V, int64_t ld, const double* __restrict__ csub, int nsub) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n3) return;
-    double x = win[e];
-    if (vprev) x -= bscale[0] * vprev[e];
-    for (int j = 0; j < nsub; ++j) x -= csub[j] * V[j * ld + e];
-    wout[e] = x;
-}
-
 // Blocking of the dot products: a block of 256 threads takes 256 m
 // consecutive entries (m per thread, 1 <= m <= kDotPerThread), with m as
 // small as keeps the grid at kDotBlocks blocks or fewer.
@@ -345,14 +332,6 @@ unsigned grid_of(int64_t n) { return (unsigned)((n + 255) / 256); }
 int64_t dot_chunks(int64_t n) {
     const int64_t span = 256 * (int64_t)dot_per_thread(n);
     return (n + span - 1) / span;
-}
-
-int vec_update(const double* win, double* wout, int64_t n, const double* vprev, const double* bscale,
-               const double* V, int64_t ld, const double* csub, int nsub, hipStream_t st) {
-    hipLaunchKernelGGL(update_kernel, dim3(grid_of(n)), dim3(256), 0, st, win, wout, n, vprev, bscale, V, ld, csub,
-                       nsub);
-    RPYW_HIP(hipGetLastError());
-    return RPYW_OK;
 }
 
 int vec_update_dots(const double* win, double* wout, int64_t n, const double* vprev, const double* bscale,

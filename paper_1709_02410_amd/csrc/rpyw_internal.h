@@ -130,20 +130,18 @@ size_t body_factors_bytes(int64_t N, int n_bodies);
 int body_factors_build(const double* pos, int64_t N, double a, double eta, const int64_t* body_offsets, int n_bodies,
                        Arena& ar, hipStream_t st, BodyFactors& pc, int* notspd);
 // Vector kernels (FP64, length n, basis vectors V_j at V + j ld):
-//   update: wout = win - bscale[0] vprev - sum_{j < nsub} csub[j] V_j;
 //   dots:   out[j] = V_j . w (j < nv), or out[0] = |w| when nv == 0, with a
 //           fixed-order finish; out[copy_idx] is also copied to copy_to;
 //           partial holds max(nv, 1) dot_chunks(n) doubles, ticket one
 //           zeroed unsigned that the kernel re-arms;
-//   update_dots: update (when vprev or nsub is given, result to wout) then
-//           dots of the result, in one pass;
+//   update_dots: the update w = win - bscale[0] vprev - sum_{j < nsub}
+//           csub[j] V_j (terms when given; written to wout when there is
+//           one) then the dots of w, in one pass;
 //   comb:   out = sum_{j < nv} c[j] V_j.
 // Asynchronous upload of a small host array (which the caller may free at
 // once) through a library-owned pinned ring.
 int stage_upload(const void* src, size_t bytes, void* dst, hipStream_t st);
 int64_t dot_chunks(int64_t n);
-int vec_update(const double* win, double* wout, int64_t n, const double* vprev, const double* bscale,
-               const double* V, int64_t ld, const double* csub, int nsub, hipStream_t st);
 int vec_dots(const double* V, int64_t ld, int nv, const double* w, int64_t n, double* partial, unsigned* ticket,
              double* out, int copy_idx, double* copy_to, hipStream_t st);
 int vec_update_dots(const double* win, double* wout, int64_t n, const double* vprev, const double* bscale,
