@@ -137,3 +137,44 @@ def test_largest_bodies_42_blobs(rp, orc):
     lam_ref, U_ref = orc.rigid_solve(pos, q, offs, None, FT)
     lam, U, it, res, ok = rp.rigid_solve(_t(pos), _t(q), offs, None, _t(FT), tol=1e-11)
     assert ok and _rel(U.cpu().numpy(), U_ref) <= 1e-8
+
+
+def test_back_to_back_calls_and_two_streams(rp, orc):
+    """The solvers return with their last kernels (and up to two speculative
+    steps) still queued, and their pinned scalar slots are shared between
+    calls: several Lanczos roots and rigid solves issued back to back, on one
+    stream and on two streams, without synchronising in between, equal the
+    same calls made one at a time."""
+    pos, offs = wl.boomerang_suspension(12, 25.0, 1.5, 4.0, seed=8)
+    Ws = [wl.gaussian(pos.shape, 40 + i) for i in range(4)]
+    q = pos[offs[:-1]].copy()
+    FT = wl.gaussian((len(offs) - 1, 6), 50)
+    p = _t(pos)
+    ref = []
+    for W in Ws:
+        out, _, _, ok = rp.lanczos_sqrt(p, _t(W), body_offsets=offs, tol=1e-10)
+        torch.cuda.synchronize()
+        ref.append(out.cpu().numpy())
+    lam_r, U_r, _, _, _ = rp.rigid_solve(p, _t(q), offs, _t(Ws[0]), _t(FT), tol=1e-10)
+    torch.cuda.synchronize()
+    U_r = U_r.cpu().numpy()
+    # back to back on the current stream
+    outs = [rp.lanczos_sqrt(p, _t(W), body_offsets=offs, tol=1e-10)[0] for W in Ws]
+    U1 = rp.rigid_solve(p, _t(q), offs, _t(Ws[0]), _t(FT), tol=1e-10)[1]
+    torch.cuda.synchronize()
+    for o, r in zip(outs, ref):
+        assert np.array_equal(o.cpu().numpy(), r)
+    assert np.array_equal(U1.cpu().numpy(), U_r)
+    # alternating between two streams (default priority)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = []
+    for i, W in enumerate(Ws):
+        with torch.cuda.stream(s1 if i % 2 == 0 else s2):
+            Wt = _t(W)
+            outs.append(rp.lanczos_sqrt(p, Wt, body_offsets=offs, tol=1e-10)[0])
+    with torch.cuda.stream(s2):
+        U2 = rp.rigid_solve(p, _t(q), offs, _t(Ws[0]), _t(FT), tol=1e-10)[1]
+    torch.cuda.synchronize()
+    for o, r in zip(outs, ref):
+        assert np.array_equal(o.cpu().numpy(), r)
+    assert np.array_equal(U2.cpu().numpy(), U_r)
