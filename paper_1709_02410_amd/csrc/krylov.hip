@@ -88,16 +88,21 @@ __global__ __launch_bounds__(kBodyThreads) void precond_build_kernel(const doubl
         L[q] = j <= i ? A(i, j) : 0.0;
     }
     // Inverse factor L^-1 (lower triangular), one column per thread: forward
-    // substitution of L x = e_col, the column written to global memory.
+    // substitution of L x = e_col.  Entry (i, col), i > col, is kept in the
+    // free upper triangle of A at (col, i), a row only this thread touches,
+    // so the substitution reads LDS rather than its own global writes.
     for (int col = threadIdx.x; col < n; col += blockDim.x) {
-        for (int i = 0; i < col; ++i) Li[i * n + col] = 0.0;
-        double xc = 1.0 / A(col, col);
-        Li[col * n + col] = xc;
+        const double xc = 1.0 / A(col, col);
         for (int i = col + 1; i < n; ++i) {
-            double s = 0.0;
-            for (int k = col; k < i; ++k) s += A(i, k) * Li[k * n + col];
-            Li[i * n + col] = -s / A(i, i);
+            double s = A(i, col) * xc;
+            for (int k = col + 1; k < i; ++k) s += A(i, k) * A(col, k);
+            A(col, i) = -s / A(i, i);
         }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < n * n; q += blockDim.x) {
+        const int i = q / n, j = q % n;
+        Li[q] = i > j ? A(j, i) : i == j ? 1.0 / A(i, i) : 0.0;
     }
     if (threadIdx.x == 0 && bad) atomicOr(notspd, 1);
 #undef A
