@@ -64,23 +64,28 @@ __global__ __launch_bounds__(kBodyThreads) void precond_build_kernel(const doubl
         }
     }
     __syncthreads();
+    // One barrier per column: step k updates the trailing lower triangle
+    // with the unscaled column, A(i, j) -= A(i, k) A(j, k) / A(k, k), then
+    // scales column k by 1 / sqrt(A(k, k)); the scaling touches only column k,
+    // which no later step reads or writes, so it needs no barrier of its own.
     for (int k = 0; k < n; ++k) {
-        if (threadIdx.x == 0) {
-            const double d = A(k, k);
-            if (!(d > 0.0)) bad = 1;
-            A(k, k) = d > 0.0 ? sqrt(d) : 1.0;
-        }
-        __syncthreads();
-        const double dk = A(k, k);
-        for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) A(i, k) /= dk;
-        __syncthreads();
+        const double d = A(k, k);
+        const bool ok = d > 0.0;
+        const double id = ok ? 1.0 / d : 0.0;
         const int m = n - k - 1;
         for (int q = threadIdx.x; q < m * m; q += blockDim.x) {
             const int i = k + 1 + q / m, j = k + 1 + q % m;
-            if (j <= i) A(i, j) -= A(i, k) * A(j, k);
+            if (j <= i) A(i, j) -= A(i, k) * A(j, k) * id;
         }
         __syncthreads();
+        const double sd = ok ? sqrt(d) : 1.0;
+        for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) A(i, k) /= sd;
+        if (threadIdx.x == 0) {
+            if (!ok) bad = 1;
+            A(k, k) = sd;
+        }
     }
+    __syncthreads();
     double* L = Lout + 2 * lofs[p];
     double* Li = L + (int64_t)n * n;
     for (int q = threadIdx.x; q < n * n; q += blockDim.x) {
@@ -94,9 +99,16 @@ __global__ __launch_bounds__(kBodyThreads) void precond_build_kernel(const doubl
     for (int col = threadIdx.x; col < n; col += blockDim.x) {
         const double xc = 1.0 / A(col, col);
         for (int i = col + 1; i < n; ++i) {
-            double s = A(i, col) * xc;
-            for (int k = col + 1; k < i; ++k) s += A(i, k) * A(col, k);
-            A(col, i) = -s / A(i, i);
+            double s0 = A(i, col) * xc, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            int k = col + 1;
+            for (; k + 3 < i; k += 4) {
+                s0 += A(i, k) * A(col, k);
+                s1 += A(i, k + 1) * A(col, k + 1);
+                s2 += A(i, k + 2) * A(col, k + 2);
+                s3 += A(i, k + 3) * A(col, k + 3);
+            }
+            for (; k < i; ++k) s0 += A(i, k) * A(col, k);
+            A(col, i) = -((s0 + s1) + (s2 + s3)) / A(i, i);
         }
     }
     __syncthreads();
@@ -485,22 +497,27 @@ int stage_upload(const void* src, size_t bytes, void* dst, hipStream_t st) {
 }
 
 int PinnedSlots::reserve(size_t bytes) {
-    if (tail) RPYW_HIP(hipEventSynchronize(tail));
-    if (cap < bytes) {
-        if (p) RPYW_HIP(hipHostFree(p));
-        p = nullptr;
-        cap = 0;
-        RPYW_HIP(hipHostMalloc((void**)&p, bytes, hipHostMallocDefault));
-        cap = bytes;
+    cur ^= 1;
+    Bank& k = bank[cur];
+    if (k.tail) RPYW_HIP(hipEventSynchronize(k.tail));
+    if (k.cap < bytes) {
+        if (k.p) RPYW_HIP(hipHostFree(k.p));
+        k.p = nullptr;
+        k.cap = 0;
+        RPYW_HIP(hipHostMalloc((void**)&k.p, bytes, hipHostMallocDefault));
+        k.cap = bytes;
     }
-    for (auto& e : ev)
+    for (auto& e : k.ev)
         if (!e) RPYW_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    p = k.p;
+    ev = k.ev;
     return RPYW_OK;
 }
 
 int PinnedSlots::release(hipStream_t st) {
-    if (!tail) RPYW_HIP(hipEventCreateWithFlags(&tail, hipEventDisableTiming));
-    RPYW_HIP(hipEventRecord(tail, st));
+    Bank& k = bank[cur];
+    if (!k.tail) RPYW_HIP(hipEventCreateWithFlags(&k.tail, hipEventDisableTiming));
+    RPYW_HIP(hipEventRecord(k.tail, st));
     return RPYW_OK;
 }
 

@@ -170,14 +170,23 @@ inline int speculate_to(int k, int depth, double m1, double m2, double tol) {
 
 // Library-owned pinned host buffer plus two events for per-iteration
 // device->host copies of a solver; the caller holds mu while using it.
+// Two banks used by alternate calls, so that a call does not wait for the
+// copies (possibly of speculative steps still queued) of the one before.
 struct PinnedSlots {
     static constexpr int kSlots = 4;  // steps in flight at most (kSpeculateDepth + 1)
+    struct Bank {
+        double* p = nullptr;
+        size_t cap = 0;
+        hipEvent_t ev[kSlots] = {};
+        hipEvent_t tail = nullptr;  // after the last copy into p of the call that used it
+    };
     std::mutex mu;
-    double* p = nullptr;
-    size_t cap = 0;
-    hipEvent_t ev[kSlots] = {};
-    hipEvent_t tail = nullptr;  // after the last copy into p of the previous call
-    // Waits for the previous call's copies into p, then makes p hold bytes.
+    Bank bank[2];
+    int cur = 0;
+    double* p = nullptr;     // the current call's bank
+    hipEvent_t* ev = nullptr;
+    // Switches bank, waits for the copies of the call that last used it, then
+    // makes p hold bytes.
     int reserve(size_t bytes);
     // Marks the end of this call's copies (the solvers return without
     // waiting for the speculative steps still queued).
