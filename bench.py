@@ -20,6 +20,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -50,10 +51,15 @@ def algorithmic_flop(N: int, k: int, sym: int) -> float:
 
 
 def kernel_hash() -> str:
+    """Hash of the pair-kernel sources with comments and blank space removed
+    (so that edits to comments alone keep the stored counter figures)."""
     h = hashlib.sha256()
     for s in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1709_02410_amd", "csrc", s), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1709_02410_amd", "csrc", s)) as fh:
+            text = fh.read()
+        text = re.sub(r"//[^\n]*", "", text)
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        h.update(re.sub(r"\s+", " ", text).strip().encode())
     return h.hexdigest()[:16]
 
 

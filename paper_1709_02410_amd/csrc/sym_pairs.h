@@ -27,9 +27,11 @@
 // In the diagonal item (d = 0) blocks above the wave's own are done
 // symmetrically, the wave's own block over all ordered pairs (self
 // included, target side only), and blocks below it are left to the waves
-// that own them.  Target sums are written per (row, chunk) and source sums
-// per (group, d); an epilogue adds both in a fixed order, so results are
-// bitwise reproducible.
+// that own them.  When there are few items, every item's passes are split
+// into nseg segments of 64 / nseg steps, each its own workgroup.  Target
+// sums are written per (row, chunk, segment) and source sums per (group, d,
+// segment); an epilogue adds both in a fixed order, so results are bitwise
+// reproducible.
 //
 // A Body supplies the per-pair arithmetic: KREC right-hand sides in the
 // record, NQ accumulated quantities, the unroll factor of the 64-step loop,
