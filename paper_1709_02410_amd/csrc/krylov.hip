@@ -469,6 +469,11 @@ int stage_upload(const void* src, size_t bytes, void* dst, hipStream_t st) {
         }
         return RPYW_OK;
     };
+    // completed copies (oldest first) free their stretch without waiting
+    while (!g_ring.busy.empty() && hipEventQuery(g_ring.busy.front().ev) == hipSuccess) {
+        g_ring.idle.push_back(g_ring.busy.front().ev);
+        g_ring.busy.erase(g_ring.busy.begin());
+    }
     if (len > g_ring.cap) {
         if (int r = retire(0, g_ring.cap)) return r;
         if (g_ring.host) RPYW_HIP(hipHostFree(g_ring.host));
