@@ -241,10 +241,14 @@ __device__ __forceinline__ void finish_dots(const double* __restrict__ partial, 
 //   w = win - bscale[0] vprev - sum_{j < nsub} csub[j] V_j  (each term only
 //   when given; written to wout unless there is nothing to write),
 //   out[j] = V_j . w (j < nv), or out[0] = |w| when nv == 0.
-// A block takes 256 m consecutive entries.  Dot products go kDotBatch
-// vectors at a time: every thread puts its entries' products into an LDS
-// tile, then 16 threads per vector add 16 tile columns each and a 16-lane
-// butterfly finishes the block partial, partial[j][block].  The last block
+// A block takes 256 m consecutive entries (blockIdx.x) and one group of
+// kDotBatch vectors (blockIdx.y; several groups run as separate blocks,
+// each repeating the update of its entries, and only group 0 writes wout,
+// which therefore must not be win when there are several groups and an
+// update).  Dot products go kDotBatch vectors at a time: every thread puts
+// its entries' products into an LDS tile, then 16 threads per vector add 16
+// tile columns each and a 16-lane butterfly finishes the block partial,
+// partial[j][blockIdx.x].  The last block
 // to finish (one atomic ticket, no waiting) adds each j's partials
 // (finish_dots) into out[j], copies out[copy_idx] to copy_to and re-arms the
 // ticket.  Every sum has a fixed order.
@@ -280,12 +284,13 @@ __global__ __launch_bounds__(256) void update_dots_kernel(const double* win, dou
             v -= csub[j + 3] * a3;
         }
         for (; j < nsub; ++j) v -= csub[j] * V[j * ld + e];
-        if (upd) wout[e] = v;
+        if (wout && (upd || wout != win) && blockIdx.y == 0) wout[e] = v;
         x[r] = v;
     }
     const int nd = nv > 0 ? nv : 1;
     const int jr = t >> 4, c0 = t & 15;  // reduction: vector jr of the batch, columns c0 + 16 i
-    for (int j0 = 0; j0 < nd; j0 += kDotBatch) {
+    const int jend = (int)(blockIdx.y + 1) * kDotBatch < nd ? (int)(blockIdx.y + 1) * kDotBatch : nd;
+    for (int j0 = (int)blockIdx.y * kDotBatch; j0 < jend; j0 += kDotBatch) {
         const int jn = nd - j0 < kDotBatch ? nd - j0 : kDotBatch;
 #pragma unroll
         for (int u = 0; u < kDotBatch; ++u) {
@@ -314,7 +319,7 @@ __global__ __launch_bounds__(256) void update_dots_kernel(const double* win, dou
         __syncthreads();
     }
     __threadfence();
-    if (t == 0) last = atomicAdd(ticket, 1u) == (unsigned)nblk - 1;
+    if (t == 0) last = atomicAdd(ticket, 1u) == (unsigned)(nblk * gridDim.y) - 1;
     __syncthreads();
     if (!last) return;
     __threadfence();
@@ -354,9 +359,13 @@ int64_t dot_chunks(int64_t n) {
 int vec_update_dots(const double* win, double* wout, int64_t n, const double* vprev, const double* bscale,
                     const double* V, int64_t ld, const double* csub, int nsub, int nv, double* partial,
                     unsigned* ticket, double* out, int copy_idx, double* copy_to, hipStream_t st) {
-    hipLaunchKernelGGL(update_dots_kernel, dim3((unsigned)dot_chunks(n)), dim3(256), 0, st, win, wout, n,
-                       dot_per_thread(n), vprev, bscale, V, ld, csub, nsub, nv, partial, ticket, out, copy_idx,
-                       copy_to);
+    // vector groups as separate blocks (more of the GPU for few entries and
+    // many vectors), unless an in-place update forbids it
+    const bool upd = vprev || nsub > 0;
+    const int ngrp = (upd && win == wout) ? 1 : (std::max(nv, 1) + kDotBatch - 1) / kDotBatch;
+    hipLaunchKernelGGL(update_dots_kernel, dim3((unsigned)dot_chunks(n), (unsigned)ngrp), dim3(256), 0, st, win,
+                       wout, n, dot_per_thread(n), vprev, bscale, V, ld, csub, nsub, nv, partial, ticket, out,
+                       copy_idx, copy_to);
     RPYW_HIP(hipGetLastError());
     return RPYW_OK;
 }

@@ -175,11 +175,11 @@ int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, dou
     else if ((rc = body_factors_build(pos, N, a, eta, body_offsets, n_bodies, ar, st, pc, notspd)))
         return rc;
 
-    // w -= bscale[0] vprev + V csub (terms when given), then the dot products
-    // of w with V_0..V_{nv-1} (nv > 0) or its norm (nv = 0)
-    auto update_dots = [&](const double* vprev, const double* bscale, const double* csub, int nsub, int nv,
-                           double* res, int copy_idx, double* copy_to) {
-        return vec_update_dots(w, w, n3, vprev, bscale, V, n3, csub, nsub, nv, partial, ticket, res, copy_idx,
+    // to = from - bscale[0] vprev - V csub (terms when given), then the dot
+    // products of the result with V_0..V_{nv-1} (nv > 0) or its norm (nv = 0)
+    auto update_dots = [&](const double* from, double* to, const double* vprev, const double* bscale,
+                           const double* csub, int nsub, int nv, double* res, int copy_idx, double* copy_to) {
+        return vec_update_dots(from, to, n3, vprev, bscale, V, n3, csub, nsub, nv, partial, ticket, res, copy_idx,
                                copy_to, st);
     };
     auto dots = [&](const double* vec, int nv, double* res, int copy_idx, double* copy_to) {
@@ -203,17 +203,18 @@ int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, dou
         if (k == 0)
             r = pc.apply(2, W, x, n3, st, d_b0, vk);  // v_0 = W / beta0, x = L^-T v_0
         else
-            r = pc.apply(2, w, x, n3, st, d_ab + 2 * (k - 1) + 1, vk);  // v_k = w / beta_{k-1}
+            r = pc.apply(2, y, x, n3, st, d_ab + 2 * (k - 1) + 1, vk);  // v_k = w / beta_{k-1} (w in y)
         if (r) return r;
         if ((r = products(pos, x, y, N, 1, a, eta, prec, ar, st, dom))) return r;  // y = M x
         if ((r = pc.apply(1, y, w, n3, st))) return r;                        // w = L^-1 y
         // w -= beta_{k-1} v_{k-1}; full reorthogonalisation in two passes,
-        // alpha_k = v_k . w from the first; beta_k = |w|
+        // alpha_k = v_k . w from the first; beta_k = |w|.  The passes go
+        // w -> y -> w -> y (not in place), so y holds w afterwards.
         const double* vprev = k > 0 ? V + (size_t)(k - 1) * n3 : nullptr;
         const double* bprev = k > 0 ? d_ab + 2 * (k - 1) + 1 : nullptr;
-        if ((r = update_dots(vprev, bprev, nullptr, 0, k + 1, d_c1, k, d_ab + 2 * k))) return r;
-        if ((r = update_dots(nullptr, nullptr, d_c1, k + 1, k + 1, d_c2, 0, nullptr))) return r;
-        if ((r = update_dots(nullptr, nullptr, d_c2, k + 1, 0, d_ab + 2 * k + 1, 0, nullptr))) return r;
+        if ((r = update_dots(w, y, vprev, bprev, nullptr, 0, k + 1, d_c1, k, d_ab + 2 * k))) return r;
+        if ((r = update_dots(y, w, nullptr, nullptr, d_c1, k + 1, k + 1, d_c2, 0, nullptr))) return r;
+        if ((r = update_dots(w, y, nullptr, nullptr, d_c2, k + 1, 0, d_ab + 2 * k + 1, 0, nullptr))) return r;
         RPYW_HIP(hipMemcpyAsync(h_ab + 2 * k, d_ab + 2 * k, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
         RPYW_HIP(hipEventRecord(g_ab.ev[k % PinnedSlots::kSlots], st));
         return RPYW_OK;

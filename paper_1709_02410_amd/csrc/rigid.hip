@@ -340,10 +340,11 @@ int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets,
         double* c1 = d_col;
         double* c2 = d_col + (k + 1);
         if ((r = dots(w, k + 1, c1, 0, nullptr))) return r;
-        if ((r = vec_update_dots(w, w, n, nullptr, nullptr, V, n, c1, k + 1, k + 1, partial, ticket, c2, 0, nullptr,
+        // the two updates go w -> z -> w (not in place; z is free again)
+        if ((r = vec_update_dots(w, z, n, nullptr, nullptr, V, n, c1, k + 1, k + 1, partial, ticket, c2, 0, nullptr,
                                  st)))
             return r;
-        if ((r = vec_update_dots(w, w, n, nullptr, nullptr, V, n, c2, k + 1, 0, partial, ticket, c2 + (k + 1), 0,
+        if ((r = vec_update_dots(z, w, n, nullptr, nullptr, V, n, c2, k + 1, 0, partial, ticket, c2 + (k + 1), 0,
                                  d_hn + k + 1, st)))
             return r;
         double* hs = h_slot + (size_t)(k % PinnedSlots::kSlots) * slot;
