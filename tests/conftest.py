@@ -18,3 +18,16 @@ def orc():
     from oracle import oracle
     oracle.build()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def solver_calls():
+    """golden/solver_calls_per_step.txt: scheme -> (solves, roots, RFD
+    products by M, printed product total at 5 iterations or None)."""
+    rows = {}
+    with open(os.path.join(ROOT, "tests", "golden", "solver_calls_per_step.txt")) as fh:
+        for line in fh:
+            cols = line.split("#")[0].split()
+            if cols:
+                rows[cols[0]] = (int(cols[1]), int(cols[2]), int(cols[3]), None if cols[4] == "-" else int(cols[4]))
+    return rows

@@ -70,7 +70,7 @@ def test_body_kinematics_match_oracle(rp, orc):
 
 
 @pytest.mark.parametrize("prec,periodic", [(0, False), (0, True), (1, False)])
-def test_ts_step_matches_oracle(rp, orc, prec, periodic):
+def test_ts_step_matches_oracle(rp, orc, prec, periodic, solver_calls):
     nb = 6
     q, th, ref, offs = _suspension(nb, 3)
     box = (30.0, 28.0) if periodic else None
@@ -97,6 +97,7 @@ def test_ts_step_matches_oracle(rp, orc, prec, periodic):
           f"q~={rel_tilde:.2e}", flush=True)
     bound = 1e-10 if prec == 0 else 1e-5
     assert rel_q <= bound and rel_t <= bound and rel_tilde <= bound
+    assert len(step.iters) == solver_calls["ts"][0] + solver_calls["ts"][1]  # three solves, one root
     np.testing.assert_allclose(np.linalg.norm(t1, axis=1), 1.0, atol=1e-13)
 
 
@@ -114,7 +115,7 @@ def test_ts_zero_temperature_is_deterministic_heun(rp, orc):
 
 @pytest.mark.parametrize("scheme", ["emt", "emrfd"])
 @pytest.mark.parametrize("prec,periodic", [(0, False), (0, True), (1, False)])
-def test_em_steps_match_oracle(rp, orc, prec, periodic, scheme):
+def test_em_steps_match_oracle(rp, orc, prec, periodic, scheme, solver_calls):
     """Euler-Maruyama Traction (Alg. 1) and Euler-Maruyama RFD (Alg. 3)."""
     nb = 6
     q, th, ref, offs = _suspension(nb, 9)
@@ -138,3 +139,4 @@ def test_em_steps_match_oracle(rp, orc, prec, periodic, scheme):
           flush=True)
     bound = 1e-10 if prec == 0 else 1e-5
     assert rel_q <= bound and rel_t <= bound
+    assert len(iters) == solver_calls[scheme][0] + solver_calls[scheme][1]

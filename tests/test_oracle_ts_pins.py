@@ -1,6 +1,7 @@
 """Pins of the oracle's body kinematics (quaternion appendix), of its
 Trapezoidal Slip step (Alg. 2) and of its Euler-Maruyama Traction step
-(Alg. 1).
+(Alg. 1), and the number of solves, roots and products by M per step that
+the paper counts for each integrator (golden/solver_calls_per_step.txt).
 
 Independent references: scipy's rotation routines for the quaternion
 updates, the deterministic trapezoidal (Heun) and forward Euler methods
@@ -194,3 +195,45 @@ def test_emrfd_drift_is_the_rfd_of_the_body_mobility(orc):
     U = (N_of(q, th) @ F0.reshape(-1)).reshape(-1, 6)
     qe, te = orc.body_move(q, th, U, 0.2)
     np.testing.assert_allclose(q1, qe, atol=1e-10)
+
+
+
+def test_solver_calls_per_step_match_the_paper_counts(orc, monkeypatch, solver_calls):
+    """Sec. I, Sec. III.B and Sec. IV.B count the mobility solves, the
+    M^{1/2}W computations and the bare products by M (the RFD on M) of one
+    step of each scheme; the oracle's steps make exactly those calls, and
+    at 5 iterations per solve and per root they add up to the printed
+    totals (22 for T-S, 17 for EM-T)."""
+    golden = solver_calls
+    assert set(golden) == {"ts", "emt", "emrfd"}
+    calls = {}
+
+    def counting(name):
+        fn = getattr(orc, name)
+
+        def wrapped(*args, **kw):
+            calls[name] = calls.get(name, 0) + 1
+            return fn(*args, **kw)
+        return wrapped
+
+    for name in ("rigid_solve", "dense_sqrt", "matvec"):
+        monkeypatch.setattr(orc, name, counting(name))
+    nb = 2
+    q, th, ref, offs = _boomerangs(nb, 31)
+    Lp = np.full(nb, 2.0)
+    Ws, Wn = wl.gaussian(ref.shape, 32), wl.gaussian(ref.shape, 33)
+    Wf, Wt = wl.gaussian((nb, 3), 34), wl.gaussian((nb, 3), 35)
+    FT = wl.gaussian((nb, 6), 36)
+    runs = {
+        "ts": lambda: orc.ts_step(q, th, ref, offs, Lp, lambda qq, tt: FT, Ws, Wn, kT=1.0, dt=0.01, delta=1e-4),
+        "emt": lambda: orc.emt_step(q, th, ref, offs, Lp, FT, Wf, Wt, Wn, kT=1.0, dt=0.01, delta=1e-4),
+        "emrfd": lambda: orc.emrfd_step(q, th, ref, offs, Lp, FT, Wf, Wt, Wn, kT=1.0, dt=0.01, delta=1e-4),
+    }
+    for scheme, run in runs.items():
+        calls.clear()
+        run()
+        solves, roots, rfd, total = golden[scheme]
+        got = (calls.get("rigid_solve", 0), calls.get("dense_sqrt", 0), calls.get("matvec", 0))
+        assert got == (solves, roots, rfd), (scheme, got)
+        if total is not None:
+            assert 5 * solves + 5 * roots + rfd == total
