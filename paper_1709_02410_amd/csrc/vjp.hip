@@ -177,19 +177,23 @@ __global__ void sym_vjp_epilogue(const double* __restrict__ tpart, const R* __re
 }
 
 // div_i,a = sum_j sum_b d(M_ij)_ab / d r_j,b (source derivative; for j = i
-// the total derivative of the self block).  One thread per target; meant
-// for the small systems on which the divergence is checked.
+// the total derivative of the self block).  One wave per target: lane l takes
+// the sources j = l (mod 64), and the 64 lane sums are added in lane order,
+// so the result does not depend on scheduling.  Meant for the small systems
+// on which the divergence is checked (every pair costs nine gradient
+// evaluations).
 template <typename R>
-__global__ void divergence_kernel(const double* __restrict__ pos, int64_t N, double inv_a, double mu0,
-                                  double* __restrict__ div) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
+__global__ __launch_bounds__(64) void divergence_kernel(const double* __restrict__ pos, int64_t N, double inv_a,
+                                                        double mu0, double* __restrict__ div) {
+    __shared__ double red[3][64];
+    const int64_t i = blockIdx.x;
+    const int l = threadIdx.x;
     const double xi = pos[3 * i] * inv_a, yi = pos[3 * i + 1] * inv_a, zri = pos[3 * i + 2] * inv_a;
     const double Bi = zri < 1.0 ? zri : 1.0, zti = zri < 1.0 ? 1.0 : zri;
     const double dBi = zri < 1.0 ? 1.0 : 0.0, dzti = zri < 1.0 ? 0.0 : 1.0;
     const R zero[3] = {R(0), R(0), R(0)};
     double acc[3] = {0.0, 0.0, 0.0};
-    for (int64_t j = 0; j < N; ++j) {
+    for (int64_t j = l; j < N; j += 64) {
         const double xj = pos[3 * j] * inv_a, yj = pos[3 * j + 1] * inv_a, zrj = pos[3 * j + 2] * inv_a;
         const double Bj = zrj < 1.0 ? zrj : 1.0, ztj = zrj < 1.0 ? 1.0 : zrj;
         const double dBj = zrj < 1.0 ? 1.0 : 0.0, dztj = zrj < 1.0 ? 0.0 : 1.0;
@@ -218,7 +222,13 @@ __global__ void divergence_kernel(const double* __restrict__ pos, int64_t N, dou
             }
         }
     }
-    for (int a = 0; a < 3; ++a) div[3 * i + a] = mu0 * inv_a * acc[a];
+    for (int a = 0; a < 3; ++a) red[a][l] = acc[a];
+    __syncthreads();
+    if (l < 3) {
+        double t = 0.0;
+        for (int k = 0; k < 64; ++k) t += red[l][k];
+        div[3 * i + l] = mu0 * inv_a * t;
+    }
 }
 
 }  // namespace
@@ -363,12 +373,12 @@ int vjp(const double* pos, const double* f, const double* g, double* grad_pos, d
 }
 
 int divergence(const double* pos, double* div, int64_t N, double a, double eta, int prec, Arena&, hipStream_t st) {
-    const unsigned g1 = (unsigned)((N + 127) / 128);
+    const unsigned g1 = (unsigned)N;  // one wave per target (N < 2^31)
     const double m0 = 1.0 / (6.0 * M_PI * eta * a);
     if (prec == RPYW_FP32C)
-        hipLaunchKernelGGL(divergence_kernel<float>, dim3(g1), dim3(128), 0, st, pos, N, 1.0 / a, m0, div);
+        hipLaunchKernelGGL(divergence_kernel<float>, dim3(g1), dim3(64), 0, st, pos, N, 1.0 / a, m0, div);
     else
-        hipLaunchKernelGGL(divergence_kernel<double>, dim3(g1), dim3(128), 0, st, pos, N, 1.0 / a, m0, div);
+        hipLaunchKernelGGL(divergence_kernel<double>, dim3(g1), dim3(64), 0, st, pos, N, 1.0 / a, m0, div);
     RPYW_HIP(hipGetLastError());
     return RPYW_OK;
 }

@@ -104,6 +104,21 @@ def test_divergence_matches_oracle(rp, orc, prec, tol):
     assert rel <= tol
 
 
+@pytest.mark.parametrize("N", [1, 37, 64, 130])
+def test_divergence_small_and_ragged_sizes(rp, orc, N):
+    """One wave per target with the sources dealt over the 64 lanes: fewer
+    sources than lanes, exactly one per lane, and a ragged second round."""
+    rng = np.random.default_rng(N)
+    pos = np.column_stack([rng.uniform(0, 12, N), rng.uniform(0, 12, N), rng.uniform(0.3, 4.0, N)])
+    if N > 2:
+        pos[2] = pos[1] + [0.4, 0.2, 0.1]  # an overlapping pair
+    ref = orc.divergence(pos)
+    got = rp.divergence(_t(pos), precision=0).cpu().numpy()
+    rel = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300)
+    print(f"divergence N={N} rel={rel:.3e}", flush=True)
+    assert rel <= 1e-11
+
+
 @pytest.mark.parametrize("prec,delta", [(0, 1e-6), (1, 1e-3)])
 def test_rfd_drift_estimate_matches_exact_divergence(rp, prec, delta):
     """Centred RFD with Delta P = Delta Q = W (Sec. III) on the 500-blob
