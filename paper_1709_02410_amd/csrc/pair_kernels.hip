@@ -251,8 +251,14 @@ struct ProductBody {
         R dxa, dya, dza, dxb, dyb, dzb;
         sym_diff(t, ra, dxa, dya, dza);
         sym_diff(t, rb, dxb, dyb, dzb);
-        PairPre<R> pa = pair_pre<R>(dxa, dya, dza, t.z, ra[2]);
-        PairPre<R> pb = pair_pre<R>(dxb, dyb, dzb, t.z, rb[2]);
+        // All four reciprocal square roots are issued before any of their
+        // results is used (the empty asm takes them as inputs and outputs),
+        // so that their latency overlaps.
+        PairGeo<R> ga = pair_geo<R>(dxa, dya, dza, t.z, ra[2]);
+        PairGeo<R> gb = pair_geo<R>(dxb, dyb, dzb, t.z, rb[2]);
+        __asm__ volatile("" : "+v"(ga.w), "+v"(ga.ir), "+v"(gb.w), "+v"(gb.ir));
+        PairPre<R> pa = pair_pre<R>(ga, dza, t.z, ra[2]);
+        PairPre<R> pb = pair_pre<R>(gb, dzb, t.z, rb[2]);
         if (__builtin_amdgcn_ballot_w64(pair_near(pa) || pair_near(pb))) {
             __asm__ volatile("" ::: "memory");  // keep this a branch: do not speculate it
             pair_fix(pa);

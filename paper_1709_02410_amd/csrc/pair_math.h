@@ -81,19 +81,34 @@ struct PairPre {
     R c1, c2, w, rA, rE, kb, kcp, kcm, r2;
 };
 
+// The two distances of a pair and their reciprocal square roots, the first
+// stage of pair_pre (kept separate so that callers can issue the reciprocal
+// square roots of several pairs before any of their results is used).
 template <typename R>
-__device__ __forceinline__ PairPre<R> pair_pre(R dx, R dy, R dz, R zi, R zj) {
-    PairPre<R> o;
-    const R rz = zi + zj;
+struct PairGeo {
+    R rz, rz2, r2, w, ir;
+};
+
+template <typename R>
+__device__ __forceinline__ PairGeo<R> pair_geo(R dx, R dy, R dz, R zi, R zj) {
+    PairGeo<R> g;
+    g.rz = zi + zj;
     const R h2 = fma_(dy, dy, dx * dx);
-    const R r2 = fma_(dz, dz, h2);
-    const R rz2 = rz * rz;
-    const R R2 = h2 + rz2;
-    const R w = rsq<R>(R2);
+    g.r2 = fma_(dz, dz, h2);
+    g.rz2 = g.rz * g.rz;
+    g.w = rsq<R>(h2 + g.rz2);
+    g.ir = rsq<R>(g.r2);
+    return g;
+}
+
+template <typename R>
+__device__ __forceinline__ PairPre<R> pair_pre(const PairGeo<R>& gm, R dz, R zi, R zj) {
+    PairPre<R> o;
+    const R rz = gm.rz, rz2 = gm.rz2, r2 = gm.r2, w = gm.w;
     const R X = w * w;
     const R wX = w * X;
     // free RPY, far branch (r > 2)
-    const R ir = rsq<R>(r2);
+    const R ir = gm.ir;
     const R ir2 = ir * ir;
     o.c1 = ir * fma_(ir2, R(0.5), R(0.75));
     o.c2 = (ir * ir2) * fma_(ir2, R(-1.5), R(0.75));
@@ -115,6 +130,11 @@ __device__ __forceinline__ PairPre<R> pair_pre(R dx, R dy, R dz, R zi, R zj) {
     o.kcm = wX * fma_(-rz, g, cw);
     o.r2 = r2;
     return o;
+}
+
+template <typename R>
+__device__ __forceinline__ PairPre<R> pair_pre(R dx, R dy, R dz, R zi, R zj) {
+    return pair_pre<R>(pair_geo<R>(dx, dy, dz, zi, zj), dz, zi, zj);
 }
 
 template <typename R>
