@@ -271,6 +271,24 @@ struct ProductBody {
         apply<SYM>(pair_fin(pa), t, ra, dxa, dya, dza, acc, sa);
         apply<SYM>(pair_fin(pb), t, rb, dxb, dyb, dzb, acc, sb);
     }
+    // Two images of source r that share one overlap branch, with their four
+    // reciprocal square roots issued before any of them is used.
+    template <bool SYM>
+    __device__ static void image2(const SymTarget<R, K>& t, const R* r, R dxa, R dya, R dxb, R dyb, R dz,
+                                  R (&acc)[NQ], R (&src)[NQ]) {
+        PairGeo<R> ga = pair_geo<R>(dxa, dya, dz, t.z, r[2]);
+        PairGeo<R> gb = pair_geo<R>(dxb, dyb, dz, t.z, r[2]);
+        __asm__ volatile("" : "+v"(ga.w), "+v"(ga.ir), "+v"(gb.w), "+v"(gb.ir));
+        PairPre<R> pa = pair_pre<R>(ga, dz, t.z, r[2]);
+        PairPre<R> pb = pair_pre<R>(gb, dz, t.z, r[2]);
+        if (__builtin_amdgcn_ballot_w64(pair_near(pa) || pair_near(pb))) {
+            __asm__ volatile("" ::: "memory");  // keep this a branch: do not speculate it
+            pair_fix(pa);
+            pair_fix(pb);
+        }
+        apply<SYM>(pair_fin(pa), t, r, dxa, dya, dz, acc, src);
+        apply<SYM>(pair_fin(pb), t, r, dxb, dyb, dz, acc, src);
+    }
     template <bool SYM>
     __device__ static void pair(const SymTarget<R, K>& t, const R* r, R (&acc)[NQ], R (&src)[NQ],
                                 const Box<R>& box) {
@@ -289,6 +307,26 @@ struct ProductBody {
             const R nx = rint_(dx * box.ilx), ny = rint_(dy * box.ily);
             dx = fma_(-nx, box.lxl, fma_(-nx, box.lxh, dx));
             dy = fma_(-ny, box.lyl, fma_(-ny, box.lyh, dy));
+            // image k: shift (k / 3 - 1, k % 3 - 1) cells
+            auto shifted = [&](int k, R& ex, R& ey) {
+                const int sx = k / 3 - 1, sy = k % 3 - 1;
+                ex = sx == 0 ? dx : sx < 0 ? dx - box.lx : dx + box.lx;
+                ey = sy == 0 ? dy : sy < 0 ? dy - box.ly : dy + box.ly;
+            };
+            if constexpr (PER == 1) {
+                // images in pairs, each pair sharing one overlap branch
+#pragma unroll
+                for (int k = 0; k < 8; k += 2) {
+                    R ea, fa, eb, fb;
+                    shifted(k, ea, fa);
+                    shifted(k + 1, eb, fb);
+                    image2<SYM>(t, r, ea, fa, eb, fb, dz, acc, src);
+                }
+                R e8, f8;
+                shifted(8, e8, f8);
+                image<SYM>(t, r, e8, f8, dz, acc, src);
+                return;
+            }
 #pragma unroll
             for (int sx = -1; sx <= 1; ++sx)
 #pragma unroll
