@@ -269,7 +269,15 @@ __global__ __launch_bounds__(64 * NB) void sym_kernel(const R* __restrict__ rec,
     constexpr bool kLds = sizeof(R) == 8;
     __shared__ VT tile[L::NV * VS];
     __shared__ R sacc[kLds ? NB : 1][kLds ? NQ : 1][kLds ? 128 : 1];  // per source block, slots l + s
-    __shared__ R red[kLds ? 1 : NB][kLds ? 1 : NQ][kLds ? 1 : G];
+    // FP32 with more than three quantities per blob (the VJP, several
+    // right-hand sides): the NB phases' passes are added into one row of G
+    // slots per quantity in phase order, with a barrier between phases, which
+    // needs NB times less LDS and so allows more workgroups per CU.  With
+    // three (the product) the waves write separate rows and one barrier
+    // follows the last phase (fewer barriers, and occupancy is bounded by
+    // registers there).
+    constexpr bool kPhased = !kLds && NQ > 3;
+    __shared__ R red[kLds ? 1 : (kPhased ? 1 : NB)][kLds ? 1 : NQ][kLds ? 1 : G];
     const int g = blockIdx.x % nseg, P = blockIdx.x / nseg / C, c = blockIdx.x / nseg % C;
     const int s0 = g * (64 / nseg), s1 = s0 + 64 / nseg;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -307,20 +315,25 @@ __global__ __launch_bounds__(64 * NB) void sym_kernel(const R* __restrict__ rec,
             } else {
                 me.template pass<true>(tile, VS, blk, l, kLds ? &sacc[blk][0][0] : nullptr, S, box, s0, s1);
             }
-            if constexpr (kLds) {
-                __syncthreads();  // one wave per source block in every phase
-            } else {
+            if constexpr (kPhased) {
+                R* slot = &red[0][0][blk * 64 + ((l + s1) & 63)];
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) slot[q * G] = bb == 0 ? S[q] : slot[q * G] + S[q];
+            } else if constexpr (!kLds) {
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) red[w][q][blk * 64 + ((l + s1) & 63)] = S[q];
             }
+            if constexpr (kLds || kPhased) __syncthreads();  // one wave per source block in every phase
         }
-        if constexpr (!kLds) __syncthreads();
+        if constexpr (!kLds && !kPhased) __syncthreads();
         R* out = spart + (((int64_t)Q * (Hmax + 1) + d) * nseg + g) * NQ * G;
         const int b = threadIdx.x >> 6, j = threadIdx.x & 63;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             if constexpr (kLds) {
                 out[q * G + threadIdx.x] = sacc[b][q][j] + sacc[b][q][j + 64];
+            } else if constexpr (kPhased) {
+                out[q * G + threadIdx.x] = red[0][q][threadIdx.x];
             } else {
                 R t = red[0][q][threadIdx.x];
 #pragma unroll
