@@ -80,7 +80,7 @@ int rpy_wall_matvec_multi(const double* pos, const double* F, double* U, int64_t
                           double eta, int precision, void* ws, size_t ws_bytes, void* stream);
 
 /* Pseudo-periodic domain along the wall (the paper's dense suspensions,
- * Sec. V): u = M f where every source blob enters at its minimum image
+ * Sec. IV.B): u = M f where every source blob enters at its minimum image
  * relative to the target and at the 8 periodic images around that one,
  * for the unit cell Lx x Ly in x and y (the wall stays at z = 0); the self
  * pair includes the blob's own 8 images.  The minimum image is the shift

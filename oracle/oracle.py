@@ -29,7 +29,7 @@ Contents (arXiv:1709.02410):
     (Alg. 1, ``emt_step``) and of the Euler-Maruyama RFD scheme (Alg. 3,
     ``emrfd_step``), with dense solves.
   * ``box=(Lx, Ly)`` on the products, dense matrices, roots and solves: the
-    pseudo-periodic domain of the paper's suspensions (Sec. V): each source
+    pseudo-periodic domain of the paper's suspensions (Sec. IV.B): each source
     at its minimum image plus the 8 periodic images around it.
 
 Readings where the paper is silent (the Lanczos stopping rule, full
@@ -115,7 +115,7 @@ def pair_block(ri, rj, a: float = 1.0, eta: float = 1.0, part: int = 0) -> np.nd
 
 def matvec(pos, f, a: float = 1.0, eta: float = 1.0, rows=None, nthreads: int = 0, box=None) -> np.ndarray:
     """u = M f; with ``rows`` only those target rows (shape (len(rows), 3)).
-    box = (Lx, Ly): pseudo-periodic domain (Sec. V): every source at its
+    box = (Lx, Ly): pseudo-periodic domain (Sec. IV.B): every source at its
     minimum image and the 8 periodic images around it."""
     pos, f = _c(pos), _c(f)
     N = pos.shape[0]

@@ -218,7 +218,7 @@ void oracle_matvec(const double* pos, const double* f, double* u, int64_t N, dou
 }
 
 /* Source blob j as seen from target i in the pseudo-periodic domain
- * (Sec. V, dense suspensions): the minimum image of r_j, shifted by
+ * (Sec. IV.B, dense suspensions): the minimum image of r_j, shifted by
  * (n_x + sx) Lx and (n_y + sy) Ly with n the nearest integer to
  * (r_i - r_j) / L (ties to even) and sx, sy in {-1, 0, 1}. */
 static void periodic_image(const double* ri, const double* rj, double Lx, double Ly, int sx, int sy, double* out) {

@@ -1,4 +1,4 @@
-// Temporal integrators for rigid multiblobs (arXiv:1709.02410, Sec. IV).
+// Temporal integrators for rigid multiblobs (arXiv:1709.02410, Sec. III and Appendix A).
 //
 // Trapezoidal Slip (T-S, Alg. 2, with the slip-corrected random finite
 // difference), split in two calls around the caller's force evaluation:

@@ -1,4 +1,4 @@
-"""GPU pseudo-periodic mobility (Sec. V suspensions: minimum image plus the
+"""GPU pseudo-periodic mobility (Sec. IV.B suspensions: minimum image plus the
 8 periodic images along the wall) against the oracle: products, the
 preconditioned Lanczos root and the rigid solve."""
 import math

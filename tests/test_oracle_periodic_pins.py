@@ -1,4 +1,4 @@
-"""Pins of the oracle's pseudo-periodic mobility (Sec. V: each source blob at
+"""Pins of the oracle's pseudo-periodic mobility (Sec. IV.B: each source blob at
 its minimum image along the wall plus the 8 periodic images around it).
 
 Expected values come from the open-domain pair blocks with the images picked
