@@ -258,7 +258,8 @@ __global__ __launch_bounds__(256) void update_dots_kernel(const double* win, dou
                                                           const double* __restrict__ csub, int nsub, int nv,
                                                           double* __restrict__ partial, unsigned* __restrict__ ticket,
                                                           double* __restrict__ out, int copy_idx,
-                                                          double* __restrict__ copy_to) {
+                                                          double* __restrict__ copy_to, double* hdst,
+                                                          const double* hsrc, int nh) {
     __shared__ double tile[kDotBatch][257];
     __shared__ double cpv;
     __shared__ bool last;
@@ -275,6 +276,15 @@ __global__ __launch_bounds__(256) void update_dots_kernel(const double* win, dou
         double v = win[e];
         if (vprev) v -= bscale[0] * vprev[e];
         int j = 0;
+        // sixteen loads in flight before their terms are subtracted (in
+        // order): the long reorthogonalisation updates are latency-bound
+        for (; j + 15 < nsub; j += 16) {
+            double av[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) av[u] = V[(j + u) * ld + e];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v -= csub[j + u] * av[u];
+        }
         for (; j + 3 < nsub; j += 4) {
             const double a0 = V[j * ld + e], a1 = V[(j + 1) * ld + e];
             const double a2 = V[(j + 2) * ld + e], a3 = V[(j + 3) * ld + e];
@@ -334,6 +344,7 @@ __global__ __launch_bounds__(256) void update_dots_kernel(const double* win, dou
         if (copy_to) copy_to[0] = cpv;
         *ticket = 0u;
     }
+    for (int i = t; i < nh; i += 256) hdst[i] = hsrc[i];
 }
 
 // out = sum_{j < nv} c[j] V_j
@@ -358,14 +369,16 @@ int64_t dot_chunks(int64_t n) {
 
 int vec_update_dots(const double* win, double* wout, int64_t n, const double* vprev, const double* bscale,
                     const double* V, int64_t ld, const double* csub, int nsub, int nv, double* partial,
-                    unsigned* ticket, double* out, int copy_idx, double* copy_to, hipStream_t st) {
+                    unsigned* ticket, double* out, int copy_idx, double* copy_to, hipStream_t st, double* hdst,
+                    const double* hsrc, int nh) {
+    if (nh < 0 || (nh > 0 && (!hdst || !hsrc))) return RPYW_EINVAL;
     // vector groups as separate blocks (more of the GPU for few entries and
     // many vectors), unless an in-place update forbids it
     const bool upd = vprev || nsub > 0;
     const int ngrp = (upd && win == wout) ? 1 : (std::max(nv, 1) + kDotBatch - 1) / kDotBatch;
     hipLaunchKernelGGL(update_dots_kernel, dim3((unsigned)dot_chunks(n), (unsigned)ngrp), dim3(256), 0, st, win,
                        wout, n, dot_per_thread(n), vprev, bscale, V, ld, csub, nsub, nv, partial, ticket, out,
-                       copy_idx, copy_to);
+                       copy_idx, copy_to, hdst, hsrc, nh);
     RPYW_HIP(hipGetLastError());
     return RPYW_OK;
 }
@@ -518,12 +531,17 @@ int PinnedSlots::reserve(size_t bytes) {
         if (k.p) RPYW_HIP(hipHostFree(k.p));
         k.p = nullptr;
         k.cap = 0;
-        RPYW_HIP(hipHostMalloc((void**)&k.p, bytes, hipHostMallocDefault));
+        k.dp = nullptr;
+        // fine-grained (coherent) so that kernel stores reach host memory
+        // without passing through the GPU caches
+        RPYW_HIP(hipHostMalloc((void**)&k.p, bytes, hipHostMallocMapped | hipHostMallocCoherent));
+        RPYW_HIP(hipHostGetDevicePointer((void**)&k.dp, k.p, 0));
         k.cap = bytes;
     }
     for (auto& e : k.ev)
         if (!e) RPYW_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     p = k.p;
+    dp = k.dp;
     ev = k.ev;
     return RPYW_OK;
 }

@@ -214,8 +214,10 @@ int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, dou
         const double* bprev = k > 0 ? d_ab + 2 * (k - 1) + 1 : nullptr;
         if ((r = update_dots(w, y, vprev, bprev, nullptr, 0, k + 1, d_c1, k, d_ab + 2 * k))) return r;
         if ((r = update_dots(y, w, nullptr, nullptr, d_c1, k + 1, k + 1, d_c2, 0, nullptr))) return r;
-        if ((r = update_dots(w, y, nullptr, nullptr, d_c2, k + 1, 0, d_ab + 2 * k + 1, 0, nullptr))) return r;
-        RPYW_HIP(hipMemcpyAsync(h_ab + 2 * k, d_ab + 2 * k, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        // the last pass also stores alpha_k, beta_k into the pinned slot
+        if ((r = vec_update_dots(w, y, n3, nullptr, nullptr, V, n3, d_c2, k + 1, 0, partial, ticket,
+                                 d_ab + 2 * k + 1, 0, nullptr, st, g_ab.dp + 2 * k, d_ab + 2 * k, 2)))
+            return r;
         RPYW_HIP(hipEventRecord(g_ab.ev[k % PinnedSlots::kSlots], st));
         return RPYW_OK;
     };

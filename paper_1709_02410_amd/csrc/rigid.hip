@@ -344,11 +344,12 @@ int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets,
         if ((r = vec_update_dots(w, z, n, nullptr, nullptr, V, n, c1, k + 1, k + 1, partial, ticket, c2, 0, nullptr,
                                  st)))
             return r;
+        // the last pass also stores column k (c1, c2, h_{k+1,k}) into its
+        // pinned slot
+        double* hs = g_h.dp + (size_t)(k % PinnedSlots::kSlots) * slot;
         if ((r = vec_update_dots(z, w, n, nullptr, nullptr, V, n, c2, k + 1, 0, partial, ticket, c2 + (k + 1), 0,
-                                 d_hn + k + 1, st)))
+                                 d_hn + k + 1, st, hs, d_col, 2 * (k + 1) + 1)))
             return r;
-        double* hs = h_slot + (size_t)(k % PinnedSlots::kSlots) * slot;
-        RPYW_HIP(hipMemcpyAsync(hs, d_col, (2 * (k + 1) + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
         RPYW_HIP(hipEventRecord(g_h.ev[k % PinnedSlots::kSlots], st));
         return RPYW_OK;
     };

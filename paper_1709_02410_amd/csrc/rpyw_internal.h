@@ -136,7 +136,11 @@ int body_factors_build(const double* pos, int64_t N, double a, double eta, const
 //           zeroed unsigned that the kernel re-arms;
 //   update_dots: the update w = win - bscale[0] vprev - sum_{j < nsub}
 //           csub[j] V_j (terms when given; written to wout when there is
-//           one) then the dots of w, in one pass;
+//           one) then the dots of w, in one pass; with nh > 0 the
+//           kernel's finishing block then copies hsrc[0..nh) (device
+//           memory, which may include this pass's out) to hdst (the device
+//           alias of pinned host memory), so the host reads the results
+//           after an event without a separate copy;
 //   comb:   out = sum_{j < nv} c[j] V_j.
 // Asynchronous upload of a small host array (which the caller may free at
 // once) through a library-owned pinned ring.
@@ -146,7 +150,8 @@ int vec_dots(const double* V, int64_t ld, int nv, const double* w, int64_t n, do
              double* out, int copy_idx, double* copy_to, hipStream_t st);
 int vec_update_dots(const double* win, double* wout, int64_t n, const double* vprev, const double* bscale,
                     const double* V, int64_t ld, const double* csub, int nsub, int nv, double* partial,
-                    unsigned* ticket, double* out, int copy_idx, double* copy_to, hipStream_t st);
+                    unsigned* ticket, double* out, int copy_idx, double* copy_to, hipStream_t st,
+                    double* hdst = nullptr, const double* hsrc = nullptr, int nh = 0);
 int vec_comb(const double* V, int64_t ld, int nv, const double* c, double* out, int64_t n, hipStream_t st);
 // Krylov drivers keep kSpeculateDepth steps queued beyond the one the host
 // examines (a step needs only device data from the previous one), so the GPU
@@ -175,7 +180,8 @@ inline int speculate_to(int k, int depth, double m1, double m2, double tol) {
 struct PinnedSlots {
     static constexpr int kSlots = 4;  // steps in flight at most (kSpeculateDepth + 1)
     struct Bank {
-        double* p = nullptr;
+        double* p = nullptr;   // host address
+        double* dp = nullptr;  // the same memory as kernels address it
         size_t cap = 0;
         hipEvent_t ev[kSlots] = {};
         hipEvent_t tail = nullptr;  // after the last copy into p of the call that used it
@@ -184,6 +190,7 @@ struct PinnedSlots {
     Bank bank[2];
     int cur = 0;
     double* p = nullptr;     // the current call's bank
+    double* dp = nullptr;    // its device alias (kernels write results there)
     hipEvent_t* ev = nullptr;
     // Switches bank, waits for the copies of the call that last used it, then
     // makes p hold bytes.

@@ -82,16 +82,25 @@ def test_determinism_and_multi_rhs(rp, orc):
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_headline_1e5_sampled_rows(rp, orc, prec):
-    """1e5 blobs (the measured workload) in the launch shape the benchmark
-    times; 192 sampled target rows computed by the oracle."""
+    """1e5 blobs (the measured workload) in every launch shape the benchmark's
+    tuner may pick there (the default, and the symmetric kernel with 1, 2 and
+    4 items per workgroup); 192 sampled target rows computed by the oracle."""
     cfg = wl.headline(seed=0)
     f = wl.gaussian(cfg.pos.shape, 1)
-    got = rp.matvec(_t(cfg.pos), _t(f), precision=prec).cpu().numpy()
+    pos, ft = _t(cfg.pos), _t(f)
     rows = np.random.default_rng(5).choice(cfg.N, 192, replace=False)
     ref = orc.matvec(cfg.pos, f, rows=rows)
-    r = _rel(got[rows], ref)
-    print(f"H prec={prec} sampled rel={r:.3e}", flush=True)
-    assert r <= TOL[prec]
+    shapes = [None] + [dict(tpl=1, tile=256, kblk=1, sym=1, ipw=ipw) for ipw in (1, 2, 4)]
+    try:
+        for sh in shapes:
+            if sh is not None:
+                rp.set_shape(prec, cfg.N, 1, **sh)
+            got = rp.matvec(pos, ft, precision=prec).cpu().numpy()
+            r = _rel(got[rows], ref)
+            print(f"H prec={prec} shape={sh} sampled rel={r:.3e}", flush=True)
+            assert r <= TOL[prec]
+    finally:
+        rp.reset_shape(prec, cfg.N, 1)
 
 
 def test_microrollers_fp32_vs_fp64(rp, orc):
