@@ -162,7 +162,8 @@ struct SymLane {
     // contribution for source (l + s) mod 64 goes either to the accumulator
     // S, which moves one lane down after every step (a DPP wave rotate fused
     // into the add), so that after the pass lane l holds source l's sum
-    // (sa == nullptr), or to LDS sa[q * 128 + l + s] by an atomic add.
+    // (FP32; sa is null), or to LDS sa[q * 128 + l + s] by an atomic add
+    // (FP64).
     // vs: LDS entries per vector slot of the tile (128 per source block).
     // Steps s0 .. s1 - 1 only (a segment of the pass; s1 - s0 even): the
     // rotating accumulator then ends with source (l + s1) mod 64 in lane l.
@@ -174,10 +175,10 @@ struct SymLane {
         R* sl = sa + l;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) S[q] = R(0);
-        // Source side of step s: to the LDS slots (FP64) or into the rotating
-        // accumulator (FP32).
+        // Source side of step s: to the LDS slots (FP64, sa given) or into
+        // the rotating accumulator (FP32, sa null); chosen at compile time.
         auto source_side = [&](const R(&c)[NQ], int s) {
-            if (sa) {
+            if constexpr (sizeof(R) == 8) {
 #pragma unroll
                 for (int q = 0; q < NQ; ++q)
                     __hip_atomic_fetch_add(sl + q * 128 + s, c[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
