@@ -90,13 +90,16 @@ def main():
     ap.add_argument("--calib-copy", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--only", action="append", default=[],
+                    help="time only the extra rows whose names contain this text (repeatable; the headline "
+                         "and the FP64 product always run)")
     ap.add_argument("--force-ipw", type=int, default=0,
                     help="after tuning, force the symmetric headline kernel with this many items per workgroup "
                          "(for counter runs of one launch shape)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the row-sharded design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(how the product would shard by target rows is a design note, not code)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -131,6 +134,10 @@ def main():
         kms, launches, pairs = rp.profile_read(True)
         rp.profile_enable(False)
         return wall, kms, launches, pairs
+
+    def want(*names):
+        """Whether any of these rows is selected (all are without --only)."""
+        return not args.only or any(o in n for o in args.only for n in names)
 
     out = {}
     # ---------------------------------------------------------- headline
@@ -180,223 +187,240 @@ def main():
     rows = {}
     if not args.headline_only:
         # 16-RHS product on the headline geometry
-        k = 16
-        F16 = T(wl.gaussian((k, N, 3), 2))
-        U16 = torch.empty_like(F16)
-        rp.autotune(pos, F16, precision=rp.FP32C)
-        w, km, ln, pr = timed(lambda: rp.matvec_multi(pos, F16, precision=rp.FP32C, out=U16), 3, 1)
-        sh16 = rp.get_shape(rp.FP32C, N, k)
-        fl = sum(algorithmic_flop(N, min(sh16["kblk"], k - k0), sh16["sym"]) for k0 in range(0, k, sh16["kblk"]))
-        call_ms = km / 3  # kernel time of one call (three timed calls)
-        rows["multi_rhs_H_k16_fp32c"] = {"pair_rhs_per_s": k * N * N / w, "ms": w * 1e3, "shape": sh16,
-                                         "tflops_alg": fl / (call_ms * 1e-3) / 1e12,
-                                         "frac_fp32_peak": fl / (call_ms * 1e-3) / 1e12 / PEAK_FP32}
-        del F16, U16
+        if want("multi_rhs"):
+            k = 16
+            F16 = T(wl.gaussian((k, N, 3), 2))
+            U16 = torch.empty_like(F16)
+            rp.autotune(pos, F16, precision=rp.FP32C)
+            w, km, ln, pr = timed(lambda: rp.matvec_multi(pos, F16, precision=rp.FP32C, out=U16), 3, 1)
+            sh16 = rp.get_shape(rp.FP32C, N, k)
+            fl = sum(algorithmic_flop(N, min(sh16["kblk"], k - k0), sh16["sym"]) for k0 in range(0, k, sh16["kblk"]))
+            call_ms = km / 3  # kernel time of one call (three timed calls)
+            rows["multi_rhs_H_k16_fp32c"] = {"pair_rhs_per_s": k * N * N / w, "ms": w * 1e3, "shape": sh16,
+                                             "tflops_alg": fl / (call_ms * 1e-3) / 1e12,
+                                             "frac_fp32_peak": fl / (call_ms * 1e-3) / 1e12 / PEAK_FP32}
+            del F16, U16
 
         # single products on configs 0, 1 and 4 (default launch shapes), both
         # precisions: pairs/s and the pair kernel's share of the call
-        for cname, cfg in (("C0", wl.config0(seed=0)), ("C1", wl.config1(seed=0)), ("C4", wl.config4(seed=0))):
-            pcf, fcf = T(cfg.pos), T(wl.gaussian(cfg.pos.shape, 4))
-            ucf = torch.empty_like(fcf)
-            for prec, pname in ((rp.FP32C, "fp32c"), (rp.FP64, "fp64")):
-                reps = 50 if cfg.N <= 4000 else 10
-                w, km, ln, pr = timed(lambda: rp.matvec(pcf, fcf, precision=prec, out=ucf), reps, 3)
-                shc = rp.get_shape(prec, cfg.N, 1)
-                kms = km / max(ln, 1)
-                rows[f"product_{cname}_{pname}"] = {
-                    "blobs": cfg.N, "pairs_per_s": cfg.N ** 2 / w, "ms": w * 1e3, "kernel_ms": kms, "shape": shc,
-                    "tflops_alg": algorithmic_flop(cfg.N, 1, shc["sym"]) / (kms * 1e-3) / 1e12}
-            del pcf, fcf, ucf
+        if want("product_C0", "product_C1", "product_C4"):
+            for cname, cfg in (("C0", wl.config0(seed=0)), ("C1", wl.config1(seed=0)), ("C4", wl.config4(seed=0))):
+                pcf, fcf = T(cfg.pos), T(wl.gaussian(cfg.pos.shape, 4))
+                ucf = torch.empty_like(fcf)
+                for prec, pname in ((rp.FP32C, "fp32c"), (rp.FP64, "fp64")):
+                    reps = 50 if cfg.N <= 4000 else 10
+                    w, km, ln, pr = timed(lambda: rp.matvec(pcf, fcf, precision=prec, out=ucf), reps, 3)
+                    shc = rp.get_shape(prec, cfg.N, 1)
+                    kms = km / max(ln, 1)
+                    rows[f"product_{cname}_{pname}"] = {
+                        "blobs": cfg.N, "pairs_per_s": cfg.N ** 2 / w, "ms": w * 1e3, "kernel_ms": kms, "shape": shc,
+                        "tflops_alg": algorithmic_flop(cfg.N, 1, shc["sym"]) / (kms * 1e-3) / 1e12}
+                del pcf, fcf, ucf
 
         # batched suspensions (config 3) against per-instance launches
-        C3 = wl.config3(seed=0)
-        offs = C3.sys_offsets
-        S = len(offs) - 1
-        F3 = T(wl.gaussian((k, C3.N, 3), 3))
-        U3 = torch.empty_like(F3)
-        p3 = T(C3.pos)
-        nmax = int(max(offs[s + 1] - offs[s] for s in range(S)))
-        smax = int(np.argmax(np.diff(offs)))
-        rp.autotune(p3[offs[smax]:offs[smax + 1]].contiguous(),
-                    F3[:, offs[smax]:offs[smax + 1]].contiguous(), precision=rp.FP32C)
-        pairs3 = float(sum(float(offs[s + 1] - offs[s]) ** 2 for s in range(S)))
-        wb, _, _, _ = timed(lambda: rp.matvec_batched(p3, offs, F3, precision=rp.FP32C, out=U3), 3, 1)
-        slices = [(int(offs[s]), int(offs[s + 1])) for s in range(S)]
-        sub = [(p3[a:b].contiguous(), F3[:, a:b].contiguous()) for a, b in slices]
+        if want("batched_C3"):
+            C3 = wl.config3(seed=0)
+            offs = C3.sys_offsets
+            S = len(offs) - 1
+            F3 = T(wl.gaussian((k, C3.N, 3), 3))
+            U3 = torch.empty_like(F3)
+            p3 = T(C3.pos)
+            nmax = int(max(offs[s + 1] - offs[s] for s in range(S)))
+            smax = int(np.argmax(np.diff(offs)))
+            rp.autotune(p3[offs[smax]:offs[smax + 1]].contiguous(),
+                        F3[:, offs[smax]:offs[smax + 1]].contiguous(), precision=rp.FP32C)
+            pairs3 = float(sum(float(offs[s + 1] - offs[s]) ** 2 for s in range(S)))
+            wb, _, _, _ = timed(lambda: rp.matvec_batched(p3, offs, F3, precision=rp.FP32C, out=U3), 3, 1)
+            slices = [(int(offs[s]), int(offs[s + 1])) for s in range(S)]
+            sub = [(p3[a:b].contiguous(), F3[:, a:b].contiguous()) for a, b in slices]
 
-        def per_system_multi():
-            for ps, Fs in sub:
-                rp.matvec_multi(ps, Fs, precision=rp.FP32C)
+            def per_system_multi():
+                for ps, Fs in sub:
+                    rp.matvec_multi(ps, Fs, precision=rp.FP32C)
 
-        def per_system_single():
-            for ps, Fs in sub:
-                for l in range(k):
-                    rp.matvec(ps, Fs[l], precision=rp.FP32C)
+            def per_system_single():
+                for ps, Fs in sub:
+                    for l in range(k):
+                        rp.matvec(ps, Fs[l], precision=rp.FP32C)
 
-        wm, _, _, _ = timed(per_system_multi, 2, 1)
-        wsn, _, _, _ = timed(per_system_single, 1, 1)
-        rows["batched_C3_k16_fp32c"] = {
-            "systems": S, "blobs": C3.N, "largest": nmax, "pair_rhs": k * pairs3,
-            "batched_ms": wb * 1e3, "per_system_multi_rhs_ms": wm * 1e3, "per_system_single_rhs_ms": wsn * 1e3,
-            "speedup_vs_multi": wm / wb, "speedup_vs_single": wsn / wb,
-            "batched_pair_rhs_per_s": k * pairs3 / wb}
-        del F3, U3, sub
+            wm, _, _, _ = timed(per_system_multi, 2, 1)
+            wsn, _, _, _ = timed(per_system_single, 1, 1)
+            rows["batched_C3_k16_fp32c"] = {
+                "systems": S, "blobs": C3.N, "largest": nmax, "pair_rhs": k * pairs3,
+                "batched_ms": wb * 1e3, "per_system_multi_rhs_ms": wm * 1e3, "per_system_single_rhs_ms": wsn * 1e3,
+                "speedup_vs_multi": wm / wb, "speedup_vs_single": wsn / wb,
+                "batched_pair_rhs_per_s": k * pairs3 / wb}
+            del F3, U3, sub
 
         # Lanczos: 256 boomerangs FP64 tol 1e-6; microrollers FP32C tol 1e-6
         C1 = wl.config1(seed=0)
         pc1, W1 = T(C1.pos), T(wl.gaussian(C1.pos.shape, 1))
-        rp.lanczos_sqrt(pc1, W1, body_offsets=C1.body_offsets, tol=1e-6)
-        sync()
-        t0 = time.perf_counter()
-        _, it1, err1, ok1 = rp.lanczos_sqrt(pc1, W1, body_offsets=C1.body_offsets, tol=1e-6)
-        sync()
-        t1 = time.perf_counter() - t0
-        rows["lanczos_C1_fp64_tol1e-6"] = {"blobs": C1.N, "iterations": it1, "converged": ok1, "ms": t1 * 1e3,
-                                           "ms_per_iteration": t1 * 1e3 / max(it1, 1)}
-        # Rigid-body mobility solve (GMRES, block-diagonal preconditioner):
-        # 256 boomerangs, reference point at the corner blob, random F and T
-        q1 = T(C1.pos[C1.body_offsets[:-1]])
-        FT1 = T(wl.gaussian((len(C1.body_offsets) - 1, 6), 5))
-        for prec, pname in ((rp.FP64, "fp64"), (rp.FP32C, "fp32c")):
-            for tol in (1e-3, 1e-6):
-                rp.rigid_solve(pc1, q1, C1.body_offsets, None, FT1, tol=tol, precision=prec)
-                sync()
-                t0 = time.perf_counter()
-                _, _, itr, resr, okr = rp.rigid_solve(pc1, q1, C1.body_offsets, None, FT1, tol=tol, precision=prec)
-                sync()
-                tr = time.perf_counter() - t0
-                rows[f"rigid_C1_{pname}_tol{tol:g}"] = {"blobs": C1.N, "bodies": len(C1.body_offsets) - 1,
-                                                        "iterations": itr, "converged": okr, "residual": resr,
-                                                        "ms": tr * 1e3, "ms_per_iteration": tr * 1e3 / max(itr, 1)}
-        # Iterations versus suspension size with the paper's boomerang
-        # geometry (Sec. II.B: about five at tolerance 1e-3, size-independent)
-        for nbody in (256, 1024, 4096):
-            PB = wl.paperlike_boomerangs(nbody, seed=2)
-            ppb, qpb = T(PB.pos), T(PB.pos[PB.body_offsets[:-1]])
-            FTpb = T(wl.gaussian((nbody, 6), 11))
-            rp.rigid_solve(ppb, qpb, PB.body_offsets, None, FTpb, tol=1e-3, precision=rp.FP32C)
+        if want("lanczos_C1"):
+            rp.lanczos_sqrt(pc1, W1, body_offsets=C1.body_offsets, tol=1e-6)
             sync()
             t0 = time.perf_counter()
-            _, _, itp, resp, okp = rp.rigid_solve(ppb, qpb, PB.body_offsets, None, FTpb, tol=1e-3,
-                                                 precision=rp.FP32C)
+            _, it1, err1, ok1 = rp.lanczos_sqrt(pc1, W1, body_offsets=C1.body_offsets, tol=1e-6)
             sync()
-            tp = time.perf_counter() - t0
-            rows[f"rigid_paperlike_{nbody}_fp32c_tol0.001"] = {
-                "blobs": PB.N, "bodies": nbody, "iterations": itp, "converged": okp, "residual": resp,
-                "ms": tp * 1e3, "ms_per_iteration": tp * 1e3 / max(itp, 1)}
-            del ppb, qpb, FTpb
-        # Pseudo-periodic cell (minimum image + 8 images), the paper's dense
-        # boomerang suspensions: products and one rigid solve at 1e-3
-        for nbody in (256, 4096):
-            PB = wl.paperlike_boomerangs(nbody, seed=2)
-            Lc = 139.8 * math.sqrt(nbody / 256.0)
-            ppb, fpb = T(PB.pos), T(wl.gaussian(PB.pos.shape, 12))
-            wpp, kpp, lpp, ppp = timed(lambda: rp.matvec(ppb, fpb, precision=rp.FP32C, box=(Lc, Lc)), 5, 2)
-            rows[f"periodic_paperlike_{nbody}_fp32c"] = {
-                "blobs": PB.N, "cell": Lc, "ms": wpp * 1e3, "kernel_ms": kpp / lpp,
-                "image_pairs_per_s": 9.0 * PB.N ** 2 / wpp,
-                "tflops_alg_sym": 9.0 * algorithmic_flop(PB.N, 1, 1) / (kpp / lpp * 1e-3) / 1e12}
-            if nbody == 256:
-                qpb = T(PB.pos[PB.body_offsets[:-1]])
+            t1 = time.perf_counter() - t0
+            rows["lanczos_C1_fp64_tol1e-6"] = {"blobs": C1.N, "iterations": it1, "converged": ok1, "ms": t1 * 1e3,
+                                               "ms_per_iteration": t1 * 1e3 / max(it1, 1)}
+        # Rigid-body mobility solve (GMRES, block-diagonal preconditioner):
+        # 256 boomerangs, reference point at the corner blob, random F and T
+        if want("rigid_C1"):
+            q1 = T(C1.pos[C1.body_offsets[:-1]])
+            FT1 = T(wl.gaussian((len(C1.body_offsets) - 1, 6), 5))
+            for prec, pname in ((rp.FP64, "fp64"), (rp.FP32C, "fp32c")):
+                for tol in (1e-3, 1e-6):
+                    rp.rigid_solve(pc1, q1, C1.body_offsets, None, FT1, tol=tol, precision=prec)
+                    sync()
+                    t0 = time.perf_counter()
+                    _, _, itr, resr, okr = rp.rigid_solve(pc1, q1, C1.body_offsets, None, FT1, tol=tol, precision=prec)
+                    sync()
+                    tr = time.perf_counter() - t0
+                    rows[f"rigid_C1_{pname}_tol{tol:g}"] = {"blobs": C1.N, "bodies": len(C1.body_offsets) - 1,
+                                                            "iterations": itr, "converged": okr, "residual": resr,
+                                                            "ms": tr * 1e3, "ms_per_iteration": tr * 1e3 / max(itr, 1)}
+        # Iterations versus suspension size with the paper's boomerang
+        # geometry (Sec. II.B: about five at tolerance 1e-3, size-independent)
+        if want("rigid_paperlike"):
+            for nbody in (256, 1024, 4096):
+                PB = wl.paperlike_boomerangs(nbody, seed=2)
+                ppb, qpb = T(PB.pos), T(PB.pos[PB.body_offsets[:-1]])
                 FTpb = T(wl.gaussian((nbody, 6), 11))
-                rp.rigid_solve(ppb, qpb, PB.body_offsets, None, FTpb, tol=1e-3, precision=rp.FP32C, box=(Lc, Lc))
+                rp.rigid_solve(ppb, qpb, PB.body_offsets, None, FTpb, tol=1e-3, precision=rp.FP32C)
                 sync()
                 t0 = time.perf_counter()
                 _, _, itp, resp, okp = rp.rigid_solve(ppb, qpb, PB.body_offsets, None, FTpb, tol=1e-3,
-                                                     precision=rp.FP32C, box=(Lc, Lc))
+                                                     precision=rp.FP32C)
                 sync()
-                rows["periodic_rigid_paperlike_256_fp32c_tol0.001"] = {
-                    "blobs": PB.N, "iterations": itp, "converged": okp, "ms": (time.perf_counter() - t0) * 1e3}
-            if nbody == 256:
-                # One Trapezoidal Slip step (Alg. 2) in the cell, the paper's
-                # settings for this suspension: tolerance 1e-3, FP32C products,
-                # delta = 1e-3; gravity-like constant force per body
-                # tracking points at the corner blobs, body frames = the current
-                # blob offsets from them (identity orientations)
-                thb = torch.zeros((nbody, 4), dtype=torch.float64, device=dev)
-                thb[:, 0] = 1.0
-                qb = T(PB.pos[PB.body_offsets[:-1]])
-                refb = T(PB.pos - np.repeat(PB.pos[PB.body_offsets[:-1]], 15, axis=0))
-                Fb = torch.zeros((nbody, 6), dtype=torch.float64, device=dev)
-                Fb[:, 2] = -1.0
-                stp = rp.TSStep(refb, PB.body_offsets, T(np.full(nbody, 5.0)), 1.0, 0.01, 1e-3, tol=1e-3,
-                                precision=rp.FP32C, box=(Lc, Lc))
-                Wsb, Wnb = T(wl.gaussian(PB.pos.shape, 21)), T(wl.gaussian(PB.pos.shape, 22))
-                stp.step(qb, thb, lambda qq, tt, pp: Fb, Wsb, Wnb)
-                sync()
-                t0 = time.perf_counter()
-                for _ in range(3):
-                    stp.step(qb, thb, lambda qq, tt, pp: Fb, Wsb, Wnb)
-                sync()
-                rows["ts_step_periodic_paperlike_256_fp32c_tol0.001"] = {
-                    "blobs": PB.N, "bodies": nbody, "ms_per_step": (time.perf_counter() - t0) / 3 * 1e3,
-                    "iterations_rfd_lanczos_predictor_corrector": stp.iters,
-                    "products_per_step": sum(stp.iters) + 2}
-                Lpb = T(np.full(nbody, 5.0))
-                Wfb, Wtb = T(wl.gaussian((nbody, 3), 23)), T(wl.gaussian((nbody, 3), 24))
-                emt = lambda: rp.emt_step(qb, thb, refb, PB.body_offsets, Lpb, Fb, Wfb, Wtb, Wnb, 1.0, 0.01,  # noqa
-                                          1e-3, tol=1e-3, precision=rp.FP32C, box=(Lc, Lc))
-                emt()
-                sync()
-                t0 = time.perf_counter()
-                for _ in range(3):
-                    _, _, ite = emt()
-                sync()
-                rows["emt_step_periodic_paperlike_256_fp32c_tol0.001"] = {
-                    "blobs": PB.N, "bodies": nbody, "ms_per_step": (time.perf_counter() - t0) / 3 * 1e3,
-                    "iterations_rfd_lanczos_solve": ite, "products_per_step": sum(ite) + 2}
-                emr = lambda: rp.emt_step(qb, thb, refb, PB.body_offsets, Lpb, Fb, Wfb, Wtb, Wnb, 1.0, 0.01,  # noqa
-                                          1e-3, tol=1e-3, precision=rp.FP32C, box=(Lc, Lc), scheme="emrfd")
-                emr()
-                sync()
-                t0 = time.perf_counter()
-                for _ in range(3):
-                    _, _, ite = emr()
-                sync()
-                rows["emrfd_step_periodic_paperlike_256_fp32c_tol0.001"] = {
-                    "blobs": PB.N, "bodies": nbody, "ms_per_step": (time.perf_counter() - t0) / 3 * 1e3,
-                    "iterations_rfd_rfd_lanczos_solve": ite, "products_per_step": sum(ite)}
-            del ppb, fpb
-        C2 = wl.config2(seed=0)
-        pc2, W2 = T(C2.pos), T(wl.gaussian(C2.pos.shape, 3))
-        sync()
-        t0 = time.perf_counter()
-        _, it2, err2, ok2 = rp.lanczos_sqrt(pc2, W2, body_offsets=C2.body_offsets, tol=1e-6,
-                                            precision=rp.FP32C)
-        sync()
-        t2 = time.perf_counter() - t0
-        u64c2 = rp.matvec(pc2, W2, precision=rp.FP64)
-        w2, k2, l2, p2 = timed(lambda: rp.matvec(pc2, W2, precision=rp.FP32C), 2, 1)
-        u32c2 = rp.matvec(pc2, W2, precision=rp.FP32C)
-        rows["lanczos_C2_fp32c_tol1e-6"] = {"blobs": C2.N, "iterations": it2, "converged": ok2, "ms": t2 * 1e3,
-                                            "ms_per_iteration": t2 * 1e3 / max(it2, 1)}
-        rows["product_C2_fp32c"] = {"blobs": C2.N, "pairs_per_s": C2.N ** 2 / w2, "ms": w2 * 1e3,
-                                    "rel_l2_vs_fp64": float((u32c2 - u64c2).norm() / u64c2.norm())}
-        nb2 = len(C2.body_offsets) - 1
-        q2 = T(C2.pos.reshape(nb2, 12, 3).mean(1))
-        FT2 = T(wl.gaussian((nb2, 6), 7))
-        rp.rigid_solve(pc2, q2, C2.body_offsets, None, FT2, tol=1e-3, precision=rp.FP32C)
-        sync()
-        t0 = time.perf_counter()
-        _, _, itr2, resr2, okr2 = rp.rigid_solve(pc2, q2, C2.body_offsets, None, FT2, tol=1e-3, precision=rp.FP32C)
-        sync()
-        tr2 = time.perf_counter() - t0
-        rows["rigid_C2_fp32c_tol0.001"] = {"blobs": C2.N, "bodies": nb2, "iterations": itr2, "converged": okr2,
-                                           "residual": resr2, "ms": tr2 * 1e3,
-                                           "ms_per_iteration": tr2 * 1e3 / max(itr2, 1)}
-        del pc2, W2, u64c2, u32c2, q2, FT2
+                tp = time.perf_counter() - t0
+                rows[f"rigid_paperlike_{nbody}_fp32c_tol0.001"] = {
+                    "blobs": PB.N, "bodies": nbody, "iterations": itp, "converged": okp, "residual": resp,
+                    "ms": tp * 1e3, "ms_per_iteration": tp * 1e3 / max(itp, 1)}
+                del ppb, qpb, FTpb
+        # Pseudo-periodic cell (minimum image + 8 images), the paper's dense
+        # boomerang suspensions: products and one rigid solve at 1e-3
+        if want("periodic_paperlike", "periodic_rigid", "ts_step", "emt_step", "emrfd_step"):
+            for nbody in (256, 4096):
+                PB = wl.paperlike_boomerangs(nbody, seed=2)
+                Lc = 139.8 * math.sqrt(nbody / 256.0)
+                ppb, fpb = T(PB.pos), T(wl.gaussian(PB.pos.shape, 12))
+                if want("periodic_paperlike"):
+                    wpp, kpp, lpp, ppp = timed(lambda: rp.matvec(ppb, fpb, precision=rp.FP32C, box=(Lc, Lc)), 5, 2)
+                    rows[f"periodic_paperlike_{nbody}_fp32c"] = {
+                        "blobs": PB.N, "cell": Lc, "ms": wpp * 1e3, "kernel_ms": kpp / lpp,
+                        "image_pairs_per_s": 9.0 * PB.N ** 2 / wpp,
+                        "tflops_alg_sym": 9.0 * algorithmic_flop(PB.N, 1, 1) / (kpp / lpp * 1e-3) / 1e12}
+                if nbody == 256:
+                    if want("periodic_rigid"):
+                        qpb = T(PB.pos[PB.body_offsets[:-1]])
+                        FTpb = T(wl.gaussian((nbody, 6), 11))
+                        rp.rigid_solve(ppb, qpb, PB.body_offsets, None, FTpb, tol=1e-3, precision=rp.FP32C,
+                                       box=(Lc, Lc))
+                        sync()
+                        t0 = time.perf_counter()
+                        _, _, itp, resp, okp = rp.rigid_solve(ppb, qpb, PB.body_offsets, None, FTpb, tol=1e-3,
+                                                             precision=rp.FP32C, box=(Lc, Lc))
+                        sync()
+                        rows["periodic_rigid_paperlike_256_fp32c_tol0.001"] = {
+                            "blobs": PB.N, "iterations": itp, "converged": okp, "ms": (time.perf_counter() - t0) * 1e3}
+                if nbody == 256:
+                    # One Trapezoidal Slip step (Alg. 2) in the cell, the paper's
+                    # settings for this suspension: tolerance 1e-3, FP32C products,
+                    # delta = 1e-3; gravity-like constant force per body
+                    # tracking points at the corner blobs, body frames = the current
+                    # blob offsets from them (identity orientations)
+                    thb = torch.zeros((nbody, 4), dtype=torch.float64, device=dev)
+                    thb[:, 0] = 1.0
+                    qb = T(PB.pos[PB.body_offsets[:-1]])
+                    refb = T(PB.pos - np.repeat(PB.pos[PB.body_offsets[:-1]], 15, axis=0))
+                    Fb = torch.zeros((nbody, 6), dtype=torch.float64, device=dev)
+                    Fb[:, 2] = -1.0
+                    Wsb, Wnb = T(wl.gaussian(PB.pos.shape, 21)), T(wl.gaussian(PB.pos.shape, 22))
+                    if want("ts_step"):
+                        stp = rp.TSStep(refb, PB.body_offsets, T(np.full(nbody, 5.0)), 1.0, 0.01, 1e-3, tol=1e-3,
+                                        precision=rp.FP32C, box=(Lc, Lc))
+                        stp.step(qb, thb, lambda qq, tt, pp: Fb, Wsb, Wnb)
+                        sync()
+                        t0 = time.perf_counter()
+                        for _ in range(3):
+                            stp.step(qb, thb, lambda qq, tt, pp: Fb, Wsb, Wnb)
+                        sync()
+                        rows["ts_step_periodic_paperlike_256_fp32c_tol0.001"] = {
+                            "blobs": PB.N, "bodies": nbody, "ms_per_step": (time.perf_counter() - t0) / 3 * 1e3,
+                            "iterations_rfd_lanczos_predictor_corrector": stp.iters,
+                            "products_per_step": sum(stp.iters) + 2}
+                    Lpb = T(np.full(nbody, 5.0))
+                    Wfb, Wtb = T(wl.gaussian((nbody, 3), 23)), T(wl.gaussian((nbody, 3), 24))
+                    if want("emt_step"):
+                        emt = lambda: rp.emt_step(qb, thb, refb, PB.body_offsets, Lpb, Fb, Wfb, Wtb, Wnb,  # noqa
+                                                  1.0, 0.01, 1e-3, tol=1e-3, precision=rp.FP32C, box=(Lc, Lc))
+                        emt()
+                        sync()
+                        t0 = time.perf_counter()
+                        for _ in range(3):
+                            _, _, ite = emt()
+                        sync()
+                        rows["emt_step_periodic_paperlike_256_fp32c_tol0.001"] = {
+                            "blobs": PB.N, "bodies": nbody, "ms_per_step": (time.perf_counter() - t0) / 3 * 1e3,
+                            "iterations_rfd_lanczos_solve": ite, "products_per_step": sum(ite) + 2}
+                    if want("emrfd_step"):
+                        emr = lambda: rp.emt_step(qb, thb, refb, PB.body_offsets, Lpb, Fb, Wfb, Wtb, Wnb,  # noqa
+                                                  1.0, 0.01, 1e-3, tol=1e-3, precision=rp.FP32C, box=(Lc, Lc),
+                                                  scheme="emrfd")
+                        emr()
+                        sync()
+                        t0 = time.perf_counter()
+                        for _ in range(3):
+                            _, _, ite = emr()
+                        sync()
+                        rows["emrfd_step_periodic_paperlike_256_fp32c_tol0.001"] = {
+                            "blobs": PB.N, "bodies": nbody, "ms_per_step": (time.perf_counter() - t0) / 3 * 1e3,
+                            "iterations_rfd_rfd_lanczos_solve": ite, "products_per_step": sum(ite)}
+                del ppb, fpb
+        if want("lanczos_C2", "product_C2", "rigid_C2"):
+            C2 = wl.config2(seed=0)
+            pc2, W2 = T(C2.pos), T(wl.gaussian(C2.pos.shape, 3))
+            sync()
+            t0 = time.perf_counter()
+            _, it2, err2, ok2 = rp.lanczos_sqrt(pc2, W2, body_offsets=C2.body_offsets, tol=1e-6,
+                                                precision=rp.FP32C)
+            sync()
+            t2 = time.perf_counter() - t0
+            u64c2 = rp.matvec(pc2, W2, precision=rp.FP64)
+            w2, k2, l2, p2 = timed(lambda: rp.matvec(pc2, W2, precision=rp.FP32C), 2, 1)
+            u32c2 = rp.matvec(pc2, W2, precision=rp.FP32C)
+            rows["lanczos_C2_fp32c_tol1e-6"] = {"blobs": C2.N, "iterations": it2, "converged": ok2, "ms": t2 * 1e3,
+                                                "ms_per_iteration": t2 * 1e3 / max(it2, 1)}
+            rows["product_C2_fp32c"] = {"blobs": C2.N, "pairs_per_s": C2.N ** 2 / w2, "ms": w2 * 1e3,
+                                        "rel_l2_vs_fp64": float((u32c2 - u64c2).norm() / u64c2.norm())}
+            nb2 = len(C2.body_offsets) - 1
+            q2 = T(C2.pos.reshape(nb2, 12, 3).mean(1))
+            FT2 = T(wl.gaussian((nb2, 6), 7))
+            rp.rigid_solve(pc2, q2, C2.body_offsets, None, FT2, tol=1e-3, precision=rp.FP32C)
+            sync()
+            t0 = time.perf_counter()
+            _, _, itr2, resr2, okr2 = rp.rigid_solve(pc2, q2, C2.body_offsets, None, FT2, tol=1e-3, precision=rp.FP32C)
+            sync()
+            tr2 = time.perf_counter() - t0
+            rows["rigid_C2_fp32c_tol0.001"] = {"blobs": C2.N, "bodies": nb2, "iterations": itr2, "converged": okr2,
+                                               "residual": resr2, "ms": tr2 * 1e3,
+                                               "ms_per_iteration": tr2 * 1e3 / max(itr2, 1)}
+            del pc2, W2, u64c2, u32c2, q2, FT2
 
         # VJP on the differentiation workload
-        C4 = wl.config4(seed=0)
-        p4, f4, g4 = T(C4.pos), T(wl.gaussian(C4.pos.shape, 1)), T(wl.gaussian(C4.pos.shape, 2))
-        for prec, name in ((rp.FP32C, "fp32c"), (rp.FP64, "fp64")):
-            w, km, ln, pr = timed(lambda: rp.matvec_vjp(p4, f4, g4, precision=prec), 3, 1)
-            rows[f"vjp_C4_{name}"] = {"blobs": C4.N, "ms": w * 1e3, "pairs_per_s": C4.N ** 2 / w,
-                                      "kernel_ms": km / ln}
-        D = wl.divergence_config(seed=0)
-        pd = T(D.pos)
-        w, _, _, _ = timed(lambda: rp.divergence(pd, precision=rp.FP64), 3, 1)
-        rows["divergence_500_fp64"] = {"blobs": D.N, "ms": w * 1e3}
+        if want("vjp_C4"):
+            C4 = wl.config4(seed=0)
+            p4, f4, g4 = T(C4.pos), T(wl.gaussian(C4.pos.shape, 1)), T(wl.gaussian(C4.pos.shape, 2))
+            for prec, name in ((rp.FP32C, "fp32c"), (rp.FP64, "fp64")):
+                w, km, ln, pr = timed(lambda: rp.matvec_vjp(p4, f4, g4, precision=prec), 3, 1)
+                rows[f"vjp_C4_{name}"] = {"blobs": C4.N, "ms": w * 1e3, "pairs_per_s": C4.N ** 2 / w,
+                                          "kernel_ms": km / ln}
+        if want("divergence"):
+            D = wl.divergence_config(seed=0)
+            pd = T(D.pos)
+            w, _, _, _ = timed(lambda: rp.divergence(pd, precision=rp.FP64), 3, 1)
+            rows["divergence_500_fp64"] = {"blobs": D.N, "ms": w * 1e3}
 
     # ---------------------------------------------------------- CPU oracle
     cpu = None
