@@ -126,20 +126,39 @@ __global__ __launch_bounds__(kBodyThreads) void precond_build_kernel(const doubl
 // mat-vec).  With `scale`, the input is v / scale[0] and, with `store`, that
 // scaled input is also written there (this forms the next Lanczos vector
 // v_{k+1} = w / beta_k).
+// v[e] - sum_{j < nc} c[j] V[j ld + e], the terms subtracted in order.
+__device__ __forceinline__ double minus_comb(const double* __restrict__ v, const double* __restrict__ V, int64_t ld,
+                                             const double* __restrict__ c, int nc, int64_t e) {
+    double x = v[e];
+    int j = 0;
+    for (; j + 7 < nc; j += 8) {
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = V[(j + u) * ld + e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x -= c[j + u] * a[u];
+    }
+    for (; j < nc; ++j) x -= c[j] * V[j * ld + e];
+    return x;
+}
+
 __global__ __launch_bounds__(kBodyThreads) void precond_apply_kernel(const double* __restrict__ Lall,
                                                                      const int* __restrict__ bofs,
                                                                      const int64_t* __restrict__ lofs, int mode,
                                                                      const double* __restrict__ v,
                                                                      const double* __restrict__ scale,
                                                                      double* __restrict__ store,
-                                                                     double* __restrict__ out) {
+                                                                     double* __restrict__ out,
+                                                                     const double* __restrict__ V, int64_t ld,
+                                                                     const double* __restrict__ c, int nc) {
     __shared__ double x[3 * kMaxBodyBlobs];
     const int p = blockIdx.x;
     const int e0 = 3 * bofs[p], n = 3 * bofs[p + 1] - e0;
     const double* F = Lall + 2 * lofs[p] + (mode == 0 ? 0 : (int64_t)n * n);
     const double inv = scale ? 1.0 / scale[0] : 1.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const double vi = scale ? v[e0 + i] * inv : v[e0 + i];
+        const double vr = nc > 0 ? minus_comb(v, V, ld, c, nc, e0 + i) : v[e0 + i];
+        const double vi = scale ? vr * inv : vr;
         x[i] = vi;
         if (store) store[e0 + i] = vi;
     }
@@ -176,10 +195,12 @@ __global__ void blob_diag_kernel(const double* __restrict__ pos, int64_t N, doub
 // mode 0: out = D v; 1, 2: out = v / D (diagonal L); scale/store as above.
 __global__ void diag_apply_kernel(const double* __restrict__ ldiag, int64_t n3, int mode, const double* __restrict__ v,
                                   const double* __restrict__ scale, double* __restrict__ store,
-                                  double* __restrict__ out) {
+                                  double* __restrict__ out, const double* __restrict__ V,
+                                  const double* __restrict__ c, int nc) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n3) return;
-    const double vi = scale ? v[e] * (1.0 / scale[0]) : v[e];
+    const double vr = nc > 0 ? minus_comb(v, V, n3, c, nc, e) : v[e];
+    const double vi = scale ? vr * (1.0 / scale[0]) : vr;
     if (store) store[e] = vi;
     out[e] = mode == 0 ? ldiag[e] * vi : vi / ldiag[e];
 }
@@ -259,7 +280,8 @@ __global__ __launch_bounds__(256) void update_dots_kernel(const double* win, dou
                                                           double* __restrict__ partial, unsigned* __restrict__ ticket,
                                                           double* __restrict__ out, int copy_idx,
                                                           double* __restrict__ copy_to, double* hdst,
-                                                          const double* hsrc, int nh) {
+                                                          const double* hsrc, int nh, int with_norm,
+                                                          double* beta_out) {
     __shared__ double tile[kDotBatch][257];
     __shared__ double cpv;
     __shared__ bool last;
@@ -297,7 +319,7 @@ __global__ __launch_bounds__(256) void update_dots_kernel(const double* win, dou
         if (wout && (upd || wout != win) && blockIdx.y == 0) wout[e] = v;
         x[r] = v;
     }
-    const int nd = nv > 0 ? nv : 1;
+    const int nd = nv > 0 ? nv + (with_norm ? 1 : 0) : 1;  // results: dots, then |w|^2 or |w|
     const int jr = t >> 4, c0 = t & 15;  // reduction: vector jr of the batch, columns c0 + 16 i
     const int jend = (int)(blockIdx.y + 1) * kDotBatch < nd ? (int)(blockIdx.y + 1) * kDotBatch : nd;
     for (int j0 = (int)blockIdx.y * kDotBatch; j0 < jend; j0 += kDotBatch) {
@@ -306,7 +328,7 @@ __global__ __launch_bounds__(256) void update_dots_kernel(const double* win, dou
         for (int u = 0; u < kDotBatch; ++u) {
             double p = 0.0;
             if (u < jn) {
-                if (nv > 0) {
+                if (j0 + u < nv) {
                     const double* a = V + (j0 + u) * ld;
 #pragma unroll
                     for (int r = 0; r < kDotPerThread; ++r) {
@@ -342,9 +364,17 @@ __global__ __launch_bounds__(256) void update_dots_kernel(const double* win, dou
     __syncthreads();
     if (t == 0) {
         if (copy_to) copy_to[0] = cpv;
+        if (beta_out) {
+            double s2 = out[nv];
+            for (int j = 0; j < nv; ++j) s2 -= out[j] * out[j];
+            *beta_out = s2 > 0.0 ? sqrt(s2) : 0.0;
+        }
         *ticket = 0u;
     }
-    for (int i = t; i < nh; i += 256) hdst[i] = hsrc[i];
+    if (nh > 0) {
+        __syncthreads();
+        for (int i = t; i < nh; i += 256) hdst[i] = hsrc[i];
+    }
 }
 
 // out = sum_{j < nv} c[j] V_j
@@ -370,15 +400,18 @@ int64_t dot_chunks(int64_t n) {
 int vec_update_dots(const double* win, double* wout, int64_t n, const double* vprev, const double* bscale,
                     const double* V, int64_t ld, const double* csub, int nsub, int nv, double* partial,
                     unsigned* ticket, double* out, int copy_idx, double* copy_to, hipStream_t st, double* hdst,
-                    const double* hsrc, int nh) {
+                    const double* hsrc, int nh, bool with_norm, double* beta_out) {
     if (nh < 0 || (nh > 0 && (!hdst || !hsrc))) return RPYW_EINVAL;
+    if ((with_norm || beta_out) && nv < 1) return RPYW_EINVAL;
+    if (beta_out && !with_norm) return RPYW_EINVAL;
     // vector groups as separate blocks (more of the GPU for few entries and
     // many vectors), unless an in-place update forbids it
     const bool upd = vprev || nsub > 0;
-    const int ngrp = (upd && win == wout) ? 1 : (std::max(nv, 1) + kDotBatch - 1) / kDotBatch;
+    const int nd = nv > 0 ? nv + (with_norm ? 1 : 0) : 1;
+    const int ngrp = (upd && win == wout) ? 1 : (nd + kDotBatch - 1) / kDotBatch;
     hipLaunchKernelGGL(update_dots_kernel, dim3((unsigned)dot_chunks(n), (unsigned)ngrp), dim3(256), 0, st, win,
                        wout, n, dot_per_thread(n), vprev, bscale, V, ld, csub, nsub, nv, partial, ticket, out,
-                       copy_idx, copy_to, hdst, hsrc, nh);
+                       copy_idx, copy_to, hdst, hsrc, nh, with_norm ? 1 : 0, beta_out);
     RPYW_HIP(hipGetLastError());
     return RPYW_OK;
 }
@@ -396,12 +429,14 @@ int vec_comb(const double* V, int64_t ld, int nv, const double* c, double* out, 
 }
 
 int BodyFactors::apply(int mode, const double* v, double* out, int64_t n3, hipStream_t st, const double* scale,
-                       double* store) const {
+                       double* store, const double* V, const double* c, int nc) const {
+    if (nc < 0 || (nc > 0 && (!V || !c))) return RPYW_EINVAL;
     if (diag)
-        hipLaunchKernelGGL(diag_apply_kernel, dim3(grid_of(n3)), dim3(256), 0, st, L, n3, mode, v, scale, store, out);
+        hipLaunchKernelGGL(diag_apply_kernel, dim3(grid_of(n3)), dim3(256), 0, st, L, n3, mode, v, scale, store, out,
+                           V, c, nc);
     else
         hipLaunchKernelGGL(precond_apply_kernel, dim3(nb), dim3(kBodyThreads), 0, st, L, bofs, lofs, mode, v, scale,
-                           store, out);
+                           store, out, V, n3, c, nc);
     RPYW_HIP(hipGetLastError());
     return RPYW_OK;
 }

@@ -202,21 +202,22 @@ int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, dou
         int r;
         if (k == 0)
             r = pc.apply(2, W, x, n3, st, d_b0, vk);  // v_0 = W / beta0, x = L^-T v_0
-        else
-            r = pc.apply(2, y, x, n3, st, d_ab + 2 * (k - 1) + 1, vk);  // v_k = w / beta_{k-1} (w in y)
+        else  // v_k = (w - V c2) / beta_{k-1}: the second correction of step k - 1
+            r = pc.apply(2, w, x, n3, st, d_ab + 2 * (k - 1) + 1, vk, V, d_c2, k);
         if (r) return r;
         if ((r = products(pos, x, y, N, 1, a, eta, prec, ar, st, dom))) return r;  // y = M x
         if ((r = pc.apply(1, y, w, n3, st))) return r;                        // w = L^-1 y
         // w -= beta_{k-1} v_{k-1}; full reorthogonalisation in two passes,
-        // alpha_k = v_k . w from the first; beta_k = |w|.  The passes go
-        // w -> y -> w -> y (not in place), so y holds w afterwards.
+        // alpha_k = v_k . w from the first (w -> y).  The second (y -> w)
+        // computes c2 = V^T w and |w|^2, and beta_k = |w - V c2| from
+        // |w|^2 - |c2|^2 (V orthonormal); w - V c2 itself is formed by the
+        // next step's preconditioner application.  The pass also stores
+        // alpha_k, beta_k into the pinned slot.
         const double* vprev = k > 0 ? V + (size_t)(k - 1) * n3 : nullptr;
         const double* bprev = k > 0 ? d_ab + 2 * (k - 1) + 1 : nullptr;
         if ((r = update_dots(w, y, vprev, bprev, nullptr, 0, k + 1, d_c1, k, d_ab + 2 * k))) return r;
-        if ((r = update_dots(y, w, nullptr, nullptr, d_c1, k + 1, k + 1, d_c2, 0, nullptr))) return r;
-        // the last pass also stores alpha_k, beta_k into the pinned slot
-        if ((r = vec_update_dots(w, y, n3, nullptr, nullptr, V, n3, d_c2, k + 1, 0, partial, ticket,
-                                 d_ab + 2 * k + 1, 0, nullptr, st, g_ab.dp + 2 * k, d_ab + 2 * k, 2)))
+        if ((r = vec_update_dots(y, w, n3, nullptr, nullptr, V, n3, d_c1, k + 1, k + 1, partial, ticket, d_c2, 0,
+                                 nullptr, st, g_ab.dp + 2 * k, d_ab + 2 * k, 2, true, d_ab + 2 * k + 1)))
             return r;
         RPYW_HIP(hipEventRecord(g_ab.ev[k % PinnedSlots::kSlots], st));
         return RPYW_OK;

@@ -118,11 +118,12 @@ struct BodyFactors {
     int64_t* lofs = nullptr;  // device [nb + 1] offsets of the (3 n_p)^2 blocks
     double* L = nullptr;      // per body L_p then L_p^-1 (at 2 lofs[p]); or the diagonal [3N]
     int* flag = nullptr;      // device int set by the build when a block is not positive definite
-    // mode 0: out = L v; 1: out = L^-1 v; 2: out = L^-T v.  With scale the
-    // input is v / scale[0] and, with store, that scaled input is written
-    // there too.
+    // mode 0: out = L v; 1: out = L^-1 v; 2: out = L^-T v.  With nc > 0 the
+    // input is first v - sum_{j < nc} c[j] V_j (V_j at V + j n3, the terms
+    // subtracted in order); with scale it is then divided by scale[0] and,
+    // with store, written there too.
     int apply(int mode, const double* v, double* out, int64_t n3, hipStream_t st, const double* scale = nullptr,
-              double* store = nullptr) const;
+              double* store = nullptr, const double* V = nullptr, const double* c = nullptr, int nc = 0) const;
 };
 size_t body_factors_bytes(int64_t N, int n_bodies);
 // Builds the factors on the stream; sets *notspd (device int, zeroed by the
@@ -132,7 +133,7 @@ int body_factors_build(const double* pos, int64_t N, double a, double eta, const
 // Vector kernels (FP64, length n, basis vectors V_j at V + j ld):
 //   dots:   out[j] = V_j . w (j < nv), or out[0] = |w| when nv == 0, with a
 //           fixed-order finish; out[copy_idx] is also copied to copy_to;
-//           partial holds max(nv, 1) dot_chunks(n) doubles, ticket one
+//           partial holds max(nv, 1) (nv + 1 with_norm) dot_chunks(n) doubles, ticket one
 //           zeroed unsigned that the kernel re-arms;
 //   update_dots: the update w = win - bscale[0] vprev - sum_{j < nsub}
 //           csub[j] V_j (terms when given; written to wout when there is
@@ -140,7 +141,10 @@ int body_factors_build(const double* pos, int64_t N, double a, double eta, const
 //           kernel's finishing block then copies hsrc[0..nh) (device
 //           memory, which may include this pass's out) to hdst (the device
 //           alias of pinned host memory), so the host reads the results
-//           after an event without a separate copy;
+//           after an event without a separate copy; with_norm (nv > 0)
+//           also puts |w|^2 in out[nv] and, with beta_out, writes
+//           sqrt(|w|^2 - sum_j out[j]^2) there: the norm of w - V out when
+//           the V_j are orthonormal (before the results are copied);
 //   comb:   out = sum_{j < nv} c[j] V_j.
 // Asynchronous upload of a small host array (which the caller may free at
 // once) through a library-owned pinned ring.
@@ -151,7 +155,8 @@ int vec_dots(const double* V, int64_t ld, int nv, const double* w, int64_t n, do
 int vec_update_dots(const double* win, double* wout, int64_t n, const double* vprev, const double* bscale,
                     const double* V, int64_t ld, const double* csub, int nsub, int nv, double* partial,
                     unsigned* ticket, double* out, int copy_idx, double* copy_to, hipStream_t st,
-                    double* hdst = nullptr, const double* hsrc = nullptr, int nh = 0);
+                    double* hdst = nullptr, const double* hsrc = nullptr, int nh = 0, bool with_norm = false,
+                    double* beta_out = nullptr);
 int vec_comb(const double* V, int64_t ld, int nv, const double* c, double* out, int64_t n, hipStream_t st);
 // Krylov drivers keep kSpeculateDepth steps queued beyond the one the host
 // examines (a step needs only device data from the previous one), so the GPU
