@@ -126,22 +126,6 @@ __global__ __launch_bounds__(kBodyThreads) void precond_build_kernel(const doubl
 // mat-vec).  With `scale`, the input is v / scale[0] and, with `store`, that
 // scaled input is also written there (this forms the next Lanczos vector
 // v_{k+1} = w / beta_k).
-// v[e] - sum_{j < nc} c[j] V[j ld + e], the terms subtracted in order.
-__device__ __forceinline__ double minus_comb(const double* __restrict__ v, const double* __restrict__ V, int64_t ld,
-                                             const double* __restrict__ c, int nc, int64_t e) {
-    double x = v[e];
-    int j = 0;
-    for (; j + 7 < nc; j += 8) {
-        double a[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) a[u] = V[(j + u) * ld + e];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) x -= c[j + u] * a[u];
-    }
-    for (; j < nc; ++j) x -= c[j] * V[j * ld + e];
-    return x;
-}
-
 __global__ __launch_bounds__(kBodyThreads) void precond_apply_kernel(const double* __restrict__ Lall,
                                                                      const int* __restrict__ bofs,
                                                                      const int64_t* __restrict__ lofs, int mode,
@@ -363,12 +347,14 @@ __global__ __launch_bounds__(256) void update_dots_kernel(const double* win, dou
         finish_dots<4>(partial, nblk, nd, nv, copy_idx, out, &cpv);
     __syncthreads();
     if (t == 0) {
-        if (copy_to) copy_to[0] = cpv;
+        double cp = cpv;
         if (beta_out) {
             double s2 = out[nv];
             for (int j = 0; j < nv; ++j) s2 -= out[j] * out[j];
-            *beta_out = s2 > 0.0 ? sqrt(s2) : 0.0;
+            cp = s2 > 0.0 ? sqrt(s2) : 0.0;
+            *beta_out = cp;
         }
+        if (copy_to) copy_to[0] = cp;
         *ticket = 0u;
     }
     if (nh > 0) {

@@ -138,16 +138,20 @@ __global__ __launch_bounds__(kRT) void rigid_factors_kernel(const double* __rest
 // z = P^-1 r for r = [rl (3N) | ru (6 nb)] (see the file comment).  With
 // scale the input is r / scale[0] and, with store (pointing at a full
 // vector), that scaled input is also written there.
+// The input r may be the output z (in place): a workgroup reads all of its
+// body's input entries before it writes any output, and touches no other
+// body's entries.  With nc > 0 the input is first r - sum_{j < nc} c[j] V_j
+// (V_j at V + j (n3 + 6 nb), the terms subtracted in order).
 __global__ __launch_bounds__(kRT) void rigid_precond_kernel(const double* __restrict__ Lall,
                                                            const int* __restrict__ bofs,
                                                            const int64_t* __restrict__ lofs,
                                                            const double* __restrict__ Wall,
                                                            const double* __restrict__ Nall, int64_t n3,
-                                                           const double* __restrict__ rl,
-                                                           const double* __restrict__ ru,
+                                                           const double* rl, const double* ru,
                                                            const double* __restrict__ scale,
-                                                           double* __restrict__ store, double* __restrict__ zl,
-                                                           double* __restrict__ zu) {
+                                                           double* __restrict__ store, double* zl, double* zu,
+                                                           const double* __restrict__ V, int64_t ld,
+                                                           const double* __restrict__ c, int nc) {
     __shared__ double r[kMaxN3], t1[kMaxN3], t[kMaxN3];
     __shared__ double r6[6], s6[6], z6[6];
     const int p = blockIdx.x;
@@ -157,14 +161,18 @@ __global__ __launch_bounds__(kRT) void rigid_precond_kernel(const double* __rest
     const double* W = Wall + 18 * (int64_t)b0;
     const double inv = scale ? 1.0 / scale[0] : 1.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const double v = scale ? rl[e0 + i] * inv : rl[e0 + i];
+        const double x = nc > 0 ? minus_comb(rl, V, ld, c, nc, e0 + i) : rl[e0 + i];
+        const double v = scale ? x * inv : x;
         r[i] = v;
         if (store) store[e0 + i] = v;
     }
     if (threadIdx.x < 6) {
-        const double v = scale ? ru[6 * p + threadIdx.x] * inv : ru[6 * p + threadIdx.x];
+        // the U part of V_j starts at n3 (ru = rl + n3 in every call)
+        const int64_t eu = 6 * p + threadIdx.x;
+        const double x = nc > 0 ? minus_comb(ru, V + n3, ld, c, nc, eu) : ru[eu];
+        const double v = scale ? x * inv : x;
         r6[threadIdx.x] = v;
-        if (store) store[n3 + 6 * p + threadIdx.x] = v;
+        if (store) store[n3 + eu] = v;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += blockDim.x) {  // t1 = L^-1 r
@@ -309,9 +317,10 @@ int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets,
     hipLaunchKernelGGL(rigid_rhs_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, slip, FT, n3, n6, bv);
     RPYW_HIP(hipGetLastError());
 
-    auto precond = [&](const double* in, const double* scale, double* store, double* outl, double* outu) -> int {
+    auto precond = [&](const double* in, const double* scale, double* store, double* outl, double* outu,
+                       const double* c = nullptr, int nc = 0) -> int {
         hipLaunchKernelGGL(rigid_precond_kernel, dim3(n_bodies), dim3(kRT), 0, st, pc.L, pc.bofs, pc.lofs, Wall, Nall,
-                           n3, in, in + n3, scale, store, outl, outu);
+                           n3, in, in + n3, scale, store, outl, outu, V, n, c, nc);
         RPYW_HIP(hipGetLastError());
         return RPYW_OK;
     };
@@ -327,12 +336,20 @@ int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets,
     if (pre && pre->flag) RPYW_HIP(hipMemcpyAsync(h_bad + 1, pre->flag, sizeof(int), hipMemcpyDeviceToHost, st));
     double beta = 0.0;
 
-    // Arnoldi step k: v_k = (k ? w : b) / d_hn[k], z = P^-1 v_k, w = A z,
-    // two Gram-Schmidt passes, d_hn[k + 1] = |w|; column k of H to the host.
+    // Arnoldi step k: v_k = (k ? z - V c2 : b) / d_hn[k] (the second
+    // correction of step k - 1), z = P^-1 v_k, w = A z, then classical
+    // Gram-Schmidt twice: c1 = V^T w; z = w - V c1 with c2 = V^T z and |z|^2
+    // in the same pass, h_{k+1,k} = |z - V c2| from |z|^2 - |c2|^2 (V
+    // orthonormal) into d_hn[k + 1]; column k of H (c1, c2, h) is stored
+    // into its pinned slot by that pass.
     auto launch_step = [&](int k) -> int {
         double* vk = V + (size_t)k * n;
         int r;
-        if ((r = precond(k == 0 ? bv : w, d_hn + k, vk, z, z + n3))) return r;
+        if (k == 0)
+            r = precond(bv, d_hn, vk, z, z + n3);
+        else  // in place: z -> z
+            r = precond(z, d_hn + k, vk, z, z + n3, d_col + k, k);
+        if (r) return r;
         if ((r = products(pos, z, y, N, 1, a, eta, prec, ar, st, dom))) return r;
         hipLaunchKernelGGL(rigid_apply_kernel, dim3(n_bodies), dim3(kRT), 0, st, pos, q, pc.bofs, z, z + n3, y, w,
                            w + n3);
@@ -340,15 +357,9 @@ int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets,
         double* c1 = d_col;
         double* c2 = d_col + (k + 1);
         if ((r = dots(w, k + 1, c1, 0, nullptr))) return r;
-        // the two updates go w -> z -> w (not in place; z is free again)
-        if ((r = vec_update_dots(w, z, n, nullptr, nullptr, V, n, c1, k + 1, k + 1, partial, ticket, c2, 0, nullptr,
-                                 st)))
-            return r;
-        // the last pass also stores column k (c1, c2, h_{k+1,k}) into its
-        // pinned slot
         double* hs = g_h.dp + (size_t)(k % PinnedSlots::kSlots) * slot;
-        if ((r = vec_update_dots(z, w, n, nullptr, nullptr, V, n, c2, k + 1, 0, partial, ticket, c2 + (k + 1), 0,
-                                 d_hn + k + 1, st, hs, d_col, 2 * (k + 1) + 1)))
+        if ((r = vec_update_dots(w, z, n, nullptr, nullptr, V, n, c1, k + 1, k + 1, partial, ticket, c2, 0,
+                                 d_hn + k + 1, st, hs, d_col, 2 * (k + 1) + 1, true, c2 + (k + 1))))
             return r;
         RPYW_HIP(hipEventRecord(g_h.ev[k % PinnedSlots::kSlots], st));
         return RPYW_OK;

@@ -107,6 +107,22 @@ bool profiling_enabled();
 void profile_begin(hipStream_t st, hipEvent_t* ev);
 void profile_end(hipStream_t st, hipEvent_t ev0, double pairs);
 
+// v[e] - sum_{j < nc} c[j] V[j ld + e], the terms subtracted in order.
+__device__ __forceinline__ double minus_comb(const double* __restrict__ v, const double* __restrict__ V, int64_t ld,
+                                             const double* __restrict__ c, int nc, int64_t e) {
+    double x = v[e];
+    int j = 0;
+    for (; j + 7 < nc; j += 8) {
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = V[(j + u) * ld + e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x -= c[j + u] * a[u];
+    }
+    for (; j < nc; ++j) x -= c[j] * V[j * ld + e];
+    return x;
+}
+
 // Krylov building blocks (krylov.hip).
 // Block-diagonal preconditioner factors: per body the Cholesky factor L_p of
 // its own block M^(pp) (other bodies ignored, wall kept) and L_p^-1; with no
@@ -144,7 +160,8 @@ int body_factors_build(const double* pos, int64_t N, double a, double eta, const
 //           after an event without a separate copy; with_norm (nv > 0)
 //           also puts |w|^2 in out[nv] and, with beta_out, writes
 //           sqrt(|w|^2 - sum_j out[j]^2) there: the norm of w - V out when
-//           the V_j are orthonormal (before the results are copied);
+//           the V_j are orthonormal (before the results are copied; copy_to
+//           then receives this value instead of out[copy_idx]);
 //   comb:   out = sum_{j < nv} c[j] V_j.
 // Asynchronous upload of a small host array (which the caller may free at
 // once) through a library-owned pinned ring.
