@@ -217,11 +217,13 @@ __device__ __forceinline__ PairGrad<R> pair_grad(R dx, R dy, R dz, R zi, R zj, c
     const R r2 = fma_(dz, dz, h2);
     const R rz2 = rz * rz;
     const R R2 = h2 + rz2;
-    const R w = rsq<R>(R2);
+    R w = rsq<R>(R2);
+    R ir = rsq<R>(r2);
+    // both reciprocal square roots issued before either result is used
+    __asm__ volatile("" : "+v"(w), "+v"(ir));
     const R X = w * w;
     const R wX = w * X;
     // free RPY coefficients and their derivatives in r2
-    const R ir = rsq<R>(r2);
     const R ir2 = ir * ir;
     const R ir3 = ir * ir2;
     R c1 = ir * fma_(ir2, R(0.5), R(0.75));
