@@ -84,6 +84,27 @@ def test_non_spd_block_is_reported(rp):
     assert ei.value.status == rp.ENOTSPD
 
 
+@pytest.mark.parametrize("N,bodies", [(1, False), (2, False), (15, True)])
+def test_exhausted_krylov_space(rp, orc, N, bodies):
+    """Tiny problems whose Krylov space is exhausted within a few steps (3N
+    at most; one body with the block preconditioner: the preconditioned
+    operator is the identity, one step): beta reaches zero, which the
+    iteration must detect as convergence and return the exact root."""
+    rng = np.random.default_rng(N)
+    if bodies:
+        pos = wl.boomerang_frame(2.1) + np.array([5.0, 5.0, 3.0])
+        offs = np.array([0, 15], dtype=np.int64)
+    else:
+        pos = np.column_stack([rng.uniform(0, 4, N), rng.uniform(0, 4, N), rng.uniform(1.5, 3.0, N)])
+        offs = None
+    W = wl.gaussian(pos.shape, 9)
+    ref = orc.dense_sqrt(pos, W, offs)
+    out, it, err, ok = rp.lanczos_sqrt(_t(pos), _t(W), body_offsets=offs, tol=1e-12, max_iter=3 * len(pos) + 4)
+    got = out.cpu().numpy()
+    print(f"exhausted N={len(pos)} bodies={bodies} iters={it} rel={_rel(got, ref):.3e}", flush=True)
+    assert ok and it <= 3 * len(pos) and _rel(got, ref) <= 1e-11
+
+
 def test_zero_vector(rp):
     pos, offs = wl.boomerang_suspension(2, 10.0, 1.5, 2.0, seed=7)
     out, it, err, ok = rp.lanczos_sqrt(_t(pos), _t(np.zeros_like(pos)), body_offsets=offs)
