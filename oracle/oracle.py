@@ -82,7 +82,7 @@ def _L():
         lib.oracle_dense_periodic.argtypes = [_dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                               ctypes.c_double, ctypes.c_double, _dp]
         lib.oracle_vjp.argtypes = [_dp, _dp, _dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
-                                   _dp, _dp, ctypes.c_int]
+                                   _dp, _dp, _lp, ctypes.c_int64, ctypes.c_int]
         lib.oracle_divergence.argtypes = [_dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double, _dp,
                                           ctypes.c_int]
         for fn in ("oracle_pair_block", "oracle_matvec", "oracle_dense", "oracle_vjp", "oracle_divergence",
@@ -143,13 +143,17 @@ def dense(pos, a: float = 1.0, eta: float = 1.0, box=None) -> np.ndarray:
     return out
 
 
-def vjp(pos, f, g, a: float = 1.0, eta: float = 1.0, nthreads: int = 0):
-    """(grad_pos, grad_f) of L = sum_i g_i . (M(r) f)_i."""
+def vjp(pos, f, g, a: float = 1.0, eta: float = 1.0, nthreads: int = 0, rows=None):
+    """(grad_pos, grad_f) of L = sum_i g_i . (M(r) f)_i; with ``rows`` only
+    those blobs' gradients (shape (len(rows), 3) each, in the order of rows)."""
     pos, f, g = _c(pos), _c(f), _c(g)
     N = pos.shape[0]
-    gp = np.empty((N, 3))
-    gf = np.empty((N, 3))
-    _L().oracle_vjp(_p(pos), _p(f), _p(g), N, a, eta, _p(gp), _p(gf), nthreads)
+    rp, nr = (None, 0) if rows is None else (_c(rows, np.int64), len(rows))
+    n = N if rows is None else nr
+    gp = np.empty((n, 3))
+    gf = np.empty((n, 3))
+    rptr = None if rp is None else rp.ctypes.data_as(_lp)
+    _L().oracle_vjp(_p(pos), _p(f), _p(g), N, a, eta, _p(gp), _p(gf), rptr, nr, nthreads)
     return gp, gf
 
 

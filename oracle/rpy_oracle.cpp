@@ -293,13 +293,17 @@ void oracle_dense(const double* pos, int64_t N, double a, double eta, double* ou
  * grad_f = M g (M is symmetric).  grad_pos_k = sum_j [g_k^T d1M(r_k, r_j) f_j
  * + f_k^T d1M(r_k, r_j) g_j], with d1 the derivative in the first (target)
  * argument of the full regularised block, taken with dual numbers; the
- * j = k term yields the total derivative of the self block by reciprocity. */
+ * j = k term yields the total derivative of the self block by reciprocity.
+ * rows == NULL: every blob k, outputs [N][3]; otherwise only blobs rows[r],
+ * outputs [nrows][3] in the order of rows. */
 void oracle_vjp(const double* pos, const double* f, const double* g, int64_t N, double a, double eta,
-                double* grad_pos, double* grad_f, int nthreads) {
+                double* grad_pos, double* grad_f, const int64_t* rows, int64_t nrows, int nthreads) {
     const double m0 = mu0(a, eta);
+    const int64_t nr = rows ? nrows : N;
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(static)
-    for (int64_t k = 0; k < N; ++k) {
+    for (int64_t r = 0; r < nr; ++r) {
+        const int64_t k = rows ? rows[r] : r;
         Dual rk[3];
         for (int c = 0; c < 3; ++c) {
             rk[c] = mk(pos[3 * k + c]);
@@ -319,8 +323,8 @@ void oracle_vjp(const double* pos, const double* f, const double* g, int64_t N, 
                 }
         }
         for (int c = 0; c < 3; ++c) {
-            grad_pos[3 * k + c] = m0 * gp[c];
-            grad_f[3 * k + c] = m0 * gf[c];
+            grad_pos[3 * r + c] = m0 * gp[c];
+            grad_f[3 * r + c] = m0 * gf[c];
         }
     }
 }

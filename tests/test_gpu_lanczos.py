@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 
 from paper_1709_02410_amd import workloads as wl
+from parity_util import check
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -34,8 +35,9 @@ def test_small_against_dense_root(rp, orc, bodies):
     ref = orc.dense_sqrt(pos, W, offs)
     out, it, err, ok = rp.lanczos_sqrt(_t(pos), _t(W), body_offsets=offs, tol=1e-10)
     got = out.cpu().numpy()
-    print(f"dense-root bodies={bodies} iters={it} rel={_rel(got, ref):.3e}", flush=True)
-    assert ok and _rel(got, ref) <= 1e-9
+    print(f"dense-root bodies={bodies} iters={it}", flush=True)
+    assert ok
+    check(got, ref, 1e-9, f"lanczos vs dense root bodies={bodies}")
 
 
 def test_boomerangs_3840_tol_1e6(rp, orc):
@@ -51,8 +53,12 @@ def test_boomerangs_3840_tol_1e6(rp, orc):
     print(f"C1 iters gpu={it} oracle={it6} (tol 1e-12: {it12}) rel-same-tol={_rel(got, ref6):.3e} "
           f"rel-converged={_rel(got, ref12):.3e}", flush=True)
     assert ok and ok6 and it == it6
-    assert _rel(got, ref6) <= 1e-9
-    assert _rel(got, ref12) <= 1e-5
+    check(got, ref6, 1e-9, "C1 lanczos vs oracle lanczos, same tolerance")
+    # Truncation error of the tolerance-1e-6 iterate (not a parity figure):
+    # the stopping rule bounds the relative L2 change of the iterate, so the
+    # entry bound is the L2 bound carried to one entry, |e|_inf <= |e|_2.
+    ref_scale = float(np.linalg.norm(ref12) / np.abs(ref12).max())
+    check(got, ref12, 1e-5, "C1 lanczos vs converged oracle root", elem_bar=1e-5 * ref_scale)
 
 
 def test_per_blob_preconditioner_config0(rp, orc):
@@ -60,7 +66,8 @@ def test_per_blob_preconditioner_config0(rp, orc):
     W = wl.gaussian(cfg.pos.shape, 2)
     out, it, err, ok = rp.lanczos_sqrt(_t(cfg.pos), _t(W), tol=1e-8)
     ref, it_o, _, _ = orc.lanczos_sqrt(cfg.pos, W, None, tol=1e-8)
-    assert ok and abs(it - it_o) <= 1 and _rel(out.cpu().numpy(), ref) <= 1e-7
+    assert ok and abs(it - it_o) <= 1
+    check(out.cpu().numpy(), ref, 1e-7, "C0 per-blob preconditioner lanczos")
 
 
 def test_not_converged_returns_best_iterate(rp, orc):
@@ -69,7 +76,7 @@ def test_not_converged_returns_best_iterate(rp, orc):
     out, it, err, ok = rp.lanczos_sqrt(_t(pos), _t(W), body_offsets=offs, tol=1e-14, max_iter=3)
     ref, it_o, _, ok_o = orc.lanczos_sqrt(pos, W, offs, tol=1e-14, max_iter=3)
     assert not ok and not ok_o and it == 3 and it_o == 3
-    assert _rel(out.cpu().numpy(), ref) <= 1e-12
+    check(out.cpu().numpy(), ref, 1e-12, "lanczos best iterate after max_iter")
     with pytest.raises(rp.RpywError):
         rp.lanczos_sqrt(_t(pos), _t(W), body_offsets=offs, tol=1e-14, max_iter=3, strict=True)
 
@@ -101,8 +108,9 @@ def test_exhausted_krylov_space(rp, orc, N, bodies):
     ref = orc.dense_sqrt(pos, W, offs)
     out, it, err, ok = rp.lanczos_sqrt(_t(pos), _t(W), body_offsets=offs, tol=1e-12, max_iter=3 * len(pos) + 4)
     got = out.cpu().numpy()
-    print(f"exhausted N={len(pos)} bodies={bodies} iters={it} rel={_rel(got, ref):.3e}", flush=True)
-    assert ok and it <= 3 * len(pos) and _rel(got, ref) <= 1e-11
+    print(f"exhausted N={len(pos)} bodies={bodies} iters={it}", flush=True)
+    assert ok and it <= 3 * len(pos)
+    check(got, ref, 1e-11, f"exhausted Krylov space N={len(pos)}")
 
 
 def test_zero_vector(rp):
@@ -119,10 +127,9 @@ def test_microrollers_fp32_products(rp):
     pos, w = _t(cfg.pos), _t(W)
     o64, it64, _, ok64 = rp.lanczos_sqrt(pos, w, body_offsets=cfg.body_offsets, tol=1e-6, precision=0)
     o32, it32, _, ok32 = rp.lanczos_sqrt(pos, w, body_offsets=cfg.body_offsets, tol=1e-6, precision=1)
-    rel = float((o32 - o64).norm() / o64.norm())
-    print(f"C2 lanczos iters fp64={it64} fp32c={it32} rel={rel:.3e}", flush=True)
+    print(f"C2 lanczos iters fp64={it64} fp32c={it32}", flush=True)
     assert ok64 and ok32 and abs(it64 - it32) <= 1
-    assert rel <= 1e-5
+    check(o32.cpu().numpy(), o64.cpu().numpy(), 1e-5, "C2 lanczos fp32c vs fp64")
 
 
 def test_iterations_independent_of_size(rp):
@@ -152,12 +159,14 @@ def test_largest_bodies_42_blobs(rp, orc):
     W = wl.gaussian(pos.shape, 21)
     out, it, err, ok = rp.lanczos_sqrt(_t(pos), _t(W), body_offsets=offs, tol=1e-10)
     ref = orc.dense_sqrt(pos, W, offs)
-    assert ok and _rel(out.cpu().numpy(), ref) <= 1e-8
+    assert ok
+    check(out.cpu().numpy(), ref, 1e-8, "42-blob bodies lanczos")
     q = np.array([pos[offs[p]:offs[p + 1]].mean(0) for p in range(3)])
     FT = wl.gaussian((3, 6), 22)
     lam_ref, U_ref = orc.rigid_solve(pos, q, offs, None, FT)
     lam, U, it, res, ok = rp.rigid_solve(_t(pos), _t(q), offs, None, _t(FT), tol=1e-11)
-    assert ok and _rel(U.cpu().numpy(), U_ref) <= 1e-8
+    assert ok
+    check(U.cpu().numpy(), U_ref, 1e-8, "42-blob bodies rigid U")
 
 
 def test_back_to_back_calls_and_two_streams(rp, orc):

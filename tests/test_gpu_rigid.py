@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 from paper_1709_02410_amd import workloads as wl
+from parity_util import check
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -50,10 +51,10 @@ def test_rigid_solve_matches_dense_saddle_point(rp, orc, prec, tol, bound):
     lam_ref, U_ref = orc.rigid_solve(pos, q, offs, slip, FT)
     lam, U, it, res, ok = rp.rigid_solve(_t(pos), _t(q), offs, _t(slip), _t(FT), tol=tol, precision=prec)
     lam, U = lam.cpu().numpy(), U.cpu().numpy()
-    print(f"rigid prec={prec} iters={it} res={res:.2e} rel U={_rel(U, U_ref):.3e} "
-          f"rel lambda={_rel(lam, lam_ref):.3e}", flush=True)
+    print(f"rigid prec={prec} iters={it} res={res:.2e}", flush=True)
     assert ok and res <= tol
-    assert _rel(U, U_ref) <= bound and _rel(lam, lam_ref) <= 10 * bound
+    check(U, U_ref, bound, f"rigid prec={prec} U vs dense solve")
+    check(lam, lam_ref, 10 * bound, f"rigid prec={prec} lambda vs dense solve")
 
 
 def test_iterations_match_oracle_gmres(rp, orc):
@@ -76,7 +77,7 @@ def test_single_body_is_solved_by_the_preconditioner(rp, orc):
     lam_ref, U_ref = orc.rigid_solve(pos, q, offs, None, FT)
     lam, U, it, res, ok = rp.rigid_solve(_t(pos), _t(q), offs, None, _t(FT), tol=1e-12)
     assert ok and it == 1
-    assert _rel(U.cpu().numpy(), U_ref) <= 1e-10
+    check(U.cpu().numpy(), U_ref, 1e-10, "single body U")
 
 
 def test_random_slip_gives_brownian_body_velocities(rp, orc):
@@ -88,8 +89,9 @@ def test_random_slip_gives_brownian_body_velocities(rp, orc):
     slip_ref = orc.dense_sqrt(pos, W, offs)
     _, U_ref = orc.rigid_solve(pos, q, offs, slip_ref, None)
     _, U, it, res, ok = rp.rigid_solve(_t(pos), _t(q), offs, root, None, tol=1e-11)
-    print(f"noise lanczos iters={it_l} gmres iters={it} rel U={_rel(U.cpu().numpy(), U_ref):.3e}", flush=True)
-    assert ok_l and ok and _rel(U.cpu().numpy(), U_ref) <= 1e-7
+    print(f"noise lanczos iters={it_l} gmres iters={it}", flush=True)
+    assert ok_l and ok
+    check(U.cpu().numpy(), U_ref, 1e-7, "random-slip body velocities")
 
 
 def _host_residual(pos, offs, q, lam, U, slip, FT, Mlam):
@@ -105,23 +107,48 @@ def _host_residual(pos, offs, q, lam, U, slip, FT, Mlam):
     return np.sqrt((r1 ** 2).sum() + (r2 ** 2).sum()) / np.sqrt((slip ** 2).sum() + (FT ** 2).sum())
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_boomerangs_3840_true_residual(rp, prec):
-    """256 boomerangs (3840 blobs) at tolerance 1e-6: the true residual,
-    with M lambda from an FP64 product and K, K^T on the host, meets the
-    tolerance up to the product precision; few iterations (Sec. II.B)."""
+@pytest.fixture(scope="module")
+def c1_rigid_case(orc):
+    """256 boomerangs (3840 blobs, config 1), reference points at the corner
+    blobs, random slip and force/torque, and the oracle GMRES at 1e-6 on it
+    (the same algorithm, FP64, about 20 s on the host CPU)."""
     cfg = wl.config1(seed=0)
     offs = cfg.body_offsets
     nb = len(offs) - 1
     q = cfg.pos[offs[:-1]].copy()  # the corner blob of each boomerang
     slip = wl.gaussian(cfg.pos.shape, 9)
     FT = wl.gaussian((nb, 6), 10)
+    _, U_ref, it_ref, res_ref, ok_ref = orc.rigid_gmres(cfg.pos, q, offs, slip, FT, tol=1e-6, max_iter=200)
+    assert ok_ref
+    return cfg, q, slip, FT, U_ref, it_ref
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_boomerangs_3840_true_residual(rp, c1_rigid_case, prec):
+    """256 boomerangs (3840 blobs) at tolerance 1e-6: the true residual,
+    with M lambda from an FP64 product and K, K^T on the host, meets the
+    tolerance up to the product precision, and the iteration count is the
+    oracle GMRES's on the same system.  The random placement overlaps bodies
+    heavily (closest blobs 0.16 a apart), which makes this system far worse
+    conditioned than the paper's suspensions: the oracle itself needs 89
+    iterations.  FP64: the same count +-1 (rounding at the threshold).
+    FP32C: the products differ from FP64 ones by about 3e-7 relative, close
+    to the tolerance, so the residual history near the threshold moves and
+    the count may differ by a few (+-5%, at least 2)."""
+    cfg, q, slip, FT, U_ref, it_ref = c1_rigid_case
+    offs = cfg.body_offsets
     lam, U, it, res, ok = rp.rigid_solve(_t(cfg.pos), _t(q), offs, _t(slip), _t(FT), tol=1e-6, precision=prec)
     Mlam = rp.matvec(_t(cfg.pos), lam, precision=0).cpu().numpy()
     true_res = _host_residual(cfg.pos, offs, q, lam.cpu().numpy(), U.cpu().numpy(), slip, FT, Mlam)
-    print(f"C1 rigid prec={prec} iters={it} est={res:.2e} true={true_res:.2e}", flush=True)
-    assert ok and it <= 150  # random placement with overlapping bodies: ill-conditioned
+    print(f"C1 rigid prec={prec} iters={it} (oracle {it_ref}) est={res:.2e} true={true_res:.2e} "
+          f"rel U vs oracle={_rel(U.cpu().numpy(), U_ref):.2e}", flush=True)
+    assert ok
+    assert abs(it - it_ref) <= (1 if prec == 0 else max(2, it_ref // 20))
     assert true_res <= (2e-6 if prec == 0 else 1e-5)
+    # Same algorithm, same stopping step: the FP64 iterate is the oracle's
+    # up to rounding; the FP32C one differs by the product rounding carried
+    # through 89 Krylov steps (observed 1.7e-6).
+    check(U.cpu().numpy(), U_ref, 1e-10 if prec == 0 else 2e-5, f"C1 rigid prec={prec} U vs oracle GMRES")
 
 
 def test_paperlike_boomerangs_iteration_counts(rp, orc):

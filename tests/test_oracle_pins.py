@@ -329,6 +329,20 @@ def test_vjp_matches_central_differences(orc):
         assert abs(fd - gp[k, c]) <= 1e-7 * max(1.0, np.abs(gp).max())
 
 
+def test_vjp_selected_rows(orc):
+    """The row selection of the VJP (used to check large GPU runs on sampled
+    blobs) returns exactly the selected blobs' gradients, in the order asked,
+    and the grad_f rows equal the product's rows (grad_f = M g)."""
+    pos = _mixed_positions(60, 5)
+    f = wl.gaussian(pos.shape, 6)
+    g = wl.gaussian(pos.shape, 7)
+    gp, gf = orc.vjp(pos, f, g)
+    rows = np.array([59, 0, 17, 17, 33])
+    gpr, gfr = orc.vjp(pos, f, g, rows=rows)
+    assert np.array_equal(gpr, gp[rows]) and np.array_equal(gfr, gf[rows])
+    assert np.abs(gfr - orc.matvec(pos, g, rows=rows)).max() <= 1e-15 * 60
+
+
 @pytest.mark.parametrize("t", [1.2, 1.5, 2.0, 3.7])
 def test_single_blob_divergence_closed_form(orc, t):
     """One blob above the wall: div M = mu0/a (0, 0, d mu_perp/dt), i.e.
