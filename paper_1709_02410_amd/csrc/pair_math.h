@@ -42,6 +42,14 @@ __device__ __forceinline__ double rint_(double x) { return __builtin_rint(x); }
 template <typename R>
 __device__ __forceinline__ R rsq(R x);
 
+// An empty asm statement that takes both values as inputs and outputs: every
+// use of either is scheduled after both are computed (used to issue two
+// reciprocal square roots back to back, so that their latencies overlap).
+template <typename R>
+__device__ __forceinline__ void issue_together(R& a, R& b) {
+    __asm__ volatile("" : "+v"(a), "+v"(b));
+}
+
 // FP32: the hardware reciprocal square root (about 1 ulp).
 template <>
 __device__ __forceinline__ float rsq<float>(float x) {
@@ -219,8 +227,7 @@ __device__ __forceinline__ PairGrad<R> pair_grad(R dx, R dy, R dz, R zi, R zj, c
     const R R2 = h2 + rz2;
     R w = rsq<R>(R2);
     R ir = rsq<R>(r2);
-    // both reciprocal square roots issued before either result is used
-    __asm__ volatile("" : "+v"(w), "+v"(ir));
+    issue_together(w, ir);
     const R X = w * w;
     const R wX = w * X;
     // free RPY coefficients and their derivatives in r2
