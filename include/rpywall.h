@@ -72,6 +72,28 @@ enum rpyw_op {
 int rpy_wall_matvec(const double* pos, const double* force, double* vel, int64_t N, double a, double eta,
                     int precision, void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the same product as
+ * rpy_wall_matvec (same kernels, launch shapes and results), with its
+ * scratch memory in a fixed device array of rpy_wall_noalloc_scratch_bytes()
+ * bytes (32 MiB) that the library holds on every GPU it runs on until the
+ * process ends.  No allocation of any kind happens in the call.  N is
+ * limited to problems whose workspace (rpy_wall_workspace_bytes with
+ * RPYW_OP_MATVEC, k = 1, which is exact) fits that array: every N up to
+ * 4096 blobs fits in both precisions (and many larger sizes, depending on
+ * the launch plan); a larger workspace returns RPYW_ENOMEM and launches
+ * nothing.  Every call on
+ * one GPU shares that GPU's array, so calls that overlap in time on one GPU
+ * (different streams, threads or processes' streams not ordered by the
+ * caller) race and must be ordered by the caller; the array keeps the last
+ * call's contents, none of which a later call reads.  Arguments as for
+ * rpy_wall_matvec. */
+int rpy_wall_matvec_noalloc(const double* pos, const double* force, double* vel, int64_t N, double a, double eta,
+                            int precision, void* stream);
+
+/* Size of the fixed scratch array of rpy_wall_matvec_noalloc (host call). */
+size_t rpy_wall_noalloc_scratch_bytes(void);
+
 /* U_l = M(r) F_l for k right-hand sides sharing one geometry (one time step
  * needs M f, random-finite-difference probes and Lanczos vectors, Sec. III).
  * F, U: device [k][N][3].  Each pair's 3x3 block is evaluated once per RHS

@@ -46,6 +46,30 @@ int acquire(void* ws, size_t ws_bytes, size_t need, hipStream_t st, Scratch& s) 
     return RPYW_OK;
 }
 
+// ---------------------------------------------------------- fixed scratch
+// Workspace of rpy_wall_matvec_noalloc: a file-scope device array, one copy
+// per GPU, held until the process ends.  Host code uses its device address
+// from hipGetSymbolAddress (taken once per device, with that device
+// current), never the array's name.
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array, or nullptr.
+void* scratch_address() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
 // ---------------------------------------------------------- shape table
 std::mutex g_shape_mu;
 std::map<std::tuple<int, int, int>, Shape> g_shapes;
@@ -199,6 +223,20 @@ int rpy_wall_matvec_periodic(const double* pos, const double* F, double* U, int6
 int rpy_wall_matvec(const double* pos, const double* force, double* vel, int64_t N, double a, double eta,
                     int precision, void* ws, size_t ws_bytes, void* stream) {
     return rpy_wall_matvec_multi(pos, force, vel, N, 1, a, eta, precision, ws, ws_bytes, stream);
+}
+
+size_t rpy_wall_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+int rpy_wall_matvec_noalloc(const double* pos, const double* force, double* vel, int64_t N, double a, double eta,
+                            int precision, void* stream) {
+    if (!pos || !force || !vel || N < 1 || N >= kMaxN || !finite_pos(a) || !finite_pos(eta) ||
+        !valid_prec(precision))
+        return RPYW_EINVAL;
+    if (product_ws_bytes(N, precision, 1) > kScratchBytes) return RPYW_ENOMEM;
+    void* p = scratch_address();
+    if (!p) return RPYW_EHIP;
+    Arena ar{(char*)p, kScratchBytes, 0};
+    return products(pos, force, vel, N, 1, a, eta, precision, ar, (hipStream_t)stream);
 }
 
 int rpy_wall_matvec_batched(const double* pos, const int64_t* sys_offsets, int32_t S, const double* F, double* U,

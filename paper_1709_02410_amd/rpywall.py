@@ -45,6 +45,7 @@ def lib():
     sig = {
         "rpy_wall_matvec": [vp, vp, vp, i64, dbl, dbl, ctypes.c_int, vp, sz, vp],
         "rpy_wall_matvec_multi": [vp, vp, vp, i64, i32, dbl, dbl, ctypes.c_int, vp, sz, vp],
+        "rpy_wall_matvec_noalloc": [vp, vp, vp, i64, dbl, dbl, ctypes.c_int, vp],
         "rpy_wall_matvec_periodic": [vp, vp, vp, i64, i32, dbl, dbl, dbl, dbl, ctypes.c_int, vp, sz, vp],
         "rpy_wall_lanczos_sqrt_periodic": [vp, vp, vp, i64, dbl, dbl, dbl, dbl, i64p, i32, dbl, i32, ctypes.c_int,
                                            vp, sz, ctypes.POINTER(i32), ctypes.POINTER(dbl), vp],
@@ -78,6 +79,8 @@ def lib():
         fn = getattr(L, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
+    L.rpy_wall_noalloc_scratch_bytes.argtypes = []
+    L.rpy_wall_noalloc_scratch_bytes.restype = sz
     L.rpy_wall_ts_state_bytes.argtypes = [i64, i32]
     L.rpy_wall_ts_state_bytes.restype = sz
     L.rpy_wall_workspace_bytes.argtypes = [ctypes.c_int, i64, i32, i32, i32, ctypes.c_int]
@@ -130,6 +133,19 @@ def matvec(pos: torch.Tensor, force: torch.Tensor, a: float = 1.0, eta: float = 
     ws = _workspace(workspace_bytes(OP_MATVEC, N, 1, precision=precision), pos.device)
     _check(lib().rpy_wall_matvec(pos.data_ptr(), force.data_ptr(), out.data_ptr(), N, a, eta, precision,
                                  ws.data_ptr(), ws.numel(), _stream(pos.device)), "rpy_wall_matvec")
+    return out
+
+
+def matvec_noalloc(pos: torch.Tensor, force: torch.Tensor, a: float = 1.0, eta: float = 1.0,
+                   precision: int = FP64, out: torch.Tensor | None = None) -> torch.Tensor:
+    """u = M(r) f through the entry point that allocates nothing (its
+    workspace is a fixed device array in the library; small N only)."""
+    N = pos.shape[0]
+    _dev(pos, "pos", (N, 3))
+    _dev(force, "force", (N, 3))
+    out = torch.empty_like(force) if out is None else _dev(out, "out", (N, 3))
+    _check(lib().rpy_wall_matvec_noalloc(pos.data_ptr(), force.data_ptr(), out.data_ptr(), N, a, eta, precision,
+                                         _stream(pos.device)), "rpy_wall_matvec_noalloc")
     return out
 
 

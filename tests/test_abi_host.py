@@ -39,6 +39,26 @@ def test_every_declared_symbol_is_exported(lib):
         assert hasattr(lib, n)
 
 
+def test_noalloc_entry_rejects_before_any_gpu_work(lib):
+    """The no-allocation product validates on the host like rpy_wall_matvec
+    and refuses problems whose workspace exceeds its fixed scratch array
+    (RPYW_ENOMEM) before touching the GPU."""
+    dummy = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    cap = lib.rpy_wall_noalloc_scratch_bytes()
+    assert cap == 32 << 20
+    E = rpywall.EINVAL
+    assert lib.rpy_wall_matvec_noalloc(None, dummy, dummy, 10, 1.0, 1.0, 0, None) == E
+    assert lib.rpy_wall_matvec_noalloc(dummy, dummy, dummy, 0, 1.0, 1.0, 0, None) == E
+    assert lib.rpy_wall_matvec_noalloc(dummy, dummy, dummy, 10, -1.0, 1.0, 0, None) == E
+    assert lib.rpy_wall_matvec_noalloc(dummy, dummy, dummy, 10, 1.0, 1.0, 5, None) == E
+    for prec in (0, 1):
+        # the largest N whose product workspace fits, and the refusal above it
+        for n in (1, 1000, 3840, 4096):
+            assert rpywall.workspace_bytes(rpywall.OP_MATVEC, n, 1, precision=prec) <= cap
+        assert rpywall.workspace_bytes(rpywall.OP_MATVEC, 20000, 1, precision=prec) > cap
+        assert lib.rpy_wall_matvec_noalloc(dummy, dummy, dummy, 20000, 1.0, 1.0, prec, None) == rpywall.ENOMEM
+
+
 def test_validation_rejects_before_any_launch(lib):
     E = rpywall.EINVAL
     dummy = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
