@@ -36,13 +36,17 @@ PinnedSlots g_ab;
 
 // ---------------------------------------------------- tridiagonal (host)
 
-// Implicit symmetric QL with Wilkinson shifts on T = tridiag(e, d, e)
-// (Golub & Van Loan, Sec. 8.3).  The eigenvector matrix is the product
-// Z = G_1 G_2 ... G_M of the plane rotations the sweeps apply; only
-// Z^T e1 (its first row) and products Z v are needed, so the rotations are
-// recorded and the first row is tracked instead of accumulating Z: O(k^2)
-// work per solve instead of O(k^3).  Returns false if an eigenvalue needs
-// more than 60 sweeps.
+// Eigen-decomposition T = Z Lambda Z^T of the symmetric tridiagonal
+// T = tridiag(e, d, e) (d: diagonal, e[i] = T(i, i+1)) by the implicit
+// symmetric QR algorithm with Wilkinson shifts (Golub & Van Loan, Sec. 8.3:
+// the implicit shifted QR step, Alg. 8.3.2, inside the deflating driver of
+// Alg. 8.3.3).  Each step chases a bulge down the trailing unreduced block
+// with plane rotations T <- Q^T T Q, Q = [[c, -s], [s, c]] on rows and
+// columns (i, i+1); Z is the product of all the Q's.  Only Z^T e1 (the first
+// row of Z) and one product Z v are needed, so the rotations are recorded
+// and the first row is updated as they are made, instead of accumulating Z:
+// O(k^2) work per solve instead of O(k^3).  Returns false if the driver
+// needs more than 30 k steps.
 struct Rot {
     int i;
     double c, s;
@@ -52,57 +56,53 @@ struct Rot {
 // preconditioned mobility), far from overflow, so no rescaling is needed.
 static inline double pyth(double a, double b) { return std::sqrt(a * a + b * b); }
 
-static bool tridiag_ql(std::vector<double>& d, std::vector<double>& e, std::vector<double>& row0,
-                       std::vector<Rot>& rots, int k) {
+// Whether e[i] is negligible next to its two diagonal neighbours.
+static inline bool negligible(const std::vector<double>& d, const std::vector<double>& e, int i) {
+    return std::fabs(e[i]) <= 1e-16 * (std::fabs(d[i]) + std::fabs(d[i + 1]));
+}
+
+static bool tridiag_eig(std::vector<double>& d, std::vector<double>& e, std::vector<double>& row0,
+                        std::vector<Rot>& rots, int k) {
     row0.assign(k, 0.0);
     row0[0] = 1.0;
     rots.clear();
-    if (k == 1) return true;
     e.resize(k);
-    e[k - 1] = 0.0;
-    for (int l = 0; l < k; ++l) {
-        int iter = 0;
-        for (;;) {
-            int m = l;
-            for (; m < k - 1; ++m) {
-                const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
-                if (std::fabs(e[m]) <= 1e-16 * dd) break;
+    int steps = 0;
+    int hi = k - 1;  // last row of the trailing block that is not yet diagonal
+    while (hi > 0) {
+        if (negligible(d, e, hi - 1)) {
+            e[hi - 1] = 0.0;
+            --hi;
+            continue;
+        }
+        int lo = hi - 1;  // first row of the unreduced block that ends at hi
+        while (lo > 0 && !negligible(d, e, lo - 1)) --lo;
+        if (++steps > 30 * k) return false;
+        // Wilkinson shift: the eigenvalue of the trailing 2 x 2 block closer
+        // to its last diagonal entry.
+        const double half = 0.5 * (d[hi - 1] - d[hi]);
+        const double b2 = e[hi - 1] * e[hi - 1];
+        const double mu = d[hi] - b2 / (half + (half >= 0.0 ? 1.0 : -1.0) * pyth(half, e[hi - 1]));
+        // Implicit QR step: the first rotation acts on (d[lo] - mu, e[lo]);
+        // every later one removes the bulge T(i - 1, i + 1) it left behind.
+        double x = d[lo] - mu, z = e[lo];
+        for (int i = lo; i < hi; ++i) {
+            const double r = pyth(x, z);
+            const double c = r > 0.0 ? x / r : 1.0, s = r > 0.0 ? z / r : 0.0;
+            if (i > lo) e[i - 1] = r;
+            const double a = d[i], b = e[i], dd = d[i + 1];
+            d[i] = c * c * a + 2.0 * c * s * b + s * s * dd;
+            d[i + 1] = s * s * a - 2.0 * c * s * b + c * c * dd;
+            e[i] = (c * c - s * s) * b + c * s * (dd - a);
+            if (i + 1 < hi) {
+                z = s * e[i + 1];  // new bulge T(i, i + 2)
+                e[i + 1] *= c;
+                x = e[i];
             }
-            if (m == l) break;
-            if (++iter > 60) return false;
-            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-            double r = pyth(g, 1.0);
-            g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
-            double s = 1.0, c = 1.0, p = 0.0;
-            bool deflated = false;
-            for (int i = m - 1; i >= l; --i) {
-                double f = s * e[i];
-                const double b = c * e[i];
-                r = pyth(f, g);
-                e[i + 1] = r;
-                if (r == 0.0) {
-                    d[i + 1] -= p;
-                    e[m] = 0.0;
-                    deflated = true;
-                    break;
-                }
-                s = f / r;
-                c = g / r;
-                g = d[i + 1] - p;
-                r = (d[i] - g) * s + 2.0 * c * b;
-                p = s * r;
-                d[i + 1] = g + p;
-                g = c * r - b;
-                // Z <- Z G with G = [[c, s], [-s, c]] on columns (i, i+1)
-                rots.push_back({i, c, s});
-                const double zi = row0[i], zi1 = row0[i + 1];
-                row0[i + 1] = s * zi + c * zi1;
-                row0[i] = c * zi - s * zi1;
-            }
-            if (deflated) continue;
-            d[l] -= p;
-            e[l] = g;
-            e[m] = 0.0;
+            rots.push_back({i, c, s});
+            const double zi = row0[i], zi1 = row0[i + 1];
+            row0[i] = c * zi + s * zi1;
+            row0[i + 1] = c * zi1 - s * zi;
         }
     }
     return true;
@@ -112,14 +112,14 @@ int tridiag_sqrt_coeffs(const double* alpha, const double* beta, int k, double b
     std::vector<double> d(alpha, alpha + k), e(k, 0.0), row0;
     std::vector<Rot> rots;
     for (int i = 0; i + 1 < k; ++i) e[i] = beta[i];
-    if (!tridiag_ql(d, e, row0, rots, k)) return RPYW_NOT_CONVERGED;
-    // c = beta0 Z (Lambda^{1/2} Z^T e1) = beta0 G_1 (G_2 (... (G_M v)))
+    if (!tridiag_eig(d, e, row0, rots, k)) return RPYW_NOT_CONVERGED;
+    // c = beta0 Z (Lambda^{1/2} Z^T e1) = beta0 Q_1 (Q_2 (... (Q_M v)))
     for (int i = 0; i < k; ++i) c[i] = beta0 * std::sqrt(std::max(d[i], 0.0)) * row0[i];
     for (size_t t = rots.size(); t-- > 0;) {
         const Rot& g = rots[t];
         const double vi = c[g.i], vi1 = c[g.i + 1];
-        c[g.i] = g.c * vi + g.s * vi1;
-        c[g.i + 1] = -g.s * vi + g.c * vi1;
+        c[g.i] = g.c * vi - g.s * vi1;
+        c[g.i + 1] = g.s * vi + g.c * vi1;
     }
     return RPYW_OK;
 }

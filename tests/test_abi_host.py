@@ -138,7 +138,7 @@ def test_workspace_sizes(lib):
 
 @pytest.mark.parametrize("k", [1, 2, 5, 30, 120])
 def test_tridiagonal_root_coefficients(lib, k):
-    """beta0 Q Lambda^{1/2} Q^T e1 from the host QL solver against numpy."""
+    """beta0 Q Lambda^{1/2} Q^T e1 from the host implicit QR solver against numpy."""
     rng = np.random.default_rng(k)
     alpha = rng.uniform(0.5, 2.0, k)
     beta = rng.uniform(0.01, 0.4, max(k - 1, 0))
@@ -147,6 +147,51 @@ def test_tridiagonal_root_coefficients(lib, k):
     ref = 1.7 * Q @ (np.sqrt(np.clip(lam, 0, None)) * Q[0])
     got = rpywall.tridiag_sqrt_coeffs(alpha, beta, 1.7)
     assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("case", ["split", "clustered", "graded", "lanczos_like", "tiny_offdiag"])
+def test_tridiagonal_root_structured(lib, case):
+    """The implicit QR solver on matrices that exercise deflation and
+    shifts: a zero off-diagonal in the middle, clustered and graded
+    eigenvalues, the tridiagonal of a Lanczos run on an SPD matrix, and
+    off-diagonals at rounding level."""
+    rng = np.random.default_rng(7)
+    k = 60
+    if case == "split":
+        alpha = rng.uniform(0.5, 2.0, k)
+        beta = rng.uniform(0.01, 0.4, k - 1)
+        beta[k // 2] = 0.0
+    elif case == "clustered":
+        alpha = 1.0 + 1e-9 * rng.standard_normal(k)
+        beta = 1e-7 * rng.uniform(0.5, 1.0, k - 1)
+    elif case == "graded":
+        alpha = np.logspace(0, -6, k)
+        beta = 0.3 * np.sqrt(alpha[:-1] * alpha[1:])
+    elif case == "lanczos_like":
+        A = rng.standard_normal((200, 200))
+        A = A @ A.T / 200 + 0.1 * np.eye(200)
+        v = rng.standard_normal(200)
+        V = [v / np.linalg.norm(v)]
+        alpha, beta = [], []
+        for j in range(k):
+            w = A @ V[-1]
+            alpha.append(V[-1] @ w)
+            for u in V:
+                w -= (u @ w) * u
+            for u in V:
+                w -= (u @ w) * u
+            if j < k - 1:
+                beta.append(np.linalg.norm(w))
+                V.append(w / beta[-1])
+        alpha, beta = np.array(alpha), np.array(beta)
+    else:
+        alpha = rng.uniform(0.5, 2.0, k)
+        beta = 1e-17 * rng.uniform(0.5, 1.0, k - 1)
+    T = np.diag(alpha) + np.diag(beta, 1) + np.diag(beta, -1)
+    lam, Q = np.linalg.eigh(T)
+    ref = 1.3 * Q @ (np.sqrt(np.clip(lam, 0, None)) * Q[0])
+    got = rpywall.tridiag_sqrt_coeffs(alpha, beta, 1.3)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), case
 
 
 def test_tridiagonal_root_clamps_negative_eigenvalues(lib):
