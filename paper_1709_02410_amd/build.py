@@ -16,7 +16,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librpywall.so")
-SOURCES = ["api.hip", "pair_kernels.hip", "krylov.hip", "lanczos.hip", "rigid.hip", "ts.hip", "vjp.hip"]
+SOURCES = ["api.hip", "pair_kernels.hip", "krylov.hip", "lanczos.hip", "rigid.hip", "ts.hip", "vjp.hip",
+           "settings.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -115,24 +115,84 @@ Shape default_shape(int64_t N, int k, int prec) {
     return s;
 }
 
+namespace {
+// Persisted shapes: loaded once (under g_shape_mu) from RPYW_AUTOTUNE_CACHE;
+// entries of other GPU architectures are kept for the rewrite.
+bool g_cache_loaded = false;
+std::vector<CachedShape> g_foreign;
+
+void load_cache_locked() {
+    if (g_cache_loaded) return;
+    g_cache_loaded = true;
+    const char* path = autotune_cache_path();
+    if (!path) return;
+    std::vector<CachedShape> entries;
+    if (read_shape_cache(path, entries) != 0) {
+        log_line("autotune cache %s not read (missing or unparsable)", path);
+        return;
+    }
+    const std::string arch = device_arch();
+    int used = 0;
+    for (const CachedShape& c : entries) {
+        if (c.arch != arch) {
+            g_foreign.push_back(c);
+            continue;
+        }
+        const auto key = std::make_tuple(c.prec, c.size_class, c.kclass);
+        if (!g_shapes.count(key)) {
+            g_shapes[key] = c.s;
+            ++used;
+        }
+    }
+    log_line("autotune cache %s: %d shapes for %s", path, used, arch.c_str());
+}
+
+void save_cache_locked() {
+    const char* path = autotune_cache_path();
+    if (!path) return;
+    std::vector<CachedShape> out = g_foreign;
+    const std::string arch = device_arch();
+    for (const auto& kv : g_shapes) {
+        CachedShape c;
+        c.arch = arch;
+        c.prec = std::get<0>(kv.first);
+        c.size_class = std::get<1>(kv.first);
+        c.kclass = std::get<2>(kv.first);
+        c.s = kv.second;
+        out.push_back(c);
+    }
+    if (write_shape_cache(path, out) != 0) log_line("autotune cache %s not written", path);
+}
+}  // namespace
+
 Shape tuned_shape(int64_t N, int k, int prec) {
     std::lock_guard<std::mutex> lk(g_shape_mu);
+    load_cache_locked();
     auto it = g_shapes.find({prec, size_class(N), kclass(k)});
-    if (it != g_shapes.end()) return it->second;
-    return default_shape(N, k, prec);
+    return apply_env_overrides(it != g_shapes.end() ? it->second : default_shape(N, k, prec));
 }
 
 void set_tuned_shape(int64_t N, int k, int prec, Shape s) {
     std::lock_guard<std::mutex> lk(g_shape_mu);
+    load_cache_locked();
     g_shapes[{prec, size_class(N), kclass(k)}] = s;
 }
 
 void clear_tuned_shape(int64_t N, int k, int prec) {
     std::lock_guard<std::mutex> lk(g_shape_mu);
+    load_cache_locked();
     g_shapes.erase({prec, size_class(N), kclass(k)});
 }
 
 bool profiling_enabled() { return g_prof; }
+
+// One log line for a product-type call: sizes, precision, the launch shape
+// its products use, and the status.
+void log_shape(const char* fn, int64_t N, int k, int prec, int rc) {
+    const Shape sh = tuned_shape(N, k, prec);
+    log_line("%s N=%lld k=%d prec=%d shape tpl=%d tile=%d kblk=%d sym=%d ipw=%d status=%d", fn, (long long)N, k, prec,
+             sh.tpl, sh.tile, sh.kblk, sh.sym, sh.ipw, rc);
+}
 
 void profile_begin(hipStream_t st, hipEvent_t* ev) {
     *ev = nullptr;
@@ -203,8 +263,9 @@ int rpy_wall_matvec_multi(const double* pos, const double* F, double* U, int64_t
     hipStream_t st = (hipStream_t)stream;
     Scratch s;
     int rc = acquire(ws, ws_bytes, product_ws_bytes(N, precision, std::min(kclass(k), 16)), st, s);
-    if (rc != RPYW_OK) return rc;
-    return products(pos, F, U, N, k, a, eta, precision, s.ar, st);
+    if (rc == RPYW_OK) rc = products(pos, F, U, N, k, a, eta, precision, s.ar, st);
+    if (log_enabled()) log_shape("rpy_wall_matvec_multi", N, k, precision, rc);
+    return rc;
 }
 
 int rpy_wall_matvec_periodic(const double* pos, const double* F, double* U, int64_t N, int32_t k, double a,
@@ -216,8 +277,9 @@ int rpy_wall_matvec_periodic(const double* pos, const double* F, double* U, int6
     hipStream_t st = (hipStream_t)stream;
     Scratch s;
     int rc = acquire(ws, ws_bytes, product_ws_bytes(N, precision, 1), st, s);
-    if (rc != RPYW_OK) return rc;
-    return products(pos, F, U, N, k, a, eta, precision, s.ar, st, Domain{Lx, Ly});
+    if (rc == RPYW_OK) rc = products(pos, F, U, N, k, a, eta, precision, s.ar, st, Domain{Lx, Ly});
+    if (log_enabled()) log_shape("rpy_wall_matvec_periodic", N, k, precision, rc);
+    return rc;
 }
 
 int rpy_wall_matvec(const double* pos, const double* force, double* vel, int64_t N, double a, double eta,
@@ -232,11 +294,17 @@ int rpy_wall_matvec_noalloc(const double* pos, const double* force, double* vel,
     if (!pos || !force || !vel || N < 1 || N >= kMaxN || !finite_pos(a) || !finite_pos(eta) ||
         !valid_prec(precision))
         return RPYW_EINVAL;
-    if (product_ws_bytes(N, precision, 1) > kScratchBytes) return RPYW_ENOMEM;
+    if (product_ws_bytes(N, precision, 1) > kScratchBytes) {
+        log_line("rpy_wall_matvec_noalloc N=%lld: workspace %zu B exceeds the fixed scratch (%zu B)", (long long)N,
+                 product_ws_bytes(N, precision, 1), kScratchBytes);
+        return RPYW_ENOMEM;
+    }
     void* p = scratch_address();
     if (!p) return RPYW_EHIP;
     Arena ar{(char*)p, kScratchBytes, 0};
-    return products(pos, force, vel, N, 1, a, eta, precision, ar, (hipStream_t)stream);
+    const int rc = products(pos, force, vel, N, 1, a, eta, precision, ar, (hipStream_t)stream);
+    if (log_enabled()) log_shape("rpy_wall_matvec_noalloc", N, 1, precision, rc);
+    return rc;
 }
 
 int rpy_wall_matvec_batched(const double* pos, const int64_t* sys_offsets, int32_t S, const double* F, double* U,
@@ -253,8 +321,9 @@ int rpy_wall_matvec_batched(const double* pos, const int64_t* sys_offsets, int32
     hipStream_t st = (hipStream_t)stream;
     Scratch s;
     int rc = acquire(ws, ws_bytes, batched_ws_bytes(Ntot, S, k, precision), st, s);
-    if (rc != RPYW_OK) return rc;
-    return batched_products(pos, sys_offsets, S, F, U, k, a, eta, precision, s.ar, st);
+    if (rc == RPYW_OK) rc = batched_products(pos, sys_offsets, S, F, U, k, a, eta, precision, s.ar, st);
+    log_line("rpy_wall_matvec_batched S=%d Ntot=%lld k=%d prec=%d status=%d", S, (long long)Ntot, k, precision, rc);
+    return rc;
 }
 
 static int lanczos_api(const double* pos, const double* W, double* out, int64_t N, double a, double eta,
@@ -283,6 +352,8 @@ static int lanczos_api(const double* pos, const double* W, double* out, int64_t 
                       dom);
     if (iters_out) *iters_out = it;
     if (err_est_out) *err_est_out = err;
+    log_line("rpy_wall_lanczos_sqrt%s N=%lld bodies=%d prec=%d tol=%g iterations=%d change=%.3e status=%d",
+             dom.periodic() ? "_periodic" : "", (long long)N, n_bodies, precision, tol, it, err, rc);
     return rc;
 }
 
@@ -325,6 +396,8 @@ static int rigid_api(const double* pos, const double* q, const int64_t* body_off
                      precision, s.ar, &it, &res, st, dom);
     if (iters_out) *iters_out = it;
     if (res_out) *res_out = res;
+    log_line("rpy_wall_rigid_solve%s N=%lld bodies=%d prec=%d tol=%g iterations=%d residual=%.3e status=%d",
+             dom.periodic() ? "_periodic" : "", (long long)N, n_bodies, precision, tol, it, res, rc);
     return rc;
 }
 
@@ -489,8 +562,9 @@ int rpy_wall_matvec_vjp(const double* pos, const double* force, const double* gr
     hipStream_t st = (hipStream_t)stream;
     Scratch s;
     int rc = acquire(ws, ws_bytes, vjp_ws_bytes(N, precision), st, s);
-    if (rc != RPYW_OK) return rc;
-    return vjp(pos, force, grad_vel, grad_pos, grad_force, N, a, eta, precision, s.ar, st);
+    if (rc == RPYW_OK) rc = vjp(pos, force, grad_vel, grad_pos, grad_force, N, a, eta, precision, s.ar, st);
+    if (log_enabled()) log_shape("rpy_wall_matvec_vjp", N, 1, precision, rc);
+    return rc;
 }
 
 int rpy_wall_divergence(const double* pos, double* div, int64_t N, double a, double eta, int precision, void* ws,
@@ -500,8 +574,9 @@ int rpy_wall_divergence(const double* pos, double* div, int64_t N, double a, dou
     hipStream_t st = (hipStream_t)stream;
     Scratch s;
     int rc = acquire(ws, ws_bytes, vjp_ws_bytes(N, precision), st, s);
-    if (rc != RPYW_OK) return rc;
-    return divergence(pos, div, N, a, eta, precision, s.ar, st);
+    if (rc == RPYW_OK) rc = divergence(pos, div, N, a, eta, precision, s.ar, st);
+    log_line("rpy_wall_divergence N=%lld prec=%d status=%d", (long long)N, precision, rc);
+    return rc;
 }
 
 int rpy_wall_autotune(const double* pos, const double* F, double* U, int64_t N, int32_t k, double a, double eta,
@@ -571,6 +646,12 @@ int rpy_wall_autotune(const double* pos, const double* F, double* U, int64_t N, 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     set_tuned_shape(N, k, precision, best);
+    {
+        std::lock_guard<std::mutex> lk(g_shape_mu);
+        save_cache_locked();
+    }
+    log_line("rpy_wall_autotune N=%lld k=%d prec=%d -> tpl=%d tile=%d kblk=%d sym=%d ipw=%d (%.4f ms)", (long long)N,
+             k, precision, best.tpl, best.tile, best.kblk, best.sym, best.ipw, best_t / 2.0);
     return RPYW_OK;
 }
 

@@ -8,6 +8,8 @@
 #include <cstddef>
 #include <cstdint>
 #include <mutex>
+#include <string>
+#include <vector>
 
 #include "../../include/rpywall.h"
 
@@ -98,9 +100,27 @@ int batched_products(const double* pos, const int64_t* sys_offsets, int S, const
 
 // Shape selection.
 Shape default_shape(int64_t N, int k, int prec);
+// The launch shape products of N blobs and k right-hand sides use: the
+// tuned one for this (precision, size class, RHS class) if any, else the
+// built-in default; then the RPYW_TILE / RPYW_RHS_WIDTH overrides.
 Shape tuned_shape(int64_t N, int k, int prec);
 void set_tuned_shape(int64_t N, int k, int prec, Shape s);
 void clear_tuned_shape(int64_t N, int k, int prec);
+
+// Run-time settings (settings.hip): RPYW_LOG, RPYW_TILE, RPYW_RHS_WIDTH and
+// the persisted shape cache RPYW_AUTOTUNE_CACHE.
+struct CachedShape {
+    std::string arch;
+    int prec = 0, size_class = 0, kclass = 0;
+    Shape s{};
+};
+bool log_enabled();
+void log_line(const char* fmt, ...);
+Shape apply_env_overrides(Shape s);
+const char* autotune_cache_path();
+std::string device_arch();
+int read_shape_cache(const char* path, std::vector<CachedShape>& out);
+int write_shape_cache(const char* path, const std::vector<CachedShape>& entries);
 
 // Instrumentation around the O(N^2) launches.
 bool profiling_enabled();

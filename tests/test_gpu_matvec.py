@@ -175,3 +175,36 @@ def test_symmetric_equals_plain_at_1e5(rp, prec):
     u_sym = rp.matvec(pos, f, precision=prec)
     rp.reset_shape(prec, cfg.N, 1)
     check(u_sym.cpu().numpy(), u_plain.cpu().numpy(), 1e-13 if prec == 0 else 2e-6, f"sym vs plain prec={prec}")
+
+
+def test_autotune_writes_the_persisted_cache(rp, tmp_path):
+    """rpy_wall_autotune rewrites RPYW_AUTOTUNE_CACHE with the tuned shape
+    (GPU architecture, precision, size class, RHS class), and a later
+    process with the same file starts from it."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    path = tmp_path / "shapes.json"
+    prog = f"""
+import sys
+sys.path.insert(0, {root!r})
+import numpy as np, torch
+from paper_1709_02410_amd import rpywall as rp, workloads as wl
+cfg = wl.config0(seed=0)
+pos = torch.tensor(cfg.pos, device="cuda")
+F = torch.tensor(wl.gaussian((1, cfg.N, 3), 1), device="cuda")
+if sys.argv[1] == "tune":
+    rp.autotune(pos, F, precision=rp.FP32C)
+print(rp.get_shape(rp.FP32C, cfg.N, 1), flush=True)
+"""
+    env = dict(os.environ, RPYW_AUTOTUNE_CACHE=str(path))
+    r1 = subprocess.run([sys.executable, "-c", prog, "tune"], env=env, capture_output=True, text=True, timeout=300)
+    assert r1.returncode == 0, r1.stderr
+    data = json.loads(path.read_text())
+    ent = [e for e in data["entries"] if e["precision"] == 1 and e["size_class"] == 9 and e["k"] == 1]
+    assert len(ent) == 1 and ent[0]["arch"].startswith("gfx")
+    r2 = subprocess.run([sys.executable, "-c", prog, "read"], env=env, capture_output=True, text=True, timeout=300)
+    assert r2.returncode == 0, r2.stderr
+    assert r2.stdout.strip().splitlines()[-1] == r1.stdout.strip().splitlines()[-1]
