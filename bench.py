@@ -221,6 +221,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--headline-only", action="store_true", help="time only the headline product")
     ap.add_argument("--calib-copy", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--calib-valu", action="store_true",
+                    help="also run the library's calibration kernels of known FMA count (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle leg (the CPU baseline and every error against the oracle)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -317,6 +319,18 @@ def main():
                                        "not counted"}}
     hrows = sample_rows(N, 256, 11)
     check_matvec(None, f"256 sampled rows of {N}", H.pos, f_np, H2(vel)[hrows], hrows, key="headline")
+
+    if args.calib_valu:
+        # 2048 blocks x 4 waves; FP32: 8 x 20000 FMA instructions per wave,
+        # FP64: 8 x 5000
+        calib = {}
+        for kind, iters, name in ((0, 20000, "fp32"), (1, 5000, "fp64")):
+            rp.calibrate(kind, 2048, iters)
+            sync()
+            waves = 2048 * 4
+            calib[name] = {"kernel": "calib_fma_kernel<" + ("float" if kind == 0 else "double") + ">",
+                           "fma_instructions": waves * 8 * iters, "flop": waves * 8 * iters * 64 * 2}
+        out["calib_valu"] = calib
 
     if args.calib_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB

@@ -371,6 +371,16 @@ int rpyw_tridiag_sqrt_coeffs(const double* alpha, const double* beta, int32_t k,
 int rpy_wall_profile_enable(int enable);
 int rpy_wall_profile_read(double* ms_total, int64_t* launches, double* pair_interactions, int reset);
 
+/* Instrumentation: a kernel with an exactly known instruction count, for
+ * calibrating hardware counters (rocprofv3 instruction and FLOP counts)
+ * before they are used to report the FLOP rate of the pair kernels.
+ * kind 0: FP32, 1: FP64.  `blocks` workgroups of 256 threads (4 waves) each
+ * run `iters` x 8 fused multiply-add instructions per wave (8 independent
+ * chains, operands in vector registers), then store one value per thread to
+ * out (device, blocks x 256 floats or doubles, caller-owned).  Asynchronous
+ * on stream.  1 <= blocks <= 2^20, iters >= 1. */
+int rpy_wall_calibrate(int kind, int64_t blocks, int32_t iters, void* out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

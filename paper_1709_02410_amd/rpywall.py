@@ -71,6 +71,7 @@ def lib():
         "rpy_wall_autotune": [vp, vp, vp, i64, i32, dbl, dbl, ctypes.c_int, vp, sz, vp],
         "rpyw_tridiag_sqrt_coeffs": [ctypes.POINTER(dbl), ctypes.POINTER(dbl), i32, dbl, ctypes.POINTER(dbl)],
         "rpy_wall_profile_enable": [ctypes.c_int],
+        "rpy_wall_calibrate": [ctypes.c_int, i64, i32, vp, vp],
         "rpy_wall_set_shape": [ctypes.c_int, i64, i32, i32, i32, i32, i32, i32],
         "rpy_wall_get_shape": [ctypes.c_int, i64, i32, ctypes.POINTER(i32)],
         "rpy_wall_profile_read": [ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl), ctypes.c_int],
@@ -463,6 +464,15 @@ def tridiag_sqrt_coeffs(alpha, beta, beta0: float) -> np.ndarray:
     _check(lib().rpyw_tridiag_sqrt_coeffs(a_.ctypes.data_as(dp), b_.ctypes.data_as(dp) if k > 1 else None, k,
                                           float(beta0), c.ctypes.data_as(dp)), "rpyw_tridiag_sqrt_coeffs")
     return c
+
+
+def calibrate(kind: int, blocks: int, iters: int, device=None) -> torch.Tensor:
+    """Run the counter-calibration kernel (kind 0: FP32 FMAs, 1: FP64 FMAs;
+    8 x iters FMA instructions per wave, 4 waves per block)."""
+    dev = torch.device("cuda") if device is None else device
+    out = torch.empty(blocks * 256, dtype=torch.float32 if kind == 0 else torch.float64, device=dev)
+    _check(lib().rpy_wall_calibrate(kind, blocks, iters, out.data_ptr(), _stream(dev)), "rpy_wall_calibrate")
+    return out
 
 
 def profile_enable(flag: bool = True):

@@ -59,6 +59,15 @@ def test_noalloc_entry_rejects_before_any_gpu_work(lib):
         assert lib.rpy_wall_matvec_noalloc(dummy, dummy, dummy, 20000, 1.0, 1.0, prec, None) == rpywall.ENOMEM
 
 
+def test_calibration_kernel_validation(lib):
+    dummy = ctypes.c_void_p(0x1000)
+    E = rpywall.EINVAL
+    assert lib.rpy_wall_calibrate(2, 1, 1, dummy, None) == E
+    assert lib.rpy_wall_calibrate(0, 0, 1, dummy, None) == E
+    assert lib.rpy_wall_calibrate(0, 1, 0, dummy, None) == E
+    assert lib.rpy_wall_calibrate(1, 1, 1, None, None) == E
+
+
 def test_validation_rejects_before_any_launch(lib):
     E = rpywall.EINVAL
     dummy = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first

@@ -208,3 +208,33 @@ print(rp.get_shape(rp.FP32C, cfg.N, 1), flush=True)
     r2 = subprocess.run([sys.executable, "-c", prog, "read"], env=env, capture_output=True, text=True, timeout=300)
     assert r2.returncode == 0, r2.stderr
     assert r2.stdout.strip().splitlines()[-1] == r1.stdout.strip().splitlines()[-1]
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_calibration_kernel_computes_its_recurrence(rp, kind):
+    """The counter-calibration kernel runs exactly its documented recurrence
+    (8 chains x <- fma(x, b, c) per thread, summed): checked against the
+    same recurrence on the host (to rounding: the kernel may contract the
+    set-up of b and c into FMAs)."""
+    iters = 7
+    out = rp.calibrate(kind, 3, iters).cpu().numpy().astype(np.float64)
+    t = np.arange(3 * 256) % 256
+    if kind == 0:
+        f32 = np.float32
+        b = (f32(1.0000001) + t.astype(f32) * f32(1e-9)).astype(f32)
+        c = (f32(0.9999999) - t.astype(f32) * f32(1e-9)).astype(f32)
+        x = [(t + k).astype(f32) for k in range(8)]
+        for _ in range(iters):
+            x = [(xk.astype(np.float64) * b + c).astype(f32) for xk in x]
+        s = x[0]
+        for k in range(1, 8):
+            s = (s + x[k]).astype(f32)
+        assert np.allclose(out, s.astype(np.float64), rtol=1e-5)
+    else:
+        b = 1.0000000001 + t * 1e-9
+        c = 0.9999999999 - t * 1e-9
+        x = [(t + k).astype(np.float64) for k in range(8)]
+        for _ in range(iters):
+            x = [xk * b + c for xk in x]
+        s = sum(x[1:], x[0])
+        assert np.allclose(out, s, rtol=1e-14)
