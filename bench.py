@@ -450,15 +450,23 @@ def main():
         if want("lanczos_C1"):
             rp.lanczos_sqrt(pc1, W1, body_offsets=C1.body_offsets, tol=1e-6)
             sync()
+            # the call's time (median of 5), then the product kernel's share
+            # from one more call with the library's kernel timing on
+            t1s = []
+            for _ in range(5):
+                t0 = time.perf_counter()
+                o1, it1, err1, ok1 = rp.lanczos_sqrt(pc1, W1, body_offsets=C1.body_offsets, tol=1e-6)
+                sync()
+                t1s.append(time.perf_counter() - t0)
+            t1 = float(np.median(t1s))
             rp.profile_enable(True)
             rp.profile_read(True)
-            t0 = time.perf_counter()
-            o1, it1, err1, ok1 = rp.lanczos_sqrt(pc1, W1, body_offsets=C1.body_offsets, tol=1e-6)
+            rp.lanczos_sqrt(pc1, W1, body_offsets=C1.body_offsets, tol=1e-6)
             sync()
-            t1 = time.perf_counter() - t0
             kms1, ln1, _ = rp.profile_read(True)
             rp.profile_enable(False)
             rows["lanczos_C1_fp64_tol1e-6"] = {"blobs": C1.N, "iterations": it1, "converged": ok1, "ms": t1 * 1e3,
+                                               "ms_min": min(t1s) * 1e3,
                                                "ms_per_iteration": t1 * 1e3 / max(it1, 1),
                                                "product_kernel_ms_per_iteration": kms1 / max(ln1, 1)}
             checks.append({"kind": "lanczos", "row": "lanczos_C1_fp64_tol1e-6", "what": "all 3840 blobs",

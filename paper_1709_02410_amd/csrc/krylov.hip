@@ -19,13 +19,14 @@ namespace rpyw {
 namespace {
 
 constexpr int kBodyThreads = 128;
+constexpr int kBuildThreads = 256;
 
 // Dense M^(pp) of one body (units: physical, includes mu0 and B factors)
 // assembled in LDS, then factorised in place (right-looking Cholesky).  The
 // LDS is sized at launch for the largest body of the call (ld = 3 n_max + 1
 // doubles per row, then 4 n_max doubles of blob data), so that small bodies
 // keep many workgroups per CU.
-__global__ __launch_bounds__(kBodyThreads) void precond_build_kernel(const double* __restrict__ pos,
+__global__ __launch_bounds__(kBuildThreads) void precond_build_kernel(const double* __restrict__ pos,
                                                                      const int* __restrict__ bofs,
                                                                      const int64_t* __restrict__ lofs, double inv_a,
                                                                      double mu0, double* __restrict__ Lout,
@@ -68,14 +69,15 @@ __global__ __launch_bounds__(kBodyThreads) void precond_build_kernel(const doubl
     // with the unscaled column, A(i, j) -= A(i, k) A(j, k) / A(k, k), then
     // scales column k by 1 / sqrt(A(k, k)); the scaling touches only column k,
     // which no later step reads or writes, so it needs no barrier of its own.
+    // Threads form a 16 x 16 grid over (row, column) of the trailing block.
+    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
     for (int k = 0; k < n; ++k) {
         const double d = A(k, k);
         const bool ok = d > 0.0;
         const double id = ok ? 1.0 / d : 0.0;
-        const int m = n - k - 1;
-        for (int q = threadIdx.x; q < m * m; q += blockDim.x) {
-            const int i = k + 1 + q / m, j = k + 1 + q % m;
-            if (j <= i) A(i, j) -= A(i, k) * A(j, k) * id;
+        for (int i = k + 1 + tr; i < n; i += 16) {
+            const double aik = A(i, k);
+            for (int j = k + 1 + tc; j <= i; j += 16) A(i, j) -= aik * A(j, k) * id;
         }
         __syncthreads();
         const double sd = ok ? sqrt(d) : 1.0;
@@ -92,23 +94,28 @@ __global__ __launch_bounds__(kBodyThreads) void precond_build_kernel(const doubl
         const int i = q / n, j = q % n;
         L[q] = j <= i ? A(i, j) : 0.0;
     }
-    // Inverse factor L^-1 (lower triangular), one column per thread: forward
-    // substitution of L x = e_col.  Entry (i, col), i > col, is kept in the
-    // free upper triangle of A at (col, i), a row only this thread touches,
-    // so the substitution reads LDS rather than its own global writes.
-    for (int col = threadIdx.x; col < n; col += blockDim.x) {
-        const double xc = 1.0 / A(col, col);
-        for (int i = col + 1; i < n; ++i) {
-            double s0 = A(i, col) * xc, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-            int k = col + 1;
-            for (; k + 3 < i; k += 4) {
-                s0 += A(i, k) * A(col, k);
-                s1 += A(i, k + 1) * A(col, k + 1);
-                s2 += A(i, k + 2) * A(col, k + 2);
-                s3 += A(i, k + 3) * A(col, k + 3);
+    // Inverse factor L^-1 (lower triangular), four lanes per column: forward
+    // substitution of L x = e_col, entry (i, col) = -(sum over col <= k < i
+    // of L(i, k) x_k) / L(i, i), the lanes taking k = col + lane (mod 4) and
+    // adding their shares in a fixed butterfly (all four get the same sum).
+    // Entry (i, col), i > col, is kept in the free upper triangle of A at
+    // (col, i), a row only this lane group touches (one wave), written by its
+    // first lane and read by all four in later rows.
+    {
+        const int sub = threadIdx.x & 3;
+        for (int col = threadIdx.x >> 2; col < n; col += kBuildThreads / 4) {
+            const double xc = 1.0 / A(col, col);
+            for (int i = col + 1; i < n; ++i) {
+                double s = 0.0;
+                for (int k = col + sub; k < i; k += 4) s += A(i, k) * (k == col ? xc : A(col, k));
+                s += __shfl_xor(s, 1, 4);
+                s += __shfl_xor(s, 2, 4);
+                const double x = -s / A(i, i);
+                if (sub == 0) A(col, i) = x;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
-            for (; k < i; ++k) s0 += A(i, k) * A(col, k);
-            A(col, i) = -((s0 + s1) + (s2 + s3)) / A(i, i);
         }
     }
     __syncthreads();
@@ -461,7 +468,7 @@ int body_factors_build(const double* pos, int64_t N, double a, double eta, const
         if (lds > 65536)  // up to 129 KB for 42-blob bodies
             RPYW_HIP(hipFuncSetAttribute((const void*)precond_build_kernel,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(precond_build_kernel, dim3(n_bodies), dim3(kBodyThreads), lds, st, pos, pc.bofs, pc.lofs,
+        hipLaunchKernelGGL(precond_build_kernel, dim3(n_bodies), dim3(kBuildThreads), lds, st, pos, pc.bofs, pc.lofs,
                            inv_a, m0, pc.L, notspd, nmax);
     } else {
         pc.L = (double*)ar.take((size_t)3 * N * sizeof(double));

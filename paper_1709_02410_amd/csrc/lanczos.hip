@@ -18,7 +18,10 @@
 //   out = L (V c).
 // All reductions are two-stage with a fixed order (bitwise reproducible).
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
+#include <cstring>
 #include <mutex>
 #include <vector>
 
@@ -135,12 +138,268 @@ size_t lanczos_ws_bytes(int64_t N, int max_iter, int n_bodies, int prec) {
     b += 4 * align_up((size_t)2 * (max_iter + 8) * sizeof(double));  // alpha/beta, c1, c2, b0
     b += align_up(sizeof(unsigned)) + align_up(sizeof(int));        // ticket, notspd
     b += product_ws_bytes(N, prec, 1);
-    return b + 16 * kAlign;
+    // fused steps: the block partials of both Gram-Schmidt passes and the
+    // workgroup tables (one unit per body or per kLanczosOutEntries / 3 blobs)
+    const size_t units = (size_t)std::max<int64_t>(n_bodies, N / (kLanczosOutEntries / 3) + 1) + 1;
+    int m;
+    b += align_up((size_t)(max_iter + 2) * units * sizeof(double));
+    b += align_up((size_t)(max_iter + 3) * lanczos_gs2_blocks((int64_t)n3, &m) * sizeof(double));
+    b += align_up((units + 1) * sizeof(int)) + align_up((units + 1) * sizeof(LanczosGroup));
+    return b + 24 * kAlign;
 }
+
+namespace {
+
+// The Lanczos iteration with fused steps (lanczos_step.hip); same results
+// as the unfused driver below up to rounding (different summation orders).
+int lanczos_fused(const double* pos, const double* W, double* out, int64_t N, double a, double eta,
+                  const int64_t* body_offsets, int n_bodies, double tol, int max_iter, int prec, Arena& ar, int* iters,
+                  double* err, hipStream_t st, const Domain& dom, const BodyFactors* pre, const SymPlan& sp,
+                  int ipw) {
+    const int64_t n3 = 3 * N;
+    *iters = 0;
+    *err = 0.0;
+    std::vector<int> h_units, h_groups;
+    lanczos_units(N, body_offsets, n_bodies, h_units, h_groups);
+    const int nunits = (int)h_units.size() - 1, ngroups = (int)h_groups.size() - 1;
+    int m4;
+    const int64_t nblk4 = lanczos_gs2_blocks(n3, &m4);
+    BodyFactors pc;
+    const int rw = rec_width(prec, 1);
+    const int64_t npad = (int64_t)sp.ng * sp.G;
+    double* V = (double*)ar.take((size_t)(max_iter + 1) * n3 * sizeof(double));
+    double* y = (double*)ar.take(n3 * sizeof(double));
+    double* w = (double*)ar.take(n3 * sizeof(double));
+    double* partial = (double*)ar.take((size_t)2 * dot_chunks(n3) * sizeof(double));  // setup norm
+    double* part1 = (double*)ar.take((size_t)(max_iter + 2) * ngroups * sizeof(double));
+    double* part2 = (double*)ar.take((size_t)(max_iter + 3) * nblk4 * sizeof(double));
+    double* d_ab = (double*)ar.take(2 * (max_iter + 8) * sizeof(double));
+    double* d_c = (double*)ar.take(2 * (max_iter + 8) * sizeof(double));
+    double* d_b0 = (double*)ar.take(8 * sizeof(double));
+    unsigned* ticket = (unsigned*)ar.take(kAlign);
+    int* notspd = (int*)ar.take(sizeof(int));
+    int* d_units = (int*)ar.take((size_t)(nunits + 1) * sizeof(int));
+    LanczosGroup* d_groups = (LanczosGroup*)ar.take((size_t)ngroups * sizeof(LanczosGroup));
+    void* rec = ar.take((size_t)npad * rw * real_size(prec));
+    double* B = (double*)ar.take((size_t)npad * sizeof(double));
+    double* tpart = (double*)ar.take(sp.tpart_bytes);
+    void* spart = ar.take(sp.spart_bytes);
+    if (!V || !y || !w || !partial || !part1 || !part2 || !d_ab || !d_c || !d_b0 || !ticket || !notspd || !d_units ||
+        !d_groups || !rec || !B || !tpart || !spart)
+        return RPYW_ENOMEM;
+    std::lock_guard<std::mutex> lk(g_ab.mu);
+    int rc = g_ab.reserve((size_t)(3 * (max_iter + 2) + 2) * sizeof(double));
+    if (rc) return rc;
+    double* h_ab = g_ab.p;
+    double* dh_ab = g_ab.dp;  // the same pinned memory as kernels address it
+    SlotRelease slots_done{g_ab, st};
+    double* h_b0 = h_ab + 2 * (max_iter + 2);
+    int* h_bad = (int*)(h_b0 + 1);
+    // step flags: set by the step's last kernel after alpha_k and beta_{k-1}
+    // (no event per step: an event between the steps' kernels delays the next)
+    double* h_flag = h_b0 + 2;
+    double* dh_flag = dh_ab + (h_flag - h_ab);
+    std::memset(h_flag, 0, (size_t)(max_iter + 2) * sizeof(double));
+
+    RPYW_HIP(hipMemsetAsync(notspd, 0, sizeof(int), st));
+    RPYW_HIP(hipMemsetAsync(ticket, 0, sizeof(unsigned), st));
+    if (pre)
+        pc = *pre;
+    else if ((rc = body_factors_build(pos, N, a, eta, body_offsets, n_bodies, ar, st, pc, notspd)))
+        return rc;
+    if ((rc = stage_upload(h_units.data(), h_units.size() * sizeof(int), d_units, st))) return rc;
+    {
+        // the gather groups' table: units, blobs, first factor block, factor size
+        std::vector<LanczosGroup> gt(ngroups);
+        int64_t loff = 0;
+        for (int g = 0; g < ngroups; ++g) {
+            LanczosGroup& G = gt[g];
+            G.g0 = h_groups[g];
+            G.g1 = h_groups[g + 1];
+            G.b0 = h_units[G.g0];
+            G.b1 = h_units[G.g1];
+            G.loff = loff;
+            G.sq = 0;
+            G.pad = 0;
+            if (G.g1 - G.g0 > kLanczosGroupUnits) return RPYW_EINVAL;  // not produced by lanczos_units
+            for (int q = G.g0; q < G.g1; ++q) {
+                const int nq = 3 * (h_units[q + 1] - h_units[q]);
+                G.sq += nq * nq;
+            }
+            loff += G.sq;
+        }
+        if ((rc = stage_upload(gt.data(), gt.size() * sizeof(LanczosGroup), d_groups, st))) return rc;
+    }
+    // positions and B once; the force slots are rewritten by every step
+    if ((rc = sym_pack(pos, W, N, 1, 1, prec, sp, a, dom, rec, B, st))) return rc;
+    // beta0 = |W|
+    if ((rc = vec_dots(nullptr, n3, 0, W, n3, partial, ticket, d_b0, 0, nullptr, st))) return rc;
+    h_bad[0] = h_bad[1] = 0;
+    RPYW_HIP(hipMemcpyAsync(h_b0, d_b0, sizeof(double), hipMemcpyDeviceToHost, st));
+    RPYW_HIP(hipMemcpyAsync(h_bad, notspd, sizeof(int), hipMemcpyDeviceToHost, st));
+    if (pre && pre->flag) RPYW_HIP(hipMemcpyAsync(h_bad + 1, pre->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    const double m0 = 1.0 / (6.0 * M_PI * eta * a);
+
+    // Step k: v_k (from y' and the second projection of step k - 1, or from
+    // W), the product, w = L^-1 M x - beta_{k-1} v_{k-1} with the first
+    // projection, then y' = w - V c1 with the second projection.
+    auto launch_step = [&](int k) -> int {
+        int r;
+        if ((r = lz_launch_vin(prec, pc, d_units, nunits, n3, k, k == 0 ? W : y, d_b0, part2, (int)nblk4, V, d_ab,
+                               dh_ab, rec, rw, B, st)))
+            return r;
+        hipEvent_t ev = nullptr;
+        profile_begin(st, &ev);
+        if ((r = sym_launch(rec, sp, ipw, 1, prec, a, dom, tpart, spart, st))) return r;
+        profile_end(st, ev, (dom.periodic() ? 9.0 : 1.0) * (double)N * (double)N);
+        if ((r = lz_launch_out(prec, pc, d_units, d_groups, ngroups, tpart, spart, sp, B, m0, n3, k, V, d_ab, w,
+                               part1, st)))
+            return r;
+        if ((r = lz_launch_gs2(w, y, n3, V, k, part1, ngroups, part2, d_ab, dh_ab, dh_flag, st))) return r;
+        // step 0 also waits for the set-up copies (beta_0, the definiteness flags)
+        if (k == 0) RPYW_HIP(hipEventRecord(g_ab.ev[0], st));
+        return RPYW_OK;
+    };
+    const int depth = (double)N * (double)N <= kSpeculatePairs ? kSpeculateDepth : 0;
+    int queued = 0;
+    auto fill = [&](int upto) -> int {  // queue steps up to index upto - 1
+        for (; queued < upto && queued < max_iter; ++queued)
+            if (int r = launch_step(queued)) return r;
+        return RPYW_OK;
+    };
+
+    std::vector<double> alpha, beta, c, cprev;
+    bool converged = false;
+    double rel = INFINITY, rel1 = INFINITY, rel2 = INFINITY;
+    int k = 0, used = 0;
+    // host time spent waiting for steps, and steps the device had queued
+    // behind the awaited one when the wait began (RPYW_LOG)
+    using Clock = std::chrono::steady_clock;
+    const bool logging = log_enabled();
+    double wait_ms = 0.0;
+    int starved = 0;
+    const auto t_call = Clock::now();
+    if ((rc = fill(1 + depth))) return rc;
+    // Waits for step k: its flag in host memory, polled; the stream is
+    // queried now and then so that a stream that drains without setting it
+    // (a failed launch) ends the wait with an error instead of spinning.
+    auto wait_step = [&](int k) -> int {
+        if (k == 0) {
+            RPYW_HIP(hipEventSynchronize(g_ab.ev[0]));
+            return RPYW_OK;
+        }
+        const volatile double* f = h_flag + k;
+        for (unsigned spin = 1;; ++spin) {
+            if (*f != 0.0) break;
+            if ((spin & 4095) == 0) {
+                const hipError_t q = hipStreamQuery(st);
+                if (q == hipSuccess) {
+                    if (*f != 0.0) break;
+                    return RPYW_EHIP;
+                }
+                if (q != hipErrorNotReady) return RPYW_EHIP;
+            }
+            __builtin_ia32_pause();
+        }
+        std::atomic_thread_fence(std::memory_order_acquire);
+        return RPYW_OK;
+    };
+    for (; k < max_iter; ++k) {
+        if (logging) {
+            if (queued <= k + 1) ++starved;
+            const auto t0 = Clock::now();
+            if ((rc = wait_step(k))) return rc;
+            wait_ms += std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+        } else if ((rc = wait_step(k))) {
+            return rc;
+        }
+        if (k == 0) {
+            const bool bad = h_bad[0] || h_bad[1];
+            if (bad || *h_b0 == 0.0) {
+                RPYW_HIP(hipStreamSynchronize(st));
+                if (bad) return RPYW_ENOTSPD;
+                RPYW_HIP(hipMemsetAsync(out, 0, n3 * sizeof(double), st));
+                return RPYW_OK;
+            }
+        }
+        const double ak = h_ab[2 * k];
+        if (k > 0) {
+            // beta_{k-1} arrives with step k: a breakdown (invariant
+            // subspace) means step k - 1 was the last, with its iterate
+            const double bk1 = h_ab[2 * (k - 1) + 1];
+            const double prev_b = k > 1 ? beta[k - 2] : 0.0;
+            if (bk1 <= 1e-14 * (std::fabs(alpha[k - 1]) + prev_b)) {
+                converged = true;
+                used = k;
+                *iters = k;
+                break;
+            }
+            beta.push_back(bk1);
+        }
+        if (depth && (rc = fill(speculate_to(k, depth, rel1, rel2, tol) + 1))) return rc;
+        alpha.push_back(ak);
+        c.assign(k + 1, 0.0);
+        if (tridiag_sqrt_coeffs(alpha.data(), beta.data(), k + 1, *h_b0, c.data()) != RPYW_OK) return RPYW_EHIP;
+        if (k > 0) {
+            double num = 0.0, den = 0.0;
+            for (int i = 0; i <= k; ++i) {
+                const double dlt = c[i] - (i < k ? cprev[i] : 0.0);
+                num += dlt * dlt;
+                den += c[i] * c[i];
+            }
+            rel = std::sqrt(num / den);
+            if (rel <= tol) {
+                converged = true;
+                used = k + 1;
+                *iters = k + 1;
+                break;
+            }
+        }
+        cprev = c;
+        rel2 = rel1;
+        rel1 = rel;
+        if ((rc = fill(k + 2))) return rc;
+    }
+    if (!converged) {
+        // The last step's beta is known only after the next step's first
+        // kernel: run it (V has room for one more vector) to test for a
+        // breakdown at the last step.
+        if ((rc = lz_launch_vin(prec, pc, d_units, nunits, n3, max_iter, y, d_b0, part2, (int)nblk4, V, d_ab, dh_ab,
+                                rec, rw, B, st)))
+            return rc;
+        RPYW_HIP(hipStreamSynchronize(st));
+        const double bl = h_ab[2 * (max_iter - 1) + 1];
+        const double prev_b = max_iter > 1 ? beta[max_iter - 2] : 0.0;
+        converged = bl <= 1e-14 * (std::fabs(alpha[max_iter - 1]) + prev_b);
+        used = max_iter;
+        *iters = max_iter;
+    } else if (used == k) {
+        c = cprev;  // breakdown: the iterate of step k - 1
+    }
+    *err = std::isfinite(rel) ? rel : 0.0;
+    if ((rc = stage_upload(c.data(), used * sizeof(double), d_c, st))) return rc;
+    if ((rc = vec_comb(V, n3, used, d_c, y, n3, st))) return rc;  // y = V c
+    if ((rc = pc.apply(0, y, out, n3, st))) return rc;            // out = L y
+    if (logging)
+        log_line("lanczos fused steps: %d run, %d queued; host %.3f ms, of which %.3f ms waiting; %d waits with no "
+                 "later step queued",
+                 used, queued, std::chrono::duration<double, std::milli>(Clock::now() - t_call).count(), wait_ms,
+                 starved);
+    return converged ? RPYW_OK : RPYW_NOT_CONVERGED;
+}
+
+}  // namespace
 
 int lanczos_sqrt(const double* pos, const double* W, double* out, int64_t N, double a, double eta,
                  const int64_t* body_offsets, int n_bodies, double tol, int max_iter, int prec, Arena& ar, int* iters,
                  double* err, hipStream_t st, const Domain& dom, const BodyFactors* pre) {
+    {
+        SymPlan sp;
+        int ipw;
+        if (lanczos_fused_applies(N, prec, max_iter, dom, &sp, &ipw))
+            return lanczos_fused(pos, W, out, N, a, eta, body_offsets, n_bodies, tol, max_iter, prec, ar, iters, err,
+                                 st, dom, pre, sp, ipw);
+    }
     const int64_t n3 = 3 * N;
     *iters = 0;
     *err = 0.0;

@@ -369,7 +369,10 @@ template <typename R, int K, int PER>
 hipError_t launch_sym_t(const R* rec, const SymPlan& sp, int ipw, double* tpart, R* spart, const Box<R>& box,
                         hipStream_t st) {
     const dim3 grid((unsigned)((int64_t)sp.ng * sp.C * sp.nseg));
-    if (sp.G == 64)
+    if (sp.G == 64 && sp.ns == 4)
+        hipLaunchKernelGGL((sym_kernel<R, ProductBody<R, K, PER>, 1, 4>), grid, dim3(256), 0, st, rec, sp.ng, sp.C,
+                           ipw, sp.Hmax, sp.nseg, tpart, spart, box);
+    else if (sp.G == 64)
         hipLaunchKernelGGL((sym_kernel<R, ProductBody<R, K, PER>, 1>), grid, dim3(64), 0, st, rec, sp.ng, sp.C, ipw,
                            sp.Hmax, sp.nseg, tpart, spart, box);
     else
@@ -484,13 +487,21 @@ SymPlan sym_plan(int64_t N, int prec, int K, int ipw, int G) {
     // Segments: enough work items to give every SIMD several (independent
     // of ipw, so that the workspace bound taken at ipw 1 holds).
     const int64_t items = (int64_t)s.ng * (s.Hmax + 1);
+    // Groups of 64 split the passes of few items over 4 waves of one
+    // workgroup first (their sums meet in LDS), and over workgroups (each
+    // with partials of its own) only when there are fewer than half as many
+    // waves as wanted.
+    s.ns = (s.G == 64 && items < kSymItemsMin) ? 4 : 1;
+    const int64_t want = s.ns > 1 ? kSymItemsMin / 2 : kSymItemsMin;
     s.nseg = 1;
-    while (s.nseg < 4 && items * s.nseg < kSymItemsMin) s.nseg *= 2;
+    while (s.nseg < 4 && items * s.ns * s.nseg < want) s.nseg *= 2;
+    if (s.G == 64) sym_split_override(&s.ns, &s.nseg);
     const size_t npad = (size_t)s.ng * s.G;
     s.rec_bytes = align_up(npad * rec_width(prec, K) * real_size(prec)) + align_up(npad * sizeof(double));
     s.tpart_bytes = align_up((size_t)s.ng * s.C * s.nseg * 3 * K * s.G * sizeof(double));
     s.spart_bytes = align_up((size_t)s.ng * (s.Hmax + 1) * s.nseg * 3 * K * s.G * real_size(prec));
-    s.ok = K <= 4 && s.spart_bytes <= ((size_t)4 << 30) && (s.G == 256 || N <= kSym64MaxN);
+    s.ok = K <= 4 && s.spart_bytes <= kSymPartialMaxBytes && s.tpart_bytes <= kSymPartialMaxBytes &&
+           (s.G == 256 || N <= kSym64MaxN);
     return s;
 }
 
@@ -541,6 +552,26 @@ int sym_pass(const double* pos, const double* F, double* U, int64_t N, int kb, i
         ar.used = mark;
         return RPYW_ENOMEM;
     }
+    int rc = sym_pack(pos, F, N, kb, K, prec, sp, a, dom, rec, B, st);
+    if (rc == RPYW_OK) {
+        hipEvent_t ev = nullptr;
+        profile_begin(st, &ev);
+        rc = sym_launch(rec, sp, ipw, K, prec, a, dom, tpart, spart, st);
+        if (rc == RPYW_OK) {
+            profile_end(st, ev, (dom.periodic() ? 9.0 : 1.0) * (double)kb * (double)N * (double)N);
+            rc = sym_finish(tpart, spart, B, N, kb, K, prec, sp, mu0_of(a, eta), U, st);
+        }
+    }
+    ar.used = mark;
+    return rc;
+}
+
+}  // namespace
+
+int sym_pack(const double* pos, const double* F, int64_t N, int kb, int K, int prec, const SymPlan& sp, double a,
+             const Domain& dom, void* rec, double* B, hipStream_t st) {
+    const int rw = rec_width(prec, K);
+    const int64_t npad = (int64_t)sp.ng * sp.G;
     const unsigned g1 = (unsigned)((N + kBlock - 1) / kBlock);
     const unsigned gp = (unsigned)((npad - N + kBlock - 1) / kBlock);
     if (prec == RPYW_FP32C) {
@@ -553,9 +584,11 @@ int sym_pass(const double* pos, const double* F, double* U, int64_t N, int kb, i
         if (gp) hipLaunchKernelGGL(pad_kernel<double>, dim3(gp), dim3(kBlock), 0, st, (double*)rec, N, npad, rw, B);
     }
     RPYW_HIP(hipGetLastError());
-    hipEvent_t ev = nullptr;
-    profile_begin(st, &ev);
-    hipError_t e;
+    return RPYW_OK;
+}
+
+int sym_launch(const void* rec, const SymPlan& sp, int ipw, int K, int prec, double a, const Domain& dom,
+               double* tpart, void* spart, hipStream_t st) {
     auto go = [&](auto Rt, auto Kc) -> hipError_t {
         using R = decltype(Rt);
         constexpr int KK = decltype(Kc)::value;
@@ -573,28 +606,28 @@ int sym_pass(const double* pos, const double* F, double* U, int64_t N, int kb, i
         }
         return launch_sym_t<R, KK, 0>((const R*)rec, sp, ipw, tpart, (R*)spart, Box<R>{}, st);
     };
+    hipError_t e;
     if (prec == RPYW_FP32C)
         e = K == 1 ? go(0.f, std::integral_constant<int, 1>{})
                    : K == 2 ? go(0.f, std::integral_constant<int, 2>{}) : go(0.f, std::integral_constant<int, 4>{});
     else
         e = K == 1 ? go(0.0, std::integral_constant<int, 1>{})
                    : K == 2 ? go(0.0, std::integral_constant<int, 2>{}) : go(0.0, std::integral_constant<int, 4>{});
-    if (e != hipSuccess) return RPYW_EHIP;
-    profile_end(st, ev, (dom.periodic() ? 9.0 : 1.0) * (double)kb * (double)N * (double)N);
-    const double m0 = mu0_of(a, eta);
+    return e == hipSuccess ? RPYW_OK : RPYW_EHIP;
+}
+
+int sym_finish(const double* tpart, const void* spart, const double* B, int64_t N, int kb, int K, int prec,
+               const SymPlan& sp, double mu0, double* U, hipStream_t st) {
     const dim3 ge((unsigned)((N + 63) / 64), (unsigned)(3 * kb));
     if (prec == RPYW_FP32C)
         hipLaunchKernelGGL(sym_epilogue<float>, ge, dim3(64 * kEpiParts), 0, st, tpart, (const float*)spart, B, N,
-                           sp.ng, sp.C, sp.Hmax, sp.nseg, K, sp.G, m0, U);
+                           sp.ng, sp.C, sp.Hmax, sp.nseg, K, sp.G, mu0, U);
     else
         hipLaunchKernelGGL(sym_epilogue<double>, ge, dim3(64 * kEpiParts), 0, st, tpart, (const double*)spart, B, N,
-                           sp.ng, sp.C, sp.Hmax, sp.nseg, K, sp.G, m0, U);
+                           sp.ng, sp.C, sp.Hmax, sp.nseg, K, sp.G, mu0, U);
     RPYW_HIP(hipGetLastError());
-    ar.used = mark;
     return RPYW_OK;
 }
-
-}  // namespace
 
 int product_pass(const double* pos, const double* F, double* U, int64_t N, int kb, double a, double eta, int prec,
                  Shape sh, Arena& ar, hipStream_t st) {

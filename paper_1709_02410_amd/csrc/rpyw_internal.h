@@ -41,7 +41,8 @@ struct Domain {
 // Symmetric path geometry for N blobs, K right-hand sides.
 struct SymPlan {
     int G;     // blobs per group: 256 or 64
-    int nseg;  // segments per item pass (1, 2 or 4: more workgroups for tiny problems)
+    int ns;    // waves per item that split its passes (1, or 4 for groups of 64 when items are few)
+    int nseg;  // workgroups per item that split its passes (1, 2 or 4: more workgroups for tiny problems)
     int ng, Hmax, C;
     size_t rec_bytes, tpart_bytes, spart_bytes;
     bool ok;
@@ -53,8 +54,29 @@ constexpr int64_t kSym64MaxN = 32768;
 // Work items (group pairs) below which the symmetric passes are split into
 // segments.
 constexpr int64_t kSymItemsMin = 8192;
+// Largest partial-sum array (source or target side) the symmetric path
+// takes.  The partials grow as N^2 / G (3 N^2 / 512 values per side for one
+// right-hand side and groups of 256), so this admits the symmetric kernel
+// up to about 6e5 blobs in FP64 and 8.5e5 in FP32 (the "hundreds of
+// thousands of blobs" up to which the paper finds direct products
+// competitive); beyond it products use the plain kernel, whose workspace
+// grows as N.
+constexpr size_t kSymPartialMaxBytes = (size_t)16 << 30;
 SymPlan sym_plan(int64_t N, int prec, int K, int ipw, int G = 256);
 inline int sym_group(int sym) { return sym == 2 ? 64 : 256; }
+// The three stages of a symmetric product pass, for callers that keep the
+// records between passes (the Krylov solvers):
+//   sym_pack   records (positions, wrapped into the cell when periodic, and
+//              B f for kb right-hand sides; padded records are force-free
+//              blobs far away) and B, for ng G blobs;
+//   sym_launch the pair kernel over the records into the partial sums;
+//   sym_finish U = mu0 B (sum of the partials), fixed order.
+int sym_pack(const double* pos, const double* F, int64_t N, int kb, int K, int prec, const SymPlan& sp, double a,
+             const Domain& dom, void* rec, double* B, hipStream_t st);
+int sym_launch(const void* rec, const SymPlan& sp, int ipw, int K, int prec, double a, const Domain& dom,
+               double* tpart, void* spart, hipStream_t st);
+int sym_finish(const double* tpart, const void* spart, const double* B, int64_t N, int kb, int K, int prec,
+               const SymPlan& sp, double mu0, double* U, hipStream_t st);
 
 // Bump allocator over a caller workspace.
 struct Arena {
@@ -117,6 +139,9 @@ struct CachedShape {
 bool log_enabled();
 void log_line(const char* fmt, ...);
 Shape apply_env_overrides(Shape s);
+// RPYW_SYM_SPLIT: the split of item passes of the symmetric kernel with
+// groups of 64 (false when not set).
+bool sym_split_override(int* ns, int* nseg);
 const char* autotune_cache_path();
 std::string device_arch();
 int read_shape_cache(const char* path, std::vector<CachedShape>& out);
@@ -142,6 +167,35 @@ __device__ __forceinline__ double minus_comb(const double* __restrict__ v, const
     for (; j < nc; ++j) x -= c[j] * V[j * ld + e];
     return x;
 }
+
+// Fused Lanczos steps (lanczos_step.hip): four launches per step when the
+// product runs through the symmetric kernel and max_iter is at most
+// kLanczosFusedMaxIter (the coefficient vectors live in LDS).
+constexpr int kLanczosFusedMaxIter = 512;
+constexpr int kLanczosGs2PerThread = 8;
+constexpr int kLanczosOutEntries = 64;  // entries per workgroup of the gather (larger bodies alone)
+// A gather group: units [g0, g1) (bodies, or runs of blobs), blobs [b0, b1),
+// the offset loff of the first unit's factor block (L_p then L_p^-1 at
+// 2 loff) and sq = sum of n_p^2 over its units (entries of each factor).
+struct LanczosGroup {
+    int g0, g1, b0, b1;
+    int64_t loff;
+    int sq, pad;
+};
+constexpr int kLanczosGroupUnits = kLanczosOutEntries / 3 + 1;  // units of a group, at most
+struct BodyFactors;
+bool lanczos_fused_applies(int64_t N, int prec, int max_iter, const Domain& dom, SymPlan* sp, int* ipw);
+int64_t lanczos_gs2_blocks(int64_t n3, int* m);
+void lanczos_units(int64_t N, const int64_t* body_offsets, int n_bodies, std::vector<int>& units,
+                   std::vector<int>& groups);
+int lz_launch_vin(int prec, const BodyFactors& pc, const int* units, int nunits, int64_t n3, int k,
+                  const double* src, const double* b0, const double* part2, int ncol2, double* V, double* d_ab,
+                  double* h_ab, void* rec, int recw, const double* B, hipStream_t st);
+int lz_launch_out(int prec, const BodyFactors& pc, const int* units, const LanczosGroup* ginfo, int ngroups,
+                  const double* tpart, const void* spart, const SymPlan& sp, const double* B, double mu0, int64_t n3,
+                  int k, const double* V, const double* d_ab, double* w, double* part1, hipStream_t st);
+int lz_launch_gs2(const double* w, double* yo, int64_t n3, const double* V, int k, const double* part1, int ngroups,
+                  double* part2, double* d_ab, double* h_ab, double* h_flag, hipStream_t st);
 
 // Krylov building blocks (krylov.hip).
 // Block-diagonal preconditioner factors: per body the Cholesky factor L_p of

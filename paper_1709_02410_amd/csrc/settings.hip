@@ -7,6 +7,11 @@
 //                              product (overrides tuned and built-in shapes)
 //   RPYW_RHS_WIDTH=1|2|4|8|16  right-hand sides per pass (FP64 stops at 8);
 //                              widths above 4 use the plain kernel
+//   RPYW_SYM_SPLIT=ns,nseg     how the symmetric kernel with groups of 64
+//                              splits the passes of an item: over ns waves
+//                              of a workgroup (1 or 4) and nseg workgroups
+//                              (1, 2 or 4); by default chosen from the
+//                              number of items
 //   RPYW_AUTOTUNE_CACHE=path   JSON file of tuned launch shapes, keyed by
 //                              (GPU architecture, precision, size class of N
 //                              = floor(log2 N), RHS class k); read at the
@@ -45,6 +50,7 @@ struct Env {
     bool log;
     int tile;       // 0: no override
     int rhs_width;  // 0: no override
+    int sym_ns = 0, sym_nseg = 0;  // 0: no override
     std::string cache;
     Env() {
         log = env_int("RPYW_LOG", 0) != 0;
@@ -52,6 +58,17 @@ struct Env {
         tile = (t == 64 || t == 256) ? t : 0;
         const int w = env_int("RPYW_RHS_WIDTH", 0);
         rhs_width = (w == 1 || w == 2 || w == 4 || w == 8 || w == 16) ? w : 0;
+        if (const char* sp = std::getenv("RPYW_SYM_SPLIT")) {
+            int a = 0, b = 0;
+            char tail = 0;
+            if (std::sscanf(sp, "%d,%d%c", &a, &b, &tail) == 2 && (a == 1 || a == 4) &&
+                (b == 1 || b == 2 || b == 4)) {
+                sym_ns = a;
+                sym_nseg = b;
+            } else if (log) {
+                std::fprintf(stderr, "[rpywall] ignoring RPYW_SYM_SPLIT (ns,nseg with ns 1 or 4, nseg 1, 2 or 4)\n");
+            }
+        }
         const char* c = std::getenv("RPYW_AUTOTUNE_CACHE");
         cache = c ? c : "";
         if (log) {
@@ -113,6 +130,13 @@ Shape apply_env_overrides(Shape s) {
     if (e.tile) s.tile = e.tile;
     if (e.rhs_width) s.kblk = e.rhs_width;
     return s;
+}
+
+bool sym_split_override(int* ns, int* nseg) {
+    if (!env().sym_ns) return false;
+    *ns = env().sym_ns;
+    *nseg = env().sym_nseg;
+    return true;
 }
 
 const char* autotune_cache_path() { return env().cache.empty() ? nullptr : env().cache.c_str(); }

@@ -250,18 +250,23 @@ struct SymLane {
 
 // Groups of G = 64 NB blobs (NB blocks of 64, one wave each): NB = 4 for
 // large problems, NB = 1 to have enough workgroups when there are few groups.
-// Very small problems also split every item's 64-step passes into nseg
-// segments, each its own workgroup (nseg = 1, 2 or 4).
+// Small problems split every item's 64-step passes into segments: NS
+// segments are NS waves of one workgroup (NB = 1), which hold the same
+// target block, take 64 / NS consecutive steps each and add their sums
+// through LDS in wave order; beyond that, nseg segments are workgroups of
+// their own (nseg = 1, 2 or 4), each writing its own partials.
 // rec: ng * G records (padded with force-free blobs far away).
 // tpart: [ng * C * nseg][NQ][G] doubles; spart: [ng * (Hmax + 1) * nseg][NQ][G].
-template <typename R, class Body, int NB = 4>
-__global__ __launch_bounds__(64 * NB) void sym_kernel(const R* __restrict__ rec, int ng, int C, int ipw, int Hmax,
-                                                      int nseg, double* __restrict__ tpart, R* __restrict__ spart,
-                                                      Box<R> box) {
+template <typename R, class Body, int NB = 4, int NS = 1>
+__global__ __launch_bounds__(64 * NB * NS) void sym_kernel(const R* __restrict__ rec, int ng, int C, int ipw,
+                                                           int Hmax, int nseg, double* __restrict__ tpart,
+                                                           R* __restrict__ spart, Box<R> box) {
+    static_assert(NS == 1 || NB == 1, "step segments within a workgroup need one target block");
     using L = SymLane<R, Body>;
     using VT = typename Vec<R>::T;
     constexpr int NQ = L::NQ;
     constexpr int G = 64 * NB;
+    constexpr int NW = NB * NS;   // waves
     constexpr int VS = 128 * NB;  // tile entries per vector slot
     // FP64: source sums by LDS atomics (one wave per source block and phase);
     // FP32: by the DPP rotation, then across the waves through `red` (LDS
@@ -269,7 +274,9 @@ __global__ __launch_bounds__(64 * NB) void sym_kernel(const R* __restrict__ rec,
     // ones are faster).
     constexpr bool kLds = sizeof(R) == 8;
     __shared__ VT tile[L::NV * VS];
-    __shared__ R sacc[kLds ? NB : 1][kLds ? NQ : 1][kLds ? 128 : 1];  // per source block, slots l + s
+    // per source block (NS = 1) or per step segment (NS > 1), slots l + s
+    __shared__ R sacc[kLds ? NW : 1][kLds ? NQ : 1][kLds ? 128 : 1];
+    __shared__ double tred[NS > 1 ? NS : 1][NS > 1 ? NQ : 1][NS > 1 ? 64 : 1];  // target sums of the step segments
     // FP32 with more than three quantities per blob (the VJP, several
     // right-hand sides): the NB phases' passes are added into one row of G
     // slots per quantity in phase order, with a barrier between phases, which
@@ -277,13 +284,16 @@ __global__ __launch_bounds__(64 * NB) void sym_kernel(const R* __restrict__ rec,
     // three (the product) the waves write separate rows and one barrier
     // follows the last phase (fewer barriers, and occupancy is bounded by
     // registers there).
-    constexpr bool kPhased = !kLds && NQ > 3;
-    __shared__ R red[kLds ? 1 : (kPhased ? 1 : NB)][kLds ? 1 : NQ][kLds ? 1 : G];
+    constexpr bool kPhased = !kLds && NQ > 3 && NS == 1;
+    __shared__ R red[kLds ? 1 : (kPhased ? 1 : NW)][kLds ? 1 : NQ][kLds ? 1 : G];
     const int g = blockIdx.x % nseg, P = blockIdx.x / nseg / C, c = blockIdx.x / nseg % C;
-    const int s0 = g * (64 / nseg), s1 = s0 + 64 / nseg;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int w = NS > 1 ? 0 : wave;     // target block of the wave
+    const int seg = NS > 1 ? wave : 0;   // step segment of the wave
+    const int s0 = (g * NS + seg) * (64 / (nseg * NS)), s1 = s0 + 64 / (nseg * NS);
+    const bool loader = NS == 1 || threadIdx.x < G;  // one thread per record of a group
     L me;
-    me.load(rec + ((int64_t)P * G + threadIdx.x) * L::RW);
+    me.load(rec + ((int64_t)P * G + w * 64 + l) * L::RW);
     const int H = sym_rowlen(P, ng);
     const int d0 = c * ipw;
     const int d1 = d0 + ipw - 1 < H ? d0 + ipw - 1 : H;
@@ -291,17 +301,19 @@ __global__ __launch_bounds__(64 * NB) void sym_kernel(const R* __restrict__ rec,
         const int Q = (P + d) % ng;
         __syncthreads();
         {
-            const VT* gr = reinterpret_cast<const VT*>(rec + ((int64_t)Q * G + threadIdx.x) * L::RW);
             const int b = threadIdx.x >> 6, j = threadIdx.x & 63;
+            if (loader) {
+                const VT* gr = reinterpret_cast<const VT*>(rec + ((int64_t)Q * G + threadIdx.x) * L::RW);
 #pragma unroll
-            for (int v = 0; v < L::NV; ++v) {
-                const VT q = gr[v];
-                tile[v * VS + b * 128 + j] = q;
-                tile[v * VS + b * 128 + j + 64] = q;
+                for (int v = 0; v < L::NV; ++v) {
+                    const VT q = gr[v];
+                    tile[v * VS + b * 128 + j] = q;
+                    tile[v * VS + b * 128 + j + 64] = q;
+                }
             }
             if constexpr (kLds) {
                 R* z = &sacc[0][0][0];
-                for (int e = threadIdx.x; e < NB * NQ * 128; e += blockDim.x) z[e] = R(0);
+                for (int e = threadIdx.x; e < NW * NQ * 128; e += blockDim.x) z[e] = R(0);
             }
         }
         __syncthreads();
@@ -314,7 +326,8 @@ __global__ __launch_bounds__(64 * NB) void sym_kernel(const R* __restrict__ rec,
             } else if (d == 0 && blk == w) {
                 me.template pass<false>(tile, VS, blk, l, nullptr, S, box, s0, s1);
             } else {
-                me.template pass<true>(tile, VS, blk, l, kLds ? &sacc[blk][0][0] : nullptr, S, box, s0, s1);
+                me.template pass<true>(tile, VS, blk, l, kLds ? &sacc[NS > 1 ? seg : blk][0][0] : nullptr, S, box,
+                                       s0, s1);
             }
             if constexpr (kPhased) {
                 R* slot = &red[0][0][blk * 64 + ((l + s1) & 63)];
@@ -322,30 +335,52 @@ __global__ __launch_bounds__(64 * NB) void sym_kernel(const R* __restrict__ rec,
                 for (int q = 0; q < NQ; ++q) slot[q * G] = bb == 0 ? S[q] : slot[q * G] + S[q];
             } else if constexpr (!kLds) {
 #pragma unroll
-                for (int q = 0; q < NQ; ++q) red[w][q][blk * 64 + ((l + s1) & 63)] = S[q];
+                for (int q = 0; q < NQ; ++q) red[wave][q][blk * 64 + ((l + s1) & 63)] = S[q];
             }
             if constexpr (kLds || kPhased) __syncthreads();  // one wave per source block in every phase
         }
         if constexpr (!kLds && !kPhased) __syncthreads();
         R* out = spart + (((int64_t)Q * (Hmax + 1) + d) * nseg + g) * NQ * G;
         const int b = threadIdx.x >> 6, j = threadIdx.x & 63;
+        if (loader) {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            if constexpr (kLds) {
-                out[q * G + threadIdx.x] = sacc[b][q][j] + sacc[b][q][j + 64];
-            } else if constexpr (kPhased) {
-                out[q * G + threadIdx.x] = red[0][q][threadIdx.x];
-            } else {
-                R t = red[0][q][threadIdx.x];
+            for (int q = 0; q < NQ; ++q) {
+                if constexpr (kLds && NS > 1) {
+                    R t = sacc[0][q][j] + sacc[0][q][j + 64];
 #pragma unroll
-                for (int k = 1; k < NB; ++k) t += red[k][q][threadIdx.x];
-                out[q * G + threadIdx.x] = t;
+                    for (int k = 1; k < NS; ++k) t += sacc[k][q][j] + sacc[k][q][j + 64];
+                    out[q * G + threadIdx.x] = t;
+                } else if constexpr (kLds) {
+                    out[q * G + threadIdx.x] = sacc[b][q][j] + sacc[b][q][j + 64];
+                } else if constexpr (kPhased) {
+                    out[q * G + threadIdx.x] = red[0][q][threadIdx.x];
+                } else {
+                    R t = red[0][q][threadIdx.x];
+#pragma unroll
+                    for (int k = 1; k < NW; ++k) t += red[k][q][threadIdx.x];
+                    out[q * G + threadIdx.x] = t;
+                }
             }
         }
     }
     double* tp = tpart + (int64_t)blockIdx.x * NQ * G;  // chunk c * nseg + g of row P
+    if constexpr (NS > 1) {
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) tp[q * G + threadIdx.x] = me.total(q);
+        for (int q = 0; q < NQ; ++q) tred[seg][q][l] = me.total(q);
+        __syncthreads();
+        if (threadIdx.x < G) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                double t = tred[0][q][l];
+#pragma unroll
+                for (int k = 1; k < NS; ++k) t += tred[k][q][l];
+                tp[q * G + threadIdx.x] = t;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) tp[q * G + threadIdx.x] = me.total(q);
+    }
 }
 
 // Part u of U of the sum of quantity q of blob i over the chunk target

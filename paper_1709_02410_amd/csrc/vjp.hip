@@ -244,7 +244,7 @@ bool vjp_sym_plan(int64_t N, int prec, int ipw, int G, int* ng, int* C, int* Hma
     *C = (*Hmax + 1 + ipw - 1) / ipw;
     *tb = align_up((size_t)*ng * *C * kQ * G * sizeof(double));
     *sb = align_up((size_t)*ng * (*Hmax + 1) * kQ * G * real_size(prec));
-    return *tb <= ((size_t)4 << 30) && *sb <= ((size_t)4 << 30);
+    return *tb <= kSymPartialMaxBytes && *sb <= kSymPartialMaxBytes;
 }
 
 template <typename R, int NB>

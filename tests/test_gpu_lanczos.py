@@ -1,5 +1,9 @@
 """GPU preconditioned Lanczos (Sec. II.B) against the oracle's Lanczos and
-dense square roots."""
+dense square roots.  Small cases run both drivers: the fused one (four
+launches per step, used whenever the product goes through the symmetric
+kernel) and the unfused one."""
+import contextlib
+
 import numpy as np
 import pytest
 
@@ -27,13 +31,30 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+@contextlib.contextmanager
+def _path(rp, N, fused, prec=0):
+    """fused: force the symmetric product for this size class, which makes
+    the Lanczos driver take its fused four-launch steps (it does so whenever
+    the product is symmetric); otherwise the size's default shape (below 512
+    blobs the plain product, whose steps are not fused)."""
+    if fused:
+        rp.set_shape(prec, N, 1, tpl=1, tile=256, kblk=1, sym=2, ipw=1)
+    try:
+        yield
+    finally:
+        if fused:
+            rp.reset_shape(prec, N, 1)
+
+
+@pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("bodies", [True, False])
-def test_small_against_dense_root(rp, orc, bodies):
+def test_small_against_dense_root(rp, orc, bodies, fused):
     pos, offs = wl.boomerang_suspension(12, 25.0, 1.5, 4.0, seed=3)
     offs = offs if bodies else None
     W = wl.gaussian(pos.shape, 4)
     ref = orc.dense_sqrt(pos, W, offs)
-    out, it, err, ok = rp.lanczos_sqrt(_t(pos), _t(W), body_offsets=offs, tol=1e-10)
+    with _path(rp, len(pos), fused):
+        out, it, err, ok = rp.lanczos_sqrt(_t(pos), _t(W), body_offsets=offs, tol=1e-10)
     got = out.cpu().numpy()
     print(f"dense-root bodies={bodies} iters={it}", flush=True)
     assert ok
@@ -70,29 +91,33 @@ def test_per_blob_preconditioner_config0(rp, orc):
     check(out.cpu().numpy(), ref, 1e-7, "C0 per-blob preconditioner lanczos")
 
 
-def test_not_converged_returns_best_iterate(rp, orc):
+@pytest.mark.parametrize("fused", [False, True])
+def test_not_converged_returns_best_iterate(rp, orc, fused):
     pos, offs = wl.boomerang_suspension(8, 20.0, 1.5, 4.0, seed=5)
     W = wl.gaussian(pos.shape, 6)
-    out, it, err, ok = rp.lanczos_sqrt(_t(pos), _t(W), body_offsets=offs, tol=1e-14, max_iter=3)
-    ref, it_o, _, ok_o = orc.lanczos_sqrt(pos, W, offs, tol=1e-14, max_iter=3)
-    assert not ok and not ok_o and it == 3 and it_o == 3
-    check(out.cpu().numpy(), ref, 1e-12, "lanczos best iterate after max_iter")
-    with pytest.raises(rp.RpywError):
-        rp.lanczos_sqrt(_t(pos), _t(W), body_offsets=offs, tol=1e-14, max_iter=3, strict=True)
+    with _path(rp, len(pos), fused):
+        out, it, err, ok = rp.lanczos_sqrt(_t(pos), _t(W), body_offsets=offs, tol=1e-14, max_iter=3)
+        ref, it_o, _, ok_o = orc.lanczos_sqrt(pos, W, offs, tol=1e-14, max_iter=3)
+        assert not ok and not ok_o and it == 3 and it_o == 3
+        check(out.cpu().numpy(), ref, 1e-12, f"lanczos best iterate after max_iter fused={fused}")
+        with pytest.raises(rp.RpywError):
+            rp.lanczos_sqrt(_t(pos), _t(W), body_offsets=offs, tol=1e-14, max_iter=3, strict=True)
 
 
-def test_non_spd_block_is_reported(rp):
+@pytest.mark.parametrize("fused", [False, True])
+def test_non_spd_block_is_reported(rp, fused):
     """A body with a blob on the wall (B = 0) has a singular block."""
     pos, offs = wl.boomerang_suspension(2, 10.0, 1.5, 2.0, seed=7)
     pos[3, 2] = 0.0
     W = wl.gaussian(pos.shape, 1)
-    with pytest.raises(rp.RpywError) as ei:
+    with _path(rp, len(pos), fused), pytest.raises(rp.RpywError) as ei:
         rp.lanczos_sqrt(_t(pos), _t(W), body_offsets=offs, tol=1e-6)
     assert ei.value.status == rp.ENOTSPD
 
 
+@pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("N,bodies", [(1, False), (2, False), (15, True)])
-def test_exhausted_krylov_space(rp, orc, N, bodies):
+def test_exhausted_krylov_space(rp, orc, N, bodies, fused):
     """Tiny problems whose Krylov space is exhausted within a few steps (3N
     at most; one body with the block preconditioner: the preconditioned
     operator is the identity, one step): beta reaches zero, which the
@@ -106,16 +131,19 @@ def test_exhausted_krylov_space(rp, orc, N, bodies):
         offs = None
     W = wl.gaussian(pos.shape, 9)
     ref = orc.dense_sqrt(pos, W, offs)
-    out, it, err, ok = rp.lanczos_sqrt(_t(pos), _t(W), body_offsets=offs, tol=1e-12, max_iter=3 * len(pos) + 4)
+    with _path(rp, len(pos), fused):
+        out, it, err, ok = rp.lanczos_sqrt(_t(pos), _t(W), body_offsets=offs, tol=1e-12, max_iter=3 * len(pos) + 4)
     got = out.cpu().numpy()
     print(f"exhausted N={len(pos)} bodies={bodies} iters={it}", flush=True)
     assert ok and it <= 3 * len(pos)
     check(got, ref, 1e-11, f"exhausted Krylov space N={len(pos)}")
 
 
-def test_zero_vector(rp):
+@pytest.mark.parametrize("fused", [False, True])
+def test_zero_vector(rp, fused):
     pos, offs = wl.boomerang_suspension(2, 10.0, 1.5, 2.0, seed=7)
-    out, it, err, ok = rp.lanczos_sqrt(_t(pos), _t(np.zeros_like(pos)), body_offsets=offs)
+    with _path(rp, len(pos), fused):
+        out, it, err, ok = rp.lanczos_sqrt(_t(pos), _t(np.zeros_like(pos)), body_offsets=offs)
     assert ok and it == 0 and float(out.abs().max()) == 0.0
 
 
@@ -148,7 +176,8 @@ def test_iterations_independent_of_size(rp):
     assert max(pc) <= 8 and max(pc) - min(pc) <= 1
 
 
-def test_largest_bodies_42_blobs(rp, orc):
+@pytest.mark.parametrize("fused", [False, True])
+def test_largest_bodies_42_blobs(rp, orc, fused):
     """Bodies of the largest supported size (42 blobs, a 6 x 7 plate; the
     preconditioner factors need 129 KB of LDS) next to small ones: the
     Lanczos root and the rigid solve against the oracle."""
@@ -157,7 +186,8 @@ def test_largest_bodies_42_blobs(rp, orc):
     pos = np.concatenate([plate, plate + [16.0, 0.0, 0.5], plate[[0, 1, 6, 7, 13]] + [0.0, 16.0, 0.0]])
     offs = np.array([0, 42, 84, 89])
     W = wl.gaussian(pos.shape, 21)
-    out, it, err, ok = rp.lanczos_sqrt(_t(pos), _t(W), body_offsets=offs, tol=1e-10)
+    with _path(rp, len(pos), fused):
+        out, it, err, ok = rp.lanczos_sqrt(_t(pos), _t(W), body_offsets=offs, tol=1e-10)
     ref = orc.dense_sqrt(pos, W, offs)
     assert ok
     check(out.cpu().numpy(), ref, 1e-8, "42-blob bodies lanczos")
@@ -169,12 +199,18 @@ def test_largest_bodies_42_blobs(rp, orc):
     check(U.cpu().numpy(), U_ref, 1e-8, "42-blob bodies rigid U")
 
 
-def test_back_to_back_calls_and_two_streams(rp, orc):
+@pytest.mark.parametrize("fused", [False, True])
+def test_back_to_back_calls_and_two_streams(rp, orc, fused):
     """The solvers return with their last kernels (and up to two speculative
     steps) still queued, and their pinned scalar slots are shared between
     calls: several Lanczos roots and rigid solves issued back to back, on one
     stream and on two streams, without synchronising in between, equal the
     same calls made one at a time."""
+    with _path(rp, 180, fused):
+        _back_to_back(rp)
+
+
+def _back_to_back(rp):
     pos, offs = wl.boomerang_suspension(12, 25.0, 1.5, 4.0, seed=8)
     Ws = [wl.gaussian(pos.shape, 40 + i) for i in range(4)]
     q = pos[offs[:-1]].copy()

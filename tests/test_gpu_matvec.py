@@ -238,3 +238,23 @@ def test_calibration_kernel_computes_its_recurrence(rp, kind):
             x = [xk * b + c for xk in x]
         s = sum(x[1:], x[0])
         assert np.allclose(out, s, rtol=1e-14)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_5e5_blobs_symmetric_sampled_rows(rp, orc, prec):
+    """5e5 blobs (the headline density, box 1341.6): the default shape is
+    the symmetric kernel (its partial sums, about 6 and 12 GB here, are
+    within the library's limit), checked on 96 sampled rows plus the first
+    and the last against the oracle."""
+    cfg = wl.headline(seed=3, N=500_000)
+    sh = rp.get_shape(prec, cfg.N, 1)
+    print(f"5e5 shape prec={prec}: {sh}", flush=True)
+    assert sh["sym"] == 1
+    # the workspace includes the symmetric plan's partials only when the plan
+    # is admitted (the plain kernel's would be under 0.2 GB)
+    assert rp.workspace_bytes(rp.OP_MATVEC, cfg.N, 1, precision=prec) > (4 << 30)
+    f = wl.gaussian(cfg.pos.shape, 4)
+    got = rp.matvec(_t(cfg.pos), _t(f), precision=prec).cpu().numpy()
+    rows = np.concatenate([np.random.default_rng(9).choice(cfg.N, 96, replace=False), [0, cfg.N - 1]])
+    check(got[rows], orc.matvec(cfg.pos, f, rows=rows), TOL[prec], f"5e5 prec={prec} sampled rows")
+    torch.cuda.empty_cache()
