@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librpywall.so")
 SOURCES = ["api.hip", "pair_kernels.hip", "krylov.hip", "lanczos.hip", "rigid.hip", "ts.hip", "vjp.hip",
-           "settings.hip", "calibrate.hip", "lanczos_step.hip"]
+           "settings.hip", "calibrate.hip", "lanczos_step.hip", "rigid_step.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -29,6 +29,7 @@
 #include <cmath>
 #include <vector>
 
+#include "krylov_step.h"
 #include "records.h"
 #include "rpyw_internal.h"
 #include "sym_pairs.h"
@@ -37,124 +38,12 @@ namespace rpyw {
 
 namespace {
 
+using namespace kstep;
+
 constexpr int kVinThreads = 256;
 constexpr int kOutThreads = 512;
 constexpr int kGs2Threads = 256;
-constexpr int kPre = 16;  // values loaded ahead of use per thread
 constexpr int kVinReg = 64;  // basis values vin keeps in registers
-
-// Sum over groups of G consecutive lanes (fixed butterfly order).
-template <int G>
-__device__ __forceinline__ double lane_group_sum(double s) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    return s;
-}
-
-// out[r] = sum over c < ncol of partial[r ncol + c], r < nrows, by a
-// workgroup of T threads: LPR lanes per row, lane q adding the columns
-// c = q (mod LPR) in increasing order (PRE loads in flight), then an
-// LPR-lane butterfly.  Ends with a barrier.
-template <int T, int LPR = 8, int PRE = kPre>
-__device__ void reduce_rows(const double* __restrict__ partial, int nrows, int ncol, double* out) {
-    constexpr int kRows = T / LPR;
-    const int rq = threadIdx.x / LPR, q = threadIdx.x % LPR;
-    for (int r0 = 0; r0 < nrows; r0 += kRows) {
-        const int r = r0 + rq;
-        double s = 0.0;
-        if (r < nrows) {
-            const double* p = partial + (int64_t)r * ncol;
-            for (int c = q; c < ncol; c += LPR * PRE) {
-                // every load in bounds (the last column for the tail), so
-                // that they issue without branches; the tail is not added
-                double v[PRE];
-#pragma unroll
-                for (int i = 0; i < PRE; ++i) v[i] = p[c + LPR * i < ncol ? c + LPR * i : ncol - 1];
-#pragma unroll
-                for (int i = 0; i < PRE; ++i)
-                    if (c + LPR * i < ncol) s += v[i];
-            }
-        }
-        s = lane_group_sum<LPR>(s);
-        if (q == 0 && r < nrows) out[r] = s;
-    }
-    __syncthreads();
-}
-
-// Sum of the target-chunk and source-item partials of quantity q of blob i
-// (layout of sym_kernel) taken by share u of U: chunks c and items d with
-// c, d = u (mod U), in increasing order, sixteen loads in flight.
-template <typename R>
-__device__ double gather_share(const double* __restrict__ tpart, const R* __restrict__ spart, int64_t i, int ng,
-                               int C, int Hmax, int nseg, int G, int q, int u, int U) {
-    const int P = (int)(i / G), t = (int)(i % G);
-    const int Cs = C * nseg;
-    const int nd = (sym_dmax(P, ng) + 1) * nseg;
-    const int64_t st = (int64_t)3 * G;
-    const double* tp = tpart + ((int64_t)P * Cs * 3 + q) * G + t;
-    const R* sp = spart + ((int64_t)P * (Hmax + 1) * nseg * 3 + q) * G + t;
-    double s = 0.0;
-    for (int c = u; c < Cs; c += U * kPre) {
-        double v[kPre];
-#pragma unroll
-        for (int k = 0; k < kPre; ++k) v[k] = c + U * k < Cs ? tp[(c + U * k) * st] : 0.0;
-#pragma unroll
-        for (int k = 0; k < kPre; ++k) s += v[k];
-    }
-    for (int d = u; d < nd; d += U * kPre) {
-        double v[kPre];
-#pragma unroll
-        for (int k = 0; k < kPre; ++k) v[k] = d + U * k < nd ? (double)sp[(d + U * k) * st] : 0.0;
-#pragma unroll
-        for (int k = 0; k < kPre; ++k) s += v[k];
-    }
-    return s;
-}
-
-// A contiguous range of up to NT M values held in registers, NT threads
-// taking every NT-th: load issues all of a thread's loads at once (only
-// whole batches of NT that the range reaches), store writes them to LDS
-// later, so that the loads overlap other work instead of each waiting for
-// its value before the next is issued.
-constexpr int kLdsFactor = 64 * 64;
-template <int NT, int M>
-struct Staged {
-    double v[M];
-    __device__ __forceinline__ void load(const double* __restrict__ F, int len) {
-#pragma unroll
-        for (int i = 0; i < M; ++i) {
-            if (i * NT >= len) break;  // uniform
-            const int q = (int)threadIdx.x + i * NT;
-            v[i] = F[q < len ? q : 0];
-        }
-    }
-    __device__ __forceinline__ void store(double* Lds, int len) const {
-#pragma unroll
-        for (int i = 0; i < M; ++i) {
-            if (i * NT >= len) break;
-            const int q = (int)threadIdx.x + i * NT;
-            if (q < len) Lds[q] = v[i];
-        }
-    }
-};
-
-// Sum over j < len of F[j * fs] x[j] in four partial sums (j = i (mod 4)),
-// added pairwise.  The loop body has no branches, so that its LDS reads
-// issue together; the last len mod 4 terms follow.
-__device__ __forceinline__ double dot4(const double* __restrict__ F, int fs, const double* __restrict__ x,
-                                       int len) {
-    double s4[4] = {0.0, 0.0, 0.0, 0.0};
-    int j = 0;
-#pragma unroll 2
-    for (; j + 4 <= len; j += 4) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) s4[i] = fma(F[(j + i) * fs], x[j + i], s4[i]);
-    }
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-        if (j + i < len) s4[i] = fma(F[(j + i) * fs], x[j + i], s4[i]);
-    return (s4[0] + s4[1]) + (s4[2] + s4[3]);
-}
 
 template <typename R>
 __global__ __launch_bounds__(kVinThreads) void lz_vin_kernel(int diag, const int* __restrict__ units,
@@ -378,11 +267,50 @@ __device__ __forceinline__ void publish_step(int k, const double* c1, double* __
     h_flag[k] = 1.0;
 }
 
+// GMRES form of the end of gs2: the last block to finish (an atomic
+// ticket; no block waits) adds up c2 = V^T y' and |y'|^2 from all blocks'
+// partials in a fixed order, forms h = (|y'|^2 - |c2|^2)^{1/2}, and stores
+// fin = [c2 (k + 1 values), h] for the next step's first kernel and the
+// Hessenberg column [c1, c2, h] into the host slot hcol, then (after a
+// system-scope fence) the step's flag; it re-arms the ticket.
+__device__ void gs2_finish(int k, int nblk, const double* c1, const double* __restrict__ part2,
+                           double* __restrict__ fin, unsigned* __restrict__ ticket, double* __restrict__ hcol,
+                           double* __restrict__ h_flag) {
+    __shared__ double c2[kLanczosFusedMaxIter + 2];
+    __shared__ bool last;
+    const int t = threadIdx.x;
+    __threadfence();
+    __syncthreads();
+    if (t == 0) last = atomicAdd(ticket, 1u) == (unsigned)nblk - 1u;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    reduce_rows<kGs2Threads, 4, kPre>(part2, k + 2, nblk, c2);  // c2[0..k], then |y'|^2
+    for (int j = t; j <= k; j += kGs2Threads) {
+        fin[j] = c2[j];
+        hcol[j] = c1[j];
+        hcol[k + 1 + j] = c2[j];
+    }
+    if (t == 0) {
+        double s2 = c2[k + 1];
+        for (int j = 0; j <= k; ++j) s2 -= c2[j] * c2[j];
+        const double h = s2 > 0.0 ? sqrt(s2) : 0.0;
+        fin[k + 1] = h;
+        hcol[2 * (k + 1)] = h;
+        *ticket = 0u;
+    }
+    __threadfence_system();
+    __syncthreads();
+    if (t == 0) h_flag[k] = 1.0;
+}
+
 __global__ __launch_bounds__(kGs2Threads) void lz_gs2_kernel(const double* __restrict__ w, double* __restrict__ yo,
                                                              int64_t n3, int m, const double* __restrict__ V, int k,
                                                              const double* __restrict__ part1, int ngroups,
                                                              double* __restrict__ part2, double* __restrict__ d_ab,
-                                                             double* __restrict__ h_ab, double* __restrict__ h_flag) {
+                                                             double* __restrict__ h_ab, double* __restrict__ h_flag,
+                                                             double* __restrict__ fin, unsigned* __restrict__ ticket,
+                                                             double* __restrict__ hcol) {
     constexpr int kBatch = 32;  // results per pass through the tile
     __shared__ double c1[kLanczosFusedMaxIter + 1];
     __shared__ double tile[kBatch][kGs2Threads + 1];
@@ -405,7 +333,7 @@ __global__ __launch_bounds__(kGs2Threads) void lz_gs2_kernel(const double* __res
             for (int j = j0; j < j0 + 16; ++j) a[j] = V[(j <= k ? j : 0) * n3 + bc];
         }
         reduce_rows<kGs2Threads, 4, kPre>(part1, k + 1, ngroups, c1);  // one pass over up to 64 rows
-        publish_step(k, c1, d_ab, h_ab, h_flag);
+        if (!fin) publish_step(k, c1, d_ab, h_ab, h_flag);
 #pragma unroll
         for (int j = 0; j < kGs2Reg; ++j)
             if (j <= k) v -= c1[j] * a[j];
@@ -438,11 +366,12 @@ __global__ __launch_bounds__(kGs2Threads) void lz_gs2_kernel(const double* __res
             if (c0 == 0 && jr < jn) part2[(int64_t)(j0 + jr) * nblk + blockIdx.x] = s;
             __syncthreads();
         }
+        if (fin) gs2_finish(k, nblk, c1, part2, fin, ticket, hcol, h_flag);
         return;
     }
     // general path: several entries per thread or many basis vectors
     reduce_rows<kGs2Threads>(part1, k + 1, ngroups, c1);
-    publish_step(k, c1, d_ab, h_ab, h_flag);
+    if (!fin) publish_step(k, c1, d_ab, h_ab, h_flag);
     double x[kLanczosGs2PerThread];
 #pragma unroll
     for (int r = 0; r < kLanczosGs2PerThread; ++r) {
@@ -488,6 +417,7 @@ __global__ __launch_bounds__(kGs2Threads) void lz_gs2_kernel(const double* __res
         if (c0 == 0 && jr < jn) part2[(int64_t)(j0 + jr) * nblk + blockIdx.x] = s;
         __syncthreads();
     }
+    if (fin) gs2_finish(k, nblk, c1, part2, fin, ticket, hcol, h_flag);
 }
 
 }  // namespace
@@ -568,11 +498,12 @@ int lz_launch_out(int prec, const BodyFactors& pc, const int* units, const Lancz
 }
 
 int lz_launch_gs2(const double* w, double* yo, int64_t n3, const double* V, int k, const double* part1, int ngroups,
-                  double* part2, double* d_ab, double* h_ab, double* h_flag, hipStream_t st) {
+                  double* part2, double* d_ab, double* h_ab, double* h_flag, hipStream_t st, double* fin,
+                  unsigned* ticket, double* hcol) {
     int m;
     const int64_t nb = lanczos_gs2_blocks(n3, &m);
     hipLaunchKernelGGL(lz_gs2_kernel, dim3((unsigned)nb), dim3(kGs2Threads), 0, st, w, yo, n3, m, V, k, part1, ngroups,
-                       part2, d_ab, h_ab, h_flag);
+                       part2, d_ab, h_ab, h_flag, fin, ticket, hcol);
     RPYW_HIP(hipGetLastError());
     return RPYW_OK;
 }

@@ -22,6 +22,9 @@
 // h_{k+1,k} on the device, so for small problems it is queued before the
 // host has examined step k (and is discarded if step k converged).
 #include <algorithm>
+#include <mutex>
+#include <cstring>
+#include <atomic>
 #include <cmath>
 #include <vector>
 
@@ -253,6 +256,55 @@ __global__ void rigid_rhs_kernel(const double* __restrict__ slip, const double* 
 
 PinnedSlots g_h;  // Hessenberg columns, one slot per step in flight
 
+// Host side of Arnoldi step k: applies the previous Givens rotations to
+// column k of H (h: k + 2 entries), forms rotation k, appends the rotated
+// column to R and updates g = Q^T (beta e1).  Returns false when the
+// residual estimate |g_{k+1}| / beta (into *res) is not finite; *hk1 is
+// h_{k+1,k} as computed.
+bool givens_column(std::vector<double>& h, int k, std::vector<std::vector<double>>& R, std::vector<double>& cs,
+                   std::vector<double>& sn, std::vector<double>& g, double beta, double* res, double* hk1) {
+    for (int j = 0; j < k; ++j) {
+        const double t0 = cs[j] * h[j] + sn[j] * h[j + 1];
+        h[j + 1] = -sn[j] * h[j] + cs[j] * h[j + 1];
+        h[j] = t0;
+    }
+    const double rr = std::hypot(h[k], h[k + 1]);
+    const double c = rr > 0.0 ? h[k] / rr : 1.0, s = rr > 0.0 ? h[k + 1] / rr : 0.0;
+    cs.push_back(c);
+    sn.push_back(s);
+    *hk1 = h[k + 1];
+    h[k] = rr;
+    h.resize(k + 1);
+    R.push_back(h);
+    g.push_back(-s * g[k]);
+    g[k] = c * g[k];
+    *res = std::fabs(g[k + 1]) / beta;
+    return std::isfinite(*res);
+}
+
+// The GMRES solution: back substitution R y = g, then x = P^-1 (V y)
+// (precond: the preconditioner applied to a device vector, into the
+// caller's outputs).
+template <class Precond>
+int rigid_finish(const std::vector<std::vector<double>>& R, const std::vector<double>& g, double res,
+                 bool converged, int* iters, double* res_out, double* d_y, const double* V, int64_t n, double* tmp,
+                 hipStream_t st, Precond precond) {
+    const int m = (int)R.size();
+    *iters = m;
+    *res_out = res;
+    std::vector<double> yv(m);
+    for (int i = m - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int j = i + 1; j < m; ++j) s -= R[j][i] * yv[j];
+        yv[i] = R[i][i] != 0.0 ? s / R[i][i] : 0.0;
+    }
+    int rc;
+    if ((rc = stage_upload(yv.data(), m * sizeof(double), d_y, st))) return rc;
+    if ((rc = vec_comb(V, n, m, d_y, tmp, n, st))) return rc;
+    if ((rc = precond(tmp))) return rc;
+    return converged ? RPYW_OK : RPYW_NOT_CONVERGED;
+}
+
 }  // namespace
 
 size_t rigid_ws_bytes(int64_t N, int max_iter, int n_bodies, int prec) {
@@ -268,13 +320,194 @@ size_t rigid_ws_bytes(int64_t N, int max_iter, int n_bodies, int prec) {
     b += 4 * align_up((m + 8) * sizeof(double));              // c1, c2, norms, coefficients
     b += align_up(sizeof(unsigned)) + align_up(sizeof(int));  // ticket, notspd
     b += product_ws_bytes(N, prec, 1);
-    return b + 16 * kAlign;
+    // fused steps: y', the block partials of both projections, c2 and h
+    int m4;
+    b += align_up(n * sizeof(double));
+    b += align_up((m + 2) * (size_t)std::max(n_bodies, 1) * sizeof(double));
+    b += align_up((m + 3) * (size_t)lanczos_gs2_blocks((int64_t)n, &m4) * sizeof(double));
+    b += align_up((m + 8) * sizeof(double));
+    return b + 24 * kAlign;
 }
+
+namespace {
+
+// The GMRES solve with fused four-launch Arnoldi steps (rigid_step.hip):
+// the same recurrence, preconditioner and host-side Givens rotations as the
+// driver below, with the product's records written by the preconditioner
+// kernel, the product gathered by the operator kernel, and the Hessenberg
+// column of step k published by its last kernel (a flag in pinned memory
+// instead of an event between steps).
+int rigid_fused(const double* pos, const double* q, const int64_t* body_offsets, int n_bodies, const double* slip,
+                const double* FT, double* lam_out, double* U_out, int64_t N, double a, double eta, double tol,
+                int max_iter, int prec, Arena& ar, int* iters, double* res_out, hipStream_t st, const Domain& dom,
+                const BodyFactors* pre, const SymPlan& sp, int ipw) {
+    const int64_t n3 = 3 * N, n6 = 6 * (int64_t)n_bodies, n = n3 + n6;
+    *iters = 0;
+    *res_out = 0.0;
+    int m4;
+    const int64_t nblk4 = lanczos_gs2_blocks(n, &m4);
+    const int rw = rec_width(prec, 1);
+    const int64_t npad = (int64_t)sp.ng * sp.G;
+    BodyFactors pc;
+    double* Wall = (double*)ar.take((size_t)18 * N * sizeof(double));
+    double* Nall = (double*)ar.take((size_t)36 * n_bodies * sizeof(double));
+    double* V = (double*)ar.take((size_t)(max_iter + 1) * n * sizeof(double));
+    double* zb = (double*)ar.take(n * sizeof(double));  // z = P^-1 v_k
+    double* wb = (double*)ar.take(n * sizeof(double));  // w = A z
+    double* yb = (double*)ar.take(n * sizeof(double));  // y' = w - V c1
+    double* bv = (double*)ar.take(n * sizeof(double));
+    double* partial = (double*)ar.take((size_t)2 * dot_chunks(n) * sizeof(double));  // |b|
+    double* part1 = (double*)ar.take((size_t)(max_iter + 2) * n_bodies * sizeof(double));
+    double* part2 = (double*)ar.take((size_t)(max_iter + 3) * nblk4 * sizeof(double));
+    double* fin = (double*)ar.take((max_iter + 8) * sizeof(double));  // c2 and h of the last step
+    double* d_b = (double*)ar.take(8 * sizeof(double));
+    double* d_y = (double*)ar.take((max_iter + 8) * sizeof(double));
+    unsigned* ticket = (unsigned*)ar.take(kAlign);
+    int* notspd = (int*)ar.take(sizeof(int));
+    void* rec = ar.take((size_t)npad * rw * real_size(prec));
+    double* B = (double*)ar.take((size_t)npad * sizeof(double));
+    double* tpart = (double*)ar.take(sp.tpart_bytes);
+    void* spart = ar.take(sp.spart_bytes);
+    if (!Wall || !Nall || !V || !zb || !wb || !yb || !bv || !partial || !part1 || !part2 || !fin || !d_b || !d_y ||
+        !ticket || !notspd || !rec || !B || !tpart || !spart)
+        return RPYW_ENOMEM;
+    std::lock_guard<std::mutex> lk(g_h.mu);
+    const int slot = 2 * (max_iter + 2);  // c1[0..k], c2[0..k], h_{k+1,k}
+    int rc = g_h.reserve(((size_t)PinnedSlots::kSlots * slot + 2 + (max_iter + 2)) * sizeof(double));
+    if (rc) return rc;
+    SlotRelease slots_done{g_h, st};
+    double* h_slot = g_h.p;
+    double* h_b = h_slot + (size_t)PinnedSlots::kSlots * slot;
+    int* h_bad = (int*)(h_b + 1);
+    double* h_flag = h_b + 2;
+    double* dh_flag = g_h.dp + (h_flag - h_slot);
+    std::memset(h_flag, 0, (size_t)(max_iter + 2) * sizeof(double));
+
+    RPYW_HIP(hipMemsetAsync(notspd, 0, sizeof(int), st));
+    RPYW_HIP(hipMemsetAsync(ticket, 0, sizeof(unsigned), st));
+    if (pre)
+        pc = *pre;
+    else if ((rc = body_factors_build(pos, N, a, eta, body_offsets, n_bodies, ar, st, pc, notspd)))
+        return rc;
+    hipLaunchKernelGGL(rigid_factors_kernel, dim3(n_bodies), dim3(kRT), 0, st, pos, q, pc.bofs, pc.lofs, pc.L, Wall,
+                       Nall, notspd);
+    RPYW_HIP(hipGetLastError());
+    hipLaunchKernelGGL(rigid_rhs_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, slip, FT, n3, n6, bv);
+    RPYW_HIP(hipGetLastError());
+    // positions and B once; the force slots are rewritten by every step
+    if ((rc = sym_pack(pos, bv, N, 1, 1, prec, sp, a, dom, rec, B, st))) return rc;
+    if ((rc = vec_dots(nullptr, n, 0, bv, n, partial, ticket, d_b, 0, nullptr, st))) return rc;  // |b|
+    h_bad[0] = h_bad[1] = 0;
+    RPYW_HIP(hipMemcpyAsync(h_b, d_b, sizeof(double), hipMemcpyDeviceToHost, st));
+    RPYW_HIP(hipMemcpyAsync(h_bad, notspd, sizeof(int), hipMemcpyDeviceToHost, st));
+    if (pre && pre->flag) RPYW_HIP(hipMemcpyAsync(h_bad + 1, pre->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    const double m0 = 1.0 / (6.0 * M_PI * eta * a);
+
+    auto launch_step = [&](int k) -> int {
+        int r;
+        if ((r = rg_launch_pre(prec, pc, Wall, Nall, n_bodies, n3, n, k ? yb : bv, fin, k ? fin + k : d_b, k, V, zb,
+                               zb + n3, rec, rw, B, st)))
+            return r;
+        if ((r = sym_launch(rec, sp, ipw, 1, prec, a, dom, tpart, spart, st))) return r;
+        if ((r = rg_launch_out(prec, pos, q, pc.bofs, n_bodies, tpart, spart, sp, B, m0, zb, zb + n3, n3, n, V, k, wb,
+                               part1, st)))
+            return r;
+        double* hs = g_h.dp + (size_t)(k % PinnedSlots::kSlots) * slot;
+        if ((r = lz_launch_gs2(wb, yb, n, V, k, part1, n_bodies, part2, nullptr, nullptr, dh_flag, st, fin, ticket,
+                               hs)))
+            return r;
+        // step 0 also waits for the set-up copies (|b|, the definiteness flags)
+        if (k == 0) RPYW_HIP(hipEventRecord(g_h.ev[0], st));
+        return RPYW_OK;
+    };
+    const int depth = (double)N * (double)N <= kSpeculatePairs ? kSpeculateDepth : 0;
+    int queued = 0;
+    auto fill = [&](int upto) -> int {  // queue steps up to index upto - 1
+        for (; queued < upto && queued < max_iter; ++queued)
+            if (int r = launch_step(queued)) return r;
+        return RPYW_OK;
+    };
+    // Waits for step k: its flag, polled; the stream is queried now and then
+    // so that a stream that drains without setting it ends the wait.
+    auto wait_step = [&](int k) -> int {
+        if (k == 0) {
+            RPYW_HIP(hipEventSynchronize(g_h.ev[0]));
+            return RPYW_OK;
+        }
+        const volatile double* f = h_flag + k;
+        for (unsigned spin = 1;; ++spin) {
+            if (*f != 0.0) break;
+            if ((spin & 4095) == 0) {
+                const hipError_t qs = hipStreamQuery(st);
+                if (qs == hipSuccess) {
+                    if (*f != 0.0) break;
+                    return RPYW_EHIP;
+                }
+                if (qs != hipErrorNotReady) return RPYW_EHIP;
+            }
+            __builtin_ia32_pause();
+        }
+        std::atomic_thread_fence(std::memory_order_acquire);
+        return RPYW_OK;
+    };
+
+    std::vector<std::vector<double>> R;
+    std::vector<double> cs, sn, g;
+    bool converged = false;
+    double beta = 0.0, res = 1.0, res1 = INFINITY, res2 = INFINITY;
+    int k = 0;
+    if ((rc = fill(1 + depth))) return rc;
+    for (; k < max_iter; ++k) {
+        if ((rc = wait_step(k))) return rc;
+        if (k == 0) {
+            beta = *h_b;
+            const bool bad = h_bad[0] || h_bad[1];
+            if (bad || !std::isfinite(beta) || beta == 0.0) {
+                RPYW_HIP(hipStreamSynchronize(st));
+                if (bad) return RPYW_ENOTSPD;
+                if (!std::isfinite(beta)) return RPYW_EINVAL;
+                RPYW_HIP(hipMemsetAsync(lam_out, 0, n3 * sizeof(double), st));
+                RPYW_HIP(hipMemsetAsync(U_out, 0, n6 * sizeof(double), st));
+                return RPYW_OK;
+            }
+            g.assign(1, beta);
+        }
+        const double* hs = h_slot + (size_t)(k % PinnedSlots::kSlots) * slot;
+        std::vector<double> h(k + 2);
+        for (int j = 0; j <= k; ++j) h[j] = hs[j] + hs[k + 1 + j];
+        h[k + 1] = hs[2 * (k + 1)];
+        if (depth && (rc = fill(speculate_to(k, depth, res1, res2, tol) + 1))) return rc;
+        double hk1;
+        if (!givens_column(h, k, R, cs, sn, g, beta, &res, &hk1)) return RPYW_EHIP;
+        if (res <= tol || hk1 <= 1e-14 * beta) {
+            converged = true;
+            break;
+        }
+        res2 = res1;
+        res1 = res;
+        if ((rc = fill(k + 2))) return rc;
+    }
+    return rigid_finish(R, g, res, converged, iters, res_out, d_y, V, n, wb, st, [&](const double* in) {
+        hipLaunchKernelGGL(rigid_precond_kernel, dim3(n_bodies), dim3(kRT), 0, st, pc.L, pc.bofs, pc.lofs, Wall, Nall,
+                           n3, in, in + n3, nullptr, nullptr, lam_out, U_out, V, n, nullptr, 0);
+        RPYW_HIP(hipGetLastError());
+        return RPYW_OK;
+    });
+}
+
+}  // namespace
 
 int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets, int n_bodies, const double* slip,
                 const double* FT, double* lam_out, double* U_out, int64_t N, double a, double eta, double tol,
                 int max_iter, int prec, Arena& ar, int* iters, double* res_out, hipStream_t st, const Domain& dom,
                 const BodyFactors* pre) {
+    {
+        SymPlan sp;
+        int ipw;
+        if (n_bodies > 0 && lanczos_fused_applies(N, prec, max_iter, dom, &sp, &ipw))
+            return rigid_fused(pos, q, body_offsets, n_bodies, slip, FT, lam_out, U_out, N, a, eta, tol, max_iter,
+                               prec, ar, iters, res_out, st, dom, pre, sp, ipw);
+    }
     const int64_t n3 = 3 * N, n6 = 6 * (int64_t)n_bodies, n = n3 + n6;
     *iters = 0;
     *res_out = 0.0;
@@ -399,23 +632,8 @@ int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets,
         for (int j = 0; j <= k; ++j) h[j] = hs[j] + hs[k + 1 + j];
         h[k + 1] = hs[2 * (k + 1)];
         if (depth && (rc = fill(speculate_to(k, depth, res1, res2, tol) + 1))) return rc;
-        for (int j = 0; j < k; ++j) {
-            const double t0 = cs[j] * h[j] + sn[j] * h[j + 1];
-            h[j + 1] = -sn[j] * h[j] + cs[j] * h[j + 1];
-            h[j] = t0;
-        }
-        const double rr = std::hypot(h[k], h[k + 1]);
-        const double c = rr > 0.0 ? h[k] / rr : 1.0, s = rr > 0.0 ? h[k + 1] / rr : 0.0;
-        cs.push_back(c);
-        sn.push_back(s);
-        const double hk1 = h[k + 1];
-        h[k] = rr;
-        h.resize(k + 1);
-        R.push_back(h);
-        g.push_back(-s * g[k]);
-        g[k] = c * g[k];
-        res = std::fabs(g[k + 1]) / beta;
-        if (!std::isfinite(res)) return RPYW_EHIP;
+        double hk1;
+        if (!givens_column(h, k, R, cs, sn, g, beta, &res, &hk1)) return RPYW_EHIP;
         if (res <= tol || hk1 <= 1e-14 * beta) {
             converged = true;
             break;
@@ -424,20 +642,8 @@ int rigid_solve(const double* pos, const double* q, const int64_t* body_offsets,
         res1 = res;
         if ((rc = fill(k + 2))) return rc;  // step k + 1, unless queued already
     }
-    const int m = (int)R.size();
-    *iters = m;
-    *res_out = res;
-    // Back substitution R y = g, then x = P^-1 (V y).
-    std::vector<double> yv(m);
-    for (int i = m - 1; i >= 0; --i) {
-        double s = g[i];
-        for (int j = i + 1; j < m; ++j) s -= R[j][i] * yv[j];
-        yv[i] = R[i][i] != 0.0 ? s / R[i][i] : 0.0;
-    }
-    if ((rc = stage_upload(yv.data(), m * sizeof(double), d_y, st))) return rc;
-    if ((rc = vec_comb(V, n, m, d_y, w, n, st))) return rc;
-    if ((rc = precond(w, nullptr, nullptr, lam_out, U_out))) return rc;
-    return converged ? RPYW_OK : RPYW_NOT_CONVERGED;
+    return rigid_finish(R, g, res, converged, iters, res_out, d_y, V, n, w, st,
+                        [&](const double* in) { return precond(in, nullptr, nullptr, lam_out, U_out); });
 }
 
 }  // namespace rpyw

@@ -195,7 +195,18 @@ int lz_launch_out(int prec, const BodyFactors& pc, const int* units, const Lancz
                   const double* tpart, const void* spart, const SymPlan& sp, const double* B, double mu0, int64_t n3,
                   int k, const double* V, const double* d_ab, double* w, double* part1, hipStream_t st);
 int lz_launch_gs2(const double* w, double* yo, int64_t n3, const double* V, int k, const double* part1, int ngroups,
-                  double* part2, double* d_ab, double* h_ab, double* h_flag, hipStream_t st);
+                  double* part2, double* d_ab, double* h_ab, double* h_flag, hipStream_t st, double* fin = nullptr,
+                  unsigned* ticket = nullptr, double* hcol = nullptr);
+
+// Fused GMRES steps of the rigid solve (rigid_step.hip), with the Lanczos
+// gs2 kernel in its GMRES form.
+int rg_launch_pre(int prec, const BodyFactors& pc, const double* Wall, const double* Nall, int n_bodies, int64_t n3,
+                  int64_t ld, const double* src, const double* cvec, const double* scale, int k, double* V,
+                  double* zl, double* zu, void* rec, int recw, const double* B, hipStream_t st);
+int rg_launch_out(int prec, const double* pos, const double* q, const int* bofs, int n_bodies, const double* tpart,
+                  const void* spart, const SymPlan& sp, const double* B, double mu0, const double* zl,
+                  const double* zu, int64_t n3, int64_t ld, const double* V, int k, double* w, double* part1,
+                  hipStream_t st);
 
 // Krylov building blocks (krylov.hip).
 // Block-diagonal preconditioner factors: per body the Cholesky factor L_p of

@@ -14,6 +14,8 @@ Both figures are printed, so that a run's log states the observed errors.
 """
 from __future__ import annotations
 
+import contextlib
+
 import numpy as np
 
 
@@ -41,3 +43,18 @@ def check(got, ref, bar: float, what: str = "", elem_bar: float | None = None):
     assert rel <= bar, f"{what}: relative L2 {rel:.3e} > {bar:g}"
     assert emax <= eb, f"{what}: max entry error {emax:.3e} > {eb:g} of max |ref|"
     return rel, emax
+
+
+@contextlib.contextmanager
+def krylov_path(rp, N, fused, prec=0):
+    """fused: force the symmetric product for this size class, which makes
+    the Lanczos and GMRES drivers take their fused four-launch steps (they
+    do so whenever the product is symmetric); otherwise the size's default
+    shape (below 512 blobs the plain product, whose steps are not fused)."""
+    if fused:
+        rp.set_shape(prec, N, 1, tpl=1, tile=256, kblk=1, sym=2, ipw=1)
+    try:
+        yield
+    finally:
+        if fused:
+            rp.reset_shape(prec, N, 1)

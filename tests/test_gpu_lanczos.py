@@ -2,13 +2,12 @@
 dense square roots.  Small cases run both drivers: the fused one (four
 launches per step, used whenever the product goes through the symmetric
 kernel) and the unfused one."""
-import contextlib
 
 import numpy as np
 import pytest
 
 from paper_1709_02410_amd import workloads as wl
-from parity_util import check
+from parity_util import check, krylov_path
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -31,19 +30,7 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-@contextlib.contextmanager
-def _path(rp, N, fused, prec=0):
-    """fused: force the symmetric product for this size class, which makes
-    the Lanczos driver take its fused four-launch steps (it does so whenever
-    the product is symmetric); otherwise the size's default shape (below 512
-    blobs the plain product, whose steps are not fused)."""
-    if fused:
-        rp.set_shape(prec, N, 1, tpl=1, tile=256, kblk=1, sym=2, ipw=1)
-    try:
-        yield
-    finally:
-        if fused:
-            rp.reset_shape(prec, N, 1)
+_path = krylov_path
 
 
 @pytest.mark.parametrize("fused", [False, True])

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from paper_1709_02410_amd import workloads as wl
-from parity_util import check
+from parity_util import check, krylov_path
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -42,22 +42,27 @@ def _mixed(seed):
     return pos, offs, q
 
 
+# fused: the four-launch GMRES steps (symmetric product forced); otherwise
+# the unfused driver these small sizes take by default
+@pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("prec,tol,bound", [(0, 1e-11, 1e-8), (1, 1e-8, 1e-4)])
-def test_rigid_solve_matches_dense_saddle_point(rp, orc, prec, tol, bound):
+def test_rigid_solve_matches_dense_saddle_point(rp, orc, prec, tol, bound, fused):
     pos, offs, q = _mixed(0)
     nb = len(offs) - 1
     slip = wl.gaussian(pos.shape, 1)
     FT = wl.gaussian((nb, 6), 2)
     lam_ref, U_ref = orc.rigid_solve(pos, q, offs, slip, FT)
-    lam, U, it, res, ok = rp.rigid_solve(_t(pos), _t(q), offs, _t(slip), _t(FT), tol=tol, precision=prec)
+    with krylov_path(rp, len(pos), fused, prec):
+        lam, U, it, res, ok = rp.rigid_solve(_t(pos), _t(q), offs, _t(slip), _t(FT), tol=tol, precision=prec)
     lam, U = lam.cpu().numpy(), U.cpu().numpy()
-    print(f"rigid prec={prec} iters={it} res={res:.2e}", flush=True)
+    print(f"rigid prec={prec} fused={fused} iters={it} res={res:.2e}", flush=True)
     assert ok and res <= tol
     check(U, U_ref, bound, f"rigid prec={prec} U vs dense solve")
     check(lam, lam_ref, 10 * bound, f"rigid prec={prec} lambda vs dense solve")
 
 
-def test_iterations_match_oracle_gmres(rp, orc):
+@pytest.mark.parametrize("fused", [False, True])
+def test_iterations_match_oracle_gmres(rp, orc, fused):
     """Same algorithm in exact arithmetic: the FP64 GPU solve takes the
     oracle GMRES's iteration count (+-1 for rounding at the threshold)."""
     pos, offs, q = _mixed(3)
@@ -65,30 +70,35 @@ def test_iterations_match_oracle_gmres(rp, orc):
     FT = wl.gaussian((nb, 6), 4)
     for tol in (1e-3, 1e-8):
         _, _, it_ref, _, ok_ref = orc.rigid_gmres(pos, q, offs, None, FT, tol=tol)
-        _, _, it, res, ok = rp.rigid_solve(_t(pos), _t(q), offs, None, _t(FT), tol=tol)
+        with krylov_path(rp, len(pos), fused):
+            _, _, it, res, ok = rp.rigid_solve(_t(pos), _t(q), offs, None, _t(FT), tol=tol)
         print(f"tol={tol} iters gpu={it} oracle={it_ref}", flush=True)
         assert ok and ok_ref and abs(it - it_ref) <= 1
 
 
-def test_single_body_is_solved_by_the_preconditioner(rp, orc):
+@pytest.mark.parametrize("fused", [False, True])
+def test_single_body_is_solved_by_the_preconditioner(rp, orc, fused):
     pos, offs = wl.boomerang_suspension(1, 10.0, 1.5, 4.0, 5)
     q = pos[:1].copy()
     FT = wl.gaussian((1, 6), 6)
     lam_ref, U_ref = orc.rigid_solve(pos, q, offs, None, FT)
-    lam, U, it, res, ok = rp.rigid_solve(_t(pos), _t(q), offs, None, _t(FT), tol=1e-12)
+    with krylov_path(rp, len(pos), fused):
+        lam, U, it, res, ok = rp.rigid_solve(_t(pos), _t(q), offs, None, _t(FT), tol=1e-12)
     assert ok and it == 1
     check(U.cpu().numpy(), U_ref, 1e-10, "single body U")
 
 
-def test_random_slip_gives_brownian_body_velocities(rp, orc):
+@pytest.mark.parametrize("fused", [False, True])
+def test_random_slip_gives_brownian_body_velocities(rp, orc, fused):
     """slip = M^{1/2} W from the GPU Lanczos, F = 0: U = N K^T M^-1 slip
     (Sec. II.B) for the same root the oracle forms densely."""
     pos, offs, q = _mixed(7)
     W = wl.gaussian(pos.shape, 8)
-    root, it_l, _, ok_l = rp.lanczos_sqrt(_t(pos), _t(W), body_offsets=offs, tol=1e-11)
     slip_ref = orc.dense_sqrt(pos, W, offs)
     _, U_ref = orc.rigid_solve(pos, q, offs, slip_ref, None)
-    _, U, it, res, ok = rp.rigid_solve(_t(pos), _t(q), offs, root, None, tol=1e-11)
+    with krylov_path(rp, len(pos), fused):
+        root, it_l, _, ok_l = rp.lanczos_sqrt(_t(pos), _t(W), body_offsets=offs, tol=1e-11)
+        _, U, it, res, ok = rp.rigid_solve(_t(pos), _t(q), offs, root, None, tol=1e-11)
     print(f"noise lanczos iters={it_l} gmres iters={it}", flush=True)
     assert ok_l and ok
     check(U.cpu().numpy(), U_ref, 1e-7, "random-slip body velocities")
@@ -173,18 +183,20 @@ def test_paperlike_boomerangs_iteration_counts(rp, orc):
             assert it <= 8
 
 
-def test_zero_rhs_and_not_converged_and_rod(rp):
+@pytest.mark.parametrize("fused", [False, True])
+def test_zero_rhs_and_not_converged_and_rod(rp, fused):
     pos, offs, q = _mixed(11)
     nb = len(offs) - 1
-    lam, U, it, res, ok = rp.rigid_solve(_t(pos), _t(q), offs)
-    assert ok and it == 0 and float(lam.abs().max()) == 0.0 and float(U.abs().max()) == 0.0
-    FT = _t(wl.gaussian((nb, 6), 12))
-    lam, U, it, res, ok = rp.rigid_solve(_t(pos), _t(q), offs, None, FT, tol=1e-14, max_iter=2)
-    assert not ok and it == 2 and res > 1e-14 and bool(torch.isfinite(U).all())
-    with pytest.raises(rp.RpywError):
-        rp.rigid_solve(_t(pos), _t(q), offs, None, FT, tol=1e-14, max_iter=2, strict=True)
+    with krylov_path(rp, len(pos), fused):
+        lam, U, it, res, ok = rp.rigid_solve(_t(pos), _t(q), offs)
+        assert ok and it == 0 and float(lam.abs().max()) == 0.0 and float(U.abs().max()) == 0.0
+        FT = _t(wl.gaussian((nb, 6), 12))
+        lam, U, it, res, ok = rp.rigid_solve(_t(pos), _t(q), offs, None, FT, tol=1e-14, max_iter=2)
+        assert not ok and it == 2 and res > 1e-14 and bool(torch.isfinite(U).all())
+        with pytest.raises(rp.RpywError):
+            rp.rigid_solve(_t(pos), _t(q), offs, None, FT, tol=1e-14, max_iter=2, strict=True)
     # a straight rod does not fix rotations about its axis
     rod = np.array([[0.0, 0.0, 3.0], [2.0, 0.0, 3.0], [4.0, 0.0, 3.0]])
-    with pytest.raises(rp.RpywError) as ei:
+    with krylov_path(rp, 3, fused), pytest.raises(rp.RpywError) as ei:
         rp.rigid_solve(_t(rod), _t(np.array([[2.0, 0.0, 3.0]])), [0, 3], None, _t(np.ones((1, 6))))
     assert ei.value.status == rp.ENOTSPD
