@@ -240,14 +240,16 @@ int lanczos_fused(const double* pos, const double* W, double* out, int64_t N, do
     if (pre && pre->flag) RPYW_HIP(hipMemcpyAsync(h_bad + 1, pre->flag, sizeof(int), hipMemcpyDeviceToHost, st));
     const double m0 = 1.0 / (6.0 * M_PI * eta * a);
 
-    // Step k: v_k (from y' and the second projection of step k - 1, or from
-    // W), the product, w = L^-1 M x - beta_{k-1} v_{k-1} with the first
-    // projection, then y' = w - V c1 with the second projection.
+    // Step k: the product (its records written by vin of step k), w = L^-1
+    // M x - beta_{k-1} v_{k-1} with the first projection, y' = w - V c1
+    // with the second projection, then vin of step k + 1: beta_k, v_{k+1}
+    // and the next records; it publishes step k (alpha_k, beta_k, flag).
+    auto vin = [&](int k) {
+        return lz_launch_vin(prec, pc, d_units, nunits, n3, k, k == 0 ? W : y, d_b0, part2, (int)nblk4, V, d_ab,
+                             dh_ab, dh_flag, rec, rw, B, st);
+    };
     auto launch_step = [&](int k) -> int {
         int r;
-        if ((r = lz_launch_vin(prec, pc, d_units, nunits, n3, k, k == 0 ? W : y, d_b0, part2, (int)nblk4, V, d_ab,
-                               dh_ab, rec, rw, B, st)))
-            return r;
         hipEvent_t ev = nullptr;
         profile_begin(st, &ev);
         if ((r = sym_launch(rec, sp, ipw, 1, prec, a, dom, tpart, spart, st))) return r;
@@ -255,7 +257,8 @@ int lanczos_fused(const double* pos, const double* W, double* out, int64_t N, do
         if ((r = lz_launch_out(prec, pc, d_units, d_groups, ngroups, tpart, spart, sp, B, m0, n3, k, V, d_ab, w,
                                part1, st)))
             return r;
-        if ((r = lz_launch_gs2(w, y, n3, V, k, part1, ngroups, part2, d_ab, dh_ab, dh_flag, st))) return r;
+        if ((r = lz_launch_gs2(w, y, n3, V, k, part1, ngroups, part2, d_ab, nullptr, st))) return r;
+        if ((r = vin(k + 1))) return r;  // V has room for max_iter + 1 vectors
         // step 0 also waits for the set-up copies (beta_0, the definiteness flags)
         if (k == 0) RPYW_HIP(hipEventRecord(g_ab.ev[0], st));
         return RPYW_OK;
@@ -279,6 +282,7 @@ int lanczos_fused(const double* pos, const double* W, double* out, int64_t N, do
     double wait_ms = 0.0;
     int starved = 0;
     const auto t_call = Clock::now();
+    if ((rc = vin(0))) return rc;
     if ((rc = fill(1 + depth))) return rc;
     // Waits for step k: its flag in host memory, polled; the stream is
     // queried now and then so that a stream that drains without setting it
@@ -322,20 +326,7 @@ int lanczos_fused(const double* pos, const double* W, double* out, int64_t N, do
                 return RPYW_OK;
             }
         }
-        const double ak = h_ab[2 * k];
-        if (k > 0) {
-            // beta_{k-1} arrives with step k: a breakdown (invariant
-            // subspace) means step k - 1 was the last, with its iterate
-            const double bk1 = h_ab[2 * (k - 1) + 1];
-            const double prev_b = k > 1 ? beta[k - 2] : 0.0;
-            if (bk1 <= 1e-14 * (std::fabs(alpha[k - 1]) + prev_b)) {
-                converged = true;
-                used = k;
-                *iters = k;
-                break;
-            }
-            beta.push_back(bk1);
-        }
+        const double ak = h_ab[2 * k], bk = h_ab[2 * k + 1];
         if (depth && (rc = fill(speculate_to(k, depth, rel1, rel2, tol) + 1))) return rc;
         alpha.push_back(ak);
         c.assign(k + 1, 0.0);
@@ -351,31 +342,24 @@ int lanczos_fused(const double* pos, const double* W, double* out, int64_t N, do
             if (rel <= tol) {
                 converged = true;
                 used = k + 1;
-                *iters = k + 1;
                 break;
             }
         }
+        // beta_k ~ 0: the Krylov space is invariant (a breakdown), and this
+        // step's iterate is the last
+        if (bk <= 1e-14 * (std::fabs(ak) + (k > 0 ? beta[k - 1] : 0.0))) {
+            converged = true;
+            used = k + 1;
+            break;
+        }
+        beta.push_back(bk);
         cprev = c;
         rel2 = rel1;
         rel1 = rel;
         if ((rc = fill(k + 2))) return rc;
     }
-    if (!converged) {
-        // The last step's beta is known only after the next step's first
-        // kernel: run it (V has room for one more vector) to test for a
-        // breakdown at the last step.
-        if ((rc = lz_launch_vin(prec, pc, d_units, nunits, n3, max_iter, y, d_b0, part2, (int)nblk4, V, d_ab, dh_ab,
-                                rec, rw, B, st)))
-            return rc;
-        RPYW_HIP(hipStreamSynchronize(st));
-        const double bl = h_ab[2 * (max_iter - 1) + 1];
-        const double prev_b = max_iter > 1 ? beta[max_iter - 2] : 0.0;
-        converged = bl <= 1e-14 * (std::fabs(alpha[max_iter - 1]) + prev_b);
-        used = max_iter;
-        *iters = max_iter;
-    } else if (used == k) {
-        c = cprev;  // breakdown: the iterate of step k - 1
-    }
+    if (!converged) used = max_iter;
+    *iters = used;
     *err = std::isfinite(rel) ? rel : 0.0;
     if ((rc = stage_upload(c.data(), used * sizeof(double), d_c, st))) return rc;
     if ((rc = vec_comb(V, n3, used, d_c, y, n3, st))) return rc;  // y = V c

@@ -20,11 +20,11 @@
 //         correction), and the block partials of V^T y' and |y'|^2.
 // The first correction and the second projection are the two classical
 // Gram-Schmidt passes of the full reorthogonalisation; beta_k =
-// (|y'|^2 - |c2|^2)^{1/2} as in the unfused driver.  alpha_k reaches the host
-// with step k (gs2 stores it into pinned memory), beta_{k-1} too (vin of step
-// k stores it): beta is known one step after the recurrence produced it, so
-// the breakdown test beta ~ 0 is applied one step late, with the iterate of
-// the step it belongs to.
+// (|y'|^2 - |c2|^2)^{1/2} as in the unfused driver.  vin of step k + 1 is
+// launched with step k: its first workgroup publishes step k (alpha_k, kept
+// in device memory by gs2, and beta_k into pinned memory, then, after a
+// system-scope fence, the step's flag), so that the host sees both
+// coefficients of a step when its flag is set.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -53,7 +53,8 @@ __global__ __launch_bounds__(kVinThreads) void lz_vin_kernel(int diag, const int
                                                              const double* __restrict__ b0,
                                                              const double* __restrict__ part2, int ncol2,
                                                              double* __restrict__ V, double* __restrict__ d_ab,
-                                                             double* __restrict__ h_ab, R* __restrict__ rec, int recw,
+                                                             double* __restrict__ h_ab, double* __restrict__ h_flag,
+                                                             R* __restrict__ rec, int recw,
                                                              const double* __restrict__ B) {
     constexpr int PW = pos_slots<R>();
     __shared__ double c[kLanczosFusedMaxIter + 2];
@@ -90,8 +91,13 @@ __global__ __launch_bounds__(kVinThreads) void lz_vin_kernel(int diag, const int
             const double beta = s2 > 0.0 ? sqrt(s2) : 0.0;
             sinv = 1.0 / beta;  // beta = 0: breakdown, this step's values are discarded
             if (p == 0) {
+                // publish step k - 1: alpha (kept by its gs2) and beta, then,
+                // after a system-scope fence, its flag
                 d_ab[2 * (k - 1) + 1] = beta;
+                h_ab[2 * (k - 1)] = d_ab[2 * (k - 1)];
                 h_ab[2 * (k - 1) + 1] = beta;
+                __threadfence_system();
+                h_flag[k - 1] = 1.0;
             }
         }
     } else if (t == 0) {
@@ -255,62 +261,24 @@ __global__ __launch_bounds__(kOutThreads) void lz_out_kernel(
 // thread and k < kGs2Reg, the entry's basis values are loaded once, before
 // the reduction of c1, and serve both the update and the dot products.
 constexpr int kGs2Reg = 64;
-// Block 0 also publishes the step to the host: alpha_k and beta_{k-1} into
-// the host buffer, then, after a system-scope fence, the step's flag.
-__device__ __forceinline__ void publish_step(int k, const double* c1, double* __restrict__ d_ab,
-                                             double* __restrict__ h_ab, double* __restrict__ h_flag) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    d_ab[2 * k] = c1[k];
-    h_ab[2 * k] = c1[k];
-    if (k > 0) h_ab[2 * (k - 1) + 1] = d_ab[2 * (k - 1) + 1];
-    __threadfence_system();
-    h_flag[k] = 1.0;
-}
-
-// GMRES form of the end of gs2: the last block to finish (an atomic
-// ticket; no block waits) adds up c2 = V^T y' and |y'|^2 from all blocks'
-// partials in a fixed order, forms h = (|y'|^2 - |c2|^2)^{1/2}, and stores
-// fin = [c2 (k + 1 values), h] for the next step's first kernel and the
-// Hessenberg column [c1, c2, h] into the host slot hcol, then (after a
-// system-scope fence) the step's flag; it re-arms the ticket.
-__device__ void gs2_finish(int k, int nblk, const double* c1, const double* __restrict__ part2,
-                           double* __restrict__ fin, unsigned* __restrict__ ticket, double* __restrict__ hcol,
-                           double* __restrict__ h_flag) {
-    __shared__ double c2[kLanczosFusedMaxIter + 2];
-    __shared__ bool last;
-    const int t = threadIdx.x;
-    __threadfence();
-    __syncthreads();
-    if (t == 0) last = atomicAdd(ticket, 1u) == (unsigned)nblk - 1u;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    reduce_rows<kGs2Threads, 4, kPre>(part2, k + 2, nblk, c2);  // c2[0..k], then |y'|^2
-    for (int j = t; j <= k; j += kGs2Threads) {
-        fin[j] = c2[j];
-        hcol[j] = c1[j];
-        hcol[k + 1 + j] = c2[j];
+// Block 0 keeps the step's first projection for the next step's first
+// kernel, which publishes the step: alpha_k = c1[k] into d_ab (Lanczos), or
+// all of c1 into gc1 (GMRES).
+__device__ __forceinline__ void keep_c1(int k, const double* c1, double* __restrict__ d_ab,
+                                        double* __restrict__ gc1) {
+    if (blockIdx.x != 0) return;
+    if (gc1) {
+        for (int j = threadIdx.x; j <= k; j += blockDim.x) gc1[j] = c1[j];
+    } else if (threadIdx.x == 0) {
+        d_ab[2 * k] = c1[k];
     }
-    if (t == 0) {
-        double s2 = c2[k + 1];
-        for (int j = 0; j <= k; ++j) s2 -= c2[j] * c2[j];
-        const double h = s2 > 0.0 ? sqrt(s2) : 0.0;
-        fin[k + 1] = h;
-        hcol[2 * (k + 1)] = h;
-        *ticket = 0u;
-    }
-    __threadfence_system();
-    __syncthreads();
-    if (t == 0) h_flag[k] = 1.0;
 }
 
 __global__ __launch_bounds__(kGs2Threads) void lz_gs2_kernel(const double* __restrict__ w, double* __restrict__ yo,
                                                              int64_t n3, int m, const double* __restrict__ V, int k,
                                                              const double* __restrict__ part1, int ngroups,
                                                              double* __restrict__ part2, double* __restrict__ d_ab,
-                                                             double* __restrict__ h_ab, double* __restrict__ h_flag,
-                                                             double* __restrict__ fin, unsigned* __restrict__ ticket,
-                                                             double* __restrict__ hcol) {
+                                                             double* __restrict__ gc1) {
     constexpr int kBatch = 32;  // results per pass through the tile
     __shared__ double c1[kLanczosFusedMaxIter + 1];
     __shared__ double tile[kBatch][kGs2Threads + 1];
@@ -333,7 +301,7 @@ __global__ __launch_bounds__(kGs2Threads) void lz_gs2_kernel(const double* __res
             for (int j = j0; j < j0 + 16; ++j) a[j] = V[(j <= k ? j : 0) * n3 + bc];
         }
         reduce_rows<kGs2Threads, 4, kPre>(part1, k + 1, ngroups, c1);  // one pass over up to 64 rows
-        if (!fin) publish_step(k, c1, d_ab, h_ab, h_flag);
+        keep_c1(k, c1, d_ab, gc1);
 #pragma unroll
         for (int j = 0; j < kGs2Reg; ++j)
             if (j <= k) v -= c1[j] * a[j];
@@ -366,12 +334,11 @@ __global__ __launch_bounds__(kGs2Threads) void lz_gs2_kernel(const double* __res
             if (c0 == 0 && jr < jn) part2[(int64_t)(j0 + jr) * nblk + blockIdx.x] = s;
             __syncthreads();
         }
-        if (fin) gs2_finish(k, nblk, c1, part2, fin, ticket, hcol, h_flag);
         return;
     }
     // general path: several entries per thread or many basis vectors
     reduce_rows<kGs2Threads>(part1, k + 1, ngroups, c1);
-    if (!fin) publish_step(k, c1, d_ab, h_ab, h_flag);
+    keep_c1(k, c1, d_ab, gc1);
     double x[kLanczosGs2PerThread];
 #pragma unroll
     for (int r = 0; r < kLanczosGs2PerThread; ++r) {
@@ -417,7 +384,6 @@ __global__ __launch_bounds__(kGs2Threads) void lz_gs2_kernel(const double* __res
         if (c0 == 0 && jr < jn) part2[(int64_t)(j0 + jr) * nblk + blockIdx.x] = s;
         __syncthreads();
     }
-    if (fin) gs2_finish(k, nblk, c1, part2, fin, ticket, hcol, h_flag);
 }
 
 }  // namespace
@@ -471,13 +437,15 @@ void lanczos_units(int64_t N, const int64_t* body_offsets, int n_bodies, std::ve
 
 int lz_launch_vin(int prec, const BodyFactors& pc, const int* units, int nunits, int64_t n3, int k,
                   const double* src, const double* b0, const double* part2, int ncol2, double* V, double* d_ab,
-                  double* h_ab, void* rec, int recw, const double* B, hipStream_t st) {
+                  double* h_ab, double* h_flag, void* rec, int recw, const double* B, hipStream_t st) {
     if (prec == RPYW_FP32C)
         hipLaunchKernelGGL(lz_vin_kernel<float>, dim3((unsigned)nunits), dim3(kVinThreads), 0, st, pc.diag ? 1 : 0,
-                           units, pc.lofs, pc.L, n3, k, src, b0, part2, ncol2, V, d_ab, h_ab, (float*)rec, recw, B);
+                           units, pc.lofs, pc.L, n3, k, src, b0, part2, ncol2, V, d_ab, h_ab, h_flag, (float*)rec,
+                           recw, B);
     else
         hipLaunchKernelGGL(lz_vin_kernel<double>, dim3((unsigned)nunits), dim3(kVinThreads), 0, st, pc.diag ? 1 : 0,
-                           units, pc.lofs, pc.L, n3, k, src, b0, part2, ncol2, V, d_ab, h_ab, (double*)rec, recw, B);
+                           units, pc.lofs, pc.L, n3, k, src, b0, part2, ncol2, V, d_ab, h_ab, h_flag, (double*)rec,
+                           recw, B);
     RPYW_HIP(hipGetLastError());
     return RPYW_OK;
 }
@@ -498,12 +466,11 @@ int lz_launch_out(int prec, const BodyFactors& pc, const int* units, const Lancz
 }
 
 int lz_launch_gs2(const double* w, double* yo, int64_t n3, const double* V, int k, const double* part1, int ngroups,
-                  double* part2, double* d_ab, double* h_ab, double* h_flag, hipStream_t st, double* fin,
-                  unsigned* ticket, double* hcol) {
+                  double* part2, double* d_ab, double* gc1, hipStream_t st) {
     int m;
     const int64_t nb = lanczos_gs2_blocks(n3, &m);
     hipLaunchKernelGGL(lz_gs2_kernel, dim3((unsigned)nb), dim3(kGs2Threads), 0, st, w, yo, n3, m, V, k, part1, ngroups,
-                       part2, d_ab, h_ab, h_flag, fin, ticket, hcol);
+                       part2, d_ab, gc1);
     RPYW_HIP(hipGetLastError());
     return RPYW_OK;
 }

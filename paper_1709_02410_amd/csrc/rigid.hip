@@ -359,7 +359,7 @@ int rigid_fused(const double* pos, const double* q, const int64_t* body_offsets,
     double* partial = (double*)ar.take((size_t)2 * dot_chunks(n) * sizeof(double));  // |b|
     double* part1 = (double*)ar.take((size_t)(max_iter + 2) * n_bodies * sizeof(double));
     double* part2 = (double*)ar.take((size_t)(max_iter + 3) * nblk4 * sizeof(double));
-    double* fin = (double*)ar.take((max_iter + 8) * sizeof(double));  // c2 and h of the last step
+    double* gc1 = (double*)ar.take((max_iter + 8) * sizeof(double));  // c1 of the last step
     double* d_b = (double*)ar.take(8 * sizeof(double));
     double* d_y = (double*)ar.take((max_iter + 8) * sizeof(double));
     unsigned* ticket = (unsigned*)ar.take(kAlign);
@@ -368,7 +368,7 @@ int rigid_fused(const double* pos, const double* q, const int64_t* body_offsets,
     double* B = (double*)ar.take((size_t)npad * sizeof(double));
     double* tpart = (double*)ar.take(sp.tpart_bytes);
     void* spart = ar.take(sp.spart_bytes);
-    if (!Wall || !Nall || !V || !zb || !wb || !yb || !bv || !partial || !part1 || !part2 || !fin || !d_b || !d_y ||
+    if (!Wall || !Nall || !V || !zb || !wb || !yb || !bv || !partial || !part1 || !part2 || !gc1 || !d_b || !d_y ||
         !ticket || !notspd || !rec || !B || !tpart || !spart)
         return RPYW_ENOMEM;
     std::lock_guard<std::mutex> lk(g_h.mu);
@@ -403,19 +403,21 @@ int rigid_fused(const double* pos, const double* q, const int64_t* body_offsets,
     if (pre && pre->flag) RPYW_HIP(hipMemcpyAsync(h_bad + 1, pre->flag, sizeof(int), hipMemcpyDeviceToHost, st));
     const double m0 = 1.0 / (6.0 * M_PI * eta * a);
 
+    // Step k: the product of z (records written by pre of step k), w = A z
+    // with the first projection, y' = w - V c1 with the second projection,
+    // then pre of step k + 1, which publishes the column of step k.
+    auto pre_k = [&](int k) {
+        return rg_launch_pre(prec, pc, Wall, Nall, n_bodies, n3, n, k ? yb : bv, part2, (int)nblk4, d_b, gc1, g_h.dp,
+                             slot, dh_flag, k, V, zb, zb + n3, rec, rw, B, st);
+    };
     auto launch_step = [&](int k) -> int {
         int r;
-        if ((r = rg_launch_pre(prec, pc, Wall, Nall, n_bodies, n3, n, k ? yb : bv, fin, k ? fin + k : d_b, k, V, zb,
-                               zb + n3, rec, rw, B, st)))
-            return r;
         if ((r = sym_launch(rec, sp, ipw, 1, prec, a, dom, tpart, spart, st))) return r;
         if ((r = rg_launch_out(prec, pos, q, pc.bofs, n_bodies, tpart, spart, sp, B, m0, zb, zb + n3, n3, n, V, k, wb,
                                part1, st)))
             return r;
-        double* hs = g_h.dp + (size_t)(k % PinnedSlots::kSlots) * slot;
-        if ((r = lz_launch_gs2(wb, yb, n, V, k, part1, n_bodies, part2, nullptr, nullptr, dh_flag, st, fin, ticket,
-                               hs)))
-            return r;
+        if ((r = lz_launch_gs2(wb, yb, n, V, k, part1, n_bodies, part2, nullptr, gc1, st))) return r;
+        if ((r = pre_k(k + 1))) return r;  // V has room for max_iter + 1 vectors
         // step 0 also waits for the set-up copies (|b|, the definiteness flags)
         if (k == 0) RPYW_HIP(hipEventRecord(g_h.ev[0], st));
         return RPYW_OK;
@@ -456,6 +458,7 @@ int rigid_fused(const double* pos, const double* q, const int64_t* body_offsets,
     bool converged = false;
     double beta = 0.0, res = 1.0, res1 = INFINITY, res2 = INFINITY;
     int k = 0;
+    if ((rc = pre_k(0))) return rc;
     if ((rc = fill(1 + depth))) return rc;
     for (; k < max_iter; ++k) {
         if ((rc = wait_step(k))) return rc;

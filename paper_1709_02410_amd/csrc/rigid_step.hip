@@ -2,9 +2,11 @@
 // multiblob system (arXiv:1709.02410, Sec. II.A for the system, Sec. II.B
 // for the block-diagonal preconditioner) when the product by M runs
 // through the symmetric pair kernel.  Step k is four launches:
-//   pre   one workgroup per body: v_k = (y' - V c2) / h (the second
-//         Gram-Schmidt correction of step k - 1, c2 and h as the previous
-//         step's gs2 left them; b / |b| at k = 0), stored as basis vector k;
+//   pre   one workgroup per body: c2 = V^T y' and |y'|^2 of step k - 1
+//         added up from the block partials of its gs2 in a fixed order
+//         (every workgroup repeats that small sum), h = (|y'|^2 -
+//         |c2|^2)^{1/2}, and v_k = (y' - V c2) / h, the second Gram-Schmidt
+//         correction (b / |b| at k = 0), stored as basis vector k;
 //         z = P^-1 v_k for the body (the exact inverse of its own
 //         saddle-point block, factors staged through LDS); B z_lambda
 //         written straight into the force slots of the pair kernel's
@@ -13,10 +15,11 @@
 //   out   one workgroup per body: y = M z_lambda gathered from the partial
 //         sums in a fixed order, w = A z = [y - K z_U | -K^T z_lambda], and
 //         the body's partial dot products V_j . w (j <= k);
-//   gs2   the Lanczos gs2 kernel in its GMRES form: c1 = V^T w,
-//         y' = w - V c1, the block partials of V^T y' and |y'|^2, and in the
-//         last block to finish c2, h_{k+1,k} = (|y'|^2 - |c2|^2)^{1/2} and
-//         the Hessenberg column for the host.
+//   gs2   the Lanczos gs2 kernel: c1 = V^T w (kept for the next pre),
+//         y' = w - V c1, and the block partials of V^T y' and |y'|^2.
+// The pre kernel of step k + 1 is launched with step k: its first
+// workgroup publishes the Hessenberg column of step k ([c1, c2, h] into a
+// pinned slot, then, after a system-scope fence, the step's flag).
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -40,7 +43,8 @@ template <typename R>
 __global__ __launch_bounds__(kPreThreads) void rg_pre_kernel(
     const double* __restrict__ Lall, const int* __restrict__ bofs, const int64_t* __restrict__ lofs,
     const double* __restrict__ Wall, const double* __restrict__ Nall, int64_t n3, int64_t ld,
-    const double* __restrict__ src, const double* __restrict__ cvec, const double* __restrict__ scale, int k,
+    const double* __restrict__ src, const double* __restrict__ part2, int ncol2, const double* __restrict__ bnorm,
+    const double* __restrict__ gc1, double* __restrict__ hslots, int slot, double* __restrict__ h_flag, int k,
     double* __restrict__ V, double* __restrict__ zl, double* __restrict__ zu, R* __restrict__ rec, int recw,
     const double* __restrict__ B) {
     constexpr int PW = pos_slots<R>();
@@ -48,7 +52,7 @@ __global__ __launch_bounds__(kPreThreads) void rg_pre_kernel(
     __shared__ double r[kMaxN3 + 6], t1[kMaxN3], tt[kMaxN3];
     __shared__ double Ls[kLdsFactor];
     __shared__ double Ws[6 * kMaxN3];
-    __shared__ double s6[6], z6[6];
+    __shared__ double s6[6], z6[6], sc;
     const int p = blockIdx.x, t = threadIdx.x;
     const int b0 = bofs[p], n = 3 * (bofs[p + 1] - b0);
     const int64_t e0 = 3 * (int64_t)b0;
@@ -76,8 +80,30 @@ __global__ __launch_bounds__(kPreThreads) void rg_pre_kernel(
     if (t < 6)
 #pragma unroll
         for (int c = 0; c < 6; ++c) np[c] = Nall[36 * (int64_t)p + 6 * t + c];
-    for (int j = t; j < k; j += kPreThreads) cs[j] = cvec[j];
-    const double sc = scale[0];
+    if (k > 0) {
+        // c2 of step k - 1 into cs[0..k), |y'|^2 into cs[k]
+        reduce_rows<kPreThreads, 4, kPre>(part2, k + 1, ncol2, cs);
+        if (t == 0) {
+            double s2 = cs[k];
+            for (int j = 0; j < k; ++j) s2 -= cs[j] * cs[j];
+            const double h = s2 > 0.0 ? sqrt(s2) : 0.0;
+            sc = h;  // h = 0: breakdown, this step's values are discarded
+            if (p == 0) hslots[(size_t)((k - 1) % PinnedSlots::kSlots) * slot + 2 * k] = h;
+        }
+        if (p == 0) {
+            // publish column k - 1: c1 (kept by its gs2), c2, h; then its flag
+            double* hc = hslots + (size_t)((k - 1) % PinnedSlots::kSlots) * slot;
+            for (int j = t; j < k; j += kPreThreads) {
+                hc[j] = gc1[j];
+                hc[k + j] = cs[j];
+            }
+            __threadfence_system();
+            __syncthreads();
+            if (t == 0) h_flag[k - 1] = 1.0;
+        }
+    } else if (t == 0) {
+        sc = bnorm[0];
+    }
     if (lds_factor) sl.store(Ls, n * n);
     sw.store(Ws, 6 * n);
     __syncthreads();
@@ -257,14 +283,17 @@ __global__ __launch_bounds__(kOutThreads) void rg_out_kernel(
 }  // namespace
 
 int rg_launch_pre(int prec, const BodyFactors& pc, const double* Wall, const double* Nall, int n_bodies, int64_t n3,
-                  int64_t ld, const double* src, const double* cvec, const double* scale, int k, double* V,
-                  double* zl, double* zu, void* rec, int recw, const double* B, hipStream_t st) {
+                  int64_t ld, const double* src, const double* part2, int ncol2, const double* bnorm,
+                  const double* gc1, double* hslots, int slot, double* h_flag, int k, double* V, double* zl,
+                  double* zu, void* rec, int recw, const double* B, hipStream_t st) {
     if (prec == RPYW_FP32C)
         hipLaunchKernelGGL(rg_pre_kernel<float>, dim3((unsigned)n_bodies), dim3(kPreThreads), 0, st, pc.L, pc.bofs,
-                           pc.lofs, Wall, Nall, n3, ld, src, cvec, scale, k, V, zl, zu, (float*)rec, recw, B);
+                           pc.lofs, Wall, Nall, n3, ld, src, part2, ncol2, bnorm, gc1, hslots, slot, h_flag, k, V, zl,
+                           zu, (float*)rec, recw, B);
     else
         hipLaunchKernelGGL(rg_pre_kernel<double>, dim3((unsigned)n_bodies), dim3(kPreThreads), 0, st, pc.L, pc.bofs,
-                           pc.lofs, Wall, Nall, n3, ld, src, cvec, scale, k, V, zl, zu, (double*)rec, recw, B);
+                           pc.lofs, Wall, Nall, n3, ld, src, part2, ncol2, bnorm, gc1, hslots, slot, h_flag, k, V, zl,
+                           zu, (double*)rec, recw, B);
     RPYW_HIP(hipGetLastError());
     return RPYW_OK;
 }

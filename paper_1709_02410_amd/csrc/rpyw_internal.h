@@ -190,19 +190,21 @@ void lanczos_units(int64_t N, const int64_t* body_offsets, int n_bodies, std::ve
                    std::vector<int>& groups);
 int lz_launch_vin(int prec, const BodyFactors& pc, const int* units, int nunits, int64_t n3, int k,
                   const double* src, const double* b0, const double* part2, int ncol2, double* V, double* d_ab,
-                  double* h_ab, void* rec, int recw, const double* B, hipStream_t st);
+                  double* h_ab, double* h_flag, void* rec, int recw, const double* B, hipStream_t st);
 int lz_launch_out(int prec, const BodyFactors& pc, const int* units, const LanczosGroup* ginfo, int ngroups,
                   const double* tpart, const void* spart, const SymPlan& sp, const double* B, double mu0, int64_t n3,
                   int k, const double* V, const double* d_ab, double* w, double* part1, hipStream_t st);
 int lz_launch_gs2(const double* w, double* yo, int64_t n3, const double* V, int k, const double* part1, int ngroups,
-                  double* part2, double* d_ab, double* h_ab, double* h_flag, hipStream_t st, double* fin = nullptr,
-                  unsigned* ticket = nullptr, double* hcol = nullptr);
+                  double* part2, double* d_ab, double* gc1, hipStream_t st);
 
 // Fused GMRES steps of the rigid solve (rigid_step.hip), with the Lanczos
-// gs2 kernel in its GMRES form.
+// gs2 kernel (gc1: where its block 0 keeps c1 for the next pre).
+// pre publishes column k - 1 of the Hessenberg matrix into the pinned
+// slot hslots + ((k - 1) mod PinnedSlots::kSlots) slot and sets h_flag[k - 1].
 int rg_launch_pre(int prec, const BodyFactors& pc, const double* Wall, const double* Nall, int n_bodies, int64_t n3,
-                  int64_t ld, const double* src, const double* cvec, const double* scale, int k, double* V,
-                  double* zl, double* zu, void* rec, int recw, const double* B, hipStream_t st);
+                  int64_t ld, const double* src, const double* part2, int ncol2, const double* bnorm,
+                  const double* gc1, double* hslots, int slot, double* h_flag, int k, double* V, double* zl,
+                  double* zu, void* rec, int recw, const double* B, hipStream_t st);
 int rg_launch_out(int prec, const double* pos, const double* q, const int* bofs, int n_bodies, const double* tpart,
                   const void* spart, const SymPlan& sp, const double* B, double mu0, const double* zl,
                   const double* zu, int64_t n3, int64_t ld, const double* V, int k, double* w, double* part1,
