@@ -258,18 +258,23 @@ def main():
         torch.cuda.synchronize()
 
     def timed(fn, steps, warmup):
-        """Wall time per call over `steps` calls and the library-recorded
-        pair-kernel time (HIP events on the launch stream)."""
+        """Wall time per call over `steps` calls, then the library-recorded
+        pair-kernel time (HIP events on the launch stream) from as many calls
+        again; the events add work to the stream, so the wall-clock loop
+        runs without them."""
         for _ in range(warmup):
             fn()
         sync()
-        rp.profile_enable(True)
-        rp.profile_read(True)
         t0 = time.perf_counter()
         for _ in range(steps):
             fn()
         sync()
         wall = (time.perf_counter() - t0) / steps
+        rp.profile_enable(True)
+        rp.profile_read(True)
+        for _ in range(steps):
+            fn()
+        sync()
         kms, launches, pairs = rp.profile_read(True)
         rp.profile_enable(False)
         return wall, kms, launches, pairs

@@ -351,7 +351,8 @@ __global__ __launch_bounds__(64 * kEpiParts) void sym_epilogue(const double* __r
                                                                const R* __restrict__ spart,
                                                                const double* __restrict__ B, int64_t N, int ng, int C,
                                                                int Hmax, int nseg, int K, int G, double mu0,
-                                                               double* __restrict__ U) {
+                                                               double* __restrict__ U,
+                                                               const double* __restrict__ pos, double inv_a) {
     __shared__ double red[kEpiParts][64];
     const int x = threadIdx.x & 63, u = threadIdx.x >> 6;
     const int64_t i = (int64_t)blockIdx.x * 64 + x;
@@ -362,22 +363,42 @@ __global__ __launch_bounds__(64 * kEpiParts) void sym_epilogue(const double* __r
     double s = red[0][x];
 #pragma unroll
     for (int v = 1; v < kEpiParts; ++v) s += red[v][x];
-    U[((int64_t)(q / 3) * N + i) * 3 + q % 3] = mu0 * B[i] * s;
+    double b;
+    if (B) {
+        b = B[i];
+    } else {  // records formed in the pair kernel: B from the position
+        const double z = pos[3 * i + 2] * inv_a;
+        b = z < 1.0 ? z : 1.0;
+    }
+    U[((int64_t)(q / 3) * N + i) * 3 + q % 3] = mu0 * b * s;
 }
 
+// ps: the kernel forms its records from ps (groups of 64 only); otherwise
+// they are read from rec.
 template <typename R, int K, int PER>
 hipError_t launch_sym_t(const R* rec, const SymPlan& sp, int ipw, double* tpart, R* spart, const Box<R>& box,
-                        hipStream_t st) {
+                        hipStream_t st, const PackSrc* ps = nullptr) {
     const dim3 grid((unsigned)((int64_t)sp.ng * sp.C * sp.nseg));
-    if (sp.G == 64 && sp.ns == 4)
-        hipLaunchKernelGGL((sym_kernel<R, ProductBody<R, K, PER>, 1, 4>), grid, dim3(256), 0, st, rec, sp.ng, sp.C,
-                           ipw, sp.Hmax, sp.nseg, tpart, spart, box);
-    else if (sp.G == 64)
-        hipLaunchKernelGGL((sym_kernel<R, ProductBody<R, K, PER>, 1>), grid, dim3(64), 0, st, rec, sp.ng, sp.C, ipw,
-                           sp.Hmax, sp.nseg, tpart, spart, box);
-    else
+    const PackSrc p0 = ps ? *ps : PackSrc{};
+    if (ps && sp.G != 64) return hipErrorInvalidValue;
+    if (sp.G == 64 && sp.ns == 4) {
+        if (ps)
+            hipLaunchKernelGGL((sym_kernel<R, ProductBody<R, K, PER>, 1, 4, true>), grid, dim3(256), 0, st, rec, sp.ng,
+                               sp.C, ipw, sp.Hmax, sp.nseg, tpart, spart, box, p0);
+        else
+            hipLaunchKernelGGL((sym_kernel<R, ProductBody<R, K, PER>, 1, 4>), grid, dim3(256), 0, st, rec, sp.ng, sp.C,
+                               ipw, sp.Hmax, sp.nseg, tpart, spart, box, p0);
+    } else if (sp.G == 64) {
+        if (ps)
+            hipLaunchKernelGGL((sym_kernel<R, ProductBody<R, K, PER>, 1, 1, true>), grid, dim3(64), 0, st, rec, sp.ng,
+                               sp.C, ipw, sp.Hmax, sp.nseg, tpart, spart, box, p0);
+        else
+            hipLaunchKernelGGL((sym_kernel<R, ProductBody<R, K, PER>, 1>), grid, dim3(64), 0, st, rec, sp.ng, sp.C,
+                               ipw, sp.Hmax, sp.nseg, tpart, spart, box, p0);
+    } else {
         hipLaunchKernelGGL((sym_kernel<R, ProductBody<R, K, PER>, 4>), grid, dim3(256), 0, st, rec, sp.ng, sp.C, ipw,
-                           sp.Hmax, sp.nseg, tpart, spart, box);
+                           sp.Hmax, sp.nseg, tpart, spart, box, p0);
+    }
     return hipGetLastError();
 }
 
@@ -542,24 +563,38 @@ namespace {
 int sym_pass(const double* pos, const double* F, double* U, int64_t N, int kb, int K, double a, double eta, int prec,
              const SymPlan& sp, int ipw, Arena& ar, hipStream_t st, const Domain& dom = Domain{}) {
     const size_t mark = ar.used;
-    const int rw = rec_width(prec, K);
-    const int64_t npad = (int64_t)sp.ng * sp.G;
-    void* rec = ar.take((size_t)npad * rw * real_size(prec));
-    double* B = (double*)ar.take((size_t)npad * sizeof(double));
     double* tpart = (double*)ar.take(sp.tpart_bytes);
     void* spart = ar.take(sp.spart_bytes);
-    if (!rec || !B || !tpart || !spart) {
+    if (!tpart || !spart) {
         ar.used = mark;
         return RPYW_ENOMEM;
     }
-    int rc = sym_pack(pos, F, N, kb, K, prec, sp, a, dom, rec, B, st);
+    // Groups of 64 (small problems): the pair kernel forms the records
+    // itself, two launches per product; otherwise the records are packed
+    // once by their own kernel.
+    const bool fused = sp.G == 64;
+    const PackSrc ps{pos, F, N, kb, 1.0 / a, dom.lx / a, dom.ly / a};
+    void* rec = nullptr;
+    double* B = nullptr;
+    int rc = RPYW_OK;
+    if (!fused) {
+        const int rw = rec_width(prec, K);
+        const int64_t npad = (int64_t)sp.ng * sp.G;
+        rec = ar.take((size_t)npad * rw * real_size(prec));
+        B = (double*)ar.take((size_t)npad * sizeof(double));
+        if (!rec || !B) {
+            ar.used = mark;
+            return RPYW_ENOMEM;
+        }
+        rc = sym_pack(pos, F, N, kb, K, prec, sp, a, dom, rec, B, st);
+    }
     if (rc == RPYW_OK) {
         hipEvent_t ev = nullptr;
         profile_begin(st, &ev);
-        rc = sym_launch(rec, sp, ipw, K, prec, a, dom, tpart, spart, st);
+        rc = sym_launch(rec, sp, ipw, K, prec, a, dom, tpart, spart, st, fused ? &ps : nullptr);
         if (rc == RPYW_OK) {
             profile_end(st, ev, (dom.periodic() ? 9.0 : 1.0) * (double)kb * (double)N * (double)N);
-            rc = sym_finish(tpart, spart, B, N, kb, K, prec, sp, mu0_of(a, eta), U, st);
+            rc = sym_finish(tpart, spart, B, N, kb, K, prec, sp, mu0_of(a, eta), U, st, pos, 1.0 / a);
         }
     }
     ar.used = mark;
@@ -572,23 +607,19 @@ int sym_pack(const double* pos, const double* F, int64_t N, int kb, int K, int p
              const Domain& dom, void* rec, double* B, hipStream_t st) {
     const int rw = rec_width(prec, K);
     const int64_t npad = (int64_t)sp.ng * sp.G;
-    const unsigned g1 = (unsigned)((N + kBlock - 1) / kBlock);
-    const unsigned gp = (unsigned)((npad - N + kBlock - 1) / kBlock);
-    if (prec == RPYW_FP32C) {
+    const unsigned g1 = (unsigned)((npad + kBlock - 1) / kBlock);
+    if (prec == RPYW_FP32C)
         hipLaunchKernelGGL(pack_kernel<float>, dim3(g1), dim3(kBlock), 0, st, pos, F, N, kb, rw, 1.0 / a, (float*)rec, B,
-                           nullptr, dom.lx / a, dom.ly / a);
-        if (gp) hipLaunchKernelGGL(pad_kernel<float>, dim3(gp), dim3(kBlock), 0, st, (float*)rec, N, npad, rw, B);
-    } else {
+                           nullptr, dom.lx / a, dom.ly / a, npad);
+    else
         hipLaunchKernelGGL(pack_kernel<double>, dim3(g1), dim3(kBlock), 0, st, pos, F, N, kb, rw, 1.0 / a,
-                           (double*)rec, B, nullptr, dom.lx / a, dom.ly / a);
-        if (gp) hipLaunchKernelGGL(pad_kernel<double>, dim3(gp), dim3(kBlock), 0, st, (double*)rec, N, npad, rw, B);
-    }
+                           (double*)rec, B, nullptr, dom.lx / a, dom.ly / a, npad);
     RPYW_HIP(hipGetLastError());
     return RPYW_OK;
 }
 
 int sym_launch(const void* rec, const SymPlan& sp, int ipw, int K, int prec, double a, const Domain& dom,
-               double* tpart, void* spart, hipStream_t st) {
+               double* tpart, void* spart, hipStream_t st, const PackSrc* ps) {
     auto go = [&](auto Rt, auto Kc) -> hipError_t {
         using R = decltype(Rt);
         constexpr int KK = decltype(Kc)::value;
@@ -599,12 +630,12 @@ int sym_launch(const void* rec, const SymPlan& sp, int ipw, int K, int prec, dou
                 if constexpr (sizeof(R) == 8)
                     if (std::min(dom.lx, dom.ly) > 4.5 * a)
                         return launch_sym_t<R, 1, 2>((const R*)rec, sp, ipw, tpart, (R*)spart, make_box<R>(dom, a),
-                                                     st);
-                return launch_sym_t<R, 1, 1>((const R*)rec, sp, ipw, tpart, (R*)spart, make_box<R>(dom, a), st);
+                                                     st, ps);
+                return launch_sym_t<R, 1, 1>((const R*)rec, sp, ipw, tpart, (R*)spart, make_box<R>(dom, a), st, ps);
             }
             return hipErrorInvalidValue;
         }
-        return launch_sym_t<R, KK, 0>((const R*)rec, sp, ipw, tpart, (R*)spart, Box<R>{}, st);
+        return launch_sym_t<R, KK, 0>((const R*)rec, sp, ipw, tpart, (R*)spart, Box<R>{}, st, ps);
     };
     hipError_t e;
     if (prec == RPYW_FP32C)
@@ -617,14 +648,15 @@ int sym_launch(const void* rec, const SymPlan& sp, int ipw, int K, int prec, dou
 }
 
 int sym_finish(const double* tpart, const void* spart, const double* B, int64_t N, int kb, int K, int prec,
-               const SymPlan& sp, double mu0, double* U, hipStream_t st) {
+               const SymPlan& sp, double mu0, double* U, hipStream_t st, const double* pos, double inv_a) {
+    if (!B && !pos) return RPYW_EINVAL;
     const dim3 ge((unsigned)((N + 63) / 64), (unsigned)(3 * kb));
     if (prec == RPYW_FP32C)
         hipLaunchKernelGGL(sym_epilogue<float>, ge, dim3(64 * kEpiParts), 0, st, tpart, (const float*)spart, B, N,
-                           sp.ng, sp.C, sp.Hmax, sp.nseg, K, sp.G, mu0, U);
+                           sp.ng, sp.C, sp.Hmax, sp.nseg, K, sp.G, mu0, U, pos, inv_a);
     else
         hipLaunchKernelGGL(sym_epilogue<double>, ge, dim3(64 * kEpiParts), 0, st, tpart, (const double*)spart, B, N,
-                           sp.ng, sp.C, sp.Hmax, sp.nseg, K, sp.G, mu0, U);
+                           sp.ng, sp.C, sp.Hmax, sp.nseg, K, sp.G, mu0, U, pos, inv_a);
     RPYW_HIP(hipGetLastError());
     return RPYW_OK;
 }
@@ -654,10 +686,10 @@ int product_pass(const double* pos, const double* F, double* U, int64_t N, int k
     const unsigned g1 = (unsigned)((N + kBlock - 1) / kBlock);
     if (prec == RPYW_FP32C)
         hipLaunchKernelGGL(pack_kernel<float>, dim3(g1), dim3(kBlock), 0, st, pos, F, N, kb, rw, 1.0 / a, (float*)rec,
-                           B, nullptr, 0.0, 0.0);
+                           B, nullptr, 0.0, 0.0, N);
     else
         hipLaunchKernelGGL(pack_kernel<double>, dim3(g1), dim3(kBlock), 0, st, pos, F, N, kb, rw, 1.0 / a,
-                           (double*)rec, B, nullptr, 0.0, 0.0);
+                           (double*)rec, B, nullptr, 0.0, 0.0, N);
     RPYW_HIP(hipGetLastError());
     const int64_t ntb = (N + (int64_t)kBlock * sh.tpl - 1) / ((int64_t)kBlock * sh.tpl);
     const int64_t nblocks = ntb * splits;
@@ -773,10 +805,10 @@ int batched_products(const double* pos, const int64_t* sys_offsets, int S, const
         double* Uk = U + (size_t)k0 * Ntot * 3;
         if (prec == RPYW_FP32C)
             hipLaunchKernelGGL(pack_kernel<float>, dim3(g1), dim3(kBlock), 0, st, pos, Fk, Ntot, kb, rw, 1.0 / a,
-                               (float*)rec, B, nullptr, 0.0, 0.0);
+                               (float*)rec, B, nullptr, 0.0, 0.0, Ntot);
         else
             hipLaunchKernelGGL(pack_kernel<double>, dim3(g1), dim3(kBlock), 0, st, pos, Fk, Ntot, kb, rw, 1.0 / a,
-                               (double*)rec, B, nullptr, 0.0, 0.0);
+                               (double*)rec, B, nullptr, 0.0, 0.0, Ntot);
         RPYW_HIP(hipGetLastError());
         hipLaunchKernelGGL(zero_u32, dim3(1), dim3(1), 0, st, counter);
         RPYW_HIP(hipGetLastError());

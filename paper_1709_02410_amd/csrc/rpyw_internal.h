@@ -69,14 +69,19 @@ inline int sym_group(int sym) { return sym == 2 ? 64 : 256; }
 //   sym_pack   records (positions, wrapped into the cell when periodic, and
 //              B f for kb right-hand sides; padded records are force-free
 //              blobs far away) and B, for ng G blobs;
-//   sym_launch the pair kernel over the records into the partial sums;
-//   sym_finish U = mu0 B (sum of the partials), fixed order.
+//   sym_launch the pair kernel over the records into the partial sums (with
+//              ps, groups of 64 only: the kernel forms the records from
+//              positions and right-hand sides itself; rec is unused);
+//   sym_finish U = mu0 B (sum of the partials), fixed order (B null: B from
+//              the positions, pos and 1 / a given).
 int sym_pack(const double* pos, const double* F, int64_t N, int kb, int K, int prec, const SymPlan& sp, double a,
              const Domain& dom, void* rec, double* B, hipStream_t st);
+struct PackSrc;
 int sym_launch(const void* rec, const SymPlan& sp, int ipw, int K, int prec, double a, const Domain& dom,
-               double* tpart, void* spart, hipStream_t st);
+               double* tpart, void* spart, hipStream_t st, const PackSrc* ps = nullptr);
 int sym_finish(const double* tpart, const void* spart, const double* B, int64_t N, int kb, int K, int prec,
-               const SymPlan& sp, double mu0, double* U, hipStream_t st);
+               const SymPlan& sp, double mu0, double* U, hipStream_t st, const double* pos = nullptr,
+               double inv_a = 1.0);
 
 // Bump allocator over a caller workspace.
 struct Arena {

@@ -107,12 +107,25 @@ struct Vec<float> {
     using T = float4;
     static constexpr int W = 4;
     __device__ static float get(const float4& v, int e) { return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w; }
+    __device__ static float4 make(const float* p) { return make_float4(p[0], p[1], p[2], p[3]); }
 };
 template <>
 struct Vec<double> {
     using T = double2;
     static constexpr int W = 2;
     __device__ static double get(const double2& v, int e) { return e == 0 ? v.x : v.y; }
+    __device__ static double2 make(const double* p) { return make_double2(p[0], p[1]); }
+};
+
+// Inputs of the records when the kernel forms them itself (make_record):
+// positions [N][3], kb right-hand sides [kb][N][3], 1 / a and the periodic
+// cell in units of a (zeros for the open domain).
+struct PackSrc {
+    const double* pos;
+    const double* F;
+    int64_t N;
+    int kb;
+    double inv_a, lx, ly;
 };
 
 // The target a lane holds: scaled position (FP32: plus low parts) and the
@@ -255,12 +268,15 @@ struct SymLane {
 // target block, take 64 / NS consecutive steps each and add their sums
 // through LDS in wave order; beyond that, nseg segments are workgroups of
 // their own (nseg = 1, 2 or 4), each writing its own partials.
-// rec: ng * G records (padded with force-free blobs far away).
+// rec: ng * G records (padded with force-free blobs far away), or, with FP,
+// none: every workgroup forms the records of its target and source groups
+// from ps (make_record) as it loads them, which saves small problems the
+// launch of the packing kernel.
 // tpart: [ng * C * nseg][NQ][G] doubles; spart: [ng * (Hmax + 1) * nseg][NQ][G].
-template <typename R, class Body, int NB = 4, int NS = 1>
+template <typename R, class Body, int NB = 4, int NS = 1, bool FP = false>
 __global__ __launch_bounds__(64 * NB * NS) void sym_kernel(const R* __restrict__ rec, int ng, int C, int ipw,
                                                            int Hmax, int nseg, double* __restrict__ tpart,
-                                                           R* __restrict__ spart, Box<R> box) {
+                                                           R* __restrict__ spart, Box<R> box, PackSrc ps) {
     static_assert(NS == 1 || NB == 1, "step segments within a workgroup need one target block");
     using L = SymLane<R, Body>;
     using VT = typename Vec<R>::T;
@@ -293,7 +309,15 @@ __global__ __launch_bounds__(64 * NB * NS) void sym_kernel(const R* __restrict__
     const int s0 = (g * NS + seg) * (64 / (nseg * NS)), s1 = s0 + 64 / (nseg * NS);
     const bool loader = NS == 1 || threadIdx.x < G;  // one thread per record of a group
     L me;
-    me.load(rec + ((int64_t)P * G + w * 64 + l) * L::RW);
+    if constexpr (FP) {
+        R rr[L::RW];
+        double bd;
+        make_record<R>(ps.pos, ps.F, ps.N, ps.kb, L::RW, ps.inv_a, nullptr, ps.lx, ps.ly, (int64_t)P * G + w * 64 + l,
+                       rr, &bd);
+        me.load(rr);
+    } else {
+        me.load(rec + ((int64_t)P * G + w * 64 + l) * L::RW);
+    }
     const int H = sym_rowlen(P, ng);
     const int d0 = c * ipw;
     const int d1 = d0 + ipw - 1 < H ? d0 + ipw - 1 : H;
@@ -303,12 +327,25 @@ __global__ __launch_bounds__(64 * NB * NS) void sym_kernel(const R* __restrict__
         {
             const int b = threadIdx.x >> 6, j = threadIdx.x & 63;
             if (loader) {
-                const VT* gr = reinterpret_cast<const VT*>(rec + ((int64_t)Q * G + threadIdx.x) * L::RW);
+                if constexpr (FP) {
+                    R rr[L::RW];
+                    double bd;
+                    make_record<R>(ps.pos, ps.F, ps.N, ps.kb, L::RW, ps.inv_a, nullptr, ps.lx, ps.ly,
+                                   (int64_t)Q * G + threadIdx.x, rr, &bd);
 #pragma unroll
-                for (int v = 0; v < L::NV; ++v) {
-                    const VT q = gr[v];
-                    tile[v * VS + b * 128 + j] = q;
-                    tile[v * VS + b * 128 + j + 64] = q;
+                    for (int v = 0; v < L::NV; ++v) {
+                        const VT q = Vec<R>::make(rr + v * Vec<R>::W);
+                        tile[v * VS + b * 128 + j] = q;
+                        tile[v * VS + b * 128 + j + 64] = q;
+                    }
+                } else {
+                    const VT* gr = reinterpret_cast<const VT*>(rec + ((int64_t)Q * G + threadIdx.x) * L::RW);
+#pragma unroll
+                    for (int v = 0; v < L::NV; ++v) {
+                        const VT q = gr[v];
+                        tile[v * VS + b * 128 + j] = q;
+                        tile[v * VS + b * 128 + j + 64] = q;
+                    }
                 }
             }
             if constexpr (kLds) {
@@ -414,19 +451,6 @@ __device__ __forceinline__ double sym_gather(const double* __restrict__ tpart, c
     }
     for (; d <= dmax; d += U) s0 += (double)sp[d * st];
     return (s0 + s1) + (s2 + s3);
-}
-
-// Records [N, Npad): force-free blobs far from everything (x = y = 1e6 a).
-template <typename R>
-__global__ void pad_kernel(R* __restrict__ rec, int64_t N, int64_t Npad, int recw, double* __restrict__ B) {
-    const int64_t i = N + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= Npad) return;
-    R* r = rec + i * recw;
-    for (int e = 0; e < recw; ++e) r[e] = R(0);
-    r[0] = R(1e6);
-    r[1] = R(1e6);
-    r[2] = R(1);
-    B[i] = 0.0;
 }
 
 }  // namespace rpyw

@@ -250,7 +250,7 @@ bool vjp_sym_plan(int64_t N, int prec, int ipw, int G, int* ng, int* C, int* Hma
 template <typename R, int NB>
 void launch_vjp_sym(const R* rec, int ng, int C, int ipw, int Hmax, double* tpart, R* spart, hipStream_t st) {
     hipLaunchKernelGGL((sym_kernel<R, VjpBody<R>, NB>), dim3((unsigned)(ng * C)), dim3(64 * NB), 0, st, rec, ng, C,
-                       ipw, Hmax, 1, tpart, spart, Box<R>{});
+                       ipw, Hmax, 1, tpart, spart, Box<R>{}, PackSrc{});
 }
 
 }  // namespace
@@ -300,12 +300,11 @@ int vjp(const double* pos, const double* f, const double* g, double* grad_pos, d
             ar.used = mark;
             return RPYW_ENOMEM;
         }
-        const unsigned gp = (unsigned)((npad - N + kBlock - 1) / kBlock);
+        const unsigned gpk = (unsigned)((npad + kBlock - 1) / kBlock);  // records and padding
         hipEvent_t ev = nullptr;
         if (prec == RPYW_FP32C) {
-            hipLaunchKernelGGL(pack_kernel<float>, dim3(g1), dim3(kBlock), 0, st, pos, f, N, 2, rw, 1.0 / a,
-                               (float*)rec, B, g, 0.0, 0.0);
-            if (gp) hipLaunchKernelGGL(pad_kernel<float>, dim3(gp), dim3(kBlock), 0, st, (float*)rec, N, npad, rw, B);
+            hipLaunchKernelGGL(pack_kernel<float>, dim3(gpk), dim3(kBlock), 0, st, pos, f, N, 2, rw, 1.0 / a,
+                               (float*)rec, B, g, 0.0, 0.0, npad);
             RPYW_HIP(hipGetLastError());
             profile_begin(st, &ev);
             if (G == 64)
@@ -317,10 +316,8 @@ int vjp(const double* pos, const double* f, const double* g, double* grad_pos, d
             hipLaunchKernelGGL(sym_vjp_epilogue<float>, dim3(g1), dim3(kBlock), 0, st, tpart, (const float*)spart, pos,
                                f, g, N, ng, C, Hmax, G, 1.0 / a, m0, grad_pos, grad_f);
         } else {
-            hipLaunchKernelGGL(pack_kernel<double>, dim3(g1), dim3(kBlock), 0, st, pos, f, N, 2, rw, 1.0 / a,
-                               (double*)rec, B, g, 0.0, 0.0);
-            if (gp)
-                hipLaunchKernelGGL(pad_kernel<double>, dim3(gp), dim3(kBlock), 0, st, (double*)rec, N, npad, rw, B);
+            hipLaunchKernelGGL(pack_kernel<double>, dim3(gpk), dim3(kBlock), 0, st, pos, f, N, 2, rw, 1.0 / a,
+                               (double*)rec, B, g, 0.0, 0.0, npad);
             RPYW_HIP(hipGetLastError());
             profile_begin(st, &ev);
             if (G == 64)
@@ -350,14 +347,14 @@ int vjp(const double* pos, const double* f, const double* g, double* grad_pos, d
     hipEvent_t ev = nullptr;
     if (prec == RPYW_FP32C) {
         hipLaunchKernelGGL(pack_kernel<float>, dim3(g1), dim3(kBlock), 0, st, pos, f, N, 2, rw, 1.0 / a, (float*)rec, B,
-                           g, 0.0, 0.0);
+                           g, 0.0, 0.0, N);
         RPYW_HIP(hipGetLastError());
         profile_begin(st, &ev);
         hipLaunchKernelGGL((vjp_kernel<float, 256>), dim3((unsigned)nblocks), dim3(kBlock), 0, st, (const float*)rec,
                            N, splits, chunk, part);
     } else {
         hipLaunchKernelGGL(pack_kernel<double>, dim3(g1), dim3(kBlock), 0, st, pos, f, N, 2, rw, 1.0 / a,
-                           (double*)rec, B, g, 0.0, 0.0);
+                           (double*)rec, B, g, 0.0, 0.0, N);
         RPYW_HIP(hipGetLastError());
         profile_begin(st, &ev);
         hipLaunchKernelGGL((vjp_kernel<double, 128>), dim3((unsigned)nblocks), dim3(kBlock), 0, st,

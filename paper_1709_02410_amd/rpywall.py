@@ -112,13 +112,35 @@ def _stream(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
+_ws_bytes: dict = {}
+
+
 def workspace_bytes(op: int, N: int, k: int = 1, max_iter: int = 0, n_bodies: int = 0,
                     precision: int = FP64) -> int:
-    return int(lib().rpy_wall_workspace_bytes(op, N, k, max_iter, n_bodies, precision))
+    key = (op, N, k, max_iter, n_bodies, precision)
+    b = _ws_bytes.get(key)
+    if b is None:
+        b = _ws_bytes[key] = int(lib().rpy_wall_workspace_bytes(op, N, k, max_iter, n_bodies, precision))
+    return b
 
 
 def _workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+_scratch_ws: dict = {}
+
+
+def _scratch(nbytes: int, device, stream: int) -> torch.Tensor:
+    """A workspace kept per (device, stream) and grown on demand, for the
+    single-call entry points whose workspace holds nothing between calls:
+    calls on one stream run one after the other on the GPU, so they can share
+    it (a replaced buffer goes back to PyTorch's stream-ordered allocator)."""
+    key = (device.index, stream)
+    t = _scratch_ws.get(key)
+    if t is None or t.numel() < nbytes:
+        t = _scratch_ws[key] = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+    return t
 
 
 def matvec(pos: torch.Tensor, force: torch.Tensor, a: float = 1.0, eta: float = 1.0,
@@ -131,9 +153,10 @@ def matvec(pos: torch.Tensor, force: torch.Tensor, a: float = 1.0, eta: float = 
     out = torch.empty_like(force) if out is None else _dev(out, "out", (N, 3))
     if box is not None:
         return matvec_periodic(pos, force.view(1, N, 3), box, a, eta, precision, out.view(1, N, 3)).view(N, 3)
-    ws = _workspace(workspace_bytes(OP_MATVEC, N, 1, precision=precision), pos.device)
-    _check(lib().rpy_wall_matvec(pos.data_ptr(), force.data_ptr(), out.data_ptr(), N, a, eta, precision,
-                                 ws.data_ptr(), ws.numel(), _stream(pos.device)), "rpy_wall_matvec")
+    st = _stream(pos.device)
+    ws = _scratch(workspace_bytes(OP_MATVEC, N, 1, precision=precision), pos.device, st)
+    _check(_lib.rpy_wall_matvec(pos.data_ptr(), force.data_ptr(), out.data_ptr(), N, a, eta, precision,
+                                ws.data_ptr(), ws.numel(), st), "rpy_wall_matvec")
     return out
 
 
