@@ -108,7 +108,14 @@ def _dev(t: torch.Tensor, name: str, shape=None) -> torch.Tensor:
     return t
 
 
+_raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
 def _stream(device) -> int:
+    """PyTorch's current HIP stream of the device (the raw handle; the
+    public accessor builds a Stream object on every call, about 2 us)."""
+    if _raw_stream is not None:
+        return _raw_stream(device.index if device.index is not None else torch.cuda.current_device())
     return torch.cuda.current_stream(device).cuda_stream
 
 

@@ -258,3 +258,20 @@ def test_5e5_blobs_symmetric_sampled_rows(rp, orc, prec):
     rows = np.concatenate([np.random.default_rng(9).choice(cfg.N, 96, replace=False), [0, cfg.N - 1]])
     check(got[rows], orc.matvec(cfg.pos, f, rows=rows), TOL[prec], f"5e5 prec={prec} sampled rows")
     torch.cuda.empty_cache()
+
+
+def test_binding_uses_torch_current_stream(rp):
+    """The binding's raw stream handle is PyTorch's current stream, also
+    inside a stream context (the product then runs on that stream)."""
+    dev = torch.device("cuda:0")
+    assert rp._stream(dev) == torch.cuda.current_stream(dev).cuda_stream
+    s = torch.cuda.Stream(dev)
+    pos = _t(wl.config0(seed=0).pos)
+    f = _t(wl.gaussian(pos.shape, 2))
+    ref = rp.matvec(pos, f)
+    s.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(s):
+        assert rp._stream(dev) == s.cuda_stream
+        got = rp.matvec(pos, f)
+    s.synchronize()
+    assert torch.equal(got, ref)
