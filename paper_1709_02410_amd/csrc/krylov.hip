@@ -88,6 +88,11 @@ __global__ __launch_bounds__(kBuildThreads) void precond_build_kernel(const doub
         }
     }
     __syncthreads();
+    // reciprocals of the diagonal of L (the inverse's diagonal), in the free
+    // position-staging area
+    double* rd = px;  // 4 nmax >= n doubles
+    for (int i = threadIdx.x; i < n; i += blockDim.x) rd[i] = 1.0 / A(i, i);
+    __syncthreads();
     double* L = Lout + 2 * lofs[p];
     double* Li = L + (int64_t)n * n;
     for (int q = threadIdx.x; q < n * n; q += blockDim.x) {
@@ -100,28 +105,28 @@ __global__ __launch_bounds__(kBuildThreads) void precond_build_kernel(const doub
     // adding their shares in a fixed butterfly (all four get the same sum).
     // Entry (i, col), i > col, is kept in the free upper triangle of A at
     // (col, i), a row only this lane group touches (one wave), written by its
-    // first lane and read by all four in later rows.
+    // first lane and read by all four in later rows: LDS operations of one
+    // wave complete in order, and every later read of the row follows the
+    // write in program order.
     {
         const int sub = threadIdx.x & 3;
         for (int col = threadIdx.x >> 2; col < n; col += kBuildThreads / 4) {
-            const double xc = 1.0 / A(col, col);
+            const double xc = rd[col];
             for (int i = col + 1; i < n; ++i) {
                 double s = 0.0;
                 for (int k = col + sub; k < i; k += 4) s += A(i, k) * (k == col ? xc : A(col, k));
                 s += __shfl_xor(s, 1, 4);
                 s += __shfl_xor(s, 2, 4);
-                const double x = -s / A(i, i);
+                const double x = -s * rd[i];
                 if (sub == 0) A(col, i) = x;
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
         }
     }
     __syncthreads();
     for (int q = threadIdx.x; q < n * n; q += blockDim.x) {
         const int i = q / n, j = q % n;
-        Li[q] = i > j ? A(j, i) : i == j ? 1.0 / A(i, i) : 0.0;
+        Li[q] = i > j ? A(j, i) : i == j ? rd[i] : 0.0;
     }
     if (threadIdx.x == 0 && bad) atomicOr(notspd, 1);
 #undef A

@@ -62,10 +62,22 @@ __global__ __launch_bounds__(kVinThreads) void lz_vin_kernel(int diag, const int
     __shared__ double Li[kLdsFactor];
     __shared__ double sinv;
     const int p = blockIdx.x, t = threadIdx.x;
+    // The partials of gs2 first (they depend on nothing this kernel loads):
+    // with up to 64 rows of up to 64 columns, one batch of loads per lane
+    // (4 lanes per row), added up after the other loads are issued.
+    constexpr int kRl = 4;
+    const bool one_batch = k > 0 && k + 1 <= kVinThreads / kRl && ncol2 <= kRl * kPre;
+    const int rr = t / kRl, rq = t % kRl;
+    double pv[kPre];
+    if (one_batch && rr <= k) {
+        const double* pr = part2 + (int64_t)rr * ncol2;
+#pragma unroll
+        for (int i = 0; i < kPre; ++i) pv[i] = pr[rq + kRl * i < ncol2 ? rq + kRl * i : ncol2 - 1];
+    }
     const int64_t e0 = 3 * (int64_t)units[p];
     const int n = (int)(3 * (int64_t)units[p + 1] - e0);
     const bool lds_factor = !diag && n * n <= kLdsFactor;
-    // loads that do not depend on the reductions go first: this entry's
+    // loads that do not depend on the reductions go next: this entry's
     // source value, B of its blob, its basis values (the first kVinReg), and
     // the inverse factor
     Staged<kVinThreads, kLdsFactor / kVinThreads> sf;
@@ -84,7 +96,17 @@ __global__ __launch_bounds__(kVinThreads) void lz_vin_kernel(int diag, const int
     }
     if (k > 0) {
         // c[0..k) = c2, c[k] = |y'|^2; one pass over up to 64 rows
-        reduce_rows<kVinThreads, 4, kPre>(part2, k + 1, ncol2, c);
+        if (one_batch) {
+            double sr = 0.0;
+#pragma unroll
+            for (int i = 0; i < kPre; ++i)
+                if (rq + kRl * i < ncol2) sr += pv[i];
+            sr = lane_group_sum<kRl>(sr);
+            if (rq == 0 && rr <= k) c[rr] = sr;
+            __syncthreads();
+        } else {
+            reduce_rows<kVinThreads, 4, kPre>(part2, k + 1, ncol2, c);
+        }
         if (t == 0) {
             double s2 = c[k];
             for (int j = 0; j < k; ++j) s2 -= c[j] * c[j];
