@@ -131,6 +131,15 @@ def cpu_model() -> str:
     return "unknown"
 
 
+class _ProgressRows(dict):
+    """The benchmark's rows; each one prints a progress line on stderr as it
+    is filled, so a long run shows where it is."""
+
+    def __setitem__(self, key, value):
+        super().__setitem__(key, value)
+        print(f"[bench] row {key} done", file=sys.stderr, flush=True)
+
+
 def oracle_leg(checks, H, args, out_rows, top):
     """The CPU leg of the benchmark: the FP64 oracle (test infrastructure,
     never on the product path) evaluates every queued check on the host and
@@ -180,6 +189,7 @@ def oracle_leg(checks, H, args, out_rows, top):
         except MemoryError:
             e = {"rel_l2_vs_oracle": None, "note": "oracle out of memory"}
         e["compared"] = c["what"]
+        print(f"[bench] oracle check {c['row'] or c['key']} done", file=sys.stderr, flush=True)
         if c["row"] is None:
             top[c["key"]] = e
         else:
@@ -290,7 +300,7 @@ def main():
                        "rows": rows, "got": got_rows, "box": box})
 
     out = {}
-    rows_out = {}
+    rows_out = _ProgressRows()
     # ---------------------------------------------------------- headline
     H = wl.headline(seed=0)
     N = H.N

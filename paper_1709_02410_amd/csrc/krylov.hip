@@ -461,12 +461,17 @@ int body_factors_build(const double* pos, int64_t N, double a, double eta, const
             const int64_t n = 3 * (body_offsets[p + 1] - body_offsets[p]);
             hl[p + 1] = hl[p] + n * n;
         }
-        pc.bofs = (int*)ar.take(hb.size() * sizeof(int));
-        pc.lofs = (int64_t*)ar.take(hl.size() * sizeof(int64_t));
+        // both tables in one upload: lofs, then bofs
+        const size_t lb = align_up(hl.size() * sizeof(int64_t));
+        std::vector<char> tab(lb + hb.size() * sizeof(int));
+        std::memcpy(tab.data(), hl.data(), hl.size() * sizeof(int64_t));
+        std::memcpy(tab.data() + lb, hb.data(), hb.size() * sizeof(int));
+        char* dtab = (char*)ar.take(tab.size());
         pc.L = (double*)ar.take((size_t)2 * hl[n_bodies] * sizeof(double));  // L and L^-1
-        if (!pc.bofs || !pc.lofs || !pc.L) return RPYW_ENOMEM;
-        if (int r = stage_upload(hb.data(), hb.size() * sizeof(int), pc.bofs, st)) return r;
-        if (int r = stage_upload(hl.data(), hl.size() * sizeof(int64_t), pc.lofs, st)) return r;
+        if (!dtab || !pc.L) return RPYW_ENOMEM;
+        pc.lofs = (int64_t*)dtab;
+        pc.bofs = (int*)(dtab + lb);
+        if (int r = stage_upload(tab.data(), tab.size(), dtab, st)) return r;
         int nmax = 1;
         for (int p = 0; p < n_bodies; ++p) nmax = std::max(nmax, (int)(body_offsets[p + 1] - body_offsets[p]));
         const size_t lds = ((size_t)3 * nmax * (3 * nmax + 1) + 4 * (size_t)nmax) * sizeof(double);

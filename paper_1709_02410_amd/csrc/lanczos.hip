@@ -12,10 +12,10 @@
 //   for small problems it is queued before the host has examined iteration
 //   k and is discarded if k turns out to be the last: the host solve
 //   overlaps the GPU work.
-//   Host: eigendecomposition of the k x k tridiagonal T_k, coefficients
-//   c_k = beta0 Q Lambda^{1/2} Q^T e1; since V is orthonormal the stopping
-//   test |y_k - y_{k-1}| <= tol |y_k| is evaluated on c.  At the end
-//   out = L (V c).
+//   Host: the coefficients c_k = beta0 T_k^{1/2} e1 of the k x k
+//   tridiagonal T_k (= beta0 Q Lambda^{1/2} Q^T e1 for T_k = Q Lambda Q^T);
+//   since V is orthonormal the stopping test |y_k - y_{k-1}| <= tol |y_k| is
+//   evaluated on c.  At the end out = L (V c).
 // All reductions are two-stage with a fixed order (bitwise reproducible).
 #include <algorithm>
 #include <atomic>
@@ -111,7 +111,151 @@ static bool tridiag_eig(std::vector<double>& d, std::vector<double>& e, std::vec
     return true;
 }
 
+// Whether T - shift I is positive definite: its LDL^T factorisation
+// (Sturm sequence) has positive pivots only.
+static bool shifted_pd(const double* a, const double* b, int k, double shift) {
+    double p = a[0] - shift;
+    if (!(p > 0.0)) return false;
+    for (int i = 1; i < k; ++i) {
+        p = a[i] - shift - b[i - 1] * b[i - 1] / p;
+        if (!(p > 0.0)) return false;
+    }
+    return true;
+}
+
+// x = T^-1 v for the SPD tridiagonal T (elimination without pivoting, which
+// is stable for SPD T); wk holds 2k doubles.
+static void tridiag_solve(const double* a, const double* b, int k, const double* v, double* x, double* wk) {
+    double* mul = wk;
+    double* piv = wk + k;
+    piv[0] = a[0];
+    x[0] = v[0];
+    for (int i = 1; i < k; ++i) {
+        mul[i - 1] = b[i - 1] / piv[i - 1];
+        piv[i] = a[i] - b[i - 1] * mul[i - 1];
+        x[i] = v[i] - mul[i - 1] * x[i - 1];
+    }
+    x[k - 1] /= piv[k - 1];
+    for (int i = k - 2; i >= 0; --i) x[i] = x[i] / piv[i] - mul[i] * x[i + 1];
+}
+
+// x = T v.
+static void tridiag_mul(const double* a, const double* b, int k, const double* v, double* x) {
+    for (int i = 0; i < k; ++i)
+        x[i] = (i > 0 ? b[i - 1] * v[i - 1] : 0.0) + a[i] * v[i] + (i + 1 < k ? b[i] * v[i + 1] : 0.0);
+}
+
+// c = beta0 T^{1/2} e1 for an SPD tridiagonal T by quadrature instead of an
+// eigendecomposition (whose rotation sweeps are one long dependent chain,
+// O(k^2) rotations: 0.1-0.2 ms at k = 60 on the host, longer than a GPU
+// step).  T^{1/2} e1 = T T^{-1/2} e1, with
+//   T^{-1/2} = (2/pi) int_0^inf (s^2 I + T)^{-1} ds
+//            = (2/pi) int_R e^u (e^{2u} I + T)^{-1} du        (s = e^u).
+// For one eigenvalue l the integrand is l^{-1/2} sech(u - log(l)/2) / 2:
+// analytic in the strip |Im u| < pi/2 and decaying like e^{-|u|}, so the
+// trapezoidal rule of step h has relative error about 2 pi exp(-pi^2 / h)
+// for every eigenvalue alike (the exponentially convergent trapezoidal
+// rule: Trefethen & Weideman, SIAM Review 56, 2014).  h = 1/4
+// gives ~1e-17.  The nodes span the spectrum's bounds (lo <= lambda_min
+// from a Sturm test, hi >= lambda_max by Gershgorin) widened by 5.5 on
+// each side; the rest of the node sum, where e^{2u} is far below lo or far
+// above hi, is the geometric sum of the first three terms of the series
+// (s^2 I + T)^{-1} = sum_m (-s^2)^m T^{-m-1} = sum_m (-1)^m T^m s^{-2m-2}
+// (neglected terms below (e^{-11})^3 of the tail).  Every node is one
+// shifted tridiagonal solve; the nodes are independent, so they run in
+// blocks with the node as the inner loop.  Returns false when T is not
+// positive definite.
+static bool tridiag_sqrt_quadrature(const double* a, const double* b, int k, double beta0, double* c) {
+    constexpr int NB = 16;  // nodes per block
+    double hi = 0.0, amin = INFINITY;
+    for (int i = 0; i < k; ++i) {
+        const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < k ? std::fabs(b[i]) : 0.0);
+        hi = std::max(hi, a[i] + r);
+        amin = std::min(amin, a[i]);
+    }
+    if (!(amin > 0.0) || !std::isfinite(hi)) return false;
+    double lo = 0.5 * amin;  // min_i a_i >= lambda_min
+    for (int t = 0; !shifted_pd(a, b, k, lo); ++t) {
+        if (t == 60) return false;
+        lo *= 0.125;
+    }
+    const double h = 0.25, widen = 5.5, wc = (2.0 / M_PI) * h;
+    const double u0 = 0.5 * std::log(lo) - widen;
+    const int nn = (int)std::ceil((0.5 * std::log(hi) + widen - u0) / h) + 1;  // nodes u0 + n h, n < nn
+    std::vector<double> buf((size_t)3 * k * NB + (size_t)9 * k, 0.0);
+    double* mul = buf.data();                // [row][node] elimination multipliers
+    double* zp = mul + (size_t)k * NB;       // [row][node] forward-eliminated right-hand side / pivot
+    double* acc = zp + (size_t)k * NB;       // [row][node] weighted sums, added over nodes at the end
+    double* y = acc + (size_t)k * NB;        // T^{-1/2} e1
+    double* t1 = y + k;
+    double* t2 = t1 + k;
+    double* t3 = t2 + k;
+    double* e1 = t3 + k;
+    double* te = e1 + k;
+    double* tte = te + k;
+    double* wk = tte + k;                    // 2k
+    for (int n0 = 0; n0 < nn; n0 += NB) {
+        double s2[NB], w[NB], p[NB], z[NB], x[NB];
+        for (int j = 0; j < NB; ++j) {
+            const double u = u0 + (n0 + j) * h;
+            s2[j] = std::exp(2.0 * u);
+            w[j] = n0 + j < nn ? wc * std::exp(u) : 0.0;
+            p[j] = s2[j] + a[0];
+            z[j] = 1.0;
+        }
+        for (int i = 0; i + 1 < k; ++i) {
+            const double bi = b[i], ai1 = a[i + 1];
+            for (int j = 0; j < NB; ++j) {
+                const double r = 1.0 / p[j];
+                const double m = bi * r;
+                zp[i * NB + j] = z[j] * r;
+                mul[i * NB + j] = m;
+                z[j] = -m * z[j];
+                p[j] = s2[j] + ai1 - bi * m;
+            }
+        }
+        for (int j = 0; j < NB; ++j) {
+            x[j] = z[j] / p[j];
+            acc[(k - 1) * NB + j] += w[j] * x[j];
+        }
+        for (int i = k - 2; i >= 0; --i)
+            for (int j = 0; j < NB; ++j) {
+                x[j] = zp[i * NB + j] - mul[i * NB + j] * x[j];
+                acc[i * NB + j] += w[j] * x[j];
+            }
+    }
+    for (int i = 0; i < k; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < NB; ++j) s += acc[i * NB + j];
+        y[i] = s;
+    }
+    // the node sum beyond both ends: sum over u = u0 - h, u0 - 2h, ... of
+    // e^{(2m+1)u}, and over u = u0 + nn h, ... of e^{-(2m+1)u}
+    e1[0] = 1.0;
+    tridiag_solve(a, b, k, e1, t1, wk);
+    tridiag_solve(a, b, k, t1, t2, wk);
+    tridiag_solve(a, b, k, t2, t3, wk);
+    tridiag_mul(a, b, k, e1, te);
+    tridiag_mul(a, b, k, te, tte);
+    const double uL = u0 - h, uR = u0 + nn * h;
+    double gl[3], gr[3];
+    for (int m = 0; m < 3; ++m) {
+        const double q = 2.0 * m + 1.0, sg = (m & 1) ? -1.0 : 1.0;
+        gl[m] = sg * wc * std::exp(q * uL) / (1.0 - std::exp(-q * h));
+        gr[m] = sg * wc * std::exp(-q * uR) / (1.0 - std::exp(-q * h));
+    }
+    for (int i = 0; i < k; ++i)
+        y[i] += (gl[0] * t1[i] + gl[1] * t2[i] + gl[2] * t3[i]) + (gr[0] * e1[i] + gr[1] * te[i] + gr[2] * tte[i]);
+    tridiag_mul(a, b, k, y, c);
+    for (int i = 0; i < k; ++i) c[i] *= beta0;
+    return true;
+}
+
+// c = beta0 T^{1/2} e1: by quadrature for positive definite T, else
+// (rounding made T indefinite) through the eigendecomposition with the
+// negative eigenvalues clamped to zero.
 int tridiag_sqrt_coeffs(const double* alpha, const double* beta, int k, double beta0, double* c) {
+    if (tridiag_sqrt_quadrature(alpha, beta, k, beta0, c)) return RPYW_OK;
     std::vector<double> d(alpha, alpha + k), e(k, 0.0), row0;
     std::vector<Rot> rots;
     for (int i = 0; i + 1 < k; ++i) e[i] = beta[i];
@@ -145,6 +289,7 @@ size_t lanczos_ws_bytes(int64_t N, int max_iter, int n_bodies, int prec) {
     b += align_up((size_t)(max_iter + 2) * units * sizeof(double));
     b += align_up((size_t)(max_iter + 3) * lanczos_gs2_blocks((int64_t)n3, &m) * sizeof(double));
     b += align_up((units + 1) * sizeof(int)) + align_up((units + 1) * sizeof(LanczosGroup));
+    b += align_up(((size_t)N / 256 + 3) * sizeof(double));  // partials of |W|^2 (padded blobs / 256)
     return b + 24 * kAlign;
 }
 
@@ -170,22 +315,24 @@ int lanczos_fused(const double* pos, const double* W, double* out, int64_t N, do
     double* V = (double*)ar.take((size_t)(max_iter + 1) * n3 * sizeof(double));
     double* y = (double*)ar.take(n3 * sizeof(double));
     double* w = (double*)ar.take(n3 * sizeof(double));
-    double* partial = (double*)ar.take((size_t)2 * dot_chunks(n3) * sizeof(double));  // setup norm
+    const int64_t npack = lz_pack_blocks(npad);
+    double* sqp = (double*)ar.take((size_t)npack * sizeof(double));  // partials of |W|^2
     double* part1 = (double*)ar.take((size_t)(max_iter + 2) * ngroups * sizeof(double));
     double* part2 = (double*)ar.take((size_t)(max_iter + 3) * nblk4 * sizeof(double));
     double* d_ab = (double*)ar.take(2 * (max_iter + 8) * sizeof(double));
     double* d_c = (double*)ar.take(2 * (max_iter + 8) * sizeof(double));
-    double* d_b0 = (double*)ar.take(8 * sizeof(double));
-    unsigned* ticket = (unsigned*)ar.take(kAlign);
     int* notspd = (int*)ar.take(sizeof(int));
-    int* d_units = (int*)ar.take((size_t)(nunits + 1) * sizeof(int));
-    LanczosGroup* d_groups = (LanczosGroup*)ar.take((size_t)ngroups * sizeof(LanczosGroup));
+    // the gather groups' table, then the unit table, in one block (one upload)
+    const size_t gbytes = align_up((size_t)ngroups * sizeof(LanczosGroup));
+    char* d_tab = (char*)ar.take(gbytes + (size_t)(nunits + 1) * sizeof(int));
+    LanczosGroup* d_groups = (LanczosGroup*)d_tab;
+    int* d_units = (int*)(d_tab + gbytes);
     void* rec = ar.take((size_t)npad * rw * real_size(prec));
     double* B = (double*)ar.take((size_t)npad * sizeof(double));
     double* tpart = (double*)ar.take(sp.tpart_bytes);
     void* spart = ar.take(sp.spart_bytes);
-    if (!V || !y || !w || !partial || !part1 || !part2 || !d_ab || !d_c || !d_b0 || !ticket || !notspd || !d_units ||
-        !d_groups || !rec || !B || !tpart || !spart)
+    if (!V || !y || !w || !sqp || !part1 || !part2 || !d_ab || !d_c || !notspd || !d_tab || !rec || !B || !tpart ||
+        !spart)
         return RPYW_ENOMEM;
     std::lock_guard<std::mutex> lk(g_ab.mu);
     int rc = g_ab.reserve((size_t)(3 * (max_iter + 2) + 2) * sizeof(double));
@@ -193,21 +340,24 @@ int lanczos_fused(const double* pos, const double* W, double* out, int64_t N, do
     double* h_ab = g_ab.p;
     double* dh_ab = g_ab.dp;  // the same pinned memory as kernels address it
     SlotRelease slots_done{g_ab, st};
+    // the header (beta_0, then the two definiteness flags), written by vin
+    // of step 0 and read by the host with step 0
     double* h_b0 = h_ab + 2 * (max_iter + 2);
     int* h_bad = (int*)(h_b0 + 1);
+    double* dh_hdr = dh_ab + (h_b0 - h_ab);
     // step flags: set by the step's last kernel after alpha_k and beta_{k-1}
     // (no event per step: an event between the steps' kernels delays the next)
     double* h_flag = h_b0 + 2;
     double* dh_flag = dh_ab + (h_flag - h_ab);
     std::memset(h_flag, 0, (size_t)(max_iter + 2) * sizeof(double));
 
-    RPYW_HIP(hipMemsetAsync(notspd, 0, sizeof(int), st));
-    RPYW_HIP(hipMemsetAsync(ticket, 0, sizeof(unsigned), st));
+    // positions, B and the partials of |W|^2; clears notspd before the
+    // factor build (the force slots are rewritten by every step)
+    if ((rc = lz_launch_pack(prec, pos, W, N, npad, rw, a, dom, rec, B, sqp, notspd, st))) return rc;
     if (pre)
         pc = *pre;
     else if ((rc = body_factors_build(pos, N, a, eta, body_offsets, n_bodies, ar, st, pc, notspd)))
         return rc;
-    if ((rc = stage_upload(h_units.data(), h_units.size() * sizeof(int), d_units, st))) return rc;
     {
         // the gather groups' table: units, blobs, first factor block, factor size
         std::vector<LanczosGroup> gt(ngroups);
@@ -228,16 +378,11 @@ int lanczos_fused(const double* pos, const double* W, double* out, int64_t N, do
             }
             loff += G.sq;
         }
-        if ((rc = stage_upload(gt.data(), gt.size() * sizeof(LanczosGroup), d_groups, st))) return rc;
+        std::vector<char> tab(gbytes + h_units.size() * sizeof(int));
+        std::memcpy(tab.data(), gt.data(), gt.size() * sizeof(LanczosGroup));
+        std::memcpy(tab.data() + gbytes, h_units.data(), h_units.size() * sizeof(int));
+        if ((rc = stage_upload(tab.data(), tab.size(), d_tab, st))) return rc;
     }
-    // positions and B once; the force slots are rewritten by every step
-    if ((rc = sym_pack(pos, W, N, 1, 1, prec, sp, a, dom, rec, B, st))) return rc;
-    // beta0 = |W|
-    if ((rc = vec_dots(nullptr, n3, 0, W, n3, partial, ticket, d_b0, 0, nullptr, st))) return rc;
-    h_bad[0] = h_bad[1] = 0;
-    RPYW_HIP(hipMemcpyAsync(h_b0, d_b0, sizeof(double), hipMemcpyDeviceToHost, st));
-    RPYW_HIP(hipMemcpyAsync(h_bad, notspd, sizeof(int), hipMemcpyDeviceToHost, st));
-    if (pre && pre->flag) RPYW_HIP(hipMemcpyAsync(h_bad + 1, pre->flag, sizeof(int), hipMemcpyDeviceToHost, st));
     const double m0 = 1.0 / (6.0 * M_PI * eta * a);
 
     // Step k: the product (its records written by vin of step k), w = L^-1
@@ -245,8 +390,9 @@ int lanczos_fused(const double* pos, const double* W, double* out, int64_t N, do
     // with the second projection, then vin of step k + 1: beta_k, v_{k+1}
     // and the next records; it publishes step k (alpha_k, beta_k, flag).
     auto vin = [&](int k) {
-        return lz_launch_vin(prec, pc, d_units, nunits, n3, k, k == 0 ? W : y, d_b0, part2, (int)nblk4, V, d_ab,
-                             dh_ab, dh_flag, rec, rw, B, st);
+        return lz_launch_vin(prec, pc, d_units, nunits, n3, k, k == 0 ? W : y, k == 0 ? sqp : part2,
+                             k == 0 ? (int)npack : (int)nblk4, V, d_ab, dh_ab, dh_flag, rec, rw, B, dh_hdr, notspd,
+                             pre ? pre->flag : nullptr, st);
     };
     auto launch_step = [&](int k) -> int {
         int r;
@@ -259,8 +405,6 @@ int lanczos_fused(const double* pos, const double* W, double* out, int64_t N, do
             return r;
         if ((r = lz_launch_gs2(w, y, n3, V, k, part1, ngroups, part2, d_ab, nullptr, st))) return r;
         if ((r = vin(k + 1))) return r;  // V has room for max_iter + 1 vectors
-        // step 0 also waits for the set-up copies (beta_0, the definiteness flags)
-        if (k == 0) RPYW_HIP(hipEventRecord(g_ab.ev[0], st));
         return RPYW_OK;
     };
     const int depth = (double)N * (double)N <= kSpeculatePairs ? kSpeculateDepth : 0;
@@ -288,10 +432,6 @@ int lanczos_fused(const double* pos, const double* W, double* out, int64_t N, do
     // queried now and then so that a stream that drains without setting it
     // (a failed launch) ends the wait with an error instead of spinning.
     auto wait_step = [&](int k) -> int {
-        if (k == 0) {
-            RPYW_HIP(hipEventSynchronize(g_ab.ev[0]));
-            return RPYW_OK;
-        }
         const volatile double* f = h_flag + k;
         for (unsigned spin = 1;; ++spin) {
             if (*f != 0.0) break;
@@ -361,9 +501,14 @@ int lanczos_fused(const double* pos, const double* W, double* out, int64_t N, do
     if (!converged) used = max_iter;
     *iters = used;
     *err = std::isfinite(rel) ? rel : 0.0;
-    if ((rc = stage_upload(c.data(), used * sizeof(double), d_c, st))) return rc;
-    if ((rc = vec_comb(V, n3, used, d_c, y, n3, st))) return rc;  // y = V c
-    if ((rc = pc.apply(0, y, out, n3, st))) return rc;            // out = L y
+    if (used <= kLanczosCoefArgs) {
+        // out = L (V c) in one launch, c passed by value
+        if ((rc = lz_launch_fin(pc, d_units, nunits, n3, V, c.data(), used, out, st))) return rc;
+    } else {
+        if ((rc = stage_upload(c.data(), used * sizeof(double), d_c, st))) return rc;
+        if ((rc = vec_comb(V, n3, used, d_c, y, n3, st))) return rc;  // y = V c
+        if ((rc = pc.apply(0, y, out, n3, st))) return rc;            // out = L y
+    }
     if (logging)
         log_line("lanczos fused steps: %d run, %d queued; host %.3f ms, of which %.3f ms waiting; %d waits with no "
                  "later step queued",

@@ -44,29 +44,33 @@ constexpr int kVinThreads = 256;
 constexpr int kOutThreads = 512;
 constexpr int kGs2Threads = 256;
 constexpr int kVinReg = 64;  // basis values vin keeps in registers
+constexpr int kPackThreads = 256;
 
 template <typename R>
 __global__ __launch_bounds__(kVinThreads) void lz_vin_kernel(int diag, const int* __restrict__ units,
                                                              const int64_t* __restrict__ lofs,
                                                              const double* __restrict__ Lall, int64_t n3, int k,
                                                              const double* __restrict__ src,
-                                                             const double* __restrict__ b0,
                                                              const double* __restrict__ part2, int ncol2,
                                                              double* __restrict__ V, double* __restrict__ d_ab,
                                                              double* __restrict__ h_ab, double* __restrict__ h_flag,
                                                              R* __restrict__ rec, int recw,
-                                                             const double* __restrict__ B) {
+                                                             const double* __restrict__ B,
+                                                             double* __restrict__ h_hdr,
+                                                             const int* __restrict__ bad0,
+                                                             const int* __restrict__ bad1) {
     constexpr int PW = pos_slots<R>();
     __shared__ double c[kLanczosFusedMaxIter + 2];
     __shared__ double x[3 * kMaxBodyBlobs];
     __shared__ double Li[kLdsFactor];
     __shared__ double sinv;
     const int p = blockIdx.x, t = threadIdx.x;
-    // The partials of gs2 first (they depend on nothing this kernel loads):
-    // with up to 64 rows of up to 64 columns, one batch of loads per lane
-    // (4 lanes per row), added up after the other loads are issued.
+    // The partials of gs2 first (they depend on nothing this kernel loads;
+    // at k = 0 the packing kernel's partials of |W|^2): with up to 64 rows
+    // of up to 64 columns, one batch of loads per lane (4 lanes per row),
+    // added up after the other loads are issued.
     constexpr int kRl = 4;
-    const bool one_batch = k > 0 && k + 1 <= kVinThreads / kRl && ncol2 <= kRl * kPre;
+    const bool one_batch = k + 1 <= kVinThreads / kRl && ncol2 <= kRl * kPre;
     const int rr = t / kRl, rq = t % kRl;
     double pv[kPre];
     if (one_batch && rr <= k) {
@@ -94,8 +98,9 @@ __global__ __launch_bounds__(kVinThreads) void lz_vin_kernel(int diag, const int
 #pragma unroll
         for (int j = j0; j < j0 + 16; ++j) a[j] = V[(j < k ? j : 0) * n3 + ec];
     }
-    if (k > 0) {
-        // c[0..k) = c2, c[k] = |y'|^2; one pass over up to 64 rows
+    {
+        // c[0..k) = c2, c[k] = |y'|^2 (k = 0: |W|^2); one pass over up to 64
+        // rows
         if (one_batch) {
             double sr = 0.0;
 #pragma unroll
@@ -112,7 +117,7 @@ __global__ __launch_bounds__(kVinThreads) void lz_vin_kernel(int diag, const int
             for (int j = 0; j < k; ++j) s2 -= c[j] * c[j];
             const double beta = s2 > 0.0 ? sqrt(s2) : 0.0;
             sinv = 1.0 / beta;  // beta = 0: breakdown, this step's values are discarded
-            if (p == 0) {
+            if (p == 0 && k > 0) {
                 // publish step k - 1: alpha (kept by its gs2) and beta, then,
                 // after a system-scope fence, its flag
                 d_ab[2 * (k - 1) + 1] = beta;
@@ -120,10 +125,17 @@ __global__ __launch_bounds__(kVinThreads) void lz_vin_kernel(int diag, const int
                 h_ab[2 * (k - 1) + 1] = beta;
                 __threadfence_system();
                 h_flag[k - 1] = 1.0;
+            } else if (p == 0) {
+                // the call's header: beta_0 = |W| and the definiteness flags
+                // of the factors; the host reads it with step 0, whose flag a
+                // later kernel sets
+                h_hdr[0] = beta;
+                int* hb = reinterpret_cast<int*>(h_hdr + 1);
+                hb[0] = bad0[0];
+                hb[1] = bad1 ? bad1[0] : 0;
+                __threadfence_system();
             }
         }
-    } else if (t == 0) {
-        sinv = 1.0 / b0[0];
     }
     if (lds_factor) sf.store(Li, n * n);  // read after the next barrier
     __syncthreads();
@@ -408,6 +420,80 @@ __global__ __launch_bounds__(kGs2Threads) void lz_gs2_kernel(const double* __res
     }
 }
 
+// The call's first kernel: the pair kernel's records of positions (and W
+// in the force slots, which vin rewrites), B, and per block of 256 blobs
+// the partial sum of |W_i|^2 (a fixed-order tree), from which vin of step 0
+// forms beta_0 = |W|; block 0 also clears the definiteness flag that the
+// factor build sets, which runs next.
+template <typename R>
+__global__ __launch_bounds__(kPackThreads) void lz_pack_kernel(const double* __restrict__ pos,
+                                                               const double* __restrict__ W, int64_t N, int recw,
+                                                               double inv_a, double lx, double ly, int64_t npad,
+                                                               R* __restrict__ rec, double* __restrict__ B,
+                                                               double* __restrict__ sqp, int* __restrict__ bad) {
+    __shared__ double red[kPackThreads];
+    const int t = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * kPackThreads + t;
+    double w2 = 0.0;
+    if (i < npad) {
+        double b;
+        make_record<R>(pos, W, N, 1, recw, inv_a, nullptr, lx, ly, i, rec + i * recw, &b);
+        B[i] = b;
+        if (i < N) w2 = W[3 * i] * W[3 * i] + W[3 * i + 1] * W[3 * i + 1] + W[3 * i + 2] * W[3 * i + 2];
+    }
+    red[t] = w2;
+    __syncthreads();
+    for (int h = kPackThreads / 2; h > 0; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    if (t == 0) {
+        sqp[blockIdx.x] = red[0];
+        if (blockIdx.x == 0) *bad = 0;
+    }
+}
+
+// The call's last kernel: out = L (V c) per unit (body, or run of blobs),
+// with the coefficients c passed by value.
+struct LzCoefs {
+    double c[kLanczosCoefArgs];
+};
+__global__ __launch_bounds__(kVinThreads) void lz_fin_kernel(int diag, const int* __restrict__ units,
+                                                             const int64_t* __restrict__ lofs,
+                                                             const double* __restrict__ Lall, int64_t n3,
+                                                             const double* __restrict__ V, int nv, LzCoefs cf,
+                                                             double* __restrict__ out) {
+    __shared__ double y[3 * kMaxBodyBlobs];
+    const int p = blockIdx.x, t = threadIdx.x;
+    const int64_t e0 = 3 * (int64_t)units[p];
+    const int n = (int)(3 * (int64_t)units[p + 1] - e0);
+    double s = 0.0;
+    if (t < n) {
+        const double* v = V + e0 + t;
+        double s1 = 0.0;
+        int j = 0;
+        for (; j + 1 < nv; j += 2) {
+            s = fma(cf.c[j], v[j * n3], s);
+            s1 = fma(cf.c[j + 1], v[(j + 1) * n3], s1);
+        }
+        if (j < nv) s = fma(cf.c[j], v[j * n3], s);
+        s += s1;
+        y[t] = s;
+    }
+    __syncthreads();
+    if (t < n) {
+        double o;
+        if (diag) {
+            o = Lall[e0 + t] * s;
+        } else {
+            const double* Lr = Lall + 2 * lofs[p] + (int64_t)t * n;  // row t of L_p
+            o = 0.0;
+            for (int m = 0; m <= t; ++m) o = fma(Lr[m], y[m], o);
+        }
+        out[e0 + t] = o;
+    }
+}
+
 }  // namespace
 
 bool lanczos_fused_applies(int64_t N, int prec, int max_iter, const Domain& dom, SymPlan* sp, int* ipw) {
@@ -458,16 +544,17 @@ void lanczos_units(int64_t N, const int64_t* body_offsets, int n_bodies, std::ve
 }
 
 int lz_launch_vin(int prec, const BodyFactors& pc, const int* units, int nunits, int64_t n3, int k,
-                  const double* src, const double* b0, const double* part2, int ncol2, double* V, double* d_ab,
-                  double* h_ab, double* h_flag, void* rec, int recw, const double* B, hipStream_t st) {
+                  const double* src, const double* part2, int ncol2, double* V, double* d_ab, double* h_ab,
+                  double* h_flag, void* rec, int recw, const double* B, double* h_hdr, const int* bad0,
+                  const int* bad1, hipStream_t st) {
     if (prec == RPYW_FP32C)
         hipLaunchKernelGGL(lz_vin_kernel<float>, dim3((unsigned)nunits), dim3(kVinThreads), 0, st, pc.diag ? 1 : 0,
-                           units, pc.lofs, pc.L, n3, k, src, b0, part2, ncol2, V, d_ab, h_ab, h_flag, (float*)rec,
-                           recw, B);
+                           units, pc.lofs, pc.L, n3, k, src, part2, ncol2, V, d_ab, h_ab, h_flag, (float*)rec, recw,
+                           B, h_hdr, bad0, bad1);
     else
         hipLaunchKernelGGL(lz_vin_kernel<double>, dim3((unsigned)nunits), dim3(kVinThreads), 0, st, pc.diag ? 1 : 0,
-                           units, pc.lofs, pc.L, n3, k, src, b0, part2, ncol2, V, d_ab, h_ab, h_flag, (double*)rec,
-                           recw, B);
+                           units, pc.lofs, pc.L, n3, k, src, part2, ncol2, V, d_ab, h_ab, h_flag, (double*)rec, recw,
+                           B, h_hdr, bad0, bad1);
     RPYW_HIP(hipGetLastError());
     return RPYW_OK;
 }
@@ -483,6 +570,32 @@ int lz_launch_out(int prec, const BodyFactors& pc, const int* units, const Lancz
         hipLaunchKernelGGL(lz_out_kernel<double>, dim3((unsigned)ngroups), dim3(kOutThreads), 0, st, pc.diag ? 1 : 0,
                            units, ginfo, pc.L, tpart, (const double*)spart, sp.ng, sp.C, sp.Hmax, sp.nseg, sp.G, B,
                            mu0, n3, k, V, d_ab, w, part1, ngroups);
+    RPYW_HIP(hipGetLastError());
+    return RPYW_OK;
+}
+
+int64_t lz_pack_blocks(int64_t npad) { return (npad + kPackThreads - 1) / kPackThreads; }
+
+int lz_launch_pack(int prec, const double* pos, const double* W, int64_t N, int64_t npad, int recw, double a,
+                   const Domain& dom, void* rec, double* B, double* sqp, int* bad, hipStream_t st) {
+    const unsigned g = (unsigned)lz_pack_blocks(npad);
+    if (prec == RPYW_FP32C)
+        hipLaunchKernelGGL(lz_pack_kernel<float>, dim3(g), dim3(kPackThreads), 0, st, pos, W, N, recw, 1.0 / a,
+                           dom.lx / a, dom.ly / a, npad, (float*)rec, B, sqp, bad);
+    else
+        hipLaunchKernelGGL(lz_pack_kernel<double>, dim3(g), dim3(kPackThreads), 0, st, pos, W, N, recw, 1.0 / a,
+                           dom.lx / a, dom.ly / a, npad, (double*)rec, B, sqp, bad);
+    RPYW_HIP(hipGetLastError());
+    return RPYW_OK;
+}
+
+int lz_launch_fin(const BodyFactors& pc, const int* units, int nunits, int64_t n3, const double* V, const double* c,
+                  int nv, double* out, hipStream_t st) {
+    if (nv < 1 || nv > kLanczosCoefArgs) return RPYW_EINVAL;
+    LzCoefs cf;
+    for (int j = 0; j < kLanczosCoefArgs; ++j) cf.c[j] = j < nv ? c[j] : 0.0;
+    hipLaunchKernelGGL(lz_fin_kernel, dim3((unsigned)nunits), dim3(kVinThreads), 0, st, pc.diag ? 1 : 0, units,
+                       pc.lofs, pc.L, n3, V, nv, cf, out);
     RPYW_HIP(hipGetLastError());
     return RPYW_OK;
 }

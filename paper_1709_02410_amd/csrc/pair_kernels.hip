@@ -753,14 +753,14 @@ int batched_products(const double* pos, const int64_t* sys_offsets, int S, const
     const int64_t Ntot = sys_offsets[S];
     int64_t nmax = 0;
     for (int s = 0; s < S; ++s) nmax = std::max(nmax, sys_offsets[s + 1] - sys_offsets[s]);
-    // The batched kernel is the plain one: a symmetric tuned shape (chosen
-    // for single products of this size) gives way to the plain default with
-    // the widest RHS block.
-    Shape sh = tuned_shape(nmax, k, prec);
-    if (sh.sym) {
-        sh = default_shape(nmax, k, prec);
-        sh.sym = 0;
-    }
+    // The batched kernel is the plain one, with the widest RHS block (one
+    // pass over the sources per item): the shapes tuned for products of one
+    // system (a symmetric kernel, or narrower blocks that fill the GPU with a
+    // single system) do not carry over to a persistent launch over many; the
+    // RPYW_TILE / RPYW_RHS_WIDTH overrides still apply.
+    Shape sh = default_shape(nmax, k, prec);
+    sh.sym = 0;
+    sh = apply_env_overrides(sh);
     sh = normalized(sh, kernel_k(sh.kblk, prec));
     // Work list in LPT order: systems by decreasing size, then their tiles.
     std::vector<int> order(S);

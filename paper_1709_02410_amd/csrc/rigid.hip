@@ -326,6 +326,7 @@ size_t rigid_ws_bytes(int64_t N, int max_iter, int n_bodies, int prec) {
     b += align_up((m + 2) * (size_t)std::max(n_bodies, 1) * sizeof(double));
     b += align_up((m + 3) * (size_t)lanczos_gs2_blocks((int64_t)n, &m4) * sizeof(double));
     b += align_up((m + 8) * sizeof(double));
+    b += align_up((n / 256 + 2) * sizeof(double));  // partials of |b|^2
     return b + 24 * kAlign;
 }
 
@@ -356,20 +357,19 @@ int rigid_fused(const double* pos, const double* q, const int64_t* body_offsets,
     double* wb = (double*)ar.take(n * sizeof(double));  // w = A z
     double* yb = (double*)ar.take(n * sizeof(double));  // y' = w - V c1
     double* bv = (double*)ar.take(n * sizeof(double));
-    double* partial = (double*)ar.take((size_t)2 * dot_chunks(n) * sizeof(double));  // |b|
+    const int64_t nrhs = rg_rhs_blocks(n);
+    double* sqp = (double*)ar.take((size_t)nrhs * sizeof(double));  // partials of |b|^2
     double* part1 = (double*)ar.take((size_t)(max_iter + 2) * n_bodies * sizeof(double));
     double* part2 = (double*)ar.take((size_t)(max_iter + 3) * nblk4 * sizeof(double));
     double* gc1 = (double*)ar.take((max_iter + 8) * sizeof(double));  // c1 of the last step
-    double* d_b = (double*)ar.take(8 * sizeof(double));
     double* d_y = (double*)ar.take((max_iter + 8) * sizeof(double));
-    unsigned* ticket = (unsigned*)ar.take(kAlign);
     int* notspd = (int*)ar.take(sizeof(int));
     void* rec = ar.take((size_t)npad * rw * real_size(prec));
     double* B = (double*)ar.take((size_t)npad * sizeof(double));
     double* tpart = (double*)ar.take(sp.tpart_bytes);
     void* spart = ar.take(sp.spart_bytes);
-    if (!Wall || !Nall || !V || !zb || !wb || !yb || !bv || !partial || !part1 || !part2 || !gc1 || !d_b || !d_y ||
-        !ticket || !notspd || !rec || !B || !tpart || !spart)
+    if (!Wall || !Nall || !V || !zb || !wb || !yb || !bv || !sqp || !part1 || !part2 || !gc1 || !d_y || !notspd ||
+        !rec || !B || !tpart || !spart)
         return RPYW_ENOMEM;
     std::lock_guard<std::mutex> lk(g_h.mu);
     const int slot = 2 * (max_iter + 2);  // c1[0..k], c2[0..k], h_{k+1,k}
@@ -377,14 +377,17 @@ int rigid_fused(const double* pos, const double* q, const int64_t* body_offsets,
     if (rc) return rc;
     SlotRelease slots_done{g_h, st};
     double* h_slot = g_h.p;
+    // the header (|b|, then the two definiteness flags), written by pre of
+    // step 0 and read by the host with step 0
     double* h_b = h_slot + (size_t)PinnedSlots::kSlots * slot;
     int* h_bad = (int*)(h_b + 1);
+    double* dh_hdr = g_h.dp + (h_b - h_slot);
     double* h_flag = h_b + 2;
     double* dh_flag = g_h.dp + (h_flag - h_slot);
     std::memset(h_flag, 0, (size_t)(max_iter + 2) * sizeof(double));
 
-    RPYW_HIP(hipMemsetAsync(notspd, 0, sizeof(int), st));
-    RPYW_HIP(hipMemsetAsync(ticket, 0, sizeof(unsigned), st));
+    // b, the partials of |b|^2, and notspd cleared before the factor kernels
+    if ((rc = rg_launch_rhs(slip, FT, n3, n6, bv, sqp, notspd, st))) return rc;
     if (pre)
         pc = *pre;
     else if ((rc = body_factors_build(pos, N, a, eta, body_offsets, n_bodies, ar, st, pc, notspd)))
@@ -392,23 +395,17 @@ int rigid_fused(const double* pos, const double* q, const int64_t* body_offsets,
     hipLaunchKernelGGL(rigid_factors_kernel, dim3(n_bodies), dim3(kRT), 0, st, pos, q, pc.bofs, pc.lofs, pc.L, Wall,
                        Nall, notspd);
     RPYW_HIP(hipGetLastError());
-    hipLaunchKernelGGL(rigid_rhs_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, slip, FT, n3, n6, bv);
-    RPYW_HIP(hipGetLastError());
     // positions and B once; the force slots are rewritten by every step
     if ((rc = sym_pack(pos, bv, N, 1, 1, prec, sp, a, dom, rec, B, st))) return rc;
-    if ((rc = vec_dots(nullptr, n, 0, bv, n, partial, ticket, d_b, 0, nullptr, st))) return rc;  // |b|
-    h_bad[0] = h_bad[1] = 0;
-    RPYW_HIP(hipMemcpyAsync(h_b, d_b, sizeof(double), hipMemcpyDeviceToHost, st));
-    RPYW_HIP(hipMemcpyAsync(h_bad, notspd, sizeof(int), hipMemcpyDeviceToHost, st));
-    if (pre && pre->flag) RPYW_HIP(hipMemcpyAsync(h_bad + 1, pre->flag, sizeof(int), hipMemcpyDeviceToHost, st));
     const double m0 = 1.0 / (6.0 * M_PI * eta * a);
 
     // Step k: the product of z (records written by pre of step k), w = A z
     // with the first projection, y' = w - V c1 with the second projection,
     // then pre of step k + 1, which publishes the column of step k.
     auto pre_k = [&](int k) {
-        return rg_launch_pre(prec, pc, Wall, Nall, n_bodies, n3, n, k ? yb : bv, part2, (int)nblk4, d_b, gc1, g_h.dp,
-                             slot, dh_flag, k, V, zb, zb + n3, rec, rw, B, st);
+        return rg_launch_pre(prec, pc, Wall, Nall, n_bodies, n3, n, k ? yb : bv, k ? part2 : sqp,
+                             k ? (int)nblk4 : (int)nrhs, gc1, g_h.dp, slot, dh_flag, k, V, zb, zb + n3, rec, rw, B,
+                             dh_hdr, notspd, pre ? pre->flag : nullptr, st);
     };
     auto launch_step = [&](int k) -> int {
         int r;
@@ -418,8 +415,6 @@ int rigid_fused(const double* pos, const double* q, const int64_t* body_offsets,
             return r;
         if ((r = lz_launch_gs2(wb, yb, n, V, k, part1, n_bodies, part2, nullptr, gc1, st))) return r;
         if ((r = pre_k(k + 1))) return r;  // V has room for max_iter + 1 vectors
-        // step 0 also waits for the set-up copies (|b|, the definiteness flags)
-        if (k == 0) RPYW_HIP(hipEventRecord(g_h.ev[0], st));
         return RPYW_OK;
     };
     const int depth = (double)N * (double)N <= kSpeculatePairs ? kSpeculateDepth : 0;
@@ -432,10 +427,6 @@ int rigid_fused(const double* pos, const double* q, const int64_t* body_offsets,
     // Waits for step k: its flag, polled; the stream is queried now and then
     // so that a stream that drains without setting it ends the wait.
     auto wait_step = [&](int k) -> int {
-        if (k == 0) {
-            RPYW_HIP(hipEventSynchronize(g_h.ev[0]));
-            return RPYW_OK;
-        }
         const volatile double* f = h_flag + k;
         for (unsigned spin = 1;; ++spin) {
             if (*f != 0.0) break;

@@ -6,7 +6,8 @@
 //         added up from the block partials of its gs2 in a fixed order
 //         (every workgroup repeats that small sum), h = (|y'|^2 -
 //         |c2|^2)^{1/2}, and v_k = (y' - V c2) / h, the second Gram-Schmidt
-//         correction (b / |b| at k = 0), stored as basis vector k;
+//         correction (b / |b| at k = 0, |b|^2 from the block partials of
+//         the right-hand side kernel), stored as basis vector k;
 //         z = P^-1 v_k for the body (the exact inverse of its own
 //         saddle-point block, factors staged through LDS); B z_lambda
 //         written straight into the force slots of the pair kernel's
@@ -38,15 +39,16 @@ constexpr int kPreThreads = 256;  // at least 3 kMaxBodyBlobs + 6 (one thread pe
 constexpr int kOutThreads = 256;
 constexpr int kMaxN3 = 3 * kMaxBodyBlobs;
 constexpr int kPreReg = 64;  // basis values pre keeps in registers
+constexpr int kRhsThreads = 256;
 
 template <typename R>
 __global__ __launch_bounds__(kPreThreads) void rg_pre_kernel(
     const double* __restrict__ Lall, const int* __restrict__ bofs, const int64_t* __restrict__ lofs,
     const double* __restrict__ Wall, const double* __restrict__ Nall, int64_t n3, int64_t ld,
-    const double* __restrict__ src, const double* __restrict__ part2, int ncol2, const double* __restrict__ bnorm,
-    const double* __restrict__ gc1, double* __restrict__ hslots, int slot, double* __restrict__ h_flag, int k,
-    double* __restrict__ V, double* __restrict__ zl, double* __restrict__ zu, R* __restrict__ rec, int recw,
-    const double* __restrict__ B) {
+    const double* __restrict__ src, const double* __restrict__ part2, int ncol2, const double* __restrict__ gc1,
+    double* __restrict__ hslots, int slot, double* __restrict__ h_flag, int k, double* __restrict__ V,
+    double* __restrict__ zl, double* __restrict__ zu, R* __restrict__ rec, int recw, const double* __restrict__ B,
+    double* __restrict__ h_hdr, const int* __restrict__ bad0, const int* __restrict__ bad1) {
     constexpr int PW = pos_slots<R>();
     __shared__ double cs[kLanczosFusedMaxIter + 1];
     __shared__ double r[kMaxN3 + 6], t1[kMaxN3], tt[kMaxN3];
@@ -80,16 +82,28 @@ __global__ __launch_bounds__(kPreThreads) void rg_pre_kernel(
     if (t < 6)
 #pragma unroll
         for (int c = 0; c < 6; ++c) np[c] = Nall[36 * (int64_t)p + 6 * t + c];
-    if (k > 0) {
-        // c2 of step k - 1 into cs[0..k), |y'|^2 into cs[k]
-        reduce_rows<kPreThreads, 4, kPre>(part2, k + 1, ncol2, cs);
-        if (t == 0) {
-            double s2 = cs[k];
-            for (int j = 0; j < k; ++j) s2 -= cs[j] * cs[j];
-            const double h = s2 > 0.0 ? sqrt(s2) : 0.0;
-            sc = h;  // h = 0: breakdown, this step's values are discarded
-            if (p == 0) hslots[(size_t)((k - 1) % PinnedSlots::kSlots) * slot + 2 * k] = h;
+    // c2 of step k - 1 into cs[0..k), |y'|^2 into cs[k] (k = 0: |b|^2 from
+    // the right-hand side kernel's partials)
+    reduce_rows<kPreThreads, 4, kPre>(part2, k + 1, ncol2, cs);
+    if (t == 0) {
+        double s2 = cs[k];
+        for (int j = 0; j < k; ++j) s2 -= cs[j] * cs[j];
+        const double h = s2 > 0.0 ? sqrt(s2) : 0.0;
+        sc = h;  // h = 0: breakdown, this step's values are discarded
+        if (p == 0 && k > 0) {
+            hslots[(size_t)((k - 1) % PinnedSlots::kSlots) * slot + 2 * k] = h;
+        } else if (p == 0) {
+            // the call's header: |b| and the definiteness flags of the
+            // factors; the host reads it with step 0, whose flag a later
+            // kernel sets
+            h_hdr[0] = h;
+            int* hb = reinterpret_cast<int*>(h_hdr + 1);
+            hb[0] = bad0[0];
+            hb[1] = bad1 ? bad1[0] : 0;
+            __threadfence_system();
         }
+    }
+    if (k > 0) {
         if (p == 0) {
             // publish column k - 1: c1 (kept by its gs2), c2, h; then its flag
             double* hc = hslots + (size_t)((k - 1) % PinnedSlots::kSlots) * slot;
@@ -101,8 +115,6 @@ __global__ __launch_bounds__(kPreThreads) void rg_pre_kernel(
             __syncthreads();
             if (t == 0) h_flag[k - 1] = 1.0;
         }
-    } else if (t == 0) {
-        sc = bnorm[0];
     }
     if (lds_factor) sl.store(Ls, n * n);
     sw.store(Ws, 6 * n);
@@ -154,6 +166,35 @@ __global__ __launch_bounds__(kPreThreads) void rg_pre_kernel(
         zl[e0 + t] = s;
         const int64_t blob = (e0 + t) / 3;
         rec[blob * recw + PW + (int)(e0 + t - 3 * blob)] = (R)(B[blob] * s);
+    }
+}
+
+// The right-hand side b = [-slip | -F, -T] of the saddle-point system, per
+// block the partial sum of |b_e|^2 (a fixed-order tree; pre of step 0
+// forms |b| from them), and block 0 clears the definiteness flag that the
+// factor kernels, which run next, set.
+__global__ __launch_bounds__(kRhsThreads) void rg_rhs_kernel(const double* __restrict__ slip,
+                                                             const double* __restrict__ FT, int64_t n3, int64_t n6,
+                                                             double* __restrict__ b, double* __restrict__ sqp,
+                                                             int* __restrict__ bad) {
+    __shared__ double red[kRhsThreads];
+    const int t = threadIdx.x;
+    const int64_t e = (int64_t)blockIdx.x * kRhsThreads + t;
+    double v = 0.0;
+    if (e < n3)
+        v = slip ? -slip[e] : 0.0;
+    else if (e < n3 + n6)
+        v = FT ? -FT[e - n3] : 0.0;
+    if (e < n3 + n6) b[e] = v;
+    red[t] = v * v;
+    __syncthreads();
+    for (int h = kRhsThreads / 2; h > 0; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    if (t == 0) {
+        sqp[blockIdx.x] = red[0];
+        if (blockIdx.x == 0) *bad = 0;
     }
 }
 
@@ -283,17 +324,27 @@ __global__ __launch_bounds__(kOutThreads) void rg_out_kernel(
 }  // namespace
 
 int rg_launch_pre(int prec, const BodyFactors& pc, const double* Wall, const double* Nall, int n_bodies, int64_t n3,
-                  int64_t ld, const double* src, const double* part2, int ncol2, const double* bnorm,
-                  const double* gc1, double* hslots, int slot, double* h_flag, int k, double* V, double* zl,
-                  double* zu, void* rec, int recw, const double* B, hipStream_t st) {
+                  int64_t ld, const double* src, const double* part2, int ncol2, const double* gc1, double* hslots,
+                  int slot, double* h_flag, int k, double* V, double* zl, double* zu, void* rec, int recw,
+                  const double* B, double* h_hdr, const int* bad0, const int* bad1, hipStream_t st) {
     if (prec == RPYW_FP32C)
         hipLaunchKernelGGL(rg_pre_kernel<float>, dim3((unsigned)n_bodies), dim3(kPreThreads), 0, st, pc.L, pc.bofs,
-                           pc.lofs, Wall, Nall, n3, ld, src, part2, ncol2, bnorm, gc1, hslots, slot, h_flag, k, V, zl,
-                           zu, (float*)rec, recw, B);
+                           pc.lofs, Wall, Nall, n3, ld, src, part2, ncol2, gc1, hslots, slot, h_flag, k, V, zl, zu,
+                           (float*)rec, recw, B, h_hdr, bad0, bad1);
     else
         hipLaunchKernelGGL(rg_pre_kernel<double>, dim3((unsigned)n_bodies), dim3(kPreThreads), 0, st, pc.L, pc.bofs,
-                           pc.lofs, Wall, Nall, n3, ld, src, part2, ncol2, bnorm, gc1, hslots, slot, h_flag, k, V, zl,
-                           zu, (double*)rec, recw, B);
+                           pc.lofs, Wall, Nall, n3, ld, src, part2, ncol2, gc1, hslots, slot, h_flag, k, V, zl, zu,
+                           (double*)rec, recw, B, h_hdr, bad0, bad1);
+    RPYW_HIP(hipGetLastError());
+    return RPYW_OK;
+}
+
+int64_t rg_rhs_blocks(int64_t n) { return (n + kRhsThreads - 1) / kRhsThreads; }
+
+int rg_launch_rhs(const double* slip, const double* FT, int64_t n3, int64_t n6, double* b, double* sqp, int* bad,
+                  hipStream_t st) {
+    hipLaunchKernelGGL(rg_rhs_kernel, dim3((unsigned)rg_rhs_blocks(n3 + n6)), dim3(kRhsThreads), 0, st, slip, FT, n3,
+                       n6, b, sqp, bad);
     RPYW_HIP(hipGetLastError());
     return RPYW_OK;
 }

@@ -193,9 +193,22 @@ bool lanczos_fused_applies(int64_t N, int prec, int max_iter, const Domain& dom,
 int64_t lanczos_gs2_blocks(int64_t n3, int* m);
 void lanczos_units(int64_t N, const int64_t* body_offsets, int n_bodies, std::vector<int>& units,
                    std::vector<int>& groups);
+// vin of step k; at k = 0, part2 holds the packing kernel's partials of
+// |W|^2 and vin writes the header (beta_0, then the two definiteness flags
+// *bad0 and *bad1 (0 when null) as ints) to the pinned h_hdr.
 int lz_launch_vin(int prec, const BodyFactors& pc, const int* units, int nunits, int64_t n3, int k,
-                  const double* src, const double* b0, const double* part2, int ncol2, double* V, double* d_ab,
-                  double* h_ab, double* h_flag, void* rec, int recw, const double* B, hipStream_t st);
+                  const double* src, const double* part2, int ncol2, double* V, double* d_ab, double* h_ab,
+                  double* h_flag, void* rec, int recw, const double* B, double* h_hdr, const int* bad0,
+                  const int* bad1, hipStream_t st);
+// Records, B and the |W|^2 partials (lz_pack_blocks of them) for npad
+// blobs; clears *bad.
+int64_t lz_pack_blocks(int64_t npad);
+int lz_launch_pack(int prec, const double* pos, const double* W, int64_t N, int64_t npad, int recw, double a,
+                   const Domain& dom, void* rec, double* B, double* sqp, int* bad, hipStream_t st);
+// out = L (V c) for nv <= kLanczosCoefArgs coefficients (passed by value).
+constexpr int kLanczosCoefArgs = 448;
+int lz_launch_fin(const BodyFactors& pc, const int* units, int nunits, int64_t n3, const double* V, const double* c,
+                  int nv, double* out, hipStream_t st);
 int lz_launch_out(int prec, const BodyFactors& pc, const int* units, const LanczosGroup* ginfo, int ngroups,
                   const double* tpart, const void* spart, const SymPlan& sp, const double* B, double mu0, int64_t n3,
                   int k, const double* V, const double* d_ab, double* w, double* part1, hipStream_t st);
@@ -206,10 +219,18 @@ int lz_launch_gs2(const double* w, double* yo, int64_t n3, const double* V, int 
 // gs2 kernel (gc1: where its block 0 keeps c1 for the next pre).
 // pre publishes column k - 1 of the Hessenberg matrix into the pinned
 // slot hslots + ((k - 1) mod PinnedSlots::kSlots) slot and sets h_flag[k - 1].
+// At k = 0, part2 holds the right-hand side kernel's partials of |b|^2 and
+// pre writes the header (|b|, then the flags *bad0 and *bad1 (0 when null)
+// as ints) to the pinned h_hdr.
 int rg_launch_pre(int prec, const BodyFactors& pc, const double* Wall, const double* Nall, int n_bodies, int64_t n3,
-                  int64_t ld, const double* src, const double* part2, int ncol2, const double* bnorm,
-                  const double* gc1, double* hslots, int slot, double* h_flag, int k, double* V, double* zl,
-                  double* zu, void* rec, int recw, const double* B, hipStream_t st);
+                  int64_t ld, const double* src, const double* part2, int ncol2, const double* gc1, double* hslots,
+                  int slot, double* h_flag, int k, double* V, double* zl, double* zu, void* rec, int recw,
+                  const double* B, double* h_hdr, const int* bad0, const int* bad1, hipStream_t st);
+// b = [-slip | -F, -T] (n3 + n6 entries), the partials of |b|^2
+// (rg_rhs_blocks of them); clears *bad.
+int64_t rg_rhs_blocks(int64_t n);
+int rg_launch_rhs(const double* slip, const double* FT, int64_t n3, int64_t n6, double* b, double* sqp, int* bad,
+                  hipStream_t st);
 int rg_launch_out(int prec, const double* pos, const double* q, const int* bofs, int n_bodies, const double* tpart,
                   const void* spart, const SymPlan& sp, const double* B, double mu0, const double* zl,
                   const double* zu, int64_t n3, int64_t ld, const double* V, int k, double* w, double* part1,

@@ -145,9 +145,10 @@ def test_workspace_sizes(lib):
         assert lib.rpyw_strerror(s)
 
 
-@pytest.mark.parametrize("k", [1, 2, 5, 30, 120])
+@pytest.mark.parametrize("k", [1, 2, 5, 30, 120, 250])
 def test_tridiagonal_root_coefficients(lib, k):
-    """beta0 Q Lambda^{1/2} Q^T e1 from the host implicit QR solver against numpy."""
+    """beta0 T^{1/2} e1 from the host solver (quadrature for SPD T) against
+    numpy's eigendecomposition."""
     rng = np.random.default_rng(k)
     alpha = rng.uniform(0.5, 2.0, k)
     beta = rng.uniform(0.01, 0.4, max(k - 1, 0))
