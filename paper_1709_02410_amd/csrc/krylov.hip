@@ -26,6 +26,7 @@ constexpr int kBuildThreads = 256;
 // LDS is sized at launch for the largest body of the call (ld = 3 n_max + 1
 // doubles per row, then 4 n_max doubles of blob data), so that small bodies
 // keep many workgroups per CU.
+template <int KR>
 __global__ __launch_bounds__(kBuildThreads) void precond_build_kernel(const double* __restrict__ pos,
                                                                      const int* __restrict__ bofs,
                                                                      const int64_t* __restrict__ lofs, double inv_a,
@@ -38,11 +39,18 @@ __global__ __launch_bounds__(kBuildThreads) void precond_build_kernel(const doub
     double* py = px + nmax;
     double* pz = py + nmax;
     double* pb = pz + nmax;
+    // KR > 0: the eliminated identity Y (n x n, row stride 3 nmax), after
+    // the blob data
+    double* Ybase = pb + nmax;
+    const int ldy = 3 * nmax;
     __shared__ int bad;
     const int p = blockIdx.x;
     const int b0 = bofs[p], nb = bofs[p + 1] - b0, n = 3 * nb;
 #define A(i, j) Abase[(i) * ld + (j)]
+#define Y(i, j) Ybase[(i) * ldy + (j)]
     if (threadIdx.x == 0) bad = 0;
+    if constexpr (KR > 0)
+        for (int q = threadIdx.x; q < n * n; q += blockDim.x) Y(q / n, q % n) = q / n == q % n ? 1.0 : 0.0;
     for (int a = threadIdx.x; a < nb; a += blockDim.x) {
         const double x = pos[3 * (b0 + a)] * inv_a, y = pos[3 * (b0 + a) + 1] * inv_a,
                      z = pos[3 * (b0 + a) + 2] * inv_a;
@@ -67,21 +75,72 @@ __global__ __launch_bounds__(kBuildThreads) void precond_build_kernel(const doub
     __syncthreads();
     // One barrier per column: step k updates the trailing lower triangle
     // with the unscaled column, A(i, j) -= A(i, k) A(j, k) / A(k, k), then
-    // scales column k by 1 / sqrt(A(k, k)); the scaling touches only column k,
-    // which no later step reads or writes, so it needs no barrier of its own.
+    // scales column k by 1 / sqrt(A(k, k)) (one reciprocal, then products);
+    // the scaling touches only column k, which no later step reads or
+    // writes, so it needs no barrier of its own.
     // Threads form a 16 x 16 grid over (row, column) of the trailing block.
+    // For bodies of up to 16 blobs (KR = 3 rows and columns per thread) a
+    // thread loads its column-k values and its entries first, then updates
+    // and stores them, so that its LDS reads overlap; the same steps also
+    // eliminate an identity block Y, which yields L^-1 without a separate
+    // substitution (below).
     const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
     for (int k = 0; k < n; ++k) {
         const double d = A(k, k);
         const bool ok = d > 0.0;
-        const double id = ok ? 1.0 / d : 0.0;
-        for (int i = k + 1 + tr; i < n; i += 16) {
-            const double aik = A(i, k);
-            for (int j = k + 1 + tc; j <= i; j += 16) A(i, j) -= aik * A(j, k) * id;
+        if constexpr (KR > 0) {
+            // every load is issued unconditionally from an in-bounds entry
+            // (row and column clamped to n - 1) and masked afterwards, so
+            // that the loads go out together instead of one branch each
+            const int nl = n - 1;
+            double ai[KR], aj[KR], v[KR][KR];
+#pragma unroll
+            for (int r = 0; r < KR; ++r) {
+                const int i = k + 1 + tr + 16 * r, j = k + 1 + tc + 16 * r;
+                ai[r] = A(i < n ? i : nl, k);
+                aj[r] = A(j < n ? j : nl, k);
+            }
+#pragma unroll
+            for (int r = 0; r < KR; ++r)
+#pragma unroll
+                for (int c = 0; c < KR; ++c) {
+                    const int i = k + 1 + tr + 16 * r, j = k + 1 + tc + 16 * c;
+                    v[r][c] = A(i < n ? i : nl, j < n ? j : nl);
+                }
+            // the same row operations on Y (rows i > k, columns j <= k, the
+            // only nonzero ones): Y(i, j) -= (A(i, k) / A(k, k)) Y(k, j)
+            double yk[KR], yv[KR][KR];
+#pragma unroll
+            for (int c = 0; c < KR; ++c) {
+                const int j = tc + 16 * c;
+                yk[c] = Y(k, j < n ? j : nl);
+            }
+#pragma unroll
+            for (int r = 0; r < KR; ++r)
+#pragma unroll
+                for (int c = 0; c < KR; ++c) {
+                    const int i = k + 1 + tr + 16 * r, j = tc + 16 * c;
+                    yv[r][c] = Y(i < n ? i : nl, j < n ? j : nl);
+                }
+            const double id = ok ? 1.0 / d : 0.0;
+#pragma unroll
+            for (int r = 0; r < KR; ++r)
+#pragma unroll
+                for (int c = 0; c < KR; ++c) {
+                    const int i = k + 1 + tr + 16 * r, j = k + 1 + tc + 16 * c, jy = tc + 16 * c;
+                    if (j <= i && i < n) A(i, j) = v[r][c] - ai[r] * aj[c] * id;
+                    if (jy <= k && i < n) Y(i, jy) = yv[r][c] - ai[r] * id * yk[c];
+                }
+        } else {
+            const double id = ok ? 1.0 / d : 0.0;
+            for (int i = k + 1 + tr; i < n; i += 16) {
+                const double aik = A(i, k);
+                for (int j = k + 1 + tc; j <= i; j += 16) A(i, j) -= aik * A(j, k) * id;
+            }
         }
         __syncthreads();
-        const double sd = ok ? sqrt(d) : 1.0;
-        for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) A(i, k) /= sd;
+        const double sd = ok ? sqrt(d) : 1.0, isd = 1.0 / sd;
+        for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) A(i, k) *= isd;
         if (threadIdx.x == 0) {
             if (!ok) bad = 1;
             A(k, k) = sd;
@@ -98,6 +157,17 @@ __global__ __launch_bounds__(kBuildThreads) void precond_build_kernel(const doub
     for (int q = threadIdx.x; q < n * n; q += blockDim.x) {
         const int i = q / n, j = q % n;
         L[q] = j <= i ? A(i, j) : 0.0;
+    }
+    if constexpr (KR > 0) {
+        // A = L1 D L1^T with L1 unit lower triangular; the elimination turned
+        // the identity into Y = L1^-1, and L = L1 D^{1/2}, so L^-1 =
+        // D^{-1/2} Y: row i of Y times 1 / L(i, i)
+        for (int q = threadIdx.x; q < n * n; q += blockDim.x) {
+            const int i = q / n, j = q % n;
+            Li[q] = j <= i ? Y(i, j) * rd[i] : 0.0;
+        }
+        if (threadIdx.x == 0 && bad) atomicOr(notspd, 1);
+        return;
     }
     // Inverse factor L^-1 (lower triangular), four lanes per column: forward
     // substitution of L x = e_col, entry (i, col) = -(sum over col <= k < i
@@ -130,6 +200,7 @@ __global__ __launch_bounds__(kBuildThreads) void precond_build_kernel(const doub
     }
     if (threadIdx.x == 0 && bad) atomicOr(notspd, 1);
 #undef A
+#undef Y
 }
 
 // mode 0: out = L v;  1: out = L^-1 v;  2: out = L^-T v, with the factor L
@@ -447,20 +518,52 @@ size_t body_factors_bytes(int64_t N, int n_bodies) {
            align_up(lsz * sizeof(double));
 }
 
+void body_factors_tables(const int64_t* body_offsets, int n_bodies, std::vector<int>& hb, std::vector<int64_t>& hl,
+                         int* nmax) {
+    hb.assign(n_bodies + 1, 0);
+    hl.assign(n_bodies + 1, 0);
+    *nmax = 1;
+    for (int p = 0; p <= n_bodies; ++p) hb[p] = (int)body_offsets[p];
+    for (int p = 0; p < n_bodies; ++p) {
+        const int64_t nbl = body_offsets[p + 1] - body_offsets[p];
+        hl[p + 1] = hl[p] + 9 * nbl * nbl;
+        *nmax = std::max(*nmax, (int)nbl);
+    }
+}
+
+int body_factors_launch(const double* pos, int64_t N, double a, double eta, const BodyFactors& pc, int nmax,
+                        int* notspd, hipStream_t st) {
+    const double inv_a = 1.0 / a, m0 = 1.0 / (6.0 * M_PI * eta * a);
+    if (!pc.diag) {
+        const size_t lds = ((size_t)3 * nmax * (3 * nmax + 1) + 4 * (size_t)nmax) * sizeof(double);
+        if (3 * nmax <= 48) {
+            const size_t ldsy = lds + (size_t)9 * nmax * nmax * sizeof(double);  // and Y
+            hipLaunchKernelGGL(precond_build_kernel<3>, dim3(pc.nb), dim3(kBuildThreads), ldsy, st, pos, pc.bofs,
+                               pc.lofs, inv_a, m0, pc.L, notspd, nmax);
+        } else {
+            if (lds > 65536)  // up to 129 KB for 42-blob bodies
+                RPYW_HIP(hipFuncSetAttribute((const void*)precond_build_kernel<0>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            hipLaunchKernelGGL(precond_build_kernel<0>, dim3(pc.nb), dim3(kBuildThreads), lds, st, pos, pc.bofs,
+                               pc.lofs, inv_a, m0, pc.L, notspd, nmax);
+        }
+    } else {
+        hipLaunchKernelGGL(blob_diag_kernel, dim3(grid_of(N)), dim3(256), 0, st, pos, N, inv_a, m0, pc.L, notspd);
+    }
+    RPYW_HIP(hipGetLastError());
+    return RPYW_OK;
+}
+
 int body_factors_build(const double* pos, int64_t N, double a, double eta, const int64_t* body_offsets, int n_bodies,
                        Arena& ar, hipStream_t st, BodyFactors& pc, int* notspd) {
-    const double inv_a = 1.0 / a, m0 = 1.0 / (6.0 * M_PI * eta * a);
     pc.diag = n_bodies == 0;
     pc.nb = n_bodies;
     pc.flag = notspd;
+    int nmax = 1;
     if (!pc.diag) {
-        std::vector<int> hb(n_bodies + 1);
-        std::vector<int64_t> hl(n_bodies + 1, 0);
-        for (int p = 0; p <= n_bodies; ++p) hb[p] = (int)body_offsets[p];
-        for (int p = 0; p < n_bodies; ++p) {
-            const int64_t n = 3 * (body_offsets[p + 1] - body_offsets[p]);
-            hl[p + 1] = hl[p] + n * n;
-        }
+        std::vector<int> hb;
+        std::vector<int64_t> hl;
+        body_factors_tables(body_offsets, n_bodies, hb, hl, &nmax);
         // both tables in one upload: lofs, then bofs
         const size_t lb = align_up(hl.size() * sizeof(int64_t));
         std::vector<char> tab(lb + hb.size() * sizeof(int));
@@ -472,21 +575,11 @@ int body_factors_build(const double* pos, int64_t N, double a, double eta, const
         pc.lofs = (int64_t*)dtab;
         pc.bofs = (int*)(dtab + lb);
         if (int r = stage_upload(tab.data(), tab.size(), dtab, st)) return r;
-        int nmax = 1;
-        for (int p = 0; p < n_bodies; ++p) nmax = std::max(nmax, (int)(body_offsets[p + 1] - body_offsets[p]));
-        const size_t lds = ((size_t)3 * nmax * (3 * nmax + 1) + 4 * (size_t)nmax) * sizeof(double);
-        if (lds > 65536)  // up to 129 KB for 42-blob bodies
-            RPYW_HIP(hipFuncSetAttribute((const void*)precond_build_kernel,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(precond_build_kernel, dim3(n_bodies), dim3(kBuildThreads), lds, st, pos, pc.bofs, pc.lofs,
-                           inv_a, m0, pc.L, notspd, nmax);
     } else {
         pc.L = (double*)ar.take((size_t)3 * N * sizeof(double));
         if (!pc.L) return RPYW_ENOMEM;
-        hipLaunchKernelGGL(blob_diag_kernel, dim3(grid_of(N)), dim3(256), 0, st, pos, N, inv_a, m0, pc.L, notspd);
     }
-    RPYW_HIP(hipGetLastError());
-    return RPYW_OK;
+    return body_factors_launch(pos, N, a, eta, pc, nmax, notspd, st);
 }
 
 // ---------------------------------------------------------- staging ring

@@ -322,44 +322,29 @@ int lanczos_fused(const double* pos, const double* W, double* out, int64_t N, do
     double* d_ab = (double*)ar.take(2 * (max_iter + 8) * sizeof(double));
     double* d_c = (double*)ar.take(2 * (max_iter + 8) * sizeof(double));
     int* notspd = (int*)ar.take(sizeof(int));
-    // the gather groups' table, then the unit table, in one block (one upload)
-    const size_t gbytes = align_up((size_t)ngroups * sizeof(LanczosGroup));
-    char* d_tab = (char*)ar.take(gbytes + (size_t)(nunits + 1) * sizeof(int));
-    LanczosGroup* d_groups = (LanczosGroup*)d_tab;
-    int* d_units = (int*)(d_tab + gbytes);
-    void* rec = ar.take((size_t)npad * rw * real_size(prec));
-    double* B = (double*)ar.take((size_t)npad * sizeof(double));
-    double* tpart = (double*)ar.take(sp.tpart_bytes);
-    void* spart = ar.take(sp.spart_bytes);
-    if (!V || !y || !w || !sqp || !part1 || !part2 || !d_ab || !d_c || !notspd || !d_tab || !rec || !B || !tpart ||
-        !spart)
-        return RPYW_ENOMEM;
-    std::lock_guard<std::mutex> lk(g_ab.mu);
-    int rc = g_ab.reserve((size_t)(3 * (max_iter + 2) + 2) * sizeof(double));
-    if (rc) return rc;
-    double* h_ab = g_ab.p;
-    double* dh_ab = g_ab.dp;  // the same pinned memory as kernels address it
-    SlotRelease slots_done{g_ab, st};
-    // the header (beta_0, then the two definiteness flags), written by vin
-    // of step 0 and read by the host with step 0
-    double* h_b0 = h_ab + 2 * (max_iter + 2);
-    int* h_bad = (int*)(h_b0 + 1);
-    double* dh_hdr = dh_ab + (h_b0 - h_ab);
-    // step flags: set by the step's last kernel after alpha_k and beta_{k-1}
-    // (no event per step: an event between the steps' kernels delays the next)
-    double* h_flag = h_b0 + 2;
-    double* dh_flag = dh_ab + (h_flag - h_ab);
-    std::memset(h_flag, 0, (size_t)(max_iter + 2) * sizeof(double));
-
-    // positions, B and the partials of |W|^2; clears notspd before the
-    // factor build (the force slots are rewritten by every step)
-    if ((rc = lz_launch_pack(prec, pos, W, N, npad, rw, a, dom, rec, B, sqp, notspd, st))) return rc;
-    if (pre)
+    // The call's small tables in one block, which the first kernel copies
+    // from pinned memory: the factor tables (when the factors are built
+    // here), the gather groups (units, blobs, first factor block, factor
+    // size), the unit offsets.
+    TableBlock tb;
+    int nmax = 1;
+    size_t o_lofs = 0, o_bofs = 0;
+    std::vector<int64_t> hl;
+    if (pre) {
         pc = *pre;
-    else if ((rc = body_factors_build(pos, N, a, eta, body_offsets, n_bodies, ar, st, pc, notspd)))
-        return rc;
+    } else {
+        pc.diag = n_bodies == 0;
+        pc.nb = n_bodies;
+        pc.flag = notspd;
+        if (!pc.diag) {
+            std::vector<int> hb;
+            body_factors_tables(body_offsets, n_bodies, hb, hl, &nmax);
+            o_lofs = tb.add(hl.data(), hl.size() * sizeof(int64_t));
+            o_bofs = tb.add(hb.data(), hb.size() * sizeof(int));
+        }
+    }
+    size_t o_groups, o_units;
     {
-        // the gather groups' table: units, blobs, first factor block, factor size
         std::vector<LanczosGroup> gt(ngroups);
         int64_t loff = 0;
         for (int g = 0; g < ngroups; ++g) {
@@ -378,11 +363,53 @@ int lanczos_fused(const double* pos, const double* W, double* out, int64_t N, do
             }
             loff += G.sq;
         }
-        std::vector<char> tab(gbytes + h_units.size() * sizeof(int));
-        std::memcpy(tab.data(), gt.data(), gt.size() * sizeof(LanczosGroup));
-        std::memcpy(tab.data() + gbytes, h_units.data(), h_units.size() * sizeof(int));
-        if ((rc = stage_upload(tab.data(), tab.size(), d_tab, st))) return rc;
+        o_groups = tb.add(gt.data(), gt.size() * sizeof(LanczosGroup));
+        o_units = tb.add(h_units.data(), h_units.size() * sizeof(int));
     }
+    const size_t tbytes = align_up(tb.host.size());
+    tb.host.resize(tbytes, 0);
+    char* d_tab = (char*)ar.take(tbytes);
+    const LanczosGroup* d_groups = (const LanczosGroup*)(d_tab + o_groups);
+    const int* d_units = (const int*)(d_tab + o_units);
+    if (!pre) {
+        pc.L = (double*)ar.take((pc.diag ? (size_t)3 * N : (size_t)2 * hl[n_bodies]) * sizeof(double));
+        pc.lofs = (int64_t*)(d_tab + o_lofs);
+        pc.bofs = (int*)(d_tab + o_bofs);
+    }
+    void* rec = ar.take((size_t)npad * rw * real_size(prec));
+    double* B = (double*)ar.take((size_t)npad * sizeof(double));
+    double* tpart = (double*)ar.take(sp.tpart_bytes);
+    void* spart = ar.take(sp.spart_bytes);
+    if (!V || !y || !w || !sqp || !part1 || !part2 || !d_ab || !d_c || !notspd || !d_tab || !pc.L || !rec || !B ||
+        !tpart || !spart)
+        return RPYW_ENOMEM;
+    std::lock_guard<std::mutex> lk(g_ab.mu);
+    const size_t hdr_bytes = align_up((size_t)(3 * (max_iter + 2) + 2) * sizeof(double));
+    int rc = g_ab.reserve(hdr_bytes + tbytes);
+    if (rc) return rc;
+    double* h_ab = g_ab.p;
+    double* dh_ab = g_ab.dp;  // the same pinned memory as kernels address it
+    SlotRelease slots_done{g_ab, st};
+    // the header (beta_0, then the two definiteness flags), written by vin
+    // of step 0 and read by the host with step 0
+    double* h_b0 = h_ab + 2 * (max_iter + 2);
+    int* h_bad = (int*)(h_b0 + 1);
+    double* dh_hdr = dh_ab + (h_b0 - h_ab);
+    // step flags: set by the step's last kernel after alpha_k and beta_{k-1}
+    // (no event per step: an event between the steps' kernels delays the next)
+    double* h_flag = h_b0 + 2;
+    double* dh_flag = dh_ab + (h_flag - h_ab);
+    std::memset(h_flag, 0, (size_t)(max_iter + 2) * sizeof(double));
+    // the tables after them
+    std::memcpy((char*)h_ab + hdr_bytes, tb.host.data(), tbytes);
+    const int* dh_tab = (const int*)((const char*)dh_ab + hdr_bytes);
+
+    // positions, B, the partials of |W|^2 and the tables; clears notspd
+    // before the factor build (the force slots are rewritten by every step)
+    if ((rc = lz_launch_pack(prec, pos, W, N, npad, rw, a, dom, rec, B, sqp, notspd, dh_tab, (int*)d_tab,
+                             (int)(tbytes / sizeof(int)), st)))
+        return rc;
+    if (!pre && (rc = body_factors_launch(pos, N, a, eta, pc, nmax, notspd, st))) return rc;
     const double m0 = 1.0 / (6.0 * M_PI * eta * a);
 
     // Step k: the product (its records written by vin of step k), w = L^-1

@@ -424,16 +424,21 @@ __global__ __launch_bounds__(kGs2Threads) void lz_gs2_kernel(const double* __res
 // in the force slots, which vin rewrites), B, and per block of 256 blobs
 // the partial sum of |W_i|^2 (a fixed-order tree), from which vin of step 0
 // forms beta_0 = |W|; block 0 also clears the definiteness flag that the
-// factor build sets, which runs next.
+// factor build sets, which runs next.  The call's small tables (factor and
+// gather offsets) come from pinned host memory with it, instead of a copy
+// of their own.
 template <typename R>
 __global__ __launch_bounds__(kPackThreads) void lz_pack_kernel(const double* __restrict__ pos,
                                                                const double* __restrict__ W, int64_t N, int recw,
                                                                double inv_a, double lx, double ly, int64_t npad,
                                                                R* __restrict__ rec, double* __restrict__ B,
-                                                               double* __restrict__ sqp, int* __restrict__ bad) {
+                                                               double* __restrict__ sqp, int* __restrict__ bad,
+                                                               const int* __restrict__ htab, int* __restrict__ dtab,
+                                                               int nwords) {
     __shared__ double red[kPackThreads];
     const int t = threadIdx.x;
     const int64_t i = (int64_t)blockIdx.x * kPackThreads + t;
+    for (int64_t q = i; q < nwords; q += (int64_t)gridDim.x * kPackThreads) dtab[q] = htab[q];
     double w2 = 0.0;
     if (i < npad) {
         double b;
@@ -577,14 +582,15 @@ int lz_launch_out(int prec, const BodyFactors& pc, const int* units, const Lancz
 int64_t lz_pack_blocks(int64_t npad) { return (npad + kPackThreads - 1) / kPackThreads; }
 
 int lz_launch_pack(int prec, const double* pos, const double* W, int64_t N, int64_t npad, int recw, double a,
-                   const Domain& dom, void* rec, double* B, double* sqp, int* bad, hipStream_t st) {
+                   const Domain& dom, void* rec, double* B, double* sqp, int* bad, const int* htab, int* dtab,
+                   int nwords, hipStream_t st) {
     const unsigned g = (unsigned)lz_pack_blocks(npad);
     if (prec == RPYW_FP32C)
         hipLaunchKernelGGL(lz_pack_kernel<float>, dim3(g), dim3(kPackThreads), 0, st, pos, W, N, recw, 1.0 / a,
-                           dom.lx / a, dom.ly / a, npad, (float*)rec, B, sqp, bad);
+                           dom.lx / a, dom.ly / a, npad, (float*)rec, B, sqp, bad, htab, dtab, nwords);
     else
         hipLaunchKernelGGL(lz_pack_kernel<double>, dim3(g), dim3(kPackThreads), 0, st, pos, W, N, recw, 1.0 / a,
-                           dom.lx / a, dom.ly / a, npad, (double*)rec, B, sqp, bad);
+                           dom.lx / a, dom.ly / a, npad, (double*)rec, B, sqp, bad, htab, dtab, nwords);
     RPYW_HIP(hipGetLastError());
     return RPYW_OK;
 }

@@ -364,6 +364,30 @@ int rigid_fused(const double* pos, const double* q, const int64_t* body_offsets,
     double* gc1 = (double*)ar.take((max_iter + 8) * sizeof(double));  // c1 of the last step
     double* d_y = (double*)ar.take((max_iter + 8) * sizeof(double));
     int* notspd = (int*)ar.take(sizeof(int));
+    // the factor tables (when the factors are built here) in one block,
+    // which the first kernel copies from pinned memory
+    TableBlock tb;
+    int nmax = 1;
+    std::vector<int64_t> hl;
+    char* d_tab = nullptr;
+    if (pre) {
+        pc = *pre;
+    } else {
+        pc.diag = false;
+        pc.nb = n_bodies;
+        pc.flag = notspd;
+        std::vector<int> hb;
+        body_factors_tables(body_offsets, n_bodies, hb, hl, &nmax);
+        const size_t o_lofs = tb.add(hl.data(), hl.size() * sizeof(int64_t));
+        const size_t o_bofs = tb.add(hb.data(), hb.size() * sizeof(int));
+        tb.host.resize(align_up(tb.host.size()), 0);
+        d_tab = (char*)ar.take(tb.host.size());
+        pc.L = (double*)ar.take((size_t)2 * hl[n_bodies] * sizeof(double));
+        if (!d_tab || !pc.L) return RPYW_ENOMEM;
+        pc.lofs = (int64_t*)(d_tab + o_lofs);
+        pc.bofs = (int*)(d_tab + o_bofs);
+    }
+    const size_t tbytes = tb.host.size();
     void* rec = ar.take((size_t)npad * rw * real_size(prec));
     double* B = (double*)ar.take((size_t)npad * sizeof(double));
     double* tpart = (double*)ar.take(sp.tpart_bytes);
@@ -373,7 +397,8 @@ int rigid_fused(const double* pos, const double* q, const int64_t* body_offsets,
         return RPYW_ENOMEM;
     std::lock_guard<std::mutex> lk(g_h.mu);
     const int slot = 2 * (max_iter + 2);  // c1[0..k], c2[0..k], h_{k+1,k}
-    int rc = g_h.reserve(((size_t)PinnedSlots::kSlots * slot + 2 + (max_iter + 2)) * sizeof(double));
+    const size_t hdr_bytes = align_up(((size_t)PinnedSlots::kSlots * slot + 2 + (max_iter + 2)) * sizeof(double));
+    int rc = g_h.reserve(hdr_bytes + tbytes);
     if (rc) return rc;
     SlotRelease slots_done{g_h, st};
     double* h_slot = g_h.p;
@@ -385,18 +410,19 @@ int rigid_fused(const double* pos, const double* q, const int64_t* body_offsets,
     double* h_flag = h_b + 2;
     double* dh_flag = g_h.dp + (h_flag - h_slot);
     std::memset(h_flag, 0, (size_t)(max_iter + 2) * sizeof(double));
+    if (tbytes) std::memcpy((char*)h_slot + hdr_bytes, tb.host.data(), tbytes);
+    const int* dh_tab = (const int*)((const char*)g_h.dp + hdr_bytes);
 
-    // b, the partials of |b|^2, and notspd cleared before the factor kernels
-    if ((rc = rg_launch_rhs(slip, FT, n3, n6, bv, sqp, notspd, st))) return rc;
-    if (pre)
-        pc = *pre;
-    else if ((rc = body_factors_build(pos, N, a, eta, body_offsets, n_bodies, ar, st, pc, notspd)))
+    // b, the partials of |b|^2, the records' positions and B (the force
+    // slots are rewritten by every step), the tables, and notspd cleared
+    // before the factor kernels
+    if ((rc = rg_launch_rhs(prec, pos, N, npad, rw, a, dom, rec, B, slip, FT, n3, n6, bv, sqp, notspd, dh_tab,
+                            (int*)d_tab, (int)(tbytes / sizeof(int)), st)))
         return rc;
+    if (!pre && (rc = body_factors_launch(pos, N, a, eta, pc, nmax, notspd, st))) return rc;
     hipLaunchKernelGGL(rigid_factors_kernel, dim3(n_bodies), dim3(kRT), 0, st, pos, q, pc.bofs, pc.lofs, pc.L, Wall,
                        Nall, notspd);
     RPYW_HIP(hipGetLastError());
-    // positions and B once; the force slots are rewritten by every step
-    if ((rc = sym_pack(pos, bv, N, 1, 1, prec, sp, a, dom, rec, B, st))) return rc;
     const double m0 = 1.0 / (6.0 * M_PI * eta * a);
 
     // Step k: the product of z (records written by pre of step k), w = A z

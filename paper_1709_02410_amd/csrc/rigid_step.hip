@@ -169,17 +169,31 @@ __global__ __launch_bounds__(kPreThreads) void rg_pre_kernel(
     }
 }
 
-// The right-hand side b = [-slip | -F, -T] of the saddle-point system, per
-// block the partial sum of |b_e|^2 (a fixed-order tree; pre of step 0
-// forms |b| from them), and block 0 clears the definiteness flag that the
-// factor kernels, which run next, set.
-__global__ __launch_bounds__(kRhsThreads) void rg_rhs_kernel(const double* __restrict__ slip,
+// The call's first kernel: the right-hand side b = [-slip | -F, -T] of the
+// saddle-point system, per block the partial sum of |b_e|^2 (a fixed-order
+// tree; pre of step 0 forms |b| from them), the pair kernel's records of
+// the positions with zero force slots (pre rewrites those every step) and
+// B, the call's tables from pinned host memory (htab, nwords ints), and
+// block 0 clears the definiteness flag that the factor kernels, which run
+// next, set.
+template <typename R>
+__global__ __launch_bounds__(kRhsThreads) void rg_rhs_kernel(const double* __restrict__ pos, int64_t N, int64_t npad,
+                                                             int recw, double inv_a, double lx, double ly,
+                                                             R* __restrict__ rec, double* __restrict__ B,
+                                                             const double* __restrict__ slip,
                                                              const double* __restrict__ FT, int64_t n3, int64_t n6,
                                                              double* __restrict__ b, double* __restrict__ sqp,
-                                                             int* __restrict__ bad) {
+                                                             int* __restrict__ bad, const int* __restrict__ htab,
+                                                             int* __restrict__ dtab, int nwords) {
     __shared__ double red[kRhsThreads];
     const int t = threadIdx.x;
-    const int64_t e = (int64_t)blockIdx.x * kRhsThreads + t;
+    const int64_t e = (int64_t)blockIdx.x * kRhsThreads + t, stride = (int64_t)gridDim.x * kRhsThreads;
+    for (int64_t q = e; q < nwords; q += stride) dtab[q] = htab[q];
+    for (int64_t i = e; i < npad; i += stride) {
+        double bb;
+        make_record<R>(pos, nullptr, N, 0, recw, inv_a, nullptr, lx, ly, i, rec + i * recw, &bb);
+        B[i] = bb;
+    }
     double v = 0.0;
     if (e < n3)
         v = slip ? -slip[e] : 0.0;
@@ -341,10 +355,17 @@ int rg_launch_pre(int prec, const BodyFactors& pc, const double* Wall, const dou
 
 int64_t rg_rhs_blocks(int64_t n) { return (n + kRhsThreads - 1) / kRhsThreads; }
 
-int rg_launch_rhs(const double* slip, const double* FT, int64_t n3, int64_t n6, double* b, double* sqp, int* bad,
-                  hipStream_t st) {
-    hipLaunchKernelGGL(rg_rhs_kernel, dim3((unsigned)rg_rhs_blocks(n3 + n6)), dim3(kRhsThreads), 0, st, slip, FT, n3,
-                       n6, b, sqp, bad);
+int rg_launch_rhs(int prec, const double* pos, int64_t N, int64_t npad, int recw, double a, const Domain& dom,
+                  void* rec, double* B, const double* slip, const double* FT, int64_t n3, int64_t n6, double* b,
+                  double* sqp, int* bad, const int* htab, int* dtab, int nwords, hipStream_t st) {
+    const unsigned g = (unsigned)rg_rhs_blocks(n3 + n6);
+    if (prec == RPYW_FP32C)
+        hipLaunchKernelGGL(rg_rhs_kernel<float>, dim3(g), dim3(kRhsThreads), 0, st, pos, N, npad, recw, 1.0 / a,
+                           dom.lx / a, dom.ly / a, (float*)rec, B, slip, FT, n3, n6, b, sqp, bad, htab, dtab, nwords);
+    else
+        hipLaunchKernelGGL(rg_rhs_kernel<double>, dim3(g), dim3(kRhsThreads), 0, st, pos, N, npad, recw, 1.0 / a,
+                           dom.lx / a, dom.ly / a, (double*)rec, B, slip, FT, n3, n6, b, sqp, bad, htab, dtab,
+                           nwords);
     RPYW_HIP(hipGetLastError());
     return RPYW_OK;
 }

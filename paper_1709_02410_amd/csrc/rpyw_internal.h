@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstdint>
+#include <cstring>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -202,9 +203,12 @@ int lz_launch_vin(int prec, const BodyFactors& pc, const int* units, int nunits,
                   const int* bad1, hipStream_t st);
 // Records, B and the |W|^2 partials (lz_pack_blocks of them) for npad
 // blobs; clears *bad.
+// Also copies the call's tables (nwords ints) from pinned host memory htab
+// (the device's address of it) to the device block dtab.
 int64_t lz_pack_blocks(int64_t npad);
 int lz_launch_pack(int prec, const double* pos, const double* W, int64_t N, int64_t npad, int recw, double a,
-                   const Domain& dom, void* rec, double* B, double* sqp, int* bad, hipStream_t st);
+                   const Domain& dom, void* rec, double* B, double* sqp, int* bad, const int* htab, int* dtab,
+                   int nwords, hipStream_t st);
 // out = L (V c) for nv <= kLanczosCoefArgs coefficients (passed by value).
 constexpr int kLanczosCoefArgs = 448;
 int lz_launch_fin(const BodyFactors& pc, const int* units, int nunits, int64_t n3, const double* V, const double* c,
@@ -227,10 +231,13 @@ int rg_launch_pre(int prec, const BodyFactors& pc, const double* Wall, const dou
                   int slot, double* h_flag, int k, double* V, double* zl, double* zu, void* rec, int recw,
                   const double* B, double* h_hdr, const int* bad0, const int* bad1, hipStream_t st);
 // b = [-slip | -F, -T] (n3 + n6 entries), the partials of |b|^2
-// (rg_rhs_blocks of them); clears *bad.
+// (rg_rhs_blocks of them), the records' positions (zero force slots) and B
+// for npad blobs, the tables (nwords ints) from pinned host memory htab to
+// dtab; clears *bad.
 int64_t rg_rhs_blocks(int64_t n);
-int rg_launch_rhs(const double* slip, const double* FT, int64_t n3, int64_t n6, double* b, double* sqp, int* bad,
-                  hipStream_t st);
+int rg_launch_rhs(int prec, const double* pos, int64_t N, int64_t npad, int recw, double a, const Domain& dom,
+                  void* rec, double* B, const double* slip, const double* FT, int64_t n3, int64_t n6, double* b,
+                  double* sqp, int* bad, const int* htab, int* dtab, int nwords, hipStream_t st);
 int rg_launch_out(int prec, const double* pos, const double* q, const int* bofs, int n_bodies, const double* tpart,
                   const void* spart, const SymPlan& sp, const double* B, double mu0, const double* zl,
                   const double* zu, int64_t n3, int64_t ld, const double* V, int k, double* w, double* part1,
@@ -259,6 +266,26 @@ size_t body_factors_bytes(int64_t N, int n_bodies);
 // caller) when a block is not positive definite.  body_offsets: host.
 int body_factors_build(const double* pos, int64_t N, double a, double eta, const int64_t* body_offsets, int n_bodies,
                        Arena& ar, hipStream_t st, BodyFactors& pc, int* notspd);
+// The two steps of body_factors_build for callers that place the tables
+// themselves: the host tables (blob offsets hb, factor offsets hl = prefix
+// sums of (3 n_p)^2, the largest body nmax), then the build launch for pc
+// with bofs, lofs and L (2 hl[nb] doubles; 3N for no bodies) set and the
+// tables on the device when the launch runs.
+void body_factors_tables(const int64_t* body_offsets, int n_bodies, std::vector<int>& hb, std::vector<int64_t>& hl,
+                         int* nmax);
+int body_factors_launch(const double* pos, int64_t N, double a, double eta, const BodyFactors& pc, int nmax,
+                        int* notspd, hipStream_t st);
+// Small host tables gathered into one block: add() returns each part's
+// byte offset (parts 256-byte aligned).
+struct TableBlock {
+    std::vector<char> host;
+    size_t add(const void* src, size_t bytes) {
+        const size_t o = align_up(host.size());
+        host.resize(o + bytes);
+        if (bytes) std::memcpy(host.data() + o, src, bytes);
+        return o;
+    }
+};
 // Vector kernels (FP64, length n, basis vectors V_j at V + j ld):
 //   dots:   out[j] = V_j . w (j < nv), or out[0] = |w| when nv == 0, with a
 //           fixed-order finish; out[copy_idx] is also copied to copy_to;
