@@ -164,7 +164,7 @@ static void tridiag_mul(const double* a, const double* b, int k, const double* v
 // (neglected terms below (e^{-11})^3 of the tail).  Every node is one
 // shifted tridiagonal solve; the nodes are independent, so they run in
 // blocks with the node as the inner loop.  Returns false when T is not
-// positive definite.
+// positive definite or too ill-conditioned for this.
 static bool tridiag_sqrt_quadrature(const double* a, const double* b, int k, double beta0, double* c) {
     constexpr int NB = 16;  // nodes per block
     double hi = 0.0, amin = INFINITY;
@@ -179,6 +179,10 @@ static bool tridiag_sqrt_quadrature(const double* a, const double* b, int k, dou
         if (t == 60) return false;
         lo *= 0.125;
     }
+    // rounding in the solves near lambda_min grows with the condition
+    // number: beyond hi / lo = 1e8 (errors then reach 1e-13 of the largest
+    // coefficient) the eigendecomposition is used instead
+    if (hi > 1e8 * lo) return false;
     const double h = 0.25, widen = 5.5, wc = (2.0 / M_PI) * h;
     const double u0 = 0.5 * std::log(lo) - widen;
     const int nn = (int)std::ceil((0.5 * std::log(hi) + widen - u0) / h) + 1;  // nodes u0 + n h, n < nn
@@ -251,9 +255,10 @@ static bool tridiag_sqrt_quadrature(const double* a, const double* b, int k, dou
     return true;
 }
 
-// c = beta0 T^{1/2} e1: by quadrature for positive definite T, else
-// (rounding made T indefinite) through the eigendecomposition with the
-// negative eigenvalues clamped to zero.
+// c = beta0 T^{1/2} e1: by quadrature for positive definite T of moderate
+// condition, else (rounding made T indefinite, or it is very ill
+// conditioned) through the eigendecomposition with the negative eigenvalues
+// clamped to zero.
 int tridiag_sqrt_coeffs(const double* alpha, const double* beta, int k, double beta0, double* c) {
     if (tridiag_sqrt_quadrature(alpha, beta, k, beta0, c)) return RPYW_OK;
     std::vector<double> d(alpha, alpha + k), e(k, 0.0), row0;

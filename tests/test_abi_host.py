@@ -204,6 +204,39 @@ def test_tridiagonal_root_structured(lib, case):
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), case
 
 
+@pytest.mark.parametrize("kappa", [1e1, 1e3, 1e6, 1e9, 1e12, 1e14])
+@pytest.mark.parametrize("k", [5, 40, 150])
+def test_tridiagonal_root_across_conditioning(lib, kappa, k):
+    """The Lanczos tridiagonal of a diagonal SPD matrix with spectrum in
+    [1 / kappa, 1] (both ends present): the host square root (quadrature while
+    hi / lo <= 1e8, the eigendecomposition beyond) against numpy's eigh."""
+    rng = np.random.default_rng(int(np.log10(kappa)) * 1000 + k)
+    lam = np.exp(rng.uniform(np.log(1.0 / kappa), 0.0, 400))
+    lam[0], lam[1] = 1.0 / kappa, 1.0
+    v = rng.standard_normal(400)
+    V = [v / np.linalg.norm(v)]
+    alpha, beta = [], []
+    for j in range(k):
+        w = lam * V[-1]
+        alpha.append(V[-1] @ w)
+        w -= alpha[-1] * V[-1]
+        for _ in range(2):
+            for u in V:
+                w -= (u @ w) * u
+        if j < k - 1:
+            beta.append(np.linalg.norm(w))
+            V.append(w / beta[-1])
+    alpha, beta = np.array(alpha), np.array(beta)
+    T = np.diag(alpha) + np.diag(beta, 1) + np.diag(beta, -1)
+    ev, Q = np.linalg.eigh(T)
+    ref = Q @ (np.sqrt(np.clip(ev, 0, None)) * Q[0])
+    got = rpywall.tridiag_sqrt_coeffs(alpha, beta, 1.0)
+    # both computations are backward stable; with eigenvalues down to 1e-8
+    # of the largest (k = 150, kappa >= 1e9) they differ by up to about
+    # 5e-13 of the largest coefficient, whichever host method runs
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
 def test_tridiagonal_root_clamps_negative_eigenvalues(lib):
     alpha = np.array([1.0, -3.0, 0.5])
     beta = np.array([0.2, 0.1])
