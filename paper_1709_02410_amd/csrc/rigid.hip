@@ -282,6 +282,18 @@ bool givens_column(std::vector<double>& h, int k, std::vector<std::vector<double
     return std::isfinite(*res);
 }
 
+// The GMRES coefficients: back substitution R y = g (R stored by columns).
+std::vector<double> gmres_coefficients(const std::vector<std::vector<double>>& R, const std::vector<double>& g) {
+    const int m = (int)R.size();
+    std::vector<double> yv(m);
+    for (int i = m - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int j = i + 1; j < m; ++j) s -= R[j][i] * yv[j];
+        yv[i] = R[i][i] != 0.0 ? s / R[i][i] : 0.0;
+    }
+    return yv;
+}
+
 // The GMRES solution: back substitution R y = g, then x = P^-1 (V y)
 // (precond: the preconditioner applied to a device vector, into the
 // caller's outputs).
@@ -292,12 +304,7 @@ int rigid_finish(const std::vector<std::vector<double>>& R, const std::vector<do
     const int m = (int)R.size();
     *iters = m;
     *res_out = res;
-    std::vector<double> yv(m);
-    for (int i = m - 1; i >= 0; --i) {
-        double s = g[i];
-        for (int j = i + 1; j < m; ++j) s -= R[j][i] * yv[j];
-        yv[i] = R[i][i] != 0.0 ? s / R[i][i] : 0.0;
-    }
+    const std::vector<double> yv = gmres_coefficients(R, g);
     int rc;
     if ((rc = stage_upload(yv.data(), m * sizeof(double), d_y, st))) return rc;
     if ((rc = vec_comb(V, n, m, d_y, tmp, n, st))) return rc;
@@ -506,6 +513,15 @@ int rigid_fused(const double* pos, const double* q, const int64_t* body_offsets,
         res2 = res1;
         res1 = res;
         if ((rc = fill(k + 2))) return rc;
+    }
+    if ((int)R.size() <= kLanczosCoefArgs) {
+        // x = P^-1 (V y) in one launch, y passed by value
+        const std::vector<double> yv = gmres_coefficients(R, g);
+        *iters = (int)R.size();
+        *res_out = res;
+        if ((rc = rg_launch_fin(pc, Wall, Nall, n_bodies, n3, n, V, yv.data(), (int)yv.size(), lam_out, U_out, st)))
+            return rc;
+        return converged ? RPYW_OK : RPYW_NOT_CONVERGED;
     }
     return rigid_finish(R, g, res, converged, iters, res_out, d_y, V, n, wb, st, [&](const double* in) {
         hipLaunchKernelGGL(rigid_precond_kernel, dim3(n_bodies), dim3(kRT), 0, st, pc.L, pc.bofs, pc.lofs, Wall, Nall,

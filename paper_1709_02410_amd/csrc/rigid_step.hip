@@ -212,6 +212,68 @@ __global__ __launch_bounds__(kRhsThreads) void rg_rhs_kernel(const double* __res
     }
 }
 
+// The solve's last kernel: x = P^-1 (V y) per body, the coefficients y
+// passed by value: r = sum_j y_j V_j over the body's lambda entries and its
+// six U entries, then the body's exact saddle-point inverse as in pre
+// (M_pp^-1 = L^-T L^-1, z_U = -N_p (r_U + W^T r_lambda), z_lambda =
+// M_pp^-1 r_lambda + W z_U), into the caller's outputs.
+struct RgCoefs {
+    double y[kLanczosCoefArgs];
+};
+__global__ __launch_bounds__(kPreThreads) void rg_fin_kernel(const double* __restrict__ Lall,
+                                                             const int* __restrict__ bofs,
+                                                             const int64_t* __restrict__ lofs,
+                                                             const double* __restrict__ Wall,
+                                                             const double* __restrict__ Nall, int64_t n3, int64_t ld,
+                                                             const double* __restrict__ V, int nv, RgCoefs cf,
+                                                             double* __restrict__ lam_out,
+                                                             double* __restrict__ U_out) {
+    __shared__ double r[kMaxN3 + 6], t1[kMaxN3], tt[kMaxN3];
+    __shared__ double s6[6], z6[6];
+    const int p = blockIdx.x, t = threadIdx.x;
+    const int b0 = bofs[p], n = 3 * (bofs[p + 1] - b0);
+    const int64_t e0 = 3 * (int64_t)b0;
+    const double* Li = Lall + 2 * lofs[p] + (int64_t)n * n;
+    const double* W = Wall + 18 * (int64_t)b0;
+    if (t < n + 6) {
+        const int64_t e = t < n ? e0 + t : n3 + 6 * (int64_t)p + (t - n);
+        const double* v = V + e;
+        double s0 = 0.0, s1 = 0.0;
+        int j = 0;
+        for (; j + 1 < nv; j += 2) {
+            s0 = fma(cf.y[j], v[j * ld], s0);
+            s1 = fma(cf.y[j + 1], v[(j + 1) * ld], s1);
+        }
+        if (j < nv) s0 = fma(cf.y[j], v[j * ld], s0);
+        r[t] = s0 + s1;
+    }
+    __syncthreads();
+    if (t < n) t1[t] = dot4(Li + (int64_t)t * n, 1, r, t + 1);  // row t of L^-1
+    if (t < 96) {
+        const int c = t >> 4, l16 = t & 15;
+        double s = 0.0;
+        for (int i = l16; i < n; i += 16) s = fma(W[6 * i + c], r[i], s);
+        s = lane_group_sum<16>(s);
+        if (l16 == 0) s6[c] = s;
+    }
+    __syncthreads();
+    if (t < n) tt[t] = dot4(Li + (int64_t)t * n + t, n, t1 + t, n - t);  // row t of L^-T
+    if (t < 6) {
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) s = fma(Nall[36 * (int64_t)p + 6 * t + c], r[n + c] + s6[c], s);
+        z6[t] = -s;
+        U_out[6 * (int64_t)p + t] = -s;
+    }
+    __syncthreads();
+    if (t < n) {
+        double s = tt[t];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) s = fma(W[6 * t + c], z6[c], s);
+        lam_out[e0 + t] = s;
+    }
+}
+
 template <typename R>
 __global__ __launch_bounds__(kOutThreads) void rg_out_kernel(
     const double* __restrict__ pos, const double* __restrict__ q, const int* __restrict__ bofs,
@@ -349,6 +411,17 @@ int rg_launch_pre(int prec, const BodyFactors& pc, const double* Wall, const dou
         hipLaunchKernelGGL(rg_pre_kernel<double>, dim3((unsigned)n_bodies), dim3(kPreThreads), 0, st, pc.L, pc.bofs,
                            pc.lofs, Wall, Nall, n3, ld, src, part2, ncol2, gc1, hslots, slot, h_flag, k, V, zl, zu,
                            (double*)rec, recw, B, h_hdr, bad0, bad1);
+    RPYW_HIP(hipGetLastError());
+    return RPYW_OK;
+}
+
+int rg_launch_fin(const BodyFactors& pc, const double* Wall, const double* Nall, int n_bodies, int64_t n3, int64_t ld,
+                  const double* V, const double* y, int nv, double* lam_out, double* U_out, hipStream_t st) {
+    if (nv < 1 || nv > kLanczosCoefArgs) return RPYW_EINVAL;
+    RgCoefs cf;
+    for (int j = 0; j < kLanczosCoefArgs; ++j) cf.y[j] = j < nv ? y[j] : 0.0;
+    hipLaunchKernelGGL(rg_fin_kernel, dim3((unsigned)n_bodies), dim3(kPreThreads), 0, st, pc.L, pc.bofs, pc.lofs, Wall,
+                       Nall, n3, ld, V, nv, cf, lam_out, U_out);
     RPYW_HIP(hipGetLastError());
     return RPYW_OK;
 }

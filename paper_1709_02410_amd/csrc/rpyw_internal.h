@@ -234,6 +234,10 @@ int rg_launch_pre(int prec, const BodyFactors& pc, const double* Wall, const dou
 // (rg_rhs_blocks of them), the records' positions (zero force slots) and B
 // for npad blobs, the tables (nwords ints) from pinned host memory htab to
 // dtab; clears *bad.
+// x = P^-1 (V y) into lam_out (3N) and U_out (6 n_bodies), for nv <=
+// kLanczosCoefArgs coefficients y (passed by value); V_j at V + j ld.
+int rg_launch_fin(const BodyFactors& pc, const double* Wall, const double* Nall, int n_bodies, int64_t n3, int64_t ld,
+                  const double* V, const double* y, int nv, double* lam_out, double* U_out, hipStream_t st);
 int64_t rg_rhs_blocks(int64_t n);
 int rg_launch_rhs(int prec, const double* pos, int64_t N, int64_t npad, int recw, double a, const Domain& dom,
                   void* rec, double* B, const double* slip, const double* FT, int64_t n3, int64_t n6, double* b,
