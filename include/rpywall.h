@@ -132,8 +132,9 @@ int rpy_wall_matvec_batched(const double* pos, const int64_t* sys_offsets, int32
  * increasing, at most 42 blobs per body) or NULL for one 3x3 block per blob.
  * The iteration stops when |y_k - y_{k-1}| <= tol |y_k| (k >= 2) or on an
  * exact invariant subspace; full reorthogonalisation, FP64 Krylov vectors and
- * tridiagonal eigensolve; `precision` selects the pair arithmetic of the
- * products by M.  pos, W, out: device [N][3].  iters_out, err_est_out: HOST
+ * the host tridiagonal square root of rpyw_tridiag_sqrt_coeffs;
+ * `precision` selects the pair arithmetic of the products by M.  pos, W,
+ * out: device [N][3].  iters_out, err_est_out: HOST
  * (may be NULL) receive the iteration count and the last relative change.
  * Waits once per iteration for that step's scalars, so the iteration count
  * and the status are known on return; the final combination into `out`
@@ -354,12 +355,16 @@ int rpy_wall_set_shape(int precision, int64_t N, int32_t k, int32_t tpl, int32_t
  * rpy_wall_set_shape.  Host-only. */
 int rpy_wall_get_shape(int precision, int64_t N, int32_t k, int32_t* out5);
 
-/* Host-only: coefficients c = beta0 Q Lambda^{1/2} Q^T e1 of the Lanczos
- * iterate for the k x k symmetric tridiagonal T (diagonal alpha[k],
- * off-diagonal beta[k-1]) with eigendecomposition T = Q Lambda Q^T, negative
- * eigenvalues clamped to zero (Sec. II.B).  HOST arrays.  Implicit
- * symmetric QL with Wilkinson shifts; returns RPYW_EINVAL for k < 1 or
- * non-finite input, RPYW_NOT_CONVERGED if the QL sweep stalls. */
+/* Host-only: coefficients c = beta0 T^{1/2} e1 = beta0 Q Lambda^{1/2} Q^T e1
+ * of the Lanczos iterate for the k x k symmetric tridiagonal T (diagonal
+ * alpha[k], off-diagonal beta[k-1]) with eigendecomposition T = Q Lambda
+ * Q^T, negative eigenvalues clamped to zero (Sec. II.B).  HOST arrays.  For
+ * positive definite T of condition below 1e8 by an exponentially convergent
+ * quadrature of T^{-1/2} (shifted tridiagonal solves; agrees with the
+ * eigendecomposition to about 1e-15 of the largest coefficient); otherwise
+ * the implicit symmetric QR algorithm with Wilkinson shifts.  Returns
+ * RPYW_EINVAL for k < 1 or non-finite input, RPYW_NOT_CONVERGED if the QR
+ * sweeps stall. */
 int rpyw_tridiag_sqrt_coeffs(const double* alpha, const double* beta, int32_t k, double beta0,
                              double* c_out);
 
