@@ -28,6 +28,7 @@
 #include <cmath>
 #include <vector>
 
+#include "krylov_step.h"
 #include "rpyw_internal.h"
 
 namespace rpyw {
@@ -48,10 +49,26 @@ __device__ inline double k_entry(int alpha, int col, const double d[3]) {
     return sgn * d[g];
 }
 
+// Sum over j < len of F[j fs] x[j xs] in four partial sums (j = i (mod 4)),
+// added pairwise, so that the reads of a step issue together.
+__device__ __forceinline__ double dot4s(const double* F, int fs, const double* x, int xs, int len) {
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    int j = 0;
+    for (; j + 4 <= len; j += 4) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s4[i] = fma(F[(j + i) * fs], x[(j + i) * xs], s4[i]);
+    }
+    for (int i = 0; j + i < len; ++i) s4[i] = fma(F[(j + i) * fs], x[(j + i) * xs], s4[i]);
+    return (s4[0] + s4[1]) + (s4[2] + s4[3]);
+}
+
 // Per body: W_p = M_pp^-1 K_p ([3n][6], at 18 bofs[p]) and the 6 x 6 body
 // mobility N_p = (K_p^T W_p)^-1 (at 36 p).  Sets *notspd when K_p^T W_p is
 // not numerically positive definite (a body whose blobs do not fix all six
-// rigid motions, e.g. a single blob or a straight rod).
+// rigid motions, e.g. a single blob or a straight rod).  The inverse factor
+// is staged in LDS when it fits (bodies of up to 21 blobs); the 6 x 6
+// inverse is a Cholesky factorisation on one thread, then the six columns of
+// its inverse factor on six threads and the 36 entries of N on 36.
 __global__ __launch_bounds__(kRT) void rigid_factors_kernel(const double* __restrict__ pos,
                                                            const double* __restrict__ q,
                                                            const int* __restrict__ bofs,
@@ -59,82 +76,90 @@ __global__ __launch_bounds__(kRT) void rigid_factors_kernel(const double* __rest
                                                            const double* __restrict__ Lall, double* __restrict__ Wall,
                                                            double* __restrict__ Nall, int* __restrict__ notspd) {
     __shared__ double Kl[kMaxN3][6], X[kMaxN3][6], Wl[kMaxN3][6];
-    __shared__ double G[6][6], A[6][6], Linv[6][6];
-    const int p = blockIdx.x;
+    __shared__ double Ls[kstep::kLdsFactor];
+    __shared__ double G[6][6], A[6][6], Linv[6][6], rdg[6];
+    __shared__ int bad;
+    const int p = blockIdx.x, t = threadIdx.x;
     const int b0 = bofs[p], n = 3 * (bofs[p + 1] - b0);
-    const double* Li = Lall + 2 * lofs[p] + (int64_t)n * n;
-    for (int idx = threadIdx.x; idx < 6 * n; idx += blockDim.x) {
+    const double* Lg = Lall + 2 * lofs[p] + (int64_t)n * n;  // L^-1, row-major
+    const bool staged = n * n <= kstep::kLdsFactor;
+    kstep::Staged<kRT, kstep::kLdsFactor / kRT> sl;
+    if (staged) sl.load(Lg, n * n);
+    for (int idx = t; idx < 6 * n; idx += kRT) {
         const int i = idx / 6, c = idx % 6;
         const int blob = b0 + i / 3;
         const double d[3] = {pos[3 * blob] - q[3 * p], pos[3 * blob + 1] - q[3 * p + 1],
                              pos[3 * blob + 2] - q[3 * p + 2]};
         Kl[i][c] = k_entry(i % 3, c, d);
     }
+    if (staged) sl.store(Ls, n * n);
     __syncthreads();
-    for (int idx = threadIdx.x; idx < 6 * n; idx += blockDim.x) {  // X = L^-1 K
+    const double* Li = staged ? Ls : Lg;
+    for (int idx = t; idx < 6 * n; idx += kRT) {  // X = L^-1 K
         const int i = idx / 6, c = idx % 6;
-        double s = 0.0;
-        for (int j = 0; j <= i; ++j) s += Li[(int64_t)i * n + j] * Kl[j][c];
-        X[i][c] = s;
+        X[i][c] = dot4s(Li + (int64_t)i * n, 1, &Kl[0][c], 6, i + 1);
     }
     __syncthreads();
     double* Wp = Wall + 18 * (int64_t)b0;
-    for (int idx = threadIdx.x; idx < 6 * n; idx += blockDim.x) {  // W = L^-T X
+    for (int idx = t; idx < 6 * n; idx += kRT) {  // W = L^-T X
         const int i = idx / 6, c = idx % 6;
-        double s = 0.0;
-        for (int j = i; j < n; ++j) s += Li[(int64_t)j * n + i] * X[j][c];
+        const double s = dot4s(Li + (int64_t)i * n + i, n, &X[i][c], 6, n - i);
         Wl[i][c] = s;
         Wp[idx] = s;
     }
     __syncthreads();
-    if (threadIdx.x < 36) {  // G = K^T W
-        const int c = threadIdx.x / 6, e = threadIdx.x % 6;
+    if (t < 36) {  // G = K^T W
+        const int c = t / 6, e = t % 6;
         double s = 0.0;
-        for (int i = 0; i < n; ++i) s += Kl[i][c] * Wl[i][e];
+        for (int i = 0; i < n; ++i) s = fma(Kl[i][c], Wl[i][e], s);
         G[c][e] = s;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        // Cholesky of the symmetrised G, then N = L^-T L^-1 (one thread).
+    if (t == 0) {
+        // Cholesky of the symmetrised G, with the reciprocals of its diagonal
         double dmax = 0.0;
         for (int i = 0; i < 6; ++i) {
             for (int j = 0; j < 6; ++j) A[i][j] = 0.5 * (G[i][j] + G[j][i]);
             dmax = fmax(dmax, fabs(A[i][i]));
         }
-        bool bad = !(dmax > 0.0);
-        for (int k = 0; k < 6 && !bad; ++k) {
+        int b = !(dmax > 0.0);
+        for (int k = 0; k < 6 && !b; ++k) {
             double dk = A[k][k];
             for (int m = 0; m < k; ++m) dk -= A[k][m] * A[k][m];
             if (!(dk > 1e-12 * dmax)) {
-                bad = true;
+                b = 1;
                 break;
             }
             dk = sqrt(dk);
             A[k][k] = dk;
+            rdg[k] = 1.0 / dk;
             for (int i = k + 1; i < 6; ++i) {
                 double s = A[i][k];
                 for (int m = 0; m < k; ++m) s -= A[i][m] * A[k][m];
-                A[i][k] = s / dk;
+                A[i][k] = s * rdg[k];
             }
         }
-        double* Np = Nall + 36 * (int64_t)p;
-        if (bad) {
-            atomicOr(notspd, 1);
-            for (int i = 0; i < 36; ++i) Np[i] = 0.0;
-        } else {
-            for (int c = 0; c < 6; ++c)  // columns of L^-1 by forward substitution
-                for (int i = 0; i < 6; ++i) {
-                    double s = (i == c) ? 1.0 : 0.0;
-                    for (int m = 0; m < i; ++m) s -= A[i][m] * Linv[m][c];
-                    Linv[i][c] = s / A[i][i];
-                }
-            for (int i = 0; i < 6; ++i)
-                for (int j = 0; j < 6; ++j) {
-                    double s = 0.0;
-                    for (int m = 0; m < 6; ++m) s += Linv[m][i] * Linv[m][j];
-                    Np[6 * i + j] = s;
-                }
+        bad = b;
+        if (b) atomicOr(notspd, 1);
+    }
+    __syncthreads();
+    if (bad) {
+        if (t < 36) Nall[36 * (int64_t)p + t] = 0.0;
+        return;
+    }
+    if (t < 6) {  // column t of the inverse factor, by forward substitution
+        for (int i = 0; i < 6; ++i) {
+            double s = (i == t) ? 1.0 : 0.0;
+            for (int m = 0; m < i; ++m) s -= A[i][m] * Linv[m][t];
+            Linv[i][t] = s * rdg[i];
         }
+    }
+    __syncthreads();
+    if (t < 36) {  // N = L^-T L^-1
+        const int i = t / 6, j = t % 6;
+        double s = 0.0;
+        for (int m = 0; m < 6; ++m) s = fma(Linv[m][i], Linv[m][j], s);
+        Nall[36 * (int64_t)p + t] = s;
     }
 }
 
