@@ -46,6 +46,12 @@ FLOP_PAIR_SHARED = 75
 FLOP_PAIR_RHS = 24
 FLOP_VJP_PAIR = 460
 FLOP_VJP_SELF = 406
+# The matrix-core multi-RHS kernel: the 3 x 3 block written out from the
+# coefficients (vector units), and its contraction with one right-hand side
+# (matrix cores), counted the same way.
+FLOP_PAIR_BLOCK = 19
+FLOP_BLOCK_RHS = 18
+PEAK_FP32_MATRIX = 157.3  # TFLOP/s, MI355X dense FP32 matrix cores
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pair_kernel_traffic.json")
 KERNEL_SOURCES = ["pair_kernels.hip", "pair_math.h", "records.h", "sym_pairs.h"]
 
@@ -59,6 +65,14 @@ def algorithmic_flop(N: int, k: int, sym: int) -> float:
     if sym:
         return n * (n - 1) / 2 * (FLOP_PAIR_SHARED + 2 * k * FLOP_PAIR_RHS) + n * (FLOP_PAIR_SHARED + k * FLOP_PAIR_RHS)
     return n * n * (FLOP_PAIR_SHARED + k * FLOP_PAIR_RHS)
+
+
+def mat_flop(N: int, k: int):
+    """(vector-unit, matrix-core) algorithmic FLOPs of one product of N blobs
+    and k RHS on the matrix-core kernel: every ordered pair forms its block
+    once (75 + 19) and contracts it with each right-hand side (18 each)."""
+    n = float(N)
+    return n * n * (FLOP_PAIR_SHARED + FLOP_PAIR_BLOCK), n * n * k * FLOP_BLOCK_RHS
 
 
 def vjp_flop(N: int, sym: int) -> float:
@@ -378,11 +392,29 @@ def main():
             rp.autotune(pos, F16, precision=rp.FP32C)
             w, km, ln, pr = timed(lambda: rp.matvec_multi(pos, F16, precision=rp.FP32C, out=U16), 3, 1)
             sh16 = rp.get_shape(rp.FP32C, N, k)
-            fl = sum(algorithmic_flop(N, min(sh16["kblk"], k - k0), sh16["sym"]) for k0 in range(0, k, sh16["kblk"]))
             call_ms = km / 3  # kernel time of one call (three timed calls)
-            rows["multi_rhs_H_k16_fp32c"] = {"pair_rhs_per_s": k * N * N / w, "ms": w * 1e3, "shape": sh16,
-                                             "tflops_alg": fl / (call_ms * 1e-3) / 1e12,
-                                             "frac_fp32_peak": fl / (call_ms * 1e-3) / 1e12 / PEAK_FP32}
+            row = {"pair_rhs_per_s": k * N * N / w, "ms": w * 1e3, "kernel_ms": call_ms, "shape": sh16}
+            if sh16["mat"]:
+                fv, fm = mat_flop(N, k)
+                tv, tm = fv / (call_ms * 1e-3) / 1e12, fm / (call_ms * 1e-3) / 1e12
+                row.update({"tflops_alg": tv + tm, "bound": "mfma",
+                            "matrix_tflops": tm, "frac_fp32_matrix_peak": tm / PEAK_FP32_MATRIX,
+                            "vector_tflops": tv, "frac_fp32_vector_peak": tv / PEAK_FP32})
+                # the same product with the contraction on the vector units
+                rp.set_shape(rp.FP32C, N, k, tpl=1, tile=256, kblk=16, sym=0, ipw=4, mat=0)
+                wv, kmv, _, _ = timed(lambda: rp.matvec_multi(pos, F16, precision=rp.FP32C, out=U16), 2, 1)
+                rp.reset_shape(rp.FP32C, N, k)
+                fl = algorithmic_flop(N, k, 0)
+                row["vector_kernel"] = {"ms": wv * 1e3, "kernel_ms": kmv / 2,
+                                        "tflops_alg": fl / (kmv / 2 * 1e-3) / 1e12,
+                                        "frac_fp32_peak": fl / (kmv / 2 * 1e-3) / 1e12 / PEAK_FP32}
+                rp.matvec_multi(pos, F16, precision=rp.FP32C, out=U16)
+            else:
+                fl = sum(algorithmic_flop(N, min(sh16["kblk"], k - k0), sh16["sym"])
+                         for k0 in range(0, k, sh16["kblk"]))
+                row.update({"tflops_alg": fl / (call_ms * 1e-3) / 1e12, "bound": "alu",
+                            "frac_fp32_peak": fl / (call_ms * 1e-3) / 1e12 / PEAK_FP32})
+            rows["multi_rhs_H_k16_fp32c"] = row
             mrows = sample_rows(N, 64, 12)
             U16_np = H2(U16)
             for l in (0, 7, 15):
@@ -447,7 +479,7 @@ def main():
                 "systems": S, "blobs": C3.N, "largest": nmax, "pair_rhs": k * pairs3,
                 "batched_ms": wb * 1e3, "per_system_multi_rhs_ms": wm * 1e3, "per_system_single_rhs_ms": wsn * 1e3,
                 "speedup_vs_multi": wm / wb, "speedup_vs_single": wsn / wb,
-                "batched_pair_rhs_per_s": k * pairs3 / wb}
+                "batched_pair_rhs_per_s": k * pairs3 / wb, "shape_largest": rp.get_shape(rp.FP32C, nmax, k)}
             U3_np = H2(U3)
             for s in sorted({0, smax, S // 2, S - 1}):
                 b0, b1 = slices[s]

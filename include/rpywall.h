@@ -343,17 +343,21 @@ int rpy_wall_autotune(const double* pos, const double* F, double* U, int64_t N, 
  * the symmetric kernel, which evaluates each unordered pair once and applies
  * it in both directions (kblk <= 4), over groups of 256 blobs (1) or of 64
  * blobs (2, more workgroups for small problems; taken for N <= 32768, else
- * groups of 256); ipw: source groups per workgroup of the symmetric kernel.
+ * groups of 256); ipw: source groups per workgroup of the symmetric kernel;
+ * mat: 1 contracts the 3 x 3 pair blocks with the RHS block on the matrix
+ * cores (FP32C with kblk 8 or 16 only; tpl, tile, sym and ipw then do not
+ * apply), 0 on the vector units.  The batched products follow mat too.
  * Pseudo-periodic products always use the symmetric kernel, over groups of
  * 256 when sym is 1 and of 64 otherwise.  tpl = 0 removes the override (back to the tuner's or
- * the built-in choice).  Host-only, takes effect for later calls. */
+ * the built-in choice).  Host-only, takes effect for later calls.
+ * RPYW_EINVAL for values outside these sets. */
 int rpy_wall_set_shape(int precision, int64_t N, int32_t k, int32_t tpl, int32_t tile, int32_t kblk, int32_t sym,
-                       int32_t ipw);
+                       int32_t ipw, int32_t mat);
 
 /* The launch shape later products of this precision and size class will
- * use: out5 = {tpl, tile, kblk, sym, ipw} (HOST int32[5]), as for
+ * use: out6 = {tpl, tile, kblk, sym, ipw, mat} (HOST int32[6]), as for
  * rpy_wall_set_shape.  Host-only. */
-int rpy_wall_get_shape(int precision, int64_t N, int32_t k, int32_t* out5);
+int rpy_wall_get_shape(int precision, int64_t N, int32_t k, int32_t* out6);
 
 /* Host-only: coefficients c = beta0 T^{1/2} e1 = beta0 Q Lambda^{1/2} Q^T e1
  * of the Lanczos iterate for the k x k symmetric tridiagonal T (diagonal

@@ -102,7 +102,8 @@ int64_t g_prof_n = 0;
 // where its passes are also split into segments); groups of
 // 64 blobs, one item per workgroup, are up to 3x faster than groups of 256
 // below ten thousand blobs (which leave the GPU underfilled) and still 5% at
-// 30000; wider RHS blocks are faster on the plain kernel.  For groups of 256
+// 30000; wider RHS blocks are faster on the plain kernel, and FP32C blocks
+// of 8 or more are contracted on the matrix cores.  For groups of 256
 // ipw keeps the grid at roughly 16k workgroups or more.
 Shape default_shape(int64_t N, int k, int prec) {
     Shape s;
@@ -112,6 +113,7 @@ Shape default_shape(int64_t N, int k, int prec) {
     s.sym = (s.kblk == 1 && N >= 512) ? (N <= kSym64MaxN ? 2 : 1) : 0;
     const int64_t ng = (N + 255) / 256, hm = ng / 2 + 1;
     s.ipw = s.sym == 2 ? 1 : (int)std::max<int64_t>(1, std::min<int64_t>(4, hm * ng / 16384));
+    s.mat = (prec == RPYW_FP32C && s.kblk >= 8) ? 1 : 0;
     return s;
 }
 
@@ -190,8 +192,8 @@ bool profiling_enabled() { return g_prof; }
 // its products use, and the status.
 void log_shape(const char* fn, int64_t N, int k, int prec, int rc) {
     const Shape sh = tuned_shape(N, k, prec);
-    log_line("%s N=%lld k=%d prec=%d shape tpl=%d tile=%d kblk=%d sym=%d ipw=%d status=%d", fn, (long long)N, k, prec,
-             sh.tpl, sh.tile, sh.kblk, sh.sym, sh.ipw, rc);
+    log_line("%s N=%lld k=%d prec=%d shape tpl=%d tile=%d kblk=%d sym=%d ipw=%d mat=%d status=%d", fn, (long long)N, k,
+             prec, sh.tpl, sh.tile, sh.kblk, sh.sym, sh.ipw, sh.mat, rc);
 }
 
 void profile_begin(hipStream_t st, hipEvent_t* ev) {
@@ -596,8 +598,9 @@ int rpy_wall_autotune(const double* pos, const double* F, double* U, int64_t N, 
     g_prof = false;
     // Candidates in order of preference (least partial-sum traffic first):
     // symmetric over groups of 256 with ipw 4, 2, 1, then (small problems)
-    // over groups of 64 with ipw 4, 2, 1, then plain (tpl, tile) in
-    // {1,2} x {64,256}, for every RHS block width.  Two timed rounds over all candidates (the
+    // over groups of 64 with ipw 4, 2, 1, then (FP32C blocks of 8 or more)
+    // the matrix-core kernel, then plain (tpl, tile) in {1,2} x {64,256},
+    // for every RHS block width.  Two timed rounds over all candidates (the
     // first also brings the clocks up); each candidate keeps its faster
     // round.  A later candidate must be faster by 1.5% to win, so near-ties
     // resolve the same way every time.
@@ -610,6 +613,11 @@ int rpy_wall_autotune(const double* pos, const double* F, double* U, int64_t N, 
             if (cand >= 6 && kb >= 8 && sh.tpl == 2) continue;
             if (cand < 6 && kb > 4) continue;
             if (sh.sym == 2 && N > kSym64MaxN) continue;
+            if (cand == 6 && precision == RPYW_FP32C && kb >= 8) {
+                Shape m{1, 64, kb, 0, 4};
+                m.mat = 1;
+                cands.push_back(m);
+            }
             cands.push_back(sh);
         }
     }
@@ -650,36 +658,41 @@ int rpy_wall_autotune(const double* pos, const double* F, double* U, int64_t N, 
         std::lock_guard<std::mutex> lk(g_shape_mu);
         save_cache_locked();
     }
-    log_line("rpy_wall_autotune N=%lld k=%d prec=%d -> tpl=%d tile=%d kblk=%d sym=%d ipw=%d (%.4f ms)", (long long)N,
-             k, precision, best.tpl, best.tile, best.kblk, best.sym, best.ipw, best_t / 2.0);
+    log_line("rpy_wall_autotune N=%lld k=%d prec=%d -> tpl=%d tile=%d kblk=%d sym=%d ipw=%d mat=%d (%.4f ms)",
+             (long long)N, k, precision, best.tpl, best.tile, best.kblk, best.sym, best.ipw, best.mat, best_t / 2.0);
     return RPYW_OK;
 }
 
 int rpy_wall_set_shape(int precision, int64_t N, int32_t k, int32_t tpl, int32_t tile, int32_t kblk, int32_t sym,
-                       int32_t ipw) {
+                       int32_t ipw, int32_t mat) {
     if (tpl == 0 && valid_prec(precision) && N >= 1 && N < kMaxN && k >= 1) {
         clear_tuned_shape(N, k, precision);
         return RPYW_OK;
     }
     if (!valid_prec(precision) || N < 1 || N >= kMaxN || k < 1 || (tpl != 1 && tpl != 2) ||
         (tile != 64 && tile != 256) || kblk < 1 || kblk > (precision == RPYW_FP32C ? 16 : 8) ||
-        (kblk & (kblk - 1)) != 0 || sym < 0 || sym > 2 || (sym && kblk > 4) || ipw < 1)
+        (kblk & (kblk - 1)) != 0 || sym < 0 || sym > 2 || (sym && kblk > 4) || ipw < 1 || mat < 0 || mat > 1 ||
+        (mat && (precision != RPYW_FP32C || kblk < 8)))
         return RPYW_EINVAL;
-    set_tuned_shape(N, k, precision, Shape{tpl, tile, kblk, sym, ipw});
+    Shape sh{tpl, tile, kblk, sym, ipw};
+    sh.mat = mat;
+    set_tuned_shape(N, k, precision, sh);
     return RPYW_OK;
 }
 
-int rpy_wall_get_shape(int precision, int64_t N, int32_t k, int32_t* out5) {
-    if (!valid_prec(precision) || N < 1 || N >= kMaxN || k < 1 || !out5) return RPYW_EINVAL;
+int rpy_wall_get_shape(int precision, int64_t N, int32_t k, int32_t* out6) {
+    if (!valid_prec(precision) || N < 1 || N >= kMaxN || k < 1 || !out6) return RPYW_EINVAL;
     Shape s = tuned_shape(N, k, precision);
     const int K = std::min(kclass(s.kblk), precision == RPYW_FP32C ? 16 : 8);
     if (K >= 8) s.tpl = 1;
     if (K > 4) s.sym = 0;
-    out5[0] = s.tpl;
-    out5[1] = s.tile;
-    out5[2] = s.kblk;
-    out5[3] = s.sym;
-    out5[4] = s.ipw;
+    if (precision != RPYW_FP32C || K < 8) s.mat = 0;
+    out6[0] = s.tpl;
+    out6[1] = s.tile;
+    out6[2] = s.kblk;
+    out6[3] = s.sym;
+    out6[4] = s.ipw;
+    out6[5] = s.mat;
     return RPYW_OK;
 }
 

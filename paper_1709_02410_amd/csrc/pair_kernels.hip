@@ -194,6 +194,169 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(const R* __restrict__ r
     }
 }
 
+// ------------------------------------------------------------ multi-RHS on the matrix cores
+//
+// With a block of K >= 8 right-hand sides the product is a dense contraction:
+// u_i = sum_j M_ij F_j, F_j the 3 x K block of source j's forces.  The vector
+// units form each 3 x 3 block M_ij once (the pair geometry and its wall
+// coefficients); the matrix cores contract the blocks with F, one
+// v_mfma_f32_16x16x4f32 per block entry (c, d) and step of 4 sources:
+//   D_c[t][k] += sum_{s < 4} M_cd(t, s) F_d(s, k),  16 targets t x 16 RHS k.
+// A wave holds 16 targets.  In each step lane l evaluates the pair (target
+// l % 16, source l / 16): its nine block entries are the A operands (row t =
+// l % 16, column s = l / 16) of the step's nine instructions, and component d
+// of right-hand side l % 16 of source l / 16 is the B operand (row s, column
+// k) of the three instructions of column d.  Accumulator c of lane l holds
+// velocity component c of targets 4 (l / 16) + v, v < 4, for right-hand side
+// l % 16.  The instructions sum in FP32 within a tile of sources; after each
+// tile the sums are folded into TwoSum (hi, lo) pairs, as on the vector
+// path.  Right-hand sides k >= K (K = 8) contract zero forces.
+typedef float mf4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMatWaveTargets = 16;
+constexpr int kMatTargets = kMatWaveTargets * (kBlock / 64);  // per workgroup
+constexpr int kMatTile = 64;                                  // sources per LDS tile
+
+template <int K>
+struct MatLane {
+    static constexpr int RW = rec_w<float, K>();
+    float x, y, z, xl, yl;  // target l % 16 of the wave's 16
+    mf4 acc[3];
+    float hi[3][4], lo[3][4];
+
+    __device__ void load(const float* __restrict__ rec, int64_t first, int64_t last) {
+        int64_t i = first + kMatWaveTargets * (threadIdx.x >> 6) + (threadIdx.x & 15);
+        if (i >= last) i = last - 1;
+        const float* r = rec + i * RW;
+        x = r[0];
+        y = r[1];
+        z = r[2];
+        xl = r[3];
+        yl = r[4];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            acc[c] = mf4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                hi[c][v] = 0.f;
+                lo[c][v] = 0.f;
+            }
+        }
+    }
+
+    // Sum over sources [s0, s1) staged through the LDS tile.  Slots past the
+    // last source of a tile, up to the next multiple of 4, hold force-free
+    // blobs far from everything (their blocks are finite, their forces 0).
+    __device__ void run(const float* __restrict__ rec, int64_t s0, int64_t s1, float* tile) {
+        const int q = (threadIdx.x >> 4) & 3;  // source of the step
+        const int k = threadIdx.x & 15;        // right-hand side
+        const int kf = k < K ? k : 0;
+        const float fscale = k < K ? 1.f : 0.f;
+        for (int64_t t0 = s0; t0 < s1; t0 += kMatTile) {
+            const int n = (int)((s1 - t0) < kMatTile ? (s1 - t0) : kMatTile);
+            const int n4 = (n + 3) & ~3;
+            __syncthreads();
+            const float* g = rec + t0 * RW;
+            for (int e = threadIdx.x; e < n * RW; e += kBlock) tile[e] = g[e];
+            for (int e = n * RW + threadIdx.x; e < n4 * RW; e += kBlock) {
+                const int o = e % RW;
+                tile[e] = o < 2 ? 1e6f : (o == 2 ? 1.f : 0.f);
+            }
+            __syncthreads();
+            for (int j = 0; j < n4; j += 4) {
+                const float* s = tile + (j + q) * RW;
+                const float sz = s[2];
+                const float dx = (x - s[0]) + (xl - s[3]);
+                const float dy = (y - s[1]) + (yl - s[4]);
+                const float dz = z - sz;
+                const float fx = fscale * s[5 + 3 * kf];
+                const float fy = fscale * s[6 + 3 * kf];
+                const float fz = fscale * s[7 + 3 * kf];
+                const PairBlock<float> m = pair_block<float>(pair_coef<float>(dx, dy, dz, z, sz), dx, dy, dz);
+                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(m.xx, fx, acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(m.xy, fx, acc[1], 0, 0, 0);
+                acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(m.zx, fx, acc[2], 0, 0, 0);
+                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(m.xy, fy, acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(m.yy, fy, acc[1], 0, 0, 0);
+                acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(m.zy, fy, acc[2], 0, 0, 0);
+                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(m.xz, fz, acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(m.yz, fz, acc[1], 0, 0, 0);
+                acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(m.zz, fz, acc[2], 0, 0, 0);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) two_sum_acc(hi[c][v], lo[c][v], acc[c][v]);
+                acc[c] = mf4{0.f, 0.f, 0.f, 0.f};
+            }
+        }
+    }
+
+    // Target of accumulator entry v of this lane (offset from the first of
+    // the workgroup) and its right-hand side.
+    __device__ static int target(int v) { return kMatWaveTargets * (threadIdx.x >> 6) + 4 * ((threadIdx.x >> 4) & 3) + v; }
+    __device__ static int rhs() { return threadIdx.x & 15; }
+    __device__ double total(int c, int v) const { return (double)hi[c][v] + (double)lo[c][v]; }
+};
+
+// Block b -> (source chunk b % splits, targets [64 (b / splits), +64)); the
+// partial sums go to the same layout as pair_kernel's.
+template <int K>
+__global__ __launch_bounds__(kBlock) void mat_pair_kernel(const float* __restrict__ rec, int64_t N, int splits,
+                                                          int64_t chunk, double* __restrict__ part) {
+    __shared__ __attribute__((aligned(16))) float tile[kMatTile * rec_w<float, K>()];
+    const int b = blockIdx.x;
+    const int split = b % splits;
+    const int64_t first = (int64_t)(b / splits) * kMatTargets;
+    const int64_t s0 = (int64_t)split * chunk;
+    const int64_t s1 = s0 + chunk < N ? s0 + chunk : N;
+    MatLane<K> L;
+    L.load(rec, first, N);
+    L.run(rec, s0, s1, tile);
+    const int k = MatLane<K>::rhs();
+    if (k >= K) return;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int64_t i = first + MatLane<K>::target(v);
+        if (i >= N) continue;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) part[((int64_t)(split * K + k) * 3 + c) * N + i] = L.total(c, v);
+    }
+}
+
+// Batched systems on the matrix cores: as batched_kernel, with work items of
+// 64 targets.
+template <int K>
+__global__ __launch_bounds__(kBlock) void mat_batched_kernel(const float* __restrict__ rec,
+                                                             const int4* __restrict__ items, int n_items,
+                                                             unsigned* __restrict__ counter,
+                                                             const double* __restrict__ B, double mu0, int64_t Ntot,
+                                                             int kb, double* __restrict__ U) {
+    __shared__ __attribute__((aligned(16))) float tile[kMatTile * rec_w<float, K>()];
+    __shared__ int s_item;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int item = s_item;
+        if (item >= n_items) break;
+        const int4 it = items[item];
+        MatLane<K> L;
+        L.load(rec, it.z, it.y);
+        L.run(rec, it.x, it.y, tile);
+        const int k = MatLane<K>::rhs();
+        if (k >= kb) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t i = (int64_t)it.z + MatLane<K>::target(v);
+            if (i >= it.y) continue;
+            const double sc = mu0 * B[i];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) U[((int64_t)k * Ntot + i) * 3 + c] = sc * L.total(c, v);
+        }
+    }
+}
+
 // ------------------------------------------------------------ symmetric product
 //
 // Each unordered pair is evaluated once (sym_pairs.h): the target side
@@ -444,6 +607,23 @@ hipError_t launch_batched_t(const R* rec, const int4* items, int n_items, unsign
     return hipGetLastError();
 }
 
+template <int K>
+hipError_t launch_mat_t(const float* rec, int64_t N, int splits, int64_t chunk, double* part, int64_t nblocks,
+                        hipStream_t st) {
+    hipLaunchKernelGGL((mat_pair_kernel<K>), dim3((unsigned)nblocks), dim3(kBlock), 0, st, rec, N, splits, chunk,
+                       part);
+    return hipGetLastError();
+}
+
+template <int K>
+hipError_t launch_mat_batched_t(const float* rec, const int4* items, int n_items, unsigned* counter,
+                                const double* B, double mu0, int64_t Ntot, int kb, double* U, int grid,
+                                hipStream_t st) {
+    hipLaunchKernelGGL((mat_batched_kernel<K>), dim3(grid), dim3(kBlock), 0, st, rec, items, n_items, counter, B, mu0,
+                       Ntot, kb, U);
+    return hipGetLastError();
+}
+
 // Expand (K, TPL, TILE) runtime values into template instantiations.
 #define RPYW_DISPATCH(R, K, TPL, TILE, FN, ...)                                   \
     [&]() -> hipError_t {                                                         \
@@ -483,7 +663,8 @@ int kernel_k(int kb, int prec) { return std::min(pow2ceil(kb), prec == RPYW_FP32
 
 // The launch shape the dispatch actually instantiates: blocks of 8 or more
 // right-hand sides run one target per lane, tiles are 64 or 256.
-Shape normalized(Shape s, int K) {
+Shape normalized(Shape s, int K, int prec) {
+    s.mat = (s.mat && prec == RPYW_FP32C && K >= 8) ? 1 : 0;
     if (K >= 8) s.tpl = 1;
     if (K > 4) s.sym = 0;
     if (s.ipw < 1) s.ipw = 4;
@@ -540,12 +721,30 @@ void split_plan(int64_t N, int tpl, int* splits, int64_t* chunk) {
     *chunk = c;
 }
 
+// Source chunks of the matrix-core kernel: workgroups of 64 targets, enough
+// of them for several rounds of five per CU (the tail of the last round
+// then costs little), chunks of at least 256 sources.
+void mat_split_plan(int64_t N, int* splits, int64_t* chunk) {
+    const int64_t ntb = (N + kMatTargets - 1) / kMatTargets;
+    const int64_t want_wg = 8192;
+    int64_t s = (want_wg + ntb - 1) / ntb;
+    const int64_t max_s = std::max<int64_t>(1, N / 256);
+    if (s > max_s) s = max_s;
+    if (s > 8) s = (s + 7) / 8 * 8;
+    if (s < 1) s = 1;
+    int64_t c = (N + s - 1) / s;
+    s = (N + c - 1) / c;
+    *splits = (int)s;
+    *chunk = c;
+}
+
 size_t product_ws_bytes(int64_t N, int prec, int kblk) {
-    int s1, s2;
+    int s1, s2, s3 = 1;
     int64_t c;
     split_plan(N, 1, &s1, &c);
     split_plan(N, 2, &s2, &c);
-    const int smax = std::max(s1, s2);
+    if (prec == RPYW_FP32C && kblk >= 8) mat_split_plan(N, &s3, &c);
+    const int smax = std::max(std::max(s1, s2), s3);
     size_t b = align_up((size_t)N * rec_width(prec, kblk) * real_size(prec));
     b += align_up((size_t)N * sizeof(double));
     b += align_up((size_t)smax * kblk * 3 * N * sizeof(double));
@@ -666,7 +865,7 @@ int product_pass(const double* pos, const double* F, double* U, int64_t N, int k
     const size_t mark = ar.used;
     const int K = kernel_k(kb, prec);
     if (kb < 1 || kb > K) return RPYW_EINVAL;
-    sh = normalized(sh, K);
+    sh = normalized(sh, K, prec);
     if (sh.sym && K <= 4) {
         SymPlan sp = sym_plan(N, prec, K, sh.ipw, sym_group(sh.sym));
         if (!sp.ok && sp.G == 64) sp = sym_plan(N, prec, K, sh.ipw, 256);
@@ -677,7 +876,10 @@ int product_pass(const double* pos, const double* F, double* U, int64_t N, int k
     double* B = (double*)ar.take((size_t)N * sizeof(double));
     int splits;
     int64_t chunk;
-    split_plan(N, sh.tpl, &splits, &chunk);
+    if (sh.mat)
+        mat_split_plan(N, &splits, &chunk);
+    else
+        split_plan(N, sh.tpl, &splits, &chunk);
     double* part = (double*)ar.take((size_t)splits * K * 3 * N * sizeof(double));
     if (!rec || !B || !part) {
         ar.used = mark;
@@ -691,12 +893,16 @@ int product_pass(const double* pos, const double* F, double* U, int64_t N, int k
         hipLaunchKernelGGL(pack_kernel<double>, dim3(g1), dim3(kBlock), 0, st, pos, F, N, kb, rw, 1.0 / a,
                            (double*)rec, B, nullptr, 0.0, 0.0, N);
     RPYW_HIP(hipGetLastError());
-    const int64_t ntb = (N + (int64_t)kBlock * sh.tpl - 1) / ((int64_t)kBlock * sh.tpl);
+    const int span = sh.mat ? kMatTargets : kBlock * sh.tpl;
+    const int64_t ntb = (N + span - 1) / span;
     const int64_t nblocks = ntb * splits;
     hipEvent_t ev = nullptr;
     profile_begin(st, &ev);
     hipError_t e;
-    if (prec == RPYW_FP32C)
+    if (sh.mat)
+        e = K == 16 ? launch_mat_t<16>((const float*)rec, N, splits, chunk, part, nblocks, st)
+                    : launch_mat_t<8>((const float*)rec, N, splits, chunk, part, nblocks, st);
+    else if (prec == RPYW_FP32C)
         e = RPYW_DISPATCH(float, K, sh.tpl, sh.tile, launch_pair_t, (const float*)rec, N, splits, chunk, part, nblocks,
                           st);
     else
@@ -742,7 +948,7 @@ size_t batched_ws_bytes(int64_t Ntot, int S, int k, int prec) {
     const int kb = kernel_k(std::max(k, 1), prec);
     size_t b = align_up((size_t)Ntot * rec_width(prec, kb) * real_size(prec));
     b += align_up((size_t)Ntot * sizeof(double));
-    const size_t max_items = (size_t)(Ntot / kBlock) + (size_t)S + 1;
+    const size_t max_items = (size_t)(Ntot / kMatTargets) + (size_t)S + 1;  // items of 64 or more targets
     b += align_up(max_items * sizeof(int4));
     b += kAlign;  // counter
     return b + 4 * kAlign;
@@ -761,14 +967,14 @@ int batched_products(const double* pos, const int64_t* sys_offsets, int S, const
     Shape sh = default_shape(nmax, k, prec);
     sh.sym = 0;
     sh = apply_env_overrides(sh);
-    sh = normalized(sh, kernel_k(sh.kblk, prec));
+    sh = normalized(sh, kernel_k(sh.kblk, prec), prec);
     // Work list in LPT order: systems by decreasing size, then their tiles.
     std::vector<int> order(S);
     for (int s = 0; s < S; ++s) order[s] = s;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
         return sys_offsets[x + 1] - sys_offsets[x] > sys_offsets[y + 1] - sys_offsets[y];
     });
-    const int span = kBlock * sh.tpl;
+    const int span = sh.mat ? kMatTargets : kBlock * sh.tpl;
     std::vector<int4> items;
     for (int s : order) {
         const int b0 = (int)sys_offsets[s], b1 = (int)sys_offsets[s + 1];
@@ -815,7 +1021,12 @@ int batched_products(const double* pos, const int64_t* sys_offsets, int S, const
         hipEvent_t ev = nullptr;
         profile_begin(st, &ev);
         hipError_t e;
-        if (prec == RPYW_FP32C)
+        if (sh.mat)
+            e = K == 16 ? launch_mat_batched_t<16>((const float*)rec, ditems, (int)items.size(), counter, B, m0, Ntot,
+                                                   kb, Uk, grid, st)
+                        : launch_mat_batched_t<8>((const float*)rec, ditems, (int)items.size(), counter, B, m0, Ntot,
+                                                  kb, Uk, grid, st);
+        else if (prec == RPYW_FP32C)
             e = RPYW_DISPATCH(float, K, sh.tpl, sh.tile, launch_batched_t, (const float*)rec, ditems,
                               (int)items.size(), counter, B, m0, Ntot, kb, Uk, grid, st);
         else

@@ -198,6 +198,46 @@ __device__ __forceinline__ void pair_apply(const PairCoef<R>& p, R dx, R dy, R d
     uz = fma_(t0, dz, fma_(p.kcm, G, fma_(p.cz, fz, uz)));
 }
 
+// The 3 x 3 block M_ij that pair_apply applies (units of mu0, B factors
+// excluded), written out for contracting one pair with a block of
+// right-hand sides.  From pair_apply: t = (kb + c2) (dx fx + dy fy) +
+// (kcp + c2 dz) fz enters along (dx, dy), and the normal row is
+// cz fz + (kcm + c2 dz)(dx fx + dy fy) + c2 dz^2 fz.  The block is not
+// symmetric (in-plane force to normal velocity and back have different wall
+// coefficients), but M_xy = M_yx.
+template <typename R>
+struct PairBlock {
+    R xx, xy, xz, yy, yz, zx, zy, zz;
+};
+
+template <typename R>
+__device__ __forceinline__ PairBlock<R> pair_block(const PairCoef<R>& p, R dx, R dy, R dz) {
+    PairBlock<R> m;
+    const R qb = p.kb + p.c2;
+    const R qx = qb * dx;
+    m.xx = fma_(qx, dx, p.cc);
+    m.xy = qx * dy;
+    m.yy = fma_(qb * dy, dy, p.cc);
+    const R pz = fma_(p.c2, dz, p.kcp);
+    m.xz = dx * pz;
+    m.yz = dy * pz;
+    const R qz = fma_(p.c2, dz, p.kcm);
+    m.zx = dx * qz;
+    m.zy = dy * qz;
+    m.zz = fma_(p.c2 * dz, dz, p.cz);
+    return m;
+}
+
+// u += M f for one right-hand side: the contraction that the matrix cores
+// carry out for a block of right-hand sides (this form serves the host
+// checks and the operation count).
+template <typename R>
+__device__ __forceinline__ void block_apply(const PairBlock<R>& m, R fx, R fy, R fz, R& ux, R& uy, R& uz) {
+    ux = fma_(m.xx, fx, fma_(m.xy, fy, fma_(m.xz, fz, ux)));
+    uy = fma_(m.xy, fx, fma_(m.yy, fy, fma_(m.yz, fz, uy)));
+    uz = fma_(m.zx, fx, fma_(m.zy, fy, fma_(m.zz, fz, uz)));
+}
+
 // Gradient of Phi = a^T M b + a2^T M b2 (units of mu0, radius 1) for one
 // pair, with respect to the base variables of the pair geometry
 // (dx, dy, dz, Rz = z_i + z_j, zz = z_i z_j).  Writing

@@ -29,6 +29,7 @@ struct Shape {
     int kblk;  // right-hand sides per pass: 1, 2, 4, 8 or 16
     int sym;   // symmetric pair evaluation (kblk <= 4): 0 off, 1 groups of 256 blobs, 2 groups of 64
     int ipw;   // symmetric path: source groups per workgroup
+    int mat = 0;  // FP32C blocks of 8 or 16 right-hand sides: contraction on the matrix cores
 };
 
 // Domain along the wall: open (lx = ly = 0) or the pseudo-periodic cell

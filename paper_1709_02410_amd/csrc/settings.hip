@@ -6,7 +6,9 @@
 //   RPYW_TILE=64|256           source tile of the plain pair kernel, for every
 //                              product (overrides tuned and built-in shapes)
 //   RPYW_RHS_WIDTH=1|2|4|8|16  right-hand sides per pass (FP64 stops at 8);
-//                              widths above 4 use the plain kernel
+//                              widths above 4 use the plain kernel, or in
+//                              FP32C the matrix-core kernel where the shape
+//                              selects it
 //   RPYW_SYM_SPLIT=ns,nseg     how the symmetric kernel with groups of 64
 //                              splits the passes of an item: over ns waves
 //                              of a workgroup (1 or 4) and nseg workgroups
@@ -23,7 +25,7 @@
 // set).  The file format is one JSON object:
 //   {"version": 1, "entries": [{"arch": "gfx950", "precision": 1,
 //     "size_class": 16, "k": 1, "tpl": 1, "tile": 256, "kblk": 1, "sym": 1,
-//     "ipw": 2}, ...]}
+//     "ipw": 2, "mat": 0}, ...]}   ("mat" may be missing: 0)
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -172,8 +174,10 @@ int read_shape_cache(const char* path, std::vector<CachedShape>& out) {
         if (field_str(obj, "arch", &c.arch) && field_int(obj, "precision", &c.prec) &&
             field_int(obj, "size_class", &c.size_class) && field_int(obj, "k", &c.kclass) &&
             field_int(obj, "tpl", &c.s.tpl) && field_int(obj, "tile", &c.s.tile) &&
-            field_int(obj, "kblk", &c.s.kblk) && field_int(obj, "sym", &c.s.sym) && field_int(obj, "ipw", &c.s.ipw))
+            field_int(obj, "kblk", &c.s.kblk) && field_int(obj, "sym", &c.s.sym) && field_int(obj, "ipw", &c.s.ipw)) {
+            if (!field_int(obj, "mat", &c.s.mat)) c.s.mat = 0;  // entries written before the field existed
             out.push_back(c);
+        }
         p = b + 1;
     }
     return 0;
@@ -188,9 +192,9 @@ int write_shape_cache(const char* path, const std::vector<CachedShape>& entries)
         const CachedShape& c = entries[i];
         std::fprintf(f,
                      "%s\n  {\"arch\": \"%s\", \"precision\": %d, \"size_class\": %d, \"k\": %d, \"tpl\": %d, "
-                     "\"tile\": %d, \"kblk\": %d, \"sym\": %d, \"ipw\": %d}",
+                     "\"tile\": %d, \"kblk\": %d, \"sym\": %d, \"ipw\": %d, \"mat\": %d}",
                      i ? "," : "", c.arch.c_str(), c.prec, c.size_class, c.kclass, c.s.tpl, c.s.tile, c.s.kblk,
-                     c.s.sym, c.s.ipw);
+                     c.s.sym, c.s.ipw, c.s.mat);
     }
     std::fprintf(f, "\n]}\n");
     const bool ok = std::fclose(f) == 0;

@@ -72,7 +72,7 @@ def lib():
         "rpyw_tridiag_sqrt_coeffs": [ctypes.POINTER(dbl), ctypes.POINTER(dbl), i32, dbl, ctypes.POINTER(dbl)],
         "rpy_wall_profile_enable": [ctypes.c_int],
         "rpy_wall_calibrate": [ctypes.c_int, i64, i32, vp, vp],
-        "rpy_wall_set_shape": [ctypes.c_int, i64, i32, i32, i32, i32, i32, i32],
+        "rpy_wall_set_shape": [ctypes.c_int, i64, i32, i32, i32, i32, i32, i32, i32],
         "rpy_wall_get_shape": [ctypes.c_int, i64, i32, ctypes.POINTER(i32)],
         "rpy_wall_profile_read": [ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl), ctypes.c_int],
     }
@@ -466,22 +466,22 @@ def autotune(pos: torch.Tensor, F: torch.Tensor, a: float = 1.0, eta: float = 1.
 
 
 def set_shape(precision: int, N: int, k: int = 1, tpl: int = 1, tile: int = 256, kblk: int = 1, sym: int = 0,
-              ipw: int = 4):
+              ipw: int = 4, mat: int = 0):
     """Fix the launch shape for products of this precision and size class
     (tpl=0 removes the override)."""
-    _check(lib().rpy_wall_set_shape(precision, N, k, tpl, tile, kblk, sym, ipw), "rpy_wall_set_shape")
+    _check(lib().rpy_wall_set_shape(precision, N, k, tpl, tile, kblk, sym, ipw, mat), "rpy_wall_set_shape")
 
 
 def reset_shape(precision: int, N: int, k: int = 1):
     """Back to the built-in or tuned launch shape for this size class."""
-    _check(lib().rpy_wall_set_shape(precision, N, k, 0, 0, 0, 0, 0), "rpy_wall_set_shape")
+    _check(lib().rpy_wall_set_shape(precision, N, k, 0, 0, 0, 0, 0, 0), "rpy_wall_set_shape")
 
 
 def get_shape(precision: int, N: int, k: int = 1) -> dict:
     """Launch shape that products of this precision and size class use."""
-    out = (ctypes.c_int32 * 5)()
+    out = (ctypes.c_int32 * 6)()
     _check(lib().rpy_wall_get_shape(precision, N, k, out), "rpy_wall_get_shape")
-    return dict(zip(("tpl", "tile", "kblk", "sym", "ipw"), list(out)))
+    return dict(zip(("tpl", "tile", "kblk", "sym", "ipw", "mat"), list(out)))
 
 
 def tridiag_sqrt_coeffs(alpha, beta, beta0: float) -> np.ndarray:

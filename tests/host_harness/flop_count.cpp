@@ -12,6 +12,8 @@
 //   shared      geometry and coefficients of one pair (the three coordinate
 //               differences included), far branch (r > 2a)
 //   apply       one application M_ij f_j accumulated into a sum
+//   block       the 3 x 3 block M_ij written out from the coefficients
+//   block_apply one right-hand side contracted with the written-out block
 //   vjp_pair    one unordered pair of the symmetric VJP: the analytic pair
 //               gradient, both blobs' gradient sums and the four products
 //               (two per blob)
@@ -90,6 +92,14 @@ int main() {
     pair_apply<Flop>(c, dx, dy, dz, fj[0], fj[1], fj[2], u[0], u[1], u[2]);
     const long apply = g_count;
 
+    g_count = 0;
+    const PairBlock<Flop> m = pair_block<Flop>(c, dx, dy, dz);
+    const long block = g_count;
+    g_count = 0;
+    Flop v[3];
+    block_apply<Flop>(m, fj[0], fj[1], fj[2], v[0], v[1], v[2]);
+    const long block_apply_n = g_count;
+
     // symmetric VJP, one unordered pair: target side and source side
     g_count = 0;
     PairCoef<Flop> p;
@@ -111,7 +121,9 @@ int main() {
     pair_apply<Flop>(p, dx, dy, dz, gi[0], gi[1], gi[2], sacc[6], sacc[7], sacc[8]);
     const long vjp_pair = g_count + 3;
 
-    std::printf("{\"shared\": %ld, \"apply\": %ld, \"vjp_pair\": %ld, \"vjp_self\": %ld}\n", shared, apply, vjp_pair,
-                vjp_self);
+    std::printf(
+        "{\"shared\": %ld, \"apply\": %ld, \"block\": %ld, \"block_apply\": %ld, \"vjp_pair\": %ld, "
+        "\"vjp_self\": %ld}\n",
+        shared, apply, block, block_apply_n, vjp_pair, vjp_self);
     return 0;
 }

@@ -14,6 +14,19 @@ static void block(const double* d, const double* z, double* out) {
     }
 }
 
+// The same block through the written-out form the matrix-core kernel
+// contracts (pair_block, block_apply).
+template <typename R>
+static void block2(const double* d, const double* z, double* out) {
+    PairCoef<R> c = pair_coef<R>((R)d[0], (R)d[1], (R)d[2], (R)z[0], (R)z[1]);
+    const PairBlock<R> m = pair_block<R>(c, (R)d[0], (R)d[1], (R)d[2]);
+    for (int col = 0; col < 3; ++col) {
+        R u[3] = {0, 0, 0};
+        block_apply<R>(m, R(col == 0), R(col == 1), R(col == 2), u[0], u[1], u[2]);
+        for (int r = 0; r < 3; ++r) out[3 * r + col] = (double)u[r];
+    }
+}
+
 template <typename R>
 static void grad(const double* d, const double* z, const double* v12, double* out) {
     R a[3], b[3], a2[3], b2[3];
@@ -46,6 +59,8 @@ static void grad(const double* d, const double* z, const double* v12, double* ou
 extern "C" {
 void host_block_f64(const double* d, const double* z, double* out) { block<double>(d, z, out); }
 void host_block_f32(const double* d, const double* z, double* out) { block<float>(d, z, out); }
+void host_block2_f64(const double* d, const double* z, double* out) { block2<double>(d, z, out); }
+void host_block2_f32(const double* d, const double* z, double* out) { block2<float>(d, z, out); }
 void host_grad_f64(const double* d, const double* z, const double* v, double* out) { grad<double>(d, z, v, out); }
 void host_grad_f32(const double* d, const double* z, const double* v, double* out) { grad<float>(d, z, v, out); }
 }

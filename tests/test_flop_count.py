@@ -25,8 +25,8 @@ def test_bench_flop_constants_match_the_counted_formula(tmp_path):
                    check=True)
     counts = json.loads(subprocess.run([exe], check=True, capture_output=True, text=True).stdout)
     b = _bench()
-    assert counts == {"shared": b.FLOP_PAIR_SHARED, "apply": b.FLOP_PAIR_RHS, "vjp_pair": b.FLOP_VJP_PAIR,
-                      "vjp_self": b.FLOP_VJP_SELF}
+    assert counts == {"shared": b.FLOP_PAIR_SHARED, "apply": b.FLOP_PAIR_RHS, "block": b.FLOP_PAIR_BLOCK,
+                      "block_apply": b.FLOP_BLOCK_RHS, "vjp_pair": b.FLOP_VJP_PAIR, "vjp_self": b.FLOP_VJP_SELF}
     # symmetric product of N blobs: N(N-1)/2 unordered pairs (geometry once,
     # two applications) plus N self pairs (one application)
     N = 10
@@ -34,3 +34,6 @@ def test_bench_flop_constants_match_the_counted_formula(tmp_path):
         counts["shared"] + counts["apply"])
     assert b.algorithmic_flop(N, 2, 0) == 100 * (counts["shared"] + 2 * counts["apply"])
     assert b.vjp_flop(N, 1) == 45 * counts["vjp_pair"] + 10 * counts["vjp_self"]
+    # matrix-core multi-RHS kernel: every ordered pair forms its block once
+    # (vector units) and contracts it with each right-hand side (matrix cores)
+    assert b.mat_flop(N, 16) == (100 * (counts["shared"] + counts["block"]), 100 * 16 * counts["block_apply"])

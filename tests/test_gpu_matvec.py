@@ -70,6 +70,53 @@ def test_determinism_and_multi_rhs(rp, orc):
             single = rp.matvec(pos, _t(F[l]), precision=prec).cpu().numpy()
             check(U1[l], single, 1e-14 if prec == 0 else 1e-6, f"multi vs single prec={prec} rhs={l}")
 
+@pytest.mark.parametrize("N", [1, 3, 15, 16, 17, 64, 65, 257, 1500, 4097])
+@pytest.mark.parametrize("k", [8, 11, 16])
+def test_matrix_core_multi_rhs_ragged(rp, orc, N, k):
+    """FP32C blocks of 8 and 16 right-hand sides (11: a partial block of 16)
+    contracted on the matrix cores, against the oracle per right-hand side,
+    at sizes from one partial 16-target wave to many workgroups and source
+    chunks, with ragged 4-source steps, overlapping pairs, blobs below z = a
+    and a coincident pair; the vector kernel of the same block width too.
+    The matrix-core result repeats bitwise."""
+    rng = np.random.default_rng(2000 + N)
+    box = max(2.0, 2.0 * np.sqrt(N))
+    pos = np.column_stack([rng.uniform(0, box, N), rng.uniform(0, box, N), rng.uniform(0.3, 4.0, N)])
+    if N >= 3:
+        pos[2] = pos[1]
+    F = rng.standard_normal((k, N, 3))
+    refs = [orc.matvec(pos, F[l]) for l in range(k)]
+    kblk = 8 if k <= 8 else 16
+    try:
+        for mat in (1, 0):
+            rp.set_shape(1, N, k, tpl=1, tile=64, kblk=kblk, sym=0, ipw=4, mat=mat)
+            U = rp.matvec_multi(_t(pos), _t(F), precision=1).cpu().numpy()
+            for l in range(k):
+                check(U[l], refs[l], TOL[1], f"multi-RHS N={N} k={k} mat={mat} rhs={l}")
+            if mat:
+                assert np.array_equal(U, rp.matvec_multi(_t(pos), _t(F), precision=1).cpu().numpy())
+    finally:
+        rp.reset_shape(1, N, k)
+
+
+def test_matrix_core_1e5_sampled_rows(rp, orc):
+    """The 16-RHS product on the 1e5-blob workload in the launch shape the
+    benchmark times (matrix cores): sampled rows, the first and the last
+    blob, for three right-hand sides, against the oracle."""
+    cfg = wl.headline(seed=0)
+    k = 16
+    F = wl.gaussian((k, cfg.N, 3), 2)
+    rows = np.concatenate([np.random.default_rng(9).choice(cfg.N, 64, replace=False), [0, cfg.N - 1]])
+    rp.set_shape(1, cfg.N, k, tpl=1, tile=64, kblk=16, sym=0, ipw=4, mat=1)
+    try:
+        U = rp.matvec_multi(_t(cfg.pos), _t(F), precision=1).cpu().numpy()
+    finally:
+        rp.reset_shape(1, cfg.N, k)
+    for l in (0, 5, 15):
+        ref = orc.matvec(cfg.pos, F[l], rows=rows)
+        check(U[l][rows], ref, TOL[1], f"H 16-RHS matrix cores rhs={l} sampled rows")
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_headline_1e5_sampled_rows(rp, orc, prec):
     """1e5 blobs (the measured workload) in every launch shape the benchmark's

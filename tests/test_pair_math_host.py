@@ -20,7 +20,7 @@ def pm(tmp_path_factory):
                     os.path.join(HARNESS, "pair_math_host.cpp"), "-o", out], check=True)
     lib = ctypes.CDLL(out)
     dp = ctypes.POINTER(ctypes.c_double)
-    for n in ("host_block_f64", "host_block_f32"):
+    for n in ("host_block_f64", "host_block_f32", "host_block2_f64", "host_block2_f32"):
         getattr(lib, n).argtypes = [dp, dp, dp]
     for n in ("host_grad_f64", "host_grad_f32"):
         getattr(lib, n).argtypes = [dp, dp, dp, dp]
@@ -31,11 +31,13 @@ def _p(x):
     return np.ascontiguousarray(x, dtype=np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def _block(pm, d, z, f32=False):
+def _block(pm, d, z, f32=False, written_out=False):
     out = np.empty(9)
     d = np.ascontiguousarray(d, dtype=np.float64)
     z = np.ascontiguousarray(z, dtype=np.float64)
-    (pm.host_block_f32 if f32 else pm.host_block_f64)(_p(d), _p(z), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    fn = {(False, False): pm.host_block_f64, (True, False): pm.host_block_f32,
+          (False, True): pm.host_block2_f64, (True, True): pm.host_block2_f32}[(f32, written_out)]
+    fn(_p(d), _p(z), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     return out.reshape(3, 3)
 
 
@@ -67,6 +69,26 @@ def test_block_matches_oracle(pm, orc):
         assert np.abs(got - ref).max() <= 2e-15 * max(1.0, np.abs(ref).max()), (d, z)
         got32 = _block(pm, d, z, f32=True)
         assert np.abs(got32 - ref).max() <= 3e-6 * max(1.0, np.abs(ref).max())
+
+
+def test_written_out_block_matches_oracle(pm, orc):
+    """The 3 x 3 block as the matrix-core kernel forms it (pair_block, then
+    one contraction per right-hand side) against the oracle's block, at the
+    same bars as the applied form, including overlapping and coincident
+    pairs."""
+    rng = np.random.default_rng(7)
+    cases = list(_pairs(rng, 400)) + [(np.zeros(3), np.array([1.7, 1.7])), (np.array([0.3, -0.2, 0.1]),
+                                                                             np.array([1.2, 1.1]))]
+    for d, z in cases:
+        ri = np.array([d[0], d[1], z[0]])
+        rj = np.array([0.0, 0.0, z[1]])
+        ref = orc.pair_block(ri, rj, 1.0, 1.0, 0) * 6 * np.pi
+        got = _block(pm, d, z, written_out=True)
+        assert np.abs(got - ref).max() <= 2e-15 * max(1.0, np.abs(ref).max()), (d, z)
+        got32 = _block(pm, d, z, f32=True, written_out=True)
+        assert np.abs(got32 - ref).max() <= 3e-6 * max(1.0, np.abs(ref).max())
+        # and it is the block pair_apply applies, entry for entry in FP64
+        assert np.abs(got - _block(pm, d, z)).max() <= 1e-15 * max(1.0, np.abs(ref).max())
 
 
 def test_pair_gradient_matches_central_differences(pm):

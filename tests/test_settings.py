@@ -58,7 +58,7 @@ def test_autotune_cache_is_read(tmp_path):
     entries.append(dict(arch="gfx000", precision=1, size_class=12, k=2, tpl=1, tile=256, kblk=1, sym=1, ipw=1))
     path.write_text(json.dumps({"version": 1, "entries": entries}))
     got, err = _run({"RPYW_AUTOTUNE_CACHE": str(path), "RPYW_LOG": "1"}, [(1, 5000, 2), (1, 9000, 2), (0, 5000, 2)])
-    assert got[0] == shape  # size class 12 = [4096, 8192), two right-hand sides
+    assert got[0] == dict(shape, mat=0)  # size class 12 = [4096, 8192), two right-hand sides; no "mat": 0
     assert got[1] != shape and got[2] != shape  # other size class, other precision
     assert "1 shapes for" in err
 
