@@ -315,7 +315,7 @@ struct MatLane {
     // forces from the tile, the pair's distances and far-field coefficients.
     __device__ void front(const float* tile, int j, int q, int kf, float fscale, PairPre<float>& pp, float& dx,
                           float& dy, float& dz, float* fn) const {
-        const float* s = tile + (j + q) * RW;
+        const float* s = (tile + q * RW) + j * RW;  // j is uniform: no per-lane multiply
         const float sz = s[2];
         dx = (x - s[0]) + (xl - s[3]);
         dy = (y - s[1]) + (yl - s[4]);
