@@ -52,6 +52,18 @@ __device__ void reduce_rows(const double* __restrict__ partial, int nrows, int n
     __syncthreads();
 }
 
+// Entry slots of a group of n entries (3 per blob, n <= 128) whose partial
+// sums a workgroup gathers: thread t takes slot t % S (S = 64, or 128 when
+// n > 64) and share t / S.  Slots run over the blobs first (slot q nb + b for
+// component q of blob b, nb = n / 3), so that the lanes of a wave read the
+// partials of consecutive blobs, which lie next to each other.
+__device__ __forceinline__ int gather_slots(int n) { return n <= 64 ? 64 : 128; }
+__device__ __forceinline__ int gather_entry(int slot, int n) {
+    const int nb = n / 3, q = slot / nb;
+    return 3 * (slot - q * nb) + q;
+}
+__device__ __forceinline__ int gather_slot(int entry, int n) { return (entry % 3) * (n / 3) + entry / 3; }
+
 // Sum of the target-chunk and source-item partials of quantity q of blob i
 // (layout of sym_kernel) taken by share u of U: chunks c and items d with
 // c, d = u (mod U), in increasing order, sixteen loads in flight.

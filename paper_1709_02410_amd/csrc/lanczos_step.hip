@@ -214,11 +214,12 @@ __global__ __launch_bounds__(kOutThreads) void lz_out_kernel(
         av[i][0] = (j <= k && l < n) ? V[j * n3 + e0 + l] : 0.0;
         av[i][1] = (j <= k && l + 64 < n) ? V[j * n3 + e0 + l + 64] : 0.0;
     }
+    const int S = gather_slots(n);  // U = kOutThreads / S
     {
-        const int s = t / U, u = t % U;
+        const int slot = t % S, u = t / S;
         double r = 0.0;
-        if (s < n) {
-            const int64_t e = e0 + s, blob = e / 3;
+        if (slot < n) {
+            const int64_t e = e0 + gather_entry(slot, n), blob = e / 3;
             r = gather_share<R>(tpart, spart, blob, ng, C, Hmax, nseg, G, (int)(e - 3 * blob), u, U);
         }
         red[t] = r;
@@ -227,14 +228,14 @@ __global__ __launch_bounds__(kOutThreads) void lz_out_kernel(
     if (lds_factor) sf.store(Lf, 2 * gi.sq);
     __syncthreads();
     if (t < n) {
-        const double* rt = red + t * U;
+        const double* rt = red + gather_slot(t, n);
         double s = rt[0];
         if (U == 8) {
 #pragma unroll
-            for (int u = 1; u < 8; ++u) s += rt[u];
+            for (int u = 1; u < 8; ++u) s += rt[u * 64];
         } else {
 #pragma unroll
-            for (int u = 1; u < 4; ++u) s += rt[u];
+            for (int u = 1; u < 4; ++u) s += rt[u * 128];
         }
         y[t] = mu0 * bb * s;
     }

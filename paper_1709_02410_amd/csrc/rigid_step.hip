@@ -325,11 +325,12 @@ __global__ __launch_bounds__(kOutThreads) void rg_out_kernel(
     }
     // y = M z_lambda: U threads per entry add their share of the partials
     const int U = n <= 64 ? 4 : 2;
+    const int S = gather_slots(n);  // U = kOutThreads / S
     {
-        const int s = t / U, u = t % U;
+        const int slot = t % S, u = t / S;
         double rr = 0.0;
-        if (s < n) {
-            const int64_t e = e0 + s, blob = e / 3;
+        if (slot < n) {
+            const int64_t e = e0 + gather_entry(slot, n), blob = e / 3;
             rr = gather_share<R>(tpart, spart, blob, ng, C, Hmax, nseg, G, (int)(e - 3 * blob), u, U);
         }
         red[t] = rr;
@@ -345,8 +346,9 @@ __global__ __launch_bounds__(kOutThreads) void rg_out_kernel(
     }
     __syncthreads();
     if (t < n) {
-        double s = red[t * U];
-        for (int u = 1; u < U; ++u) s += red[t * U + u];
+        const int slot = gather_slot(t, n);
+        double s = red[slot];
+        for (int u = 1; u < U; ++u) s += red[u * S + slot];
         const double y = mu0 * bb * s;
         // (K z_U) for this entry's component: u + omega x d
         const int al = t % 3;
