@@ -295,6 +295,7 @@ size_t lanczos_ws_bytes(int64_t N, int max_iter, int n_bodies, int prec) {
     b += align_up((size_t)(max_iter + 3) * lanczos_gs2_blocks((int64_t)n3, &m) * sizeof(double));
     b += align_up((units + 1) * sizeof(int)) + align_up((units + 1) * sizeof(LanczosGroup));
     b += align_up(((size_t)N / 256 + 3) * sizeof(double));  // partials of |W|^2 (padded blobs / 256)
+    b += align_up(n3 * sizeof(double));                       // the summed product (large problems)
     return b + 24 * kAlign;
 }
 
@@ -385,8 +386,9 @@ int lanczos_fused(const double* pos, const double* W, double* out, int64_t N, do
     double* B = (double*)ar.take((size_t)npad * sizeof(double));
     double* tpart = (double*)ar.take(sp.tpart_bytes);
     void* spart = ar.take(sp.spart_bytes);
+    double* ypre = krylov_presum(sp) ? (double*)ar.take((size_t)n3 * sizeof(double)) : nullptr;
     if (!V || !y || !w || !sqp || !part1 || !part2 || !d_ab || !d_c || !notspd || !d_tab || !pc.L || !rec || !B ||
-        !tpart || !spart)
+        !tpart || !spart || (krylov_presum(sp) && !ypre))
         return RPYW_ENOMEM;
     std::lock_guard<std::mutex> lk(g_ab.mu);
     const size_t hdr_bytes = align_up((size_t)(3 * (max_iter + 2) + 2) * sizeof(double));
@@ -432,8 +434,9 @@ int lanczos_fused(const double* pos, const double* W, double* out, int64_t N, do
         profile_begin(st, &ev);
         if ((r = sym_launch(rec, sp, ipw, 1, prec, a, dom, tpart, spart, st))) return r;
         profile_end(st, ev, (dom.periodic() ? 9.0 : 1.0) * (double)N * (double)N);
+        if (ypre && (r = sym_finish(tpart, spart, B, N, 1, 1, prec, sp, m0, ypre, st, nullptr, 1.0 / a))) return r;
         if ((r = lz_launch_out(prec, pc, d_units, d_groups, ngroups, tpart, spart, sp, B, m0, n3, k, V, d_ab, w,
-                               part1, st)))
+                               part1, ypre, st)))
             return r;
         if ((r = lz_launch_gs2(w, y, n3, V, k, part1, ngroups, part2, d_ab, nullptr, st))) return r;
         if ((r = vin(k + 1))) return r;  // V has room for max_iter + 1 vectors

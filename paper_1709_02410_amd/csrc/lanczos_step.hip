@@ -176,7 +176,7 @@ __global__ __launch_bounds__(kOutThreads) void lz_out_kernel(
     const double* __restrict__ Lall, const double* __restrict__ tpart, const R* __restrict__ spart, int ng, int C,
     int Hmax, int nseg, int G, const double* __restrict__ B, double mu0, int64_t n3, int k,
     const double* __restrict__ V, const double* __restrict__ d_ab, double* __restrict__ w,
-    double* __restrict__ part1, int ngroups) {
+    double* __restrict__ part1, int ngroups, const double* __restrict__ ypre) {
     __shared__ double red[kOutThreads];
     __shared__ double y[3 * kMaxBodyBlobs];  // a group has at most 64 entries, or one body of up to 126
     __shared__ double wl[3 * kMaxBodyBlobs];
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kOutThreads) void lz_out_kernel(
         av[i][1] = (j <= k && l + 64 < n) ? V[j * n3 + e0 + l + 64] : 0.0;
     }
     const int S = gather_slots(n);  // U = kOutThreads / S
-    {
+    if (!ypre) {
         const int slot = t % S, u = t / S;
         double r = 0.0;
         if (slot < n) {
@@ -227,7 +227,9 @@ __global__ __launch_bounds__(kOutThreads) void lz_out_kernel(
     if (t <= nu) ub[t] = uv;
     if (lds_factor) sf.store(Lf, 2 * gi.sq);
     __syncthreads();
-    if (t < n) {
+    if (t < n && ypre) {
+        y[t] = ypre[e0 + t];
+    } else if (t < n) {
         const double* rt = red + gather_slot(t, n);
         double s = rt[0];
         if (U == 8) {
@@ -567,15 +569,16 @@ int lz_launch_vin(int prec, const BodyFactors& pc, const int* units, int nunits,
 
 int lz_launch_out(int prec, const BodyFactors& pc, const int* units, const LanczosGroup* ginfo, int ngroups,
                   const double* tpart, const void* spart, const SymPlan& sp, const double* B, double mu0, int64_t n3,
-                  int k, const double* V, const double* d_ab, double* w, double* part1, hipStream_t st) {
+                  int k, const double* V, const double* d_ab, double* w, double* part1, const double* ypre,
+                  hipStream_t st) {
     if (prec == RPYW_FP32C)
         hipLaunchKernelGGL(lz_out_kernel<float>, dim3((unsigned)ngroups), dim3(kOutThreads), 0, st, pc.diag ? 1 : 0,
                            units, ginfo, pc.L, tpart, (const float*)spart, sp.ng, sp.C, sp.Hmax, sp.nseg, sp.G, B,
-                           mu0, n3, k, V, d_ab, w, part1, ngroups);
+                           mu0, n3, k, V, d_ab, w, part1, ngroups, ypre);
     else
         hipLaunchKernelGGL(lz_out_kernel<double>, dim3((unsigned)ngroups), dim3(kOutThreads), 0, st, pc.diag ? 1 : 0,
                            units, ginfo, pc.L, tpart, (const double*)spart, sp.ng, sp.C, sp.Hmax, sp.nseg, sp.G, B,
-                           mu0, n3, k, V, d_ab, w, part1, ngroups);
+                           mu0, n3, k, V, d_ab, w, part1, ngroups, ypre);
     RPYW_HIP(hipGetLastError());
     return RPYW_OK;
 }

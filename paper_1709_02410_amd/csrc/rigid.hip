@@ -359,6 +359,7 @@ size_t rigid_ws_bytes(int64_t N, int max_iter, int n_bodies, int prec) {
     b += align_up((m + 3) * (size_t)lanczos_gs2_blocks((int64_t)n, &m4) * sizeof(double));
     b += align_up((m + 8) * sizeof(double));
     b += align_up((n / 256 + 2) * sizeof(double));  // partials of |b|^2
+    b += align_up(n3 * sizeof(double));             // the summed product (large problems)
     return b + 24 * kAlign;
 }
 
@@ -424,8 +425,9 @@ int rigid_fused(const double* pos, const double* q, const int64_t* body_offsets,
     double* B = (double*)ar.take((size_t)npad * sizeof(double));
     double* tpart = (double*)ar.take(sp.tpart_bytes);
     void* spart = ar.take(sp.spart_bytes);
+    double* ypre = krylov_presum(sp) ? (double*)ar.take((size_t)n3 * sizeof(double)) : nullptr;
     if (!Wall || !Nall || !V || !zb || !wb || !yb || !bv || !sqp || !part1 || !part2 || !gc1 || !d_y || !notspd ||
-        !rec || !B || !tpart || !spart)
+        !rec || !B || !tpart || !spart || (krylov_presum(sp) && !ypre))
         return RPYW_ENOMEM;
     std::lock_guard<std::mutex> lk(g_h.mu);
     const int slot = 2 * (max_iter + 2);  // c1[0..k], c2[0..k], h_{k+1,k}
@@ -468,8 +470,9 @@ int rigid_fused(const double* pos, const double* q, const int64_t* body_offsets,
     auto launch_step = [&](int k) -> int {
         int r;
         if ((r = sym_launch(rec, sp, ipw, 1, prec, a, dom, tpart, spart, st))) return r;
+        if (ypre && (r = sym_finish(tpart, spart, B, N, 1, 1, prec, sp, m0, ypre, st, nullptr, 1.0 / a))) return r;
         if ((r = rg_launch_out(prec, pos, q, pc.bofs, n_bodies, tpart, spart, sp, B, m0, zb, zb + n3, n3, n, V, k, wb,
-                               part1, st)))
+                               part1, ypre, st)))
             return r;
         if ((r = lz_launch_gs2(wb, yb, n, V, k, part1, n_bodies, part2, nullptr, gc1, st))) return r;
         if ((r = pre_k(k + 1))) return r;  // V has room for max_iter + 1 vectors

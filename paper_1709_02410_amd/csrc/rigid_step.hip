@@ -280,7 +280,7 @@ __global__ __launch_bounds__(kOutThreads) void rg_out_kernel(
     const double* __restrict__ tpart, const R* __restrict__ spart, int ng, int C, int Hmax, int nseg, int G,
     const double* __restrict__ B, double mu0, const double* __restrict__ zl, const double* __restrict__ zu,
     int64_t n3, int64_t ld, const double* __restrict__ V, int k, double* __restrict__ w,
-    double* __restrict__ part1, int nbodies) {
+    double* __restrict__ part1, int nbodies, const double* __restrict__ ypre) {
     constexpr int kWaves = kOutThreads / 64;
     constexpr int kSlots = 3;  // entries per lane for the dot products (n + 6 <= 132)
     __shared__ double red[kOutThreads];
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(kOutThreads) void rg_out_kernel(
     // y = M z_lambda: U threads per entry add their share of the partials
     const int U = n <= 64 ? 4 : 2;
     const int S = gather_slots(n);  // U = kOutThreads / S
-    {
+    if (!ypre) {
         const int slot = t % S, u = t / S;
         double rr = 0.0;
         if (slot < n) {
@@ -346,10 +346,15 @@ __global__ __launch_bounds__(kOutThreads) void rg_out_kernel(
     }
     __syncthreads();
     if (t < n) {
-        const int slot = gather_slot(t, n);
-        double s = red[slot];
-        for (int u = 1; u < U; ++u) s += red[u * S + slot];
-        const double y = mu0 * bb * s;
+        double y;
+        if (ypre) {
+            y = ypre[e0 + t];
+        } else {
+            const int slot = gather_slot(t, n);
+            double s = red[slot];
+            for (int u = 1; u < U; ++u) s += red[u * S + slot];
+            y = mu0 * bb * s;
+        }
         // (K z_U) for this entry's component: u + omega x d
         const int al = t % 3;
         const double ku = al == 0   ? zu6[0] + zu6[4] * d[2] - zu6[5] * d[1]
@@ -448,15 +453,15 @@ int rg_launch_rhs(int prec, const double* pos, int64_t N, int64_t npad, int recw
 int rg_launch_out(int prec, const double* pos, const double* q, const int* bofs, int n_bodies, const double* tpart,
                   const void* spart, const SymPlan& sp, const double* B, double mu0, const double* zl,
                   const double* zu, int64_t n3, int64_t ld, const double* V, int k, double* w, double* part1,
-                  hipStream_t st) {
+                  const double* ypre, hipStream_t st) {
     if (prec == RPYW_FP32C)
         hipLaunchKernelGGL(rg_out_kernel<float>, dim3((unsigned)n_bodies), dim3(kOutThreads), 0, st, pos, q, bofs,
                            tpart, (const float*)spart, sp.ng, sp.C, sp.Hmax, sp.nseg, sp.G, B, mu0, zl, zu, n3, ld, V,
-                           k, w, part1, n_bodies);
+                           k, w, part1, n_bodies, ypre);
     else
         hipLaunchKernelGGL(rg_out_kernel<double>, dim3((unsigned)n_bodies), dim3(kOutThreads), 0, st, pos, q, bofs,
                            tpart, (const double*)spart, sp.ng, sp.C, sp.Hmax, sp.nseg, sp.G, B, mu0, zl, zu, n3, ld,
-                           V, k, w, part1, n_bodies);
+                           V, k, w, part1, n_bodies, ypre);
     RPYW_HIP(hipGetLastError());
     return RPYW_OK;
 }

@@ -214,9 +214,14 @@ int lz_launch_pack(int prec, const double* pos, const double* W, int64_t N, int6
 constexpr int kLanczosCoefArgs = 448;
 int lz_launch_fin(const BodyFactors& pc, const int* units, int nunits, int64_t n3, const double* V, const double* c,
                   int nv, double* out, hipStream_t st);
+// ypre: when given, the product mu0 B_i sum(partials) already summed by the
+// symmetric epilogue ([N][3]); the kernel then reads it instead of gathering
+// the partials of its own entries (which is latency-bound but uncoalesced:
+// the better choice for small problems only).
 int lz_launch_out(int prec, const BodyFactors& pc, const int* units, const LanczosGroup* ginfo, int ngroups,
                   const double* tpart, const void* spart, const SymPlan& sp, const double* B, double mu0, int64_t n3,
-                  int k, const double* V, const double* d_ab, double* w, double* part1, hipStream_t st);
+                  int k, const double* V, const double* d_ab, double* w, double* part1, const double* ypre,
+                  hipStream_t st);
 int lz_launch_gs2(const double* w, double* yo, int64_t n3, const double* V, int k, const double* part1, int ngroups,
                   double* part2, double* d_ab, double* gc1, hipStream_t st);
 
@@ -243,10 +248,15 @@ int64_t rg_rhs_blocks(int64_t n);
 int rg_launch_rhs(int prec, const double* pos, int64_t N, int64_t npad, int recw, double a, const Domain& dom,
                   void* rec, double* B, const double* slip, const double* FT, int64_t n3, int64_t n6, double* b,
                   double* sqp, int* bad, const int* htab, int* dtab, int nwords, hipStream_t st);
+// ypre: as for lz_launch_out.
 int rg_launch_out(int prec, const double* pos, const double* q, const int* bofs, int n_bodies, const double* tpart,
                   const void* spart, const SymPlan& sp, const double* B, double mu0, const double* zl,
                   const double* zu, int64_t n3, int64_t ld, const double* V, int k, double* w, double* part1,
-                  hipStream_t st);
+                  const double* ypre, hipStream_t st);
+
+// Whether the fused Krylov steps sum the product's partials with the
+// symmetric epilogue first (groups of 256 blobs: large problems).
+inline bool krylov_presum(const SymPlan& sp) { return sp.G == 256; }
 
 // Krylov building blocks (krylov.hip).
 // Block-diagonal preconditioner factors: per body the Cholesky factor L_p of

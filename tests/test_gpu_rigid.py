@@ -200,3 +200,32 @@ def test_zero_rhs_and_not_converged_and_rod(rp, fused):
     with krylov_path(rp, 3, fused), pytest.raises(rp.RpywError) as ei:
         rp.rigid_solve(_t(rod), _t(np.array([[2.0, 0.0, 3.0]])), [0, 3], None, _t(np.ones((1, 6))))
     assert ei.value.status == rp.ENOTSPD
+
+
+def test_large_suspension_presummed_product(rp):
+    """4096 paper-like boomerangs (61440 blobs, groups of 256: the fused
+    steps sum the product's partials with the symmetric epilogue before
+    their operator kernel): the fused rigid solve and Lanczos root against
+    the unfused drivers on the plain product, FP64."""
+    cfg = wl.paperlike_boomerangs(4096, seed=2)
+    offs = cfg.body_offsets
+    nb = len(offs) - 1
+    N = len(cfg.pos)
+    q = cfg.pos[offs[:-1]].copy()
+    FT = wl.gaussian((nb, 6), 10)
+    W = wl.gaussian(cfg.pos.shape, 3)
+    pos = _t(cfg.pos)
+    got = {}
+    for sym in (1, 0):
+        rp.set_shape(0, N, 1, tpl=1, tile=256, kblk=1, sym=sym, ipw=4)
+        try:
+            _, U, it, _, ok = rp.rigid_solve(pos, _t(q), offs, None, _t(FT), tol=1e-8)
+            out, itl, _, okl = rp.lanczos_sqrt(pos, _t(W), body_offsets=offs, tol=1e-8)
+        finally:
+            rp.reset_shape(0, N, 1)
+        assert ok and okl
+        got[sym] = (U.cpu().numpy(), it, out.cpu().numpy(), itl)
+        print(f"4096 boomerangs sym={sym}: rigid {it} iterations, lanczos {itl}", flush=True)
+    assert abs(got[1][1] - got[0][1]) <= 1 and abs(got[1][3] - got[0][3]) <= 1
+    check(got[1][0], got[0][0], 1e-10, "4096 boomerangs rigid U fused vs unfused")
+    check(got[1][2], got[0][2], 1e-10, "4096 boomerangs Lanczos fused vs unfused")
