@@ -369,9 +369,11 @@ __global__ __launch_bounds__(kBlock) void mat_pair_kernel(const float* __restric
 }
 
 // Batched systems on the matrix cores: as batched_kernel, with work items of
-// 64 targets.
+// 64 targets; five resident workgroups per CU (the register bound keeps the
+// item loop's extra registers within five waves per SIMD).
+constexpr int kMatBatchedWaves = 5;
 template <int K>
-__global__ __launch_bounds__(kBlock) void mat_batched_kernel(const float* __restrict__ rec,
+__global__ __launch_bounds__(kBlock, kMatBatchedWaves) void mat_batched_kernel(const float* __restrict__ rec,
                                                              const int4* __restrict__ items, int n_items,
                                                              unsigned* __restrict__ counter,
                                                              const double* __restrict__ B, double mu0, int64_t Ntot,
@@ -1041,7 +1043,7 @@ int batched_products(const double* pos, const int64_t* sys_offsets, int S, const
     int dev = 0, ncu = 256;
     RPYW_HIP(hipGetDevice(&dev));
     RPYW_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    const int grid = (int)std::min<size_t>(items.size(), (size_t)ncu * 4);
+    const int grid = (int)std::min<size_t>(items.size(), (size_t)ncu * (sh.mat ? kMatBatchedWaves : 4));
     const unsigned g1 = (unsigned)((Ntot + kBlock - 1) / kBlock);
     const double m0 = mu0_of(a, eta);
     double pairs = 0.0;
