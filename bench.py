@@ -53,6 +53,8 @@ FLOP_PAIR_BLOCK = 19
 FLOP_BLOCK_RHS = 18
 PEAK_FP32_MATRIX = 157.3  # TFLOP/s, MI355X dense FP32 matrix cores
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pair_kernel_traffic.json")
+# sources of the single-RHS pair kernels whose stored counter figures the hash
+# guards (the matrix-core multi-RHS kernels of mat_pairs.h are not among them)
 KERNEL_SOURCES = ["pair_kernels.hip", "pair_math.h", "records.h", "sym_pairs.h"]
 
 
