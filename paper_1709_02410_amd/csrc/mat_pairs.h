@@ -13,8 +13,6 @@
 
 namespace rpyw {
 
-// ------------------------------------------------------------ multi-RHS on the matrix cores
-//
 // With a block of K >= 8 right-hand sides the product is a dense contraction:
 // u_i = sum_j M_ij F_j, F_j the 3 x K block of source j's forces.  The vector
 // units form each 3 x 3 block M_ij once (the pair geometry and its wall
@@ -88,8 +86,8 @@ struct MatLane {
             // scheduling groups interleave the two: six contractions go with
             // the tile reads and distances of the next step, before its
             // overlap branch, three with its wall coefficients after it.
-            // Without them the matrix and vector work of a wave run one
-            // after the other (18% slower at 1e5 blobs).
+            // Without them the loop ran up to 18% slower at 1e5 blobs (on
+            // some MI355X units; the same on others).
             PairPre<float> pp;
             float dx, dy, dz, fn[3];
             front(tile, 0, q, kf, fscale, pp, dx, dy, dz, fn);
