@@ -99,6 +99,20 @@ def test_matrix_core_multi_rhs_ragged(rp, orc, N, k):
         rp.reset_shape(1, N, k)
 
 
+def test_matrix_core_scaled_and_split_blocks(rp, orc):
+    """Blob radius and viscosity other than 1 (blobs below z = a, scaled
+    forces) and 17 right-hand sides: one block of 16 on the matrix cores and
+    a last block of one on the plain vector kernel, in the default shape."""
+    N, k, a, eta = 1500, 17, 0.9, 1.3
+    rng = np.random.default_rng(77)
+    pos = np.column_stack([rng.uniform(0, 70, N), rng.uniform(0, 70, N), rng.uniform(0.3, 4.0, N)]) * a
+    F = 3.0 * rng.standard_normal((k, N, 3))
+    rp.reset_shape(1, N, k)
+    U = rp.matvec_multi(_t(pos), _t(F), a, eta, precision=1).cpu().numpy()
+    for l in range(k):
+        check(U[l], orc.matvec(pos, F[l], a, eta), TOL[1], f"scaled multi-RHS k=17 rhs={l}")
+
+
 def test_matrix_core_1e5_sampled_rows(rp, orc):
     """The 16-RHS product on the 1e5-blob workload in the launch shape the
     benchmark times (matrix cores): sampled rows, the first and the last
