@@ -97,10 +97,11 @@ size_t rpy_wall_noalloc_scratch_bytes(void);
 /* U_l = M(r) F_l for k right-hand sides sharing one geometry (one time step
  * needs M f, random-finite-difference probes and Lanczos vectors, Sec. III).
  * F, U: device [k][N][3].  Each pair's 3x3 block is evaluated once per RHS
- * block and contracted with every RHS in the block: in FP32C blocks of 8 or
- * 16 by default on the matrix cores (the block written out on the vector
- * units, FP32 matrix products summed per source tile, then compensated),
- * otherwise on the vector units.  1 <= k <= 4096. */
+ * block and contracted with every RHS in the block: by default on the matrix
+ * cores for FP32C blocks of 8 or 16 (FP32 matrix products summed per source
+ * tile, then compensated) and FP64 blocks of 16 (FP64 matrix products), the
+ * block written out on the vector units; otherwise on the vector units.
+ * 1 <= k <= 4096. */
 int rpy_wall_matvec_multi(const double* pos, const double* F, double* U, int64_t N, int32_t k, double a,
                           double eta, int precision, void* ws, size_t ws_bytes, void* stream);
 
@@ -123,8 +124,9 @@ int rpy_wall_matvec_periodic(const double* pos, const double* F, double* U, int6
  * interact.  sys_offsets: HOST int64 [S+1], sys_offsets[0] = 0, strictly
  * increasing.  pos: device [Ntot][3]; F, U: device [k][Ntot][3].  Work items
  * (system, target tile) are taken largest-first from an atomic counter;
- * FP32C blocks of 8 or more right-hand sides run on the matrix cores (tiles
- * of 64 targets), others on the vector units (tiles of 256). */
+ * FP32C blocks of 8 or more and FP64 blocks of 9 or more right-hand sides
+ * run on the matrix cores (tiles of 64 targets), others on the vector units
+ * (tiles of 256). */
 int rpy_wall_matvec_batched(const double* pos, const int64_t* sys_offsets, int32_t S, const double* F,
                             double* U, int32_t k, double a, double eta, int precision, void* ws,
                             size_t ws_bytes, void* stream);
@@ -350,9 +352,10 @@ int rpy_wall_autotune(const double* pos, const double* F, double* U, int64_t N, 
  * blobs (2, more workgroups for small problems; taken for N <= 32768, else
  * groups of 256); ipw: source groups per workgroup of the symmetric kernel;
  * mat: 1 contracts the 3 x 3 pair blocks with the RHS block on the matrix
- * cores (FP32C with kblk 8 or 16 only; tpl, tile, sym and ipw then do not
- * apply), 0 on the vector units.  The batched products do not read these
- * shapes: they contract FP32C blocks of 8 or more on the matrix cores.
+ * cores (kblk 8 or 16, in FP64 the only way to a block of 16; tpl, tile,
+ * sym and ipw then do not apply), 0 on the vector units.  The batched
+ * products do not read these shapes: they contract FP32C blocks of 8 or
+ * more and FP64 blocks of 16 on the matrix cores.
  * Pseudo-periodic products always use the symmetric kernel, over groups of
  * 256 when sym is 1 and of 64 otherwise.  tpl = 0 removes the override (back to the tuner's or
  * the built-in choice).  Host-only, takes effect for later calls.

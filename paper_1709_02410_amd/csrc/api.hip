@@ -109,11 +109,14 @@ Shape default_shape(int64_t N, int k, int prec) {
     Shape s;
     s.tpl = N >= 65536 ? 2 : 1;
     s.tile = 64;
-    s.kblk = std::min(kclass(k), prec == RPYW_FP32C ? 16 : 8);
+    // FP64: blocks of up to 8 on the vector units; 9 to 16 right-hand sides
+    // go to the matrix cores as one block of 16 (a block of 8 there would
+    // leave half of every contraction empty).
+    s.kblk = std::min(kclass(k), prec == RPYW_FP32C ? 16 : (kclass(k) > 8 ? 16 : 8));
     s.sym = (s.kblk == 1 && N >= 512) ? (N <= kSym64MaxN ? 2 : 1) : 0;
     const int64_t ng = (N + 255) / 256, hm = ng / 2 + 1;
     s.ipw = s.sym == 2 ? 1 : (int)std::max<int64_t>(1, std::min<int64_t>(4, hm * ng / 16384));
-    s.mat = (prec == RPYW_FP32C && s.kblk >= 8) ? 1 : 0;
+    s.mat = (s.kblk >= (prec == RPYW_FP32C ? 8 : 16)) ? 1 : 0;
     return s;
 }
 
@@ -606,18 +609,18 @@ int rpy_wall_autotune(const double* pos, const double* F, double* U, int64_t N, 
     // resolve the same way every time.
     std::vector<Shape> cands;
     for (int kb = 1; kb <= std::min(kc, 16); kb <<= 1) {
-        if (precision == RPYW_FP64 && kb > 8) continue;
         for (int cand = 0; cand < 10; ++cand) {
             Shape sh{1, 256, kb, cand < 3 ? 1 : 2, 4 >> (cand % 3)};
             if (cand >= 6) sh = Shape{1 + ((cand - 6) & 1), ((cand - 6) & 2) ? 256 : 64, kb, 0, 4};
             if (cand >= 6 && kb >= 8 && sh.tpl == 2) continue;
             if (cand < 6 && kb > 4) continue;
             if (sh.sym == 2 && N > kSym64MaxN) continue;
-            if (cand == 6 && precision == RPYW_FP32C && kb >= 8) {
+            if (cand == 6 && kb >= 8) {
                 Shape m{1, 64, kb, 0, 4};
                 m.mat = 1;
                 cands.push_back(m);
             }
+            if (precision == RPYW_FP64 && kb > 8) continue;  // the vector units take FP64 blocks of up to 8
             cands.push_back(sh);
         }
     }
@@ -670,9 +673,9 @@ int rpy_wall_set_shape(int precision, int64_t N, int32_t k, int32_t tpl, int32_t
         return RPYW_OK;
     }
     if (!valid_prec(precision) || N < 1 || N >= kMaxN || k < 1 || (tpl != 1 && tpl != 2) ||
-        (tile != 64 && tile != 256) || kblk < 1 || kblk > (precision == RPYW_FP32C ? 16 : 8) ||
+        (tile != 64 && tile != 256) || kblk < 1 || kblk > (precision == RPYW_FP32C || mat ? 16 : 8) ||
         (kblk & (kblk - 1)) != 0 || sym < 0 || sym > 2 || (sym && kblk > 4) || ipw < 1 || mat < 0 || mat > 1 ||
-        (mat && (precision != RPYW_FP32C || kblk < 8)))
+        (mat && kblk < 8))
         return RPYW_EINVAL;
     Shape sh{tpl, tile, kblk, sym, ipw};
     sh.mat = mat;
@@ -683,10 +686,10 @@ int rpy_wall_set_shape(int precision, int64_t N, int32_t k, int32_t tpl, int32_t
 int rpy_wall_get_shape(int precision, int64_t N, int32_t k, int32_t* out6) {
     if (!valid_prec(precision) || N < 1 || N >= kMaxN || k < 1 || !out6) return RPYW_EINVAL;
     Shape s = tuned_shape(N, k, precision);
-    const int K = std::min(kclass(s.kblk), precision == RPYW_FP32C ? 16 : 8);
+    const int K = std::min(kclass(s.kblk), precision == RPYW_FP32C || s.mat ? 16 : 8);
     if (K >= 8) s.tpl = 1;
     if (K > 4) s.sym = 0;
-    if (precision != RPYW_FP32C || K < 8) s.mat = 0;
+    if (K < 8) s.mat = 0;
     out6[0] = s.tpl;
     out6[1] = s.tile;
     out6[2] = s.kblk;

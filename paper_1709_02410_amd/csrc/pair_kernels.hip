@@ -445,21 +445,41 @@ hipError_t launch_batched_t(const R* rec, const int4* items, int n_items, unsign
     return hipGetLastError();
 }
 
-template <int K>
-hipError_t launch_mat_t(const float* rec, int64_t N, int splits, int64_t chunk, double* part, int64_t nblocks,
+template <typename R, int K>
+hipError_t launch_mat_t(const void* rec, int64_t N, int splits, int64_t chunk, double* part, int64_t nblocks,
                         hipStream_t st) {
-    hipLaunchKernelGGL((mat_pair_kernel<K>), dim3((unsigned)nblocks), dim3(kBlock), 0, st, rec, N, splits, chunk,
-                       part);
+    hipLaunchKernelGGL((mat_pair_kernel<R, K>), dim3((unsigned)nblocks), dim3(kBlock), 0, st, (const R*)rec, N, splits,
+                       chunk, part);
     return hipGetLastError();
 }
 
-template <int K>
-hipError_t launch_mat_batched_t(const float* rec, const int4* items, int n_items, unsigned* counter,
+template <typename R, int K>
+hipError_t launch_mat_batched_t(const void* rec, const int4* items, int n_items, unsigned* counter,
                                 const double* B, double mu0, int64_t Ntot, int kb, double* U, int grid,
                                 hipStream_t st) {
-    hipLaunchKernelGGL((mat_batched_kernel<K>), dim3(grid), dim3(kBlock), 0, st, rec, items, n_items, counter, B, mu0,
-                       Ntot, kb, U);
+    hipLaunchKernelGGL((mat_batched_kernel<R, K>), dim3(grid), dim3(kBlock), 0, st, (const R*)rec, items, n_items,
+                       counter, B, mu0, Ntot, kb, U);
     return hipGetLastError();
+}
+
+// The matrix-core launches for a precision and a block of 8 or 16.
+hipError_t launch_mat(int prec, int K, const void* rec, int64_t N, int splits, int64_t chunk, double* part,
+                      int64_t nblocks, hipStream_t st) {
+    if (prec == RPYW_FP32C)
+        return K == 16 ? launch_mat_t<float, 16>(rec, N, splits, chunk, part, nblocks, st)
+                       : launch_mat_t<float, 8>(rec, N, splits, chunk, part, nblocks, st);
+    return K == 16 ? launch_mat_t<double, 16>(rec, N, splits, chunk, part, nblocks, st)
+                   : launch_mat_t<double, 8>(rec, N, splits, chunk, part, nblocks, st);
+}
+
+hipError_t launch_mat_batched(int prec, int K, const void* rec, const int4* items, int n_items, unsigned* counter,
+                              const double* B, double mu0, int64_t Ntot, int kb, double* U, int grid,
+                              hipStream_t st) {
+    if (prec == RPYW_FP32C)
+        return K == 16 ? launch_mat_batched_t<float, 16>(rec, items, n_items, counter, B, mu0, Ntot, kb, U, grid, st)
+                       : launch_mat_batched_t<float, 8>(rec, items, n_items, counter, B, mu0, Ntot, kb, U, grid, st);
+    return K == 16 ? launch_mat_batched_t<double, 16>(rec, items, n_items, counter, B, mu0, Ntot, kb, U, grid, st)
+                   : launch_mat_batched_t<double, 8>(rec, items, n_items, counter, B, mu0, Ntot, kb, U, grid, st);
 }
 
 // Expand (K, TPL, TILE) runtime values into template instantiations.
@@ -496,13 +516,17 @@ int pow2ceil(int k) {
 }
 
 // RHS block width of the kernel instantiation that serves kb right-hand
-// sides (FP64 stops at 8: wider blocks do not fit the register file).
-int kernel_k(int kb, int prec) { return std::min(pow2ceil(kb), prec == RPYW_FP32C ? 16 : 8); }
+// sides (on the vector units FP64 stops at 8: wider blocks do not fit the
+// register file; the matrix-core kernel takes 16 in both precisions).
+int kernel_k(int kb, int prec, int mat) {
+    return std::min(pow2ceil(kb), (prec == RPYW_FP32C || mat) ? 16 : 8);
+}
 
 // The launch shape the dispatch actually instantiates: blocks of 8 or more
 // right-hand sides run one target per lane, tiles are 64 or 256.
 Shape normalized(Shape s, int K, int prec) {
-    s.mat = (s.mat && prec == RPYW_FP32C && K >= 8) ? 1 : 0;
+    (void)prec;
+    s.mat = (s.mat && K >= 8) ? 1 : 0;
     if (K >= 8) s.tpl = 1;
     if (K > 4) s.sym = 0;
     if (s.ipw < 1) s.ipw = 4;
@@ -581,7 +605,7 @@ size_t product_ws_bytes(int64_t N, int prec, int kblk) {
     int64_t c;
     split_plan(N, 1, &s1, &c);
     split_plan(N, 2, &s2, &c);
-    if (prec == RPYW_FP32C && kblk >= 8) mat_split_plan(N, &s3, &c);
+    if (kblk >= 8) mat_split_plan(N, &s3, &c);
     const int smax = std::max(std::max(s1, s2), s3);
     size_t b = align_up((size_t)N * rec_width(prec, kblk) * real_size(prec));
     b += align_up((size_t)N * sizeof(double));
@@ -701,7 +725,7 @@ int sym_finish(const double* tpart, const void* spart, const double* B, int64_t 
 int product_pass(const double* pos, const double* F, double* U, int64_t N, int kb, double a, double eta, int prec,
                  Shape sh, Arena& ar, hipStream_t st) {
     const size_t mark = ar.used;
-    const int K = kernel_k(kb, prec);
+    const int K = kernel_k(kb, prec, sh.mat);
     if (kb < 1 || kb > K) return RPYW_EINVAL;
     sh = normalized(sh, K, prec);
     if (sh.sym && K <= 4) {
@@ -738,8 +762,7 @@ int product_pass(const double* pos, const double* F, double* U, int64_t N, int k
     profile_begin(st, &ev);
     hipError_t e;
     if (sh.mat)
-        e = K == 16 ? launch_mat_t<16>((const float*)rec, N, splits, chunk, part, nblocks, st)
-                    : launch_mat_t<8>((const float*)rec, N, splits, chunk, part, nblocks, st);
+        e = launch_mat(prec, K, rec, N, splits, chunk, part, nblocks, st);
     else if (prec == RPYW_FP32C)
         e = RPYW_DISPATCH(float, K, sh.tpl, sh.tile, launch_pair_t, (const float*)rec, N, splits, chunk, part, nblocks,
                           st);
@@ -770,7 +793,8 @@ int products(const double* pos, const double* F, double* U, int64_t N, int k, do
         }
         return RPYW_OK;
     }
-    const Shape sh = tuned_shape(N, k, prec);
+    Shape sh = tuned_shape(N, k, prec);
+    if (prec != RPYW_FP32C && !sh.mat) sh.kblk = std::min(sh.kblk, 8);  // e.g. RPYW_RHS_WIDTH=16 on the vector units
     for (int k0 = 0; k0 < k; k0 += sh.kblk) {
         const int kb = std::min(sh.kblk, k - k0);
         const int rc = product_pass(pos, F + (size_t)k0 * N * 3, U + (size_t)k0 * N * 3, N, kb, a, eta, prec, sh, ar,
@@ -783,7 +807,7 @@ int products(const double* pos, const double* F, double* U, int64_t N, int k, do
 // ------------------------------------------------------------ batched
 
 size_t batched_ws_bytes(int64_t Ntot, int S, int k, int prec) {
-    const int kb = kernel_k(std::max(k, 1), prec);
+    const int kb = kernel_k(std::max(k, 1), prec, 1);  // the widest the batched kernels take
     size_t b = align_up((size_t)Ntot * rec_width(prec, kb) * real_size(prec));
     b += align_up((size_t)Ntot * sizeof(double));
     const size_t max_items = (size_t)(Ntot / kMatTargets) + (size_t)S + 1;  // items of 64 or more targets
@@ -805,7 +829,7 @@ int batched_products(const double* pos, const int64_t* sys_offsets, int S, const
     Shape sh = default_shape(nmax, k, prec);
     sh.sym = 0;
     sh = apply_env_overrides(sh);
-    sh = normalized(sh, kernel_k(sh.kblk, prec), prec);
+    sh = normalized(sh, kernel_k(sh.kblk, prec, sh.mat), prec);
     // Work list in LPT order: systems by decreasing size, then their tiles.
     std::vector<int> order(S);
     for (int s = 0; s < S; ++s) order[s] = s;
@@ -819,7 +843,7 @@ int batched_products(const double* pos, const int64_t* sys_offsets, int S, const
         for (int t = b0; t < b1; t += span) items.push_back(make_int4(b0, b1, t, 0));
     }
     const size_t mark = ar.used;
-    const int K = kernel_k(sh.kblk, prec);
+    const int K = kernel_k(sh.kblk, prec, sh.mat);
     if (sh.kblk > K) return RPYW_EINVAL;
     const int rw = rec_width(prec, K);
     void* rec = ar.take((size_t)Ntot * rw * real_size(prec));
@@ -835,7 +859,8 @@ int batched_products(const double* pos, const int64_t* sys_offsets, int S, const
     int dev = 0, ncu = 256;
     RPYW_HIP(hipGetDevice(&dev));
     RPYW_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    const int grid = (int)std::min<size_t>(items.size(), (size_t)ncu * (sh.mat ? kMatBatchedWaves : 4));
+    const int per_cu = sh.mat ? (prec == RPYW_FP32C ? mat_batched_waves<float>() : mat_batched_waves<double>()) : 4;
+    const int grid = (int)std::min<size_t>(items.size(), (size_t)ncu * per_cu);
     const unsigned g1 = (unsigned)((Ntot + kBlock - 1) / kBlock);
     const double m0 = mu0_of(a, eta);
     double pairs = 0.0;
@@ -860,10 +885,7 @@ int batched_products(const double* pos, const int64_t* sys_offsets, int S, const
         profile_begin(st, &ev);
         hipError_t e;
         if (sh.mat)
-            e = K == 16 ? launch_mat_batched_t<16>((const float*)rec, ditems, (int)items.size(), counter, B, m0, Ntot,
-                                                   kb, Uk, grid, st)
-                        : launch_mat_batched_t<8>((const float*)rec, ditems, (int)items.size(), counter, B, m0, Ntot,
-                                                  kb, Uk, grid, st);
+            e = launch_mat_batched(prec, K, rec, ditems, (int)items.size(), counter, B, m0, Ntot, kb, Uk, grid, st);
         else if (prec == RPYW_FP32C)
             e = RPYW_DISPATCH(float, K, sh.tpl, sh.tile, launch_batched_t, (const float*)rec, ditems,
                               (int)items.size(), counter, B, m0, Ntot, kb, Uk, grid, st);

@@ -256,18 +256,22 @@ def test_launch_shape_validation_and_defaults(lib):
     assert lib.rpy_wall_set_shape(1, 5000, 1, 1, 256, 1, 3, 1, 0) == E
     assert lib.rpy_wall_set_shape(1, 5000, 1, 1, 256, 8, 2, 1, 0) == E
     assert lib.rpy_wall_set_shape(1, 5000, 1, 1, 256, 1, -1, 1, 0) == E
-    # the matrix-core contraction: FP32C blocks of 8 or 16 right-hand sides only
-    assert lib.rpy_wall_set_shape(0, 5000, 16, 1, 64, 8, 0, 4, 1) == E
+    # the matrix-core contraction: blocks of 8 or 16 right-hand sides; FP64
+    # blocks of 16 only there
     assert lib.rpy_wall_set_shape(1, 5000, 16, 1, 64, 4, 0, 4, 1) == E
     assert lib.rpy_wall_set_shape(1, 5000, 16, 1, 64, 16, 0, 4, 2) == E
-    for mat in (0, 1):
-        rpywall.set_shape(1, 5000, 16, tpl=1, tile=64, kblk=16, sym=0, ipw=4, mat=mat)
-        assert rpywall.get_shape(1, 5000, 16)["mat"] == mat
-    rpywall.reset_shape(1, 5000, 16)
+    assert lib.rpy_wall_set_shape(0, 5000, 16, 1, 64, 16, 0, 4, 0) == E
+    for prec in (0, 1):
+        for mat in (0, 1):
+            kb = 16 if (prec == 1 or mat) else 8
+            rpywall.set_shape(prec, 5000, 16, tpl=1, tile=64, kblk=kb, sym=0, ipw=4, mat=mat)
+            assert rpywall.get_shape(prec, 5000, 16) == dict(tpl=1, tile=64, kblk=kb, sym=0, ipw=4, mat=mat)
+        rpywall.reset_shape(prec, 5000, 16)
     assert rpywall.get_shape(1, 100000, 16)["mat"] == 1
     assert rpywall.get_shape(1, 100000, 8)["mat"] == 1
     assert rpywall.get_shape(1, 100000, 4)["mat"] == 0
-    assert rpywall.get_shape(0, 100000, 16)["mat"] == 0
+    assert rpywall.get_shape(0, 100000, 16)["mat"] == 1 and rpywall.get_shape(0, 100000, 16)["kblk"] == 16
+    assert rpywall.get_shape(0, 100000, 8)["mat"] == 0 and rpywall.get_shape(0, 100000, 8)["kblk"] == 8
     for sym in (0, 1, 2):
         rpywall.set_shape(1, 5000, 1, tpl=1, tile=256, kblk=1, sym=sym, ipw=2)
         assert rpywall.get_shape(1, 5000, 1)["sym"] == sym

@@ -23,11 +23,12 @@ def _t(x):
     return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
 
 
-@pytest.mark.parametrize("prec,k", [(0, 3), (1, 3), (1, 6), (1, 9), (1, 16)])
+@pytest.mark.parametrize("prec,k", [(0, 3), (0, 16), (1, 3), (1, 6), (1, 9), (1, 16)])
 def test_small_systems_against_oracle(rp, orc, prec, k):
     """Overlapping systems (same region of space) must not interact.  FP32C
-    with 6, 9 and 16 right-hand sides takes the matrix-core kernel (blocks of
-    8 and 16, work items of 64 targets), the others the vector kernel."""
+    with 6, 9 and 16 right-hand sides and FP64 with 16 take the matrix-core
+    kernel (blocks of 8 and 16, work items of 64 targets), the others the
+    vector kernel."""
     rng = np.random.default_rng(3)
     sizes = [1, 7, 300, 256, 513, 40, 65]
     parts = [np.column_stack([rng.uniform(0, 20, n), rng.uniform(0, 20, n), rng.uniform(0.5, 5, n)]) for n in sizes]

@@ -99,6 +99,32 @@ def test_matrix_core_multi_rhs_ragged(rp, orc, N, k):
         rp.reset_shape(1, N, k)
 
 
+@pytest.mark.parametrize("N", [1, 17, 65, 1500, 4097])
+@pytest.mark.parametrize("k", [8, 11, 16])
+def test_matrix_core_fp64(rp, orc, N, k):
+    """FP64 blocks on the matrix cores (FP64 matrix products, no
+    compensation): blocks of 8 and 16 (11: a partial block of 16) against
+    the oracle at the FP64 bar, bitwise repeatable; the vector kernel with
+    blocks of 8 on the same input too."""
+    rng = np.random.default_rng(3000 + N)
+    box = max(2.0, 2.0 * np.sqrt(N))
+    pos = np.column_stack([rng.uniform(0, box, N), rng.uniform(0, box, N), rng.uniform(0.3, 4.0, N)])
+    if N >= 3:
+        pos[2] = pos[1]
+    F = rng.standard_normal((k, N, 3))
+    refs = [orc.matvec(pos, F[l]) for l in range(k)]
+    try:
+        for mat, kblk in ((1, 8 if k <= 8 else 16), (0, 8)):
+            rp.set_shape(0, N, k, tpl=1, tile=64, kblk=kblk, sym=0, ipw=4, mat=mat)
+            U = rp.matvec_multi(_t(pos), _t(F), precision=0).cpu().numpy()
+            for l in range(k):
+                check(U[l], refs[l], TOL[0], f"FP64 multi-RHS N={N} k={k} mat={mat} rhs={l}")
+            if mat:
+                assert np.array_equal(U, rp.matvec_multi(_t(pos), _t(F), precision=0).cpu().numpy())
+    finally:
+        rp.reset_shape(0, N, k)
+
+
 def test_matrix_core_scaled_and_split_blocks(rp, orc):
     """Blob radius and viscosity other than 1 (blobs below z = a, scaled
     forces) and 17 right-hand sides: one block of 16 on the matrix cores and
