@@ -52,6 +52,7 @@ FLOP_VJP_SELF = 406
 FLOP_PAIR_BLOCK = 19
 FLOP_BLOCK_RHS = 18
 PEAK_FP32_MATRIX = 157.3  # TFLOP/s, MI355X dense FP32 matrix cores
+PEAK_FP64_MATRIX = 78.6   # TFLOP/s, MI355X dense FP64 matrix cores
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pair_kernel_traffic.json")
 # sources of the single-RHS pair kernels whose stored counter figures the hash
 # guards (the matrix-core multi-RHS kernels of mat_pairs.h are not among them)
@@ -422,7 +423,31 @@ def main():
             for l in (0, 7, 15):
                 check_matvec("multi_rhs_H_k16_fp32c", f"RHS {l}, 64 sampled rows", H.pos, F16_np[l],
                              U16_np[l][mrows], mrows, key=f"error_vs_oracle_rhs{l}")
-            del F16, U16, U16_np, F16_np
+            # the same 16-RHS product in FP64 (built-in shape: one block of 16
+            # on the matrix cores), against two passes of 8 on the vector units
+            U16.zero_()
+            w64m, km64, _, _ = timed(lambda: rp.matvec_multi(pos, F16, precision=rp.FP64, out=U16), 2, 1)
+            sh64 = rp.get_shape(rp.FP64, N, k)
+            fv, fm = mat_flop(N, k)
+            km64 /= 2
+            row64 = {"pair_rhs_per_s": k * N * N / w64m, "ms": w64m * 1e3, "kernel_ms": km64, "shape": sh64,
+                     "bound": "mfma", "matrix_tflops": fm / (km64 * 1e-3) / 1e12,
+                     "frac_fp64_matrix_peak": fm / (km64 * 1e-3) / 1e12 / PEAK_FP64_MATRIX,
+                     "vector_tflops": fv / (km64 * 1e-3) / 1e12,
+                     "frac_fp64_vector_peak": fv / (km64 * 1e-3) / 1e12 / PEAK_FP64}
+            U64_np = H2(U16)
+            rp.set_shape(rp.FP64, N, k, tpl=1, tile=256, kblk=8, sym=0, ipw=4, mat=0)
+            wv64, kmv64, _, _ = timed(lambda: rp.matvec_multi(pos, F16, precision=rp.FP64, out=U16), 1, 1)
+            rp.reset_shape(rp.FP64, N, k)
+            flv = 2 * algorithmic_flop(N, 8, 0)
+            row64["vector_kernel"] = {"ms": wv64 * 1e3, "kernel_ms": kmv64, "kblk": 8,
+                                      "tflops_alg": flv / (kmv64 * 1e-3) / 1e12,
+                                      "frac_fp64_peak": flv / (kmv64 * 1e-3) / 1e12 / PEAK_FP64}
+            rows["multi_rhs_H_k16_fp64"] = row64
+            for l in (0, 15):
+                check_matvec("multi_rhs_H_k16_fp64", f"RHS {l}, 64 sampled rows", H.pos, F16_np[l],
+                             U64_np[l][mrows], mrows, key=f"error_vs_oracle_rhs{l}")
+            del F16, U16, U16_np, F16_np, U64_np
 
         # single products on configs 0, 1 and 4 (default launch shapes), both
         # precisions: pairs/s and the pair kernel's share of the call
