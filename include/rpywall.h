@@ -346,7 +346,7 @@ int rpy_wall_autotune(const double* pos, const double* F, double* U, int64_t N, 
 /* Fix the launch shape used for products of this precision and size class
  * (the class of N: floor(log2 N); of k: next power of two up to 16) instead
  * of the tuner's choice.  tpl: targets per lane (1, 2); tile: LDS tile (64,
- * 256); kblk: RHS block width (1..16, FP64 up to 8); sym: 1 or 2 selects
+ * 256); kblk: RHS block width (1..16; FP64 above 8 only with mat); sym: 1 or 2 selects
  * the symmetric kernel, which evaluates each unordered pair once and applies
  * it in both directions (kblk <= 4), over groups of 256 blobs (1) or of 64
  * blobs (2, more workgroups for small problems; taken for N <= 32768, else

@@ -5,7 +5,7 @@
 //                              sizes, precision, chosen launch shape, status)
 //   RPYW_TILE=64|256           source tile of the plain pair kernel, for every
 //                              product (overrides tuned and built-in shapes)
-//   RPYW_RHS_WIDTH=1|2|4|8|16  right-hand sides per pass (FP64 stops at 8);
+//   RPYW_RHS_WIDTH=1|2|4|8|16  right-hand sides per pass (FP64: 16 only on the matrix cores);
 //                              widths above 4 use the plain kernel, or in
 //                              FP32C the matrix-core kernel where the shape
 //                              selects it
