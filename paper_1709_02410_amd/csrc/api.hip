@@ -72,7 +72,8 @@ void* scratch_address() {
 
 // ---------------------------------------------------------- shape table
 std::mutex g_shape_mu;
-std::map<std::tuple<int, int, int>, Shape> g_shapes;
+std::map<std::tuple<int, int, int>, Shape> g_shapes;     // tuned (and persisted)
+std::map<std::tuple<int, int, int>, Shape> g_overrides;  // rpy_wall_set_shape (not persisted)
 
 int size_class(int64_t N) {
     int c = 0;
@@ -173,7 +174,10 @@ void save_cache_locked() {
 Shape tuned_shape(int64_t N, int k, int prec) {
     std::lock_guard<std::mutex> lk(g_shape_mu);
     load_cache_locked();
-    auto it = g_shapes.find({prec, size_class(N), kclass(k)});
+    const std::tuple<int, int, int> key{prec, size_class(N), kclass(k)};
+    auto ov = g_overrides.find(key);
+    if (ov != g_overrides.end()) return apply_env_overrides(ov->second);
+    auto it = g_shapes.find(key);
     return apply_env_overrides(it != g_shapes.end() ? it->second : default_shape(N, k, prec));
 }
 
@@ -183,10 +187,14 @@ void set_tuned_shape(int64_t N, int k, int prec, Shape s) {
     g_shapes[{prec, size_class(N), kclass(k)}] = s;
 }
 
-void clear_tuned_shape(int64_t N, int k, int prec) {
+void set_shape_override(int64_t N, int k, int prec, Shape s) {
     std::lock_guard<std::mutex> lk(g_shape_mu);
-    load_cache_locked();
-    g_shapes.erase({prec, size_class(N), kclass(k)});
+    g_overrides[{prec, size_class(N), kclass(k)}] = s;
+}
+
+void clear_shape_override(int64_t N, int k, int prec) {
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    g_overrides.erase({prec, size_class(N), kclass(k)});
 }
 
 bool profiling_enabled() { return g_prof; }
@@ -669,7 +677,7 @@ int rpy_wall_autotune(const double* pos, const double* F, double* U, int64_t N, 
 int rpy_wall_set_shape(int precision, int64_t N, int32_t k, int32_t tpl, int32_t tile, int32_t kblk, int32_t sym,
                        int32_t ipw, int32_t mat) {
     if (tpl == 0 && valid_prec(precision) && N >= 1 && N < kMaxN && k >= 1) {
-        clear_tuned_shape(N, k, precision);
+        clear_shape_override(N, k, precision);
         return RPYW_OK;
     }
     if (!valid_prec(precision) || N < 1 || N >= kMaxN || k < 1 || (tpl != 1 && tpl != 2) ||
@@ -679,7 +687,7 @@ int rpy_wall_set_shape(int precision, int64_t N, int32_t k, int32_t tpl, int32_t
         return RPYW_EINVAL;
     Shape sh{tpl, tile, kblk, sym, ipw};
     sh.mat = mat;
-    set_tuned_shape(N, k, precision, sh);
+    set_shape_override(N, k, precision, sh);
     return RPYW_OK;
 }
 

@@ -129,12 +129,14 @@ int batched_products(const double* pos, const int64_t* sys_offsets, int S, const
 
 // Shape selection.
 Shape default_shape(int64_t N, int k, int prec);
-// The launch shape products of N blobs and k right-hand sides use: the
-// tuned one for this (precision, size class, RHS class) if any, else the
-// built-in default; then the RPYW_TILE / RPYW_RHS_WIDTH overrides.
+// The launch shape products of N blobs and k right-hand sides use: the one
+// fixed by rpy_wall_set_shape for this (precision, size class, RHS class) if
+// any, else the tuned one, else the built-in default; then the RPYW_TILE /
+// RPYW_RHS_WIDTH overrides.
 Shape tuned_shape(int64_t N, int k, int prec);
 void set_tuned_shape(int64_t N, int k, int prec, Shape s);
-void clear_tuned_shape(int64_t N, int k, int prec);
+void set_shape_override(int64_t N, int k, int prec, Shape s);
+void clear_shape_override(int64_t N, int k, int prec);
 
 // Run-time settings (settings.hip): RPYW_LOG, RPYW_TILE, RPYW_RHS_WIDTH and
 // the persisted shape cache RPYW_AUTOTUNE_CACHE.

@@ -66,3 +66,36 @@ def test_autotune_cache_is_read(tmp_path):
 def test_missing_cache_is_reported_not_fatal(tmp_path):
     got, err = _run({"RPYW_AUTOTUNE_CACHE": str(tmp_path / "absent.json"), "RPYW_LOG": "1"}, [(1, 5000, 1)])
     assert got and "not read" in err
+
+
+OVERRIDE_PROBE = """
+import sys
+sys.path.insert(0, {root!r})
+from paper_1709_02410_amd import rpywall as rp
+print(rp.get_shape(1, 5000, 2), flush=True)
+rp.set_shape(1, 5000, 2, tpl=1, tile=256, kblk=1, sym=1, ipw=2)
+print(rp.get_shape(1, 5000, 2), flush=True)
+rp.reset_shape(1, 5000, 2)
+print(rp.get_shape(1, 5000, 2), flush=True)
+"""
+
+
+def test_override_and_reset_keep_the_tuned_shape(tmp_path):
+    """rpy_wall_set_shape fixes a shape over the tuned one; removing the
+    override goes back to the tuned shape (here from the cache file), not to
+    the built-in default."""
+    if not os.path.exists(os.path.join(ROOT, "paper_1709_02410_amd", "librpywall.so")):
+        pytest.skip("librpywall.so not built")
+    path = tmp_path / "shapes.json"
+    tuned = {"tpl": 2, "tile": 64, "kblk": 2, "sym": 0, "ipw": 3, "mat": 0}
+    entries = [dict(arch=a, precision=1, size_class=12, k=2, **tuned) for a in ("unknown", "gfx950")]
+    path.write_text(json.dumps({"version": 1, "entries": entries}))
+    env = {k: v for k, v in os.environ.items() if not k.startswith("RPYW_")}
+    env["RPYW_AUTOTUNE_CACHE"] = str(path)
+    r = subprocess.run([sys.executable, "-c", OVERRIDE_PROBE.format(root=ROOT)], env=env, capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    got = [eval(line) for line in r.stdout.strip().splitlines()]
+    assert got[0] == tuned
+    assert got[1] == dict(tpl=1, tile=256, kblk=1, sym=1, ipw=2, mat=0)
+    assert got[2] == tuned
